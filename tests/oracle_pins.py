@@ -1,0 +1,464 @@
+"""Pins for the FP64 oracle: facts fixed by the paper and by mathematics,
+never by the oracle itself.
+
+Every check takes the oracle module as an argument so that the same checks
+can be run against deliberately broken copies of the oracle source (see
+test_oracle_mutations.py): each plausible mistake must fail at least one.
+
+Kinds of pin used here:
+  closed forms  -- results computable by hand for special dictionaries
+                   (identity, scaled identity, orthonormal, diagonal);
+  library       -- scikit-learn's coordinate-descent LASSO and its OMP,
+                   SciPy's DCT and symmetric eigen-solver, NumPy's SVD lstsq;
+  brute force   -- exhaustive L0 search on tiny problems;
+  invariants    -- KKT conditions, residual orthogonality, sparsity, norms.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+import scipy.fft
+import scipy.linalg
+
+from paper_2401_14762_amd import workloads as W
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+def _orthonormal(n, seed):
+    q, r = np.linalg.qr(_rng(seed).standard_normal((n, n)))
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def _sparse_problem(M, N, K, P, seed, noise=0.0):
+    rng = _rng(seed)
+    A = rng.standard_normal((M, N)) / math.sqrt(M)
+    X = np.zeros((P, N))
+    for p in range(P):
+        idx = rng.choice(N, K, replace=False)
+        X[p, idx] = rng.choice([-1.0, 1.0], K) * (1.0 + rng.random(K))
+    Y = X @ A.T + noise * rng.standard_normal((P, M))
+    return A, X, Y
+
+
+# ---------------------------------------------------------------- dictionary
+
+def check_dct_basis():
+    for N in (8, 100, 200, 224):
+        psi = W.dct_synthesis(N)
+        assert np.max(np.abs(psi.T @ psi - np.eye(N))) < 1e-13
+        f = _rng(N).standard_normal(N)
+        assert np.allclose(psi.T @ f, scipy.fft.dct(f, type=2, norm="ortho"), atol=1e-12)
+        assert np.allclose(psi @ f, scipy.fft.idct(f, type=2, norm="ortho"), atol=1e-12)
+
+
+def check_lipschitz(orc):
+    A = _rng(1).standard_normal((30, 70))
+    lam_max = scipy.linalg.eigh(A.T @ A, eigvals_only=True)[-1]
+    assert abs(orc.lipschitz(A) - lam_max) <= 1e-10 * lam_max
+    # closed form: scaled orthonormal rows
+    Q = _orthonormal(50, 2)[:20]
+    assert abs(orc.lipschitz(3.0 * Q) - 9.0) < 1e-12
+
+
+# ---------------------------------------------------------------- FISTA
+
+def _soft(v, t):
+    out = np.zeros_like(v)
+    out[v > t] = v[v > t] - t
+    out[v < -t] = v[v < -t] + t
+    return out
+
+
+def check_fista_identity(orc):
+    """A = c I, L = c^2: every iterate equals soft(y / c, lam / c^2)."""
+    Y = _rng(3).standard_normal((7, 12)) * 2.0
+    for c, lam in ((1.0, 0.3), (2.0, 0.5), (0.5, 0.01)):
+        A = c * np.eye(12)
+        want = _soft(Y / c, lam / c ** 2)
+        for it in (1, 2, 7):
+            out = orc.fista(A, Y, lam, c * c, it)
+            assert np.max(np.abs(out["X"] - want)) < 1e-12, (c, lam, it)
+
+
+def check_fista_zero_solution(orc):
+    """lam >= ||A^T y||_inf gives x = 0 from x^0 = 0; slightly below gives x != 0."""
+    A, _, Y = _sparse_problem(20, 50, 4, 5, 4)
+    L = orc.lipschitz(A)
+    lam0 = np.max(np.abs(Y @ A), axis=1)
+    for p in range(Y.shape[0]):
+        out = orc.fista(A, Y[p:p + 1], lam0[p] * 1.0000001, L, 30)
+        assert np.all(out["X"] == 0.0)
+        out = orc.fista(A, Y[p:p + 1], lam0[p] * 0.9, L, 30)
+        assert np.any(out["X"] != 0.0)
+
+
+def check_fista_diagonal_momentum(orc):
+    """lam = 0 and A = diag(sigma): each coordinate's error e = x - x* obeys
+    the scalar recursion e^i = q (e^{i-1} + b_{i-1}(e^{i-1} - e^{i-2})),
+    q = 1 - sigma^2 / L, b_i = (t_{i-1} - 1) / t_i, t_0 = 1, from x^0 = 0."""
+    sig = np.array([1.0, 0.8, 0.5, 0.3, 0.1])
+    A = np.diag(sig)
+    xstar = np.array([1.0, -2.0, 0.5, 3.0, -1.0])
+    Y = (A @ xstar)[None, :]
+    L = 1.0
+    for n_it in (1, 2, 3, 10, 40):
+        out = orc.fista(A, Y, 0.0, L, n_it)
+        e_prev = -xstar.copy()      # e^{-1} = e^0 = -x*
+        e = -xstar.copy()
+        t = 1.0
+        b = 0.0
+        for _ in range(n_it):
+            zerr = e + b * (e - e_prev)
+            e_new = (1.0 - sig ** 2 / L) * zerr
+            t_new = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
+            b = (t - 1.0) / t_new
+            t = t_new
+            e_prev, e = e, e_new
+        assert np.max(np.abs(out["X"][0] - (xstar + e))) < 1e-12, n_it
+
+
+def check_fista_matches_sklearn_lasso(orc):
+    """At convergence FISTA reaches the LASSO minimiser of Eq. 2, computed
+    independently by scikit-learn's coordinate descent (alpha = lam / M)."""
+    from sklearn.linear_model import Lasso
+    A, _, Y = _sparse_problem(20, 35, 3, 3, 5, noise=0.01)
+    lam = 0.02
+    L = orc.lipschitz(A)
+    out = orc.fista(A, Y, lam, L, 6000)
+    for p in range(Y.shape[0]):
+        m = Lasso(alpha=lam / A.shape[0], fit_intercept=False, tol=1e-14, max_iter=200000)
+        m.fit(A, Y[p])
+        assert np.max(np.abs(out["X"][p] - m.coef_)) < 1e-7, p
+
+
+def check_fista_kkt_and_rate(orc):
+    """KKT residual of Eq. 2 vanishes at convergence; along the way the
+    objective gap obeys Beck-Teboulle's bound 2 L ||x0 - x*||^2 / (k+1)^2."""
+    from oracle import metrics
+    A, _, Y = _sparse_problem(15, 30, 3, 2, 6, noise=0.05)
+    lam = 0.05
+    L = orc.lipschitz(A)
+    xs = orc.fista(A, Y, lam, L, 20000)["X"]
+    kkt = metrics.lasso_kkt_residual(A, Y, xs, lam)
+    assert np.all(kkt < 1e-9), kkt
+    Hs = metrics.lasso_objective(A, Y, xs, lam)
+    for k in (1, 2, 5, 20, 100):
+        xk = orc.fista(A, Y, lam, L, k)["X"]
+        gap = metrics.lasso_objective(A, Y, xk, lam) - Hs
+        bound = 2.0 * L * np.sum(xs ** 2, axis=1) / (k + 1) ** 2
+        assert np.all(gap <= bound * (1 + 1e-9) + 1e-12), (k, gap, bound)
+
+
+def check_fista_stop_rule(orc):
+    """Delta = ||r^i - r^{i-1}||, r^0 = y: a huge eps stops after iteration 1,
+    eps = 0 runs the full budget; Delta at iteration 1 is ||A x^1||."""
+    A, _, Y = _sparse_problem(20, 40, 3, 4, 7)
+    L = orc.lipschitz(A)
+    out = orc.fista(A, Y, 0.01, L, 50, eps=1e30)
+    assert np.all(out["iters"] == 1)
+    assert np.allclose(out["delta"], np.linalg.norm(out["X"] @ A.T, axis=1), rtol=1e-12)
+    out = orc.fista(A, Y, 0.01, L, 50, eps=0.0)
+    assert np.all(out["iters"] == 50)
+    # a single converged pixel freezes while the others continue
+    Y2 = Y.copy()
+    Y2[0] = 0.0
+    out = orc.fista(A, Y2, 0.01, L, 50, eps=1e-300)
+    assert out["iters"][0] == 1 and np.all(out["iters"][1:] == 50)
+
+
+def check_fista_nonfinite(orc):
+    A, _, Y = _sparse_problem(10, 20, 2, 3, 8)
+    Y[1, 3] = np.nan
+    out = orc.fista(A, Y, 0.01, orc.lipschitz(A), 5)
+    assert np.all(out["X"][1] == 0) and out["flags"][1] & orc.STOP_NONFINITE
+    assert np.all(np.isfinite(out["X"]))
+
+
+# ---------------------------------------------------------------- least squares
+
+def check_lstsq(orc):
+    rng = _rng(9)
+    A = rng.standard_normal((30, 60))
+    Y = rng.standard_normal((6, 30))
+    cols = np.stack([rng.choice(60, 11, replace=False) for _ in range(6)])
+    s = orc.lstsq_on_support(A, Y, cols)
+    for p in range(6):
+        B = A[:, cols[p]]
+        ref = np.linalg.lstsq(B, Y[p], rcond=None)[0]       # SVD-based LAPACK gelsd
+        assert np.max(np.abs(s[p] - ref)) < 1e-11
+        assert np.max(np.abs(B.T @ (Y[p] - B @ s[p]))) < 1e-11   # normal equations
+
+
+def check_top_indices(orc):
+    v = np.array([[0.5, -2.0, 2.0, 1.0, -2.0, 0.1]])
+    assert orc.top_indices(v, 3).tolist() == [[1, 2, 4]]
+    allowed = np.array([[True, False, True, True, True, True]])
+    assert orc.top_indices(v, 3, allowed).tolist() == [[2, 4, 3]]
+    assert orc.top_indices(np.zeros((1, 5)), 2).tolist() == [[0, 1]]
+
+
+# ---------------------------------------------------------------- gOMP
+
+def check_gomp_is_omp_when_S1(orc):
+    """G = 1 without pruning is textbook OMP (scikit-learn's Cholesky OMP)."""
+    from sklearn.linear_model import OrthogonalMatchingPursuit
+    A, _, Y = _sparse_problem(40, 90, 6, 6, 10, noise=0.02)
+    K = 6
+    out = orc.gomp(A, Y, K=K, S=1, max_iter=K)
+    for p in range(Y.shape[0]):
+        m = OrthogonalMatchingPursuit(n_nonzero_coefs=K, fit_intercept=False).fit(A, Y[p])
+        assert np.max(np.abs(out["X"][p] - m.coef_)) < 1e-9, p
+        assert out["support"][p].tolist() == np.sort(np.nonzero(m.coef_)[0]).tolist()
+
+
+def check_gomp_orthonormal(orc):
+    """Orthonormal A (M = N): after the loop and the prune the support is the K
+    largest |A^T y| and the values are A^T y there."""
+    N = 24
+    Q = _orthonormal(N, 11)
+    Y = _rng(12).standard_normal((5, N))
+    for K, S, it in ((5, 2, 4), (4, 1, 0), (6, 3, 3), (3, 2, 5)):
+        out = orc.gomp(Q, Y, K=K, S=S, max_iter=it)
+        c = Y @ Q
+        for p in range(5):
+            top = np.argsort(-np.abs(c[p]), kind="stable")[:K]
+            want = np.zeros(N)
+            want[top] = c[p, top]
+            assert np.max(np.abs(out["X"][p] - want)) < 1e-12, (K, S, it, p)
+            assert out["support"][p].tolist() == np.sort(top).tolist()
+
+
+def check_gomp_exact_recovery(orc):
+    A, X, Y = _sparse_problem(40, 100, 5, 20, 13)
+    out = orc.gomp(A, Y, K=5, S=2, res_tol=1e-10)
+    ok = np.max(np.abs(out["X"] - X), axis=1) < 1e-10
+    assert ok.mean() >= 0.9, ok.mean()
+    for p in np.nonzero(ok)[0]:
+        assert out["support"][p].tolist() == np.sort(np.nonzero(X[p])[0]).tolist()
+        assert out["flags"][p] & orc.STOP_CONVERGED
+
+
+def check_gomp_brute_force(orc):
+    """N=12, K=2: gOMP's residual is never below the exhaustive L0 minimum and
+    reaches it on exactly 2-sparse noiseless data when it finds the support."""
+    rng = _rng(14)
+    M, N, K = 8, 12, 2
+    A = rng.standard_normal((M, N))
+    for trial in range(20):
+        y = rng.standard_normal(M)
+        best = min(np.linalg.norm(y - A[:, list(s)] @ np.linalg.lstsq(A[:, list(s)], y, rcond=None)[0])
+                   for s in itertools.combinations(range(N), K))
+        out = orc.gomp(A, y[None, :], K=K, S=1, max_iter=2)
+        assert out["resid"][0] >= best - 1e-12
+        assert np.count_nonzero(out["X"][0]) <= K
+    x = np.zeros(N)
+    x[[3, 9]] = [1.5, -2.0]
+    out = orc.gomp(A, (A @ x)[None, :], K=K, S=1, max_iter=2)
+    assert out["resid"][0] < 1e-12 and np.allclose(out["X"][0], x, atol=1e-12)
+
+
+def check_gomp_prune_invariants(orc):
+    """With |c| > K: output is K-sparse, its support is inside the grown set,
+    and the residual is orthogonal to the kept columns (values re-solved)."""
+    A, _, Y = _sparse_problem(40, 80, 6, 8, 15, noise=0.1)
+    K, S, it = 6, 2, 8
+    out = orc.gomp(A, Y, K=K, S=S, max_iter=it)
+    for p in range(Y.shape[0]):
+        sup = out["support"][p]
+        assert np.all(sup >= 0) and len(sup) == K
+        assert np.count_nonzero(out["X"][p]) == K
+        r = Y[p] - A @ out["X"][p]
+        assert np.max(np.abs(A[:, sup].T @ r)) < 1e-10
+        assert out["iters"][p] == it
+
+
+def check_gomp_no_reselect(orc):
+    """Indices already in c are never selected again: with A = I the support
+    grows through the S largest |y| entries in order, ties to lower index."""
+    y = np.array([[3.0, 1.0, 3.0, 2.0, 2.0, 0.5, 1.0, 0.0]])
+    out = orc.gomp(np.eye(8), y, K=3, S=2, max_iter=3)
+    assert out["support"][0].tolist() == [0, 2, 3]
+    assert np.allclose(out["X"][0], [3, 0, 3, 2, 0, 0, 0, 0])
+
+
+def check_gomp_stop(orc):
+    A, X, Y = _sparse_problem(40, 100, 4, 6, 16)
+    out = orc.gomp(A, Y, K=10, S=2, res_tol=1e-8)
+    # exact 4-sparse data: stops no later than two iterations after the
+    # support is covered, well before the cap of 10
+    assert np.all(out["iters"] < 10) and np.all(out["flags"] & orc.STOP_CONVERGED)
+    out = orc.gomp(A, Y, K=10, S=2, res_tol=0.0, eps=0.0, max_iter=7)
+    assert np.all(out["iters"] == 7) and np.all(out["flags"] & orc.STOP_ITER_CAP)
+    # the residual rule is relative: scaling y scales x and keeps the iterations
+    base = orc.gomp(A, Y, K=10, S=2, res_tol=1e-8)
+    for c in (1e-9, 1e9):
+        sc = orc.gomp(A, c * Y, K=10, S=2, res_tol=1e-8)
+        assert np.array_equal(sc["iters"], base["iters"])
+        assert np.allclose(sc["X"], c * base["X"], rtol=1e-9,
+                           atol=1e-12 * c * np.abs(base["X"]).max())
+
+
+# ---------------------------------------------------------------- CoSaMP
+
+def check_cosamp_orthonormal(orc):
+    N = 30
+    Q = _orthonormal(N, 17)
+    Y = _rng(18).standard_normal((4, N))
+    K = 4
+    c = Y @ Q
+    for it in (1, 2, 5):
+        out = orc.cosamp(Q, Y, K=K, max_iter=it)
+        for p in range(4):
+            top = np.argsort(-np.abs(c[p]), kind="stable")[:K]
+            want = np.zeros(N)
+            want[top] = c[p, top]
+            assert np.max(np.abs(out["X"][p] - want)) < 1e-12
+
+
+def check_cosamp_recovery(orc):
+    A, X, Y = _sparse_problem(60, 120, 6, 10, 19)
+    out = orc.cosamp(A, Y, K=6, max_iter=15)
+    assert np.mean(np.max(np.abs(out["X"] - X), axis=1) < 1e-10) >= 0.9
+    assert np.all(np.count_nonzero(out["X"], axis=1) <= 6)
+
+
+def check_cosamp_no_resolve(orc):
+    """The kept values are the least-squares values on the merged support, not
+    a second solve on the kept atoms: the residual is generally not
+    orthogonal to the kept columns, but x equals the merged solution there."""
+    A, _, Y = _sparse_problem(30, 60, 4, 6, 20, noise=0.2)
+    K = 4
+    out = orc.cosamp(A, Y, K=K, max_iter=1)
+    p_all = Y @ A
+    for p in range(Y.shape[0]):
+        theta = np.argsort(-np.abs(p_all[p]), kind="stable")[:2 * K]
+        c = np.sort(theta)
+        s = np.linalg.lstsq(A[:, c], Y[p], rcond=None)[0]
+        keep = np.argsort(-np.abs(s), kind="stable")[:K]
+        want = np.zeros(A.shape[1])
+        want[c[keep]] = s[keep]
+        assert np.max(np.abs(out["X"][p] - want)) < 1e-10
+
+
+# ---------------------------------------------------------------- BIHT
+
+def check_biht_orthonormal(orc):
+    N = 20
+    Q = _orthonormal(N, 21)
+    Y = _rng(22).standard_normal((4, N))
+    K = 5
+    c = Y @ Q
+    for it in (1, 3):
+        out = orc.biht(Q, Y, K=K, max_iter=it, mu=0.1)
+        for p in range(4):
+            top = np.argsort(-np.abs(c[p]), kind="stable")[:K]
+            want = np.zeros(N)
+            want[top] = c[p, top]
+            assert np.max(np.abs(out["X"][p] - want)) < 1e-12
+
+
+def check_biht_first_step(orc):
+    """From x_a = 0, u = mu A^T y; with a non-orthonormal A the first iterate is
+    the least squares on the K largest |A^T y| (the set is K, so nothing is
+    pruned), independently of mu."""
+    A, _, Y = _sparse_problem(30, 60, 4, 5, 23, noise=0.3)
+    K = 4
+    for mu in (0.1, 1.0):
+        out = orc.biht(A, Y, K=K, max_iter=1, mu=mu)
+        for p in range(Y.shape[0]):
+            top = np.sort(np.argsort(-np.abs(Y[p] @ A), kind="stable")[:K])
+            s = np.linalg.lstsq(A[:, top], Y[p], rcond=None)[0]
+            want = np.zeros(60)
+            want[top] = s
+            assert np.max(np.abs(out["X"][p] - want)) < 1e-10
+
+
+def check_biht_second_step_mu(orc):
+    """The second candidate set depends on mu through u = x_a + mu A^T r:
+    with a huge mu the gradient term decides the new atoms."""
+    A, _, Y = _sparse_problem(30, 60, 4, 3, 24, noise=0.3)
+    K = 4
+    x1 = orc.biht(A, Y, K=K, max_iter=1)["X"]
+    for mu in (1e6, 0.1):
+        out = orc.biht(A, Y, K=K, max_iter=2, mu=mu)
+        for p in range(Y.shape[0]):
+            u = x1[p] + mu * (A.T @ (Y[p] - A @ x1[p]))
+            theta = np.argsort(-np.abs(u), kind="stable")[:K]
+            c = np.union1d(np.nonzero(x1[p])[0], theta)
+            s = np.linalg.lstsq(A[:, c], Y[p], rcond=None)[0]
+            h = np.argsort(-np.abs(s), kind="stable")[:K]
+            want = np.zeros(60)
+            want[c[h]] = s[h]
+            assert np.max(np.abs(out["X"][p] - want)) < 1e-9
+
+
+def check_biht_recovery(orc):
+    # a step mu = 1 lets the gradient term bring in new atoms; with a small mu
+    # the kept atoms dominate u and the candidate set can stall
+    A, X, Y = _sparse_problem(50, 100, 5, 10, 25)
+    out = orc.biht(A, Y, K=5, max_iter=30, mu=1.0)
+    assert np.mean(np.max(np.abs(out["X"] - X), axis=1) < 1e-10) >= 0.9
+    assert np.all(np.count_nonzero(out["X"], axis=1) <= 5)
+
+
+def check_one_bit(orc):
+    rng = _rng(26)
+    M, N, K = 400, 60, 4
+    A = rng.standard_normal((M, N)) / math.sqrt(M)
+    X = np.zeros((6, N))
+    for p in range(6):
+        X[p, rng.choice(N, K, replace=False)] = rng.standard_normal(K)
+    Ys = np.where(X @ A.T >= 0, 1, -1).astype(np.int8)
+    # one iteration from zero is H_K(mu A^T y), normalised
+    out1 = orc.biht_one_bit(A, Ys, K, 1, mu=0.1)
+    u = 0.1 * (Ys.astype(float) @ A)
+    for p in range(6):
+        top = np.argsort(-np.abs(u[p]), kind="stable")[:K]
+        want = np.zeros(N)
+        want[top] = u[p, top]
+        want /= np.linalg.norm(want)
+        assert np.max(np.abs(out1["X"][p] - want)) < 1e-12
+    out = orc.biht_one_bit(A, Ys, K, 60, mu=0.1)
+    nrm = np.linalg.norm(out["X"], axis=1)
+    assert np.allclose(nrm, 1.0, atol=1e-12)
+    assert np.all(np.count_nonzero(out["X"], axis=1) <= K)
+    cosang = np.sum(out["X"] * X, axis=1) / np.linalg.norm(X, axis=1)
+    assert np.median(cosang) > 0.95, cosang
+    agree = np.mean(np.sign(out["X"] @ A.T) == Ys, axis=1)
+    assert np.median(agree) > 0.95, agree
+
+
+# ---------------------------------------------------------------- metrics
+
+def check_metrics():
+    from oracle import metrics
+    ref = _rng(27).standard_normal((10, 20))
+    ref[3, 4] = 5.0
+    est = ref + 0.01
+    assert abs(metrics.psnr(est, ref) - 20.0 * math.log10(5.0 / 0.01)) < 1e-9
+    assert metrics.psnr(ref, ref) == float("inf")
+    e = np.zeros_like(ref)
+    e[:, 0] = 1.0
+    assert np.allclose(metrics.rel_err(ref + e, ref), 1.0 / np.linalg.norm(ref, axis=1))
+    # KKT residual is zero at the closed-form LASSO solution for A = I
+    y = _rng(28).standard_normal((3, 8))
+    x = _soft(y, 0.4)
+    assert np.max(metrics.lasso_kkt_residual(np.eye(8), y, x, 0.4)) < 1e-15
+    assert np.min(metrics.lasso_kkt_residual(np.eye(8), y, y, 0.4)) > 0.0
+
+
+ORACLE_CHECKS = [
+    check_lipschitz, check_fista_identity, check_fista_zero_solution,
+    check_fista_diagonal_momentum, check_fista_matches_sklearn_lasso, check_fista_kkt_and_rate,
+    check_fista_stop_rule, check_fista_nonfinite, check_lstsq, check_top_indices,
+    check_gomp_is_omp_when_S1, check_gomp_orthonormal, check_gomp_exact_recovery,
+    check_gomp_brute_force, check_gomp_prune_invariants, check_gomp_no_reselect,
+    check_gomp_stop, check_cosamp_orthonormal, check_cosamp_recovery, check_cosamp_no_resolve,
+    check_biht_orthonormal, check_biht_first_step, check_biht_second_step_mu,
+    check_biht_recovery, check_one_bit,
+]

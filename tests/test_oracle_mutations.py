@@ -1,0 +1,66 @@
+"""Plant plausible mistakes in a copy of the oracle source (on the CPU) and
+check that the pins catch every one of them.  The real oracle is untouched."""
+import importlib.util
+import os
+import sys
+import types
+
+import pytest
+
+import oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "cs.py")
+
+# (id, text to replace (first occurrence), replacement)
+MUTATIONS = [
+    ("fista-threshold-lam", "soft_threshold(aux, lam / L)", "soft_threshold(aux, lam)"),
+    ("fista-no-step-1/L", "(1.0 / L) * ((za @ A.T - ya) @ A)", "((za @ A.T - ya) @ A)"),
+    ("fista-gradient-sign", "((za @ A.T - ya) @ A)", "((ya - za @ A.T) @ A)"),
+    ("fista-no-momentum", "z_new = x_new + ((t - 1.0) / t_new) * (x_new - xa)", "z_new = x_new"),
+    ("fista-t-recursion", "math.sqrt(1.0 + 4.0 * t * t)", "math.sqrt(1.0 + t * t)"),
+    ("fista-momentum-index", "((t - 1.0) / t_new)", "((t_new - 1.0) / t_new)"),
+    ("fista-delta-vs-y", "d = np.linalg.norm(r_new - r[a], axis=1)", "d = np.linalg.norm(r_new, axis=1)"),
+    ("ties-to-higher-index", 'order = np.argsort(-key, axis=1, kind="stable")',
+     'order = key.shape[1] - 1 - np.argsort(-key[:, ::-1], axis=1, kind="stable")'),
+    ("lstsq-transposed-R", "np.linalg.solve(R, qty[..., None])",
+     "np.linalg.solve(np.transpose(R, (0, 2, 1)), qty[..., None])"),
+    ("gomp-no-mask", "theta = top_indices(p, S, allowed)", "theta = top_indices(p, S)"),
+    ("gomp-no-prune", 'if prune == "each" and i * S > K:', "if False:"),
+    ("gomp-prune-no-resolve", "sq = lstsq_on_support(A, ya, q)",
+     "sq = xa[np.arange(len(a))[:, None], q]"),
+    ("gomp-wrong-ls-columns", "s = lstsq_on_support(A, ya, cur)",
+     "s = lstsq_on_support(A, ya, cur)[:, ::-1]"),
+    ("gomp-absolute-res-tol", "stop = (rn <= res_tol * ynorm[a]) | (d < eps)",
+     "stop = (rn <= res_tol) | (d < eps)"),
+    ("cosamp-K-not-2K", "theta = top_indices(p, 2 * K)", "theta = top_indices(p, K)"),
+    ("cosamp-no-union", "np.union1d(theta[j], cprev[a[j]])", "np.sort(theta[j])"),
+    ("biht-no-mu", "u = xa_prev + mu * ((ya - xa_prev @ A.T) @ A)",
+     "u = xa_prev + ((ya - xa_prev @ A.T) @ A)"),
+    ("biht-no-union", "np.union1d(np.nonzero(xa_prev[j])[0], theta[j])", "np.sort(theta[j])"),
+    ("onebit-sgn0-plus", "u = x + mu * ((Ys - np.sign(ax)) @ A)",
+     "u = x + mu * ((Ys - np.where(ax >= 0, 1.0, -1.0)) @ A)"),
+    ("onebit-no-normalise", "x = np.where(nrm > 0, x / np.where(nrm > 0, nrm, 1.0), 0.0)", "x = x"),
+]
+
+
+def _mutant(old, new):
+    with open(SRC) as f:
+        text = f.read()
+    assert text.count(old) >= 1, old
+    text = text.replace(old, new, 1)
+    mod = types.ModuleType("oracle_mutant")
+    mod.__file__ = SRC
+    exec(compile(text, SRC + ":mutant", "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("mid,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_mutation(mid, old, new):
+    mod = _mutant(old, new)
+    failed = []
+    for check in pins.ORACLE_CHECKS:
+        try:
+            check(mod)
+        except (AssertionError, ValueError, IndexError, FloatingPointError, AttributeError):
+            failed.append(check.__name__)
+    assert failed, f"no pin catches mutation {mid}"
