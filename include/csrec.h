@@ -1,0 +1,192 @@
+/*
+ * csrec.h -- batched per-pixel sparse recovery of compressed hyperspectral
+ * cubes on AMD Instinct MI355X (gfx950).
+ *
+ * Every pixel spectrum is measured as y = Phi f = Phi Psi x = A x with one
+ * dictionary A (M x N, M < N) shared by all pixels (Section II, Eq. 1).  The
+ * entry points recover the sparse coefficients x of all P pixels of a cube
+ * at once with the paper's algorithms:
+ *
+ *   csrec_fista   FISTA for the LASSO of Eq. 2            (Alg. 1)
+ *   csrec_gomp    generalised OMP                          (Alg. 3)
+ *   csrec_biht    backtracking IHT (Alg. 4), or binary IHT on 1-bit
+ *                 measurements (mode CSREC_BIHT_ONE_BIT; not from the paper)
+ *   csrec_cosamp  CoSaMP                                   (Alg. 5)
+ *
+ * Layout.  A is M x N row-major FP32.  Y is P x M row-major FP32 (pixel
+ * major: the measurements of one pixel are contiguous).  X is P x N
+ * row-major FP32.  All of A, Y, X, support, stats and workspace are DEVICE
+ * pointers owned by the caller; the library never keeps them past the call's
+ * stream work and never frees them.
+ *
+ * Asynchrony.  Arguments are checked synchronously on the host; the work is
+ * then enqueued on problem->stream (a hipStream_t; NULL = the null stream)
+ * and the call returns.  The caller synchronises the stream before reading
+ * results.  Calls on different streams with disjoint outputs and workspaces
+ * may run concurrently.
+ *
+ * Workspace.  csrec_workspace_bytes() reports the device scratch a call
+ * needs; the caller allocates it and passes it in problem->workspace.  The
+ * solve path itself allocates no device memory.
+ *
+ * Errors.  Every entry point returns CSREC_OK or a negative CSREC_E_* code
+ * and enqueues nothing when it fails.  Per-pixel events (non-convergence,
+ * FP64 fallback, non-finite input) are not errors: they are reported in the
+ * per-pixel stats flags; a pixel with a non-finite measurement gets x = 0.
+ */
+#ifndef CSREC_H
+#define CSREC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSREC_ABI_VERSION 1
+
+/* return codes */
+#define CSREC_OK             0
+#define CSREC_E_INVAL       -1  /* null pointer, bad parameter value, struct_size mismatch */
+#define CSREC_E_SHAPE       -2  /* M >= N, N > CSREC_MAX_N, M < 1, P < 0, or shape the solver cannot hold */
+#define CSREC_E_WORKSPACE   -3  /* workspace missing or smaller than csrec_workspace_bytes() */
+#define CSREC_E_DEVICE      -4  /* a HIP call failed; see csrec_last_hip_error() */
+#define CSREC_E_UNSUPPORTED -5  /* precision / mode not available for this solver or shape */
+#define CSREC_E_BUDGET      -6  /* serving: a tile needs more than the server's HBM budget */
+
+/* arithmetic of the dictionary products */
+#define CSREC_PREC_F32  0   /* FP32 everywhere */
+#define CSREC_PREC_BF16 1   /* BF16 operands on MFMA, FP32 accumulation and state */
+#define CSREC_PREC_F16  2   /* FP16 operands on MFMA, FP32 accumulation and state */
+
+/* per-pixel flags (csrec_pixel_stats.flags) */
+#define CSREC_FLAG_CONVERGED     1u  /* stopped by Delta < eps or the residual tolerance */
+#define CSREC_FLAG_ITER_CAP      2u  /* ran max_iter iterations */
+#define CSREC_FLAG_FP64_FALLBACK 4u  /* gOMP least squares redone in FP64 (pivot ratio) */
+#define CSREC_FLAG_NONFINITE     8u  /* non-finite measurement: x = 0, no iterations */
+
+/* solver ids for csrec_workspace_bytes */
+#define CSREC_SOLVER_FISTA  0
+#define CSREC_SOLVER_GOMP   1
+#define CSREC_SOLVER_COSAMP 2
+#define CSREC_SOLVER_BIHT   3
+
+#define CSREC_MAX_N 256
+
+/* gOMP prune placement (Alg. 3 step 3) */
+#define CSREC_PRUNE_EACH  0  /* prune to K and re-solve in every iteration where |c| > K (Alg. 3 as printed) */
+#define CSREC_PRUNE_FINAL 1  /* prune once after the loop (textbook gOMP) */
+
+/* BIHT modes */
+#define CSREC_BIHT_REAL    0 /* Alg. 4, backtracking IHT on real measurements Y */
+#define CSREC_BIHT_ONE_BIT 1 /* binary IHT on int8 sign measurements Ysign */
+
+/* One cube: P pixels, each y (M values) = A x (N values). */
+typedef struct {
+    int32_t struct_size;      /* sizeof(csrec_problem) */
+    int32_t M, N;             /* 1 <= M < N <= CSREC_MAX_N */
+    int64_t P;                /* pixels; 0 is a valid empty problem */
+    const float* A;           /* device, M x N row-major */
+    const float* Y;           /* device, P x M row-major (unused by BIHT ONE_BIT) */
+    void* stream;             /* hipStream_t, NULL = null stream */
+    void* workspace;          /* device scratch, >= csrec_workspace_bytes() */
+    size_t workspace_bytes;
+} csrec_problem;
+
+/* Per-pixel result statistics (optional output, P entries). */
+typedef struct {
+    int32_t iters;            /* iterations run */
+    uint32_t flags;           /* CSREC_FLAG_* */
+    float resid;              /* ||y - A x||_2 of the returned x */
+    float delta;              /* last Delta = ||r^i - r^{i-1}||_2 */
+} csrec_pixel_stats;
+
+/* Alg. 1.  Inputs y, A, x^0, L, lambda, eps (kappa is unused by FISTA). */
+typedef struct {
+    int32_t struct_size;      /* sizeof(csrec_fista_params) */
+    int32_t max_iter;         /* >= 0; replaces the paper's wall-clock cap */
+    double lambda;            /* >= 0, the l1 weight of Eq. 2 */
+    double L;                 /* > 0: Lipschitz constant lambda_max(A^T A) (Eq. 2);
+                                 0: the library estimates it on the device by power iteration */
+    double eps;               /* a pixel stops after the iteration with Delta < eps; 0 disables */
+    const float* X0;          /* device P x N starting point, NULL = 0 */
+    int32_t prec;             /* CSREC_PREC_* */
+    int32_t correction_iters; /* BF16/F16 only: FP32 iterations run after the low-precision
+                                 ones, warm-started from their result (0 = none) */
+} csrec_fista_params;
+
+/* Alg. 3.  Inputs y, A, kappa (= K), G (= S), eps. */
+typedef struct {
+    int32_t struct_size;      /* sizeof(csrec_gomp_params) */
+    int32_t K;                /* kappa: sparsity of the returned x, 1 <= K */
+    int32_t S;                /* G: atoms added per iteration, 1 <= S <= 8 */
+    int32_t max_iter;         /* 0 = min(K, floor(M / S)); S * max_iter <= min(M, 64) */
+    double res_tol;           /* stop when ||r|| <= res_tol * ||y|| (0 disables) */
+    double eps;               /* stop when Delta < eps (0 disables) */
+    int32_t prune;            /* CSREC_PRUNE_EACH or CSREC_PRUNE_FINAL */
+    int32_t prec;             /* precision of the correlation A^T r */
+    double pivot_fallback;    /* FP64 redo of a pixel when a Cholesky pivot ratio d_j / G_jj falls
+                                 below this (e.g. 1e-6); 0 disables */
+} csrec_gomp_params;
+
+/* Alg. 5.  Inputs y, A, kappa (= K), eps. */
+typedef struct {
+    int32_t struct_size;      /* sizeof(csrec_cosamp_params) */
+    int32_t K;                /* 1 <= K, 3K <= min(M, 64) */
+    int32_t max_iter;         /* >= 0 */
+    double eps;               /* stop when Delta < eps (0 disables) */
+    double res_tol;           /* stop when ||r|| <= res_tol * ||y|| (0 disables) */
+    int32_t prec;             /* precision of the correlation A^T r */
+} csrec_cosamp_params;
+
+/* Alg. 4 (REAL) or binary IHT (ONE_BIT).  Inputs y, A, kappa (= K), mu, eps. */
+typedef struct {
+    int32_t struct_size;      /* sizeof(csrec_biht_params) */
+    int32_t K;                /* REAL: 1 <= K, 2K <= min(M, 64);  ONE_BIT: 1 <= K <= N */
+    int32_t max_iter;         /* >= 0 */
+    double mu;                /* gradient step (0.1 in Section IV) */
+    double eps;               /* REAL: stop when Delta < eps (0 disables) */
+    double res_tol;           /* REAL: stop when ||r|| <= res_tol * ||y|| (0 disables) */
+    int32_t mode;             /* CSREC_BIHT_REAL or CSREC_BIHT_ONE_BIT */
+    const int8_t* Ysign;      /* ONE_BIT: device P x M signs in {-1, +1}; REAL: ignored */
+    int32_t prec;             /* precision of the correlation */
+} csrec_biht_params;
+
+/* Library version and ABI. */
+int32_t csrec_abi_version(void);
+const char* csrec_strerror(int32_t code);
+/* Last HIP error code seen by this thread (0 = none). */
+int32_t csrec_last_hip_error(void);
+
+/* Device scratch (bytes) a solve of `solver` on `problem` with `params` needs.
+ * params points to the solver's params struct.  Returns CSREC_OK or an error
+ * for invalid arguments; *bytes may be 0. */
+int32_t csrec_workspace_bytes(int32_t solver, const csrec_problem* problem, const void* params,
+                              size_t* bytes);
+
+/* FISTA (Alg. 1): X (P x N) receives x^I; stats nullable. */
+int32_t csrec_fista(const csrec_problem* problem, const csrec_fista_params* params, float* X,
+                    csrec_pixel_stats* stats);
+
+/* gOMP (Alg. 3): X (P x N) receives the K-sparse x; support (P x K int32, nullable) the
+ * indices of its atoms in ascending order, -1 padded; stats nullable. */
+int32_t csrec_gomp(const csrec_problem* problem, const csrec_gomp_params* params, float* X,
+                   int32_t* support, csrec_pixel_stats* stats);
+
+/* CoSaMP (Alg. 5): outputs as csrec_gomp. */
+int32_t csrec_cosamp(const csrec_problem* problem, const csrec_cosamp_params* params, float* X,
+                     int32_t* support, csrec_pixel_stats* stats);
+
+/* BIHT (Alg. 4 / binary IHT): outputs as csrec_gomp.  ONE_BIT returns x / ||x||. */
+int32_t csrec_biht(const csrec_problem* problem, const csrec_biht_params* params, float* X,
+                   int32_t* support, csrec_pixel_stats* stats);
+
+/* Lipschitz constant L = lambda_max(A^T A) of Eq. 2 by power iteration on the device:
+ * writes one float to *L_out (device pointer) on `stream`. */
+int32_t csrec_lipschitz(const float* A, int32_t M, int32_t N, float* L_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSREC_H */

@@ -1,0 +1,248 @@
+"""csrec -- batched per-pixel sparse recovery of compressed hyperspectral cubes
+on AMD Instinct MI355X (gfx950).
+
+Python binding of ``libcsrec.so`` (C ABI in ``include/csrec.h``).  The
+functions take and return torch tensors that live on the GPU; torch provides
+device memory and the stream, the library's HIP kernels do all the work.
+
+    X, st = fista(A, Y, lam=1e-2, L=L, max_iter=200)           # Alg. 1
+    X, S, st = gomp(A, Y, K=20, S=2, res_tol=1e-3)              # Alg. 3
+    X, S, st = biht(A, Y, K=15, max_iter=100, mu=0.1)           # Alg. 4
+    X, S, st = biht(A, None, K=15, max_iter=100, Ysign=Ys, mode="one_bit")
+    X, S, st = cosamp(A, Y, K=15, max_iter=30)                  # Alg. 5
+
+A: M x N float32, Y: P x M float32, both CUDA (HIP) tensors, contiguous.
+``st`` is a dict of per-pixel tensors: iters, flags, resid, delta.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (CsrecError, FLAG_CONVERGED, FLAG_FP64_FALLBACK, FLAG_ITER_CAP,
+                   FLAG_NONFINITE, MAX_N)
+
+__all__ = ["fista", "gomp", "cosamp", "biht", "lipschitz", "CsrecError", "FLAG_CONVERGED",
+           "FLAG_ITER_CAP", "FLAG_FP64_FALLBACK", "FLAG_NONFINITE", "MAX_N", "workspace_bytes",
+           "library"]
+
+
+def library():
+    """The loaded ctypes library (raises if libcsrec.so is not built)."""
+    return _lib.load()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_dev(name, t, dtype, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _problem(A, Y, P, stream):
+    torch = _torch()
+    M, N = A.shape
+    pb = _lib.Problem()
+    pb.struct_size = ctypes.sizeof(_lib.Problem)
+    pb.M, pb.N, pb.P = M, N, P
+    pb.A = A.data_ptr()
+    pb.Y = Y.data_ptr() if Y is not None else 0
+    if stream is None:
+        stream = torch.cuda.current_stream(A.device)
+    pb.stream = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    return pb
+
+
+def _stats_view(st):
+    torch = _torch()
+    return dict(iters=st[:, 0].clone(), flags=st[:, 1].clone(),
+                resid=st[:, 2].view(torch.float32).clone(), delta=st[:, 3].view(torch.float32).clone())
+
+
+def _workspace(lib, solver, pb, params, device):
+    torch = _torch()
+    nbytes = ctypes.c_size_t(0)
+    _lib.check(lib.csrec_workspace_bytes(solver, ctypes.byref(pb), ctypes.byref(params),
+                                         ctypes.byref(nbytes)), "csrec_workspace_bytes")
+    ws = None
+    if nbytes.value > 0:
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+        pb.workspace = ws.data_ptr()
+        pb.workspace_bytes = nbytes.value
+    return ws
+
+
+def workspace_bytes(solver: str, A, Y, **params) -> int:
+    """Device scratch bytes a call of ``solver`` would allocate."""
+    lib = library()
+    P = Y.shape[0] if Y is not None else params.pop("P")
+    pb = _problem(A, Y, P, None)
+    prm, sid = _params(solver, A, P, params)
+    nbytes = ctypes.c_size_t(0)
+    _lib.check(lib.csrec_workspace_bytes(sid, ctypes.byref(pb), ctypes.byref(prm), ctypes.byref(nbytes)),
+               "csrec_workspace_bytes")
+    return nbytes.value
+
+
+def _params(solver, A, P, kw):
+    if solver == "fista":
+        p = _lib.FistaParams()
+        p.struct_size = ctypes.sizeof(p)
+        p.max_iter = int(kw.get("max_iter", 100))
+        p.lambda_ = float(kw.get("lam", 0.0))
+        p.L = float(kw.get("L", 0.0))
+        p.eps = float(kw.get("eps", 0.0))
+        x0 = kw.get("X0")
+        p.X0 = x0.data_ptr() if x0 is not None else 0
+        p.prec = _lib.PREC[kw.get("prec", "f32")]
+        p.correction_iters = int(kw.get("correction_iters", 0))
+        return p, _lib.SOLVER_FISTA
+    if solver == "gomp":
+        p = _lib.GompParams()
+        p.struct_size = ctypes.sizeof(p)
+        p.K = int(kw["K"])
+        p.S = int(kw.get("S", 1))
+        p.max_iter = int(kw.get("max_iter", 0))
+        p.res_tol = float(kw.get("res_tol", 0.0))
+        p.eps = float(kw.get("eps", 0.0))
+        p.prune = _lib.PRUNE[kw.get("prune", "each")]
+        p.prec = _lib.PREC[kw.get("prec", "f32")]
+        p.pivot_fallback = float(kw.get("pivot_fallback", 0.0))
+        return p, _lib.SOLVER_GOMP
+    if solver == "cosamp":
+        p = _lib.CosampParams()
+        p.struct_size = ctypes.sizeof(p)
+        p.K = int(kw["K"])
+        p.max_iter = int(kw.get("max_iter", 30))
+        p.eps = float(kw.get("eps", 0.0))
+        p.res_tol = float(kw.get("res_tol", 0.0))
+        p.prec = _lib.PREC[kw.get("prec", "f32")]
+        return p, _lib.SOLVER_COSAMP
+    if solver == "biht":
+        p = _lib.BihtParams()
+        p.struct_size = ctypes.sizeof(p)
+        p.K = int(kw["K"])
+        p.max_iter = int(kw.get("max_iter", 100))
+        p.mu = float(kw.get("mu", 0.1))
+        p.eps = float(kw.get("eps", 0.0))
+        p.res_tol = float(kw.get("res_tol", 0.0))
+        p.mode = _lib.BIHT_MODE[kw.get("mode", "real")]
+        ys = kw.get("Ysign")
+        p.Ysign = ys.data_ptr() if ys is not None else 0
+        p.prec = _lib.PREC[kw.get("prec", "f32")]
+        return p, _lib.SOLVER_BIHT
+    raise ValueError(solver)
+
+
+def fista(A, Y, lam: float, L: float = 0.0, max_iter: int = 100, eps: float = 0.0, X0=None,
+          prec: str = "f32", correction_iters: int = 0, stream=None, out=None):
+    """FISTA (Alg. 1) on every pixel: returns (X (P x N), stats)."""
+    torch = _torch()
+    lib = library()
+    _check_dev("A", A, torch.float32)
+    M, N = A.shape
+    _check_dev("Y", Y, torch.float32)
+    P = Y.shape[0]
+    if Y.shape[1] != M:
+        raise ValueError("Y must be P x M")
+    if X0 is not None:
+        _check_dev("X0", X0, torch.float32, (P, N))
+    pb = _problem(A, Y, P, stream)
+    prm, sid = _params("fista", A, P, dict(lam=lam, L=L, max_iter=max_iter, eps=eps, X0=X0, prec=prec,
+                                           correction_iters=correction_iters))
+    ws = _workspace(lib, sid, pb, prm, A.device)
+    X = out if out is not None else torch.empty((P, N), dtype=torch.float32, device=A.device)
+    st = torch.empty((max(P, 1), 4), dtype=torch.int32, device=A.device)
+    _lib.check(lib.csrec_fista(ctypes.byref(pb), ctypes.byref(prm), _ptr(X), _ptr(st)), "csrec_fista")
+    _keep_alive(ws, A.device, stream)
+    return X, _stats_view(st[:P])
+
+
+def _keep_alive(ws, device, stream):
+    # the workspace must outlive the enqueued kernels: tie it to the stream
+    if ws is not None:
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        if hasattr(s, "cuda_stream"):
+            ws.record_stream(s)
+
+
+def _greedy(solver, entry, A, Y, P, stream, kw):
+    torch = _torch()
+    lib = library()
+    _check_dev("A", A, torch.float32)
+    M, N = A.shape
+    if Y is not None:
+        _check_dev("Y", Y, torch.float32)
+        if Y.shape[1] != M:
+            raise ValueError("Y must be P x M")
+    pb = _problem(A, Y, P, stream)
+    prm, sid = _params(solver, A, P, kw)
+    ws = _workspace(lib, sid, pb, prm, A.device)
+    K = int(kw["K"])
+    X = torch.empty((P, N), dtype=torch.float32, device=A.device)
+    S = torch.empty((max(P, 1), K), dtype=torch.int32, device=A.device)
+    st = torch.empty((max(P, 1), 4), dtype=torch.int32, device=A.device)
+    fn = getattr(lib, entry)
+    _lib.check(fn(ctypes.byref(pb), ctypes.byref(prm), _ptr(X), _ptr(S), _ptr(st)), entry)
+    _keep_alive(ws, A.device, stream)
+    return X, S[:P], _stats_view(st[:P])
+
+
+def gomp(A, Y, K: int, S: int = 1, max_iter: int = 0, res_tol: float = 0.0, eps: float = 0.0,
+         prune: str = "each", prec: str = "f32", pivot_fallback: float = 0.0, stream=None):
+    """gOMP (Alg. 3) on every pixel: returns (X, support (P x K, ascending, -1 padded), stats)."""
+    return _greedy("gomp", "csrec_gomp", A, Y, Y.shape[0], stream,
+                   dict(K=K, S=S, max_iter=max_iter, res_tol=res_tol, eps=eps, prune=prune, prec=prec,
+                        pivot_fallback=pivot_fallback))
+
+
+def cosamp(A, Y, K: int, max_iter: int = 30, eps: float = 0.0, res_tol: float = 0.0,
+           prec: str = "f32", stream=None):
+    """CoSaMP (Alg. 5) on every pixel: returns (X, support, stats)."""
+    return _greedy("cosamp", "csrec_cosamp", A, Y, Y.shape[0], stream,
+                   dict(K=K, max_iter=max_iter, eps=eps, res_tol=res_tol, prec=prec))
+
+
+def biht(A, Y, K: int, max_iter: int = 100, mu: float = 0.1, eps: float = 0.0, res_tol: float = 0.0,
+         mode: str = "real", Ysign=None, prec: str = "f32", stream=None):
+    """BIHT: backtracking IHT (Alg. 4, mode='real') or binary IHT on int8
+    signs (mode='one_bit', not from the paper).  Returns (X, support, stats)."""
+    torch = _torch()
+    if mode == "one_bit":
+        _check_dev("Ysign", Ysign, torch.int8)
+        P = Ysign.shape[0]
+    else:
+        P = Y.shape[0]
+    return _greedy("biht", "csrec_biht", A, Y if mode != "one_bit" else None, P, stream,
+                   dict(K=K, max_iter=max_iter, mu=mu, eps=eps, res_tol=res_tol, mode=mode, Ysign=Ysign,
+                        prec=prec))
+
+
+def lipschitz(A, stream=None):
+    """L = lambda_max(A^T A) by power iteration on the GPU (float32 tensor of one element)."""
+    torch = _torch()
+    lib = library()
+    _check_dev("A", A, torch.float32)
+    M, N = A.shape
+    out = torch.empty(1, dtype=torch.float32, device=A.device)
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    _lib.check(lib.csrec_lipschitz(_ptr(A), M, N, _ptr(out), ctypes.c_void_p(s.cuda_stream)),
+               "csrec_lipschitz")
+    return out

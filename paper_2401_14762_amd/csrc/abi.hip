@@ -1,0 +1,260 @@
+// C-ABI entry points of libcsrec: argument validation, workspace sizing and
+// dispatch to the kernels.  No device memory is allocated here.
+#include <cmath>
+#include <cstring>
+
+#include "common.hpp"
+
+namespace csrec {
+namespace {
+thread_local int32_t g_last_hip_error = 0;
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+int check_problem(const csrec_problem* p, bool needs_Y) {
+    if (!p) return CSREC_E_INVAL;
+    if (p->struct_size != (int32_t)sizeof(csrec_problem)) return CSREC_E_INVAL;
+    if (p->M < 1 || p->N > CSREC_MAX_N || p->M >= p->N || p->P < 0) return CSREC_E_SHAPE;
+    if (p->P > 0 && (!p->A || (needs_Y && !p->Y))) return CSREC_E_INVAL;
+    if (!p->A) return CSREC_E_INVAL;
+    return CSREC_OK;
+}
+
+int check_prec(int32_t prec) {
+    return (prec == CSREC_PREC_F32 || prec == CSREC_PREC_BF16 || prec == CSREC_PREC_F16) ? CSREC_OK
+                                                                                           : CSREC_E_INVAL;
+}
+
+int check_fista(const csrec_problem* p, const csrec_fista_params* f) {
+    int e = check_problem(p, true);
+    if (e) return e;
+    if (!f || f->struct_size != (int32_t)sizeof(csrec_fista_params)) return CSREC_E_INVAL;
+    if (f->max_iter < 0 || !finite_nonneg(f->lambda) || !finite_nonneg(f->L) || !finite_nonneg(f->eps))
+        return CSREC_E_INVAL;
+    if (f->correction_iters < 0) return CSREC_E_INVAL;
+    if ((e = check_prec(f->prec))) return e;
+    return fista_supported(p->M, p->N, f->prec);
+}
+
+int fill_gomp(const csrec_problem* p, const csrec_gomp_params* q, GreedyLaunch& l) {
+    int e = check_problem(p, true);
+    if (e) return e;
+    if (!q || q->struct_size != (int32_t)sizeof(csrec_gomp_params)) return CSREC_E_INVAL;
+    if (q->K < 1 || q->S < 1 || q->S > 8 || q->max_iter < 0) return CSREC_E_INVAL;
+    if (!finite_nonneg(q->res_tol) || !finite_nonneg(q->eps) || !finite_nonneg(q->pivot_fallback))
+        return CSREC_E_INVAL;
+    if (q->prune != CSREC_PRUNE_EACH && q->prune != CSREC_PRUNE_FINAL) return CSREC_E_INVAL;
+    if ((e = check_prec(q->prec))) return e;
+    if (q->prec != CSREC_PREC_F32) return CSREC_E_UNSUPPORTED;
+    const int imax = q->max_iter > 0 ? q->max_iter : (q->K < p->M / q->S ? q->K : p->M / q->S);
+    if (imax < 1) return CSREC_E_INVAL;
+    if (q->S * imax > p->M || q->S * imax > GREEDY_CMAX || q->K > GREEDY_CMAX) return CSREC_E_SHAPE;
+    if (p->M > 96) return CSREC_E_UNSUPPORTED;
+    l = GreedyLaunch{};
+    l.kind = GREEDY_GOMP;
+    l.K = q->K;
+    l.S = q->S;
+    l.max_iter = imax;
+    l.prune = q->prune;
+    l.prec = q->prec;
+    l.res_tol = (float)q->res_tol;
+    l.eps = (float)q->eps;
+    l.pivot_fallback = q->pivot_fallback;
+    return CSREC_OK;
+}
+
+int fill_cosamp(const csrec_problem* p, const csrec_cosamp_params* q, GreedyLaunch& l) {
+    int e = check_problem(p, true);
+    if (e) return e;
+    if (!q || q->struct_size != (int32_t)sizeof(csrec_cosamp_params)) return CSREC_E_INVAL;
+    if (q->K < 1 || q->max_iter < 0 || !finite_nonneg(q->eps) || !finite_nonneg(q->res_tol))
+        return CSREC_E_INVAL;
+    if ((e = check_prec(q->prec))) return e;
+    if (q->prec != CSREC_PREC_F32) return CSREC_E_UNSUPPORTED;
+    if (3 * q->K > p->M || 3 * q->K > GREEDY_CMAX) return CSREC_E_SHAPE;
+    if (p->M > 96) return CSREC_E_UNSUPPORTED;
+    l = GreedyLaunch{};
+    l.kind = GREEDY_COSAMP;
+    l.K = q->K;
+    l.S = 1;
+    l.max_iter = q->max_iter;
+    l.prec = q->prec;
+    l.res_tol = (float)q->res_tol;
+    l.eps = (float)q->eps;
+    return CSREC_OK;
+}
+
+int fill_biht(const csrec_problem* p, const csrec_biht_params* q, GreedyLaunch& l) {
+    if (!q || q->struct_size != (int32_t)sizeof(csrec_biht_params)) return CSREC_E_INVAL;
+    const bool one = q->mode == CSREC_BIHT_ONE_BIT;
+    if (!one && q->mode != CSREC_BIHT_REAL) return CSREC_E_INVAL;
+    int e = check_problem(p, !one);
+    if (e) return e;
+    if (one && p->P > 0 && !q->Ysign) return CSREC_E_INVAL;
+    if (q->K < 1 || q->max_iter < 0 || !std::isfinite(q->mu) || !finite_nonneg(q->eps) ||
+        !finite_nonneg(q->res_tol))
+        return CSREC_E_INVAL;
+    if ((e = check_prec(q->prec))) return e;
+    if (q->prec != CSREC_PREC_F32) return CSREC_E_UNSUPPORTED;
+    if (one ? (q->K > p->N || q->K > GREEDY_CMAX) : (2 * q->K > p->M || 2 * q->K > GREEDY_CMAX))
+        return CSREC_E_SHAPE;
+    if (p->M > 96) return CSREC_E_UNSUPPORTED;
+    l = GreedyLaunch{};
+    l.kind = one ? GREEDY_BIHT_ONE_BIT : GREEDY_BIHT;
+    l.K = q->K;
+    l.S = 1;
+    l.max_iter = q->max_iter;
+    l.prec = q->prec;
+    l.res_tol = (float)q->res_tol;
+    l.eps = (float)q->eps;
+    l.mu = (float)q->mu;
+    l.Ysign = q->Ysign;
+    return CSREC_OK;
+}
+
+void fill_problem(const csrec_problem* p, GreedyLaunch& l) {
+    l.A = p->A;
+    l.Y = p->Y;
+    l.M = p->M;
+    l.N = p->N;
+    l.P = p->P;
+    l.workspace = p->workspace;
+    l.workspace_bytes = p->workspace_bytes;
+    l.stream = reinterpret_cast<hipStream_t>(p->stream);
+}
+
+int run_greedy(GreedyLaunch& l, float* X, int32_t* support, csrec_pixel_stats* stats) {
+    if (l.P > 0 && !X) return CSREC_E_INVAL;
+    l.X = X;
+    l.support = support;
+    l.stats = stats;
+    if (l.P == 0) return CSREC_OK;
+    const size_t need = greedy_workspace(l);
+    if (!l.workspace || l.workspace_bytes < need) return CSREC_E_WORKSPACE;
+    return greedy_launch(l);
+}
+}  // namespace
+
+void set_hip_error(hipError_t e) { g_last_hip_error = (int32_t)e; }
+
+}  // namespace csrec
+
+using namespace csrec;
+
+extern "C" {
+
+int32_t csrec_abi_version(void) { return CSREC_ABI_VERSION; }
+
+const char* csrec_strerror(int32_t code) {
+    switch (code) {
+        case CSREC_OK: return "ok";
+        case CSREC_E_INVAL: return "invalid argument";
+        case CSREC_E_SHAPE: return "unsupported or invalid shape";
+        case CSREC_E_WORKSPACE: return "workspace missing or too small";
+        case CSREC_E_DEVICE: return "HIP runtime error";
+        case CSREC_E_UNSUPPORTED: return "precision or mode not supported for this solver/shape";
+        case CSREC_E_BUDGET: return "request exceeds the server's HBM budget";
+        default: return "unknown error";
+    }
+}
+
+int32_t csrec_last_hip_error(void) { return g_last_hip_error; }
+
+int32_t csrec_workspace_bytes(int32_t solver, const csrec_problem* problem, const void* params,
+                              size_t* bytes) {
+    if (!bytes) return CSREC_E_INVAL;
+    *bytes = 0;
+    int e = CSREC_OK;
+    GreedyLaunch l{};
+    switch (solver) {
+        case CSREC_SOLVER_FISTA: {
+            const auto* f = static_cast<const csrec_fista_params*>(params);
+            if ((e = check_fista(problem, f))) return e;
+            *bytes = fista_workspace(problem->M, problem->N, problem->P, f->prec) + (f->L == 0.0 ? 256 : 0);
+            return CSREC_OK;
+        }
+        case CSREC_SOLVER_GOMP:
+            e = fill_gomp(problem, static_cast<const csrec_gomp_params*>(params), l);
+            break;
+        case CSREC_SOLVER_COSAMP:
+            e = fill_cosamp(problem, static_cast<const csrec_cosamp_params*>(params), l);
+            break;
+        case CSREC_SOLVER_BIHT:
+            e = fill_biht(problem, static_cast<const csrec_biht_params*>(params), l);
+            break;
+        default: return CSREC_E_INVAL;
+    }
+    if (e) return e;
+    fill_problem(problem, l);
+    *bytes = problem->P > 0 ? greedy_workspace(l) : 0;
+    return CSREC_OK;
+}
+
+int32_t csrec_fista(const csrec_problem* problem, const csrec_fista_params* params, float* X,
+                    csrec_pixel_stats* stats) {
+    int e = check_fista(problem, params);
+    if (e) return e;
+    if (problem->P == 0) return CSREC_OK;
+    if (!X) return CSREC_E_INVAL;
+    FistaLaunch l{};
+    l.A = problem->A;
+    l.Y = problem->Y;
+    l.X0 = params->X0;
+    l.X = X;
+    l.stats = stats;
+    l.M = problem->M;
+    l.N = problem->N;
+    l.P = problem->P;
+    l.max_iter = params->max_iter;
+    l.eps = (float)params->eps;
+    l.lambda = params->lambda;
+    l.prec = params->prec;
+    l.stream = reinterpret_cast<hipStream_t>(problem->stream);
+    l.workspace = problem->workspace;
+    if (params->L > 0.0) {
+        l.invL = (float)(1.0 / params->L);
+        l.thr = (float)(params->lambda / params->L);
+        l.L_dev = nullptr;
+    } else {
+        if (!problem->workspace || problem->workspace_bytes < 256) return CSREC_E_WORKSPACE;
+        float* Ld = static_cast<float*>(problem->workspace);
+        if ((e = lipschitz_launch(problem->A, problem->M, problem->N, Ld, l.stream))) return e;
+        l.L_dev = Ld;
+    }
+    return fista_launch(l);
+}
+
+int32_t csrec_gomp(const csrec_problem* problem, const csrec_gomp_params* params, float* X,
+                   int32_t* support, csrec_pixel_stats* stats) {
+    GreedyLaunch l{};
+    int e = fill_gomp(problem, params, l);
+    if (e) return e;
+    fill_problem(problem, l);
+    return run_greedy(l, X, support, stats);
+}
+
+int32_t csrec_cosamp(const csrec_problem* problem, const csrec_cosamp_params* params, float* X,
+                     int32_t* support, csrec_pixel_stats* stats) {
+    GreedyLaunch l{};
+    int e = fill_cosamp(problem, params, l);
+    if (e) return e;
+    fill_problem(problem, l);
+    return run_greedy(l, X, support, stats);
+}
+
+int32_t csrec_biht(const csrec_problem* problem, const csrec_biht_params* params, float* X,
+                   int32_t* support, csrec_pixel_stats* stats) {
+    GreedyLaunch l{};
+    int e = fill_biht(problem, params, l);
+    if (e) return e;
+    fill_problem(problem, l);
+    return run_greedy(l, X, support, stats);
+}
+
+int32_t csrec_lipschitz(const float* A, int32_t M, int32_t N, float* L_out, void* stream) {
+    if (!A || !L_out) return CSREC_E_INVAL;
+    if (M < 1 || M >= N || N > CSREC_MAX_N) return CSREC_E_SHAPE;
+    return lipschitz_launch(A, M, N, L_out, reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Internal helpers shared by the HIP sources of libcsrec (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/csrec.h"
+
+namespace csrec {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Records the last HIP error of the calling thread (see csrec_last_hip_error).
+void set_hip_error(hipError_t e);
+
+#define CSREC_HIP_TRY(expr)                     \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess) {                 \
+            ::csrec::set_hip_error(e_);         \
+            return CSREC_E_DEVICE;              \
+        }                                       \
+    } while (0)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
+
+// ---------------------------------------------------------------- launchers
+// Each returns CSREC_OK or an error code; arguments are already validated.
+
+struct FistaLaunch {
+    const float* A;
+    const float* Y;
+    const float* X0;
+    float* X;
+    csrec_pixel_stats* stats;
+    int M, N;
+    int64_t P;
+    int max_iter;
+    float invL;           // 1 / L
+    float thr;            // lambda / L
+    float eps;
+    const float* L_dev;   // device L when the host value is 0 (power iteration)
+    double lambda;
+    int prec;
+    void* workspace;
+    hipStream_t stream;
+};
+
+int fista_supported(int M, int N, int prec);
+size_t fista_workspace(int M, int N, int64_t P, int prec);
+int fista_launch(const FistaLaunch& a);
+
+int lipschitz_launch(const float* A, int M, int N, float* L_out, hipStream_t stream);
+
+enum GreedyKind { GREEDY_GOMP = 0, GREEDY_COSAMP = 1, GREEDY_BIHT = 2, GREEDY_BIHT_ONE_BIT = 3 };
+
+struct GreedyLaunch {
+    GreedyKind kind;
+    const float* A;
+    const float* Y;
+    const int8_t* Ysign;
+    float* X;
+    int32_t* support;
+    csrec_pixel_stats* stats;
+    int M, N;
+    int64_t P;
+    int K, S, max_iter;
+    int prune;
+    int prec;
+    float res_tol, eps, mu;
+    double pivot_fallback;
+    void* workspace;
+    size_t workspace_bytes;
+    hipStream_t stream;
+};
+
+// Largest support the least-squares state can hold.
+constexpr int GREEDY_CMAX = 64;
+
+size_t greedy_workspace(const GreedyLaunch& a);
+int greedy_launch(const GreedyLaunch& a);
+
+}  // namespace csrec

@@ -1,0 +1,399 @@
+// FISTA (Alg. 1) for P independent LASSO problems (Eq. 2) sharing one A.
+//
+// Work decomposition.  One wavefront owns 16 pixels for the whole solve.
+// The dictionary A lives once per workgroup in LDS; every per-pixel vector
+// (x^{i-1}, z^{i-1}, A x^{i-1} - y, A x^{i-2} - y, y) lives in VGPRs for all
+// iterations, so the loop touches HBM only to read y at the start and to
+// write x at the end.
+//
+// Arithmetic per iteration i (all of Alg. 1, per pixel):
+//   U_k = A x^k - y  (= -r^k, step 5) is carried instead of recomputed, and
+//   A z^{i-1} - y = (1 + b_{i-1}) U_{i-1} - b_{i-1} U_{i-2}
+//   with b_k = (t^{k-1} - 1) / t^k (step 4 is linear, so A commutes with it).
+//   GEMM 2:  W = A^T V,   V = A z^{i-1} - y        (step 1)
+//   epilogue: aux = z - W / L; x^i = soft(aux, lambda / L); z^i = x^i + b_i (x^i - x^{i-1})
+//   GEMM 1:  U_i = A x^i - y                         (step 5)
+//   Delta = ||U_i - U_{i-1}||_2                      (step 5; r^0 = y)
+// so an iteration costs 4 M N flops per pixel instead of the 6 M N of the
+// literal form.
+//
+// MFMA mapping (v_mfma_f32_16x16x4f32, D[16x16] += A[16x4] B[4x16]).
+// Pixels are the 16 columns j of every product.  Lane l = 16 h + j holds,
+// for its pixel j, the elements of tile t with register r:
+//   n = 16 t + c_n(h, r),  c_n(h, r) = 4 r + h                 (x, z, W)
+//   m = 16 t + c_m(h, r),  c_m(h, r) = 8 (h & 1) + 4 (h >> 1) + r  (U, V, y)
+// which is exactly the D-register layout of one product and the B-operand
+// layout of the next: in k-step kk of a 16-wide contraction tile, group h
+// contributes the index c(h, kk), i.e. its own register kk.  The products
+// therefore chain register to register.  The two index permutations make the
+// single LDS copy of A (row pitch 16*NT+2, an even number whose half is odd)
+// bank-conflict free for both the A (GEMM 1) and the A^T (GEMM 2) operand
+// reads.
+#include "common.hpp"
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <cmath>
+
+namespace csrec {
+namespace {
+
+struct FistaArgs {
+    const float* A;
+    const float* Y;
+    const float* X0;
+    float* X;
+    csrec_pixel_stats* stats;
+    const float* L_dev;
+    int M, N;
+    int64_t P;
+    int max_iter;
+    float invL, thr, eps;
+    double lambda;
+};
+
+__device__ __forceinline__ float soft_thr(float v, float t) {
+    // sign(v) * max(|v| - t, 0)
+    const float a = fabsf(v) - t;
+    return a > 0.f ? copysignf(a, v) : 0.f;
+}
+
+__device__ __forceinline__ float quad_sum(float v) {
+    // sum over the four lanes j, j+16, j+32, j+48 that hold one pixel
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
+template <int MT, int NT, int WAVES, int MINW>
+__global__ __launch_bounds__(WAVES * 64, MINW) void fista_f32_kernel(FistaArgs a) {
+    constexpr int PA = 16 * NT + 2;   // LDS row pitch of A (floats)
+    constexpr int ROWS = 16 * MT;
+    __shared__ float sA[ROWS * PA];
+
+    const int M = a.M, N = a.N;
+    for (int idx = threadIdx.x; idx < ROWS * PA; idx += WAVES * 64) {
+        const int row = idx / PA;
+        const int col = idx - row * PA;
+        float v = 0.f;
+        if (row < M && col < N) v = a.A[(size_t)row * N + col];
+        sA[idx] = v;
+    }
+
+    float invL = a.invL, thr = a.thr;
+    if (a.L_dev) {
+        const float L = *a.L_dev;
+        invL = 1.f / L;
+        thr = (float)(a.lambda / (double)L);
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 4;
+    const int j = lane & 15;
+    const int64_t pix = ((int64_t)blockIdx.x * WAVES + wave) * 16 + j;
+    const bool valid = pix < a.P;
+
+    const int mu_j = 8 * ((j >> 2) & 1) + 4 * (j >> 3) + (j & 3);  // m of output row j (GEMM 1)
+    const int nu_j = 4 * (j & 3) + (j >> 2);                       // n of output row j (GEMM 2)
+    const int cm_h = 8 * (h & 1) + 4 * (h >> 1);
+    const float* a1 = sA + mu_j * PA + h;      // + 16 mt PA + 16 nt + 4 kk
+    const float* a2 = sA + cm_h * PA + nu_j;   // + (16 mt + kk) PA + 16 nt
+
+    // ---- measurements, non-finite check
+    v4f Yr[MT];
+    int bad = 0;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * mt + cm_h + r;
+            float v = 0.f;
+            if (valid && m < M) {
+                v = a.Y[pix * M + m];
+                if (!isfinite(v)) bad = 1;
+            }
+            Yr[mt][r] = v;
+        }
+    bad |= __shfl_xor(bad, 16);
+    bad |= __shfl_xor(bad, 32);
+    if (bad) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) Yr[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+
+    // ---- starting point x^0 (z^0 = x^0)
+    v4f Xr[NT], Zr[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * nt + 4 * r + h;
+            float v = 0.f;
+            if (a.X0 && valid && !bad && n < N) v = a.X0[pix * N + n];
+            Xr[nt][r] = v;
+            Zr[nt][r] = v;
+        }
+
+    // U_0 = A x^0 - y; U_{-1} = U_0 (so z^0 = x^0 whatever b_0 is)
+    v4f U1[MT], V[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) U1[mt] = -Yr[mt];
+    if (a.X0) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    U1[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                        a1[16 * mt * PA + 16 * nt + 4 * kk], Xr[nt][kk], U1[mt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) V[mt] = U1[mt];
+
+    bool active = valid && !bad;
+    bool converged = false;
+    int iters = 0;
+    float last_d2 = __builtin_nanf("");
+    double t = 1.0;
+    float bprev = 0.f;
+    const bool check_eps = a.eps > 0.f;
+
+    for (int it = 0; it < a.max_iter; ++it) {
+        const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));   // step 3
+        const float bcur = (float)((t - 1.0) / tn);                  // step 4 coefficient
+        t = tn;
+
+        // V = A z^{i-1} - y
+        const float cp = 1.f + bprev;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) V[mt] = cp * U1[mt] - bprev * V[mt];
+
+        v4f Un[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) Un[mt] = -Yr[mt];
+
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            // W = (A^T V) for 16 n-values of this tile          (step 1)
+            v4f W = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    W = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[(16 * mt + kk) * PA + 16 * nt],
+                                                             V[mt][kk], W, 0, 0, 0);
+            // steps 1, 2, 4 elementwise
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float aux = Zr[nt][r] - W[r] * invL;
+                const float xn = soft_thr(aux, thr);
+                const float zn = xn + bcur * (xn - Xr[nt][r]);
+                Xr[nt][r] = active ? xn : Xr[nt][r];
+                Zr[nt][r] = active ? zn : Zr[nt][r];
+            }
+            // U_i += A(:, tile) x^i(tile)                        (step 5)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    Un[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                        a1[16 * mt * PA + 16 * nt + 4 * kk], Xr[nt][kk], Un[mt], 0, 0, 0);
+        }
+
+        // Delta^2 = ||r^i - r^{i-1}||^2 with r^0 = y: the reference is U_{i-1},
+        // except in the first iteration from a given x^0, where it is -y.
+        const float c0 = (it == 0 && a.X0) ? 1.f : 0.f;
+        float d2 = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float ref = U1[mt][r] - c0 * (U1[mt][r] + Yr[mt][r]);
+                const float d = Un[mt][r] - ref;
+                d2 += d * d;
+            }
+        d2 = quad_sum(d2);
+        if (active) {
+            iters = it + 1;
+            last_d2 = d2;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            V[mt] = U1[mt];
+            U1[mt] = active ? Un[mt] : U1[mt];
+        }
+        bprev = bcur;
+        if (check_eps) {
+            if (active && sqrtf(d2) < a.eps) {
+                active = false;
+                converged = true;
+            }
+            if (!__any(active)) break;
+        }
+    }
+
+    float r2 = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) r2 += U1[mt][r] * U1[mt][r];
+    r2 = quad_sum(r2);
+
+    if (valid) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * nt + 4 * r + h;
+                if (n < N) a.X[pix * N + n] = bad ? 0.f : Xr[nt][r];
+            }
+        if (a.stats && h == 0) {
+            csrec_pixel_stats s;
+            s.iters = bad ? 0 : iters;
+            s.flags = bad ? CSREC_FLAG_NONFINITE : (converged ? CSREC_FLAG_CONVERGED : CSREC_FLAG_ITER_CAP);
+            s.resid = bad ? 0.f : sqrtf(r2);
+            s.delta = bad ? __builtin_nanf("") : sqrtf(last_d2);
+            a.stats[pix] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+
+typedef void (*fista_kernel_t)(FistaArgs);
+
+struct FistaVariant {
+    int MT, NT, waves;
+    fista_kernel_t fn;
+};
+
+// Tile shapes instantiated: the 2.5x-compressed band counts of the paper's
+// cubes and the synthetic workloads (N = 100, 154, 198/200, 224) plus
+// general shapes.  A shape runs on the smallest variant covering it; the
+// extra rows/columns of A are zero in LDS.
+const FistaVariant kVariants[] = {
+    {1, 2, 4, fista_f32_kernel<1, 2, 4, 2>},
+    {2, 4, 4, fista_f32_kernel<2, 4, 4, 2>},
+    {3, 7, 4, fista_f32_kernel<3, 7, 4, 2>},
+    {4, 8, 4, fista_f32_kernel<4, 8, 4, 2>},
+    {4, 10, 4, fista_f32_kernel<4, 10, 4, 1>},
+    {5, 13, 4, fista_f32_kernel<5, 13, 4, 1>},
+    {6, 14, 4, fista_f32_kernel<6, 14, 4, 1>},
+    {7, 16, 4, fista_f32_kernel<7, 16, 4, 1>},
+    {8, 16, 4, fista_f32_kernel<8, 16, 4, 1>},
+};
+
+const FistaVariant* pick_f32(int M, int N) {
+    const int mt = (int)ceil_div(M, 16), nt = (int)ceil_div(N, 16);
+    const FistaVariant* best = nullptr;
+    for (const auto& v : kVariants)
+        if (v.MT >= mt && v.NT >= nt && (!best || v.MT * v.NT < best->MT * best->NT)) best = &v;
+    return best;
+}
+
+}  // namespace
+
+int fista_supported(int M, int N, int prec) {
+    if (prec == CSREC_PREC_F32) return pick_f32(M, N) ? CSREC_OK : CSREC_E_UNSUPPORTED;
+    return CSREC_E_UNSUPPORTED;
+}
+
+size_t fista_workspace(int, int, int64_t, int) { return 0; }
+
+int fista_launch(const FistaLaunch& l) {
+    if (l.P == 0) return CSREC_OK;
+    const FistaVariant* v = pick_f32(l.M, l.N);
+    if (!v) return CSREC_E_UNSUPPORTED;
+    FistaArgs a;
+    a.A = l.A;
+    a.Y = l.Y;
+    a.X0 = l.X0;
+    a.X = l.X;
+    a.stats = l.stats;
+    a.L_dev = l.L_dev;
+    a.M = l.M;
+    a.N = l.N;
+    a.P = l.P;
+    a.max_iter = l.max_iter;
+    a.invL = l.invL;
+    a.thr = l.thr;
+    a.eps = l.eps;
+    a.lambda = l.lambda;
+    const int64_t pix_per_block = 16 * v->waves;
+    const int64_t blocks = ceil_div(l.P, pix_per_block);
+    if (blocks > 0x7fffffff) return CSREC_E_SHAPE;
+    hipLaunchKernelGGL(v->fn, dim3((unsigned)blocks), dim3(64 * v->waves), 0, l.stream, a);
+    CSREC_HIP_TRY(hipGetLastError());
+    return CSREC_OK;
+}
+
+// ---------------------------------------------------------------- L by power iteration
+
+namespace {
+// L = lambda_max(A^T A) (Eq. 2): power iteration v <- A^T A v / ||A^T A v||
+// with the Rayleigh quotient ||A v||^2 (||v|| = 1) as the estimate.  One
+// workgroup; A is small (at most 256 x 256) and read from L2.
+__device__ float block_sum(float v, float* red) {
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    const float out = red[0];
+    __syncthreads();
+    return out;
+}
+
+__global__ __launch_bounds__(256) void lipschitz_kernel(const float* __restrict__ A, int M, int N,
+                                                        float* __restrict__ L_out, int iters) {
+    __shared__ float v[CSREC_MAX_N];
+    __shared__ float u[CSREC_MAX_N];
+    __shared__ float w[CSREC_MAX_N];
+    __shared__ float red[256];
+    const int tid = threadIdx.x;
+    float part = 0.f;
+    for (int n = tid; n < N; n += 256) {
+        v[n] = 1.f + 0.01f * (float)(n % 7);
+        part += v[n] * v[n];
+    }
+    float inv = 1.f / sqrtf(block_sum(part, red));
+    for (int n = tid; n < N; n += 256) v[n] *= inv;
+    __syncthreads();
+    float lam = 0.f;
+    for (int it = 0; it < iters; ++it) {
+        part = 0.f;
+        for (int m = tid; m < M; m += 256) {
+            float s = 0.f;
+            for (int n = 0; n < N; ++n) s += A[(size_t)m * N + n] * v[n];
+            u[m] = s;
+            part += s * s;
+        }
+        lam = block_sum(part, red);          // ||A v||^2
+        part = 0.f;
+        for (int n = tid; n < N; n += 256) {
+            float s = 0.f;
+            for (int m = 0; m < M; ++m) s += A[(size_t)m * N + n] * u[m];
+            w[n] = s;
+            part += s * s;
+        }
+        inv = 1.f / sqrtf(block_sum(part, red));
+        for (int n = tid; n < N; n += 256) v[n] = w[n] * inv;
+        __syncthreads();
+    }
+    if (tid == 0) *L_out = lam;
+}
+}  // namespace
+
+int lipschitz_launch(const float* A, int M, int N, float* L_out, hipStream_t stream) {
+    hipLaunchKernelGGL(lipschitz_kernel, dim3(1), dim3(256), 0, stream, A, M, N, L_out, 400);
+    CSREC_HIP_TRY(hipGetLastError());
+    return CSREC_OK;
+}
+
+}  // namespace csrec

@@ -1,0 +1,721 @@
+// Greedy solvers -- gOMP (Alg. 3), BIHT (Alg. 4), CoSaMP (Alg. 5) and
+// binary IHT on sign measurements -- for P independent pixels sharing A.
+//
+// Work decomposition.  One lane owns one pixel and runs the algorithm's
+// steps in the paper's order.  A^T sits in LDS (row n holds column n of A,
+// padded to MMAX values) and is read two ways: the correlation A^T r loops
+// over n with every lane reading the same row (an LDS broadcast), and the
+// residual y - A x gathers the rows of the lane's own support.  The residual
+// r stays in VGPRs.  The least-squares state -- the Cholesky factor of the
+// Gram submatrix G[c, c] (G = A^T A), forward/back substitution vectors,
+// supports, candidate lists -- lives in a per-pixel scratch region laid out
+// [entry][pixel], so that every scratch access of a wavefront is one
+// contiguous 256-byte transaction.
+//
+// Least squares.  s = B^+ y with B = A(:, c) is solved through the normal
+// equations G[c, c] s = A(:, c)^T y with a Cholesky factor L (G[c,c] = L L^T):
+// gOMP appends its S new atoms to L column by column (bordered update), the
+// others factor G[c, c] afresh.  The squared pivot of an appended atom j is
+// d_j = G_jj - ||l||^2, the squared distance of a_j from span(A(:, c));
+// d_j / G_jj < pivot_fallback marks the pixel, which is then solved again
+// with the same code in FP64 (second pass, T = double).
+#include "common.hpp"
+
+#include <cmath>
+
+namespace csrec {
+namespace {
+
+struct GArgs {
+    const float* A;
+    const float* Y;
+    const int8_t* Ysign;
+    float* X;
+    int32_t* support;
+    csrec_pixel_stats* stats;
+    const float* G32;      // N x N Gram, FP32
+    const double* G64;     // N x N Gram, FP64 (fallback pass)
+    int M, N, K, S, Imax, prune;
+    float res_tol, eps, mu;
+    double pivot_thr;
+    // scratch
+    char* scr;             // base of the chunk scratch
+    int64_t CH;            // pixels per chunk (scratch column count)
+    int CM;                // largest support held by the factor
+    int LM;                // candidate list length
+    int64_t off_T;         // byte offset of the T-typed region
+    int64_t off_i;         // byte offset of the 32-bit region
+    int64_t off_r;         // byte offset of the per-lane residual rows
+    uint32_t* fbflag;      // per chunk pixel: 1 = redo in FP64
+};
+
+// strided scratch view: element k of this lane's column.  The lane base is
+// shared by every view of a region; offset and stride are wave-uniform.
+template <typename E>
+struct Col {
+    E* base;
+    int64_t off;
+    int64_t s;
+    __device__ __forceinline__ E& operator[](int k) const { return base[(off + k) * s]; }
+};
+
+template <typename T>
+struct Scratch {
+    Col<T> L, dinv, z, sv;   // factor (packed rows), 1/L_kk, L^{-1} b, solution
+    Col<float> ball;         // b = A^T y, N entries
+    float* rold;             // previous residual, MMAX contiguous entries of this lane
+    Col<float> lval;         // candidate list values
+    Col<int> lidx;           // candidate list indices
+    Col<int> cidx;           // support c (CM)
+    Col<int> xidx;           // support of x (CM)
+    Col<float> xval;         // values of x (CM)
+    Col<uint32_t> mask;      // bitmask over n (NW words)
+    Col<uint32_t> keep;      // second bitmask (NW words)
+};
+
+__device__ __forceinline__ int tri(int k) { return k * (k + 1) / 2; }
+
+// T-region layout (entries per pixel): L: CM(CM+1)/2, dinv: CM, z: CM, sv: CM
+// 32-bit region: ball N, lval LM, lidx LM, cidx CM, xidx CM, xval CM, mask NW, keep NW
+template <typename T>
+__device__ Scratch<T> make_scratch(const GArgs& g, int64_t local, int mmax) {
+    Scratch<T> s;
+    const int64_t CH = g.CH;
+    T* tb = reinterpret_cast<T*>(g.scr + g.off_T) + local;
+    int64_t o = 0;
+    s.L = {tb, o, CH};    o += tri(g.CM);
+    s.dinv = {tb, o, CH}; o += g.CM;
+    s.z = {tb, o, CH};    o += g.CM;
+    s.sv = {tb, o, CH};   o += g.CM;
+    uint32_t* ib = reinterpret_cast<uint32_t*>(g.scr + g.off_i) + local;
+    float* fb = reinterpret_cast<float*>(ib);
+    int* nb = reinterpret_cast<int*>(ib);
+    int64_t q = 0;
+    s.ball = {fb, q, CH}; q += g.N;
+    s.lval = {fb, q, CH}; q += g.LM;
+    s.lidx = {nb, q, CH}; q += g.LM;
+    s.cidx = {nb, q, CH}; q += g.CM;
+    s.xidx = {nb, q, CH}; q += g.CM;
+    s.xval = {fb, q, CH}; q += g.CM;
+    const int NW = (g.N + 31) / 32;
+    s.mask = {ib, q, CH}; q += NW;
+    s.keep = {ib, q, CH};
+    s.rold = reinterpret_cast<float*>(g.scr + g.off_r) + local * mmax;
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T gram(const GArgs& g, int a, int b);
+template <>
+__device__ __forceinline__ float gram<float>(const GArgs& g, int a, int b) { return g.G32[a * g.N + b]; }
+template <>
+__device__ __forceinline__ double gram<double>(const GArgs& g, int a, int b) { return g.G64[a * g.N + b]; }
+
+template <typename T>
+__device__ __forceinline__ T tsqrt(T v);
+template <>
+__device__ __forceinline__ float tsqrt<float>(float v) { return sqrtf(v); }
+template <>
+__device__ __forceinline__ double tsqrt<double>(double v) { return sqrt(v); }
+
+// Insert (v, n) into the descending list of length len (capacity cap).
+// Equal values keep the earlier (lower) index first; n increases over calls.
+__device__ __forceinline__ void list_insert(const Col<float>& lv, const Col<int>& li, int& len, int cap,
+                                            float& thr, float v, int n) {
+    if (len == cap && !(v > thr)) return;
+    int pos = (len < cap) ? len : cap - 1;
+    while (pos > 0) {
+        const float pv = lv[pos - 1];
+        if (!(v > pv)) break;
+        if (pos < cap) {
+            lv[pos] = pv;
+            li[pos] = li[pos - 1];
+        }
+        --pos;
+    }
+    lv[pos] = v;
+    li[pos] = n;
+    if (len < cap) ++len;
+    thr = lv[cap - 1 < len - 1 ? cap - 1 : len - 1];
+}
+
+// Append atom j to the factor of G[c, c] (c = cidx[0 .. nc-1]):
+//   l = L^{-1} G[c, j],  d = G_jj - ||l||^2,  L_new = [[L, 0], [l^T, sqrt(d)]]
+// and extend z = L^{-1} b_c with b_j.  Returns the pivot ratio d / G_jj.
+template <typename T>
+__device__ T chol_append(const GArgs& g, const Scratch<T>& s, int nc, int j, T bj) {
+    const int rn = tri(nc);
+    T ll = 0, lz = 0;
+    for (int k = 0; k < nc; ++k) {
+        T acc = gram<T>(g, s.cidx[k], j);
+        const int rk = tri(k);
+        for (int t = 0; t < k; ++t) acc -= s.L[rk + t] * s.L[rn + t];
+        const T lk = acc * s.dinv[k];
+        s.L[rn + k] = lk;
+        ll += lk * lk;
+        lz += lk * s.z[k];
+    }
+    const T gjj = gram<T>(g, j, j);
+    T d = gjj - ll;
+    const T ratio = d / gjj;
+    if (!(d > (T)0)) d = gjj * (T)1e-30 + (T)1e-38;
+    const T lkk = tsqrt<T>(d);
+    const T inv = (T)1 / lkk;
+    s.L[rn + nc] = lkk;
+    s.dinv[nc] = inv;
+    s.z[nc] = (bj - lz) * inv;
+    s.cidx[nc] = j;
+    return ratio;
+}
+
+// Back substitution L^T s = z on the first nc entries.
+template <typename T>
+__device__ void chol_back(const Scratch<T>& s, int nc) {
+    for (int k = nc - 1; k >= 0; --k) {
+        T acc = s.z[k];
+        for (int t = k + 1; t < nc; ++t) acc -= s.L[tri(t) + k] * s.sv[t];
+        s.sv[k] = acc * s.dinv[k];
+    }
+}
+
+// Fresh factorisation of G[c, c] for c = cidx[0 .. n-1], rhs b_c = ball[c];
+// leaves s.sv = G[c,c]^{-1} b_c.  Returns the smallest pivot ratio.
+template <typename T>
+__device__ T chol_solve_fresh(const GArgs& g, const Scratch<T>& s, int n) {
+    T rmin = (T)1;
+    for (int i = 0; i < n; ++i) {
+        const T r = chol_append<T>(g, s, i, s.cidx[i], (T)s.ball[s.cidx[i]]);
+        rmin = r < rmin ? r : rmin;
+    }
+    chol_back<T>(s, n);
+    return rmin;
+}
+
+// keep = the k entries of cidx[0..n-1] with largest |sv| ((|sv| desc, index asc)).
+template <typename T>
+__device__ void mark_top_k(const GArgs& g, const Scratch<T>& s, int n, int k) {
+    const int NW = (g.N + 31) / 32;
+    for (int w = 0; w < NW; ++w) s.keep[w] = 0u;
+    for (int a = 0; a < n; ++a) {
+        const T va = s.sv[a] < (T)0 ? -s.sv[a] : s.sv[a];
+        const int ia = s.cidx[a];
+        int rank = 0;
+        for (int b = 0; b < n && rank < k; ++b) {
+            const T vb = s.sv[b] < (T)0 ? -s.sv[b] : s.sv[b];
+            const int ib = s.cidx[b];
+            rank += (vb > va || (vb == va && ib < ia)) ? 1 : 0;
+        }
+        if (rank < k) s.keep[ia >> 5] |= 1u << (ia & 31);
+    }
+}
+
+// Writes the set bits of a bitmask (ascending) into dst; returns the count.
+__device__ __forceinline__ int extract_bits(const Col<uint32_t>& bits, int NW, const Col<int>& dst) {
+    int cnt = 0;
+    for (int w = 0; w < NW; ++w) {
+        uint32_t v = bits[w];
+        while (v) {
+            const int b = __builtin_ctz(v);
+            v &= v - 1;
+            dst[cnt++] = 32 * w + b;
+        }
+    }
+    return cnt;
+}
+
+template <int KIND, int MMAX, int SMAX, typename T>
+__global__ __launch_bounds__(512, 1) void greedy_kernel(GArgs g, int64_t p0, int64_t np, int pass) {
+    constexpr int PAT = MMAX + 4;
+    extern __shared__ float sAT[];
+    const int M = g.M, N = g.N, K = g.K;
+    for (int idx = threadIdx.x; idx < N * PAT; idx += blockDim.x) {
+        const int n = idx / PAT;
+        const int m = idx - n * PAT;
+        sAT[idx] = (m < M) ? g.A[(size_t)m * N + n] : 0.f;
+    }
+    __syncthreads();
+
+    const int64_t local = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (local >= np) return;
+    const int64_t pix = p0 + local;
+    if (pass == 1 && g.fbflag[local] == 0u) return;   // FP64 redo only for marked pixels
+    const Scratch<T> s = make_scratch<T>(g, local, MMAX);
+    const int NW = (N + 31) / 32;
+
+    // ---- measurements
+    float r[MMAX];
+    bool bad = false;
+    float ynorm2 = 0.f;
+#pragma unroll
+    for (int m = 0; m < MMAX; ++m) {
+        float v = 0.f;
+        if (m < M) {
+            if (KIND == GREEDY_BIHT_ONE_BIT) v = (float)g.Ysign[pix * M + m];
+            else v = g.Y[pix * M + m];
+            if (!isfinite(v)) bad = true;
+        }
+        r[m] = v;
+    }
+    if (bad) {
+#pragma unroll
+        for (int m = 0; m < MMAX; ++m) r[m] = 0.f;
+    }
+#pragma unroll
+    for (int m = 0; m < MMAX; ++m) ynorm2 += r[m] * r[m];
+    const float ynorm = sqrtf(ynorm2);   // (ONE_BIT: y - sgn(A 0) = y is the first "residual")
+    for (int w = 0; w < NW; ++w) s.mask[w] = 0u;
+
+    int nx = 0;          // entries in x (xidx/xval)
+    int nc = 0;          // support size c
+    int iters = 0;
+    bool converged = false;
+    bool fallback = false;
+    float last_d2 = __builtin_nanf("");
+    float rn2 = ynorm2;
+    const int Imax = bad ? 0 : g.Imax;
+
+    for (int it = 1; it <= Imax; ++it) {
+        // ---------------- step 1: correlation with the residual, candidate selection
+        float bv[SMAX];
+        int bi[SMAX];
+#pragma unroll
+        for (int q = 0; q < SMAX; ++q) {
+            bv[q] = -1.f;
+            bi[q] = -1;
+        }
+        int llen = 0;
+        float lthr = -1.f;
+        const int lcap = (KIND == GREEDY_COSAMP) ? 2 * K : K;
+        int xptr = 0;
+        uint32_t mword = 0u;
+        for (int n = 0; n < N; ++n) {
+            const float4* row = reinterpret_cast<const float4*>(sAT + n * PAT);
+            float acc = 0.f;
+#pragma unroll
+            for (int m4 = 0; m4 < MMAX / 4; ++m4) {
+                const float4 a = row[m4];
+                acc += a.x * r[4 * m4] + a.y * r[4 * m4 + 1] + a.z * r[4 * m4 + 2] + a.w * r[4 * m4 + 3];
+            }
+            if (it == 1 && KIND != GREEDY_BIHT_ONE_BIT) s.ball[n] = acc;   // A^T y
+            if (KIND == GREEDY_GOMP) {
+                if ((n & 31) == 0) mword = s.mask[n >> 5];
+                if ((mword >> (n & 31)) & 1u) continue;
+                const float v = fabsf(acc);
+                if (v > bv[SMAX - 1] || bi[SMAX - 1] < 0) {
+                    // insertion into the register list (first S slots used)
+                    float cv = v;
+                    int ci = n;
+#pragma unroll
+                    for (int q = 0; q < SMAX; ++q) {
+                        if (q < g.S && (bi[q] < 0 || cv > bv[q])) {
+                            const float tv = bv[q];
+                            const int ti = bi[q];
+                            bv[q] = cv;
+                            bi[q] = ci;
+                            cv = tv;
+                            ci = ti;
+                        }
+                    }
+                }
+            } else if (KIND == GREEDY_COSAMP) {
+                list_insert(s.lval, s.lidx, llen, lcap, lthr, fabsf(acc), n);
+            } else {
+                // u = x + mu A^T (.)  (BIHT REAL: residual; ONE_BIT: y - sgn(A x))
+                float xv = 0.f;
+                if (xptr < nx && s.xidx[xptr] == n) {
+                    xv = s.xval[xptr];
+                    ++xptr;
+                }
+                const float u = xv + g.mu * acc;
+                const float au = fabsf(u);
+                if (llen == lcap && !(au > lthr)) continue;
+                list_insert(s.lval, s.lidx, llen, lcap, lthr, au, n);
+            }
+        }
+
+        // ---------------- steps 2-3: support and least squares
+        if (KIND == GREEDY_GOMP) {
+            for (int q = 0; q < g.S; ++q) {
+                const int j = bi[q];
+                if (j < 0) break;   // no admissible atom left (non-finite correlations)
+                s.mask[j >> 5] |= 1u << (j & 31);
+                const T ratio = chol_append<T>(g, s, nc, j, (T)s.ball[j]);
+                if (g.pivot_thr > 0.0 && (double)ratio < g.pivot_thr) fallback = true;
+                ++nc;
+            }
+            chol_back<T>(s, nc);
+            if (g.prune == CSREC_PRUNE_EACH && nc > K) {
+                mark_top_k<T>(g, s, nc, K);
+                // re-solve on q: factor G[q, q] in the slots after c
+                // (the factor of G[c, c] stays intact at rows 0 .. nc-1)
+                int nq = 0;
+                for (int w = 0; w < NW; ++w) {
+                    uint32_t v = s.keep[w];
+                    while (v) {
+                        const int b = __builtin_ctz(v);
+                        v &= v - 1;
+                        s.xidx[nq++] = 32 * w + b;
+                    }
+                }
+                // factor into a temporary region: rows nc .. nc+nq-1 of L would exceed CM,
+                // so use a fresh solve on a copy of the indices placed after c.
+                for (int a = 0; a < nq; ++a) s.cidx[nc + a] = s.xidx[a];
+                // fresh factor of G[q, q] built in rows 0..nq-1 of a shifted view
+                Scratch<T> sq = s;
+                sq.L.off += tri(nc);
+                sq.dinv.off += nc;
+                sq.z.off += nc;
+                sq.sv.off += nc;
+                sq.cidx.off += nc;
+                chol_solve_fresh<T>(g, sq, nq);
+                for (int a = 0; a < nq; ++a) s.xval[a] = (float)sq.sv[a];
+                nx = nq;
+            } else {
+                for (int a = 0; a < NW; ++a) s.keep[a] = s.mask[a];
+                nx = extract_bits(s.keep, NW, s.xidx);
+                // values in the order of xidx: look them up in c
+                for (int a = 0; a < nx; ++a) {
+                    const int ia = s.xidx[a];
+                    for (int b = 0; b < nc; ++b)
+                        if (s.cidx[b] == ia) {
+                            s.xval[a] = (float)s.sv[b];
+                            break;
+                        }
+                }
+            }
+        } else if (KIND == GREEDY_COSAMP || KIND == GREEDY_BIHT) {
+            // c = candidates U (current support of x)
+            for (int w = 0; w < NW; ++w) s.mask[w] = 0u;
+            for (int a = 0; a < llen; ++a) {
+                const int j = s.lidx[a];
+                s.mask[j >> 5] |= 1u << (j & 31);
+            }
+            for (int a = 0; a < nx; ++a) {
+                if (KIND == GREEDY_BIHT && s.xval[a] == 0.f) continue;   // supp(x_a)
+                const int j = s.xidx[a];
+                s.mask[j >> 5] |= 1u << (j & 31);
+            }
+            nc = extract_bits(s.mask, NW, s.cidx);
+            chol_solve_fresh<T>(g, s, nc);
+            const int keepn = nc < K ? nc : K;
+            mark_top_k<T>(g, s, nc, keepn);
+            nx = 0;
+            for (int a = 0; a < nc; ++a) {
+                const int ia = s.cidx[a];
+                if ((s.keep[ia >> 5] >> (ia & 31)) & 1u) {
+                    s.xidx[nx] = ia;
+                    s.xval[nx] = (float)s.sv[a];
+                    ++nx;
+                }
+            }
+        } else {   // ONE_BIT: x = H_K(u), u values recomputed for the kept indices
+            // sort the kept indices ascending through the bitmask
+            for (int w = 0; w < NW; ++w) s.mask[w] = 0u;
+            for (int a = 0; a < llen; ++a) {
+                const int j = s.lidx[a];
+                s.mask[j >> 5] |= 1u << (j & 31);
+            }
+            // old x is needed to rebuild u on the kept indices: u_j = x_j + mu (A^T v)_j
+            int newn = 0;
+            int optr = 0;
+            // collect the new (index, value) pairs in the list slots
+            for (int w = 0; w < NW; ++w) {
+                uint32_t v = s.mask[w];
+                while (v) {
+                    const int b = __builtin_ctz(v);
+                    v &= v - 1;
+                    const int j = 32 * w + b;
+                    const float4* row = reinterpret_cast<const float4*>(sAT + j * PAT);
+                    float acc = 0.f;
+#pragma unroll
+                    for (int m4 = 0; m4 < MMAX / 4; ++m4) {
+                        const float4 a = row[m4];
+                        acc += a.x * r[4 * m4] + a.y * r[4 * m4 + 1] + a.z * r[4 * m4 + 2] +
+                               a.w * r[4 * m4 + 3];
+                    }
+                    float xv = 0.f;
+                    while (optr < nx && s.xidx[optr] < j) ++optr;
+                    if (optr < nx && s.xidx[optr] == j) xv = s.xval[optr];
+                    s.lidx[newn] = j;
+                    s.lval[newn] = xv + g.mu * acc;
+                    ++newn;
+                }
+            }
+            nx = newn;
+            for (int a = 0; a < nx; ++a) {
+                s.xidx[a] = s.lidx[a];
+                s.xval[a] = s.lval[a];
+            }
+        }
+
+        // ---------------- step 4: residual r = y - A x (ONE_BIT: v = y - sgn(A x))
+#pragma unroll
+        for (int m = 0; m < MMAX; ++m) {
+            s.rold[m] = r[m];
+            r[m] = (KIND == GREEDY_BIHT_ONE_BIT || m >= M || bad) ? 0.f : g.Y[pix * M + m];
+        }
+        for (int a = 0; a < nx; ++a) {
+            const float xv = (KIND == GREEDY_BIHT_ONE_BIT) ? -s.xval[a] : s.xval[a];
+            const float4* row = reinterpret_cast<const float4*>(sAT + s.xidx[a] * PAT);
+#pragma unroll
+            for (int m4 = 0; m4 < MMAX / 4; ++m4) {
+                const float4 av = row[m4];
+                r[4 * m4] -= av.x * xv;
+                r[4 * m4 + 1] -= av.y * xv;
+                r[4 * m4 + 2] -= av.z * xv;
+                r[4 * m4 + 3] -= av.w * xv;
+            }
+        }
+        if (KIND == GREEDY_BIHT_ONE_BIT) {
+#pragma unroll
+            for (int m = 0; m < MMAX; ++m) {
+                const float ax = r[m];
+                const float sg = ax > 0.f ? 1.f : (ax < 0.f ? -1.f : 0.f);
+                r[m] = (m < M) ? (float)g.Ysign[pix * M + m] - sg : 0.f;
+            }
+        }
+        float d2 = 0.f, n2 = 0.f;
+#pragma unroll
+        for (int m = 0; m < MMAX; ++m) {
+            const float d = r[m] - s.rold[m];
+            d2 += d * d;
+            n2 += r[m] * r[m];
+        }
+        iters = it;
+        last_d2 = d2;
+        rn2 = n2;
+        if (KIND != GREEDY_BIHT_ONE_BIT) {
+            const bool stop = (sqrtf(n2) <= g.res_tol * ynorm) || (g.eps > 0.f && sqrtf(d2) < g.eps);
+            if (stop) {
+                converged = true;
+                break;
+            }
+        }
+    }
+
+    // gOMP with the prune placed after the loop
+    if (KIND == GREEDY_GOMP && g.prune == CSREC_PRUNE_FINAL && nc > K) {
+        mark_top_k<T>(g, s, nc, K);
+        int nq = 0;
+        for (int w = 0; w < NW; ++w) {
+            uint32_t v = s.keep[w];
+            while (v) {
+                const int b = __builtin_ctz(v);
+                v &= v - 1;
+                s.cidx[nc + nq] = 32 * w + b;
+                s.xidx[nq++] = 32 * w + b;
+            }
+        }
+        Scratch<T> sq = s;
+        sq.L.off += tri(nc);
+        sq.dinv.off += nc;
+        sq.z.off += nc;
+        sq.sv.off += nc;
+        sq.cidx.off += nc;
+        chol_solve_fresh<T>(g, sq, nq);
+        for (int a = 0; a < nq; ++a) s.xval[a] = (float)sq.sv[a];
+        nx = nq;
+        // residual of the pruned x
+#pragma unroll
+        for (int m = 0; m < MMAX; ++m) r[m] = (m < M) ? g.Y[pix * M + m] : 0.f;
+        for (int a = 0; a < nx; ++a) {
+            const float xv = s.xval[a];
+            const float4* row = reinterpret_cast<const float4*>(sAT + s.xidx[a] * PAT);
+#pragma unroll
+            for (int m4 = 0; m4 < MMAX / 4; ++m4) {
+                const float4 av = row[m4];
+                r[4 * m4] -= av.x * xv;
+                r[4 * m4 + 1] -= av.y * xv;
+                r[4 * m4 + 2] -= av.z * xv;
+                r[4 * m4 + 3] -= av.w * xv;
+            }
+        }
+        float n2 = 0.f;
+#pragma unroll
+        for (int m = 0; m < MMAX; ++m) n2 += r[m] * r[m];
+        rn2 = n2;
+    }
+
+    if (KIND == GREEDY_GOMP && pass == 0 && g.fbflag) {
+        g.fbflag[local] = fallback ? 1u : 0u;
+        if (fallback) return;   // the FP64 pass writes this pixel's results
+    }
+
+    // ---------------- outputs
+    float nrm = 1.f;
+    if (KIND == GREEDY_BIHT_ONE_BIT) {
+        float x2 = 0.f;
+        for (int a = 0; a < nx; ++a) x2 += s.xval[a] * s.xval[a];
+        nrm = x2 > 0.f ? 1.f / sqrtf(x2) : 0.f;
+    }
+    float* xrow = g.X + pix * N;
+    for (int n = 0; n < N; ++n) xrow[n] = 0.f;
+    for (int a = 0; a < nx; ++a) xrow[s.xidx[a]] = s.xval[a] * nrm;
+    if (g.support) {
+        int32_t* srow = g.support + pix * K;
+        int a = 0;
+        for (; a < nx && a < K; ++a) srow[a] = s.xidx[a];
+        for (; a < K; ++a) srow[a] = -1;
+    }
+    if (g.stats) {
+        csrec_pixel_stats st;
+        st.iters = iters;
+        uint32_t f = 0;
+        if (bad) f = CSREC_FLAG_NONFINITE;
+        else f = converged ? CSREC_FLAG_CONVERGED : CSREC_FLAG_ITER_CAP;
+        if (pass == 1) f |= CSREC_FLAG_FP64_FALLBACK;
+        st.flags = f;
+        st.resid = bad ? 0.f : sqrtf(rn2);
+        st.delta = sqrtf(last_d2);
+        g.stats[pix] = st;
+    }
+}
+
+// Gram matrix G = A^T A in FP64, stored as FP32 and FP64.
+__global__ void gram_kernel(const float* __restrict__ A, int M, int N, float* __restrict__ G32,
+                            double* __restrict__ G64) {
+    const int a = blockIdx.x;
+    for (int b = threadIdx.x; b < N; b += blockDim.x) {
+        double acc = 0.0;
+        for (int m = 0; m < M; ++m) acc += (double)A[(size_t)m * N + a] * (double)A[(size_t)m * N + b];
+        G32[a * N + b] = (float)acc;
+        if (G64) G64[a * N + b] = acc;
+    }
+}
+
+typedef void (*gk_t)(GArgs, int64_t, int64_t, int);
+
+template <int KIND, int MMAX, int SMAX>
+gk_t pick_T(bool dbl) {
+    return dbl ? greedy_kernel<KIND, MMAX, SMAX, double> : greedy_kernel<KIND, MMAX, SMAX, float>;
+}
+
+template <int KIND, int SMAX>
+gk_t pick_M(int M, bool dbl) {
+    if (M <= 48) return pick_T<KIND, 48, SMAX>(dbl);
+    if (M <= 96) return pick_T<KIND, 96, SMAX>(dbl);
+    return nullptr;
+}
+
+gk_t pick_kernel(GreedyKind kind, int M, int S, bool dbl) {
+    switch (kind) {
+        case GREEDY_GOMP:
+            if (S <= 2) return pick_M<GREEDY_GOMP, 2>(M, dbl);
+            return pick_M<GREEDY_GOMP, 8>(M, dbl);
+        case GREEDY_COSAMP: return pick_M<GREEDY_COSAMP, 1>(M, dbl);
+        case GREEDY_BIHT: return pick_M<GREEDY_BIHT, 1>(M, dbl);
+        case GREEDY_BIHT_ONE_BIT: return pick_M<GREEDY_BIHT_ONE_BIT, 1>(M, false);
+    }
+    return nullptr;
+}
+
+int mmax_for(int M) { return M <= 48 ? 48 : 96; }
+
+struct Layout {
+    int CM, LM;
+    int64_t CH;
+    size_t gram32, gram64, off_T, off_i, off_r, off_f, total;
+};
+
+constexpr int64_t kChunk = 65536;
+
+Layout layout_for(const GreedyLaunch& a) {
+    Layout L;
+    int CM = 0, LM = 1;
+    switch (a.kind) {
+        case GREEDY_GOMP: CM = a.S * a.max_iter + a.K; LM = 1; break;   // c plus a q-sized tail
+        case GREEDY_COSAMP: CM = 3 * a.K; LM = 2 * a.K; break;
+        case GREEDY_BIHT: CM = 2 * a.K; LM = a.K; break;
+        case GREEDY_BIHT_ONE_BIT: CM = a.K; LM = a.K; break;
+    }
+    L.CM = CM;
+    L.LM = LM;
+    L.CH = a.P < kChunk ? ((a.P + 63) / 64) * 64 : kChunk;
+    if (L.CH == 0) L.CH = 64;
+    const bool dbl = a.kind == GREEDY_GOMP && a.pivot_fallback > 0.0;
+    const size_t tsz = dbl ? 8 : 4;
+    const int NW = (a.N + 31) / 32;
+    const int64_t tent = (int64_t)CM * (CM + 1) / 2 + 3 * (int64_t)CM;
+    const int64_t ient = a.N + 2 * LM + 3 * CM + 2 * NW;
+    L.gram32 = 0;
+    L.gram64 = align_up((size_t)a.N * a.N * 4, 256);
+    size_t o = L.gram64 + (dbl ? align_up((size_t)a.N * a.N * 8, 256) : 0);
+    L.off_T = o;
+    o += align_up((size_t)tent * L.CH * tsz, 256);
+    L.off_i = o;
+    o += align_up((size_t)ient * L.CH * 4, 256);
+    L.off_r = o;
+    o += align_up((size_t)mmax_for(a.M) * L.CH * 4, 256);
+    L.off_f = o;
+    o += align_up((size_t)L.CH * 4, 256);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+size_t greedy_workspace(const GreedyLaunch& a) { return layout_for(a).total; }
+
+int greedy_launch(const GreedyLaunch& a) {
+    if (a.P == 0) return CSREC_OK;
+    if (a.M > 96) return CSREC_E_UNSUPPORTED;
+    const Layout L = layout_for(a);
+    if (!a.workspace || a.workspace_bytes < L.total) return CSREC_E_WORKSPACE;
+    const bool dbl = a.kind == GREEDY_GOMP && a.pivot_fallback > 0.0;
+    char* ws = static_cast<char*>(a.workspace);
+    GArgs g;
+    g.A = a.A;
+    g.Y = a.Y;
+    g.Ysign = a.Ysign;
+    g.X = a.X;
+    g.support = a.support;
+    g.stats = a.stats;
+    g.G32 = reinterpret_cast<const float*>(ws + L.gram32);
+    g.G64 = dbl ? reinterpret_cast<const double*>(ws + L.gram64) : nullptr;
+    g.M = a.M;
+    g.N = a.N;
+    g.K = a.K;
+    g.S = a.S;
+    g.Imax = a.max_iter;
+    g.prune = a.prune;
+    g.res_tol = a.res_tol;
+    g.eps = a.eps;
+    g.mu = a.mu;
+    g.pivot_thr = a.pivot_fallback;
+    g.scr = ws;
+    g.CH = L.CH;
+    g.CM = L.CM;
+    g.LM = L.LM;
+    g.off_T = (int64_t)L.off_T;
+    g.off_i = (int64_t)L.off_i;
+    g.off_r = (int64_t)L.off_r;
+    g.fbflag = dbl ? reinterpret_cast<uint32_t*>(ws + L.off_f) : nullptr;
+
+    if (a.kind != GREEDY_BIHT_ONE_BIT) {
+        hipLaunchKernelGGL(gram_kernel, dim3(a.N), dim3(256), 0, a.stream, a.A, a.M, a.N,
+                           reinterpret_cast<float*>(ws + L.gram32),
+                           dbl ? reinterpret_cast<double*>(ws + L.gram64) : nullptr);
+        CSREC_HIP_TRY(hipGetLastError());
+    }
+    const int mmax = mmax_for(a.M);
+    const size_t lds = (size_t)a.N * (mmax + 4) * sizeof(float);
+    const int threads = 512;
+    gk_t fns[2] = {pick_kernel(a.kind, a.M, a.S, false), dbl ? pick_kernel(a.kind, a.M, a.S, true) : nullptr};
+    for (int pass = 0; pass < (dbl ? 2 : 1); ++pass) {
+        if (!fns[pass]) return CSREC_E_UNSUPPORTED;
+        CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fns[pass]),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    for (int64_t p0 = 0; p0 < a.P; p0 += L.CH) {
+        const int64_t np = (a.P - p0) < L.CH ? (a.P - p0) : L.CH;
+        const int64_t blocks = ceil_div(np, threads);
+        for (int pass = 0; pass < (dbl ? 2 : 1); ++pass) {
+            hipLaunchKernelGGL(fns[pass], dim3((unsigned)blocks), dim3(threads), lds, a.stream, g, p0, np,
+                               pass);
+            CSREC_HIP_TRY(hipGetLastError());
+        }
+    }
+    return CSREC_OK;
+}
+
+}  // namespace csrec

@@ -1,0 +1,156 @@
+"""GPU parity of csrec_fista (Alg. 1) against the FP64 oracle.
+
+Tolerance: per-pixel relative error <= 1e-5 of x (the FP32 bar of the
+recovery), on the same FP32 inputs.  Stats (iterations exactly; residual and
+Delta to 1e-4 relative) are checked too."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import note, np_of, rel_err_rows, require_gpu, to_dev
+from paper_2401_14762_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _run(torch, A, Y, lam, L, iters, **kw):
+    import paper_2401_14762_amd as cs
+    X, st = cs.fista(to_dev(torch, A), to_dev(torch, Y), lam=lam, L=L, max_iter=iters, **kw)
+    torch.cuda.synchronize()
+    return np_of(X), {k: np_of(v) for k, v in st.items()}
+
+
+def test_tiny_all_pixels(torch):
+    pr = W.tiny_exact_sparse()
+    L = oracle.lipschitz(pr.A)
+    note("fista tiny 16x16 N=100 M=40 500 it")
+    X, st = _run(torch, pr.A, pr.Y, 1e-3, L, 500)
+    ref = oracle.fista(pr.A, pr.Y, 1e-3, L, 500)
+    err = rel_err_rows(X, ref["X"])
+    assert err.max() <= TOL, (err.max(), np.argmax(err))
+    assert np.all(st["iters"] == 500)
+    assert np.all(st["flags"] == oracle.STOP_ITER_CAP)
+    assert np.allclose(st["resid"], ref["resid"], rtol=1e-4, atol=1e-6)
+    assert np.allclose(st["delta"], ref["delta"], rtol=1e-3, atol=1e-6)
+
+
+def test_plain_full_launch_sampled(torch):
+    """256x256 N=200 M=80 200 iterations, lambda=1e-2: the full cube is run on
+    the GPU in the benchmark's launch configuration; the oracle checks a
+    seeded sample of 1024 pixels."""
+    pr = W.plain_cube()
+    L = oracle.lipschitz(pr.A)
+    note("fista plain 256x256 N=200 M=80 200 it (full launch)")
+    X, st = _run(torch, pr.A, pr.Y, 1e-2, L, 200)
+    idx = W.pixel_subset(pr.P, 1024, 11)
+    ref = oracle.fista(pr.A, pr.Y[idx], 1e-2, L, 200)
+    err = rel_err_rows(X[idx], ref["X"])
+    assert err.max() <= TOL, err.max()
+    assert np.allclose(st["resid"][idx], ref["resid"], rtol=1e-4)
+    assert np.all(np.isfinite(X))
+
+
+@pytest.mark.parametrize("P", [1, 15, 17, 64, 65, 1000])
+def test_ragged_pixel_counts(torch, P):
+    """Tiles of 16 pixels per wave and 64 per workgroup: counts that leave
+    partial tiles."""
+    pr = W.plain_cube(P)
+    L = oracle.lipschitz(pr.A)
+    note(f"fista ragged P={P}")
+    X, _ = _run(torch, pr.A, pr.Y, 1e-2, L, 50)
+    ref = oracle.fista(pr.A, pr.Y, 1e-2, L, 50)
+    assert rel_err_rows(X, ref["X"]).max() <= TOL
+
+
+@pytest.mark.parametrize("N", [100, 154, 198, 224, 256])
+def test_band_counts(torch, N):
+    """Shapes of every tile variant, M = round(N / 2.5)."""
+    M = W.m_for(N)
+    a64, a32, _, phi = W.dictionary(N, M, 7)
+    F = W.mixing_spectra(300, N, 40.0, 5)
+    Y = (F @ phi.T).astype(np.float32)
+    L = oracle.lipschitz(a32)
+    note(f"fista band count N={N} M={M}")
+    X, _ = _run(torch, a32, Y, 1e-2, L, 60)
+    ref = oracle.fista(a32, Y, 1e-2, L, 60)
+    assert rel_err_rows(X, ref["X"]).max() <= TOL
+
+
+def test_eps_stop_and_x0(torch):
+    """Per-pixel Delta < eps stop and a caller-supplied starting point."""
+    pr = W.plain_cube(257)
+    L = oracle.lipschitz(pr.A)
+    eps = 2e-3
+    note("fista eps stop")
+    X, st = _run(torch, pr.A, pr.Y, 1e-2, L, 300, eps=eps)
+    ref = oracle.fista(pr.A, pr.Y, 1e-2, L, 300, eps=eps)
+    # iteration counts match where Delta is not within rounding of eps
+    d_margin = np.abs(ref["delta"] - eps) / eps
+    ok = d_margin > 1e-3
+    assert np.mean(st["iters"] == ref["iters"]) > 0.97
+    same = st["iters"] == ref["iters"]
+    assert rel_err_rows(X[same], ref["X"][same]).max() <= TOL
+    assert np.all(st["flags"][st["iters"] < 300] & oracle.STOP_CONVERGED)
+    x0 = ref["X"].astype(np.float32)
+    note("fista warm start X0")
+    import paper_2401_14762_amd as cs
+    Xw, stw = cs.fista(to_dev(torch, pr.A), to_dev(torch, pr.Y), lam=1e-2, L=L, max_iter=20,
+                       X0=to_dev(torch, x0))
+    torch.cuda.synchronize()
+    refw = oracle.fista(pr.A, pr.Y, 1e-2, L, 20, X0=x0.astype(np.float64))
+    assert rel_err_rows(np_of(Xw), refw["X"]).max() <= TOL
+    assert np.allclose(np_of(stw["delta"]), refw["delta"], rtol=1e-3, atol=1e-6)
+    del ok
+
+
+def test_nonfinite_pixel_and_zero(torch):
+    pr = W.plain_cube(40)
+    Y = pr.Y.copy()
+    Y[3, 5] = np.nan
+    Y[7, 0] = np.inf
+    Y[9] = 0.0
+    L = oracle.lipschitz(pr.A)
+    note("fista nonfinite pixels")
+    X, st = _run(torch, pr.A, Y, 1e-2, L, 30)
+    ref = oracle.fista(pr.A, Y, 1e-2, L, 30)
+    assert np.all(X[[3, 7, 9]] == 0.0)
+    assert st["flags"][3] == oracle.STOP_NONFINITE and st["flags"][7] == oracle.STOP_NONFINITE
+    assert st["iters"][3] == 0
+    good = np.setdiff1d(np.arange(40), [3, 7, 9])
+    assert rel_err_rows(X[good], ref["X"][good]).max() <= TOL
+
+
+def test_device_lipschitz(torch):
+    import paper_2401_14762_amd as cs
+    for N in (100, 200, 224):
+        M = W.m_for(N)
+        _, a32, _, _ = W.dictionary(N, M, N)
+        note(f"lipschitz power iteration N={N}")
+        Ld = float(np_of(cs.lipschitz(to_dev(torch, a32)))[0])
+        assert abs(Ld - oracle.lipschitz(a32)) <= 1e-5 * oracle.lipschitz(a32)
+    pr = W.tiny_exact_sparse()
+    note("fista with device-estimated L")
+    X, _ = _run(torch, pr.A, pr.Y, 1e-3, 0.0, 100)
+    ref = oracle.fista(pr.A, pr.Y, 1e-3, oracle.lipschitz(pr.A), 100)
+    assert rel_err_rows(X, ref["X"]).max() <= 1e-4
+
+
+def test_zero_iterations_and_empty(torch):
+    import paper_2401_14762_amd as cs
+    pr = W.tiny_exact_sparse(20)
+    note("fista max_iter=0")
+    X, st = _run(torch, pr.A, pr.Y, 1e-3, 1.0, 0)
+    assert np.all(X == 0) and np.all(st["iters"] == 0)
+    A = to_dev(torch, pr.A)
+    Y = torch.empty((0, pr.M), dtype=torch.float32, device="cuda")
+    X0, _ = cs.fista(A, Y, lam=1e-3, L=1.0, max_iter=5)
+    assert X0.shape == (0, pr.N)

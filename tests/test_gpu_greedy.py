@@ -1,0 +1,181 @@
+"""GPU parity of csrec_gomp / csrec_cosamp / csrec_biht against the FP64
+oracle.
+
+Bar: supports bit-exact and x within 1e-5 relative per pixel on every pixel
+whose decisions are not near-ties (the oracle's selection / prune gaps,
+stop margin and pivot ratio, thresholds in gpu_common); near-tie pixels are
+counted, must be rare, and must still return a valid K-sparse finite x."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import GAP, PIVOT, STOP_MARGIN, note, np_of, rel_err_rows, require_gpu, to_dev
+from paper_2401_14762_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _support_rows(sup):
+    return [tuple(int(v) for v in row if v >= 0) for row in sup]
+
+
+def _compare(X, S, st, ref, K, flagged, what, min_clean=0.9):
+    clean = ~flagged
+    assert clean.mean() >= min_clean, f"{what}: only {clean.mean():.3f} of pixels away from near-ties"
+    gs, rs = _support_rows(S), _support_rows(ref["support"])
+    same = np.array([a == b for a, b in zip(gs, rs)])
+    bad = np.nonzero(clean & ~same)[0]
+    assert len(bad) == 0, f"{what}: support mismatch on clean pixels {bad[:10]}"
+    err = rel_err_rows(X[clean], ref["X"][clean])
+    assert err.max() <= TOL, f"{what}: max rel err {err.max()}"
+    assert np.array_equal(st["iters"][clean], ref["iters"][clean]), what
+    # the rest: valid outputs
+    assert np.all(np.isfinite(X))
+    assert np.all(np.count_nonzero(X, axis=1) <= K)
+
+
+def _gomp_flags(ref, res_tol):
+    f = (ref["sel_gap"] < GAP) | (ref["prune_gap"] < GAP) | (ref["min_pivot"] < PIVOT)
+    if res_tol > 0:
+        f |= ref["stop_margin"] < STOP_MARGIN
+    return f
+
+
+def _gomp(torch, pr_A, Y, **kw):
+    import paper_2401_14762_amd as cs
+    X, S, st = cs.gomp(to_dev(torch, pr_A), to_dev(torch, Y), **kw)
+    torch.cuda.synchronize()
+    return np_of(X), np_of(S), {k: np_of(v) for k, v in st.items()}
+
+
+def test_gomp_tiny_exact(torch):
+    """16x16, N=100, M=40, 8-sparse noiseless, S=2, K=8."""
+    pr = W.tiny_exact_sparse()
+    note("gomp tiny")
+    X, S, st = _gomp(torch, pr.A, pr.Y, K=8, S=2, res_tol=1e-5)
+    ref = oracle.gomp(pr.A, pr.Y, K=8, S=2, res_tol=1e-5, diagnostics=True)
+    flagged = _gomp_flags(ref, 1e-5)
+    _compare(X, S, st, ref, 8, flagged, "gomp tiny")
+    # exact recovery where the oracle recovers exactly
+    exact = oracle.rel_err(ref["X"], pr.X_true) < 1e-6
+    assert rel_err_rows(X[exact & ~flagged], pr.X_true[exact & ~flagged]).max() < 1e-4
+
+
+def test_gomp_plain_sampled(torch):
+    """256x256 N=200 M=80, S=2, K=20, res_tol=1e-3: full launch, sampled check."""
+    pr = W.plain_cube()
+    note("gomp plain 256x256 (full launch)")
+    X, S, st = _gomp(torch, pr.A, pr.Y, K=20, S=2, res_tol=1e-3)
+    idx = W.pixel_subset(pr.P, 1024, 12)
+    ref = oracle.gomp(pr.A, pr.Y[idx], K=20, S=2, res_tol=1e-3, diagnostics=True)
+    sub = {k: v[idx] for k, v in st.items()}
+    _compare(X[idx], S[idx], sub, ref, 20, _gomp_flags(ref, 1e-3), "gomp plain")
+
+
+@pytest.mark.parametrize("P", [1, 63, 65, 513])
+def test_gomp_ragged(torch, P):
+    pr = W.plain_cube(P)
+    note(f"gomp ragged P={P}")
+    X, S, st = _gomp(torch, pr.A, pr.Y, K=20, S=2, res_tol=1e-3)
+    ref = oracle.gomp(pr.A, pr.Y, K=20, S=2, res_tol=1e-3, diagnostics=True)
+    _compare(X, S, st, ref, 20, _gomp_flags(ref, 1e-3), f"gomp P={P}", min_clean=0.8 if P < 50 else 0.9)
+
+
+@pytest.mark.parametrize("S,K,prune", [(1, 6, "each"), (3, 9, "each"), (4, 12, "final"), (8, 16, "each")])
+def test_gomp_variants(torch, S, K, prune):
+    pr = W.plain_cube(300)
+    note(f"gomp S={S} K={K} prune={prune}")
+    X, Sup, st = _gomp(torch, pr.A, pr.Y, K=K, S=S, prune=prune)
+    ref = oracle.gomp(pr.A, pr.Y, K=K, S=S, prune=prune, diagnostics=True)
+    _compare(X, Sup, st, ref, K, _gomp_flags(ref, 0.0), f"gomp S={S}")
+
+
+def test_gomp_nonfinite(torch):
+    pr = W.plain_cube(50)
+    Y = pr.Y.copy()
+    Y[4, 2] = np.nan
+    note("gomp nonfinite")
+    X, S, st = _gomp(torch, pr.A, Y, K=20, S=2, res_tol=1e-3)
+    assert np.all(X[4] == 0) and st["flags"][4] == oracle.STOP_NONFINITE and np.all(S[4] == -1)
+
+
+def test_gomp_fp64_fallback(torch):
+    """Nearly duplicated atoms: the FP32 Cholesky pivot ratio collapses and the
+    pixel is solved again in FP64; the result then meets the FP64 oracle."""
+    rng = np.random.default_rng(3)
+    M, N = 40, 100
+    A = (rng.standard_normal((M, N)) / np.sqrt(M))
+    A[:, 1] = A[:, 0] + 1e-5 * rng.standard_normal(M)
+    A32 = A.astype(np.float32)
+    X = np.zeros((64, N))
+    X[:, 0] = 1.0
+    X[:, 1] = 1.0
+    X[np.arange(64), 5 + np.arange(64) % 50] = 0.5
+    Y = (X @ A32.astype(np.float64).T).astype(np.float32)
+    note("gomp fp64 fallback")
+    Xg, S, st = _gomp(torch, A32, Y, K=6, S=2, res_tol=1e-6, pivot_fallback=1e-6)
+    ref = oracle.gomp(A32, Y, K=6, S=2, res_tol=1e-6, diagnostics=True)
+    fb = (st["flags"] & oracle.STOP_FALLBACK) != 0
+    assert fb.any()
+    ok = fb & (ref["sel_gap"] >= GAP) & (ref["prune_gap"] >= GAP)
+    assert ok.any()
+    err = rel_err_rows(Xg[ok], ref["X"][ok])
+    assert err.max() < 1e-5, err.max()
+
+
+# ---------------------------------------------------------------- CoSaMP / BIHT
+
+@pytest.fixture(scope="module")
+def other():
+    return W.other_solvers_cube(2048)
+
+
+def _cosamp_flags(ref):
+    return (ref["sel_gap"] < GAP) | (ref["prune_gap"] < GAP)
+
+
+def test_cosamp_other_subset(torch, other):
+    import paper_2401_14762_amd as cs
+    pr = other
+    note("cosamp K=15 30 it")
+    X, S, st = cs.cosamp(to_dev(torch, pr.A), to_dev(torch, pr.Y), K=15, max_iter=30)
+    torch.cuda.synchronize()
+    ref = oracle.cosamp(pr.A, pr.Y, K=15, max_iter=30, diagnostics=True)
+    _compare(np_of(X), np_of(S), {k: np_of(v) for k, v in st.items()}, ref, 15, _cosamp_flags(ref),
+             "cosamp", min_clean=0.8)
+
+
+def test_biht_real_subset(torch, other):
+    import paper_2401_14762_amd as cs
+    pr = other
+    note("biht real K=15 40 it")
+    X, S, st = cs.biht(to_dev(torch, pr.A), to_dev(torch, pr.Y), K=15, max_iter=40, mu=0.1)
+    torch.cuda.synchronize()
+    ref = oracle.biht(pr.A, pr.Y, K=15, max_iter=40, mu=0.1, diagnostics=True)
+    _compare(np_of(X), np_of(S), {k: np_of(v) for k, v in st.items()}, ref, 15, _cosamp_flags(ref),
+             "biht real", min_clean=0.8)
+
+
+def test_biht_one_bit_subset(torch, other):
+    import paper_2401_14762_amd as cs
+    pr = other
+    note("biht one-bit K=15 100 it")
+    X, S, st = cs.biht(to_dev(torch, pr.A), None, K=15, max_iter=100, mu=0.1, mode="one_bit",
+                       Ysign=to_dev(torch, pr.Ysign))
+    torch.cuda.synchronize()
+    ref = oracle.biht_one_bit(pr.A, pr.Ysign, K=15, max_iter=100, mu=0.1, diagnostics=True)
+    flagged = (ref["sel_gap"] < GAP) | (ref["sign_margin"] < 1e-5)
+    X, S = np_of(X), np_of(S)
+    clean = ~flagged
+    assert clean.mean() > 0.5, clean.mean()
+    same = np.array([a == b for a, b in zip(_support_rows(S), _support_rows(ref["support"]))])
+    assert np.all(same[clean])
+    assert rel_err_rows(X[clean], ref["X"][clean]).max() <= TOL
+    nrm = np.linalg.norm(X, axis=1)
+    assert np.allclose(nrm[nrm > 0], 1.0, atol=1e-5)
