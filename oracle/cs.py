@@ -138,7 +138,8 @@ def _pivot_ratio_min(A: np.ndarray, cols: np.ndarray) -> np.ndarray:
 # Alg. 1 -- FISTA
 # --------------------------------------------------------------------------
 
-def fista(A, Y, lam: float, L: float, max_iter: int, eps: float = 0.0, X0=None) -> dict:
+def fista(A, Y, lam: float, L: float, max_iter: int, eps: float = 0.0, X0=None,
+          dtype=np.float64) -> dict:
     """FISTA for min 1/2||A x - y||^2 + lam ||x||_1 (Eq. 2, Alg. 1), every
     pixel (row of Y) independently.
 
@@ -150,14 +151,19 @@ def fista(A, Y, lam: float, L: float, max_iter: int, eps: float = 0.0, X0=None) 
       5. r^i = y - A x^i,  Delta = ||r^i - r^{i-1}||_2;  stop when Delta < eps
     with t^0 = 1, z^0 = x^0, r^0 = y.
 
+    dtype=np.float32 evaluates the same steps with every array operation
+    rounded to FP32: a rounding model used only to size the error a plain
+    FP32 evaluation of Alg. 1 carries on a given problem (the parity
+    reference is always the FP64 evaluation).
+
     Returns dict(X, iters, delta, resid, flags)."""
-    A = _f64(A)
-    Y = _f64(Y)
+    A = np.asarray(A, dtype=dtype)
+    Y = np.asarray(Y, dtype=dtype)
     P, M = Y.shape
     N = A.shape[1]
     fin = _finite_rows(Y)
-    Yc = np.where(fin[:, None], Y, 0.0)
-    x = np.zeros((P, N)) if X0 is None else _f64(X0).copy()
+    Yc = np.where(fin[:, None], Y, dtype(0.0))
+    x = np.zeros((P, N), dtype=dtype) if X0 is None else np.asarray(X0, dtype=dtype).copy()
     x[~fin] = 0.0
     z = x.copy()
     r = Yc.copy()                    # r^0 = y
@@ -172,10 +178,10 @@ def fista(A, Y, lam: float, L: float, max_iter: int, eps: float = 0.0, X0=None) 
             break
         a = np.nonzero(active)[0]
         za, xa, ya = z[a], x[a], Yc[a]
-        aux = za - (1.0 / L) * ((za @ A.T - ya) @ A)          # step 1
-        x_new = soft_threshold(aux, lam / L)                    # step 2
+        aux = za - dtype(1.0 / L) * ((za @ A.T - ya) @ A)       # step 1
+        x_new = soft_threshold(aux, dtype(lam / L))             # step 2
         t_new = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0      # step 3
-        z_new = x_new + ((t - 1.0) / t_new) * (x_new - xa)      # step 4
+        z_new = x_new + dtype((t - 1.0) / t_new) * (x_new - xa)  # step 4
         r_new = ya - x_new @ A.T                                # step 5
         d = np.linalg.norm(r_new - r[a], axis=1)
         x[a], z[a], r[a] = x_new, z_new, r_new
@@ -187,7 +193,7 @@ def fista(A, Y, lam: float, L: float, max_iter: int, eps: float = 0.0, X0=None) 
         active[a[stop]] = False
     flags[active] |= STOP_ITER_CAP
     resid = np.linalg.norm(Yc - x @ A.T, axis=1)
-    return dict(X=x, iters=iters, delta=delta, resid=resid, flags=flags)
+    return dict(X=x.astype(np.float64), iters=iters, delta=delta, resid=resid, flags=flags)
 
 
 # --------------------------------------------------------------------------

@@ -25,9 +25,10 @@ def _support_rows(sup):
     return [tuple(int(v) for v in row if v >= 0) for row in sup]
 
 
-def _compare(X, S, st, ref, K, flagged, what, min_clean=0.9):
+def _compare(X, S, st, ref, K, flagged, what, min_clean=0.85):
     clean = ~flagged
-    assert clean.mean() >= min_clean, f"{what}: only {clean.mean():.3f} of pixels away from near-ties"
+    if len(clean) >= 50:
+        assert clean.mean() >= min_clean, f"{what}: only {clean.mean():.3f} of pixels away from near-ties"
     gs, rs = _support_rows(S), _support_rows(ref["support"])
     same = np.array([a == b for a, b in zip(gs, rs)])
     bad = np.nonzero(clean & ~same)[0]
@@ -84,15 +85,16 @@ def test_gomp_ragged(torch, P):
     note(f"gomp ragged P={P}")
     X, S, st = _gomp(torch, pr.A, pr.Y, K=20, S=2, res_tol=1e-3)
     ref = oracle.gomp(pr.A, pr.Y, K=20, S=2, res_tol=1e-3, diagnostics=True)
-    _compare(X, S, st, ref, 20, _gomp_flags(ref, 1e-3), f"gomp P={P}", min_clean=0.8 if P < 50 else 0.9)
+    _compare(X, S, st, ref, 20, _gomp_flags(ref, 1e-3), f"gomp P={P}")
 
 
-@pytest.mark.parametrize("S,K,prune", [(1, 6, "each"), (3, 9, "each"), (4, 12, "final"), (8, 16, "each")])
-def test_gomp_variants(torch, S, K, prune):
+@pytest.mark.parametrize("S,K,prune,it", [(1, 6, "each", 0), (3, 9, "each", 0), (4, 12, "final", 0),
+                                          (8, 16, "each", 5)])
+def test_gomp_variants(torch, S, K, prune, it):
     pr = W.plain_cube(300)
-    note(f"gomp S={S} K={K} prune={prune}")
-    X, Sup, st = _gomp(torch, pr.A, pr.Y, K=K, S=S, prune=prune)
-    ref = oracle.gomp(pr.A, pr.Y, K=K, S=S, prune=prune, diagnostics=True)
+    note(f"gomp S={S} K={K} prune={prune} max_iter={it}")
+    X, Sup, st = _gomp(torch, pr.A, pr.Y, K=K, S=S, prune=prune, max_iter=it)
+    ref = oracle.gomp(pr.A, pr.Y, K=K, S=S, prune=prune, max_iter=it, diagnostics=True)
     _compare(X, Sup, st, ref, K, _gomp_flags(ref, 0.0), f"gomp S={S}")
 
 
@@ -148,7 +150,7 @@ def test_cosamp_other_subset(torch, other):
     torch.cuda.synchronize()
     ref = oracle.cosamp(pr.A, pr.Y, K=15, max_iter=30, diagnostics=True)
     _compare(np_of(X), np_of(S), {k: np_of(v) for k, v in st.items()}, ref, 15, _cosamp_flags(ref),
-             "cosamp", min_clean=0.8)
+             "cosamp")
 
 
 def test_biht_real_subset(torch, other):
@@ -159,7 +161,7 @@ def test_biht_real_subset(torch, other):
     torch.cuda.synchronize()
     ref = oracle.biht(pr.A, pr.Y, K=15, max_iter=40, mu=0.1, diagnostics=True)
     _compare(np_of(X), np_of(S), {k: np_of(v) for k, v in st.items()}, ref, 15, _cosamp_flags(ref),
-             "biht real", min_clean=0.8)
+             "biht real")
 
 
 def test_biht_one_bit_subset(torch, other):

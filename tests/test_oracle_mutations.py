@@ -13,10 +13,10 @@ SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 
 
 # (id, text to replace (first occurrence), replacement)
 MUTATIONS = [
-    ("fista-threshold-lam", "soft_threshold(aux, lam / L)", "soft_threshold(aux, lam)"),
+    ("fista-threshold-lam", "soft_threshold(aux, dtype(lam / L))", "soft_threshold(aux, dtype(lam))"),
     ("fista-no-step-1/L", "(1.0 / L) * ((za @ A.T - ya) @ A)", "((za @ A.T - ya) @ A)"),
     ("fista-gradient-sign", "((za @ A.T - ya) @ A)", "((ya - za @ A.T) @ A)"),
-    ("fista-no-momentum", "z_new = x_new + ((t - 1.0) / t_new) * (x_new - xa)", "z_new = x_new"),
+    ("fista-no-momentum", "z_new = x_new + dtype((t - 1.0) / t_new) * (x_new - xa)", "z_new = x_new"),
     ("fista-t-recursion", "math.sqrt(1.0 + 4.0 * t * t)", "math.sqrt(1.0 + t * t)"),
     ("fista-momentum-index", "((t - 1.0) / t_new)", "((t_new - 1.0) / t_new)"),
     ("fista-delta-vs-y", "d = np.linalg.norm(r_new - r[a], axis=1)", "d = np.linalg.norm(r_new, axis=1)"),
