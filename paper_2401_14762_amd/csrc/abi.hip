@@ -209,6 +209,7 @@ int32_t csrec_fista(const csrec_problem* problem, const csrec_fista_params* para
     l.eps = (float)params->eps;
     l.lambda = params->lambda;
     l.prec = params->prec;
+    l.correction_iters = params->correction_iters;
     l.stream = reinterpret_cast<hipStream_t>(problem->stream);
     l.workspace = problem->workspace;
     if (params->L > 0.0) {

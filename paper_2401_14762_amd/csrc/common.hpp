@@ -45,6 +45,7 @@ struct FistaLaunch {
     const float* L_dev;   // device L when the host value is 0 (power iteration)
     double lambda;
     int prec;
+    int correction_iters;
     void* workspace;
     hipStream_t stream;
 };

@@ -49,6 +49,7 @@ struct FistaArgs {
     int M, N;
     int64_t P;
     int max_iter;
+    int iter_offset;      // iterations already run by an earlier pass (added to the stats)
     float invL, thr, eps;
     double lambda;
 };
@@ -253,7 +254,244 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void fista_f32_kernel(FistaArgs a
             }
         if (a.stats && h == 0) {
             csrec_pixel_stats s;
-            s.iters = bad ? 0 : iters;
+            s.iters = bad ? 0 : iters + a.iter_offset;
+            s.flags = bad ? CSREC_FLAG_NONFINITE : (converged ? CSREC_FLAG_CONVERGED : CSREC_FLAG_ITER_CAP);
+            s.resid = bad ? 0.f : sqrtf(r2);
+            s.delta = bad ? __builtin_nanf("") : sqrtf(last_d2);
+            a.stats[pix] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- 16-bit operands
+//
+// Same iteration with the two products on v_mfma_f32_16x16x32_{bf16,f16}:
+// operands rounded to 16 bits, FP32 accumulation, FP32 state and epilogue.
+// One 32-wide contraction step consumes two adjacent 16-tiles of the FP32
+// layout above: group h contributes the four indices c(h, 0..3) of tile 2s
+// followed by those of tile 2s+1, i.e. its own registers of the two tiles,
+// packed to 16 bits.  A is stored twice in LDS, pre-swizzled so that the
+// eight operand values a lane needs for one step are 16 contiguous bytes:
+//   A1[mt][s][lane][8]: rows m of tile mt, columns n of the tile pair s (GEMM 1)
+//   A2[nt][s][lane][8]: rows n of tile nt, columns m of the tile pair s (GEMM 2)
+// so every operand read is one conflict-free ds_read_b128 per lane.
+
+template <typename H>
+struct Vec8;
+template <>
+struct Vec8<__bf16> {
+    typedef __bf16 type __attribute__((ext_vector_type(8)));
+};
+template <>
+struct Vec8<_Float16> {
+    typedef _Float16 type __attribute__((ext_vector_type(8)));
+};
+
+template <typename H>
+__device__ __forceinline__ v4f mfma16(const typename Vec8<H>::type& a, const typename Vec8<H>::type& b, v4f c);
+template <>
+__device__ __forceinline__ v4f mfma16<__bf16>(const Vec8<__bf16>::type& a, const Vec8<__bf16>::type& b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ v4f mfma16<_Float16>(const Vec8<_Float16>::type& a, const Vec8<_Float16>::type& b,
+                                                v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+template <typename H>
+__device__ __forceinline__ typename Vec8<H>::type pack8(const v4f& lo, const v4f& hi) {
+    typename Vec8<H>::type v;
+    v[0] = (H)lo[0]; v[1] = (H)lo[1]; v[2] = (H)lo[2]; v[3] = (H)lo[3];
+    v[4] = (H)hi[0]; v[5] = (H)hi[1]; v[6] = (H)hi[2]; v[7] = (H)hi[3];
+    return v;
+}
+
+// MT, NT even (tile pairs); WAVES wavefronts of 16 pixels each.
+template <typename H, int MT, int NT, int WAVES, int MINW>
+__global__ __launch_bounds__(WAVES * 64, MINW) void fista_lp_kernel(FistaArgs a) {
+    typedef typename Vec8<H>::type h8;
+    constexpr int MS = MT / 2, NS = NT / 2;
+    __shared__ h8 sA1[MT * NS * 64];
+    __shared__ h8 sA2[NT * MS * 64];
+    const int M = a.M, N = a.N;
+
+    // swizzled LDS images of A: one thread builds one lane's 8-vector
+    for (int idx = threadIdx.x; idx < MT * NS * 64; idx += WAVES * 64) {
+        const int ln = idx & 63, blk = idx >> 6;
+        const int mt = blk / NS, sp = blk - mt * NS;
+        const int h = ln >> 4, j = ln & 15;
+        const int m = 16 * mt + 8 * ((j >> 2) & 1) + 4 * (j >> 3) + (j & 3);
+        h8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int n = 32 * sp + (e < 4 ? 0 : 16) + 4 * (e & 3) + h;
+            v[e] = (H)((m < M && n < N) ? a.A[(size_t)m * N + n] : 0.f);
+        }
+        sA1[idx] = v;
+    }
+    for (int idx = threadIdx.x; idx < NT * MS * 64; idx += WAVES * 64) {
+        const int ln = idx & 63, blk = idx >> 6;
+        const int nt = blk / MS, sp = blk - nt * MS;
+        const int h = ln >> 4, j = ln & 15;
+        const int n = 16 * nt + 4 * (j & 3) + (j >> 2);
+        h8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int m = 32 * sp + (e < 4 ? 0 : 16) + 8 * (h & 1) + 4 * (h >> 1) + (e & 3);
+            v[e] = (H)((m < M && n < N) ? a.A[(size_t)m * N + n] : 0.f);
+        }
+        sA2[idx] = v;
+    }
+    float invL = a.invL, thr = a.thr;
+    if (a.L_dev) {
+        const float L = *a.L_dev;
+        invL = 1.f / L;
+        thr = (float)(a.lambda / (double)L);
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 4;
+    const int j = lane & 15;
+    const int64_t pix = ((int64_t)blockIdx.x * WAVES + wave) * 16 + j;
+    const bool valid = pix < a.P;
+    const int cm_h = 8 * (h & 1) + 4 * (h >> 1);
+
+    v4f Yr[MT];
+    int bad = 0;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * mt + cm_h + r;
+            float v = 0.f;
+            if (valid && m < M) {
+                v = a.Y[pix * M + m];
+                if (!isfinite(v)) bad = 1;
+            }
+            Yr[mt][r] = v;
+        }
+    bad |= __shfl_xor(bad, 16);
+    bad |= __shfl_xor(bad, 32);
+    if (bad) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) Yr[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+    v4f Xr[NT], Zr[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * nt + 4 * r + h;
+            float v = 0.f;
+            if (a.X0 && valid && !bad && n < N) v = a.X0[pix * N + n];
+            Xr[nt][r] = v;
+            Zr[nt][r] = v;
+        }
+    v4f U1[MT], V[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) U1[mt] = -Yr[mt];
+    if (a.X0) {
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+            const h8 xb = pack8<H>(Xr[2 * sp], Xr[2 * sp + 1]);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) U1[mt] = mfma16<H>(sA1[(mt * NS + sp) * 64 + lane], xb, U1[mt]);
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) V[mt] = U1[mt];
+
+    bool active = valid && !bad;
+    bool converged = false;
+    int iters = 0;
+    float last_d2 = __builtin_nanf("");
+    double t = 1.0;
+    float bprev = 0.f;
+    const bool check_eps = a.eps > 0.f;
+
+    for (int it = 0; it < a.max_iter; ++it) {
+        const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+        const float bcur = (float)((t - 1.0) / tn);
+        t = tn;
+        const float cp = 1.f + bprev;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) V[mt] = cp * U1[mt] - bprev * V[mt];
+        h8 Vb[MS];
+#pragma unroll
+        for (int sp = 0; sp < MS; ++sp) Vb[sp] = pack8<H>(V[2 * sp], V[2 * sp + 1]);
+        v4f Un[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) Un[mt] = -Yr[mt];
+#pragma unroll
+        for (int np = 0; np < NS; ++np) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int nt = 2 * np + q;
+                v4f W = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int sp = 0; sp < MS; ++sp) W = mfma16<H>(sA2[(nt * MS + sp) * 64 + lane], Vb[sp], W);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float aux = Zr[nt][r] - W[r] * invL;
+                    const float xn = soft_thr(aux, thr);
+                    const float zn = xn + bcur * (xn - Xr[nt][r]);
+                    Xr[nt][r] = active ? xn : Xr[nt][r];
+                    Zr[nt][r] = active ? zn : Zr[nt][r];
+                }
+            }
+            const h8 xb = pack8<H>(Xr[2 * np], Xr[2 * np + 1]);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) Un[mt] = mfma16<H>(sA1[(mt * NS + np) * 64 + lane], xb, Un[mt]);
+        }
+        const float c0 = (it == 0 && a.X0) ? 1.f : 0.f;
+        float d2 = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float ref = U1[mt][r] - c0 * (U1[mt][r] + Yr[mt][r]);
+                const float d = Un[mt][r] - ref;
+                d2 += d * d;
+            }
+        d2 = quad_sum(d2);
+        if (active) {
+            iters = it + 1;
+            last_d2 = d2;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            V[mt] = U1[mt];
+            U1[mt] = active ? Un[mt] : U1[mt];
+        }
+        bprev = bcur;
+        if (check_eps) {
+            if (active && sqrtf(d2) < a.eps) {
+                active = false;
+                converged = true;
+            }
+            if (!__any(active)) break;
+        }
+    }
+    float r2 = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) r2 += U1[mt][r] * U1[mt][r];
+    r2 = quad_sum(r2);
+    if (valid) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * nt + 4 * r + h;
+                if (n < N) a.X[pix * N + n] = bad ? 0.f : Xr[nt][r];
+            }
+        if (a.stats && h == 0) {
+            csrec_pixel_stats s;
+            s.iters = bad ? 0 : iters + a.iter_offset;
             s.flags = bad ? CSREC_FLAG_NONFINITE : (converged ? CSREC_FLAG_CONVERGED : CSREC_FLAG_ITER_CAP);
             s.resid = bad ? 0.f : sqrtf(r2);
             s.delta = bad ? __builtin_nanf("") : sqrtf(last_d2);
@@ -287,6 +525,36 @@ const FistaVariant kVariants[] = {
     {8, 16, 4, fista_f32_kernel<8, 16, 4, 1>},
 };
 
+const FistaVariant kVariantsBF16[] = {
+    {2, 8, 4, fista_lp_kernel<__bf16, 2, 8, 4, 2>},
+    {4, 8, 4, fista_lp_kernel<__bf16, 4, 8, 4, 2>},
+    {4, 10, 4, fista_lp_kernel<__bf16, 4, 10, 4, 2>},
+    {6, 14, 4, fista_lp_kernel<__bf16, 6, 14, 4, 1>},
+    {8, 16, 4, fista_lp_kernel<__bf16, 8, 16, 4, 1>},
+};
+const FistaVariant kVariantsF16[] = {
+    {2, 8, 4, fista_lp_kernel<_Float16, 2, 8, 4, 2>},
+    {4, 8, 4, fista_lp_kernel<_Float16, 4, 8, 4, 2>},
+    {4, 10, 4, fista_lp_kernel<_Float16, 4, 10, 4, 2>},
+    {6, 14, 4, fista_lp_kernel<_Float16, 6, 14, 4, 1>},
+    {8, 16, 4, fista_lp_kernel<_Float16, 8, 16, 4, 1>},
+};
+
+template <size_t K>
+const FistaVariant* pick_from(const FistaVariant (&vs)[K], int M, int N) {
+    const int mt = (int)ceil_div(M, 16), nt = (int)ceil_div(N, 16);
+    const FistaVariant* best = nullptr;
+    for (const auto& v : vs)
+        if (v.MT >= mt && v.NT >= nt && (!best || v.MT * v.NT < best->MT * best->NT)) best = &v;
+    return best;
+}
+
+const FistaVariant* pick(int M, int N, int prec) {
+    if (prec == CSREC_PREC_BF16) return pick_from(kVariantsBF16, M, N);
+    if (prec == CSREC_PREC_F16) return pick_from(kVariantsF16, M, N);
+    return pick_from(kVariants, M, N);
+}
+
 const FistaVariant* pick_f32(int M, int N) {
     const int mt = (int)ceil_div(M, 16), nt = (int)ceil_div(N, 16);
     const FistaVariant* best = nullptr;
@@ -298,15 +566,27 @@ const FistaVariant* pick_f32(int M, int N) {
 }  // namespace
 
 int fista_supported(int M, int N, int prec) {
-    if (prec == CSREC_PREC_F32) return pick_f32(M, N) ? CSREC_OK : CSREC_E_UNSUPPORTED;
-    return CSREC_E_UNSUPPORTED;
+    if (!pick(M, N, prec)) return CSREC_E_UNSUPPORTED;
+    if (prec != CSREC_PREC_F32 && !pick(M, N, CSREC_PREC_F32)) return CSREC_E_UNSUPPORTED;
+    return CSREC_OK;
 }
 
 size_t fista_workspace(int, int, int64_t, int) { return 0; }
 
+namespace {
+int launch_variant(const FistaVariant* v, const FistaArgs& a, hipStream_t stream) {
+    const int64_t pix_per_block = 16 * v->waves;
+    const int64_t blocks = ceil_div(a.P, pix_per_block);
+    if (blocks > 0x7fffffff) return CSREC_E_SHAPE;
+    hipLaunchKernelGGL(v->fn, dim3((unsigned)blocks), dim3(64 * v->waves), 0, stream, a);
+    CSREC_HIP_TRY(hipGetLastError());
+    return CSREC_OK;
+}
+}  // namespace
+
 int fista_launch(const FistaLaunch& l) {
     if (l.P == 0) return CSREC_OK;
-    const FistaVariant* v = pick_f32(l.M, l.N);
+    const FistaVariant* v = pick(l.M, l.N, l.prec);
     if (!v) return CSREC_E_UNSUPPORTED;
     FistaArgs a;
     a.A = l.A;
@@ -319,16 +599,19 @@ int fista_launch(const FistaLaunch& l) {
     a.N = l.N;
     a.P = l.P;
     a.max_iter = l.max_iter;
+    a.iter_offset = 0;
     a.invL = l.invL;
     a.thr = l.thr;
     a.eps = l.eps;
     a.lambda = l.lambda;
-    const int64_t pix_per_block = 16 * v->waves;
-    const int64_t blocks = ceil_div(l.P, pix_per_block);
-    if (blocks > 0x7fffffff) return CSREC_E_SHAPE;
-    hipLaunchKernelGGL(v->fn, dim3((unsigned)blocks), dim3(64 * v->waves), 0, l.stream, a);
-    CSREC_HIP_TRY(hipGetLastError());
-    return CSREC_OK;
+    int e = launch_variant(v, a, l.stream);
+    if (e || l.prec == CSREC_PREC_F32 || l.correction_iters <= 0) return e;
+    // FP32 correction: warm start from the 16-bit result (momentum restarts);
+    // each pixel's lanes read x before they write it, so X0 = X is safe.
+    a.X0 = l.X;
+    a.max_iter = l.correction_iters;
+    a.iter_offset = l.max_iter;
+    return launch_variant(pick(l.M, l.N, CSREC_PREC_F32), a, l.stream);
 }
 
 // ---------------------------------------------------------------- L by power iteration

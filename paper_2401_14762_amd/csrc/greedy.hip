@@ -111,6 +111,23 @@ __device__ __forceinline__ float gram<float>(const GArgs& g, int a, int b) { ret
 template <>
 __device__ __forceinline__ double gram<double>(const GArgs& g, int a, int b) { return g.G64[a * g.N + b]; }
 
+// Right-hand side b_j = a_j^T y of the normal equations.  The FP32 pass
+// reuses A^T y from its first correlation; the FP64 pass forms it in FP64,
+// since an ill-conditioned G[c, c] amplifies any error of b as much as one
+// of G.
+template <typename T>
+__device__ __forceinline__ T rhs(const GArgs& g, const Col<float>& ball, int64_t pix, int j);
+template <>
+__device__ __forceinline__ float rhs<float>(const GArgs&, const Col<float>& ball, int64_t, int j) {
+    return ball[j];
+}
+template <>
+__device__ __forceinline__ double rhs<double>(const GArgs& g, const Col<float>&, int64_t pix, int j) {
+    double acc = 0.0;
+    for (int m = 0; m < g.M; ++m) acc += (double)g.A[(size_t)m * g.N + j] * (double)g.Y[pix * g.M + m];
+    return acc;
+}
+
 template <typename T>
 __device__ __forceinline__ T tsqrt(T v);
 template <>
@@ -181,31 +198,51 @@ __device__ void chol_back(const Scratch<T>& s, int nc) {
 // Fresh factorisation of G[c, c] for c = cidx[0 .. n-1], rhs b_c = ball[c];
 // leaves s.sv = G[c,c]^{-1} b_c.  Returns the smallest pivot ratio.
 template <typename T>
-__device__ T chol_solve_fresh(const GArgs& g, const Scratch<T>& s, int n) {
+__device__ T chol_solve_fresh(const GArgs& g, const Scratch<T>& s, int n, int64_t pix) {
     T rmin = (T)1;
     for (int i = 0; i < n; ++i) {
-        const T r = chol_append<T>(g, s, i, s.cidx[i], (T)s.ball[s.cidx[i]]);
+        const T r = chol_append<T>(g, s, i, s.cidx[i], rhs<T>(g, s.ball, pix, s.cidx[i]));
         rmin = r < rmin ? r : rmin;
     }
     chol_back<T>(s, n);
     return rmin;
 }
 
-// keep = the k entries of cidx[0..n-1] with largest |sv| ((|sv| desc, index asc)).
+// keep = the k entries of cidx[0..n-1] with largest |sv| ((|sv| desc, index
+// asc), compared in T): one pass inserting each position a into a sorted
+// k-slot list (lidx), then the list's atoms as a bitmask.
 template <typename T>
 __device__ void mark_top_k(const GArgs& g, const Scratch<T>& s, int n, int k) {
     const int NW = (g.N + 31) / 32;
-    for (int w = 0; w < NW; ++w) s.keep[w] = 0u;
+    int len = 0;
+    T last = (T)-1;
+    int last_i = 0x7fffffff;
     for (int a = 0; a < n; ++a) {
-        const T va = s.sv[a] < (T)0 ? -s.sv[a] : s.sv[a];
+        const T sa = s.sv[a];
+        const T va = sa < (T)0 ? -sa : sa;
         const int ia = s.cidx[a];
-        int rank = 0;
-        for (int b = 0; b < n && rank < k; ++b) {
-            const T vb = s.sv[b] < (T)0 ? -s.sv[b] : s.sv[b];
-            const int ib = s.cidx[b];
-            rank += (vb > va || (vb == va && ib < ia)) ? 1 : 0;
+        if (len == k && !(va > last || (va == last && ia < last_i))) continue;
+        int pos = len < k ? len : k - 1;
+        while (pos > 0) {
+            const int pa = s.lidx[pos - 1];
+            const T ps = s.sv[pa];
+            const T pv = ps < (T)0 ? -ps : ps;
+            const int pi = s.cidx[pa];
+            if (!(va > pv || (va == pv && ia < pi))) break;
+            if (pos < k) s.lidx[pos] = pa;
+            --pos;
         }
-        if (rank < k) s.keep[ia >> 5] |= 1u << (ia & 31);
+        s.lidx[pos] = a;
+        if (len < k) ++len;
+        const int la = s.lidx[len - 1];
+        const T ls = s.sv[la];
+        last = ls < (T)0 ? -ls : ls;
+        last_i = s.cidx[la];
+    }
+    for (int w = 0; w < NW; ++w) s.keep[w] = 0u;
+    for (int a = 0; a < len; ++a) {
+        const int ia = s.cidx[s.lidx[a]];
+        s.keep[ia >> 5] |= 1u << (ia & 31);
     }
 }
 
@@ -224,7 +261,7 @@ __device__ __forceinline__ int extract_bits(const Col<uint32_t>& bits, int NW, c
 }
 
 template <int KIND, int MMAX, int SMAX, typename T>
-__global__ __launch_bounds__(512, 1) void greedy_kernel(GArgs g, int64_t p0, int64_t np, int pass) {
+__global__ __launch_bounds__(256, 2) void greedy_kernel(GArgs g, int64_t p0, int64_t np, int pass) {
     constexpr int PAT = MMAX + 4;
     extern __shared__ float sAT[];
     const int M = g.M, N = g.N, K = g.K;
@@ -339,7 +376,7 @@ __global__ __launch_bounds__(512, 1) void greedy_kernel(GArgs g, int64_t p0, int
                 const int j = bi[q];
                 if (j < 0) break;   // no admissible atom left (non-finite correlations)
                 s.mask[j >> 5] |= 1u << (j & 31);
-                const T ratio = chol_append<T>(g, s, nc, j, (T)s.ball[j]);
+                const T ratio = chol_append<T>(g, s, nc, j, rhs<T>(g, s.ball, pix, j));
                 if (g.pivot_thr > 0.0 && (double)ratio < g.pivot_thr) fallback = true;
                 ++nc;
             }
@@ -367,7 +404,7 @@ __global__ __launch_bounds__(512, 1) void greedy_kernel(GArgs g, int64_t p0, int
                 sq.z.off += nc;
                 sq.sv.off += nc;
                 sq.cidx.off += nc;
-                chol_solve_fresh<T>(g, sq, nq);
+                chol_solve_fresh<T>(g, sq, nq, pix);
                 for (int a = 0; a < nq; ++a) s.xval[a] = (float)sq.sv[a];
                 nx = nq;
             } else {
@@ -396,7 +433,7 @@ __global__ __launch_bounds__(512, 1) void greedy_kernel(GArgs g, int64_t p0, int
                 s.mask[j >> 5] |= 1u << (j & 31);
             }
             nc = extract_bits(s.mask, NW, s.cidx);
-            chol_solve_fresh<T>(g, s, nc);
+            chol_solve_fresh<T>(g, s, nc, pix);
             const int keepn = nc < K ? nc : K;
             mark_top_k<T>(g, s, nc, keepn);
             nx = 0;
@@ -512,7 +549,7 @@ __global__ __launch_bounds__(512, 1) void greedy_kernel(GArgs g, int64_t p0, int
         sq.z.off += nc;
         sq.sv.off += nc;
         sq.cidx.off += nc;
-        chol_solve_fresh<T>(g, sq, nq);
+        chol_solve_fresh<T>(g, sq, nq, pix);
         for (int a = 0; a < nq; ++a) s.xval[a] = (float)sq.sv[a];
         nx = nq;
         // residual of the pruned x
@@ -593,6 +630,7 @@ gk_t pick_T(bool dbl) {
 template <int KIND, int SMAX>
 gk_t pick_M(int M, bool dbl) {
     if (M <= 48) return pick_T<KIND, 48, SMAX>(dbl);
+    if (M <= 80) return pick_T<KIND, 80, SMAX>(dbl);
     if (M <= 96) return pick_T<KIND, 96, SMAX>(dbl);
     return nullptr;
 }
@@ -609,7 +647,7 @@ gk_t pick_kernel(GreedyKind kind, int M, int S, bool dbl) {
     return nullptr;
 }
 
-int mmax_for(int M) { return M <= 48 ? 48 : 96; }
+int mmax_for(int M) { return M <= 48 ? 48 : (M <= 80 ? 80 : 96); }
 
 struct Layout {
     int CM, LM;
@@ -623,8 +661,8 @@ Layout layout_for(const GreedyLaunch& a) {
     Layout L;
     int CM = 0, LM = 1;
     switch (a.kind) {
-        case GREEDY_GOMP: CM = a.S * a.max_iter + a.K; LM = 1; break;   // c plus a q-sized tail
-        case GREEDY_COSAMP: CM = 3 * a.K; LM = 2 * a.K; break;
+        case GREEDY_GOMP: CM = a.S * a.max_iter + a.K; LM = a.K; break;   // c plus a q-sized tail
+        case GREEDY_COSAMP: CM = 3 * a.K; LM = 2 * a.K; break;   // (>= K for the prune list)
         case GREEDY_BIHT: CM = 2 * a.K; LM = a.K; break;
         case GREEDY_BIHT_ONE_BIT: CM = a.K; LM = a.K; break;
     }
@@ -699,7 +737,7 @@ int greedy_launch(const GreedyLaunch& a) {
     }
     const int mmax = mmax_for(a.M);
     const size_t lds = (size_t)a.N * (mmax + 4) * sizeof(float);
-    const int threads = 512;
+    const int threads = 256;
     gk_t fns[2] = {pick_kernel(a.kind, a.M, a.S, false), dbl ? pick_kernel(a.kind, a.M, a.S, true) : nullptr};
     for (int pass = 0; pass < (dbl ? 2 : 1); ++pass) {
         if (!fns[pass]) return CSREC_E_UNSUPPORTED;
