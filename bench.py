@@ -27,10 +27,28 @@ sys.path.insert(0, ROOT)
 
 FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20      # calibration copy: 256 MiB read + 256 MiB written
 
 FISTA_ITERS = 200
 LAMBDA = 1e-2
 GOMP_S, GOMP_K, GOMP_TOL = 2, 20, 1e-3
+
+
+def measured_traffic(kernel_src: str, summary: str):
+    """HBM bytes per FISTA launch from the committed rocprofv3 counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(summary).read()
+        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"fista\.hip sha256 at measurement: `([0-9a-f]+)`", text)
+    row = re.search(r"fista_f32_kernel<[^|]*\| *\d+ *\| *\d+ *\| *([0-9.]+) MB", text)
+    if not m or not row or m.group(1) != sha:
+        return None
+    return float(row.group(1)) * 1e6
 
 
 def parse():
@@ -80,6 +98,13 @@ def main():
             ev[2].record(stream)
         return out
 
+    # a plain device copy of known size, outside the timed region: the
+    # reference that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters
+    calib = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    calib_dst = torch.empty_like(calib)
+    calib_dst.copy_(calib)
+    torch.cuda.synchronize()
+    del calib, calib_dst
     print(f"[bench] workload plain {int(math.isqrt(P))}x{int(math.isqrt(P))} N={N} M={M}: warmup {args.warmup}",
           file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -154,7 +179,9 @@ def main():
                    "pixels": P, "N": N, "M": M},
         "roofline": {"bound": "mfma", "kernel": "fista_f32_kernel", "achieved": achieved,
                      "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                     "traffic": measured_traffic(os.path.join(ROOT, "paper_2401_14762_amd", "csrc", "fista.hip"),
+                                                 os.path.join(ROOT, "profiles", "fista_gomp_plain256_counters.md")),
                      "avg_launch_ms": fista_avg_ms},
         "cpu_baseline": cpu,
         "breakdown": {
