@@ -186,6 +186,63 @@ int32_t csrec_biht(const csrec_problem* problem, const csrec_biht_params* params
  * writes one float to *L_out (device pointer) on `stream`. */
 int32_t csrec_lipschitz(const float* A, int32_t M, int32_t N, float* L_out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of cube tiles (gOMP, Alg. 3).
+ *
+ * A server owns, on one device: a pool of `hbm_budget_bytes` for the tiles'
+ * measurements and results, a batch workspace for `batch_pixels` pixels of
+ * solver state, the registered dictionaries (A with its Gram matrix, resident
+ * until destroy) and a scheduler thread.  Submitted tiles wait in arrival
+ * order until their measurements and results fit in the pool (admission);
+ * admitted tiles are cut into pixel chunks, and chunks of any admitted tiles
+ * -- also of different band counts -- are solved together in batched
+ * launches, up to two batches in flight, so that tiles arriving while others
+ * run join the next launch.  Each pixel's result depends only on its own
+ * measurements and its dictionary: a tile's result is bit-identical whether
+ * it runs alone or mixed with others.
+ *
+ * Threading: submit/poll/release/drain may be called from any host thread.
+ * Host buffers passed to submit are copied before the call returns.
+ * ---------------------------------------------------------------------- */
+typedef struct csrec_server csrec_server;
+
+typedef struct {
+    int32_t struct_size;          /* sizeof(csrec_server_cfg) */
+    int32_t device;               /* HIP device ordinal */
+    size_t hbm_budget_bytes;      /* pool for admitted tiles (Y in, X/support/stats out) */
+    int64_t batch_pixels;         /* pixels per batched launch (solver workspace capacity) */
+    int64_t chunk_pixels;         /* largest piece of one tile in a batch */
+    csrec_gomp_params gomp;       /* solver parameters of every tile (K, S, res_tol, ...) */
+} csrec_server_cfg;
+
+typedef struct {
+    uint64_t tag;                 /* submit tag */
+    int32_t status;               /* CSREC_OK or an error code */
+    int32_t dict_id;
+    int64_t P;
+    int32_t N, K;
+    const float* X;               /* host, P x N; valid until csrec_server_release(tag) */
+    const int32_t* support;       /* host, P x K */
+    const csrec_pixel_stats* stats; /* host, P */
+    double t_submit, t_admit, t_done; /* seconds since server creation */
+} csrec_result;
+
+/* Creates the server (allocates its pool and workspace once). */
+int32_t csrec_server_create(const csrec_server_cfg* cfg, csrec_server** out);
+/* Registers a dictionary (host A, M x N row-major); returns its id. */
+int32_t csrec_server_add_dict(csrec_server* srv, const float* A_host, int32_t M, int32_t N, int32_t* dict_id);
+/* Queues a tile of P pixels (host Y, P x M row-major) for dictionary dict_id.
+ * CSREC_E_BUDGET if the tile alone exceeds the pool or the batch workspace. */
+int32_t csrec_server_submit(csrec_server* srv, int32_t dict_id, const float* Y_host, int64_t P, uint64_t tag);
+/* Moves up to max finished tiles into out; *n receives the count. */
+int32_t csrec_server_poll(csrec_server* srv, csrec_result* out, int32_t max, int32_t* n);
+/* Frees the host results of a polled tile. */
+int32_t csrec_server_release(csrec_server* srv, uint64_t tag);
+/* Blocks until every submitted tile has finished (results stay pollable). */
+int32_t csrec_server_drain(csrec_server* srv);
+/* Stops the scheduler and frees every resource of the server. */
+int32_t csrec_server_destroy(csrec_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

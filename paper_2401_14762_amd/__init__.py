@@ -22,7 +22,7 @@ from . import _lib
 from ._lib import (CsrecError, FLAG_CONVERGED, FLAG_FP64_FALLBACK, FLAG_ITER_CAP,
                    FLAG_NONFINITE, MAX_N)
 
-__all__ = ["fista", "gomp", "cosamp", "biht", "lipschitz", "CsrecError", "FLAG_CONVERGED",
+__all__ = ["fista", "gomp", "cosamp", "biht", "lipschitz", "Server", "CsrecError", "FLAG_CONVERGED",
            "FLAG_ITER_CAP", "FLAG_FP64_FALLBACK", "FLAG_NONFINITE", "MAX_N", "workspace_bytes",
            "library"]
 
@@ -246,3 +246,89 @@ def lipschitz(A, stream=None):
     _lib.check(lib.csrec_lipschitz(_ptr(A), M, N, _ptr(out), ctypes.c_void_p(s.cuda_stream)),
                "csrec_lipschitz")
     return out
+
+
+class Server:
+    """Continuous-batching gOMP server (csrec_server_*): tiles of any band
+    count are submitted from host memory, admitted by HBM budget, solved in
+    batched launches with other admitted tiles, and polled back with their
+    submit / admit / done times (seconds since creation)."""
+
+    def __init__(self, K: int, S: int, res_tol: float = 0.0, max_iter: int = 0, prune: str = "each",
+                 pivot_fallback: float = 0.0, hbm_budget_bytes: int = 4 << 30, batch_pixels: int = 262144,
+                 chunk_pixels: int = 65536, device: int = 0):
+        import numpy as np  # noqa: F401
+        lib = library()
+        cfg = _lib.ServerCfg()
+        cfg.struct_size = ctypes.sizeof(cfg)
+        cfg.device = device
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.batch_pixels = int(batch_pixels)
+        cfg.chunk_pixels = int(chunk_pixels)
+        g, _ = _params("gomp", None, 0, dict(K=K, S=S, max_iter=max_iter, res_tol=res_tol, prune=prune,
+                                            pivot_fallback=pivot_fallback))
+        cfg.gomp = g
+        h = ctypes.c_void_p(0)
+        _lib.check(lib.csrec_server_create(ctypes.byref(cfg), ctypes.byref(h)), "csrec_server_create")
+        self._lib, self._h, self.K = lib, h, K
+        self._dicts = {}
+
+    def add_dict(self, A) -> int:
+        import numpy as np
+        A = np.ascontiguousarray(A, dtype=np.float32)
+        M, N = A.shape
+        did = ctypes.c_int32(-1)
+        _lib.check(self._lib.csrec_server_add_dict(self._h, A.ctypes.data, M, N, ctypes.byref(did)),
+                   "csrec_server_add_dict")
+        self._dicts[did.value] = (M, N)
+        return did.value
+
+    def submit(self, dict_id: int, Y, tag: int) -> None:
+        import numpy as np
+        Y = np.ascontiguousarray(Y, dtype=np.float32)
+        _lib.check(self._lib.csrec_server_submit(self._h, dict_id, Y.ctypes.data, Y.shape[0], tag),
+                   "csrec_server_submit")
+
+    def poll(self, max_results: int = 256) -> list:
+        """Finished tiles as dicts (tag, status, X, support, iters, flags, t_submit, t_admit, t_done);
+        arrays are copies, the server's buffers are released."""
+        import numpy as np
+        buf = (_lib.Result * max_results)()
+        n = ctypes.c_int32(0)
+        _lib.check(self._lib.csrec_server_poll(self._h, buf, max_results, ctypes.byref(n)), "csrec_server_poll")
+        out = []
+        for r in buf[:n.value]:
+            P, N, K = r.P, r.N, r.K
+            if P > 0 and r.status == 0:
+                X = np.ctypeslib.as_array((ctypes.c_float * (P * N)).from_address(r.X)).reshape(P, N).copy()
+                S = np.ctypeslib.as_array((ctypes.c_int32 * (P * K)).from_address(r.support)).reshape(P, K).copy()
+                st = np.ctypeslib.as_array((ctypes.c_int32 * (P * 4)).from_address(r.stats)).reshape(P, 4).copy()
+            else:
+                X = np.zeros((P, N), np.float32)
+                S = np.full((P, K), -1, np.int32)
+                st = np.zeros((P, 4), np.int32)
+            out.append(dict(tag=r.tag, status=r.status, dict_id=r.dict_id, X=X, support=S, iters=st[:, 0],
+                            flags=st[:, 1].view(np.uint32), resid=st[:, 2].view(np.float32),
+                            t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done))
+            self._lib.csrec_server_release(self._h, r.tag)
+        return out
+
+    def drain(self) -> None:
+        _lib.check(self._lib.csrec_server_drain(self._h), "csrec_server_drain")
+
+    def close(self) -> None:
+        if self._h:
+            self._lib.csrec_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -94,6 +94,34 @@ class BihtParams(ctypes.Structure):
     ]
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("hbm_budget_bytes", ctypes.c_size_t),
+        ("batch_pixels", ctypes.c_int64),
+        ("chunk_pixels", ctypes.c_int64),
+        ("gomp", GompParams),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("tag", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("dict_id", ctypes.c_int32),
+        ("P", ctypes.c_int64),
+        ("N", ctypes.c_int32),
+        ("K", ctypes.c_int32),
+        ("X", ctypes.c_void_p),
+        ("support", ctypes.c_void_p),
+        ("stats", ctypes.c_void_p),
+        ("t_submit", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
+
+
 # every symbol the header declares, with (restype, argtypes)
 _P = ctypes.POINTER
 SIGNATURES = {
@@ -111,6 +139,16 @@ SIGNATURES = {
                                     ctypes.c_void_p]),
     "csrec_lipschitz": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "csrec_server_create": (ctypes.c_int32, [_P(ServerCfg), _P(ctypes.c_void_p)]),
+    "csrec_server_add_dict": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                               ctypes.c_int32, _P(ctypes.c_int32)]),
+    "csrec_server_submit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                             ctypes.c_int64, ctypes.c_uint64]),
+    "csrec_server_poll": (ctypes.c_int32, [ctypes.c_void_p, _P(Result), ctypes.c_int32,
+                                           _P(ctypes.c_int32)]),
+    "csrec_server_release": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64]),
+    "csrec_server_drain": (ctypes.c_int32, [ctypes.c_void_p]),
+    "csrec_server_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
 }
 
 _lib = None

@@ -84,4 +84,23 @@ constexpr int GREEDY_CMAX = 64;
 size_t greedy_workspace(const GreedyLaunch& a);
 int greedy_launch(const GreedyLaunch& a);
 
+// Grouped gOMP launches over pixel chunks of several tiles (serving).
+struct GreedyTileItem {
+    const float* A;
+    const float* Y;
+    float* X;
+    int32_t* support;
+    csrec_pixel_stats* stats;
+    const float* G32;
+    const double* G64;
+    int M, N, max_iter;
+    int64_t p0, np;
+};
+int greedy_mmax_class(int M);
+size_t greedy_group_item_bytes();
+size_t greedy_group_workspace(const GreedyLaunch& proto_max, int64_t batch_pixels);
+int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* items, int nitems,
+                        int64_t batch_pixels, void* ws, void* table_host, void* table_dev, hipStream_t stream);
+int greedy_gram(const float* A, int M, int N, float* G32, double* G64, hipStream_t stream);
+
 }  // namespace csrec

@@ -49,6 +49,13 @@ struct GArgs {
     uint32_t* fbflag;      // per chunk pixel: 1 = redo in FP64
 };
 
+struct GroupItem {
+    GArgs g;            // the item's problem (dictionary, measurements, outputs) + batch scratch
+    int64_t p0, np;     // pixels [p0, p0 + np) of the item's tile
+    int64_t block0;     // first workgroup of the item in the grouped launch
+    int64_t slot0;      // first batch scratch column of the item
+};
+
 // strided scratch view: element k of this lane's column.  The lane base is
 // shared by every view of a region; offset and stride are wave-uniform.
 template <typename E>
@@ -260,10 +267,13 @@ __device__ __forceinline__ int extract_bits(const Col<uint32_t>& bits, int NW, c
     return cnt;
 }
 
+// One workgroup of a solve: pixels p0 + block*blockDim + [0, blockDim) of the
+// problem in g (at most np of them), using scratch columns slot0 + the same
+// offsets.  Shared by the plain launch and the grouped (serving) launch.
 template <int KIND, int MMAX, int SMAX, typename T>
-__global__ __launch_bounds__(256, 2) void greedy_kernel(GArgs g, int64_t p0, int64_t np, int pass) {
+__device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t np, int pass, int64_t block,
+                                             int64_t slot0, float* sAT) {
     constexpr int PAT = MMAX + 4;
-    extern __shared__ float sAT[];
     const int M = g.M, N = g.N, K = g.K;
     for (int idx = threadIdx.x; idx < N * PAT; idx += blockDim.x) {
         const int n = idx / PAT;
@@ -272,9 +282,10 @@ __global__ __launch_bounds__(256, 2) void greedy_kernel(GArgs g, int64_t p0, int
     }
     __syncthreads();
 
-    const int64_t local = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (local >= np) return;
-    const int64_t pix = p0 + local;
+    const int64_t within = block * blockDim.x + threadIdx.x;
+    if (within >= np) return;
+    const int64_t pix = p0 + within;
+    const int64_t local = slot0 + within;   // scratch column
     if (pass == 1 && g.fbflag[local] == 0u) return;   // FP64 redo only for marked pixels
     const Scratch<T> s = make_scratch<T>(g, local, MMAX);
     const int NW = (N + 31) / 32;
@@ -608,6 +619,26 @@ __global__ __launch_bounds__(256, 2) void greedy_kernel(GArgs g, int64_t p0, int
     }
 }
 
+template <int KIND, int MMAX, int SMAX, typename T>
+__global__ __launch_bounds__(256, 2) void greedy_kernel(GArgs g, int64_t p0, int64_t np, int pass) {
+    extern __shared__ float sAT[];
+    greedy_block<KIND, MMAX, SMAX, T>(g, p0, np, pass, blockIdx.x, 0, sAT);
+}
+
+// Grouped launch: blocks [items[i].block0, items[i+1].block0) solve item i
+// (its own dictionary, measurements and outputs); scratch columns are
+// batch-wide slots.
+template <int KIND, int MMAX, int SMAX, typename T>
+__global__ __launch_bounds__(256, 2) void greedy_grouped_kernel(const GroupItem* __restrict__ items, int nitems,
+                                                                int pass) {
+    extern __shared__ float sAT[];
+    int it = 0;
+    while (it + 1 < nitems && items[it + 1].block0 <= (int64_t)blockIdx.x) ++it;
+    const GArgs g = items[it].g;
+    greedy_block<KIND, MMAX, SMAX, T>(g, items[it].p0, items[it].np, pass, blockIdx.x - items[it].block0,
+                                      items[it].slot0, sAT);
+}
+
 // Gram matrix G = A^T A in FP64, stored as FP32 and FP64.
 __global__ void gram_kernel(const float* __restrict__ A, int M, int N, float* __restrict__ G32,
                             double* __restrict__ G64) {
@@ -657,7 +688,7 @@ struct Layout {
 
 constexpr int64_t kChunk = 65536;
 
-Layout layout_for(const GreedyLaunch& a) {
+Layout layout_for(const GreedyLaunch& a, int64_t ch_override = 0) {
     Layout L;
     int CM = 0, LM = 1;
     switch (a.kind) {
@@ -669,6 +700,7 @@ Layout layout_for(const GreedyLaunch& a) {
     L.CM = CM;
     L.LM = LM;
     L.CH = a.P < kChunk ? ((a.P + 63) / 64) * 64 : kChunk;
+    if (ch_override > 0) L.CH = ((ch_override + 63) / 64) * 64;
     if (L.CH == 0) L.CH = 64;
     const bool dbl = a.kind == GREEDY_GOMP && a.pivot_fallback > 0.0;
     const size_t tsz = dbl ? 8 : 4;
@@ -693,6 +725,116 @@ Layout layout_for(const GreedyLaunch& a) {
 }  // namespace
 
 size_t greedy_workspace(const GreedyLaunch& a) { return layout_for(a).total; }
+
+// ---------------------------------------------------------------- grouped (serving) launches
+
+namespace {
+typedef void (*ggk_t)(const GroupItem*, int, int);
+
+template <int MMAX>
+ggk_t pick_grouped(bool dbl, int S) {
+    if (S <= 2)
+        return dbl ? greedy_grouped_kernel<GREEDY_GOMP, MMAX, 2, double> : greedy_grouped_kernel<GREEDY_GOMP, MMAX, 2, float>;
+    return dbl ? greedy_grouped_kernel<GREEDY_GOMP, MMAX, 8, double> : greedy_grouped_kernel<GREEDY_GOMP, MMAX, 8, float>;
+}
+ggk_t pick_grouped_m(int mmax, bool dbl, int S) {
+    if (mmax == 48) return pick_grouped<48>(dbl, S);
+    if (mmax == 80) return pick_grouped<80>(dbl, S);
+    return pick_grouped<96>(dbl, S);
+}
+}  // namespace
+
+int greedy_mmax_class(int M) { return mmax_for(M); }
+
+size_t greedy_group_item_bytes() { return sizeof(GroupItem); }
+
+size_t greedy_group_workspace(const GreedyLaunch& proto_max, int64_t batch_pixels) {
+    return layout_for(proto_max, batch_pixels).total;
+}
+
+int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* items, int nitems,
+                        int64_t batch_pixels, void* ws, void* table_host, void* table_dev, hipStream_t stream) {
+    if (nitems <= 0) return CSREC_OK;
+    const GreedyLaunch& pm = proto_max;
+    const Layout L = layout_for(pm, batch_pixels);
+    const bool dbl = pm.pivot_fallback > 0.0;
+    char* w = static_cast<char*>(ws);
+    GroupItem* th = static_cast<GroupItem*>(table_host);
+    GroupItem* td = static_cast<GroupItem*>(table_dev);
+    // items of one MMAX class go to one launch; the table is laid out class by class
+    int nt = 0;
+    int64_t slot = 0;
+    struct Range { int first, count; int64_t blocks; int mmax; size_t lds; };
+    Range ranges[3];
+    int nr = 0;
+    const int classes[3] = {48, 80, 96};
+    for (int c = 0; c < 3; ++c) {
+        const int first = nt;
+        int64_t blocks = 0;
+        size_t lds = 0;
+        for (int i = 0; i < nitems; ++i) {
+            const GreedyTileItem& it = items[i];
+            if (mmax_for(it.M) != classes[c]) continue;
+            GroupItem gi{};
+            GArgs& g = gi.g;
+            g.A = it.A;
+            g.Y = it.Y;
+            g.Ysign = nullptr;
+            g.X = it.X;
+            g.support = it.support;
+            g.stats = it.stats;
+            g.G32 = it.G32;
+            g.G64 = it.G64;
+            g.M = it.M;
+            g.N = it.N;
+            g.K = pm.K;
+            g.S = pm.S;
+            g.Imax = it.max_iter;
+            g.prune = pm.prune;
+            g.res_tol = pm.res_tol;
+            g.eps = pm.eps;
+            g.mu = 0.f;
+            g.pivot_thr = pm.pivot_fallback;
+            g.scr = w;
+            g.CH = L.CH;
+            g.CM = pm.S * it.max_iter + pm.K;
+            g.LM = pm.K;
+            g.off_T = (int64_t)L.off_T;
+            g.off_i = (int64_t)L.off_i;
+            g.off_r = (int64_t)L.off_r;
+            g.fbflag = dbl ? reinterpret_cast<uint32_t*>(w + L.off_f) : nullptr;
+            gi.p0 = it.p0;
+            gi.np = it.np;
+            gi.block0 = blocks;
+            gi.slot0 = slot;
+            if (slot + it.np > L.CH) return CSREC_E_SHAPE;
+            slot += it.np;
+            blocks += ceil_div(it.np, 256);
+            const size_t need = (size_t)it.N * (classes[c] + 4) * sizeof(float);
+            lds = need > lds ? need : lds;
+            th[nt++] = gi;
+        }
+        if (nt > first) ranges[nr++] = Range{first, nt - first, blocks, classes[c], lds};
+    }
+    CSREC_HIP_TRY(hipMemcpyAsync(td, th, (size_t)nt * sizeof(GroupItem), hipMemcpyHostToDevice, stream));
+    for (int pass = 0; pass < (dbl ? 2 : 1); ++pass) {
+        for (int r = 0; r < nr; ++r) {
+            ggk_t fn = pick_grouped_m(ranges[r].mmax, pass == 1, pm.S);
+            CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)ranges[r].lds));
+            hipLaunchKernelGGL(fn, dim3((unsigned)ranges[r].blocks), dim3(256), ranges[r].lds, stream,
+                               td + ranges[r].first, ranges[r].count, pass);
+            CSREC_HIP_TRY(hipGetLastError());
+        }
+    }
+    return CSREC_OK;
+}
+
+int greedy_gram(const float* A, int M, int N, float* G32, double* G64, hipStream_t stream) {
+    hipLaunchKernelGGL(gram_kernel, dim3(N), dim3(256), 0, stream, A, M, N, G32, G64);
+    CSREC_HIP_TRY(hipGetLastError());
+    return CSREC_OK;
+}
 
 int greedy_launch(const GreedyLaunch& a) {
     if (a.P == 0) return CSREC_OK;

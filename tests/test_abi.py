@@ -53,13 +53,16 @@ def test_struct_layout_matches_c(tmp_path):
         "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\","
         "sizeof(csrec_problem), sizeof(csrec_pixel_stats), sizeof(csrec_fista_params),"
         "sizeof(csrec_gomp_params), sizeof(csrec_cosamp_params), sizeof(csrec_biht_params),"
-        "offsetof(csrec_problem, workspace_bytes), offsetof(csrec_biht_params, Ysign));return 0;}\n")
+        "offsetof(csrec_problem, workspace_bytes), offsetof(csrec_biht_params, Ysign));"
+        "printf(\"%zu %zu %zu\\n\", sizeof(csrec_server_cfg), sizeof(csrec_result), offsetof(csrec_result, t_done));"
+        "return 0;}\n")
     exe = tmp_path / "sizes"
     subprocess.run([cc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     want = [ctypes.sizeof(L.Problem), ctypes.sizeof(L.PixelStats), ctypes.sizeof(L.FistaParams),
             ctypes.sizeof(L.GompParams), ctypes.sizeof(L.CosampParams), ctypes.sizeof(L.BihtParams),
-            L.Problem.workspace_bytes.offset, L.BihtParams.Ysign.offset]
+            L.Problem.workspace_bytes.offset, L.BihtParams.Ysign.offset,
+            ctypes.sizeof(L.ServerCfg), ctypes.sizeof(L.Result), L.Result.t_done.offset]
     assert got == want
 
 

@@ -1,0 +1,91 @@
+"""Serving (continuous batching) through the csrec_server_* C-ABI.
+
+Checks: every tile's result is bit-identical alone and in the mix (and equal
+to the direct csrec_gomp call on the same tile); tiles of different band
+counts share launches; admission waits for HBM budget and keeps arrival
+order; a tile larger than the budget is refused with CSREC_E_BUDGET."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import GAP, note, np_of, rel_err_rows, require_gpu, to_dev
+from paper_2401_14762_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+K, S, TOL = 20, 2, 1e-3
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _tiles():
+    out = []
+    for i, (side, N) in enumerate([(40, 100), (64, 200), (23, 224), (90, 200), (7, 100), (64, 224)]):
+        M = W.m_for(N)
+        _, a32, _, phi = W.serving_dictionary(N)
+        F = W.mixing_spectra(side * side, N, 40.0, 500 + i)
+        out.append((N, (F @ phi.T).astype(np.float32)))
+    return out
+
+
+def _dicts():
+    return {N: W.serving_dictionary(N)[1] for N in (100, 200, 224)}
+
+
+def _serve(cs, tiles, dicts, budget=1 << 30, batch=32768, chunk=4096):
+    with cs.Server(K=K, S=S, res_tol=TOL, hbm_budget_bytes=budget, batch_pixels=batch, chunk_pixels=chunk) as srv:
+        ids = {N: srv.add_dict(A) for N, A in dicts.items()}
+        for tag, (N, Y) in enumerate(tiles):
+            srv.submit(ids[N], Y, tag)
+        srv.drain()
+        res = {r["tag"]: r for r in srv.poll(1000)}
+    return res
+
+
+def test_alone_equals_mix_equals_direct(torch):
+    import paper_2401_14762_amd as cs
+    tiles, dicts = _tiles(), _dicts()
+    note("serving: all tiles mixed")
+    mix = _serve(cs, tiles, dicts)
+    assert sorted(mix) == list(range(len(tiles)))
+    for tag, (N, Y) in enumerate(tiles):
+        note(f"serving: tile {tag} alone (N={N}, P={Y.shape[0]})")
+        alone = _serve(cs, [(N, Y)], dicts)[0]
+        assert mix[tag]["status"] == 0 and alone["status"] == 0
+        assert np.array_equal(mix[tag]["X"], alone["X"]), tag
+        assert np.array_equal(mix[tag]["support"], alone["support"]), tag
+        X, Sup, st = cs.gomp(to_dev(torch, dicts[N]), to_dev(torch, Y), K=K, S=S, res_tol=TOL)
+        torch.cuda.synchronize()
+        assert np.array_equal(mix[tag]["X"], np_of(X)), tag
+        assert np.array_equal(mix[tag]["support"], np_of(Sup)), tag
+        assert np.array_equal(mix[tag]["iters"], np_of(st["iters"])), tag
+    # oracle parity on one tile's pixels away from near-ties
+    N, Y = tiles[1]
+    ref = oracle.gomp(dicts[N], Y[:300], K=K, S=S, res_tol=TOL, diagnostics=True)
+    clean = (ref["sel_gap"] >= GAP) & (ref["prune_gap"] >= GAP) & (ref["stop_margin"] >= 1e-3)
+    assert clean.mean() > 0.8
+    assert np.array_equal(mix[1]["support"][:300][clean], ref["support"][clean])
+    assert rel_err_rows(mix[1]["X"][:300][clean], ref["X"][clean]).max() <= 1e-5
+
+
+def test_budget_admission_and_order(torch):
+    import paper_2401_14762_amd as cs
+    tiles, dicts = _tiles(), _dicts()
+    # a pool that holds about one large tile at a time: tiles wait for space
+    big = max(Y.shape[0] * (Y.shape[1] + 224 + K + 4) * 4 for _, Y in tiles)
+    note("serving: tight budget")
+    res = _serve(cs, tiles, dicts, budget=int(big * 1.3) + 65536)
+    admits = [res[t]["t_admit"] for t in range(len(tiles))]
+    assert admits == sorted(admits)
+    for t in range(len(tiles)):
+        assert res[t]["t_submit"] <= res[t]["t_admit"] <= res[t]["t_done"]
+    mix = _serve(cs, tiles, dicts)
+    for t in range(len(tiles)):
+        assert np.array_equal(res[t]["X"], mix[t]["X"])
+    with cs.Server(K=K, S=S, res_tol=TOL, hbm_budget_bytes=1 << 20, batch_pixels=4096) as srv:
+        d = srv.add_dict(dicts[200])
+        with pytest.raises(cs.CsrecError) as ei:
+            srv.submit(d, tiles[3][1], 0)
+        assert ei.value.code == -6
