@@ -72,16 +72,18 @@ def top_indices(values: np.ndarray, k: int, allowed: Optional[np.ndarray] = None
     return order[:, :k]
 
 
-def _ordered_gap(values: np.ndarray, k: int, allowed: Optional[np.ndarray] = None) -> np.ndarray:
+def _ordered_gap(values: np.ndarray, k: int, allowed: Optional[np.ndarray] = None,
+                 scale: Optional[np.ndarray] = None) -> np.ndarray:
     """(|v|_(k) - |v|_(k+1)) / max|v| per row over the allowed entries:
-    how far the k-th choice of ``top_indices`` is from a tie."""
+    how far the k-th choice of ``top_indices`` is from a tie.  With ``scale``
+    (one value per row) the gap is divided by it instead of by max|v|."""
     key = np.abs(values)
     if allowed is not None:
         key = np.where(allowed, key, -np.inf)
     srt = -np.sort(-key, axis=1)
     if srt.shape[1] <= k:
         return np.full(key.shape[0], np.inf)
-    top = np.maximum(srt[:, 0], 1e-300)
+    top = np.maximum(srt[:, 0] if scale is None else np.asarray(scale, dtype=np.float64), 1e-300)
     nxt = np.where(np.isfinite(srt[:, k]), srt[:, k], 0.0)
     return (srt[:, k - 1] - nxt) / top
 
@@ -217,7 +219,11 @@ def gomp(A, Y, K: int, S: int, max_iter: int = 0, res_tol: float = 0.0, eps: flo
 
     Returns dict(X, support (P x K, ascending, -1 padded), iters, delta, resid,
     flags) and, with diagnostics=True, per-pixel minimum selection gap,
-    prune gap, stop margin and pivot ratio."""
+    prune gap, stop margin and pivot ratio.  The gaps come twice: relative to
+    the largest compared value (sel_gap, prune_gap) and relative to the scale
+    on which rounding perturbs the compared values -- ||y|| for the
+    correlations, which are formed from a residual y - A x, and ||s|| for the
+    least-squares coefficients (sel_gap_abs, prune_gap_abs)."""
     A = _f64(A)
     Y = _f64(Y)
     P, M = Y.shape
@@ -239,6 +245,8 @@ def gomp(A, Y, K: int, S: int, max_iter: int = 0, res_tol: float = 0.0, eps: flo
     flags[~fin] |= STOP_NONFINITE
     sel_gap = np.full(P, np.inf)
     prune_gap = np.full(P, np.inf)
+    sel_gap_abs = np.full(P, np.inf)
+    prune_gap_abs = np.full(P, np.inf)
     stop_margin = np.full(P, np.inf)
     min_pivot = np.full(P, np.inf)
     active = fin.copy()
@@ -252,6 +260,7 @@ def gomp(A, Y, K: int, S: int, max_iter: int = 0, res_tol: float = 0.0, eps: flo
         theta = top_indices(p, S, allowed)
         if diagnostics:
             sel_gap[a] = np.minimum(sel_gap[a], _ordered_gap(p, S, allowed))
+            sel_gap_abs[a] = np.minimum(sel_gap_abs[a], _ordered_gap(p, S, allowed, ynorm[a]))
         c[a, (i - 1) * S:i * S] = theta
         in_c[a[:, None], theta] = True
         cur = c[a, :i * S]
@@ -264,6 +273,8 @@ def gomp(A, Y, K: int, S: int, max_iter: int = 0, res_tol: float = 0.0, eps: flo
             q = top_indices(xa, K, in_c[a])
             if diagnostics:
                 prune_gap[a] = np.minimum(prune_gap[a], _ordered_gap(xa, K, in_c[a]))
+                prune_gap_abs[a] = np.minimum(prune_gap_abs[a],
+                                              _ordered_gap(xa, K, in_c[a], np.linalg.norm(s, axis=1)))
             sq = lstsq_on_support(A, ya, q)
             xa = np.zeros((len(a), N))
             xa[np.arange(len(a))[:, None], q] = sq
@@ -288,6 +299,10 @@ def gomp(A, Y, K: int, S: int, max_iter: int = 0, res_tol: float = 0.0, eps: flo
         big = np.nonzero(fin & (iters * S > K))[0]
         if len(big):
             q = top_indices(x[big], K, in_c[big])
+            if diagnostics:
+                prune_gap[big] = np.minimum(prune_gap[big], _ordered_gap(x[big], K, in_c[big]))
+                prune_gap_abs[big] = np.minimum(prune_gap_abs[big], _ordered_gap(
+                    x[big], K, in_c[big], np.linalg.norm(x[big], axis=1)))
             sq = lstsq_on_support(A, Yc[big], q)
             x[big] = 0.0
             x[big[:, None], q] = sq
@@ -297,7 +312,7 @@ def gomp(A, Y, K: int, S: int, max_iter: int = 0, res_tol: float = 0.0, eps: flo
     out = dict(X=x, support=support, iters=iters, delta=delta, resid=resid, flags=flags)
     if diagnostics:
         out.update(sel_gap=sel_gap, prune_gap=prune_gap, stop_margin=stop_margin,
-                   min_pivot=min_pivot)
+                   min_pivot=min_pivot, sel_gap_abs=sel_gap_abs, prune_gap_abs=prune_gap_abs)
     return out
 
 

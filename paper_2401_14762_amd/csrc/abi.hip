@@ -50,6 +50,7 @@ int fill_gomp(const csrec_problem* p, const csrec_gomp_params* q, GreedyLaunch& 
     if (imax < 1) return CSREC_E_INVAL;
     if (q->S * imax > p->M || q->S * imax > GREEDY_CMAX || q->K > GREEDY_CMAX) return CSREC_E_SHAPE;
     if (p->M > 96) return CSREC_E_UNSUPPORTED;
+    if ((e = gomp_coop_supported(p->M, p->N, q->K, q->S, imax))) return e;
     l = GreedyLaunch{};
     l.kind = GREEDY_GOMP;
     l.K = q->K;

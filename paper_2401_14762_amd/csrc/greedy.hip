@@ -22,6 +22,7 @@
 #include "common.hpp"
 
 #include <cmath>
+#include <vector>
 
 namespace csrec {
 namespace {
@@ -51,6 +52,7 @@ struct GArgs {
 
 struct GroupItem {
     GArgs g;            // the item's problem (dictionary, measurements, outputs) + batch scratch
+    const float* AT;    // the dictionary's transposed, padded copy (on-chip gOMP kernel)
     int64_t p0, np;     // pixels [p0, p0 + np) of the item's tile
     int64_t block0;     // first workgroup of the item in the grouped launch
     int64_t slot0;      // first batch scratch column of the item
@@ -683,7 +685,7 @@ int mmax_for(int M) { return M <= 48 ? 48 : (M <= 80 ? 80 : 96); }
 struct Layout {
     int CM, LM;
     int64_t CH;
-    size_t gram32, gram64, off_T, off_i, off_r, off_f, total;
+    size_t gram32, gram64, off_AT, off_T, off_i, off_r, off_f, total;
 };
 
 constexpr int64_t kChunk = 65536;
@@ -710,14 +712,22 @@ Layout layout_for(const GreedyLaunch& a, int64_t ch_override = 0) {
     L.gram32 = 0;
     L.gram64 = align_up((size_t)a.N * a.N * 4, 256);
     size_t o = L.gram64 + (dbl ? align_up((size_t)a.N * a.N * 8, 256) : 0);
+    L.off_AT = o;
+    if (a.kind == GREEDY_GOMP) o += align_up((size_t)a.N * gomp_coop_mp(a.M) * 4, 256);
+    L.off_f = o;
+    o += align_up((size_t)L.CH * 4, 256);
+    if (a.kind == GREEDY_GOMP && !dbl) {
+        // the on-chip gOMP kernel needs no per-pixel scratch
+        L.off_T = L.off_i = L.off_r = o;
+        L.total = o;
+        return L;
+    }
     L.off_T = o;
     o += align_up((size_t)tent * L.CH * tsz, 256);
     L.off_i = o;
     o += align_up((size_t)ient * L.CH * 4, 256);
     L.off_r = o;
     o += align_up((size_t)mmax_for(a.M) * L.CH * 4, 256);
-    L.off_f = o;
-    o += align_up((size_t)L.CH * 4, 256);
     L.total = o;
     return L;
 }
@@ -803,6 +813,7 @@ int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* ite
             g.off_i = (int64_t)L.off_i;
             g.off_r = (int64_t)L.off_r;
             g.fbflag = dbl ? reinterpret_cast<uint32_t*>(w + L.off_f) : nullptr;
+            gi.AT = it.AT;
             gi.p0 = it.p0;
             gi.np = it.np;
             gi.block0 = blocks;
@@ -816,8 +827,41 @@ int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* ite
         }
         if (nt > first) ranges[nr++] = Range{first, nt - first, blocks, classes[c], lds};
     }
+    // pass 0: the on-chip gOMP kernel, items grouped by their A^T row pitch
+    char* chost = static_cast<char*>(table_host) + align_up((size_t)nitems * sizeof(GroupItem), 256);
+    char* cdev = static_cast<char*>(table_dev) + align_up((size_t)nitems * sizeof(GroupItem), 256);
+    int cfirst = 0;
+    for (int mp : {64, 128}) {
+        std::vector<GompCoopItem> ci;
+        for (int k = 0; k < nt; ++k) {
+            const GroupItem& gi = th[k];
+            if (gomp_coop_mp(gi.g.M) != mp) continue;
+            GompCoopItem c{};
+            c.AT = gi.AT;
+            c.Y = gi.g.Y;
+            c.G32 = gi.g.G32;
+            c.X = gi.g.X;
+            c.support = gi.g.support;
+            c.stats = gi.g.stats;
+            c.fbflag = gi.g.fbflag ? gi.g.fbflag + gi.slot0 : nullptr;
+            c.M = gi.g.M;
+            c.N = gi.g.N;
+            c.max_iter = gi.g.Imax;
+            c.p0 = gi.p0;
+            c.np = gi.np;
+            ci.push_back(c);
+        }
+        if (ci.empty()) continue;
+        const int e = gomp_coop_group_launch(ci.data(), (int)ci.size(), chost + cfirst * gomp_coop_item_bytes(),
+                                             cdev + cfirst * gomp_coop_item_bytes(), pm.K, pm.S, pm.prune,
+                                             pm.res_tol, pm.eps, pm.pivot_fallback, stream);
+        if (e) return e;
+        cfirst += (int)ci.size();
+    }
+    if (!dbl) return CSREC_OK;
+    // pass 1: FP64 redo of the marked pixels (scratch-based kernel)
     CSREC_HIP_TRY(hipMemcpyAsync(td, th, (size_t)nt * sizeof(GroupItem), hipMemcpyHostToDevice, stream));
-    for (int pass = 0; pass < (dbl ? 2 : 1); ++pass) {
+    for (int pass = 1; pass < 2; ++pass) {
         for (int r = 0; r < nr; ++r) {
             ggk_t fn = pick_grouped_m(ranges[r].mmax, pass == 1, pm.S);
             CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -886,10 +930,20 @@ int greedy_launch(const GreedyLaunch& a) {
         CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fns[pass]),
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     }
+    const bool coop = a.kind == GREEDY_GOMP;   // gOMP's FP32 pass keeps its state on chip
+    float* AT = reinterpret_cast<float*>(ws + L.off_AT);
+    if (coop) gomp_coop_transpose(a.A, a.M, a.N, AT, a.stream);
     for (int64_t p0 = 0; p0 < a.P; p0 += L.CH) {
         const int64_t np = (a.P - p0) < L.CH ? (a.P - p0) : L.CH;
         const int64_t blocks = ceil_div(np, threads);
         for (int pass = 0; pass < (dbl ? 2 : 1); ++pass) {
+            if (coop && pass == 0) {
+                const int e = gomp_coop_launch(a.A, a.Y, a.X, a.support, a.stats, g.G32, AT, g.fbflag, a.M, a.N,
+                                               p0, np, a.K, a.S, a.max_iter, a.prune, a.res_tol, a.eps,
+                                               a.pivot_fallback, false, a.stream);
+                if (e) return e;
+                continue;
+            }
             hipLaunchKernelGGL(fns[pass], dim3((unsigned)blocks), dim3(threads), lds, a.stream, g, p0, np,
                                pass);
             CSREC_HIP_TRY(hipGetLastError());

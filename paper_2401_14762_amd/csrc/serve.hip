@@ -94,6 +94,7 @@ class Pool {
 struct Dict {
     int M = 0, N = 0, imax = 0;
     float* A = nullptr;
+    float* AT = nullptr;
     float* G32 = nullptr;
     double* G64 = nullptr;
 };
@@ -243,6 +244,7 @@ bool schedule_once(csrec_server* s) {
                 const Dict& d = s->dicts[t->dict];
                 GreedyTileItem it{};
                 it.A = d.A;
+                it.AT = d.AT;
                 it.Y = t->dY;
                 it.X = t->dX;
                 it.support = t->dS;
@@ -349,7 +351,8 @@ int32_t csrec_server_create(const csrec_server_cfg* cfg, csrec_server** out) {
     CSREC_HIP_TRY(hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking));
     CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&s->pool_mem), cfg->hbm_budget_bytes));
     CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&s->ws), s->ws_bytes));
-    const size_t tb = (size_t)s->max_items * greedy_group_item_bytes();
+    const size_t tb = align_up((size_t)s->max_items * greedy_group_item_bytes(), 256) +
+                      (size_t)s->max_items * gomp_coop_item_bytes();
     CSREC_HIP_TRY(hipMalloc(&s->table_dev, tb));
     CSREC_HIP_TRY(hipHostMalloc(&s->table_host[0], tb, hipHostMallocDefault));
     CSREC_HIP_TRY(hipHostMalloc(&s->table_host[1], tb, hipHostMallocDefault));
@@ -370,14 +373,17 @@ int32_t csrec_server_add_dict(csrec_server* s, const float* A_host, int32_t M, i
     d.N = N;
     d.imax = g.max_iter > 0 ? g.max_iter : std::min(g.K, M / g.S);
     if (d.imax < 1 || g.S * d.imax > M || d.imax > s->proto.max_iter) return CSREC_E_SHAPE;
+    if (gomp_coop_supported(M, N, g.K, g.S, d.imax) != CSREC_OK) return CSREC_E_UNSUPPORTED;
     CSREC_HIP_TRY(hipSetDevice(s->cfg.device));
     CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d.A), (size_t)M * N * 4));
     CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d.G32), (size_t)N * N * 4));
+    CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d.AT), (size_t)N * gomp_coop_mp(M) * 4));
     if (g.pivot_fallback > 0) CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d.G64), (size_t)N * N * 8));
     hipStream_t st = nullptr;
     CSREC_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     hipError_t e = hipMemcpyAsync(d.A, A_host, (size_t)M * N * 4, hipMemcpyHostToDevice, st);
     int rc = (e == hipSuccess) ? greedy_gram(d.A, M, N, d.G32, d.G64, st) : CSREC_E_DEVICE;
+    if (rc == CSREC_OK) gomp_coop_transpose(d.A, M, N, d.AT, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     hipStreamDestroy(st);
     if (e != hipSuccess) {
@@ -474,6 +480,7 @@ int32_t csrec_server_destroy(csrec_server* s) {
     hipStreamSynchronize(s->compute);
     for (auto& d : s->dicts) {
         hipFree(d.A);
+        hipFree(d.AT);
         hipFree(d.G32);
         if (d.G64) hipFree(d.G64);
     }

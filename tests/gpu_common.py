@@ -40,13 +40,28 @@ def rel_err_rows(est, ref):
     return np.linalg.norm(est - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-30)
 
 
-# Near-tie thresholds for the greedy decisions (relative gaps).  An FP32 sum
-# of M <= 96 products carries a relative error of about sqrt(M) 2^-24 ~ 6e-7
-# of the largest correlation, and the FP32 normal-equations solve one of
-# about kappa(B)^2 2^-24 ~ 3e-6 for the Gaussian sub-dictionaries met here
-# (|c| <= 45 of M = 80 columns); a decision whose gap to the next candidate is
-# above 1e-5 of the scale is therefore taken identically in FP32 and FP64.
+# Near-tie thresholds for the greedy decisions.  A decision is counted as a
+# near-tie when its gap to the next candidate is below either threshold:
+#
+# GAP, relative to the largest compared value.  An FP32 sum of M <= 96
+# products carries a relative error of about sqrt(M) 2^-24 ~ 6e-7 of the
+# largest correlation, and the FP32 normal-equations solve one of about
+# kappa(B)^2 2^-24 ~ 3e-6 for the Gaussian sub-dictionaries met here
+# (|c| <= 45 of M = 80 columns); 1e-5 is above both.
+#
+# GAP_ABS, relative to the scale on which rounding enters (the oracle's
+# sel_gap_abs / prune_gap_abs).  The residual r = y - A x of Alg. 3 step 4 is
+# formed by cancellation, so its rounding error is a multiple of 2^-24 ||y||,
+# not of ||r||: late in a solve, when ||r|| << ||y||, a correlation gap that
+# is large next to max|p| can still sit below FP32 resolution.  The typical
+# error of a correlation is about (kappa(G_q) / sqrt(M) + 1 + sqrt(K / M))
+# 2^-24 ||y|| (the coefficient error kappa 2^-24 ||s|| seen through one atom,
+# the M-term dot product, the K-term residual sum) ~ 5.5 2^-24 ||y|| with
+# kappa ~ 36, K = 20, M = 80; that of one least-squares coefficient about
+# kappa 2^-24 ||s|| / sqrt(|c|) ~ 6 2^-24 ||s||.  Gaps below 8 2^-24 on these
+# scales are counted as near-ties.
 GAP = 1e-5
+GAP_ABS = 8 * 2.0 ** -24
 STOP_MARGIN = 1e-3
 PIVOT = 1e-6
 

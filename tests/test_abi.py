@@ -157,7 +157,16 @@ def test_workspace_sizes(lib):
     assert rc == L.OK and n == 0
     rc, n = _ws(lib, L.SOLVER_FISTA, pb, _fista(L=0.0))
     assert rc == L.OK and n >= 4
+    # gOMP in FP32 keeps every per-pixel quantity on chip: the workspace is
+    # the Gram matrix, the padded A^T and nothing that grows with P
     rc, n1 = _ws(lib, L.SOLVER_GOMP, pb, _gomp(K=20, S=2))
-    assert rc == L.OK and n1 > 65536 * 820 * 4
+    assert rc == L.OK and 200 * 200 * 4 + 200 * 128 * 4 <= n1 < 2 * 1024 * 1024
+    # the FP64 fallback adds the FP64 Gram and per-pixel scratch for its redo
     rc, n2 = _ws(lib, L.SOLVER_GOMP, pb, _gomp(K=20, S=2, pivot_fallback=1e-6))
-    assert rc == L.OK and n2 > n1
+    assert rc == L.OK and n2 > n1 + 65536 * 4
+    # CoSaMP keeps its least-squares state in scratch, per pixel
+    p = L.CosampParams()
+    p.struct_size = ctypes.sizeof(p)
+    p.K, p.max_iter = 10, 20
+    rc, n3 = _ws(lib, L.SOLVER_COSAMP, pb, p)
+    assert rc == L.OK and n3 > n1
