@@ -10,6 +10,18 @@ timed region is exactly --steps steps bracketed by device synchronisation.
 Prints one JSON line (see the fields below), with the roofline of the
 dominant kernel (the FISTA kernel, FP32 MFMA) measured with HIP events on the
 stream it runs on, and the FP64 oracle timed on a bounded sample on the host.
+
+After the timed region, outside it, further legs are measured with HIP
+events and reported under "breakdown" (--legs):
+  precision  1024x1024 N=224 M=90 cube: FISTA in BF16 / FP16 with the FP32
+             correction pass and in FP32; gOMP FP32 with the FP64 fallback.
+  other      512x512 N=200 M=80 K=15-sparse cube: CoSaMP (Alg. 5), BIHT
+             (Alg. 4) and the one-bit BIHT on int8 signs.
+  serving    Poisson stream of tiles (200 tiles/s, sides log-uniform in
+             [64, 512], N in {100, 200, 224}) through csrec_server_*:
+             p50 / p99 latency (done - submit) and pixels/s.
+The oracle runs only in the cpu_baseline leg, which also supplies the FP64
+references of every PSNR-vs-oracle figure (on seeded pixel samples).
 """
 from __future__ import annotations
 
@@ -32,6 +44,9 @@ COPY_BYTES = 256 << 20      # calibration copy: 256 MiB read + 256 MiB written
 FISTA_ITERS = 200
 LAMBDA = 1e-2
 GOMP_S, GOMP_K, GOMP_TOL = 2, 20, 1e-3
+CORRECTION_ITERS = 20
+OTHER_K, COSAMP_ITERS, BIHT_REAL_ITERS, BIHT_1BIT_ITERS, BIHT_MU = 15, 30, 40, 100, 0.1
+PSNR_SAMPLE = 128
 
 
 def measured_traffic(kernel_src: str, summary: str):
@@ -59,7 +74,225 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--pixels", type=int, default=0, help="override the cube size (testing only)")
+    ap.add_argument("--legs", default="precision,other,serving",
+                    help="comma list of the legs measured after the timed region ('' for none)")
+    ap.add_argument("--serve-tiles", type=int, default=400, help="measured serving tiles")
+    ap.add_argument("--serve-warmup", type=int, default=40, help="serving tiles before the measured ones")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def event_timed(torch, stream, fn, reps=3):
+    """Run fn once untimed, then reps times between HIP events on `stream`;
+    returns (last output, mean ms)."""
+    fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    out = None
+    for e0, e1 in ev:
+        e0.record(stream)
+        out = fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return out, float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+
+
+def psnr(est, ref):
+    """PSNR of est against ref: peak = max |ref|, MSE over all entries."""
+    est = np.asarray(est, np.float64)
+    ref = np.asarray(ref, np.float64)
+    mse = float(np.mean((est - ref) ** 2))
+    peak = float(np.max(np.abs(ref)))
+    return float("inf") if mse == 0 else 10.0 * math.log10(peak * peak / mse)
+
+
+def psnr_dev(torch, X, Psi, F_ref):
+    """PSNR of the spectra Psi x (rows of X, on the GPU) against F_ref."""
+    F = X @ Psi.T
+    mse = torch.mean((F.double() - F_ref.double()) ** 2).item()
+    peak = torch.max(torch.abs(F_ref)).item()
+    return 10.0 * math.log10(peak * peak / mse)
+
+
+# ------------------------------------------------------------------ legs
+
+def leg_precision(torch, cs, W, dev, stream, samples):
+    pr = W.precision_cube()
+    P, M, N = pr.P, pr.M, pr.N
+    log(f"leg precision: {P} pixels N={N} M={M}")
+    L = float(np.linalg.norm(pr.A.astype(np.float64), 2) ** 2)
+    A = torch.from_numpy(pr.A).to(dev)
+    Y = torch.from_numpy(pr.Y).to(dev)
+    Psi = torch.from_numpy(pr.Psi.astype(np.float32)).to(dev)
+    F_true = torch.from_numpy(pr.F_true.astype(np.float32)).to(dev)
+    X = torch.empty((P, N), dtype=torch.float32, device=dev)
+    idx = W.pixel_subset(P, PSNR_SAMPLE, 31)
+    out = {"workload": f"precision mixing-model cube 1024x1024 N={N} M={M}, FISTA {FISTA_ITERS} it "
+                       f"lambda={LAMBDA} (+{CORRECTION_ITERS} FP32 correction it for bf16/f16); "
+                       f"gOMP S={GOMP_S} K={GOMP_K} res_tol={GOMP_TOL} FP64 fallback at pivot ratio 1e-6",
+           "pixels": P}
+    gpu = {}
+    for prec in ("f32", "bf16", "f16"):
+        corr = 0 if prec == "f32" else CORRECTION_ITERS
+        _, ms = event_timed(torch, stream, lambda: cs.fista(A, Y, lam=LAMBDA, L=L, max_iter=FISTA_ITERS,
+                                                            prec=prec, correction_iters=corr, out=X))
+        out[f"fista_{prec}_ms"] = ms
+        out[f"fista_{prec}_pixels_per_s"] = P / (ms * 1e-3)
+        out[f"fista_{prec}_psnr_vs_truth_db"] = psnr_dev(torch, X, Psi, F_true)
+        gpu[f"fista_{prec}"] = X[torch.from_numpy(idx).to(dev)].cpu().numpy()
+    out["fista_psnr_vs_truth_bf16_minus_f32_db"] = (out["fista_bf16_psnr_vs_truth_db"]
+                                                   - out["fista_f32_psnr_vs_truth_db"])
+    res, ms = event_timed(torch, stream, lambda: cs.gomp(A, Y, K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL,
+                                                         pivot_fallback=1e-6))
+    fb = int(((res[2]["flags"] & 4) != 0).sum().item())
+    out.update(gomp_ms=ms, gomp_pixels_per_s=P / (ms * 1e-3), gomp_fp64_fallback_pixels=fb)
+    gpu["gomp"] = res[0][torch.from_numpy(idx).to(dev)].cpu().numpy()
+    samples["precision"] = dict(A=pr.A, Y=pr.Y[idx], L=L, Psi=pr.Psi, gpu=gpu)
+    del A, Y, X, F_true, res
+    torch.cuda.empty_cache()
+    return out
+
+
+def leg_other(torch, cs, W, dev, stream, samples):
+    pr = W.other_solvers_cube()
+    P, M, N = pr.P, pr.M, pr.N
+    log(f"leg other solvers: {P} pixels N={N} M={M} K={OTHER_K}")
+    A = torch.from_numpy(pr.A).to(dev)
+    Y = torch.from_numpy(pr.Y).to(dev)
+    Ys = torch.from_numpy(pr.Ysign).to(dev)
+    idx = W.pixel_subset(P, PSNR_SAMPLE, 32)
+    tidx = torch.from_numpy(idx).to(dev)
+    out = {"workload": f"other-solvers cube 512x512 N={N} M={M}, K={OTHER_K}-sparse DCT coefficients, 30 dB: "
+                       f"CoSaMP {COSAMP_ITERS} it, BIHT {BIHT_REAL_ITERS} it, one-bit BIHT {BIHT_1BIT_ITERS} it "
+                       f"mu={BIHT_MU}", "pixels": P}
+    gpu = {}
+    runs = {
+        "cosamp": lambda: cs.cosamp(A, Y, K=OTHER_K, max_iter=COSAMP_ITERS),
+        "biht": lambda: cs.biht(A, Y, K=OTHER_K, max_iter=BIHT_REAL_ITERS, mu=BIHT_MU),
+        "biht_one_bit": lambda: cs.biht(A, None, K=OTHER_K, max_iter=BIHT_1BIT_ITERS, mu=BIHT_MU,
+                                        mode="one_bit", Ysign=Ys),
+    }
+    for name, fn in runs.items():
+        res, ms = event_timed(torch, stream, fn)
+        out[f"{name}_ms"] = ms
+        out[f"{name}_pixels_per_s"] = P / (ms * 1e-3)
+        gpu[name] = (res[0][tidx].cpu().numpy(), res[1][tidx].cpu().numpy())
+    samples["other"] = dict(A=pr.A, Y=pr.Y[idx], Ysign=pr.Ysign[idx], gpu=gpu)
+    del A, Y, Ys
+    torch.cuda.empty_cache()
+    return out
+
+
+def leg_serving(torch, cs, W, n_tiles, n_warm):
+    stream = W.serving_stream(n_warm + n_tiles)
+    rate = W.SERVING["rate"]
+    log(f"leg serving: {n_warm} + {n_tiles} tiles at {rate:g} tiles/s")
+    pools, dicts = {}, {}
+    side_max = W.SERVING["side_max"]
+    for N in W.SERVING["bands"]:
+        _, a32, _, phi = W.serving_dictionary(N)
+        F = W.mixing_spectra(side_max * side_max, N, W.SERVING["snr_db"], 7000 + N)
+        pools[N] = (F @ phi.T).astype(np.float32)
+        dicts[N] = a32
+    budget = 24 << 30
+    done, lag = {}, {}
+    with cs.Server(K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL, hbm_budget_bytes=budget) as srv:
+        ids = {N: srv.add_dict(a) for N, a in dicts.items()}
+        t0 = time.perf_counter()
+        for tile in stream:
+            while True:
+                for r in srv.poll(1024, fetch=False):
+                    done[r["tag"]] = r
+                wait = t0 + tile.t_arrival - time.perf_counter()
+                if wait <= 0:
+                    break
+                time.sleep(min(wait, 0.002))
+            P = tile.side * tile.side
+            off = (tile.seed % (side_max * side_max - P + 1))
+            lag[tile.tag] = time.perf_counter() - (t0 + tile.t_arrival)
+            srv.submit(ids[tile.N], pools[tile.N][off:off + P], tile.tag)
+        srv.drain()
+        for r in srv.poll(4096, fetch=False):
+            done[r["tag"]] = r
+    meas = [t for t in stream[n_warm:]]
+    bad = [t.tag for t in meas if t.tag not in done or done[t.tag]["status"] != 0]
+    # open-loop latency: from the scheduled arrival (a client that submits
+    # late still counts its delay), i.e. done - submit + submit lag
+    lat = np.array([done[t.tag]["t_done"] - done[t.tag]["t_submit"] + lag[t.tag] for t in meas
+                    if t.tag not in bad])
+    lag_v = np.array([lag[t.tag] for t in meas])
+    px = sum(t.side * t.side for t in meas)
+    t_first = min(done[t.tag]["t_submit"] - lag[t.tag] for t in meas if t.tag not in bad)
+    t_last = max(done[t.tag]["t_done"] for t in meas if t.tag not in bad)
+    span = meas[-1].t_arrival - meas[0].t_arrival
+    return {"workload": f"Poisson tile stream {rate:g} tiles/s, square tiles side log-uniform in "
+                        f"[{W.SERVING['side_min']}, {side_max}], N in {list(W.SERVING['bands'])}, gOMP S={GOMP_S} "
+                        f"K={GOMP_K} res_tol={GOMP_TOL} FP32, HBM budget {budget >> 30} GiB",
+            "tiles": len(meas), "warmup_tiles": n_warm, "failed_tiles": len(bad),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "submit_lag_p99_ms": float(np.percentile(lag_v, 99) * 1e3),
+            "pixels_per_s": px / (t_last - t_first), "offered_pixels_per_s": px / span if span > 0 else None}
+
+
+# ------------------------------------------------------------------ CPU (oracle) leg
+
+def cpu_baseline_leg(W, pr, L, idx_psnr, Xf_s, Xg_s, n_sample, samples):
+    """Times the FP64 oracle on a bounded sample of the headline cube (the
+    cpu_baseline), and computes the oracle references of every PSNR figure."""
+    import oracle
+    P = pr.P
+    n = min(n_sample, P)
+    sidx = W.pixel_subset(P, n, 98)
+    threads = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            threads = max(i.get("num_threads", 1) for i in info)
+    except Exception:
+        pass
+    log(f"cpu oracle on {n} pixels")
+    c0 = time.perf_counter()
+    oracle.fista(pr.A, pr.Y[sidx], LAMBDA, L, FISTA_ITERS)
+    oracle.gomp(pr.A, pr.Y[sidx], K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL)
+    cdt = time.perf_counter() - c0
+    cpu = {"value": n / cdt, "unit": "pixels/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{n} seeded pixels of the same cube, FISTA {FISTA_ITERS} it + gOMP, FP64 NumPy "
+                     f"({cdt:.1f} s)"}
+    # PSNR of the spectra against the oracle's, on seeded samples
+    q = {}
+    Psi = pr.Psi
+    ref = oracle.fista(pr.A, pr.Y[idx_psnr], LAMBDA, L, FISTA_ITERS)
+    q["plain_fista"] = psnr(Xf_s @ Psi.T, ref["X"] @ Psi.T)
+    ref = oracle.gomp(pr.A, pr.Y[idx_psnr], K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL)
+    q["plain_gomp"] = psnr(Xg_s @ Psi.T, ref["X"] @ Psi.T)
+    if "precision" in samples:
+        s = samples["precision"]
+        ref = oracle.fista(s["A"], s["Y"], LAMBDA, s["L"], FISTA_ITERS)
+        for prec in ("f32", "bf16", "f16"):
+            g = s["gpu"][f"fista_{prec}"]
+            if prec != "f32":   # the correction pass restarts the momentum from the 16-bit iterate
+                r16 = oracle.fista(s["A"], s["Y"], LAMBDA, s["L"], CORRECTION_ITERS, X0=ref["X"])
+                q[f"precision_fista_{prec}"] = psnr(g @ s["Psi"].T, r16["X"] @ s["Psi"].T)
+            else:
+                q["precision_fista_f32"] = psnr(g @ s["Psi"].T, ref["X"] @ s["Psi"].T)
+        ref = oracle.gomp(s["A"], s["Y"], K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL)
+        q["precision_gomp"] = psnr(s["gpu"]["gomp"] @ s["Psi"].T, ref["X"] @ s["Psi"].T)
+    if "other" in samples:
+        s = samples["other"]
+        refs = {"cosamp": oracle.cosamp(s["A"], s["Y"], K=OTHER_K, max_iter=COSAMP_ITERS),
+                "biht": oracle.biht(s["A"], s["Y"], K=OTHER_K, max_iter=BIHT_REAL_ITERS, mu=BIHT_MU),
+                "biht_one_bit": oracle.biht_one_bit(s["A"], s["Ysign"], K=OTHER_K, max_iter=BIHT_1BIT_ITERS,
+                                                    mu=BIHT_MU)}
+        for name, ref in refs.items():
+            Xg, Sg = s["gpu"][name]
+            same = np.mean([np.array_equal(np.sort(a[a >= 0]), np.sort(b[b >= 0]))
+                            for a, b in zip(Sg, ref["support"])])
+            q[f"other_{name}_support_match"] = float(same)
+            q[f"other_{name}"] = psnr(Xg, ref["X"])
+    return cpu, q
 
 
 def main():
@@ -105,8 +338,7 @@ def main():
     calib_dst.copy_(calib)
     torch.cuda.synchronize()
     del calib, calib_dst
-    print(f"[bench] workload plain {int(math.isqrt(P))}x{int(math.isqrt(P))} N={N} M={M}: warmup {args.warmup}",
-          file=sys.stderr, flush=True)
+    log(f"workload plain {int(math.isqrt(P))}x{int(math.isqrt(P))} N={N} M={M}: warmup {args.warmup}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -121,44 +353,36 @@ def main():
     fista_ms = [e[0].elapsed_time(e[1]) for e in evs]
     gomp_ms = [e[1].elapsed_time(e[2]) for e in evs]
     step_ms = wall * 1e3 / args.steps
-    print(f"[bench] timed {args.steps} steps: {step_ms:.3f} ms/step", file=sys.stderr, flush=True)
+    log(f"timed {args.steps} steps: {step_ms:.3f} ms/step")
 
     # dominant kernel: FISTA (one launch per solve); algorithmic FLOPs per
     # launch = P * iterations * 4 M N (A x and A^T v per pixel per iteration)
     fista_avg_ms = float(np.mean(fista_ms))
     flops = P * FISTA_ITERS * 4.0 * M * N
     achieved = flops / (fista_avg_ms * 1e-3) / 1e12
-
-    # quality on a sample: PSNR of the GPU reconstruction vs the FP64 oracle
-    import oracle
     idx = W.pixel_subset(P, 256, 99)
-    Xg = Xf.cpu().numpy()[idx]
-    ref = oracle.fista(pr.A, pr.Y[idx], LAMBDA, L, FISTA_ITERS)
-    psnr_fista = oracle.psnr(Xg @ pr.Psi.T, ref["X"] @ pr.Psi.T)
-    Xgo = res[0].cpu().numpy()[idx]
-    refg = oracle.gomp(pr.A, pr.Y[idx], K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL)
-    psnr_gomp = oracle.psnr(Xgo @ pr.Psi.T, refg["X"] @ pr.Psi.T)
+    Xf_s = Xf.cpu().numpy()[idx]
+    Xg_s = res[0].cpu().numpy()[idx]
+    del res
+
+    legs = [s for s in args.legs.split(",") if s]
+    breakdown = {
+        "fista_ms": fista_avg_ms, "gomp_ms": float(np.mean(gomp_ms)),
+        "fista_pixels_per_s": P / (fista_avg_ms * 1e-3),
+        "gomp_pixels_per_s": P / (float(np.mean(gomp_ms)) * 1e-3),
+    }
+    samples = {}
+    if "precision" in legs:
+        breakdown["precision"] = leg_precision(torch, cs, W, dev, stream, samples)
+    if "other" in legs:
+        breakdown["other_solvers"] = leg_other(torch, cs, W, dev, stream, samples)
+    if "serving" in legs:
+        breakdown["serving"] = leg_serving(torch, cs, W, args.serve_tiles, args.serve_warmup)
 
     cpu = None
     if not args.no_cpu:
-        n = min(args.cpu_sample, P)
-        sidx = W.pixel_subset(P, n, 98)
-        threads = os.cpu_count()
-        try:
-            from threadpoolctl import threadpool_info
-            info = threadpool_info()
-            if info:
-                threads = max(i.get("num_threads", 1) for i in info)
-        except Exception:
-            pass
-        print(f"[bench] cpu oracle on {n} pixels", file=sys.stderr, flush=True)
-        c0 = time.perf_counter()
-        oracle.fista(pr.A, pr.Y[sidx], LAMBDA, L, FISTA_ITERS)
-        oracle.gomp(pr.A, pr.Y[sidx], K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL)
-        cdt = time.perf_counter() - c0
-        cpu = {"value": n / cdt, "unit": "pixels/s", "cores": int(threads), "kind": "oracle",
-               "sample": f"{n} seeded pixels of the same cube, FISTA {FISTA_ITERS} it + gOMP, FP64 NumPy "
-                         f"({cdt:.1f} s)"}
+        cpu, q = cpu_baseline_leg(W, pr, L, idx, Xf_s, Xg_s, args.cpu_sample, samples)
+        breakdown["psnr_vs_oracle_db"] = q
 
     line = {
         "metric": "recovered pixels/sec (gOMP, FISTA) at fixed PSNR vs FP64 oracle",
@@ -184,12 +408,7 @@ def main():
                                                  os.path.join(ROOT, "profiles", "fista_gomp_plain256_counters.md")),
                      "avg_launch_ms": fista_avg_ms},
         "cpu_baseline": cpu,
-        "breakdown": {
-            "fista_ms": fista_avg_ms, "gomp_ms": float(np.mean(gomp_ms)),
-            "fista_pixels_per_s": P / (fista_avg_ms * 1e-3),
-            "gomp_pixels_per_s": P / (float(np.mean(gomp_ms)) * 1e-3),
-            "psnr_vs_oracle_db": {"fista": psnr_fista, "gomp": psnr_gomp},
-        },
+        "breakdown": breakdown,
     }
     print(json.dumps(line))
 

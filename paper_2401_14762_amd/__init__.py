@@ -289,9 +289,10 @@ class Server:
         _lib.check(self._lib.csrec_server_submit(self._h, dict_id, Y.ctypes.data, Y.shape[0], tag),
                    "csrec_server_submit")
 
-    def poll(self, max_results: int = 256) -> list:
+    def poll(self, max_results: int = 256, fetch: bool = True) -> list:
         """Finished tiles as dicts (tag, status, X, support, iters, flags, t_submit, t_admit, t_done);
-        arrays are copies, the server's buffers are released."""
+        arrays are copies, the server's buffers are released.  With fetch=False
+        only the tag, status, pixel count and times are returned."""
         import numpy as np
         buf = (_lib.Result * max_results)()
         n = ctypes.c_int32(0)
@@ -299,6 +300,11 @@ class Server:
         out = []
         for r in buf[:n.value]:
             P, N, K = r.P, r.N, r.K
+            if not fetch:
+                out.append(dict(tag=r.tag, status=r.status, dict_id=r.dict_id, P=P, t_submit=r.t_submit,
+                                t_admit=r.t_admit, t_done=r.t_done))
+                self._lib.csrec_server_release(self._h, r.tag)
+                continue
             if P > 0 and r.status == 0:
                 X = np.ctypeslib.as_array((ctypes.c_float * (P * N)).from_address(r.X)).reshape(P, N).copy()
                 S = np.ctypeslib.as_array((ctypes.c_int32 * (P * K)).from_address(r.support)).reshape(P, K).copy()

@@ -174,6 +174,14 @@ def load(path: str = LIB_PATH):
         raise RuntimeError(
             f"{path} is missing: build the HIP library first "
             "(python -m paper_2401_14762_amd.build); there is no CPU fallback")
+    # PyTorch ships its own libamdhip64.so.7.  Loaded first, this library would
+    # map the system copy as well, and a second HIP runtime in the process
+    # shares neither devices nor pointers with torch's.  With torch imported
+    # first, the library binds to the runtime that owns the tensors it gets.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 import shutil
+import sys
 import subprocess
 
 import pytest
@@ -170,3 +171,14 @@ def test_workspace_sizes(lib):
     p.K, p.max_iter = 10, 20
     rc, n3 = _ws(lib, L.SOLVER_COSAMP, pb, p)
     assert rc == L.OK and n3 > n1
+
+
+def test_one_hip_runtime_in_process():
+    """Loading the library before torch must not map a second libamdhip64
+    (torch bundles its own copy; two runtimes do not share devices)."""
+    code = ("import sys; sys.path.insert(0, %r); from paper_2401_14762_amd import _lib; _lib.load(); "
+            "import torch; print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))"
+            % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"
