@@ -87,7 +87,7 @@ int greedy_launch(const GreedyLaunch& a);
 // Grouped gOMP launches over pixel chunks of several tiles (serving).
 struct GreedyTileItem {
     const float* A;
-    const float* AT;      // N x gomp_coop_mp(M) transposed copy of A
+    const float* dict;    // gomp_coop_prepare output for A
     const float* Y;
     float* X;
     int32_t* support;
@@ -104,17 +104,19 @@ int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* ite
                         int64_t batch_pixels, void* ws, void* table_host, void* table_dev, hipStream_t stream);
 int greedy_gram(const float* A, int M, int N, float* G32, double* G64, hipStream_t stream);
 
-// gOMP with the least-squares state on chip (16 lanes per pixel).
+// gOMP with the least-squares state on chip (16 lanes per pixel, MFMA
+// correlation).  Every solve reads a per-dictionary buffer of
+// gomp_coop_dict_floats(M, N) floats built once by gomp_coop_prepare.
 int gomp_coop_mp(int M);
 size_t gomp_coop_lds_floats(int MP, int CM, int K);
+size_t gomp_coop_dict_floats(int M, int N);
 int gomp_coop_supported(int M, int N, int K, int S, int Imax);
-int gomp_coop_launch(const float* A, const float* Y, float* X, int32_t* support, csrec_pixel_stats* stats,
-                     const float* G32, float* AT, uint32_t* fbflag, int M, int N, int64_t p0, int64_t P, int K,
-                     int S, int Imax, int prune, float res_tol, float eps, double pivot_thr, bool build_AT,
-                     hipStream_t stream);
-void gomp_coop_transpose(const float* A, int M, int N, float* AT, hipStream_t stream);
+void gomp_coop_prepare(const float* A, int M, int N, float* dictbuf, hipStream_t stream);
+int gomp_coop_launch(const float* Y, float* X, int32_t* support, csrec_pixel_stats* stats, const float* G32,
+                     const float* dictbuf, uint32_t* fbflag, int M, int N, int64_t p0, int64_t P, int K, int S,
+                     int Imax, int prune, float res_tol, float eps, double pivot_thr, hipStream_t stream);
 struct GompCoopItem {
-    const float* AT;
+    const float* dict;    // gomp_coop_prepare output for this item's A
     const float* Y;
     const float* G32;
     float* X;

@@ -1,9 +1,19 @@
 // gOMP (Alg. 3) with the least-squares state on chip.
 //
-// Work decomposition.  A workgroup is one wavefront holding 4 pixels; the
-// 16 lanes t = 0..15 of lane row g cooperate on pixel g.  Every per-pixel
+// Work decomposition.  A workgroup is one wavefront holding 4 pixels: lane l
+// serves pixel x = l & 3 as sub-lane t = l >> 2 (0..15).  Every per-pixel
 // quantity lives in LDS or in the lanes' registers for the whole solve, so
-// the solve reads y and A^T and writes x, and nothing else leaves the CU.
+// the solve reads y and the dictionary copies and writes x, and nothing else
+// leaves the CU.
+//
+// Correlation on the matrix cores.  p = A^T r for the wave's 4 pixels is a
+// (N x M) by (M x 4) product: v_mfma_f32_4x4x1_16b_f32 forms 16 independent
+// 4x4 outer products per instruction, lane 4b + i supplying A's entry for
+// atom 4b + i and lane 4b + x pixel x's residual entry, so one instruction
+// per row m covers 64 atoms x 4 pixels with no padding waste.  Lane l then
+// holds p of pixel l & 3 for atoms 64 g + 4 (l >> 2) + i, which is where the
+// top-S selection reads it.  A is read row-major (64 consecutive atoms per
+// load instruction, fully coalesced) from an L2-resident padded copy.
 //
 // Least squares without triangular-solve chains.  With G[c,c] = L L^T the
 // kernel keeps W = L^{-1} (lower triangular, packed rows in LDS) instead of
@@ -11,19 +21,20 @@
 //   l = W G[c, j],  d = G_jj - ||l||^2,  new row of W = [-l^T W, 1] / sqrt(d)
 // and the least-squares solution of G[c,c] s = b_c is s = W^T (W b_c), with
 // z = W b_c extended by one dot product per append.  Every one of these is a
-// matrix-vector product whose rows (or columns) the 16 lanes split, so a step
-// has constant depth instead of the |c| sequential steps of forward and back
-// substitution.  d / G_jj is the pivot ratio (squared distance of a_j from
-// span(A[:, c]) over ||a_j||^2); a pixel with a ratio below the threshold is
-// marked for the FP64 pass of the scratch-based kernel.
+// matrix-vector product whose rows (or columns) the 16 lanes split.  The
+// Gram entries an append needs are gathered from global memory beforehand,
+// all at once, into the packed slot of the row the append then writes.
+// d / G_jj is the pivot ratio (squared distance of a_j from span(A[:, c])
+// over ||a_j||^2); a pixel with a ratio below the threshold is marked for
+// the FP64 pass of the scratch-based kernel.
 //
 // Per iteration (Alg. 3, steps 1-4), for each active pixel:
-//   1. p = A^T r: lane t forms p_n for n = t + 16k from A^T rows (global,
-//      L2-resident) and r (LDS); S rounds of a 16-lane argmax over the
-//      non-members of c, ties to the lower index.
-//   2. append the S atoms (above); s = W^T z.
+//   1. p = A^T r on MFMA; S rounds of a 16-lane argmax over the non-members
+//      of c, ties to the lower index.
+//   2. append the S atoms; s = W^T z.
 //   3. if |c| > K: rank the |s_i| (ties to the lower index), keep the top K
-//      as q, build the inverse factor of G[q, q] by K appends, s_q = W_q^T z_q.
+//      as q, build the inverse factor of G[q, q] by K appends (its Gram
+//      entries gathered in one batch), s_q = W_q^T z_q.
 //   4. r = y - A(:, q) s_q with lane t owning m = 4t + j + 64i; Delta, ||r||.
 #include "common.hpp"
 
@@ -33,17 +44,21 @@ namespace csrec {
 namespace {
 
 constexpr int kGroups = 4;        // pixels per wavefront
-constexpr int kMaxNT = 16;        // N <= 256
+constexpr int kMaxNG = 4;         // 64-atom groups: N <= 256
+constexpr int kMaxS = 8;
+
+typedef float v4f_t __attribute__((ext_vector_type(4)));
 
 struct CoopArgs {
-    const float* AT;      // N x MP, row n = column n of A (zero padded to MP)
+    const float* AT;      // N x MP: row n = column n of A (zero padded to MP)
+    const float* Ap;      // M4 x NP: A with zero rows to M4 and zero columns to NP
     const float* Y;       // P x M
     const float* G32;     // N x N
     float* X;
     int32_t* support;
     csrec_pixel_stats* stats;
-    uint32_t* fbflag;     // per pixel (chunk-local) FP64 hand-off, may be null
-    int M, N, MP, K, S, Imax, prune;
+    uint32_t* fbflag;     // per pixel (launch-local) FP64 hand-off, may be null
+    int M, N, MP, NP, K, S, Imax, prune;
     float res_tol, eps;
     double pivot_thr;
     int64_t P;            // pixels of this launch
@@ -52,25 +67,27 @@ struct CoopArgs {
     int lds_floats;       // per pixel
 };
 
-__device__ __forceinline__ int tri(int k) { return k * (k + 1) / 2; }
+__host__ __device__ __forceinline__ int tri(int k) { return k * (k + 1) / 2; }
+__host__ __device__ __forceinline__ int up4(int k) { return (k + 3) & ~3; }
 
 // Atom indices read back from LDS are kept inside [0, N) before they address
 // global memory.
 __device__ __forceinline__ int clamp_atom(int j, int N) { return (unsigned)j < (unsigned)N ? j : 0; }
 
-// Sum over the 16 lanes of a lane row.
-__device__ __forceinline__ float row_sum(float v) {
-    v += __shfl_xor(v, 8);
+// Sum over the 16 lanes of a pixel (lanes x, x + 4, ..., x + 60).
+__device__ __forceinline__ float pix_sum(float v) {
     v += __shfl_xor(v, 4);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 8);
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
     return v;
 }
 
-// (value desc, index asc) argmax over a lane row; index -1 never wins.
-__device__ __forceinline__ void row_argmax(float& v, int& i) {
+// (value desc, index asc) argmax over the 16 lanes of a pixel; index -1
+// never wins.
+__device__ __forceinline__ void pix_argmax(float& v, int& i) {
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
+    for (int o = 4; o < 64; o <<= 1) {
         const float ov = __shfl_xor(v, o);
         const int oi = __shfl_xor(i, o);
         const bool take = (oi >= 0) && (i < 0 || ov > v || (ov == v && oi < i));
@@ -80,59 +97,118 @@ __device__ __forceinline__ void row_argmax(float& v, int& i) {
 }
 
 // Per-pixel LDS carving (floats; index arrays stored as int bit patterns).
+// Every array starts on a 16-byte boundary.
 struct PixLds {
-    float* rb;    // residual broadcast, MP
-    float* W;     // inverse factor of G[c,c], tri(CM)
+    float* rb;    // residual, MP (read as the MFMA B operand)
+    float* W;     // inverse factor of G[c,c], tri(CM); slot of row n holds G[c, j] before its append
     float* z;     // W b_c, CM
     float* b;     // b_c, CM
-    int* c;       // atoms, CM
     float* s;     // solution on c, CM
-    float* g;     // temporary column, CM (also q-append temporaries)
     float* l;     // temporary, CM
-    float* Wq;    // inverse factor of G[q,q], tri(K)
+    int* c;       // atoms, CM
+    int* sel;     // this iteration's selected atoms, kMaxS
+    float* bsel;  // their a_j^T y, kMaxS
+    float* Wq;    // inverse factor of G[q,q], tri(K); row slots pre-filled with G[q, q_k]
     float* zq;    // K
     float* bq;    // K
-    int* q;       // K
     float* sq;    // K
+    int* q;       // K
 };
 
-__device__ __forceinline__ PixLds carve(float* base, const CoopArgs& a) {
-    PixLds p;
-    float* o = base;
-    p.rb = o; o += a.MP;
-    p.W = o; o += tri(a.CM);
-    p.z = o; o += a.CM;
-    p.b = o; o += a.CM;
-    p.c = reinterpret_cast<int*>(o); o += a.CM;
-    p.s = o; o += a.CM;
-    p.g = o; o += a.CM;
-    p.l = o; o += a.CM;
-    p.Wq = o; o += tri(a.K);
-    p.zq = o; o += a.K;
-    p.bq = o; o += a.K;
-    p.q = reinterpret_cast<int*>(o); o += a.K;
-    p.sq = o;
+struct LdsPlan {
+    int rb, W, z, b, s, l, c, sel, bsel, Wq, zq, bq, sq, q, total;
+};
+
+// Offsets (floats) of one pixel's region; the stride is padded to 8 mod 64
+// floats so that the 4 pixels' packed-row reads fall in distinct banks.
+__host__ __device__ inline LdsPlan lds_plan(int MP, int CM, int K) {
+    LdsPlan p;
+    int o = 0;
+    p.rb = o; o += up4(MP);
+    p.W = o; o += up4(tri(CM));
+    p.z = o; o += up4(CM);
+    p.b = o; o += up4(CM);
+    p.s = o; o += up4(CM);
+    p.l = o; o += up4(CM);
+    p.c = o; o += up4(CM);
+    p.sel = o; o += kMaxS;
+    p.bsel = o; o += kMaxS;
+    p.Wq = o; o += up4(tri(K));
+    p.zq = o; o += up4(K);
+    p.bq = o; o += up4(K);
+    p.sq = o; o += up4(K);
+    p.q = o; o += up4(K);
+    o += ((8 - o) % 64 + 64) % 64;
+    p.total = o;
     return p;
 }
 
+__device__ __forceinline__ PixLds carve(float* base, const CoopArgs& a) {
+    const LdsPlan pl = lds_plan(a.MP, a.CM, a.K);
+    PixLds p;
+    p.rb = base + pl.rb;
+    p.W = base + pl.W;
+    p.z = base + pl.z;
+    p.b = base + pl.b;
+    p.s = base + pl.s;
+    p.l = base + pl.l;
+    p.c = reinterpret_cast<int*>(base + pl.c);
+    p.sel = reinterpret_cast<int*>(base + pl.sel);
+    p.bsel = base + pl.bsel;
+    p.Wq = base + pl.Wq;
+    p.zq = base + pl.zq;
+    p.bq = base + pl.bq;
+    p.sq = base + pl.sq;
+    p.q = reinterpret_cast<int*>(base + pl.q);
+    return p;
+}
+
+// sum_{k < len} u[k] v[k] over LDS operands with four independent partial sums.
+__device__ __forceinline__ float dot4(const float* u, const float* v, int len) {
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int k = 0;
+    for (; k + 4 <= len; k += 4) {
+        s0 += u[k] * v[k];
+        s1 += u[k + 1] * v[k + 1];
+        s2 += u[k + 2] * v[k + 2];
+        s3 += u[k + 3] * v[k + 3];
+    }
+    for (; k < len; ++k) s0 += u[k] * v[k];
+    return (s0 + s1) + (s2 + s3);
+}
+
+// sum_{k <= i < n} v[i] W[tri(i) + k]: column k of the packed factor below
+// (and on) the diagonal against v, four independent partial sums.
+__device__ __forceinline__ float coldot4(const float* Wf, const float* v, int k, int n) {
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int i = k;
+    for (; i + 4 <= n; i += 4) {
+        s0 += v[i] * Wf[tri(i) + k];
+        s1 += v[i + 1] * Wf[tri(i + 1) + k];
+        s2 += v[i + 2] * Wf[tri(i + 2) + k];
+        s3 += v[i + 3] * Wf[tri(i + 3) + k];
+    }
+    for (; i < n; ++i) s0 += v[i] * Wf[tri(i) + k];
+    return (s0 + s1) + (s2 + s3);
+}
+
 // One bordered step of the inverse factor: appends atom `atom` (rhs bj) to
-// the factor (Wf, zf, bf, idx) of size n.  gcol[i] must hold G[idx[i], atom]
-// for i < n (written by the caller before the barrier).  All 64 lanes call it;
-// `on` masks the lane rows whose pixel takes part.  Returns d / G_jj.
-__device__ float inv_append(bool on, int t, int n, float* Wf, float* zf, float* bf, int* idx, const float* gcol,
-                            float* ltmp, int atom, float bj, float gjj) {
+// the factor (Wf, zf, bf, idx) of size n.  The slot of row n must hold
+// G[idx[i], atom] for i < n (written before the barrier preceding the call).
+// All 64 lanes call it; `on` masks the pixels that take part.  Returns d / G_jj.
+__device__ float inv_append(bool on, int t, int n, float* Wf, float* zf, float* bf, int* idx, float* ltmp,
+                            int atom, float bj, float gjj) {
+    float* wn = Wf + tri(n);   // G[idx, atom] now, the new row after the second barrier
     // l = W g (rows i = t + 16u)
     float ll = 0.f;
     if (on) {
         for (int i = t; i < n; i += 16) {
-            const float* wr = Wf + tri(i);
-            float acc = 0.f;
-            for (int k = 0; k <= i; ++k) acc += wr[k] * gcol[k];
+            const float acc = dot4(Wf + tri(i), wn, i + 1);
             ltmp[i] = acc;
             ll += acc * acc;
         }
     }
-    ll = row_sum(ll);
+    ll = pix_sum(ll);
     __syncthreads();
     const float d = gjj - ll;
     const float ratio = d / gjj;
@@ -145,11 +221,8 @@ __device__ float inv_append(bool on, int t, int n, float* Wf, float* zf, float* 
     // new row: w[k] = -(sum_{i>=k} l_i W[i][k]) * inv, w[n] = inv; z_n = w . [b_c, bj]
     float zp = 0.f;
     if (on) {
-        float* wn = Wf + tri(n);
         for (int k = t; k < n; k += 16) {
-            float acc = 0.f;
-            for (int i = k; i < n; ++i) acc += ltmp[i] * Wf[tri(i) + k];
-            const float w = -acc * inv;
+            const float w = -coldot4(Wf, ltmp, k, n) * inv;
             wn[k] = w;
             zp += w * bf[k];
         }
@@ -158,7 +231,7 @@ __device__ float inv_append(bool on, int t, int n, float* Wf, float* zf, float* 
             zp += inv * bj;
         }
     }
-    zp = row_sum(zp);
+    zp = pix_sum(zp);
     if (on && t == 0) {
         zf[n] = zp;
         bf[n] = bj;
@@ -170,13 +243,8 @@ __device__ float inv_append(bool on, int t, int n, float* Wf, float* zf, float* 
 
 // s = W^T z on the first n entries (columns k = t + 16u).
 __device__ void inv_solve(bool on, int t, int n, const float* Wf, const float* zf, float* sf) {
-    if (on) {
-        for (int k = t; k < n; k += 16) {
-            float acc = 0.f;
-            for (int i = k; i < n; ++i) acc += Wf[tri(i) + k] * zf[i];
-            sf[k] = acc;
-        }
-    }
+    if (on)
+        for (int k = t; k < n; k += 16) sf[k] = coldot4(Wf, zf, k, n);
     __syncthreads();
 }
 
@@ -185,10 +253,10 @@ __device__ __forceinline__ float rank_key(float v) {
     return a <= 3.402823466e38f ? a : -1.f;   // NaN and inf rank last
 }
 
-// Step 3 of Alg. 3 for the lane rows with `on`: q = the K entries of c with
-// largest |s| (ties to the lower index), then s_q = G[q,q]^{-1} b_q through
-// a fresh inverse factor.  Called by every lane (it holds barriers).
-__device__ void prune_to_q(bool on, int t, int nc, int K, int N, const float* G32, const PixLds& L) {
+// Step 3 of Alg. 3 for the pixels with `on`: q = the K entries of c with
+// largest |s| (ties to the lower index), then s_q = G[q,q]^{-1} b_q through a
+// fresh inverse factor.  Called by every lane (it holds barriers).
+__device__ void prune_to_q(bool on, int t, int nc, int K, int N, const float* __restrict__ G32, const PixLds& L) {
     if (on) {
         // the key maps non-finite |s| below every finite one, so (key desc,
         // index asc) is a strict total order over the distinct atoms of c and
@@ -196,12 +264,19 @@ __device__ void prune_to_q(bool on, int t, int nc, int K, int N, const float* G3
         for (int k = t; k < nc; k += 16) {
             const float vk = rank_key(L.s[k]);
             const int ck = L.c[k];
-            int rank = 0;
-            for (int i = 0; i < nc; ++i) {
-                const float vi = rank_key(L.s[i]);
-                const int ci = L.c[i];
-                rank += (vi > vk || (vi == vk && ci < ck)) ? 1 : 0;
+            int r0 = 0, r1 = 0;
+            int i = 0;
+            for (; i + 2 <= nc; i += 2) {
+                const float v0 = rank_key(L.s[i]), v1 = rank_key(L.s[i + 1]);
+                const int c0 = L.c[i], c1 = L.c[i + 1];
+                r0 += (v0 > vk || (v0 == vk && c0 < ck)) ? 1 : 0;
+                r1 += (v1 > vk || (v1 == vk && c1 < ck)) ? 1 : 0;
             }
+            if (i < nc) {
+                const float v0 = rank_key(L.s[i]);
+                r0 += (v0 > vk || (v0 == vk && L.c[i] < ck)) ? 1 : 0;
+            }
+            const int rank = r0 + r1;
             if (rank < K) {
                 L.q[rank] = ck;
                 L.bq[rank] = L.b[k];
@@ -209,28 +284,85 @@ __device__ void prune_to_q(bool on, int t, int nc, int K, int N, const float* G3
         }
     }
     __syncthreads();
+    // all Gram entries of G[q,q] (lower triangle) in one batch of loads: entry
+    // e = tri(r) + i (i <= r) goes to the slot of row r of W_q
+    if (on) {
+        const int TK = tri(K);
+        for (int e0 = 0; e0 < TK; e0 += 64) {
+            float v[4];
+            int dst[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + 16 * u + t;
+                dst[u] = -1;
+                v[u] = 0.f;
+                if (e < TK) {
+                    int r = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
+                    while (tri(r + 1) <= e) ++r;
+                    while (tri(r) > e) --r;
+                    const int i = e - tri(r);
+                    v[u] = G32[(size_t)clamp_atom(L.q[i], N) * N + clamp_atom(L.q[r], N)];
+                    dst[u] = e;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (dst[u] >= 0) L.Wq[dst[u]] = v[u];
+        }
+    }
+    __syncthreads();
     for (int k = 0; k < K; ++k) {
-        const int j = on ? clamp_atom(L.q[k], N) : 0;
-        if (on)
-            for (int i = t; i < k; i += 16) L.g[i] = G32[(size_t)clamp_atom(L.q[i], N) * N + j];
-        const float gjj = on ? G32[(size_t)j * N + j] : 1.f;
+        const float gjj = on ? L.Wq[tri(k) + k] : 1.f;
         const float bj = on ? L.bq[k] : 0.f;
-        __syncthreads();
+        const int j = on ? L.q[k] : 0;
         // the appended entry rewrites q[k] and bq[k] with their own values
-        inv_append(on, t, k, L.Wq, L.zq, L.bq, L.q, L.g, L.l, j, bj, gjj);
+        inv_append(on, t, k, L.Wq, L.zq, L.bq, L.q, L.l, j, bj, gjj);
     }
     inv_solve(on, t, K, L.Wq, L.zq, L.sq);
+}
+
+// r = y - sum_k xv[k] A[:, xi[k]] for the lane's m = 4t + j + 64i.
+template <int MSLOT>
+__device__ __forceinline__ void residual(const float* y, float* rnew, const int* xi, const float* xv, int nx,
+                                         const float* __restrict__ AT, int MP, int N, int t) {
+#pragma unroll
+    for (int u = 0; u < MSLOT; ++u) rnew[u] = y[u];
+    for (int k0 = 0; k0 < nx; k0 += 4) {
+        float4 av[4][MSLOT / 4];
+        float v[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = k0 + kk;
+            v[kk] = k < nx ? xv[k] : 0.f;
+            const float* row = AT + (size_t)clamp_atom(k < nx ? xi[k] : 0, N) * MP;
+#pragma unroll
+            for (int u4 = 0; u4 < MSLOT / 4; ++u4) {
+                const int m = 4 * t + 64 * u4;
+                av[kk][u4] = (m < MP) ? *reinterpret_cast<const float4*>(row + m) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int u4 = 0; u4 < MSLOT / 4; ++u4) {
+                rnew[4 * u4] -= av[kk][u4].x * v[kk];
+                rnew[4 * u4 + 1] -= av[kk][u4].y * v[kk];
+                rnew[4 * u4 + 2] -= av[kk][u4].z * v[kk];
+                rnew[4 * u4 + 3] -= av[kk][u4].w * v[kk];
+            }
+    }
 }
 
 template <int MSLOT>
 __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block, float* lds) {
     const int lane = threadIdx.x;
-    const int g = lane >> 4, t = lane & 15;
-    const int64_t local = block * kGroups + g;
+    const int x = lane & 3, t = lane >> 2;
+    const int64_t local = block * kGroups + x;
     const int64_t pix = a.p0 + local;
     const bool valid = local < a.P;
-    const int M = a.M, N = a.N, K = a.K, MP = a.MP;
-    PixLds L = carve(lds + g * a.lds_floats, a);
+    const int M = a.M, N = a.N, K = a.K, MP = a.MP, NP = a.NP;
+    const int NG = NP >> 6;
+    PixLds L = carve(lds + x * a.lds_floats, a);
 
     // y and r: lane t owns m = 4t + j + 64i (i < MSLOT/4)
     float y[MSLOT], r[MSLOT];
@@ -246,10 +378,10 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
         y[u] = v;
     }
     int badi = bad ? 1 : 0;
-    badi |= __shfl_xor(badi, 8);
     badi |= __shfl_xor(badi, 4);
-    badi |= __shfl_xor(badi, 2);
-    badi |= __shfl_xor(badi, 1);
+    badi |= __shfl_xor(badi, 8);
+    badi |= __shfl_xor(badi, 16);
+    badi |= __shfl_xor(badi, 32);
     bad = badi != 0;
     float y2 = 0.f;
 #pragma unroll
@@ -258,7 +390,7 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
         r[u] = y[u];
         y2 += y[u] * y[u];
     }
-    y2 = row_sum(y2);
+    y2 = pix_sum(y2);
     const float ynorm = sqrtf(y2);
 
     bool active = valid && !bad;
@@ -266,73 +398,108 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
     int iters = 0, nc = 0, nx = 0;
     bool x_on_q = false;
     float last_d2 = __builtin_nanf(""), rn2 = y2;
-    uint32_t mask = 0u;   // bit k: atom n = t + 16k is in c
+    uint32_t mask = 0u;   // bit 4g + i: atom 64g + 4t + i is in c
+    const int M4 = (M + 3) & ~3;
 
     for (int it = 1; it <= a.Imax; ++it) {
-        // ---------------- step 1: correlation p = A^T r, top-S over the non-members
+        // ---------------- step 1: p = A^T r on MFMA, top-S over the non-members
 #pragma unroll
         for (int u = 0; u < MSLOT; ++u) {
             const int m = 4 * t + (u & 3) + 64 * (u >> 2);
             if (m < MP) L.rb[m] = r[u];
         }
         __syncthreads();
-        float p[kMaxNT];
+        v4f_t acc[kMaxNG];
 #pragma unroll
-        for (int k = 0; k < kMaxNT; ++k) p[k] = 0.f;
-        const int M4 = (M + 3) & ~3;
-        if (active) {
-            for (int m4 = 0; m4 < M4; m4 += 4) {
-                const float4 rv = *reinterpret_cast<const float4*>(L.rb + m4);
+        for (int g = 0; g < kMaxNG; ++g) acc[g] = v4f_t{0.f, 0.f, 0.f, 0.f};
+        const float* rbx = L.rb;
+        for (int m4 = 0; m4 < M4; m4 += 4) {
+            const float4 rv = *reinterpret_cast<const float4*>(rbx + m4);
+            const float* ap = a.Ap + (size_t)m4 * NP + lane;
 #pragma unroll
-                for (int k = 0; k < kMaxNT; ++k) {
-                    const int n = t + 16 * k;
-                    if (n < N) {
-                        const float4 av = *reinterpret_cast<const float4*>(a.AT + (size_t)n * MP + m4);
-                        p[k] += av.x * rv.x + av.y * rv.y + av.z * rv.z + av.w * rv.w;
-                    }
+            for (int g = 0; g < kMaxNG; ++g) {
+                if (g < NG) {
+                    const float a0 = ap[64 * g];
+                    const float a1 = ap[NP + 64 * g];
+                    const float a2 = ap[2 * NP + 64 * g];
+                    const float a3 = ap[3 * NP + 64 * g];
+                    acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, rv.x, acc[g], 0, 0, 0);
+                    acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1, rv.y, acc[g], 0, 0, 0);
+                    acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(a2, rv.z, acc[g], 0, 0, 0);
+                    acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(a3, rv.w, acc[g], 0, 0, 0);
                 }
             }
         }
         // S rounds of argmax; the winners are appended in selection order
-        int sel[8];
+        int nsel = 0;
         for (int q = 0; q < a.S; ++q) {
             float bv = -1.f;
             int bi = -1;
 #pragma unroll
-            for (int k = 0; k < kMaxNT; ++k) {
-                const int n = t + 16 * k;
-                const float v = fabsf(p[k]);
-                if (n < N && !((mask >> k) & 1u) && (bi < 0 || v > bv)) {
-                    bv = v;
-                    bi = n;
+            for (int g = 0; g < kMaxNG; ++g)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int n = 64 * g + 4 * t + i;
+                    const float v = fabsf(acc[g][i]);
+                    const bool member = (mask >> (4 * g + i)) & 1u;
+                    if (g < NG && n < N && !member && (bi < 0 || v > bv)) {
+                        bv = v;
+                        bi = n;
+                    }
                 }
-            }
-            row_argmax(bv, bi);
-            sel[q] = bi;
-            if (bi >= 0 && (bi & 15) == t) mask |= 1u << (bi >> 4);
+            pix_argmax(bv, bi);
+            if (bi >= 0 && ((bi & 63) >> 2) == t) mask |= 1u << (4 * (bi >> 6) + (bi & 3));
+            if (t == 0) L.sel[q] = bi;
+            nsel += (bi >= 0) ? 1 : 0;   // the valid selections form a prefix
         }
+        __syncthreads();
 
         // ---------------- step 2: append the atoms, s = W^T (W b_c)
+        // gather G[c + earlier selections, j] into the slot of row nc + q and
+        // form b_j = a_j^T y, all loads of the iteration in one batch
+        const int nq = active ? nsel : 0;
         for (int q = 0; q < a.S; ++q) {
-            const int j = sel[q];
-            const bool on = active && j >= 0;
-            // b_j = a_j^T y and G[c, j]
+            const int j = q < nq ? L.sel[q] : -1;
             float bpart = 0.f;
-            if (on) {
+            if (j >= 0) {
+                const int n = nc + q;
+                float v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = t + 16 * u;
+                    v[u] = 0.f;
+                    if (i <= n) {
+                        const int ci = i < nc ? L.c[i] : (i < n ? L.sel[i - nc] : j);
+                        v[u] = a.G32[(size_t)clamp_atom(ci, N) * N + j];
+                    }
+                }
+                float4 av[MSLOT / 4];
 #pragma unroll
                 for (int u4 = 0; u4 < MSLOT / 4; ++u4) {
                     const int m = 4 * t + 64 * u4;
-                    if (m < MP) {
-                        const float4 av = *reinterpret_cast<const float4*>(a.AT + (size_t)j * MP + m);
-                        bpart += av.x * y[4 * u4] + av.y * y[4 * u4 + 1] + av.z * y[4 * u4 + 2] + av.w * y[4 * u4 + 3];
-                    }
+                    av[u4] = (m < MP) ? *reinterpret_cast<const float4*>(a.AT + (size_t)j * MP + m)
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                for (int i = t; i < nc; i += 16) L.g[i] = a.G32[(size_t)L.c[i] * N + j];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = t + 16 * u;
+                    if (i <= n) L.W[tri(n) + i] = v[u];
+                }
+#pragma unroll
+                for (int u4 = 0; u4 < MSLOT / 4; ++u4)
+                    bpart += av[u4].x * y[4 * u4] + av[u4].y * y[4 * u4 + 1] + av[u4].z * y[4 * u4 + 2] +
+                             av[u4].w * y[4 * u4 + 3];
             }
-            const float bj = row_sum(bpart);
-            const float gjj = on ? a.G32[(size_t)j * N + j] : 1.f;
-            __syncthreads();
-            const float ratio = inv_append(on, t, nc, L.W, L.z, L.b, L.c, L.g, L.l, j, bj, gjj);
+            const float bj = pix_sum(bpart);
+            if (t == 0) L.bsel[q] = bj;
+        }
+        __syncthreads();
+        for (int q = 0; q < a.S; ++q) {
+            const bool on = q < nq;
+            const int j = on ? L.sel[q] : 0;
+            const float bj = on ? L.bsel[q] : 0.f;
+            const float gjj = on ? L.W[tri(nc) + nc] : 1.f;
+            const float ratio = inv_append(on, t, nc, L.W, L.z, L.b, L.c, L.l, j, bj, gjj);
             if (on && a.pivot_thr > 0.0 && (double)ratio < a.pivot_thr) fallback = true;
             if (on) ++nc;
         }
@@ -340,9 +507,7 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
 
         // ---------------- step 3: prune to K and re-solve on q
         const bool prune_g = active && a.prune == CSREC_PRUNE_EACH && nc > K;
-        if (__any(prune_g)) {
-            prune_to_q(prune_g, t, nc, K, N, a.G32, L);
-        }
+        if (__any(prune_g)) prune_to_q(prune_g, t, nc, K, N, a.G32, L);
         // a pixel that stopped earlier keeps the x of its last iteration
         if (prune_g) {
             nx = K;
@@ -354,26 +519,8 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
 
         // ---------------- step 4: residual r = y - A x, Delta, stop
         if (active) {
-            const int* xi = x_on_q ? L.q : L.c;
-            const float* xv = x_on_q ? L.sq : L.s;
             float rnew[MSLOT];
-#pragma unroll
-            for (int u = 0; u < MSLOT; ++u) rnew[u] = y[u];
-            for (int k = 0; k < nx; ++k) {
-                const float v = xv[k];
-                const float* row = a.AT + (size_t)clamp_atom(xi[k], N) * MP;
-#pragma unroll
-                for (int u4 = 0; u4 < MSLOT / 4; ++u4) {
-                    const int m = 4 * t + 64 * u4;
-                    if (m < MP) {
-                        const float4 av = *reinterpret_cast<const float4*>(row + m);
-                        rnew[4 * u4] -= av.x * v;
-                        rnew[4 * u4 + 1] -= av.y * v;
-                        rnew[4 * u4 + 2] -= av.z * v;
-                        rnew[4 * u4 + 3] -= av.w * v;
-                    }
-                }
-            }
+            residual<MSLOT>(y, rnew, x_on_q ? L.q : L.c, x_on_q ? L.sq : L.s, nx, a.AT, MP, N, t);
             float d2 = 0.f, n2 = 0.f;
 #pragma unroll
             for (int u = 0; u < MSLOT; ++u) {
@@ -382,8 +529,8 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
                 n2 += rnew[u] * rnew[u];
                 r[u] = rnew[u];
             }
-            d2 = row_sum(d2);
-            n2 = row_sum(n2);
+            d2 = pix_sum(d2);
+            n2 = pix_sum(n2);
             iters = it;
             last_d2 = d2;
             rn2 = n2;
@@ -405,27 +552,11 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
             nx = K;
             x_on_q = true;
             float rnew[MSLOT];
-#pragma unroll
-            for (int u = 0; u < MSLOT; ++u) rnew[u] = y[u];
-            for (int k = 0; k < nx; ++k) {
-                const float v = L.sq[k];
-                const float* row = a.AT + (size_t)clamp_atom(L.q[k], N) * MP;
-#pragma unroll
-                for (int u4 = 0; u4 < MSLOT / 4; ++u4) {
-                    const int m = 4 * t + 64 * u4;
-                    if (m < MP) {
-                        const float4 av = *reinterpret_cast<const float4*>(row + m);
-                        rnew[4 * u4] -= av.x * v;
-                        rnew[4 * u4 + 1] -= av.y * v;
-                        rnew[4 * u4 + 2] -= av.z * v;
-                        rnew[4 * u4 + 3] -= av.w * v;
-                    }
-                }
-            }
+            residual<MSLOT>(y, rnew, L.q, L.sq, nx, a.AT, MP, N, t);
 #pragma unroll
             for (int u = 0; u < MSLOT; ++u) n2 += rnew[u] * rnew[u];
         }
-        n2 = row_sum(n2);
+        n2 = pix_sum(n2);
         if (final_prune) rn2 = n2;
     }
 
@@ -446,11 +577,8 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
     if (a.support) {
         int32_t* srow = a.support + pix * K;
         // ascending order by rank of the index among the nx support atoms
-        for (int k = t; k < K; k += 16) {
-            if (k >= nx || bad) {
-                srow[k] = -1;
-            }
-        }
+        for (int k = t; k < K; k += 16)
+            if (k >= nx || bad) srow[k] = -1;
         for (int k = t; k < nx && !bad; k += 16) {
             const int ck = xi[k];
             int pos = 0;
@@ -489,51 +617,32 @@ __global__ __launch_bounds__(64) void gomp_coop_grouped_kernel(const CoopItem* _
     gomp_coop_body<MSLOT>(a, (int64_t)blockIdx.x - items[it].block0, lds);
 }
 
-__global__ void transpose_pad_kernel(const float* __restrict__ A, int M, int N, int MP, float* __restrict__ AT) {
-    const int n = blockIdx.x;
-    for (int m = threadIdx.x; m < MP; m += blockDim.x) AT[(size_t)n * MP + m] = m < M ? A[(size_t)m * N + n] : 0.f;
-}
-
-}  // namespace
-
-int gomp_coop_mp(int M) { return M <= 64 ? 64 : 128; }
-
-// Rounded up to 4 floats so every pixel's region (and its float4-read
-// residual at the front) is 16-byte aligned.
-size_t gomp_coop_lds_floats(int MP, int CM, int K) {
-    const size_t f = (size_t)MP + (size_t)CM * (CM + 1) / 2 + 6 * (size_t)CM + (size_t)K * (K + 1) / 2 + 4 * (size_t)K;
-    return (f + 3) & ~(size_t)3;
-}
-
-int gomp_coop_supported(int M, int N, int K, int S, int Imax) {
-    if (N > 16 * kMaxNT || M > 128) return CSREC_E_UNSUPPORTED;
-    const int CM = S * Imax;
-    const size_t lds = kGroups * gomp_coop_lds_floats(gomp_coop_mp(M), CM, K) * sizeof(float);
-    return lds <= 160 * 1024 ? CSREC_OK : CSREC_E_UNSUPPORTED;
-}
-
-// AT (N x MP floats) must be in the workspace; fbflag (P entries) may be null.
-int gomp_coop_launch(const float* A, const float* Y, float* X, int32_t* support, csrec_pixel_stats* stats,
-                     const float* G32, float* AT, uint32_t* fbflag, int M, int N, int64_t p0, int64_t P, int K,
-                     int S, int Imax, int prune, float res_tol, float eps, double pivot_thr, bool build_AT,
-                     hipStream_t stream) {
-    const int MP = gomp_coop_mp(M);
-    if (build_AT) {
-        hipLaunchKernelGGL(transpose_pad_kernel, dim3(N), dim3(128), 0, stream, A, M, N, MP, AT);
-        CSREC_HIP_TRY(hipGetLastError());
+// The two dictionary copies: AT (N x MP, rows zero padded) and Ap (M4 x NP,
+// zero rows and columns).  Block n < N writes row n of AT; block N + m
+// (m < M4) writes row m of Ap.
+__global__ void prepare_kernel(const float* __restrict__ A, int M, int N, int MP, int M4, int NP,
+                               float* __restrict__ AT, float* __restrict__ Ap) {
+    const int bidx = blockIdx.x;
+    if (bidx < N) {
+        for (int m = threadIdx.x; m < MP; m += blockDim.x)
+            AT[(size_t)bidx * MP + m] = m < M ? A[(size_t)m * N + bidx] : 0.f;
+    } else {
+        const int m = bidx - N;
+        for (int n = threadIdx.x; n < NP; n += blockDim.x)
+            Ap[(size_t)m * NP + n] = (m < M && n < N) ? A[(size_t)m * N + n] : 0.f;
     }
-    if (P == 0) return CSREC_OK;
-    CoopArgs a;
-    a.AT = AT;
-    a.Y = Y;
-    a.G32 = G32;
-    a.X = X;
-    a.support = support;
-    a.stats = stats;
-    a.fbflag = fbflag;
+}
+
+int coop_np(int N) { return ((N + 63) / 64) * 64; }
+
+void fill_args(CoopArgs& a, const float* dictbuf, int M, int N, int K, int S, int Imax, int prune, float res_tol,
+               float eps, double pivot_thr) {
     a.M = M;
     a.N = N;
-    a.MP = MP;
+    a.MP = gomp_coop_mp(M);
+    a.NP = coop_np(N);
+    a.AT = dictbuf;
+    a.Ap = dictbuf + (size_t)N * a.MP;
     a.K = K;
     a.S = S;
     a.Imax = Imax;
@@ -541,13 +650,52 @@ int gomp_coop_launch(const float* A, const float* Y, float* X, int32_t* support,
     a.res_tol = res_tol;
     a.eps = eps;
     a.pivot_thr = pivot_thr;
+    a.CM = S * Imax;
+    a.lds_floats = (int)gomp_coop_lds_floats(a.MP, a.CM, K);
+}
+
+}  // namespace
+
+int gomp_coop_mp(int M) { return M <= 64 ? 64 : 128; }
+
+size_t gomp_coop_lds_floats(int MP, int CM, int K) { return (size_t)lds_plan(MP, CM, K).total; }
+
+size_t gomp_coop_dict_floats(int M, int N) {
+    return (size_t)N * gomp_coop_mp(M) + (size_t)((M + 3) & ~3) * coop_np(N);
+}
+
+int gomp_coop_supported(int M, int N, int K, int S, int Imax) {
+    if (N > 64 * kMaxNG || M > 128 || S > kMaxS) return CSREC_E_UNSUPPORTED;
+    const int CM = S * Imax;
+    const size_t lds = kGroups * gomp_coop_lds_floats(gomp_coop_mp(M), CM, K) * sizeof(float);
+    return lds <= 160 * 1024 ? CSREC_OK : CSREC_E_UNSUPPORTED;
+}
+
+void gomp_coop_prepare(const float* A, int M, int N, float* dictbuf, hipStream_t stream) {
+    const int MP = gomp_coop_mp(M), M4 = (M + 3) & ~3, NP = coop_np(N);
+    hipLaunchKernelGGL(prepare_kernel, dim3(N + M4), dim3(128), 0, stream, A, M, N, MP, M4, NP, dictbuf,
+                       dictbuf + (size_t)N * MP);
+}
+
+// dictbuf (gomp_coop_dict_floats(M, N) floats, built by gomp_coop_prepare);
+// fbflag (P entries) may be null.
+int gomp_coop_launch(const float* Y, float* X, int32_t* support, csrec_pixel_stats* stats, const float* G32,
+                     const float* dictbuf, uint32_t* fbflag, int M, int N, int64_t p0, int64_t P, int K, int S,
+                     int Imax, int prune, float res_tol, float eps, double pivot_thr, hipStream_t stream) {
+    if (P == 0) return CSREC_OK;
+    CoopArgs a;
+    fill_args(a, dictbuf, M, N, K, S, Imax, prune, res_tol, eps, pivot_thr);
+    a.Y = Y;
+    a.G32 = G32;
+    a.X = X;
+    a.support = support;
+    a.stats = stats;
+    a.fbflag = fbflag;
     a.P = P;
     a.p0 = p0;
-    a.CM = S * Imax;
-    a.lds_floats = (int)gomp_coop_lds_floats(MP, a.CM, K);
     const size_t lds = (size_t)kGroups * a.lds_floats * sizeof(float);
     const int64_t blocks = ceil_div(P, kGroups);
-    if (MP == 64) {
+    if (a.MP == 64) {
         CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(gomp_coop_kernel<4>),
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(gomp_coop_kernel<4>, dim3((unsigned)blocks), dim3(64), lds, stream, a);
@@ -562,10 +710,6 @@ int gomp_coop_launch(const float* A, const float* Y, float* X, int32_t* support,
 
 size_t gomp_coop_item_bytes() { return sizeof(CoopItem); }
 
-void gomp_coop_transpose(const float* A, int M, int N, float* AT, hipStream_t stream) {
-    hipLaunchKernelGGL(transpose_pad_kernel, dim3(N), dim3(128), 0, stream, A, M, N, gomp_coop_mp(M), AT);
-}
-
 // Items of one launch must share MP (64 or 128).
 int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_host, void* table_dev, int K, int S,
                            int prune, float res_tol, float eps, double pivot_thr, hipStream_t stream) {
@@ -578,27 +722,15 @@ int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_ho
         const GompCoopItem& it = items[i];
         if (gomp_coop_mp(it.M) != MP) return CSREC_E_INVAL;
         CoopArgs& a = th[i].a;
-        a.AT = it.AT;
+        fill_args(a, it.dict, it.M, it.N, K, S, it.max_iter, prune, res_tol, eps, pivot_thr);
         a.Y = it.Y;
         a.G32 = it.G32;
         a.X = it.X;
         a.support = it.support;
         a.stats = it.stats;
         a.fbflag = it.fbflag;
-        a.M = it.M;
-        a.N = it.N;
-        a.MP = MP;
-        a.K = K;
-        a.S = S;
-        a.Imax = it.max_iter;
-        a.prune = prune;
-        a.res_tol = res_tol;
-        a.eps = eps;
-        a.pivot_thr = pivot_thr;
         a.P = it.np;
         a.p0 = it.p0;
-        a.CM = S * it.max_iter;
-        a.lds_floats = (int)gomp_coop_lds_floats(MP, a.CM, K);
         th[i].block0 = blocks;
         blocks += ceil_div(it.np, kGroups);
         const size_t need = (size_t)kGroups * a.lds_floats * sizeof(float);

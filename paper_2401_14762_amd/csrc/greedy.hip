@@ -52,7 +52,7 @@ struct GArgs {
 
 struct GroupItem {
     GArgs g;            // the item's problem (dictionary, measurements, outputs) + batch scratch
-    const float* AT;    // the dictionary's transposed, padded copy (on-chip gOMP kernel)
+    const float* dict;  // the dictionary copies of the on-chip gOMP kernel
     int64_t p0, np;     // pixels [p0, p0 + np) of the item's tile
     int64_t block0;     // first workgroup of the item in the grouped launch
     int64_t slot0;      // first batch scratch column of the item
@@ -713,7 +713,7 @@ Layout layout_for(const GreedyLaunch& a, int64_t ch_override = 0) {
     L.gram64 = align_up((size_t)a.N * a.N * 4, 256);
     size_t o = L.gram64 + (dbl ? align_up((size_t)a.N * a.N * 8, 256) : 0);
     L.off_AT = o;
-    if (a.kind == GREEDY_GOMP) o += align_up((size_t)a.N * gomp_coop_mp(a.M) * 4, 256);
+    if (a.kind == GREEDY_GOMP) o += align_up(gomp_coop_dict_floats(a.M, a.N) * 4, 256);
     L.off_f = o;
     o += align_up((size_t)L.CH * 4, 256);
     if (a.kind == GREEDY_GOMP && !dbl) {
@@ -813,7 +813,7 @@ int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* ite
             g.off_i = (int64_t)L.off_i;
             g.off_r = (int64_t)L.off_r;
             g.fbflag = dbl ? reinterpret_cast<uint32_t*>(w + L.off_f) : nullptr;
-            gi.AT = it.AT;
+            gi.dict = it.dict;
             gi.p0 = it.p0;
             gi.np = it.np;
             gi.block0 = blocks;
@@ -837,7 +837,7 @@ int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* ite
             const GroupItem& gi = th[k];
             if (gomp_coop_mp(gi.g.M) != mp) continue;
             GompCoopItem c{};
-            c.AT = gi.AT;
+            c.dict = gi.dict;
             c.Y = gi.g.Y;
             c.G32 = gi.g.G32;
             c.X = gi.g.X;
@@ -931,16 +931,16 @@ int greedy_launch(const GreedyLaunch& a) {
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     }
     const bool coop = a.kind == GREEDY_GOMP;   // gOMP's FP32 pass keeps its state on chip
-    float* AT = reinterpret_cast<float*>(ws + L.off_AT);
-    if (coop) gomp_coop_transpose(a.A, a.M, a.N, AT, a.stream);
+    float* dictbuf = reinterpret_cast<float*>(ws + L.off_AT);
+    if (coop) gomp_coop_prepare(a.A, a.M, a.N, dictbuf, a.stream);
     for (int64_t p0 = 0; p0 < a.P; p0 += L.CH) {
         const int64_t np = (a.P - p0) < L.CH ? (a.P - p0) : L.CH;
         const int64_t blocks = ceil_div(np, threads);
         for (int pass = 0; pass < (dbl ? 2 : 1); ++pass) {
             if (coop && pass == 0) {
-                const int e = gomp_coop_launch(a.A, a.Y, a.X, a.support, a.stats, g.G32, AT, g.fbflag, a.M, a.N,
+                const int e = gomp_coop_launch(a.Y, a.X, a.support, a.stats, g.G32, dictbuf, g.fbflag, a.M, a.N,
                                                p0, np, a.K, a.S, a.max_iter, a.prune, a.res_tol, a.eps,
-                                               a.pivot_fallback, false, a.stream);
+                                               a.pivot_fallback, a.stream);
                 if (e) return e;
                 continue;
             }

@@ -244,7 +244,7 @@ bool schedule_once(csrec_server* s) {
                 const Dict& d = s->dicts[t->dict];
                 GreedyTileItem it{};
                 it.A = d.A;
-                it.AT = d.AT;
+                it.dict = d.AT;
                 it.Y = t->dY;
                 it.X = t->dX;
                 it.support = t->dS;
@@ -377,13 +377,13 @@ int32_t csrec_server_add_dict(csrec_server* s, const float* A_host, int32_t M, i
     CSREC_HIP_TRY(hipSetDevice(s->cfg.device));
     CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d.A), (size_t)M * N * 4));
     CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d.G32), (size_t)N * N * 4));
-    CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d.AT), (size_t)N * gomp_coop_mp(M) * 4));
+    CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d.AT), gomp_coop_dict_floats(M, N) * 4));
     if (g.pivot_fallback > 0) CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d.G64), (size_t)N * N * 8));
     hipStream_t st = nullptr;
     CSREC_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     hipError_t e = hipMemcpyAsync(d.A, A_host, (size_t)M * N * 4, hipMemcpyHostToDevice, st);
     int rc = (e == hipSuccess) ? greedy_gram(d.A, M, N, d.G32, d.G64, st) : CSREC_E_DEVICE;
-    if (rc == CSREC_OK) gomp_coop_transpose(d.A, M, N, d.AT, st);
+    if (rc == CSREC_OK) gomp_coop_prepare(d.A, M, N, d.AT, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     hipStreamDestroy(st);
     if (e != hipSuccess) {
