@@ -127,6 +127,7 @@ struct GompCoopItem {
     int64_t p0, np;
 };
 size_t gomp_coop_item_bytes();
+int gomp_coop_class(int M, int N);   // items of one grouped launch share it (0..3)
 int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_host, void* table_dev, int K, int S,
                            int prune, float res_tol, float eps, double pivot_thr, hipStream_t stream);
 

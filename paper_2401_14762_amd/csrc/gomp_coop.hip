@@ -9,11 +9,13 @@
 // Correlation on the matrix cores.  p = A^T r for the wave's 4 pixels is a
 // (N x M) by (M x 4) product: v_mfma_f32_4x4x1_16b_f32 forms 16 independent
 // 4x4 outer products per instruction, lane 4b + i supplying A's entry for
-// atom 4b + i and lane 4b + x pixel x's residual entry, so one instruction
-// per row m covers 64 atoms x 4 pixels with no padding waste.  Lane l then
-// holds p of pixel l & 3 for atoms 64 g + 4 (l >> 2) + i, which is where the
-// top-S selection reads it.  A is read row-major (64 consecutive atoms per
-// load instruction, fully coalesced) from an L2-resident padded copy.
+// the block's row i and lane 4b + x pixel x's residual entry.  With NG
+// instructions per row m, lane l loads the NG consecutive atoms NG l + g
+// (g < NG) of row m in one vector load (fully coalesced over the wave) and
+// feeds entry g to instruction g; lane 4b + x then holds p of pixel x for
+// the 4 NG consecutive atoms from 4 NG b, which is where the top-S
+// selection reads it.  A is read row-major from an L2-resident padded copy,
+// eight rows ahead of the instructions that consume them.
 //
 // Least squares without triangular-solve chains.  With G[c,c] = L L^T the
 // kernel keeps W = L^{-1} (lower triangular, packed rows in LDS) instead of
@@ -33,8 +35,8 @@
 //      of c, ties to the lower index.
 //   2. append the S atoms; s = W^T z.
 //   3. if |c| > K: rank the |s_i| (ties to the lower index), keep the top K
-//      as q, build the inverse factor of G[q, q] by K appends (its Gram
-//      entries gathered in one batch), s_q = W_q^T z_q.
+//      as q, solve G[q,q] s_q = b_q by LDL^T elimination (Gram entries
+//      gathered in one batch).
 //   4. r = y - A(:, q) s_q with lane t owning m = 4t + j + 64i; Delta, ||r||.
 #include "common.hpp"
 
@@ -44,14 +46,16 @@ namespace csrec {
 namespace {
 
 constexpr int kGroups = 4;        // pixels per wavefront
-constexpr int kMaxNG = 4;         // 64-atom groups: N <= 256
+constexpr int kMaxNG = 4;         // atoms per lane and row: N <= 64 NG
+constexpr int kRowPad = 8;        // rows of the padded copy of A: multiple of 8
 constexpr int kMaxS = 8;
+constexpr int kGJ = 32;           // K up to this: the pruned system is solved in registers
 
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 
 struct CoopArgs {
     const float* AT;      // N x MP: row n = column n of A (zero padded to MP)
-    const float* Ap;      // M4 x NP: A with zero rows to M4 and zero columns to NP
+    const float* Ap;      // M8 x NP: A with zero rows to M8 and zero columns to NP = 64 NG
     const float* Y;       // P x M
     const float* G32;     // N x N
     float* X;
@@ -108,15 +112,14 @@ struct PixLds {
     int* c;       // atoms, CM
     int* sel;     // this iteration's selected atoms, kMaxS
     float* bsel;  // their a_j^T y, kMaxS
-    float* Wq;    // inverse factor of G[q,q], tri(K); row slots pre-filled with G[q, q_k]
-    float* zq;    // K
+    float* Wq;    // K > kGJ: LDL^T triangle of G[q,q], tri(K); K <= kGJ: pivot-row slots, 2 x 36
     float* bq;    // K
     float* sq;    // K
     int* q;       // K
 };
 
 struct LdsPlan {
-    int rb, W, z, b, s, l, c, sel, bsel, Wq, zq, bq, sq, q, total;
+    int rb, W, z, b, s, l, c, sel, bsel, Wq, bq, sq, q, total;
 };
 
 // Offsets (floats) of one pixel's region; the stride is padded to 8 mod 64
@@ -133,8 +136,7 @@ __host__ __device__ inline LdsPlan lds_plan(int MP, int CM, int K) {
     p.c = o; o += up4(CM);
     p.sel = o; o += kMaxS;
     p.bsel = o; o += kMaxS;
-    p.Wq = o; o += up4(tri(K));
-    p.zq = o; o += up4(K);
+    p.Wq = o; o += K > kGJ ? up4(tri(K)) : 2 * (kGJ + 4);
     p.bq = o; o += up4(K);
     p.sq = o; o += up4(K);
     p.q = o; o += up4(K);
@@ -156,7 +158,6 @@ __device__ __forceinline__ PixLds carve(float* base, const CoopArgs& a) {
     p.sel = reinterpret_cast<int*>(base + pl.sel);
     p.bsel = base + pl.bsel;
     p.Wq = base + pl.Wq;
-    p.zq = base + pl.zq;
     p.bq = base + pl.bq;
     p.sq = base + pl.sq;
     p.q = reinterpret_cast<int*>(base + pl.q);
@@ -253,48 +254,143 @@ __device__ __forceinline__ float rank_key(float v) {
     return a <= 3.402823466e38f ? a : -1.f;   // NaN and inf rank last
 }
 
+// s_q = G[q,q]^{-1} b_q for K <= kGJ by Gauss-Jordan elimination on
+// registers: lane t owns rows t and t + 16 of [G[q,q] | b_q].  Step k (fully
+// unrolled, so every register index is static) publishes pivot row k through
+// a double-buffered LDS slot (one barrier) and every other row subtracts its
+// multiple of it over the columns j >= k still in play.  The pivot is floored
+// at 2^-24 of the original diagonal like the appends.  After K steps row i
+// reads d_i s_i = rhs_i, with d_i the row's pivot.
+__device__ __forceinline__ void solve_q_gj(bool on, int t, int K, int N, const float* __restrict__ G32,
+                                        const PixLds& L) {
+    constexpr int W1 = kGJ + 1;          // K columns (padded to kGJ) + the right-hand side
+    constexpr int SLOT = kGJ + 4;
+    float R0[W1], R1[W1];
+    const bool h0 = on && t < K, h1 = on && t + 16 < K;
+    const int q0 = clamp_atom(h0 ? L.q[t] : 0, N), q1 = clamp_atom(h1 ? L.q[t + 16] : 0, N);
+#pragma unroll
+    for (int j = 0; j < kGJ; ++j) {
+        const bool hj = on && j < K;
+        const int qj = clamp_atom(hj ? L.q[j] : 0, N);
+        R0[j] = (h0 && hj) ? G32[(size_t)q0 * N + qj] : 0.f;
+        R1[j] = (h1 && hj) ? G32[(size_t)q1 * N + qj] : 0.f;
+    }
+    R0[kGJ] = h0 ? L.bq[t] : 0.f;
+    R1[kGJ] = h1 ? L.bq[t + 16] : 0.f;
+    const float fl0 = (h0 ? G32[(size_t)q0 * N + q0] : 1.f) * 5.9604645e-8f;
+    const float fl1 = (h1 ? G32[(size_t)q1 * N + q1] : 1.f) * 5.9604645e-8f;
+    float dg0 = 1.f, dg1 = 1.f;
+#pragma unroll
+    for (int k = 0; k < kGJ; ++k) {
+        if (k < K) {   // uniform
+        float* slot = L.Wq + (k & 1) * SLOT;
+        if (t == (k & 15)) {
+            float* R = k < 16 ? R0 : R1;
+            const float fl = k < 16 ? fl0 : fl1;
+            R[k] = R[k] > fl ? R[k] : fl;
+            if (k < 16) dg0 = R[k]; else dg1 = R[k];
+            if (on) {
+#pragma unroll
+                for (int j = k & ~3; j < W1 + 3; j += 4) {
+                    const float4 v = make_float4(R[j], j + 1 < W1 ? R[j + 1] : 0.f, j + 2 < W1 ? R[j + 2] : 0.f,
+                                                 j + 3 < W1 ? R[j + 3] : 0.f);
+                    *reinterpret_cast<float4*>(slot + j) = v;
+                }
+            }
+        }
+        __syncthreads();
+        if (on) {
+            const float rp = 1.f / slot[k];
+            const float f0 = (t == k) ? 0.f : R0[k] * rp;
+            const float f1 = (t + 16 == k) ? 0.f : R1[k] * rp;
+#pragma unroll
+            for (int j = k & ~3; j < W1; j += 4) {
+                const float4 v = *reinterpret_cast<const float4*>(slot + j);
+                const float pv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (j + e > k && j + e < W1) {
+                        R0[j + e] -= f0 * pv[e];
+                        R1[j + e] -= f1 * pv[e];
+                    }
+                }
+            }
+        }
+        }
+    }
+    if (h0) L.sq[t] = R0[kGJ] / dg0;
+    if (h1) L.sq[t + 16] = R1[kGJ] / dg1;
+    __syncthreads();
+}
+
 // Step 3 of Alg. 3 for the pixels with `on`: q = the K entries of c with
-// largest |s| (ties to the lower index), then s_q = G[q,q]^{-1} b_q through a
-// fresh inverse factor.  Called by every lane (it holds barriers).
+// largest |s| (ties to the lower index), then s_q = G[q,q]^{-1} b_q.
+//
+// For K <= kGJ the K x K system is solved on registers (solve_q_gj);
+// larger ones by a right-looking LDL^T elimination of the
+// lower triangle C of G[q,q] (gathered in one batch), the forward
+// substitution of b_q riding along, then a column-oriented back
+// substitution: 2K steps, each one barrier and a set of independent element
+// updates split over the 16 lanes (no reductions).  Step k divides by the
+// pivot C_kk, floored at 2^-24 of the original diagonal like the appends;
+// C keeps the unscaled columns (C_ik = D_k Lt_ik), so no square roots.
+// Called by every lane (it holds barriers).
 __device__ void prune_to_q(bool on, int t, int nc, int K, int N, const float* __restrict__ G32, const PixLds& L) {
     if (on) {
         // the key maps non-finite |s| below every finite one, so (key desc,
         // index asc) is a strict total order over the distinct atoms of c and
         // the ranks are a permutation: q[0..K) is always fully written
-        for (int k = t; k < nc; k += 16) {
-            const float vk = rank_key(L.s[k]);
-            const int ck = L.c[k];
-            int r0 = 0, r1 = 0;
-            int i = 0;
-            for (; i + 2 <= nc; i += 2) {
-                const float v0 = rank_key(L.s[i]), v1 = rank_key(L.s[i + 1]);
-                const int c0 = L.c[i], c1 = L.c[i + 1];
-                r0 += (v0 > vk || (v0 == vk && c0 < ck)) ? 1 : 0;
-                r1 += (v1 > vk || (v1 == vk && c1 < ck)) ? 1 : 0;
+        float vk[4];
+        int ck[4], rk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = t + 16 * u;
+            vk[u] = k < nc ? rank_key(L.s[k]) : 0.f;
+            ck[u] = k < nc ? L.c[k] : 0;
+            rk[u] = 0;
+        }
+        for (int i0 = 0; i0 < nc; i0 += 4) {
+            const float4 sv = *reinterpret_cast<const float4*>(L.s + i0);
+            const int4 cv = *reinterpret_cast<const int4*>(L.c + i0);
+            const float v4[4] = {rank_key(sv.x), rank_key(sv.y), rank_key(sv.z), rank_key(sv.w)};
+            const int c4[4] = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (i0 + e < nc) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        rk[u] += (v4[e] > vk[u] || (v4[e] == vk[u] && c4[e] < ck[u])) ? 1 : 0;
+                }
             }
-            if (i < nc) {
-                const float v0 = rank_key(L.s[i]);
-                r0 += (v0 > vk || (v0 == vk && L.c[i] < ck)) ? 1 : 0;
-            }
-            const int rank = r0 + r1;
-            if (rank < K) {
-                L.q[rank] = ck;
-                L.bq[rank] = L.b[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = t + 16 * u;
+            if (k < nc && rk[u] < K) {
+                L.q[rk[u]] = ck[u];
+                L.bq[rk[u]] = L.b[k];
             }
         }
     }
     __syncthreads();
-    // all Gram entries of G[q,q] (lower triangle) in one batch of loads: entry
-    // e = tri(r) + i (i <= r) goes to the slot of row r of W_q
+    if (K <= kGJ) {
+        solve_q_gj(on, t, K, N, G32, L);
+        return;
+    }
+    // all Gram entries of G[q,q] (lower triangle) in one batch of loads:
+    // entry (r, i), i <= r, goes to C[tri(r) + i]; the diagonal is also kept
+    // in sq (the pivot floors), which the back substitution overwrites last
+    float* C = L.Wq;
     if (on) {
         const int TK = tri(K);
         for (int e0 = 0; e0 < TK; e0 += 64) {
             float v[4];
-            int dst[4];
+            int dst[4], row[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int e = e0 + 16 * u + t;
                 dst[u] = -1;
+                row[u] = 0;
                 v[u] = 0.f;
                 if (e < TK) {
                     int r = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
@@ -303,22 +399,53 @@ __device__ void prune_to_q(bool on, int t, int nc, int K, int N, const float* __
                     const int i = e - tri(r);
                     v[u] = G32[(size_t)clamp_atom(L.q[i], N) * N + clamp_atom(L.q[r], N)];
                     dst[u] = e;
+                    row[u] = (i == r) ? r : -1;
                 }
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (dst[u] >= 0) L.Wq[dst[u]] = v[u];
+            for (int u = 0; u < 4; ++u) {
+                if (dst[u] >= 0) C[dst[u]] = v[u];
+                if (dst[u] >= 0 && row[u] >= 0) L.sq[row[u]] = v[u];
+            }
         }
     }
     __syncthreads();
+    // LDL^T elimination with the forward substitution of b_q
     for (int k = 0; k < K; ++k) {
-        const float gjj = on ? L.Wq[tri(k) + k] : 1.f;
-        const float bj = on ? L.bq[k] : 0.f;
-        const int j = on ? L.q[k] : 0;
-        // the appended entry rewrites q[k] and bq[k] with their own values
-        inv_append(on, t, k, L.Wq, L.zq, L.bq, L.q, L.l, j, bj, gjj);
+        if (on) {
+            float piv = C[tri(k) + k];
+            const float fl = L.sq[k] * 5.9604645e-8f;
+            piv = piv > fl ? piv : fl;
+            const float rp = 1.f / piv;
+            const float bk = L.bq[k];
+            for (int i = k + 1 + t; i < K; i += 16) {
+                float* ci = C + tri(i);
+                const float f = ci[k] * rp;
+                int j = k + 1;
+                for (; j + 4 <= i + 1; j += 4) {
+                    const float c0 = C[tri(j) + k], c1 = C[tri(j + 1) + k], c2 = C[tri(j + 2) + k],
+                                c3 = C[tri(j + 3) + k];
+                    ci[j] -= f * c0;
+                    ci[j + 1] -= f * c1;
+                    ci[j + 2] -= f * c2;
+                    ci[j + 3] -= f * c3;
+                }
+                for (; j <= i; ++j) ci[j] -= f * C[tri(j) + k];
+                L.bq[i] -= f * bk;
+            }
+            if (t == 0) C[tri(k) + k] = piv;
+        }
+        __syncthreads();
     }
-    inv_solve(on, t, K, L.Wq, L.zq, L.sq);
+    // back substitution: s_i = (bt_i - sum_{k>i} C_ki s_k) / D_i, column-oriented
+    for (int i = K - 1; i >= 0; --i) {
+        if (on) {
+            const float si = L.bq[i] / C[tri(i) + i];
+            for (int k = t; k < i; k += 16) L.bq[k] -= C[tri(i) + k] * si;
+            if (t == 0) L.sq[i] = si;
+        }
+        __syncthreads();
+    }
 }
 
 // r = y - sum_k xv[k] A[:, xi[k]] for the lane's m = 4t + j + 64i.
@@ -353,7 +480,7 @@ __device__ __forceinline__ void residual(const float* y, float* rnew, const int*
     }
 }
 
-template <int MSLOT>
+template <int MSLOT, int NG>
 __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block, float* lds) {
     const int lane = threadIdx.x;
     const int x = lane & 3, t = lane >> 2;
@@ -361,7 +488,6 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
     const int64_t pix = a.p0 + local;
     const bool valid = local < a.P;
     const int M = a.M, N = a.N, K = a.K, MP = a.MP, NP = a.NP;
-    const int NG = NP >> 6;
     PixLds L = carve(lds + x * a.lds_floats, a);
 
     // y and r: lane t owns m = 4t + j + 64i (i < MSLOT/4)
@@ -398,8 +524,8 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
     int iters = 0, nc = 0, nx = 0;
     bool x_on_q = false;
     float last_d2 = __builtin_nanf(""), rn2 = y2;
-    uint32_t mask = 0u;   // bit 4g + i: atom 64g + 4t + i is in c
-    const int M4 = (M + 3) & ~3;
+    uint32_t mask = 0u;   // bit k: atom 4 NG t + k is in c
+    const int M8 = (M + kRowPad - 1) / kRowPad * kRowPad;
 
     for (int it = 1; it <= a.Imax; ++it) {
         // ---------------- step 1: p = A^T r on MFMA, top-S over the non-members
@@ -409,46 +535,53 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
             if (m < MP) L.rb[m] = r[u];
         }
         __syncthreads();
-        v4f_t acc[kMaxNG];
+        v4f_t acc[NG];
 #pragma unroll
-        for (int g = 0; g < kMaxNG; ++g) acc[g] = v4f_t{0.f, 0.f, 0.f, 0.f};
-        const float* rbx = L.rb;
-        for (int m4 = 0; m4 < M4; m4 += 4) {
-            const float4 rv = *reinterpret_cast<const float4*>(rbx + m4);
-            const float* ap = a.Ap + (size_t)m4 * NP + lane;
+        for (int g = 0; g < NG; ++g) acc[g] = v4f_t{0.f, 0.f, 0.f, 0.f};
+        {
+            typedef float vNG __attribute__((ext_vector_type(NG)));
+            const vNG* ap = reinterpret_cast<const vNG*>(a.Ap) + lane;   // row m starts at m * 64 vectors
+            vNG cur[kRowPad], nxt[kRowPad];
 #pragma unroll
-            for (int g = 0; g < kMaxNG; ++g) {
-                if (g < NG) {
-                    const float a0 = ap[64 * g];
-                    const float a1 = ap[NP + 64 * g];
-                    const float a2 = ap[2 * NP + 64 * g];
-                    const float a3 = ap[3 * NP + 64 * g];
-                    acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, rv.x, acc[g], 0, 0, 0);
-                    acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1, rv.y, acc[g], 0, 0, 0);
-                    acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(a2, rv.z, acc[g], 0, 0, 0);
-                    acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(a3, rv.w, acc[g], 0, 0, 0);
+            for (int r8 = 0; r8 < kRowPad; ++r8) cur[r8] = ap[(size_t)r8 * 64];
+            for (int m0 = 0; m0 < M8; m0 += kRowPad) {
+                if (m0 + kRowPad < M8) {
+#pragma unroll
+                    for (int r8 = 0; r8 < kRowPad; ++r8) nxt[r8] = ap[(size_t)(m0 + kRowPad + r8) * 64];
                 }
+                const float4 r0 = *reinterpret_cast<const float4*>(L.rb + m0);
+                const float4 r1 = *reinterpret_cast<const float4*>(L.rb + m0 + 4);
+                const float rv[kRowPad] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+                for (int r8 = 0; r8 < kRowPad; ++r8)
+#pragma unroll
+                    for (int g = 0; g < NG; ++g)
+                        acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(cur[r8][g], rv[r8], acc[g], 0, 0, 0);
+#pragma unroll
+                for (int r8 = 0; r8 < kRowPad; ++r8) cur[r8] = nxt[r8];
             }
         }
-        // S rounds of argmax; the winners are appended in selection order
+        // S rounds of argmax; the winners are appended in selection order.
+        // Lane t holds atoms 4 NG t + NG i + g (entry i of accumulator g).
         int nsel = 0;
         for (int q = 0; q < a.S; ++q) {
             float bv = -1.f;
             int bi = -1;
 #pragma unroll
-            for (int g = 0; g < kMaxNG; ++g)
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int n = 64 * g + 4 * t + i;
+                for (int g = 0; g < NG; ++g) {
+                    const int k = NG * i + g;
+                    const int n = 4 * NG * t + k;
                     const float v = fabsf(acc[g][i]);
-                    const bool member = (mask >> (4 * g + i)) & 1u;
-                    if (g < NG && n < N && !member && (bi < 0 || v > bv)) {
+                    const bool member = (mask >> k) & 1u;
+                    if (n < N && !member && (bi < 0 || v > bv)) {
                         bv = v;
                         bi = n;
                     }
                 }
             pix_argmax(bv, bi);
-            if (bi >= 0 && ((bi & 63) >> 2) == t) mask |= 1u << (4 * (bi >> 6) + (bi & 3));
+            if (bi >= 0 && bi / (4 * NG) == t) mask |= 1u << (bi % (4 * NG));
             if (t == 0) L.sel[q] = bi;
             nsel += (bi >= 0) ? 1 : 0;   // the valid selections form a prefix
         }
@@ -596,10 +729,10 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
     }
 }
 
-template <int MSLOT>
+template <int MSLOT, int NG>
 __global__ __launch_bounds__(64) void gomp_coop_kernel(CoopArgs a) {
     extern __shared__ float lds[];
-    gomp_coop_body<MSLOT>(a, blockIdx.x, lds);
+    gomp_coop_body<MSLOT, NG>(a, blockIdx.x, lds);
 }
 
 struct CoopItem {
@@ -608,19 +741,32 @@ struct CoopItem {
 };
 
 // Grouped launch: blocks [items[i].block0, items[i+1].block0) solve item i.
-template <int MSLOT>
+template <int MSLOT, int NG>
 __global__ __launch_bounds__(64) void gomp_coop_grouped_kernel(const CoopItem* __restrict__ items, int nitems) {
     extern __shared__ float lds[];
     int it = 0;
     while (it + 1 < nitems && items[it + 1].block0 <= (int64_t)blockIdx.x) ++it;
     const CoopArgs a = items[it].a;
-    gomp_coop_body<MSLOT>(a, (int64_t)blockIdx.x - items[it].block0, lds);
+    gomp_coop_body<MSLOT, NG>(a, (int64_t)blockIdx.x - items[it].block0, lds);
 }
 
-// The two dictionary copies: AT (N x MP, rows zero padded) and Ap (M4 x NP,
+typedef void (*coop_kernel_t)(CoopArgs);
+typedef void (*coop_grouped_t)(const CoopItem*, int);
+
+coop_kernel_t pick_coop(int MP, int NG) {
+    if (MP == 64) return NG == 2 ? gomp_coop_kernel<4, 2> : gomp_coop_kernel<4, 4>;
+    return NG == 2 ? gomp_coop_kernel<8, 2> : gomp_coop_kernel<8, 4>;
+}
+
+coop_grouped_t pick_coop_grouped(int MP, int NG) {
+    if (MP == 64) return NG == 2 ? gomp_coop_grouped_kernel<4, 2> : gomp_coop_grouped_kernel<4, 4>;
+    return NG == 2 ? gomp_coop_grouped_kernel<8, 2> : gomp_coop_grouped_kernel<8, 4>;
+}
+
+// The two dictionary copies: AT (N x MP, rows zero padded) and Ap (M8 x NP,
 // zero rows and columns).  Block n < N writes row n of AT; block N + m
-// (m < M4) writes row m of Ap.
-__global__ void prepare_kernel(const float* __restrict__ A, int M, int N, int MP, int M4, int NP,
+// (m < M8) writes row m of Ap.
+__global__ void prepare_kernel(const float* __restrict__ A, int M, int N, int MP, int M8, int NP,
                                float* __restrict__ AT, float* __restrict__ Ap) {
     const int bidx = blockIdx.x;
     if (bidx < N) {
@@ -633,7 +779,9 @@ __global__ void prepare_kernel(const float* __restrict__ A, int M, int N, int MP
     }
 }
 
-int coop_np(int N) { return ((N + 63) / 64) * 64; }
+int coop_ng(int N) { return N <= 128 ? 2 : 4; }
+int coop_np(int N) { return 64 * coop_ng(N); }
+int coop_m8(int M) { return (M + kRowPad - 1) / kRowPad * kRowPad; }
 
 void fill_args(CoopArgs& a, const float* dictbuf, int M, int N, int K, int S, int Imax, int prune, float res_tol,
                float eps, double pivot_thr) {
@@ -660,20 +808,18 @@ int gomp_coop_mp(int M) { return M <= 64 ? 64 : 128; }
 
 size_t gomp_coop_lds_floats(int MP, int CM, int K) { return (size_t)lds_plan(MP, CM, K).total; }
 
-size_t gomp_coop_dict_floats(int M, int N) {
-    return (size_t)N * gomp_coop_mp(M) + (size_t)((M + 3) & ~3) * coop_np(N);
-}
+size_t gomp_coop_dict_floats(int M, int N) { return (size_t)N * gomp_coop_mp(M) + (size_t)coop_m8(M) * coop_np(N); }
 
 int gomp_coop_supported(int M, int N, int K, int S, int Imax) {
-    if (N > 64 * kMaxNG || M > 128 || S > kMaxS) return CSREC_E_UNSUPPORTED;
+    if (N > 64 * kMaxNG || M > 128 || S > kMaxS) return CSREC_E_UNSUPPORTED;   // M8 <= MP holds for M <= 128
     const int CM = S * Imax;
     const size_t lds = kGroups * gomp_coop_lds_floats(gomp_coop_mp(M), CM, K) * sizeof(float);
     return lds <= 160 * 1024 ? CSREC_OK : CSREC_E_UNSUPPORTED;
 }
 
 void gomp_coop_prepare(const float* A, int M, int N, float* dictbuf, hipStream_t stream) {
-    const int MP = gomp_coop_mp(M), M4 = (M + 3) & ~3, NP = coop_np(N);
-    hipLaunchKernelGGL(prepare_kernel, dim3(N + M4), dim3(128), 0, stream, A, M, N, MP, M4, NP, dictbuf,
+    const int MP = gomp_coop_mp(M), M8 = coop_m8(M), NP = coop_np(N);
+    hipLaunchKernelGGL(prepare_kernel, dim3(N + M8), dim3(128), 0, stream, A, M, N, MP, M8, NP, dictbuf,
                        dictbuf + (size_t)N * MP);
 }
 
@@ -695,32 +841,30 @@ int gomp_coop_launch(const float* Y, float* X, int32_t* support, csrec_pixel_sta
     a.p0 = p0;
     const size_t lds = (size_t)kGroups * a.lds_floats * sizeof(float);
     const int64_t blocks = ceil_div(P, kGroups);
-    if (a.MP == 64) {
-        CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(gomp_coop_kernel<4>),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(gomp_coop_kernel<4>, dim3((unsigned)blocks), dim3(64), lds, stream, a);
-    } else {
-        CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(gomp_coop_kernel<8>),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(gomp_coop_kernel<8>, dim3((unsigned)blocks), dim3(64), lds, stream, a);
-    }
+    const coop_kernel_t fn = pick_coop(a.MP, a.NP / 64);
+    CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds));
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64), lds, stream, a);
     CSREC_HIP_TRY(hipGetLastError());
     return CSREC_OK;
 }
 
 size_t gomp_coop_item_bytes() { return sizeof(CoopItem); }
 
-// Items of one launch must share MP (64 or 128).
+// Items of one launch must share MP (64 or 128) and the atom grouping NG
+// (gomp_coop_class tells them apart).
+int gomp_coop_class(int M, int N) { return (gomp_coop_mp(M) == 64 ? 0 : 2) + (coop_ng(N) == 2 ? 0 : 1); }
+
 int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_host, void* table_dev, int K, int S,
                            int prune, float res_tol, float eps, double pivot_thr, hipStream_t stream) {
     if (nitems <= 0) return CSREC_OK;
     CoopItem* th = static_cast<CoopItem*>(table_host);
     int64_t blocks = 0;
     size_t lds = 0;
-    const int MP = gomp_coop_mp(items[0].M);
+    const int cls = gomp_coop_class(items[0].M, items[0].N);
     for (int i = 0; i < nitems; ++i) {
         const GompCoopItem& it = items[i];
-        if (gomp_coop_mp(it.M) != MP) return CSREC_E_INVAL;
+        if (gomp_coop_class(it.M, it.N) != cls) return CSREC_E_INVAL;
         CoopArgs& a = th[i].a;
         fill_args(a, it.dict, it.M, it.N, K, S, it.max_iter, prune, res_tol, eps, pivot_thr);
         a.Y = it.Y;
@@ -738,15 +882,10 @@ int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_ho
     }
     CSREC_HIP_TRY(hipMemcpyAsync(table_dev, th, (size_t)nitems * sizeof(CoopItem), hipMemcpyHostToDevice, stream));
     const CoopItem* td = static_cast<const CoopItem*>(table_dev);
-    if (MP == 64) {
-        CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(gomp_coop_grouped_kernel<4>),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(gomp_coop_grouped_kernel<4>, dim3((unsigned)blocks), dim3(64), lds, stream, td, nitems);
-    } else {
-        CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(gomp_coop_grouped_kernel<8>),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(gomp_coop_grouped_kernel<8>, dim3((unsigned)blocks), dim3(64), lds, stream, td, nitems);
-    }
+    const coop_grouped_t fn = pick_coop_grouped(th[0].a.MP, th[0].a.NP / 64);
+    CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds));
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64), lds, stream, td, nitems);
     CSREC_HIP_TRY(hipGetLastError());
     return CSREC_OK;
 }

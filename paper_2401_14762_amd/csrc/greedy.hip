@@ -827,15 +827,15 @@ int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* ite
         }
         if (nt > first) ranges[nr++] = Range{first, nt - first, blocks, classes[c], lds};
     }
-    // pass 0: the on-chip gOMP kernel, items grouped by their A^T row pitch
+    // pass 0: the on-chip gOMP kernel, items grouped by kernel variant
     char* chost = static_cast<char*>(table_host) + align_up((size_t)nitems * sizeof(GroupItem), 256);
     char* cdev = static_cast<char*>(table_dev) + align_up((size_t)nitems * sizeof(GroupItem), 256);
     int cfirst = 0;
-    for (int mp : {64, 128}) {
+    for (int cls = 0; cls < 4; ++cls) {
         std::vector<GompCoopItem> ci;
         for (int k = 0; k < nt; ++k) {
             const GroupItem& gi = th[k];
-            if (gomp_coop_mp(gi.g.M) != mp) continue;
+            if (gomp_coop_class(gi.g.M, gi.g.N) != cls) continue;
             GompCoopItem c{};
             c.dict = gi.dict;
             c.Y = gi.g.Y;
