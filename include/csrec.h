@@ -227,14 +227,20 @@ typedef struct {
     double t_submit, t_admit, t_done; /* seconds since server creation */
 } csrec_result;
 
-/* Creates the server (allocates its pool and workspace once). */
+/* Creates the server: allocates once its device pool (hbm_budget_bytes), its
+ * batch workspace and a pinned host staging pool of min(max(budget, 64 MiB),
+ * 4 GiB) for inputs and results, and starts its scheduler thread. */
 int32_t csrec_server_create(const csrec_server_cfg* cfg, csrec_server** out);
 /* Registers a dictionary (host A, M x N row-major); returns its id. */
 int32_t csrec_server_add_dict(csrec_server* srv, const float* A_host, int32_t M, int32_t N, int32_t* dict_id);
 /* Queues a tile of P pixels (host Y, P x M row-major) for dictionary dict_id.
  * CSREC_E_BUDGET if the tile alone exceeds the pool or the batch workspace. */
 int32_t csrec_server_submit(csrec_server* srv, int32_t dict_id, const float* Y_host, int64_t P, uint64_t tag);
-/* Moves up to max finished tiles into out; *n receives the count. */
+/* Moves up to max finished tiles into out; *n receives the count.  The
+ * results live in the server's pinned host staging pool (pageable memory
+ * only for a tile too large for it) until csrec_server_release: a caller
+ * that keeps many results unreleased stalls the copy-back of later tiles,
+ * and with it admission. */
 int32_t csrec_server_poll(csrec_server* srv, csrec_result* out, int32_t max, int32_t* n);
 /* Frees the host results of a polled tile. */
 int32_t csrec_server_release(csrec_server* srv, uint64_t tag);

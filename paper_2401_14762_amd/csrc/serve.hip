@@ -1,20 +1,30 @@
 // Serving runtime: continuous batching of cube tiles through gOMP (Alg. 3).
 //
 // Host side of the request loop.  One scheduler thread per server:
+//   submission -- the caller's measurements are copied into a pinned host
+//                 staging pool (first fit; pageable memory only for a tile
+//                 that could never fit it), outside the server lock;
 //   admission  -- tiles leave the arrival queue in order when their device
-//                 buffers (Y in, X / support / stats out) fit in the pool;
+//                 buffers (Y in, X / support / stats out) fit in the device
+//                 pool; their input copy runs on the host-to-device stream;
 //   batching   -- admitted tiles are cut into pixel chunks; one batch takes
 //                 chunks of several tiles (any band counts) up to the batch
 //                 capacity and runs them in grouped launches, at most two
 //                 batches in flight on the compute stream, so tiles admitted
-//                 while a batch runs join the next one;
+//                 while a batch runs join the next one; a batch waits (on the
+//                 device) for the input copies of its tiles;
 //   retirement -- a finished batch credits its chunks; a tile whose pixels
-//                 are all done is copied back on the copy stream, its pool
-//                 space freed and its latency stamped.
-// Dictionaries (A and its Gram matrix in FP32 and FP64) stay on the device
-// from csrec_server_add_dict until destroy; the per-pixel solver state of a
-// batch lives in the batch workspace.  Nothing is allocated on the device
-// after creation except dictionaries.
+//                 are all done is copied into pinned host result memory on
+//                 the device-to-host stream, and once that copy's event has
+//                 completed its device memory is freed and its latency
+//                 stamped.
+// Every HIP call the scheduler makes under the lock is asynchronous (event
+// queries, copies between pinned and device memory, launches), so submit and
+// poll never wait behind a transfer.  Dictionaries (A, its copies for the
+// on-chip kernel and its Gram matrix in FP32 and FP64) stay on the device from
+// csrec_server_add_dict until destroy; the per-pixel solver state of a batch
+// lives in the batch workspace.  Nothing is allocated on the device after
+// creation except dictionaries.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -103,18 +113,26 @@ struct Tile {
     uint64_t tag = 0;
     int dict = 0;
     int64_t P = 0;
-    std::vector<float> Yh;                 // host copy of the measurements until admitted
-    char* mem = nullptr;                   // pool allocation
+    char* hin = nullptr;                   // pinned staging of the measurements (host pool) ...
+    std::vector<float> Yv;                 // ... or a pageable copy when the pool cannot hold them
+    char* mem = nullptr;                   // device pool allocation
     float* dY = nullptr;
     float* dX = nullptr;
     int32_t* dS = nullptr;
     csrec_pixel_stats* dSt = nullptr;
+    hipEvent_t ev_in = nullptr;            // input copy done (host-to-device stream)
+    hipEvent_t ev_out = nullptr;           // result copy done (device-to-host stream)
+    bool in_waited = false;                // the compute stream already waits on ev_in
     int64_t issued = 0, done = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
     int status = CSREC_OK;
-    std::vector<float> X;
-    std::vector<int32_t> S;
-    std::vector<csrec_pixel_stats> St;
+    char* hout = nullptr;                  // pinned results (host pool), or the vectors below
+    std::vector<float> Xv;
+    std::vector<int32_t> Sv;
+    std::vector<csrec_pixel_stats> Stv;
+    float* X = nullptr;
+    int32_t* S = nullptr;
+    csrec_pixel_stats* St = nullptr;
 };
 
 struct Batch {
@@ -127,14 +145,27 @@ size_t tile_bytes(const Dict& d, int64_t P, int K) {
            align_up((size_t)P * K * 4, 256) + align_up((size_t)P * sizeof(csrec_pixel_stats), 256);
 }
 
+size_t result_bytes(const Dict& d, int64_t P, int K) {
+    return align_up((size_t)P * d.N * 4, 256) + align_up((size_t)P * K * 4, 256) +
+           align_up((size_t)P * sizeof(csrec_pixel_stats), 256);
+}
+
+// Pinned host staging: the device budget, at least 64 MiB and at most 4 GiB.
+size_t host_pool_bytes(size_t hbm_budget) {
+    const size_t lo = (size_t)64 << 20, hi = (size_t)4 << 30;
+    return hbm_budget < lo ? lo : (hbm_budget > hi ? hi : hbm_budget);
+}
+
 }  // namespace
 }  // namespace csrec
 
 struct csrec_server {
     csrec_server_cfg cfg{};
     std::chrono::steady_clock::time_point t0;
-    hipStream_t compute = nullptr, copy = nullptr;
+    hipStream_t compute = nullptr, h2d = nullptr, d2h = nullptr;
     char* pool_mem = nullptr;
+    char* host_mem = nullptr;             // pinned staging for inputs and results
+    csrec::Pool hpool;
     char* ws = nullptr;
     size_t ws_bytes = 0;
     void* table_dev = nullptr;
@@ -147,7 +178,9 @@ struct csrec_server {
     std::mutex mu;
     std::condition_variable cv;
     std::deque<std::unique_ptr<csrec::Tile>> pending;
-    std::vector<std::unique_ptr<csrec::Tile>> admitted;
+    std::vector<std::unique_ptr<csrec::Tile>> admitted;  // on the device, chunks being solved
+    std::deque<std::unique_ptr<csrec::Tile>> computed;   // solved, waiting for host result memory
+    std::vector<std::unique_ptr<csrec::Tile>> copying;   // result copy in flight
     std::deque<std::unique_ptr<csrec::Tile>> finished;   // not yet polled
     std::map<uint64_t, std::unique_ptr<csrec::Tile>> polled;
     std::deque<csrec::Batch> inflight;
@@ -159,6 +192,42 @@ struct csrec_server {
 
 namespace csrec {
 namespace {
+
+// Starts the result copy of a solved tile into pinned host memory; false
+// when the host pool is momentarily full (retried on a later step).  A tile
+// whose results could never fit the pool is copied into pageable vectors.
+bool start_output(csrec_server* s, Tile* t) {
+    const Dict& d = s->dicts[t->dict];
+    const int K = s->cfg.gomp.K;
+    const size_t bytes = result_bytes(d, t->P, K);
+    char* h = s->hpool.alloc(bytes);
+    if (!h && bytes <= s->hpool.capacity()) return false;
+    if (h) {
+        t->hout = h;
+        t->X = reinterpret_cast<float*>(h);
+        t->S = reinterpret_cast<int32_t*>(h + align_up((size_t)t->P * d.N * 4, 256));
+        t->St = reinterpret_cast<csrec_pixel_stats*>(reinterpret_cast<char*>(t->S) + align_up((size_t)t->P * K * 4, 256));
+    } else {
+        t->Xv.resize((size_t)t->P * d.N);
+        t->Sv.resize((size_t)t->P * K);
+        t->Stv.resize((size_t)t->P);
+        t->X = t->Xv.data();
+        t->S = t->Sv.data();
+        t->St = t->Stv.data();
+    }
+    hipError_t e = hipEventCreateWithFlags(&t->ev_out, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemcpyAsync(t->X, t->dX, (size_t)t->P * d.N * 4, hipMemcpyDeviceToHost, s->d2h);
+    if (e == hipSuccess) e = hipMemcpyAsync(t->S, t->dS, (size_t)t->P * K * 4, hipMemcpyDeviceToHost, s->d2h);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(t->St, t->dSt, (size_t)t->P * sizeof(csrec_pixel_stats), hipMemcpyDeviceToHost, s->d2h);
+    if (e == hipSuccess) e = hipEventRecord(t->ev_out, s->d2h);
+    if (e != hipSuccess) {
+        set_hip_error(e);
+        s->error = CSREC_E_DEVICE;
+        t->status = CSREC_E_DEVICE;
+    }
+    return true;
+}
 
 // One scheduler step under the lock; returns true when it did something.
 bool schedule_once(csrec_server* s) {
@@ -172,41 +241,48 @@ bool schedule_once(csrec_server* s) {
             set_hip_error(q);
             s->error = CSREC_E_DEVICE;
         }
-        for (auto& pr : b.parts) {
-            Tile* t = pr.first;
-            t->done += pr.second;
-            if (t->done == t->P) {
-                const int K = s->cfg.gomp.K;
-                const Dict& d = s->dicts[t->dict];
-                t->X.resize((size_t)t->P * d.N);
-                t->S.resize((size_t)t->P * K);
-                t->St.resize((size_t)t->P);
-                hipError_t e = hipStreamWaitEvent(s->copy, b.ev, 0);
-                if (e == hipSuccess) e = hipMemcpyAsync(t->X.data(), t->dX, t->X.size() * 4, hipMemcpyDeviceToHost, s->copy);
-                if (e == hipSuccess) e = hipMemcpyAsync(t->S.data(), t->dS, t->S.size() * 4, hipMemcpyDeviceToHost, s->copy);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(t->St.data(), t->dSt, t->St.size() * sizeof(csrec_pixel_stats),
-                                       hipMemcpyDeviceToHost, s->copy);
-                if (e == hipSuccess) e = hipStreamSynchronize(s->copy);
-                if (e != hipSuccess) {
-                    set_hip_error(e);
-                    t->status = CSREC_E_DEVICE;
-                }
-                t->t_done = now_since(s->t0);
-                s->pool.release(t->mem);
-                t->mem = nullptr;
-                std::vector<float>().swap(t->Yh);
-                for (auto it = s->admitted.begin(); it != s->admitted.end(); ++it)
-                    if (it->get() == t) {
-                        s->finished.push_back(std::move(*it));
-                        s->admitted.erase(it);
-                        break;
-                    }
-                --s->outstanding;
-            }
-        }
+        for (auto& pr : b.parts) pr.first->done += pr.second;
         hipEventDestroy(b.ev);
         s->inflight.pop_front();
+        worked = true;
+    }
+    // ---- solved tiles leave the admitted set in order of admission
+    for (auto it = s->admitted.begin(); it != s->admitted.end();) {
+        if ((*it)->done == (*it)->P) {
+            s->computed.push_back(std::move(*it));
+            it = s->admitted.erase(it);
+            worked = true;
+        } else {
+            ++it;
+        }
+    }
+    while (!s->computed.empty() && start_output(s, s->computed.front().get())) {
+        s->copying.push_back(std::move(s->computed.front()));
+        s->computed.pop_front();
+        worked = true;
+    }
+    // ---- result copies that completed
+    for (auto it = s->copying.begin(); it != s->copying.end();) {
+        Tile* t = it->get();
+        const hipError_t q = hipEventQuery(t->ev_out);
+        if (q == hipErrorNotReady) {
+            ++it;
+            continue;
+        }
+        if (q != hipSuccess) {
+            set_hip_error(q);
+            s->error = CSREC_E_DEVICE;
+            t->status = CSREC_E_DEVICE;
+        }
+        t->t_done = now_since(s->t0);
+        s->pool.release(t->mem);
+        t->mem = nullptr;
+        if (t->hin) s->hpool.release(t->hin);
+        t->hin = nullptr;
+        std::vector<float>().swap(t->Yv);
+        --s->outstanding;
+        s->finished.push_back(std::move(*it));
+        it = s->copying.erase(it);
         worked = true;
     }
     // ---- admission in arrival order
@@ -222,7 +298,10 @@ bool schedule_once(csrec_server* s) {
         t->dS = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(t->dX) + align_up((size_t)t->P * d.N * 4, 256));
         t->dSt = reinterpret_cast<csrec_pixel_stats*>(reinterpret_cast<char*>(t->dS) +
                                                       align_up((size_t)t->P * s->cfg.gomp.K * 4, 256));
-        const hipError_t e = hipMemcpyAsync(t->dY, t->Yh.data(), t->Yh.size() * 4, hipMemcpyHostToDevice, s->compute);
+        const void* src = t->hin ? static_cast<const void*>(t->hin) : static_cast<const void*>(t->Yv.data());
+        hipError_t e = hipEventCreateWithFlags(&t->ev_in, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMemcpyAsync(t->dY, src, (size_t)t->P * d.M * 4, hipMemcpyHostToDevice, s->h2d);
+        if (e == hipSuccess) e = hipEventRecord(t->ev_in, s->h2d);
         if (e != hipSuccess) {
             set_hip_error(e);
             s->error = CSREC_E_DEVICE;
@@ -264,10 +343,18 @@ bool schedule_once(csrec_server* s) {
             if (room <= 0 || (int)items.size() >= s->max_items) break;
         }
         if (!items.empty()) {
+            hipError_t he = hipSuccess;
+            for (auto& pr : b.parts) {
+                Tile* t = pr.first;
+                if (!t->in_waited && he == hipSuccess) {
+                    he = hipStreamWaitEvent(s->compute, t->ev_in, 0);
+                    t->in_waited = true;
+                }
+            }
             int e = greedy_group_launch(s->proto, items.data(), (int)items.size(), s->cfg.batch_pixels, s->ws,
                                         s->table_host[s->table_flip], s->table_dev, s->compute);
             s->table_flip ^= 1;
-            hipError_t he = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+            if (he == hipSuccess) he = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
             if (he == hipSuccess) he = hipEventRecord(b.ev, s->compute);
             if (e != CSREC_OK || he != hipSuccess) {
                 if (he != hipSuccess) set_hip_error(he);
@@ -280,11 +367,24 @@ bool schedule_once(csrec_server* s) {
     return worked;
 }
 
+// Releases a tile's host and device resources (lock held).
+void drop_tile(csrec_server* s, Tile* t) {
+    if (t->mem) s->pool.release(t->mem);
+    if (t->hin) s->hpool.release(t->hin);
+    if (t->hout) s->hpool.release(t->hout);
+    if (t->ev_in) hipEventDestroy(t->ev_in);
+    if (t->ev_out) hipEventDestroy(t->ev_out);
+    t->mem = t->hin = t->hout = nullptr;
+    t->ev_in = t->ev_out = nullptr;
+}
+
 void scheduler(csrec_server* s) {
     hipSetDevice(s->cfg.device);
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
-        if (s->stop && s->pending.empty() && s->admitted.empty() && s->inflight.empty()) break;
+        if (s->stop && s->pending.empty() && s->admitted.empty() && s->computed.empty() && s->copying.empty() &&
+            s->inflight.empty())
+            break;
         if (s->error != CSREC_OK && s->inflight.empty()) {
             // fail every queued tile and stop issuing work
             for (auto& t : s->pending) {
@@ -293,13 +393,26 @@ void scheduler(csrec_server* s) {
                 s->finished.push_back(std::move(t));
             }
             s->pending.clear();
-            for (auto& t : s->admitted) {
+            hipStreamSynchronize(s->h2d);
+            hipStreamSynchronize(s->d2h);
+            for (auto* lst : {&s->admitted, &s->copying}) {
+                for (auto& t : *lst) {
+                    t->status = s->error;
+                    if (t->mem) s->pool.release(t->mem);
+                    t->mem = nullptr;
+                    --s->outstanding;
+                    s->finished.push_back(std::move(t));
+                }
+                lst->clear();
+            }
+            for (auto& t : s->computed) {
                 t->status = s->error;
                 if (t->mem) s->pool.release(t->mem);
+                t->mem = nullptr;
                 --s->outstanding;
                 s->finished.push_back(std::move(t));
             }
-            s->admitted.clear();
+            s->computed.clear();
             s->cv.notify_all();
             if (s->stop) break;
             s->cv.wait_for(lk, std::chrono::milliseconds(1));
@@ -348,8 +461,12 @@ int32_t csrec_server_create(const csrec_server_cfg* cfg, csrec_server** out) {
     s->ws_bytes = greedy_group_workspace(p, cfg->batch_pixels);
     s->max_items = (int)std::min<int64_t>(4096, cfg->batch_pixels);
     CSREC_HIP_TRY(hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking));
-    CSREC_HIP_TRY(hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking));
+    CSREC_HIP_TRY(hipStreamCreateWithFlags(&s->h2d, hipStreamNonBlocking));
+    CSREC_HIP_TRY(hipStreamCreateWithFlags(&s->d2h, hipStreamNonBlocking));
     CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&s->pool_mem), cfg->hbm_budget_bytes));
+    const size_t hb = host_pool_bytes(cfg->hbm_budget_bytes);
+    CSREC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&s->host_mem), hb, hipHostMallocDefault));
+    s->hpool.init(s->host_mem, hb);
     CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&s->ws), s->ws_bytes));
     const size_t tb = align_up((size_t)s->max_items * greedy_group_item_bytes(), 256) +
                       (size_t)s->max_items * gomp_coop_item_bytes();
@@ -410,8 +527,13 @@ int32_t csrec_server_submit(csrec_server* s, int32_t dict_id, const float* Y_hos
         if (tile_bytes(d, P, s->cfg.gomp.K) > s->pool.capacity()) return CSREC_E_BUDGET;
         if (P > s->cfg.batch_pixels * 4096) return CSREC_E_BUDGET;
         M = d.M;
+        if (P > 0) t->hin = s->hpool.alloc((size_t)P * M * 4);
     }
-    t->Yh.assign(Y_host, Y_host + (size_t)P * M);   // copied outside the lock
+    // copied outside the lock
+    if (t->hin)
+        std::memcpy(t->hin, Y_host, (size_t)P * M * 4);
+    else
+        t->Yv.assign(Y_host, Y_host + (size_t)P * M);
     t->tag = tag;
     t->dict = dict_id;
     t->P = P;
@@ -442,9 +564,9 @@ int32_t csrec_server_poll(csrec_server* s, csrec_result* out, int32_t max, int32
         r.P = t->P;
         r.N = d.N;
         r.K = s->cfg.gomp.K;
-        r.X = t->X.data();
-        r.support = t->S.data();
-        r.stats = t->St.data();
+        r.X = t->X;
+        r.support = t->S;
+        r.stats = t->St;
         r.t_submit = t->t_submit;
         r.t_admit = t->t_admit;
         r.t_done = t->t_done;
@@ -457,7 +579,11 @@ int32_t csrec_server_poll(csrec_server* s, csrec_result* out, int32_t max, int32
 int32_t csrec_server_release(csrec_server* s, uint64_t tag) {
     if (!s) return CSREC_E_INVAL;
     std::lock_guard<std::mutex> lk(s->mu);
-    s->polled.erase(tag);
+    auto it = s->polled.find(tag);
+    if (it != s->polled.end()) {
+        drop_tile(s, it->second.get());
+        s->polled.erase(it);
+    }
     return CSREC_OK;
 }
 
@@ -478,6 +604,10 @@ int32_t csrec_server_destroy(csrec_server* s) {
     if (s->th.joinable()) s->th.join();
     hipSetDevice(s->cfg.device);
     hipStreamSynchronize(s->compute);
+    hipStreamSynchronize(s->h2d);
+    hipStreamSynchronize(s->d2h);
+    for (auto& kv : s->polled) drop_tile(s, kv.second.get());
+    for (auto& t : s->finished) drop_tile(s, t.get());
     for (auto& d : s->dicts) {
         hipFree(d.A);
         hipFree(d.AT);
@@ -489,8 +619,10 @@ int32_t csrec_server_destroy(csrec_server* s) {
     hipFree(s->table_dev);
     hipHostFree(s->table_host[0]);
     hipHostFree(s->table_host[1]);
+    hipHostFree(s->host_mem);
     hipStreamDestroy(s->compute);
-    hipStreamDestroy(s->copy);
+    hipStreamDestroy(s->h2d);
+    hipStreamDestroy(s->d2h);
     delete s;
     return CSREC_OK;
 }
