@@ -183,13 +183,19 @@ __device__ __forceinline__ float dot4(const float* u, const float* v, int len) {
 __device__ __forceinline__ float coldot4(const float* Wf, const float* v, int k, int n) {
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
     int i = k;
+    int off = tri(k) + k;   // tri(i) + k, advanced by i + 1 per row
     for (; i + 4 <= n; i += 4) {
-        s0 += v[i] * Wf[tri(i) + k];
-        s1 += v[i + 1] * Wf[tri(i + 1) + k];
-        s2 += v[i + 2] * Wf[tri(i + 2) + k];
-        s3 += v[i + 3] * Wf[tri(i + 3) + k];
+        const int o1 = off + i + 1, o2 = o1 + i + 2, o3 = o2 + i + 3;
+        s0 += v[i] * Wf[off];
+        s1 += v[i + 1] * Wf[o1];
+        s2 += v[i + 2] * Wf[o2];
+        s3 += v[i + 3] * Wf[o3];
+        off = o3 + i + 4;
     }
-    for (; i < n; ++i) s0 += v[i] * Wf[tri(i) + k];
+    for (; i < n; ++i) {
+        s0 += v[i] * Wf[off];
+        off += i + 1;
+    }
     return (s0 + s1) + (s2 + s3);
 }
 
@@ -197,7 +203,7 @@ __device__ __forceinline__ float coldot4(const float* Wf, const float* v, int k,
 // the factor (Wf, zf, bf, idx) of size n.  The slot of row n must hold
 // G[idx[i], atom] for i < n (written before the barrier preceding the call).
 // All 64 lanes call it; `on` masks the pixels that take part.  Returns d / G_jj.
-__device__ float inv_append(bool on, int t, int n, float* Wf, float* zf, float* bf, int* idx, float* ltmp,
+__device__ __forceinline__ float inv_append(bool on, int t, int n, float* Wf, float* zf, float* bf, int* idx, float* ltmp,
                             int atom, float bj, float gjj) {
     float* wn = Wf + tri(n);   // G[idx, atom] now, the new row after the second barrier
     // l = W g (rows i = t + 16u)
@@ -243,7 +249,7 @@ __device__ float inv_append(bool on, int t, int n, float* Wf, float* zf, float* 
 }
 
 // s = W^T z on the first n entries (columns k = t + 16u).
-__device__ void inv_solve(bool on, int t, int n, const float* Wf, const float* zf, float* sf) {
+__device__ __forceinline__ void inv_solve(bool on, int t, int n, const float* Wf, const float* zf, float* sf) {
     if (on)
         for (int k = t; k < n; k += 16) sf[k] = coldot4(Wf, zf, k, n);
     __syncthreads();
@@ -292,6 +298,7 @@ __device__ __forceinline__ void solve_q_gj(bool on, int t, int K, int N, const f
             if (on) {
 #pragma unroll
                 for (int j = k & ~3; j < W1 + 3; j += 4) {
+                    if (j >= K && j < kGJ) continue;   // all-zero padding columns (uniform)
                     const float4 v = make_float4(R[j], j + 1 < W1 ? R[j + 1] : 0.f, j + 2 < W1 ? R[j + 2] : 0.f,
                                                  j + 3 < W1 ? R[j + 3] : 0.f);
                     *reinterpret_cast<float4*>(slot + j) = v;
@@ -305,6 +312,7 @@ __device__ __forceinline__ void solve_q_gj(bool on, int t, int K, int N, const f
             const float f1 = (t + 16 == k) ? 0.f : R1[k] * rp;
 #pragma unroll
             for (int j = k & ~3; j < W1; j += 4) {
+                if (j >= K && j < kGJ) continue;   // all-zero padding columns (uniform)
                 const float4 v = *reinterpret_cast<const float4*>(slot + j);
                 const float pv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -335,7 +343,8 @@ __device__ __forceinline__ void solve_q_gj(bool on, int t, int K, int N, const f
 // pivot C_kk, floored at 2^-24 of the original diagonal like the appends;
 // C keeps the unscaled columns (C_ik = D_k Lt_ik), so no square roots.
 // Called by every lane (it holds barriers).
-__device__ void prune_to_q(bool on, int t, int nc, int K, int N, const float* __restrict__ G32, const PixLds& L) {
+__device__ __forceinline__ void prune_to_q(bool on, int t, int nc, int K, int N, const float* __restrict__ G32,
+                                           const PixLds L) {
     if (on) {
         // the key maps non-finite |s| below every finite one, so (key desc,
         // index asc) is a strict total order over the distinct atoms of c and
