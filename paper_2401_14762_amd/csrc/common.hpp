@@ -128,6 +128,12 @@ struct GompCoopItem {
 };
 size_t gomp_coop_item_bytes();
 int gomp_coop_class(int M, int N);   // items of one grouped launch share it (0..3)
+// CoSaMP (Alg. 5), BIHT (Alg. 4) and one-bit BIHT on the same on-chip design.
+size_t coop_other_lds_floats(int kind, int M, int N, int K);
+int coop_other_supported(int kind, int M, int N, int K);
+int coop_other_launch(int kind, const float* Y, const int8_t* Ysign, float* X, int32_t* support,
+                      csrec_pixel_stats* stats, const float* G32, const float* dictbuf, int M, int N, int64_t p0,
+                      int64_t P, int K, int Imax, float mu, float res_tol, float eps, hipStream_t stream);
 int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_host, void* table_dev, int K, int S,
                            int prune, float res_tol, float eps, double pivot_thr, hipStream_t stream);
 

@@ -69,6 +69,8 @@ struct CoopArgs {
     int64_t p0;           // first pixel (index into Y/X/support/stats)
     int CM;               // S * Imax
     int lds_floats;       // per pixel
+    float mu;             // BIHT step
+    const int8_t* Ysign;  // one-bit BIHT: P x M signs
 };
 
 __host__ __device__ __forceinline__ int tri(int k) { return k * (k + 1) / 2; }
@@ -260,138 +262,150 @@ __device__ __forceinline__ float rank_key(float v) {
     return a <= 3.402823466e38f ? a : -1.f;   // NaN and inf rank last
 }
 
-// s_q = G[q,q]^{-1} b_q for K <= kGJ by Gauss-Jordan elimination on
-// registers: lane t owns rows t and t + 16 of [G[q,q] | b_q].  Step k (fully
-// unrolled, so every register index is static) publishes pivot row k through
-// a double-buffered LDS slot (one barrier) and every other row subtracts its
-// multiple of it over the columns j >= k still in play.  The pivot is floored
-// at 2^-24 of the original diagonal like the appends.  After K steps row i
-// reads d_i s_i = rhs_i, with d_i the row's pivot.
-__device__ __forceinline__ void solve_q_gj(bool on, int t, int K, int N, const float* __restrict__ G32,
-                                        const PixLds& L) {
-    constexpr int W1 = kGJ + 1;          // K columns (padded to kGJ) + the right-hand side
-    constexpr int SLOT = kGJ + 4;
-    float R0[W1], R1[W1];
-    const bool h0 = on && t < K, h1 = on && t + 16 < K;
-    const int q0 = clamp_atom(h0 ? L.q[t] : 0, N), q1 = clamp_atom(h1 ? L.q[t + 16] : 0, N);
+// q[rank] = c[k] and qv[rank] = vals[k] for the K entries k < n with the
+// largest |s[k]| (ties to the lower atom index).  The key maps non-finite
+// |s| below every finite one, so (key desc, index asc) is a strict total
+// order over distinct atoms and the ranks are a permutation: q[0..min(K, n))
+// is always fully written.  No barrier inside; s, c, vals must be readable
+// (their writes followed by a barrier).  s and c are read as 16-byte vectors
+// up to n rounded to 4.
+__device__ __forceinline__ void rank_top(bool on, int t, int n, int K, const float* s, const int* c,
+                                         const float* vals, int* q, float* qv) {
+    if (!on) return;
+    float vk[4];
+    int ck[4], rk[4];
 #pragma unroll
-    for (int j = 0; j < kGJ; ++j) {
-        const bool hj = on && j < K;
-        const int qj = clamp_atom(hj ? L.q[j] : 0, N);
-        R0[j] = (h0 && hj) ? G32[(size_t)q0 * N + qj] : 0.f;
-        R1[j] = (h1 && hj) ? G32[(size_t)q1 * N + qj] : 0.f;
+    for (int u = 0; u < 4; ++u) {
+        const int k = t + 16 * u;
+        vk[u] = k < n ? rank_key(s[k]) : 0.f;
+        ck[u] = k < n ? c[k] : 0;
+        rk[u] = 0;
     }
-    R0[kGJ] = h0 ? L.bq[t] : 0.f;
-    R1[kGJ] = h1 ? L.bq[t + 16] : 0.f;
-    const float fl0 = (h0 ? G32[(size_t)q0 * N + q0] : 1.f) * 5.9604645e-8f;
-    const float fl1 = (h1 ? G32[(size_t)q1 * N + q1] : 1.f) * 5.9604645e-8f;
-    float dg0 = 1.f, dg1 = 1.f;
+    for (int i0 = 0; i0 < n; i0 += 4) {
+        const float4 sv = *reinterpret_cast<const float4*>(s + i0);
+        const int4 cv = *reinterpret_cast<const int4*>(c + i0);
+        const float v4[4] = {rank_key(sv.x), rank_key(sv.y), rank_key(sv.z), rank_key(sv.w)};
+        const int c4[4] = {cv.x, cv.y, cv.z, cv.w};
 #pragma unroll
-    for (int k = 0; k < kGJ; ++k) {
-        if (k < K) {   // uniform
-        float* slot = L.Wq + (k & 1) * SLOT;
-        if (t == (k & 15)) {
-            float* R = k < 16 ? R0 : R1;
-            const float fl = k < 16 ? fl0 : fl1;
-            R[k] = R[k] > fl ? R[k] : fl;
-            if (k < 16) dg0 = R[k]; else dg1 = R[k];
-            if (on) {
+        for (int e = 0; e < 4; ++e) {
+            if (i0 + e < n) {
 #pragma unroll
-                for (int j = k & ~3; j < W1 + 3; j += 4) {
-                    if (j >= K && j < kGJ) continue;   // all-zero padding columns (uniform)
-                    const float4 v = make_float4(R[j], j + 1 < W1 ? R[j + 1] : 0.f, j + 2 < W1 ? R[j + 2] : 0.f,
-                                                 j + 3 < W1 ? R[j + 3] : 0.f);
-                    *reinterpret_cast<float4*>(slot + j) = v;
-                }
+                for (int u = 0; u < 4; ++u)
+                    rk[u] += (v4[e] > vk[u] || (v4[e] == vk[u] && c4[e] < ck[u])) ? 1 : 0;
             }
         }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int k = t + 16 * u;
+        if (k < n && rk[u] < K) {
+            q[rk[u]] = ck[u];
+            qv[rk[u]] = vals[k];
+        }
+    }
+}
+
+// sol = G[L,L]^{-1} rhs for the n atoms of the list L (n <= nmax, nmax
+// uniform over the wave; a pixel with n < nmax is padded with identity rows
+// and zero right-hand sides, so every pixel runs the same nmax barriered
+// steps).  rhs (nmax entries) is destroyed.  Called by every lane.
+//
+// nmax <= kGJ: Gauss-Jordan elimination on registers.  Lane t owns rows t
+// and t + 16 of [G[L,L] | rhs], gathered in one batch.  Step k (fully
+// unrolled, so every register index is static) publishes pivot row k
+// through a double-buffered LDS slot in scr (2 x (kGJ + 4) floats; one
+// barrier) and every other row subtracts its multiple of it over the columns
+// j >= k still in play; all-zero padding columns are skipped.  After nmax
+// steps row i reads d_i sol_i = rhs_i, with d_i the row's pivot.
+//
+// nmax > kGJ: right-looking LDL^T elimination of the lower triangle C of
+// G[L,L] in scr (tri(nmax) floats, gathered in one batch), the forward
+// substitution of rhs riding along, then a column-oriented back
+// substitution: 2 nmax steps, each one barrier and a set of independent
+// element updates split over the 16 lanes.  C keeps the unscaled columns
+// (C_ik = D_k Lt_ik), so no square roots.
+//
+// Every pivot is floored at 2^-24 of the original diagonal like the appends,
+// so a numerically dependent atom keeps the solution finite.
+template <bool PAD>
+__device__ __forceinline__ void solve_list(bool on, int t, int n, int nmax, int N, const float* __restrict__ G32,
+                                           const int* L, float* rhs, float* sol, float* scr) {
+    if (!PAD) n = nmax;   // every pixel solves a full list
+    if (PAD) {
+        if (on)
+            for (int i = n + t; i < nmax; i += 16) rhs[i] = 0.f;
         __syncthreads();
-        if (on) {
-            const float rp = 1.f / slot[k];
-            const float f0 = (t == k) ? 0.f : R0[k] * rp;
-            const float f1 = (t + 16 == k) ? 0.f : R1[k] * rp;
+    }
+    if (nmax <= kGJ) {
+        constexpr int W1 = kGJ + 1;          // nmax columns (padded to kGJ) + the right-hand side
+        constexpr int SLOT = kGJ + 4;
+        float R0[W1], R1[W1];
+        const bool h0 = on && t < n, h1 = on && t + 16 < n;
+        const int q0 = clamp_atom(h0 ? L[t] : 0, N), q1 = clamp_atom(h1 ? L[t + 16] : 0, N);
 #pragma unroll
-            for (int j = k & ~3; j < W1; j += 4) {
-                if (j >= K && j < kGJ) continue;   // all-zero padding columns (uniform)
-                const float4 v = *reinterpret_cast<const float4*>(slot + j);
-                const float pv[4] = {v.x, v.y, v.z, v.w};
+        for (int j = 0; j < kGJ; ++j) {
+            const bool hj = on && j < n;
+            const int qj = clamp_atom(hj ? L[j] : 0, N);
+            R0[j] = (h0 && hj) ? G32[(size_t)q0 * N + qj] : ((PAD && j == t) ? 1.f : 0.f);
+            R1[j] = (h1 && hj) ? G32[(size_t)q1 * N + qj] : ((PAD && j == t + 16) ? 1.f : 0.f);
+        }
+        R0[kGJ] = (PAD ? on && t < nmax : h0) ? rhs[t] : 0.f;
+        R1[kGJ] = (PAD ? on && t + 16 < nmax : h1) ? rhs[t + 16] : 0.f;
+        const float fl0 = (h0 ? G32[(size_t)q0 * N + q0] : 1.f) * 5.9604645e-8f;
+        const float fl1 = (h1 ? G32[(size_t)q1 * N + q1] : 1.f) * 5.9604645e-8f;
+        float dg0 = 1.f, dg1 = 1.f;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (j + e > k && j + e < W1) {
-                        R0[j + e] -= f0 * pv[e];
-                        R1[j + e] -= f1 * pv[e];
+        for (int k = 0; k < kGJ; ++k) {
+            if (k < nmax) {   // uniform
+                float* slot = scr + (k & 1) * SLOT;
+                if (t == (k & 15)) {
+                    float* R = k < 16 ? R0 : R1;
+                    const float fl = k < 16 ? fl0 : fl1;
+                    R[k] = R[k] > fl ? R[k] : fl;
+                    if (k < 16) dg0 = R[k]; else dg1 = R[k];
+                    if (on) {
+#pragma unroll
+                        for (int j = k & ~3; j < W1 + 3; j += 4) {
+                            if (j >= nmax && j < kGJ) continue;   // all-zero padding columns (uniform)
+                            const float4 v = make_float4(R[j], j + 1 < W1 ? R[j + 1] : 0.f,
+                                                         j + 2 < W1 ? R[j + 2] : 0.f, j + 3 < W1 ? R[j + 3] : 0.f);
+                            *reinterpret_cast<float4*>(slot + j) = v;
+                        }
+                    }
+                }
+                __syncthreads();
+                if (on) {
+                    const float rp = 1.f / slot[k];
+                    const float f0 = (t == k) ? 0.f : R0[k] * rp;
+                    const float f1 = (t + 16 == k) ? 0.f : R1[k] * rp;
+#pragma unroll
+                    for (int j = k & ~3; j < W1; j += 4) {
+                        if (j >= nmax && j < kGJ) continue;   // all-zero padding columns (uniform)
+                        const float4 v = *reinterpret_cast<const float4*>(slot + j);
+                        const float pv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            if (j + e > k && j + e < W1) {
+                                R0[j + e] -= f0 * pv[e];
+                                R1[j + e] -= f1 * pv[e];
+                            }
+                        }
                     }
                 }
             }
         }
-        }
-    }
-    if (h0) L.sq[t] = R0[kGJ] / dg0;
-    if (h1) L.sq[t + 16] = R1[kGJ] / dg1;
-    __syncthreads();
-}
-
-// Step 3 of Alg. 3 for the pixels with `on`: q = the K entries of c with
-// largest |s| (ties to the lower index), then s_q = G[q,q]^{-1} b_q.
-//
-// For K <= kGJ the K x K system is solved on registers (solve_q_gj);
-// larger ones by a right-looking LDL^T elimination of the
-// lower triangle C of G[q,q] (gathered in one batch), the forward
-// substitution of b_q riding along, then a column-oriented back
-// substitution: 2K steps, each one barrier and a set of independent element
-// updates split over the 16 lanes (no reductions).  Step k divides by the
-// pivot C_kk, floored at 2^-24 of the original diagonal like the appends;
-// C keeps the unscaled columns (C_ik = D_k Lt_ik), so no square roots.
-// Called by every lane (it holds barriers).
-__device__ __forceinline__ void prune_to_q(bool on, int t, int nc, int K, int N, const float* __restrict__ G32,
-                                           const PixLds L) {
-    if (on) {
-        // the key maps non-finite |s| below every finite one, so (key desc,
-        // index asc) is a strict total order over the distinct atoms of c and
-        // the ranks are a permutation: q[0..K) is always fully written
-        float vk[4];
-        int ck[4], rk[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int k = t + 16 * u;
-            vk[u] = k < nc ? rank_key(L.s[k]) : 0.f;
-            ck[u] = k < nc ? L.c[k] : 0;
-            rk[u] = 0;
-        }
-        for (int i0 = 0; i0 < nc; i0 += 4) {
-            const float4 sv = *reinterpret_cast<const float4*>(L.s + i0);
-            const int4 cv = *reinterpret_cast<const int4*>(L.c + i0);
-            const float v4[4] = {rank_key(sv.x), rank_key(sv.y), rank_key(sv.z), rank_key(sv.w)};
-            const int c4[4] = {cv.x, cv.y, cv.z, cv.w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                if (i0 + e < nc) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        rk[u] += (v4[e] > vk[u] || (v4[e] == vk[u] && c4[e] < ck[u])) ? 1 : 0;
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int k = t + 16 * u;
-            if (k < nc && rk[u] < K) {
-                L.q[rk[u]] = ck[u];
-                L.bq[rk[u]] = L.b[k];
-            }
-        }
-    }
-    __syncthreads();
-    if (K <= kGJ) {
-        solve_q_gj(on, t, K, N, G32, L);
+        if (on && t < n) sol[t] = R0[kGJ] / dg0;
+        if (on && t + 16 < n) sol[t + 16] = R1[kGJ] / dg1;
+        __syncthreads();
         return;
     }
-    // all Gram entries of G[q,q] (lower triangle) in one batch of loads:
-    // entry (r, i), i <= r, goes to C[tri(r) + i]; the diagonal is also kept
-    // in sq (the pivot floors), which the back substitution overwrites last
-    float* C = L.Wq;
+    // all Gram entries of G[L,L] (lower triangle) in one batch of loads:
+    // entry (r, i), i <= r, goes to C[tri(r) + i] (identity beyond n); the
+    // diagonal is also kept in sol (the pivot floors), which the back
+    // substitution overwrites last
+    float* C = scr;
     if (on) {
-        const int TK = tri(K);
+        const int TK = tri(nmax);
         for (int e0 = 0; e0 < TK; e0 += 64) {
             float v[4];
             int dst[4], row[4];
@@ -406,7 +420,7 @@ __device__ __forceinline__ void prune_to_q(bool on, int t, int nc, int K, int N,
                     while (tri(r + 1) <= e) ++r;
                     while (tri(r) > e) --r;
                     const int i = e - tri(r);
-                    v[u] = G32[(size_t)clamp_atom(L.q[i], N) * N + clamp_atom(L.q[r], N)];
+                    v[u] = r < n ? G32[(size_t)clamp_atom(L[i], N) * N + clamp_atom(L[r], N)] : (i == r ? 1.f : 0.f);
                     dst[u] = e;
                     row[u] = (i == r) ? r : -1;
                 }
@@ -414,20 +428,20 @@ __device__ __forceinline__ void prune_to_q(bool on, int t, int nc, int K, int N,
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (dst[u] >= 0) C[dst[u]] = v[u];
-                if (dst[u] >= 0 && row[u] >= 0) L.sq[row[u]] = v[u];
+                if (dst[u] >= 0 && row[u] >= 0) sol[row[u]] = v[u];
             }
         }
     }
     __syncthreads();
-    // LDL^T elimination with the forward substitution of b_q
-    for (int k = 0; k < K; ++k) {
+    // LDL^T elimination with the forward substitution of rhs
+    for (int k = 0; k < nmax; ++k) {
         if (on) {
             float piv = C[tri(k) + k];
-            const float fl = L.sq[k] * 5.9604645e-8f;
+            const float fl = sol[k] * 5.9604645e-8f;
             piv = piv > fl ? piv : fl;
             const float rp = 1.f / piv;
-            const float bk = L.bq[k];
-            for (int i = k + 1 + t; i < K; i += 16) {
+            const float bk = rhs[k];
+            for (int i = k + 1 + t; i < nmax; i += 16) {
                 float* ci = C + tri(i);
                 const float f = ci[k] * rp;
                 int j = k + 1;
@@ -440,21 +454,31 @@ __device__ __forceinline__ void prune_to_q(bool on, int t, int nc, int K, int N,
                     ci[j + 3] -= f * c3;
                 }
                 for (; j <= i; ++j) ci[j] -= f * C[tri(j) + k];
-                L.bq[i] -= f * bk;
+                rhs[i] -= f * bk;
             }
             if (t == 0) C[tri(k) + k] = piv;
         }
         __syncthreads();
     }
-    // back substitution: s_i = (bt_i - sum_{k>i} C_ki s_k) / D_i, column-oriented
-    for (int i = K - 1; i >= 0; --i) {
+    // back substitution: sol_i = (bt_i - sum_{k>i} C_ki sol_k) / D_i, column-oriented
+    for (int i = nmax - 1; i >= 0; --i) {
         if (on) {
-            const float si = L.bq[i] / C[tri(i) + i];
-            for (int k = t; k < i; k += 16) L.bq[k] -= C[tri(i) + k] * si;
-            if (t == 0) L.sq[i] = si;
+            const float si = rhs[i] / C[tri(i) + i];
+            for (int k = t; k < i; k += 16) rhs[k] -= C[tri(i) + k] * si;
+            if (t == 0) sol[i] = si;
         }
         __syncthreads();
     }
+}
+
+// Step 3 of Alg. 3 for the pixels with `on`: q = the K entries of c with
+// largest |s| (ties to the lower index), then s_q = G[q,q]^{-1} b_q.
+// Called by every lane (it holds barriers).
+__device__ __forceinline__ void prune_to_q(bool on, int t, int nc, int K, int N, const float* __restrict__ G32,
+                                           const PixLds L) {
+    rank_top(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+    __syncthreads();
+    solve_list<false>(on, t, K, K, N, G32, L.q, L.bq, L.sq, L.Wq);
 }
 
 // r = y - sum_k xv[k] A[:, xi[k]] for the lane's m = 4t + j + 64i.
@@ -738,8 +762,345 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
     }
 }
 
+// ------------------------------------------------------------ CoSaMP and BIHT on chip
+//
+// The same wave / lane / LDS organisation as gOMP.  Per iteration, for each
+// active pixel (Alg. 5, Alg. 4 and the one-bit variant):
+//   1. p = A^T v on MFMA, with v = r (CoSaMP, BIHT) or v = y - sgn(A x)
+//      (one-bit); u = p (CoSaMP) or u = x + mu p (BIHT, one-bit); the first
+//      iteration's p = A^T y is kept in LDS as the least-squares right-hand
+//      side of every atom.
+//   2. Theta = the 2K (CoSaMP) or K (BIHT) largest |u|, ties to the lower
+//      index, by rounds of a 16-lane argmax.
+//   3. c = Theta U (previous kept support: CoSaMP all of it, BIHT its nonzero
+//      entries); s = G[c,c]^{-1} (A^T y)_c (solve_list, list lengths padded
+//      to the wave's largest); keep the K largest |s| with their values and
+//      no second solve.  One-bit: x = u on Theta.
+//   4. r = y - A x, Delta, stop (CoSaMP, BIHT); one-bit: v = y - sgn(A x).
+
+struct OtherPlan {
+    int rb, ball, c, b, s, scr, sel, selv, q, sq, total;
+};
+
+__host__ __device__ inline int other_nc(int kind, int K) {
+    return kind == GREEDY_COSAMP ? 3 * K : (kind == GREEDY_BIHT ? 2 * K : 0);
+}
+
+__host__ __device__ inline OtherPlan other_plan(int kind, int MP, int N, int K) {
+    const int nc = other_nc(kind, K);
+    const int nsel = kind == GREEDY_COSAMP ? 2 * K : K;
+    OtherPlan p;
+    int o = 0;
+    p.rb = o; o += up4(MP);
+    p.ball = o; o += nc > 0 ? up4(N) : 0;
+    p.c = o; o += up4(nc);
+    p.b = o; o += up4(nc);
+    p.s = o; o += up4(nc);
+    p.scr = o; o += nc == 0 ? 0 : (nc > kGJ ? up4(tri(nc)) : 2 * (kGJ + 4));
+    p.sel = o; o += up4(nsel);
+    p.selv = o; o += up4(nsel);
+    p.q = o; o += up4(K);
+    p.sq = o; o += up4(K);
+    o += ((8 - o) % 64 + 64) % 64;
+    p.total = o;
+    return p;
+}
+
+template <int KIND, int MSLOT, int NG>
+__device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, float* lds) {
+    constexpr int NV = 4 * NG;   // atoms per lane: 4 NG t + k, k < NV
+    const int lane = threadIdx.x;
+    const int x = lane & 3, t = lane >> 2;
+    const int64_t local = block * kGroups + x;
+    const int64_t pix = a.p0 + local;
+    const bool valid = local < a.P;
+    const int M = a.M, N = a.N, K = a.K, MP = a.MP;
+    const OtherPlan pl = other_plan(KIND, MP, N, K);
+    float* base = lds + x * a.lds_floats;
+    float* rb = base + pl.rb;
+    float* ball = base + pl.ball;
+    int* c = reinterpret_cast<int*>(base + pl.c);
+    float* b = base + pl.b;
+    float* sv = base + pl.s;
+    float* scr = base + pl.scr;
+    int* sel = reinterpret_cast<int*>(base + pl.sel);
+    float* selv = base + pl.selv;
+    int* q = reinterpret_cast<int*>(base + pl.q);
+    float* sq = base + pl.sq;
+    const int nsel = KIND == GREEDY_COSAMP ? 2 * K : K;
+
+    // y (one-bit: the signs) and the vector v that is correlated
+    float y[MSLOT], v[MSLOT];
+    bool bad = false;
+#pragma unroll
+    for (int u = 0; u < MSLOT; ++u) {
+        const int m = 4 * t + (u & 3) + 64 * (u >> 2);
+        float w = 0.f;
+        if (valid && m < M) {
+            w = KIND == GREEDY_BIHT_ONE_BIT ? (float)a.Ysign[pix * M + m] : a.Y[pix * M + m];
+            if (!isfinite(w)) bad = true;
+        }
+        y[u] = w;
+    }
+    int badi = bad ? 1 : 0;
+    badi |= __shfl_xor(badi, 4);
+    badi |= __shfl_xor(badi, 8);
+    badi |= __shfl_xor(badi, 16);
+    badi |= __shfl_xor(badi, 32);
+    bad = badi != 0;
+    float y2 = 0.f;
+#pragma unroll
+    for (int u = 0; u < MSLOT; ++u) {
+        if (bad) y[u] = 0.f;
+        v[u] = y[u];
+        y2 += y[u] * y[u];
+    }
+    y2 = pix_sum(y2);
+    const float ynorm = sqrtf(y2);
+
+    bool active = valid && !bad;
+    bool converged = false;
+    int iters = 0, nq = 0;
+    float last_d2 = __builtin_nanf(""), rn2 = y2;
+    const int M8 = (M + kRowPad - 1) / kRowPad * kRowPad;
+
+    for (int it = 1; it <= a.Imax; ++it) {
+        // ---------------- step 1: p = A^T v on MFMA, u
+#pragma unroll
+        for (int u = 0; u < MSLOT; ++u) {
+            const int m = 4 * t + (u & 3) + 64 * (u >> 2);
+            if (m < MP) rb[m] = v[u];
+        }
+        __syncthreads();
+        v4f_t acc[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) acc[g] = v4f_t{0.f, 0.f, 0.f, 0.f};
+        {
+            typedef float vNG __attribute__((ext_vector_type(NG)));
+            const vNG* ap = reinterpret_cast<const vNG*>(a.Ap) + lane;
+            vNG cur[kRowPad], nxt[kRowPad];
+#pragma unroll
+            for (int r8 = 0; r8 < kRowPad; ++r8) cur[r8] = ap[(size_t)r8 * 64];
+            for (int m0 = 0; m0 < M8; m0 += kRowPad) {
+                if (m0 + kRowPad < M8) {
+#pragma unroll
+                    for (int r8 = 0; r8 < kRowPad; ++r8) nxt[r8] = ap[(size_t)(m0 + kRowPad + r8) * 64];
+                }
+                const float4 r0 = *reinterpret_cast<const float4*>(rb + m0);
+                const float4 r1 = *reinterpret_cast<const float4*>(rb + m0 + 4);
+                const float rv[kRowPad] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+                for (int r8 = 0; r8 < kRowPad; ++r8)
+#pragma unroll
+                    for (int g = 0; g < NG; ++g)
+                        acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(cur[r8][g], rv[r8], acc[g], 0, 0, 0);
+#pragma unroll
+                for (int r8 = 0; r8 < kRowPad; ++r8) cur[r8] = nxt[r8];
+            }
+        }
+        float u[NV];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const float p = acc[g][i];
+                u[NG * i + g] = KIND == GREEDY_COSAMP ? p : a.mu * p;
+            }
+        if (KIND != GREEDY_COSAMP && nq > 0) {
+            // u = x + mu p: add the kept values to the lanes holding their atoms
+            for (int kk = 0; kk < nq; ++kk) {
+                const int j = q[kk] - NV * t;
+                const float xv = sq[kk];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) u[k] += (j == k) ? xv : 0.f;
+            }
+        }
+        if (it == 1 && KIND != GREEDY_BIHT_ONE_BIT) {
+            // r = y in the first iteration, so p = A^T y: the right-hand sides
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    const int n = NV * t + NG * i + g;
+                    if (n < N) ball[n] = acc[g][i];
+                }
+        }
+        // ---------------- step 2: the nsel largest |u| (no membership mask)
+        uint32_t taken = 0u;
+        int nsl = 0;
+        for (int qq = 0; qq < nsel; ++qq) {
+            float bv = -1.f;
+            int bi = -1;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                const int n = NV * t + k;
+                const float w = fabsf(u[k]);
+                if (n < N && !((taken >> k) & 1u) && (bi < 0 || w > bv)) {
+                    bv = w;
+                    bi = n;
+                }
+            }
+            pix_argmax(bv, bi);
+            if (bi >= 0 && bi / NV == t) {
+                const int k0 = bi - NV * t;
+                taken |= 1u << k0;
+                float uv = 0.f;
+#pragma unroll
+                for (int k = 0; k < NV; ++k) uv = (k == k0) ? u[k] : uv;
+                selv[qq] = uv;
+            }
+            if (t == 0) sel[qq] = bi;
+            nsl += (bi >= 0) ? 1 : 0;
+        }
+        __syncthreads();
+        if (KIND == GREEDY_BIHT_ONE_BIT) {
+            // x = H_K(u), then v = y - sgn(A x)
+            if (active) {
+                for (int k = t; k < nsl; k += 16) {
+                    q[k] = sel[k];
+                    sq[k] = selv[k];
+                }
+                nq = nsl;
+            }
+            __syncthreads();
+            if (active) {
+                const float zero[MSLOT] = {};
+                float ax[MSLOT];
+                residual<MSLOT>(zero, ax, q, sq, nq, a.AT, MP, N, t);   // ax = -A x
+                float d2 = 0.f, n2 = 0.f;
+#pragma unroll
+                for (int uu = 0; uu < MSLOT; ++uu) {
+                    const int m = 4 * t + (uu & 3) + 64 * (uu >> 2);
+                    const float sg = ax[uu] < 0.f ? 1.f : (ax[uu] > 0.f ? -1.f : 0.f);   // sgn(A x)
+                    const float vn = m < M ? y[uu] - sg : 0.f;
+                    const float dl = vn - v[uu];
+                    d2 += dl * dl;
+                    n2 += vn * vn;
+                    v[uu] = vn;
+                }
+                d2 = pix_sum(d2);
+                n2 = pix_sum(n2);
+                iters = it;
+                last_d2 = d2;
+                rn2 = n2;
+            }
+            __syncthreads();
+            continue;
+        }
+        // ---------------- step 3: c = Theta U previous support; least squares; keep K
+        int nc = 0;
+        if (active) {
+            for (int k = t; k < nsl; k += 16) c[k] = sel[k];
+            // previous support entries not in Theta, appended in their order
+            bool keep[4];
+#pragma unroll
+            for (int u2 = 0; u2 < 4; ++u2) {
+                const int kk = t + 16 * u2;
+                bool kp = kk < nq && (KIND == GREEDY_COSAMP || sq[kk] != 0.f);
+                if (kp) {
+                    const int j = q[kk];
+                    for (int i = 0; i < nsl; ++i) kp = kp && (sel[i] != j);
+                }
+                keep[u2] = kp;
+            }
+            int total = 0;
+#pragma unroll
+            for (int u2 = 0; u2 < 4; ++u2) {
+                const uint64_t bal = __ballot(keep[u2]);
+                uint64_t mine = 0;   // this pixel's lanes (x, x + 4, ...), compacted to bit t
+#pragma unroll
+                for (int tt = 0; tt < 16; ++tt) mine |= ((bal >> (4 * tt + x)) & 1ull) << tt;
+                const int below = __builtin_popcountll(mine & ((1ull << t) - 1ull));
+                if (keep[u2]) c[nsl + total + below] = q[t + 16 * u2];
+                total += __builtin_popcountll(mine);
+            }
+            nc = nsl + total;
+        }
+        __syncthreads();
+        if (active)
+            for (int k = t; k < nc; k += 16) b[k] = ball[clamp_atom(c[k], N)];
+        int nmax = nc;
+        nmax = max(nmax, __shfl_xor(nmax, 1));
+        nmax = max(nmax, __shfl_xor(nmax, 2));
+        solve_list<true>(active, t, nc, nmax, N, a.G32, c, b, sv, scr);
+        rank_top(active, t, nc, K, sv, c, sv, q, sq);
+        if (active) nq = nc < K ? nc : K;
+        __syncthreads();
+
+        // ---------------- step 4: residual r = y - A x, Delta, stop
+        if (active) {
+            float rnew[MSLOT];
+            residual<MSLOT>(y, rnew, q, sq, nq, a.AT, MP, N, t);
+            float d2 = 0.f, n2 = 0.f;
+#pragma unroll
+            for (int uu = 0; uu < MSLOT; ++uu) {
+                const float dl = rnew[uu] - v[uu];
+                d2 += dl * dl;
+                n2 += rnew[uu] * rnew[uu];
+                v[uu] = rnew[uu];
+            }
+            d2 = pix_sum(d2);
+            n2 = pix_sum(n2);
+            iters = it;
+            last_d2 = d2;
+            rn2 = n2;
+            if (sqrtf(n2) <= a.res_tol * ynorm || (a.eps > 0.f && sqrtf(d2) < a.eps)) {
+                active = false;
+                converged = true;
+            }
+        }
+        __syncthreads();
+        if (!__any(active)) break;
+    }
+
+    if (!valid) return;
+    // ---------------- outputs: x (dense row; one-bit scaled to unit norm), support ascending, stats
+    float scale = 1.f;
+    if (KIND == GREEDY_BIHT_ONE_BIT) {
+        float x2 = 0.f;
+        for (int k = 0; k < nq; ++k) x2 += sq[k] * sq[k];
+        scale = x2 > 0.f ? 1.f / sqrtf(x2) : 0.f;
+    }
+    float* xrow = a.X + pix * N;
+    for (int n = t; n < N; n += 16) {
+        float w = 0.f;
+        for (int k = 0; k < nq; ++k) w = (q[k] == n) ? sq[k] : w;
+        xrow[n] = bad ? 0.f : w * scale;
+    }
+    if (a.support) {
+        int32_t* srow = a.support + pix * K;
+        // CoSaMP lists its kept atoms; BIHT the nonzero entries of x
+        const bool all = KIND == GREEDY_COSAMP;
+        int cnt = 0;
+        for (int k = 0; k < nq; ++k) cnt += (all || sq[k] != 0.f) ? 1 : 0;
+        for (int k = t; k < K; k += 16)
+            if (k >= cnt || bad) srow[k] = -1;
+        for (int k = t; k < nq && !bad; k += 16) {
+            if (!(all || sq[k] != 0.f)) continue;
+            const int ck = q[k];
+            int pos = 0;
+            for (int i = 0; i < nq; ++i) pos += ((all || sq[i] != 0.f) && q[i] < ck) ? 1 : 0;
+            if (pos < K) srow[pos] = ck;
+        }
+    }
+    if (a.stats && t == 0) {
+        csrec_pixel_stats st;
+        st.iters = bad ? 0 : iters;
+        st.flags = bad ? CSREC_FLAG_NONFINITE : (converged ? CSREC_FLAG_CONVERGED : CSREC_FLAG_ITER_CAP);
+        st.resid = bad ? 0.f : sqrtf(rn2);
+        st.delta = sqrtf(last_d2);
+        a.stats[pix] = st;
+    }
+}
+
+template <int KIND, int MSLOT, int NG>
+__global__ __launch_bounds__(64, 2) void other_coop_kernel(CoopArgs a) {
+    extern __shared__ float lds[];
+    other_body<KIND, MSLOT, NG>(a, blockIdx.x, lds);
+}
+
 template <int MSLOT, int NG>
-__global__ __launch_bounds__(64) void gomp_coop_kernel(CoopArgs a) {
+__global__ __launch_bounds__(64, 2) void gomp_coop_kernel(CoopArgs a) {
     extern __shared__ float lds[];
     gomp_coop_body<MSLOT, NG>(a, blockIdx.x, lds);
 }
@@ -751,7 +1112,7 @@ struct CoopItem {
 
 // Grouped launch: blocks [items[i].block0, items[i+1].block0) solve item i.
 template <int MSLOT, int NG>
-__global__ __launch_bounds__(64) void gomp_coop_grouped_kernel(const CoopItem* __restrict__ items, int nitems) {
+__global__ __launch_bounds__(64, 2) void gomp_coop_grouped_kernel(const CoopItem* __restrict__ items, int nitems) {
     extern __shared__ float lds[];
     int it = 0;
     while (it + 1 < nitems && items[it + 1].block0 <= (int64_t)blockIdx.x) ++it;
@@ -809,6 +1170,8 @@ void fill_args(CoopArgs& a, const float* dictbuf, int M, int N, int K, int S, in
     a.pivot_thr = pivot_thr;
     a.CM = S * Imax;
     a.lds_floats = (int)gomp_coop_lds_floats(a.MP, a.CM, K);
+    a.mu = 0.f;
+    a.Ysign = nullptr;
 }
 
 }  // namespace
@@ -851,6 +1214,55 @@ int gomp_coop_launch(const float* Y, float* X, int32_t* support, csrec_pixel_sta
     const size_t lds = (size_t)kGroups * a.lds_floats * sizeof(float);
     const int64_t blocks = ceil_div(P, kGroups);
     const coop_kernel_t fn = pick_coop(a.MP, a.NP / 64);
+    CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds));
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64), lds, stream, a);
+    CSREC_HIP_TRY(hipGetLastError());
+    return CSREC_OK;
+}
+
+typedef void (*other_kernel_t)(CoopArgs);
+
+template <int KIND>
+other_kernel_t pick_other_k(int MP, int NG) {
+    if (MP == 64) return NG == 2 ? other_coop_kernel<KIND, 4, 2> : other_coop_kernel<KIND, 4, 4>;
+    return NG == 2 ? other_coop_kernel<KIND, 8, 2> : other_coop_kernel<KIND, 8, 4>;
+}
+
+size_t coop_other_lds_floats(int kind, int M, int N, int K) {
+    return (size_t)other_plan(kind, gomp_coop_mp(M), N, K).total;
+}
+
+int coop_other_supported(int kind, int M, int N, int K) {
+    if (N > 64 * kMaxNG || M > 128) return CSREC_E_UNSUPPORTED;
+    if (kind == GREEDY_COSAMP ? 2 * K > 64 : K > 64) return CSREC_E_UNSUPPORTED;   // selection bits per lane
+    const size_t lds = kGroups * coop_other_lds_floats(kind, M, N, K) * sizeof(float);
+    return lds <= 160 * 1024 ? CSREC_OK : CSREC_E_UNSUPPORTED;
+}
+
+int coop_other_launch(int kind, const float* Y, const int8_t* Ysign, float* X, int32_t* support,
+                      csrec_pixel_stats* stats, const float* G32, const float* dictbuf, int M, int N, int64_t p0,
+                      int64_t P, int K, int Imax, float mu, float res_tol, float eps, hipStream_t stream) {
+    if (P == 0) return CSREC_OK;
+    CoopArgs a;
+    fill_args(a, dictbuf, M, N, K, 1, Imax, 0, res_tol, eps, 0.0);
+    a.lds_floats = (int)coop_other_lds_floats(kind, M, N, K);
+    a.Y = Y;
+    a.Ysign = Ysign;
+    a.mu = mu;
+    a.G32 = G32;
+    a.X = X;
+    a.support = support;
+    a.stats = stats;
+    a.fbflag = nullptr;
+    a.P = P;
+    a.p0 = p0;
+    const size_t lds = (size_t)kGroups * a.lds_floats * sizeof(float);
+    const int64_t blocks = ceil_div(P, kGroups);
+    const int NG = a.NP / 64;
+    other_kernel_t fn = kind == GREEDY_COSAMP ? pick_other_k<GREEDY_COSAMP>(a.MP, NG)
+                        : kind == GREEDY_BIHT ? pick_other_k<GREEDY_BIHT>(a.MP, NG)
+                                              : pick_other_k<GREEDY_BIHT_ONE_BIT>(a.MP, NG);
     CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds));
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64), lds, stream, a);

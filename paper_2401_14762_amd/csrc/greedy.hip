@@ -690,6 +690,11 @@ struct Layout {
 
 constexpr int64_t kChunk = 65536;
 
+// CoSaMP and both BIHT forms run on the on-chip design when it fits.
+bool coop_other(const GreedyLaunch& a) {
+    return a.kind != GREEDY_GOMP && coop_other_supported(a.kind, a.M, a.N, a.K) == CSREC_OK;
+}
+
 Layout layout_for(const GreedyLaunch& a, int64_t ch_override = 0) {
     Layout L;
     int CM = 0, LM = 1;
@@ -713,11 +718,11 @@ Layout layout_for(const GreedyLaunch& a, int64_t ch_override = 0) {
     L.gram64 = align_up((size_t)a.N * a.N * 4, 256);
     size_t o = L.gram64 + (dbl ? align_up((size_t)a.N * a.N * 8, 256) : 0);
     L.off_AT = o;
-    if (a.kind == GREEDY_GOMP) o += align_up(gomp_coop_dict_floats(a.M, a.N) * 4, 256);
+    if (a.kind == GREEDY_GOMP || coop_other(a)) o += align_up(gomp_coop_dict_floats(a.M, a.N) * 4, 256);
     L.off_f = o;
     o += align_up((size_t)L.CH * 4, 256);
-    if (a.kind == GREEDY_GOMP && !dbl) {
-        // the on-chip gOMP kernel needs no per-pixel scratch
+    if ((a.kind == GREEDY_GOMP && !dbl) || coop_other(a)) {
+        // the on-chip kernels need no per-pixel scratch
         L.off_T = L.off_i = L.off_r = o;
         L.total = o;
         return L;
@@ -932,7 +937,16 @@ int greedy_launch(const GreedyLaunch& a) {
     }
     const bool coop = a.kind == GREEDY_GOMP;   // gOMP's FP32 pass keeps its state on chip
     float* dictbuf = reinterpret_cast<float*>(ws + L.off_AT);
-    if (coop) gomp_coop_prepare(a.A, a.M, a.N, dictbuf, a.stream);
+    if (coop || coop_other(a)) gomp_coop_prepare(a.A, a.M, a.N, dictbuf, a.stream);
+    if (coop_other(a)) {
+        for (int64_t p0 = 0; p0 < a.P; p0 += L.CH) {
+            const int64_t np = (a.P - p0) < L.CH ? (a.P - p0) : L.CH;
+            const int e = coop_other_launch(a.kind, a.Y, a.Ysign, a.X, a.support, a.stats, g.G32, dictbuf, a.M, a.N,
+                                            p0, np, a.K, a.max_iter, a.mu, a.res_tol, a.eps, a.stream);
+            if (e) return e;
+        }
+        return CSREC_OK;
+    }
     for (int64_t p0 = 0; p0 < a.P; p0 += L.CH) {
         const int64_t np = (a.P - p0) < L.CH ? (a.P - p0) : L.CH;
         const int64_t blocks = ceil_div(np, threads);

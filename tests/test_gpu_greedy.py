@@ -188,3 +188,67 @@ def test_biht_one_bit_subset(torch, other):
     assert rel_err_rows(X[clean], ref["X"][clean]).max() <= TOL
     nrm = np.linalg.norm(X, axis=1)
     assert np.allclose(nrm[nrm > 0], 1.0, atol=1e-5)
+
+
+# CoSaMP / BIHT on chip: both least-squares paths (merged support <= 32 on
+# registers, > 32 by LDL^T in LDS), both atom groupings (N <= 128, N > 128),
+# both residual layouts (M <= 64, M > 64), ragged pixel counts.
+def _sparse_case(N, K, P, seed, snr_db=30.0):
+    M = W.m_for(N)
+    a64, a32, _, _ = W.dictionary(N, M, seed)
+    rng = np.random.default_rng(seed)
+    X = np.zeros((P, N))
+    for p in range(P):
+        X[p, rng.choice(N, K, replace=False)] = rng.standard_normal(K)
+    Y0 = X @ a64.T
+    pw = np.sum(Y0 * Y0, axis=1, keepdims=True) / (M * 10.0 ** (snr_db / 10.0))
+    Y = (Y0 + np.sqrt(pw) * rng.standard_normal(Y0.shape)).astype(np.float32)
+    sign = np.where(Y0 >= 0.0, 1, -1).astype(np.int8)
+    return a32, Y, sign
+
+
+@pytest.mark.parametrize("N,K,P", [(100, 8, 65), (100, 12, 1), (200, 10, 300), (224, 13, 129)])
+def test_cosamp_shapes(torch, N, K, P):
+    import paper_2401_14762_amd as cs
+    A, Y, _ = _sparse_case(N, K, P, 40 + N + K)
+    note(f"cosamp N={N} K={K} P={P}")
+    X, S, st = cs.cosamp(to_dev(torch, A), to_dev(torch, Y), K=K, max_iter=12)
+    torch.cuda.synchronize()
+    ref = oracle.cosamp(A, Y, K=K, max_iter=12, diagnostics=True)
+    _compare(np_of(X), np_of(S), {k: np_of(v) for k, v in st.items()}, ref, K, _cosamp_flags(ref),
+             f"cosamp N={N} K={K}", min_clean=0.5)
+
+
+@pytest.mark.parametrize("N,K,P", [(100, 8, 65), (200, 20, 200), (224, 17, 33)])
+def test_biht_shapes(torch, N, K, P):
+    import paper_2401_14762_amd as cs
+    A, Y, sign = _sparse_case(N, K, P, 70 + N + K)
+    note(f"biht N={N} K={K} P={P}")
+    X, S, st = cs.biht(to_dev(torch, A), to_dev(torch, Y), K=K, max_iter=15, mu=0.1)
+    torch.cuda.synchronize()
+    ref = oracle.biht(A, Y, K=K, max_iter=15, mu=0.1, diagnostics=True)
+    _compare(np_of(X), np_of(S), {k: np_of(v) for k, v in st.items()}, ref, K, _cosamp_flags(ref),
+             f"biht N={N} K={K}", min_clean=0.5)
+    note(f"biht one-bit N={N} K={K} P={P}")
+    X1, S1, _ = cs.biht(to_dev(torch, A), None, K=K, max_iter=30, mu=0.1, mode="one_bit",
+                        Ysign=to_dev(torch, sign))
+    torch.cuda.synchronize()
+    ref1 = oracle.biht_one_bit(A, sign, K=K, max_iter=30, mu=0.1, diagnostics=True)
+    clean = ~((ref1["sel_gap"] < GAP) | (ref1["sign_margin"] < 1e-5))
+    same = np.array([a == b for a, b in zip(_support_rows(np_of(S1)), _support_rows(ref1["support"]))])
+    assert np.all(same[clean])
+    assert rel_err_rows(np_of(X1)[clean], ref1["X"][clean]).max() <= TOL if clean.any() else True
+
+
+def test_cosamp_biht_nonfinite(torch):
+    import paper_2401_14762_amd as cs
+    A, Y, _ = _sparse_case(200, 10, 20, 5)
+    Y[3, 7] = np.inf
+    note("cosamp / biht nonfinite pixel")
+    for name, fn in (("cosamp", lambda: cs.cosamp(to_dev(torch, A), to_dev(torch, Y), K=10, max_iter=5)),
+                     ("biht", lambda: cs.biht(to_dev(torch, A), to_dev(torch, Y), K=10, max_iter=5))):
+        X, S, st = fn()
+        torch.cuda.synchronize()
+        X, S, fl = np_of(X), np_of(S), np_of(st["flags"])
+        assert np.all(X[3] == 0) and np.all(S[3] == -1) and fl[3] == oracle.STOP_NONFINITE, name
+        assert np.all(np.isfinite(X)), name
