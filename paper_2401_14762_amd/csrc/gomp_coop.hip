@@ -105,7 +105,7 @@ __device__ __forceinline__ void pix_argmax(float& v, int& i) {
 // Per-pixel LDS carving (floats; index arrays stored as int bit patterns).
 // Every array starts on a 16-byte boundary.
 struct PixLds {
-    float* rb;    // residual, MP (read as the MFMA B operand)
+    float* rb;    // residual, MP (read as the MFMA B operand); aliases l, sel, bsel, Wq
     float* W;     // inverse factor of G[c,c], tri(CM); slot of row n holds G[c, j] before its append
     float* z;     // W b_c, CM
     float* b;     // b_c, CM
@@ -125,20 +125,25 @@ struct LdsPlan {
 };
 
 // Offsets (floats) of one pixel's region; the stride is padded to 8 mod 64
-// floats so that the 4 pixels' packed-row reads fall in distinct banks.
+// floats so that the 4 pixels' packed-row reads fall in distinct banks.  The
+// residual (read by the correlation only) shares its space with the
+// temporaries that are live only after the correlation: the selections, the
+// append temporary l and the prune's scratch.
 __host__ __device__ inline LdsPlan lds_plan(int MP, int CM, int K) {
     LdsPlan p;
     int o = 0;
-    p.rb = o; o += up4(MP);
+    p.rb = o;
+    p.l = o;
+    p.sel = p.l + up4(CM);
+    p.bsel = p.sel + kMaxS;
+    p.Wq = p.bsel + kMaxS;
+    const int tail = p.Wq + (K > kGJ ? up4(tri(K)) : 2 * (kGJ + 4));
+    o = up4(MP) > tail ? up4(MP) : tail;
     p.W = o; o += up4(tri(CM));
     p.z = o; o += up4(CM);
     p.b = o; o += up4(CM);
     p.s = o; o += up4(CM);
-    p.l = o; o += up4(CM);
     p.c = o; o += up4(CM);
-    p.sel = o; o += kMaxS;
-    p.bsel = o; o += kMaxS;
-    p.Wq = o; o += K > kGJ ? up4(tri(K)) : 2 * (kGJ + 4);
     p.bq = o; o += up4(K);
     p.sq = o; o += up4(K);
     p.q = o; o += up4(K);
@@ -791,14 +796,18 @@ __host__ __device__ inline OtherPlan other_plan(int kind, int MP, int N, int K) 
     const int nsel = kind == GREEDY_COSAMP ? 2 * K : K;
     OtherPlan p;
     int o = 0;
-    p.rb = o; o += up4(MP);
+    // the residual (read by the correlation only) shares its space with the
+    // selections and the solve scratch, live only after the correlation
+    p.rb = o;
+    p.sel = o;
+    p.selv = p.sel + up4(nsel);
+    p.scr = p.selv + up4(nsel);
+    const int tail = p.scr + (nc == 0 ? 0 : (nc > kGJ ? up4(tri(nc)) : 2 * (kGJ + 4)));
+    o = up4(MP) > tail ? up4(MP) : tail;
     p.ball = o; o += nc > 0 ? up4(N) : 0;
     p.c = o; o += up4(nc);
     p.b = o; o += up4(nc);
     p.s = o; o += up4(nc);
-    p.scr = o; o += nc == 0 ? 0 : (nc > kGJ ? up4(tri(nc)) : 2 * (kGJ + 4));
-    p.sel = o; o += up4(nsel);
-    p.selv = o; o += up4(nsel);
     p.q = o; o += up4(K);
     p.sq = o; o += up4(K);
     o += ((8 - o) % 64 + 64) % 64;
