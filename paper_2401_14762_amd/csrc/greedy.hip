@@ -1,24 +1,22 @@
-// Greedy solvers -- gOMP (Alg. 3), BIHT (Alg. 4), CoSaMP (Alg. 5) and
-// binary IHT on sign measurements -- for P independent pixels sharing A.
+// gOMP (Alg. 3) redone in FP64 for the pixels whose FP32 least squares met a
+// pivot ratio below pivot_fallback, plus the launch logic of every greedy
+// solver (gOMP, CoSaMP, BIHT).  The FP32 solves themselves run on the on-chip
+// kernels of gomp_coop.hip; this file holds their workspace layout, the Gram
+// matrix, the grouped (serving) launches and the FP64 redo.
 //
-// Work decomposition.  One lane owns one pixel and runs the algorithm's
-// steps in the paper's order.  A^T sits in LDS (row n holds column n of A,
-// padded to MMAX values) and is read two ways: the correlation A^T r loops
-// over n with every lane reading the same row (an LDS broadcast), and the
-// residual y - A x gathers the rows of the lane's own support.  The residual
-// r stays in VGPRs.  The least-squares state -- the Cholesky factor of the
-// Gram submatrix G[c, c] (G = A^T A), forward/back substitution vectors,
-// supports, candidate lists -- lives in a per-pixel scratch region laid out
-// [entry][pixel], so that every scratch access of a wavefront is one
-// contiguous 256-byte transaction.
-//
-// Least squares.  s = B^+ y with B = A(:, c) is solved through the normal
-// equations G[c, c] s = A(:, c)^T y with a Cholesky factor L (G[c,c] = L L^T):
-// gOMP appends its S new atoms to L column by column (bordered update), the
-// others factor G[c, c] afresh.  The squared pivot of an appended atom j is
-// d_j = G_jj - ||l||^2, the squared distance of a_j from span(A(:, c));
-// d_j / G_jj < pivot_fallback marks the pixel, which is then solved again
-// with the same code in FP64 (second pass, T = double).
+// FP64 redo.  One lane owns one pixel and runs the algorithm's steps in the
+// paper's order.  A^T sits in LDS (row n holds column n of A, padded to MMAX
+// values) and is read two ways: the correlation A^T r loops over n with every
+// lane reading the same row (an LDS broadcast), and the residual y - A x
+// gathers the rows of the lane's own support.  The residual r stays in
+// VGPRs.  The least-squares state -- the Cholesky factor of the Gram
+// submatrix G[c, c] (G = A^T A), forward/back substitution vectors, supports
+// -- lives in a per-pixel scratch region laid out [entry][pixel], so that
+// every scratch access of a wavefront is one contiguous 256-byte
+// transaction.  s = B^+ y with B = A(:, c) is solved through the normal
+// equations G[c, c] s = A(:, c)^T y with a Cholesky factor L (G[c,c] = L L^T)
+// to which the S new atoms of an iteration are appended column by column
+// (bordered update), in FP64 throughout, right-hand sides included.
 #include "common.hpp"
 
 #include <cmath>
@@ -30,14 +28,13 @@ namespace {
 struct GArgs {
     const float* A;
     const float* Y;
-    const int8_t* Ysign;
     float* X;
     int32_t* support;
     csrec_pixel_stats* stats;
     const float* G32;      // N x N Gram, FP32
     const double* G64;     // N x N Gram, FP64 (fallback pass)
     int M, N, K, S, Imax, prune;
-    float res_tol, eps, mu;
+    float res_tol, eps;
     double pivot_thr;
     // scratch
     char* scr;             // base of the chunk scratch
@@ -73,8 +70,7 @@ struct Scratch {
     Col<T> L, dinv, z, sv;   // factor (packed rows), 1/L_kk, L^{-1} b, solution
     Col<float> ball;         // b = A^T y, N entries
     float* rold;             // previous residual, MMAX contiguous entries of this lane
-    Col<float> lval;         // candidate list values
-    Col<int> lidx;           // candidate list indices
+    Col<int> lidx;           // prune list (positions in c)
     Col<int> cidx;           // support c (CM)
     Col<int> xidx;           // support of x (CM)
     Col<float> xval;         // values of x (CM)
@@ -85,7 +81,7 @@ struct Scratch {
 __device__ __forceinline__ int tri(int k) { return k * (k + 1) / 2; }
 
 // T-region layout (entries per pixel): L: CM(CM+1)/2, dinv: CM, z: CM, sv: CM
-// 32-bit region: ball N, lval LM, lidx LM, cidx CM, xidx CM, xval CM, mask NW, keep NW
+// 32-bit region: ball N, lidx LM, cidx CM, xidx CM, xval CM, mask NW, keep NW
 template <typename T>
 __device__ Scratch<T> make_scratch(const GArgs& g, int64_t local, int mmax) {
     Scratch<T> s;
@@ -101,7 +97,6 @@ __device__ Scratch<T> make_scratch(const GArgs& g, int64_t local, int mmax) {
     int* nb = reinterpret_cast<int*>(ib);
     int64_t q = 0;
     s.ball = {fb, q, CH}; q += g.N;
-    s.lval = {fb, q, CH}; q += g.LM;
     s.lidx = {nb, q, CH}; q += g.LM;
     s.cidx = {nb, q, CH}; q += g.CM;
     s.xidx = {nb, q, CH}; q += g.CM;
@@ -143,27 +138,6 @@ template <>
 __device__ __forceinline__ float tsqrt<float>(float v) { return sqrtf(v); }
 template <>
 __device__ __forceinline__ double tsqrt<double>(double v) { return sqrt(v); }
-
-// Insert (v, n) into the descending list of length len (capacity cap).
-// Equal values keep the earlier (lower) index first; n increases over calls.
-__device__ __forceinline__ void list_insert(const Col<float>& lv, const Col<int>& li, int& len, int cap,
-                                            float& thr, float v, int n) {
-    if (len == cap && !(v > thr)) return;
-    int pos = (len < cap) ? len : cap - 1;
-    while (pos > 0) {
-        const float pv = lv[pos - 1];
-        if (!(v > pv)) break;
-        if (pos < cap) {
-            lv[pos] = pv;
-            li[pos] = li[pos - 1];
-        }
-        --pos;
-    }
-    lv[pos] = v;
-    li[pos] = n;
-    if (len < cap) ++len;
-    thr = lv[cap - 1 < len - 1 ? cap - 1 : len - 1];
-}
 
 // Append atom j to the factor of G[c, c] (c = cidx[0 .. nc-1]):
 //   l = L^{-1} G[c, j],  d = G_jj - ||l||^2,  L_new = [[L, 0], [l^T, sqrt(d)]]
@@ -272,7 +246,7 @@ __device__ __forceinline__ int extract_bits(const Col<uint32_t>& bits, int NW, c
 // One workgroup of a solve: pixels p0 + block*blockDim + [0, blockDim) of the
 // problem in g (at most np of them), using scratch columns slot0 + the same
 // offsets.  Shared by the plain launch and the grouped (serving) launch.
-template <int KIND, int MMAX, int SMAX, typename T>
+template <int MMAX, int SMAX, typename T>
 __device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t np, int pass, int64_t block,
                                              int64_t slot0, float* sAT) {
     constexpr int PAT = MMAX + 4;
@@ -300,8 +274,7 @@ __device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t
     for (int m = 0; m < MMAX; ++m) {
         float v = 0.f;
         if (m < M) {
-            if (KIND == GREEDY_BIHT_ONE_BIT) v = (float)g.Ysign[pix * M + m];
-            else v = g.Y[pix * M + m];
+            v = g.Y[pix * M + m];
             if (!isfinite(v)) bad = true;
         }
         r[m] = v;
@@ -312,7 +285,7 @@ __device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t
     }
 #pragma unroll
     for (int m = 0; m < MMAX; ++m) ynorm2 += r[m] * r[m];
-    const float ynorm = sqrtf(ynorm2);   // (ONE_BIT: y - sgn(A 0) = y is the first "residual")
+    const float ynorm = sqrtf(ynorm2);
     for (int w = 0; w < NW; ++w) s.mask[w] = 0u;
 
     int nx = 0;          // entries in x (xidx/xval)
@@ -333,10 +306,6 @@ __device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t
             bv[q] = -1.f;
             bi[q] = -1;
         }
-        int llen = 0;
-        float lthr = -1.f;
-        const int lcap = (KIND == GREEDY_COSAMP) ? 2 * K : K;
-        int xptr = 0;
         uint32_t mword = 0u;
         for (int n = 0; n < N; ++n) {
             const float4* row = reinterpret_cast<const float4*>(sAT + n * PAT);
@@ -346,8 +315,8 @@ __device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t
                 const float4 a = row[m4];
                 acc += a.x * r[4 * m4] + a.y * r[4 * m4 + 1] + a.z * r[4 * m4 + 2] + a.w * r[4 * m4 + 3];
             }
-            if (it == 1 && KIND != GREEDY_BIHT_ONE_BIT) s.ball[n] = acc;   // A^T y
-            if (KIND == GREEDY_GOMP) {
+            if (it == 1) s.ball[n] = acc;   // A^T y
+            {
                 if ((n & 31) == 0) mword = s.mask[n >> 5];
                 if ((mword >> (n & 31)) & 1u) continue;
                 const float v = fabsf(acc);
@@ -367,24 +336,11 @@ __device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t
                         }
                     }
                 }
-            } else if (KIND == GREEDY_COSAMP) {
-                list_insert(s.lval, s.lidx, llen, lcap, lthr, fabsf(acc), n);
-            } else {
-                // u = x + mu A^T (.)  (BIHT REAL: residual; ONE_BIT: y - sgn(A x))
-                float xv = 0.f;
-                if (xptr < nx && s.xidx[xptr] == n) {
-                    xv = s.xval[xptr];
-                    ++xptr;
-                }
-                const float u = xv + g.mu * acc;
-                const float au = fabsf(u);
-                if (llen == lcap && !(au > lthr)) continue;
-                list_insert(s.lval, s.lidx, llen, lcap, lthr, au, n);
             }
         }
 
         // ---------------- steps 2-3: support and least squares
-        if (KIND == GREEDY_GOMP) {
+        {
             for (int q = 0; q < g.S; ++q) {
                 const int j = bi[q];
                 if (j < 0) break;   // no admissible atom left (non-finite correlations)
@@ -433,79 +389,16 @@ __device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t
                         }
                 }
             }
-        } else if (KIND == GREEDY_COSAMP || KIND == GREEDY_BIHT) {
-            // c = candidates U (current support of x)
-            for (int w = 0; w < NW; ++w) s.mask[w] = 0u;
-            for (int a = 0; a < llen; ++a) {
-                const int j = s.lidx[a];
-                s.mask[j >> 5] |= 1u << (j & 31);
-            }
-            for (int a = 0; a < nx; ++a) {
-                if (KIND == GREEDY_BIHT && s.xval[a] == 0.f) continue;   // supp(x_a)
-                const int j = s.xidx[a];
-                s.mask[j >> 5] |= 1u << (j & 31);
-            }
-            nc = extract_bits(s.mask, NW, s.cidx);
-            chol_solve_fresh<T>(g, s, nc, pix);
-            const int keepn = nc < K ? nc : K;
-            mark_top_k<T>(g, s, nc, keepn);
-            nx = 0;
-            for (int a = 0; a < nc; ++a) {
-                const int ia = s.cidx[a];
-                if ((s.keep[ia >> 5] >> (ia & 31)) & 1u) {
-                    s.xidx[nx] = ia;
-                    s.xval[nx] = (float)s.sv[a];
-                    ++nx;
-                }
-            }
-        } else {   // ONE_BIT: x = H_K(u), u values recomputed for the kept indices
-            // sort the kept indices ascending through the bitmask
-            for (int w = 0; w < NW; ++w) s.mask[w] = 0u;
-            for (int a = 0; a < llen; ++a) {
-                const int j = s.lidx[a];
-                s.mask[j >> 5] |= 1u << (j & 31);
-            }
-            // old x is needed to rebuild u on the kept indices: u_j = x_j + mu (A^T v)_j
-            int newn = 0;
-            int optr = 0;
-            // collect the new (index, value) pairs in the list slots
-            for (int w = 0; w < NW; ++w) {
-                uint32_t v = s.mask[w];
-                while (v) {
-                    const int b = __builtin_ctz(v);
-                    v &= v - 1;
-                    const int j = 32 * w + b;
-                    const float4* row = reinterpret_cast<const float4*>(sAT + j * PAT);
-                    float acc = 0.f;
-#pragma unroll
-                    for (int m4 = 0; m4 < MMAX / 4; ++m4) {
-                        const float4 a = row[m4];
-                        acc += a.x * r[4 * m4] + a.y * r[4 * m4 + 1] + a.z * r[4 * m4 + 2] +
-                               a.w * r[4 * m4 + 3];
-                    }
-                    float xv = 0.f;
-                    while (optr < nx && s.xidx[optr] < j) ++optr;
-                    if (optr < nx && s.xidx[optr] == j) xv = s.xval[optr];
-                    s.lidx[newn] = j;
-                    s.lval[newn] = xv + g.mu * acc;
-                    ++newn;
-                }
-            }
-            nx = newn;
-            for (int a = 0; a < nx; ++a) {
-                s.xidx[a] = s.lidx[a];
-                s.xval[a] = s.lval[a];
-            }
         }
 
-        // ---------------- step 4: residual r = y - A x (ONE_BIT: v = y - sgn(A x))
+        // ---------------- step 4: residual r = y - A x
 #pragma unroll
         for (int m = 0; m < MMAX; ++m) {
             s.rold[m] = r[m];
-            r[m] = (KIND == GREEDY_BIHT_ONE_BIT || m >= M || bad) ? 0.f : g.Y[pix * M + m];
+            r[m] = (m >= M || bad) ? 0.f : g.Y[pix * M + m];
         }
         for (int a = 0; a < nx; ++a) {
-            const float xv = (KIND == GREEDY_BIHT_ONE_BIT) ? -s.xval[a] : s.xval[a];
+            const float xv = s.xval[a];
             const float4* row = reinterpret_cast<const float4*>(sAT + s.xidx[a] * PAT);
 #pragma unroll
             for (int m4 = 0; m4 < MMAX / 4; ++m4) {
@@ -514,14 +407,6 @@ __device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t
                 r[4 * m4 + 1] -= av.y * xv;
                 r[4 * m4 + 2] -= av.z * xv;
                 r[4 * m4 + 3] -= av.w * xv;
-            }
-        }
-        if (KIND == GREEDY_BIHT_ONE_BIT) {
-#pragma unroll
-            for (int m = 0; m < MMAX; ++m) {
-                const float ax = r[m];
-                const float sg = ax > 0.f ? 1.f : (ax < 0.f ? -1.f : 0.f);
-                r[m] = (m < M) ? (float)g.Ysign[pix * M + m] - sg : 0.f;
             }
         }
         float d2 = 0.f, n2 = 0.f;
@@ -534,17 +419,15 @@ __device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t
         iters = it;
         last_d2 = d2;
         rn2 = n2;
-        if (KIND != GREEDY_BIHT_ONE_BIT) {
-            const bool stop = (sqrtf(n2) <= g.res_tol * ynorm) || (g.eps > 0.f && sqrtf(d2) < g.eps);
-            if (stop) {
-                converged = true;
-                break;
-            }
+        const bool stop = (sqrtf(n2) <= g.res_tol * ynorm) || (g.eps > 0.f && sqrtf(d2) < g.eps);
+        if (stop) {
+            converged = true;
+            break;
         }
     }
 
     // gOMP with the prune placed after the loop
-    if (KIND == GREEDY_GOMP && g.prune == CSREC_PRUNE_FINAL && nc > K) {
+    if (g.prune == CSREC_PRUNE_FINAL && nc > K) {
         mark_top_k<T>(g, s, nc, K);
         int nq = 0;
         for (int w = 0; w < NW; ++w) {
@@ -586,21 +469,15 @@ __device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t
         rn2 = n2;
     }
 
-    if (KIND == GREEDY_GOMP && pass == 0 && g.fbflag) {
+    if (pass == 0 && g.fbflag) {
         g.fbflag[local] = fallback ? 1u : 0u;
         if (fallback) return;   // the FP64 pass writes this pixel's results
     }
 
     // ---------------- outputs
-    float nrm = 1.f;
-    if (KIND == GREEDY_BIHT_ONE_BIT) {
-        float x2 = 0.f;
-        for (int a = 0; a < nx; ++a) x2 += s.xval[a] * s.xval[a];
-        nrm = x2 > 0.f ? 1.f / sqrtf(x2) : 0.f;
-    }
     float* xrow = g.X + pix * N;
     for (int n = 0; n < N; ++n) xrow[n] = 0.f;
-    for (int a = 0; a < nx; ++a) xrow[s.xidx[a]] = s.xval[a] * nrm;
+    for (int a = 0; a < nx; ++a) xrow[s.xidx[a]] = s.xval[a];
     if (g.support) {
         int32_t* srow = g.support + pix * K;
         int a = 0;
@@ -621,23 +498,23 @@ __device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t
     }
 }
 
-template <int KIND, int MMAX, int SMAX, typename T>
+template <int MMAX, int SMAX, typename T>
 __global__ __launch_bounds__(256, 2) void greedy_kernel(GArgs g, int64_t p0, int64_t np, int pass) {
     extern __shared__ float sAT[];
-    greedy_block<KIND, MMAX, SMAX, T>(g, p0, np, pass, blockIdx.x, 0, sAT);
+    greedy_block<MMAX, SMAX, T>(g, p0, np, pass, blockIdx.x, 0, sAT);
 }
 
 // Grouped launch: blocks [items[i].block0, items[i+1].block0) solve item i
 // (its own dictionary, measurements and outputs); scratch columns are
 // batch-wide slots.
-template <int KIND, int MMAX, int SMAX, typename T>
+template <int MMAX, int SMAX, typename T>
 __global__ __launch_bounds__(256, 2) void greedy_grouped_kernel(const GroupItem* __restrict__ items, int nitems,
                                                                 int pass) {
     extern __shared__ float sAT[];
     int it = 0;
     while (it + 1 < nitems && items[it + 1].block0 <= (int64_t)blockIdx.x) ++it;
     const GArgs g = items[it].g;
-    greedy_block<KIND, MMAX, SMAX, T>(g, items[it].p0, items[it].np, pass, blockIdx.x - items[it].block0,
+    greedy_block<MMAX, SMAX, T>(g, items[it].p0, items[it].np, pass, blockIdx.x - items[it].block0,
                                       items[it].slot0, sAT);
 }
 
@@ -655,28 +532,11 @@ __global__ void gram_kernel(const float* __restrict__ A, int M, int N, float* __
 
 typedef void (*gk_t)(GArgs, int64_t, int64_t, int);
 
-template <int KIND, int MMAX, int SMAX>
-gk_t pick_T(bool dbl) {
-    return dbl ? greedy_kernel<KIND, MMAX, SMAX, double> : greedy_kernel<KIND, MMAX, SMAX, float>;
-}
-
-template <int KIND, int SMAX>
-gk_t pick_M(int M, bool dbl) {
-    if (M <= 48) return pick_T<KIND, 48, SMAX>(dbl);
-    if (M <= 80) return pick_T<KIND, 80, SMAX>(dbl);
-    if (M <= 96) return pick_T<KIND, 96, SMAX>(dbl);
-    return nullptr;
-}
-
-gk_t pick_kernel(GreedyKind kind, int M, int S, bool dbl) {
-    switch (kind) {
-        case GREEDY_GOMP:
-            if (S <= 2) return pick_M<GREEDY_GOMP, 2>(M, dbl);
-            return pick_M<GREEDY_GOMP, 8>(M, dbl);
-        case GREEDY_COSAMP: return pick_M<GREEDY_COSAMP, 1>(M, dbl);
-        case GREEDY_BIHT: return pick_M<GREEDY_BIHT, 1>(M, dbl);
-        case GREEDY_BIHT_ONE_BIT: return pick_M<GREEDY_BIHT_ONE_BIT, 1>(M, false);
-    }
+// The FP64 redo kernel for a dictionary with M rows and S atoms per iteration.
+gk_t pick_kernel(int M, int S) {
+    if (M <= 48) return S <= 2 ? greedy_kernel<48, 2, double> : greedy_kernel<48, 8, double>;
+    if (M <= 80) return S <= 2 ? greedy_kernel<80, 2, double> : greedy_kernel<80, 8, double>;
+    if (M <= 96) return S <= 2 ? greedy_kernel<96, 2, double> : greedy_kernel<96, 8, double>;
     return nullptr;
 }
 
@@ -690,20 +550,10 @@ struct Layout {
 
 constexpr int64_t kChunk = 65536;
 
-// CoSaMP and both BIHT forms run on the on-chip design when it fits.
-bool coop_other(const GreedyLaunch& a) {
-    return a.kind != GREEDY_GOMP && coop_other_supported(a.kind, a.M, a.N, a.K) == CSREC_OK;
-}
-
 Layout layout_for(const GreedyLaunch& a, int64_t ch_override = 0) {
     Layout L;
-    int CM = 0, LM = 1;
-    switch (a.kind) {
-        case GREEDY_GOMP: CM = a.S * a.max_iter + a.K; LM = a.K; break;   // c plus a q-sized tail
-        case GREEDY_COSAMP: CM = 3 * a.K; LM = 2 * a.K; break;   // (>= K for the prune list)
-        case GREEDY_BIHT: CM = 2 * a.K; LM = a.K; break;
-        case GREEDY_BIHT_ONE_BIT: CM = a.K; LM = a.K; break;
-    }
+    // FP64 redo of gOMP: the factor holds c plus a q-sized tail
+    const int CM = a.S * a.max_iter + a.K, LM = a.K;
     L.CM = CM;
     L.LM = LM;
     L.CH = a.P < kChunk ? ((a.P + 63) / 64) * 64 : kChunk;
@@ -713,15 +563,15 @@ Layout layout_for(const GreedyLaunch& a, int64_t ch_override = 0) {
     const size_t tsz = dbl ? 8 : 4;
     const int NW = (a.N + 31) / 32;
     const int64_t tent = (int64_t)CM * (CM + 1) / 2 + 3 * (int64_t)CM;
-    const int64_t ient = a.N + 2 * LM + 3 * CM + 2 * NW;
+    const int64_t ient = a.N + LM + 3 * CM + 2 * NW;
     L.gram32 = 0;
     L.gram64 = align_up((size_t)a.N * a.N * 4, 256);
     size_t o = L.gram64 + (dbl ? align_up((size_t)a.N * a.N * 8, 256) : 0);
     L.off_AT = o;
-    if (a.kind == GREEDY_GOMP || coop_other(a)) o += align_up(gomp_coop_dict_floats(a.M, a.N) * 4, 256);
+    o += align_up(gomp_coop_dict_floats(a.M, a.N) * 4, 256);
     L.off_f = o;
     o += align_up((size_t)L.CH * 4, 256);
-    if ((a.kind == GREEDY_GOMP && !dbl) || coop_other(a)) {
+    if (!dbl) {
         // the on-chip kernels need no per-pixel scratch
         L.off_T = L.off_i = L.off_r = o;
         L.total = o;
@@ -747,15 +597,13 @@ namespace {
 typedef void (*ggk_t)(const GroupItem*, int, int);
 
 template <int MMAX>
-ggk_t pick_grouped(bool dbl, int S) {
-    if (S <= 2)
-        return dbl ? greedy_grouped_kernel<GREEDY_GOMP, MMAX, 2, double> : greedy_grouped_kernel<GREEDY_GOMP, MMAX, 2, float>;
-    return dbl ? greedy_grouped_kernel<GREEDY_GOMP, MMAX, 8, double> : greedy_grouped_kernel<GREEDY_GOMP, MMAX, 8, float>;
+ggk_t pick_grouped(int S) {
+    return S <= 2 ? greedy_grouped_kernel<MMAX, 2, double> : greedy_grouped_kernel<MMAX, 8, double>;
 }
-ggk_t pick_grouped_m(int mmax, bool dbl, int S) {
-    if (mmax == 48) return pick_grouped<48>(dbl, S);
-    if (mmax == 80) return pick_grouped<80>(dbl, S);
-    return pick_grouped<96>(dbl, S);
+ggk_t pick_grouped_m(int mmax, int S) {
+    if (mmax == 48) return pick_grouped<48>(S);
+    if (mmax == 80) return pick_grouped<80>(S);
+    return pick_grouped<96>(S);
 }
 }  // namespace
 
@@ -794,7 +642,6 @@ int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* ite
             GArgs& g = gi.g;
             g.A = it.A;
             g.Y = it.Y;
-            g.Ysign = nullptr;
             g.X = it.X;
             g.support = it.support;
             g.stats = it.stats;
@@ -808,7 +655,6 @@ int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* ite
             g.prune = pm.prune;
             g.res_tol = pm.res_tol;
             g.eps = pm.eps;
-            g.mu = 0.f;
             g.pivot_thr = pm.pivot_fallback;
             g.scr = w;
             g.CH = L.CH;
@@ -868,7 +714,7 @@ int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* ite
     CSREC_HIP_TRY(hipMemcpyAsync(td, th, (size_t)nt * sizeof(GroupItem), hipMemcpyHostToDevice, stream));
     for (int pass = 1; pass < 2; ++pass) {
         for (int r = 0; r < nr; ++r) {
-            ggk_t fn = pick_grouped_m(ranges[r].mmax, pass == 1, pm.S);
+            ggk_t fn = pick_grouped_m(ranges[r].mmax, pm.S);
             CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)ranges[r].lds));
             hipLaunchKernelGGL(fn, dim3((unsigned)ranges[r].blocks), dim3(256), ranges[r].lds, stream,
@@ -895,7 +741,6 @@ int greedy_launch(const GreedyLaunch& a) {
     GArgs g;
     g.A = a.A;
     g.Y = a.Y;
-    g.Ysign = a.Ysign;
     g.X = a.X;
     g.support = a.support;
     g.stats = a.stats;
@@ -909,7 +754,6 @@ int greedy_launch(const GreedyLaunch& a) {
     g.prune = a.prune;
     g.res_tol = a.res_tol;
     g.eps = a.eps;
-    g.mu = a.mu;
     g.pivot_thr = a.pivot_fallback;
     g.scr = ws;
     g.CH = L.CH;
@@ -926,19 +770,12 @@ int greedy_launch(const GreedyLaunch& a) {
                            dbl ? reinterpret_cast<double*>(ws + L.gram64) : nullptr);
         CSREC_HIP_TRY(hipGetLastError());
     }
-    const int mmax = mmax_for(a.M);
-    const size_t lds = (size_t)a.N * (mmax + 4) * sizeof(float);
-    const int threads = 256;
-    gk_t fns[2] = {pick_kernel(a.kind, a.M, a.S, false), dbl ? pick_kernel(a.kind, a.M, a.S, true) : nullptr};
-    for (int pass = 0; pass < (dbl ? 2 : 1); ++pass) {
-        if (!fns[pass]) return CSREC_E_UNSUPPORTED;
-        CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fns[pass]),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    }
-    const bool coop = a.kind == GREEDY_GOMP;   // gOMP's FP32 pass keeps its state on chip
     float* dictbuf = reinterpret_cast<float*>(ws + L.off_AT);
-    if (coop || coop_other(a)) gomp_coop_prepare(a.A, a.M, a.N, dictbuf, a.stream);
-    if (coop_other(a)) {
+    gomp_coop_prepare(a.A, a.M, a.N, dictbuf, a.stream);
+    CSREC_HIP_TRY(hipGetLastError());
+    if (a.kind != GREEDY_GOMP) {
+        // CoSaMP and both BIHT forms: the on-chip kernel, in chunks
+        if (coop_other_supported(a.kind, a.M, a.N, a.K) != CSREC_OK) return CSREC_E_UNSUPPORTED;
         for (int64_t p0 = 0; p0 < a.P; p0 += L.CH) {
             const int64_t np = (a.P - p0) < L.CH ? (a.P - p0) : L.CH;
             const int e = coop_other_launch(a.kind, a.Y, a.Ysign, a.X, a.support, a.stats, g.G32, dictbuf, a.M, a.N,
@@ -947,19 +784,26 @@ int greedy_launch(const GreedyLaunch& a) {
         }
         return CSREC_OK;
     }
+    // gOMP: the on-chip FP32 pass, then (pivot_fallback > 0) the FP64 redo of
+    // the pixels it flagged
+    const int mmax = mmax_for(a.M);
+    const size_t lds = (size_t)a.N * (mmax + 4) * sizeof(float);
+    const int threads = 256;
+    const gk_t redo = dbl ? pick_kernel(a.M, a.S) : nullptr;
+    if (dbl) {
+        if (!redo) return CSREC_E_UNSUPPORTED;
+        CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(redo),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
     for (int64_t p0 = 0; p0 < a.P; p0 += L.CH) {
         const int64_t np = (a.P - p0) < L.CH ? (a.P - p0) : L.CH;
-        const int64_t blocks = ceil_div(np, threads);
-        for (int pass = 0; pass < (dbl ? 2 : 1); ++pass) {
-            if (coop && pass == 0) {
-                const int e = gomp_coop_launch(a.Y, a.X, a.support, a.stats, g.G32, dictbuf, g.fbflag, a.M, a.N,
-                                               p0, np, a.K, a.S, a.max_iter, a.prune, a.res_tol, a.eps,
-                                               a.pivot_fallback, a.stream);
-                if (e) return e;
-                continue;
-            }
-            hipLaunchKernelGGL(fns[pass], dim3((unsigned)blocks), dim3(threads), lds, a.stream, g, p0, np,
-                               pass);
+        const int e = gomp_coop_launch(a.Y, a.X, a.support, a.stats, g.G32, dictbuf, g.fbflag, a.M, a.N, p0, np,
+                                       a.K, a.S, a.max_iter, a.prune, a.res_tol, a.eps, a.pivot_fallback,
+                                       a.stream);
+        if (e) return e;
+        if (dbl) {
+            hipLaunchKernelGGL(redo, dim3((unsigned)ceil_div(np, threads)), dim3(threads), lds, a.stream, g, p0,
+                               np, 1);
             CSREC_HIP_TRY(hipGetLastError());
         }
     }

@@ -92,3 +92,41 @@ def test_budget_admission_and_order(torch):
         with pytest.raises(cs.CsrecError) as ei:
             srv.submit(d, tiles[3][1], 0)
         assert ei.value.code == -6
+
+
+def test_fp64_fallback_through_the_server(torch):
+    """Nearly duplicated atoms with pivot_fallback: the grouped FP64 redo of the
+    flagged pixels gives the same results as the direct csrec_gomp call, and
+    meets the FP64 oracle on the pixels away from near-ties."""
+    import paper_2401_14762_amd as cs
+    rng = np.random.default_rng(11)
+    M, N, P = 40, 100, 200
+    A = rng.standard_normal((M, N)) / np.sqrt(M)
+    A[:, 1] = A[:, 0] + 1e-5 * rng.standard_normal(M)
+    A32 = A.astype(np.float32)
+    X = np.zeros((P, N))
+    X[:, 0] = 1.0
+    X[:, 1] = 1.0
+    X[np.arange(P), 5 + np.arange(P) % 50] = 0.5
+    Y = (X @ A32.astype(np.float64).T).astype(np.float32)
+    note("serving: fp64 fallback")
+    with cs.Server(K=6, S=2, res_tol=1e-6, pivot_fallback=1e-6, hbm_budget_bytes=1 << 28, batch_pixels=4096,
+                   chunk_pixels=64) as srv:
+        did = srv.add_dict(A32)
+        srv.submit(did, Y[:77], 0)
+        srv.submit(did, Y[77:], 1)
+        srv.drain()
+        res = {r["tag"]: r for r in srv.poll(10)}
+    Xs = np.concatenate([res[0]["X"], res[1]["X"]])
+    Ss = np.concatenate([res[0]["support"], res[1]["support"]])
+    fl = np.concatenate([res[0]["flags"], res[1]["flags"]])
+    assert res[0]["status"] == 0 and res[1]["status"] == 0
+    Xd, Sd, std = cs.gomp(to_dev(torch, A32), to_dev(torch, Y), K=6, S=2, res_tol=1e-6, pivot_fallback=1e-6)
+    torch.cuda.synchronize()
+    assert np.array_equal(Xs, np_of(Xd)) and np.array_equal(Ss, np_of(Sd))
+    fb = (fl & oracle.STOP_FALLBACK) != 0
+    assert fb.any() and np.array_equal(fl, np_of(std["flags"]).view(np.uint32))
+    ref = oracle.gomp(A32, Y, K=6, S=2, res_tol=1e-6, diagnostics=True)
+    ok = fb & (ref["sel_gap"] >= GAP) & (ref["prune_gap"] >= GAP)
+    assert ok.any()
+    assert rel_err_rows(Xs[ok], ref["X"][ok]).max() < 1e-5
