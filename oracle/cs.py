@@ -199,6 +199,86 @@ def fista(A, Y, lam: float, L: float, max_iter: int, eps: float = 0.0, X0=None,
 
 
 # --------------------------------------------------------------------------
+# Alg. 2 -- ADMM
+# --------------------------------------------------------------------------
+
+ADMM_THRESHOLDS = ("paper", "standard")
+
+
+def admm_threshold(lam: float, alpha: float, threshold: str = "paper") -> float:
+    """The soft-threshold of Alg. 2 step 2.  The algorithm prints lam * alpha
+    ("paper"); the textbook scaled-form ADMM for Eq. 2 uses lam / alpha
+    ("standard").  With penalty alpha, a threshold tau makes the iteration
+    solve Eq. 2 with regularisation tau * alpha, so "paper" solves it with
+    lam * alpha^2 and "standard" with lam."""
+    if threshold == "paper":
+        return lam * alpha
+    if threshold == "standard":
+        return lam / alpha
+    raise ValueError(f"threshold must be one of {ADMM_THRESHOLDS}")
+
+
+def admm(A, Y, lam: float, alpha: float, max_iter: int, eps: float = 0.0, X0=None,
+         threshold: str = "paper", dtype=np.float64) -> dict:
+    """ADMM for the LASSO (Eq. 2 as the constrained problem x - z = 0; Alg. 2),
+    every pixel (row of Y) independently.
+
+    Per iteration i, for each pixel still running:
+      1. x^i = (A^T A + alpha I)^{-1} (A^T y + alpha (z^{i-1} - w^{i-1}))
+      2. z^i = sign(x^i + w^{i-1}) * max(|x^i + w^{i-1}| - thr, 0)
+      3. w^i = w^{i-1} + x^i - z^i
+      4. r^i = y - A x^i,  Delta = ||r^i - r^{i-1}||_2;  stop when Delta < eps
+    with z^0 = w^0 = x^0 (the algorithm's initialisation), r^0 = y and thr =
+    admm_threshold(lam, alpha, threshold).  Step 1 solves with a Cholesky
+    factor of the N x N matrix A^T A + alpha I.
+
+    dtype=np.float32 is the FP32 rounding model (as for fista).
+
+    Returns dict(X = x^I, Z = z^I, iters, delta, resid (||y - A x^I||), flags)."""
+    A = np.asarray(A, dtype=dtype)
+    Y = np.asarray(Y, dtype=dtype)
+    P, M = Y.shape
+    N = A.shape[1]
+    thr = dtype(admm_threshold(lam, alpha, threshold))
+    fin = _finite_rows(Y)
+    Yc = np.where(fin[:, None], Y, dtype(0.0))
+    x = np.zeros((P, N), dtype=dtype) if X0 is None else np.asarray(X0, dtype=dtype).copy()
+    x[~fin] = 0.0
+    z = x.copy()
+    w = x.copy()
+    r = Yc.copy()                    # r^0 = y
+    Lc = np.linalg.cholesky((A.T @ A + dtype(alpha) * np.eye(N, dtype=dtype)).astype(np.float64)).astype(dtype)
+    Aty = Yc @ A
+    iters = np.zeros(P, dtype=np.int64)
+    delta = np.full(P, np.nan)
+    flags = np.zeros(P, dtype=np.int64)
+    flags[~fin] |= STOP_NONFINITE
+    active = fin.copy()
+    for i in range(1, max_iter + 1):
+        if not active.any():
+            break
+        a = np.nonzero(active)[0]
+        rhs = Aty[a] + dtype(alpha) * (z[a] - w[a])                      # step 1
+        h = np.linalg.solve(Lc, rhs.T)
+        x_new = np.linalg.solve(Lc.T, h).T.astype(dtype)
+        zt = x_new + w[a]
+        z_new = soft_threshold(zt, thr)                                  # step 2
+        w_new = zt - z_new                                               # step 3
+        r_new = Yc[a] - x_new @ A.T                                      # step 4
+        d = np.linalg.norm(r_new - r[a], axis=1)
+        x[a], z[a], w[a], r[a] = x_new, z_new, w_new, r_new
+        iters[a] = i
+        delta[a] = d
+        stop = d < eps
+        flags[a[stop]] |= STOP_CONVERGED
+        active[a[stop]] = False
+    flags[active] |= STOP_ITER_CAP
+    resid = np.linalg.norm(Yc - x @ A.T, axis=1)
+    return dict(X=x.astype(np.float64), Z=z.astype(np.float64), iters=iters, delta=delta, resid=resid,
+                flags=flags)
+
+
+# --------------------------------------------------------------------------
 # Alg. 3 -- gOMP
 # --------------------------------------------------------------------------
 

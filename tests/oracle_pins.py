@@ -435,6 +435,69 @@ def check_one_bit(orc):
 
 # ---------------------------------------------------------------- metrics
 
+# ---------------------------------------------------------------- ADMM (Alg. 2)
+
+def check_admm_matches_sklearn_lasso(orc):
+    """At convergence ADMM reaches the LASSO minimiser of Eq. 2 with the
+    regularisation its threshold implies (threshold * alpha): lam alpha^2 for
+    the threshold the algorithm prints, lam for the textbook one.  Reference:
+    scikit-learn's coordinate descent (alpha = lam_eff / M).  Both x and z
+    converge to it."""
+    from sklearn.linear_model import Lasso
+    A, _, Y = _sparse_problem(20, 35, 3, 3, 31, noise=0.01)
+    for lam, alpha, mode, lam_eff in ((0.01, 1.8, "paper", 0.01 * 1.8 ** 2), (0.03, 1.8, "standard", 0.03),
+                                      (0.02, 0.7, "paper", 0.02 * 0.49)):
+        out = orc.admm(A, Y, lam, alpha, 4000, threshold=mode)
+        for p in range(Y.shape[0]):
+            m = Lasso(alpha=lam_eff / A.shape[0], fit_intercept=False, tol=1e-14, max_iter=200000)
+            m.fit(A, Y[p])
+            assert np.max(np.abs(out["Z"][p] - m.coef_)) < 1e-7, (mode, p)
+            assert np.max(np.abs(out["X"][p] - m.coef_)) < 1e-7, (mode, p)
+
+
+def check_admm_identity(orc):
+    """A = I: the fixed point is soft(y, lam_eff), and the first iterate is
+    x^1 = y / (1 + alpha) (z^0 = w^0 = 0)."""
+    y = _rng(32).standard_normal((4, 9))
+    lam, alpha = 0.2, 1.8
+    out1 = orc.admm(np.eye(9), y, lam, alpha, 1)
+    assert np.max(np.abs(out1["X"] - y / (1.0 + alpha))) < 1e-14
+    assert np.max(np.abs(out1["Z"] - _soft(y / (1.0 + alpha), lam * alpha))) < 1e-14
+    out = orc.admm(np.eye(9), y, lam, alpha, 3000)
+    assert np.max(np.abs(out["Z"] - _soft(y, lam * alpha * alpha))) < 1e-12
+    outs = orc.admm(np.eye(9), y, lam, alpha, 3000, threshold="standard")
+    assert np.max(np.abs(outs["Z"] - _soft(y, lam))) < 1e-12
+
+
+def check_admm_kkt_and_dual(orc):
+    """KKT residual of Eq. 2 at lam_eff vanishes for the converged z; the dual
+    variable w^k = sum_{j <= k} (x^j - z^j) (step 3 from w^0 = 0) stays inside
+    [-thr, thr] at every iteration, since it is what the soft threshold of
+    step 2 cut off."""
+    from oracle import metrics
+    A, _, Y = _sparse_problem(15, 30, 3, 2, 33, noise=0.05)
+    lam, alpha = 0.02, 1.8
+    out = orc.admm(A, Y, lam, alpha, 6000)
+    kkt = metrics.lasso_kkt_residual(A, Y, out["Z"], lam * alpha * alpha)
+    assert np.all(kkt < 1e-9), kkt
+    thr = lam * alpha
+    w = np.zeros_like(Y @ A)
+    for k in range(1, 9):
+        o = orc.admm(A, Y, lam, alpha, k)
+        w = w + o["X"] - o["Z"]
+        assert np.all(np.abs(w) <= thr * (1 + 1e-9)), (k, np.abs(w).max(), thr)
+
+
+def check_admm_stop_rule(orc):
+    """Delta = ||r^i - r^{i-1}||, r^0 = y: Delta at iteration 1 is ||A x^1||; a
+    huge eps stops after iteration 1."""
+    A, _, Y = _sparse_problem(20, 40, 3, 4, 34)
+    o = orc.admm(A, Y, 0.01, 1.8, 1)
+    assert np.allclose(o["delta"], np.linalg.norm(o["X"] @ A.T, axis=1), rtol=1e-12)
+    o = orc.admm(A, Y, 0.01, 1.8, 50, eps=1e9)
+    assert np.all(o["iters"] == 1) and np.all(o["flags"] == orc.STOP_CONVERGED)
+
+
 def check_metrics():
     from oracle import metrics
     ref = _rng(27).standard_normal((10, 20))
@@ -460,5 +523,6 @@ ORACLE_CHECKS = [
     check_gomp_brute_force, check_gomp_prune_invariants, check_gomp_no_reselect,
     check_gomp_stop, check_cosamp_orthonormal, check_cosamp_recovery, check_cosamp_no_resolve,
     check_biht_orthonormal, check_biht_first_step, check_biht_second_step_mu,
-    check_biht_recovery, check_one_bit,
+    check_biht_recovery, check_one_bit, check_admm_matches_sklearn_lasso, check_admm_identity,
+    check_admm_kkt_and_dual, check_admm_stop_rule,
 ]

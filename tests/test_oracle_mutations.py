@@ -40,6 +40,11 @@ MUTATIONS = [
     ("onebit-sgn0-plus", "u = x + mu * ((Ys - np.sign(ax)) @ A)",
      "u = x + mu * ((Ys - np.where(ax >= 0, 1.0, -1.0)) @ A)"),
     ("onebit-no-normalise", "x = np.where(nrm > 0, x / np.where(nrm > 0, nrm, 1.0), 0.0)", "x = x"),
+    ("admm-threshold-over-alpha", "        return lam * alpha\n", "        return lam / alpha\n"),
+    ("admm-no-alpha-identity", "(A.T @ A + dtype(alpha) * np.eye(N, dtype=dtype))", "(A.T @ A + np.eye(N, dtype=dtype))"),
+    ("admm-dual-sign", "rhs = Aty[a] + dtype(alpha) * (z[a] - w[a])", "rhs = Aty[a] + dtype(alpha) * (z[a] + w[a])"),
+    ("admm-no-dual-in-threshold", "zt = x_new + w[a]", "zt = x_new"),
+    ("admm-dual-not-accumulated", "w_new = zt - z_new", "w_new = x_new - z_new"),
 ]
 
 
