@@ -17,6 +17,8 @@ events and reported under "breakdown" (--legs):
              correction pass and in FP32; gOMP FP32 with the FP64 fallback.
   other      512x512 N=200 M=80 K=15-sparse cube: CoSaMP (Alg. 5), BIHT
              (Alg. 4) and the one-bit BIHT on int8 signs.
+  admm       the headline cube with ADMM (Alg. 2, 200 iterations, lambda=1e-2,
+             alpha=1.8, threshold lambda*alpha as printed, FP32).
   serving    Poisson stream of tiles (200 tiles/s, sides log-uniform in
              [64, 512], N in {100, 200, 224}) through csrec_server_*:
              p50 / p99 latency (done - submit) and pixels/s.
@@ -47,6 +49,7 @@ GOMP_S, GOMP_K, GOMP_TOL = 2, 20, 1e-3
 CORRECTION_ITERS = 20
 OTHER_K, COSAMP_ITERS, BIHT_REAL_ITERS, BIHT_1BIT_ITERS, BIHT_MU = 15, 30, 40, 100, 0.1
 PSNR_SAMPLE = 128
+ADMM_ITERS, ADMM_ALPHA = 200, 1.8
 
 
 def measured_traffic(kernel_src: str, summary: str):
@@ -74,7 +77,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--pixels", type=int, default=0, help="override the cube size (testing only)")
-    ap.add_argument("--legs", default="precision,other,serving",
+    ap.add_argument("--legs", default="precision,other,admm,serving",
                     help="comma list of the legs measured after the timed region ('' for none)")
     ap.add_argument("--serve-tiles", type=int, default=400, help="measured serving tiles")
     ap.add_argument("--serve-warmup", type=int, default=40, help="serving tiles before the measured ones")
@@ -185,6 +188,24 @@ def leg_other(torch, cs, W, dev, stream, samples):
     return out
 
 
+def leg_admm(torch, cs, pr, A, Y, stream, idx, samples):
+    """ADMM on the headline cube; FLOPs per launch = P * iterations *
+    (4 M N + 2 M^2): the products A v, R t (R = (alpha I + A A^T)^{-1}) and
+    A^T e of every iteration."""
+    P, M, N = pr.P, pr.M, pr.N
+    log(f"leg admm: {P} pixels N={N} M={M}, {ADMM_ITERS} it")
+    X = torch.empty((P, N), dtype=torch.float32, device=A.device)
+    res, ms = event_timed(torch, stream, lambda: cs.admm(A, Y, lam=LAMBDA, alpha=ADMM_ALPHA, max_iter=ADMM_ITERS,
+                                                         out=X))
+    flops = P * ADMM_ITERS * (4.0 * M * N + 2.0 * M * M)
+    tf = flops / (ms * 1e-3) / 1e12
+    samples["admm"] = dict(gpu=X[torch.from_numpy(idx).to(A.device)].cpu().numpy())
+    del X, res
+    return {"workload": f"plain mixing-model cube, ADMM {ADMM_ITERS} it lambda={LAMBDA} alpha={ADMM_ALPHA} "
+                        f"(threshold lambda*alpha), FP32", "pixels": P, "ms": ms, "pixels_per_s": P / (ms * 1e-3),
+            "achieved_tflops": tf, "mfma_fp32_frac": tf / FP32_MFMA_PEAK_TFLOPS}
+
+
 def leg_serving(torch, cs, W, n_tiles, n_warm):
     stream = W.serving_stream(n_warm + n_tiles)
     rate = W.SERVING["rate"]
@@ -268,6 +289,9 @@ def cpu_baseline_leg(W, pr, L, idx_psnr, Xf_s, Xg_s, n_sample, samples):
     q["plain_fista"] = psnr(Xf_s @ Psi.T, ref["X"] @ Psi.T)
     ref = oracle.gomp(pr.A, pr.Y[idx_psnr], K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL)
     q["plain_gomp"] = psnr(Xg_s @ Psi.T, ref["X"] @ Psi.T)
+    if "admm" in samples:
+        ref = oracle.admm(pr.A, pr.Y[idx_psnr], LAMBDA, ADMM_ALPHA, ADMM_ITERS)
+        q["plain_admm"] = psnr(samples["admm"]["gpu"] @ Psi.T, ref["X"] @ Psi.T)
     if "precision" in samples:
         s = samples["precision"]
         ref = oracle.fista(s["A"], s["Y"], LAMBDA, s["L"], FISTA_ITERS)
@@ -376,6 +400,8 @@ def main():
         breakdown["precision"] = leg_precision(torch, cs, W, dev, stream, samples)
     if "other" in legs:
         breakdown["other_solvers"] = leg_other(torch, cs, W, dev, stream, samples)
+    if "admm" in legs:
+        breakdown["admm"] = leg_admm(torch, cs, pr, A, Y, stream, idx, samples)
     if "serving" in legs:
         breakdown["serving"] = leg_serving(torch, cs, W, args.serve_tiles, args.serve_warmup)
 

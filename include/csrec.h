@@ -12,6 +12,7 @@
  *   csrec_biht    backtracking IHT (Alg. 4), or binary IHT on 1-bit
  *                 measurements (mode CSREC_BIHT_ONE_BIT; not from the paper)
  *   csrec_cosamp  CoSaMP                                   (Alg. 5)
+ *   csrec_admm    ADMM for the LASSO of Eq. 2             (Alg. 2)
  *
  * Layout.  A is M x N row-major FP32.  Y is P x M row-major FP32 (pixel
  * major: the measurements of one pixel are contiguous).  X is P x N
@@ -71,12 +72,18 @@ extern "C" {
 #define CSREC_SOLVER_GOMP   1
 #define CSREC_SOLVER_COSAMP 2
 #define CSREC_SOLVER_BIHT   3
+#define CSREC_SOLVER_ADMM   4
 
 #define CSREC_MAX_N 256
 
 /* gOMP prune placement (Alg. 3 step 3) */
 #define CSREC_PRUNE_EACH  0  /* prune to K and re-solve in every iteration where |c| > K (Alg. 3 as printed) */
 #define CSREC_PRUNE_FINAL 1  /* prune once after the loop (textbook gOMP) */
+
+/* ADMM soft threshold (Alg. 2 step 2) */
+#define CSREC_ADMM_THR_PAPER    0  /* lambda * alpha, as Alg. 2 prints it: the fixed point solves Eq. 2
+                                      with l1 weight lambda * alpha^2 */
+#define CSREC_ADMM_THR_STANDARD 1  /* lambda / alpha, scaled-form ADMM: solves Eq. 2 with weight lambda */
 
 /* BIHT modes */
 #define CSREC_BIHT_REAL    0 /* Alg. 4, backtracking IHT on real measurements Y */
@@ -153,6 +160,19 @@ typedef struct {
     int32_t prec;             /* precision of the correlation */
 } csrec_biht_params;
 
+/* Alg. 2.  Inputs y, A, x^0, lambda, alpha, eps (kappa is unused by ADMM).
+ * Initialisation z^0 = w^0 = x^0, r^0 = y; each iteration runs steps 1-4 and
+ * a pixel stops after the iteration with Delta = ||r^i - r^{i-1}|| < eps. */
+typedef struct {
+    int32_t struct_size;      /* sizeof(csrec_admm_params) */
+    int32_t max_iter;         /* >= 0; replaces the paper's wall-clock cap */
+    double lambda;            /* >= 0 */
+    double alpha;             /* > 0: the penalty of the augmented Lagrangian (1.8 in Section IV) */
+    double eps;               /* 0 disables the Delta stop */
+    const float* X0;          /* device P x N starting point, NULL = 0 */
+    int32_t threshold;        /* CSREC_ADMM_THR_PAPER or CSREC_ADMM_THR_STANDARD */
+} csrec_admm_params;
+
 /* Library version and ABI. */
 int32_t csrec_abi_version(void);
 const char* csrec_strerror(int32_t code);
@@ -181,6 +201,13 @@ int32_t csrec_cosamp(const csrec_problem* problem, const csrec_cosamp_params* pa
 /* BIHT (Alg. 4 / binary IHT): outputs as csrec_gomp.  ONE_BIT returns x / ||x||. */
 int32_t csrec_biht(const csrec_problem* problem, const csrec_biht_params* params, float* X,
                    int32_t* support, csrec_pixel_stats* stats);
+
+/* ADMM (Alg. 2): X (P x N) receives x^I, Z (P x N, nullable) z^I; stats nullable (resid is
+ * ||y - A x^I||).  Needs a workspace of csrec_workspace_bytes() (the M x M matrix
+ * (alpha I + A A^T)^{-1}, formed on the device in FP64 on every call).  FP32; M <= 96,
+ * otherwise CSREC_E_UNSUPPORTED.  X may alias X0. */
+int32_t csrec_admm(const csrec_problem* problem, const csrec_admm_params* params, float* X, float* Z,
+                   csrec_pixel_stats* stats);
 
 /* Lipschitz constant L = lambda_max(A^T A) of Eq. 2 by power iteration on the device:
  * writes one float to *L_out (device pointer) on `stream`. */

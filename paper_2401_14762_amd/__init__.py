@@ -22,7 +22,7 @@ from . import _lib
 from ._lib import (CsrecError, FLAG_CONVERGED, FLAG_FP64_FALLBACK, FLAG_ITER_CAP,
                    FLAG_NONFINITE, MAX_N)
 
-__all__ = ["fista", "gomp", "cosamp", "biht", "lipschitz", "Server", "CsrecError", "FLAG_CONVERGED",
+__all__ = ["fista", "admm", "gomp", "cosamp", "biht", "lipschitz", "Server", "CsrecError", "FLAG_CONVERGED",
            "FLAG_ITER_CAP", "FLAG_FP64_FALLBACK", "FLAG_NONFINITE", "MAX_N", "workspace_bytes",
            "library"]
 
@@ -113,6 +113,19 @@ def _params(solver, A, P, kw):
         p.prec = _lib.PREC[kw.get("prec", "f32")]
         p.correction_iters = int(kw.get("correction_iters", 0))
         return p, _lib.SOLVER_FISTA
+    if solver == "admm":
+        p = _lib.AdmmParams()
+        p.struct_size = ctypes.sizeof(p)
+        p.max_iter = int(kw.get("max_iter", 100))
+        p.lambda_ = float(kw.get("lam", 0.0))
+        p.alpha = float(kw.get("alpha", 1.8))
+        p.eps = float(kw.get("eps", 0.0))
+        x0 = kw.get("X0")
+        p.X0 = x0.data_ptr() if x0 is not None else 0
+        if kw.get("threshold", "paper") not in _lib.ADMM_THR:
+            raise ValueError(f"threshold must be one of {sorted(_lib.ADMM_THR)}")
+        p.threshold = _lib.ADMM_THR[kw.get("threshold", "paper")]
+        return p, _lib.SOLVER_ADMM
     if solver == "gomp":
         p = _lib.GompParams()
         p.struct_size = ctypes.sizeof(p)
@@ -172,6 +185,34 @@ def fista(A, Y, lam: float, L: float = 0.0, max_iter: int = 100, eps: float = 0.
     _lib.check(lib.csrec_fista(ctypes.byref(pb), ctypes.byref(prm), _ptr(X), _ptr(st)), "csrec_fista")
     _keep_alive(ws, A.device, stream)
     return X, _stats_view(st[:P])
+
+
+def admm(A, Y, lam: float, alpha: float = 1.8, max_iter: int = 100, eps: float = 0.0, X0=None,
+         threshold: str = "paper", want_z: bool = False, stream=None, out=None):
+    """ADMM (Alg. 2) on every pixel: returns (X = x^I, Z = z^I or None, stats).
+    threshold "paper" soft-thresholds at lam * alpha (Alg. 2 step 2 as
+    printed), "standard" at lam / alpha."""
+    torch = _torch()
+    lib = library()
+    _check_dev("A", A, torch.float32)
+    M, N = A.shape
+    _check_dev("Y", Y, torch.float32)
+    P = Y.shape[0]
+    if Y.shape[1] != M:
+        raise ValueError("Y must be P x M")
+    if X0 is not None:
+        _check_dev("X0", X0, torch.float32, (P, N))
+    pb = _problem(A, Y, P, stream)
+    prm, sid = _params("admm", A, P, dict(lam=lam, alpha=alpha, max_iter=max_iter, eps=eps, X0=X0,
+                                          threshold=threshold))
+    ws = _workspace(lib, sid, pb, prm, A.device)
+    X = out if out is not None else torch.empty((P, N), dtype=torch.float32, device=A.device)
+    Z = torch.empty((P, N), dtype=torch.float32, device=A.device) if want_z else None
+    st = torch.empty((max(P, 1), 4), dtype=torch.int32, device=A.device)
+    _lib.check(lib.csrec_admm(ctypes.byref(pb), ctypes.byref(prm), _ptr(X), _ptr(Z),
+                              _ptr(st)), "csrec_admm")
+    _keep_alive(ws, A.device, stream)
+    return X, Z, _stats_view(st[:P])
 
 
 def _keep_alive(ws, device, stream):

@@ -17,7 +17,8 @@ CSREC_ABI_VERSION = 1
 OK, E_INVAL, E_SHAPE, E_WORKSPACE, E_DEVICE, E_UNSUPPORTED, E_BUDGET = 0, -1, -2, -3, -4, -5, -6
 PREC = {"f32": 0, "bf16": 1, "f16": 2}
 FLAG_CONVERGED, FLAG_ITER_CAP, FLAG_FP64_FALLBACK, FLAG_NONFINITE = 1, 2, 4, 8
-SOLVER_FISTA, SOLVER_GOMP, SOLVER_COSAMP, SOLVER_BIHT = 0, 1, 2, 3
+SOLVER_FISTA, SOLVER_GOMP, SOLVER_COSAMP, SOLVER_BIHT, SOLVER_ADMM = 0, 1, 2, 3, 4
+ADMM_THR = {"paper": 0, "standard": 1}
 PRUNE = {"each": 0, "final": 1}
 BIHT_MODE = {"real": 0, "one_bit": 1}
 MAX_N = 256
@@ -52,6 +53,18 @@ class FistaParams(ctypes.Structure):
         ("X0", ctypes.c_void_p),
         ("prec", ctypes.c_int32),
         ("correction_iters", ctypes.c_int32),
+    ]
+
+
+class AdmmParams(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32),
+        ("lambda_", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("X0", ctypes.c_void_p),
+        ("threshold", ctypes.c_int32),
     ]
 
 
@@ -136,6 +149,8 @@ SIGNATURES = {
     "csrec_cosamp": (ctypes.c_int32, [_P(Problem), _P(CosampParams), ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),
     "csrec_biht": (ctypes.c_int32, [_P(Problem), _P(BihtParams), ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]),
+    "csrec_admm": (ctypes.c_int32, [_P(Problem), _P(AdmmParams), ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p]),
     "csrec_lipschitz": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_void_p]),

@@ -36,6 +36,24 @@ int check_fista(const csrec_problem* p, const csrec_fista_params* f) {
     return fista_supported(p->M, p->N, f->prec);
 }
 
+int check_admm(const csrec_problem* p, const csrec_admm_params* q, float* thr) {
+    int e = check_problem(p, true);
+    if (e) return e;
+    if (!q || q->struct_size != (int32_t)sizeof(csrec_admm_params)) return CSREC_E_INVAL;
+    if (q->max_iter < 0 || !finite_nonneg(q->lambda) || !finite_nonneg(q->eps)) return CSREC_E_INVAL;
+    if (!std::isfinite(q->alpha) || !((float)q->alpha > 0.f) || !std::isfinite((float)q->alpha)) return CSREC_E_INVAL;
+    double t;
+    if (q->threshold == CSREC_ADMM_THR_PAPER)
+        t = q->lambda * q->alpha;
+    else if (q->threshold == CSREC_ADMM_THR_STANDARD)
+        t = q->lambda / q->alpha;
+    else
+        return CSREC_E_INVAL;
+    if (!std::isfinite((float)t) || !std::isfinite((float)q->eps)) return CSREC_E_INVAL;
+    *thr = (float)t;
+    return admm_supported(p->M, p->N);
+}
+
 int fill_gomp(const csrec_problem* p, const csrec_gomp_params* q, GreedyLaunch& l) {
     int e = check_problem(p, true);
     if (e) return e;
@@ -174,6 +192,12 @@ int32_t csrec_workspace_bytes(int32_t solver, const csrec_problem* problem, cons
             *bytes = fista_workspace(problem->M, problem->N, problem->P, f->prec) + (f->L == 0.0 ? 256 : 0);
             return CSREC_OK;
         }
+        case CSREC_SOLVER_ADMM: {
+            float thr;
+            if ((e = check_admm(problem, static_cast<const csrec_admm_params*>(params), &thr))) return e;
+            *bytes = problem->P > 0 ? admm_workspace(problem->M) : 0;
+            return CSREC_OK;
+        }
         case CSREC_SOLVER_GOMP:
             e = fill_gomp(problem, static_cast<const csrec_gomp_params*>(params), l);
             break;
@@ -251,6 +275,33 @@ int32_t csrec_biht(const csrec_problem* problem, const csrec_biht_params* params
     if (e) return e;
     fill_problem(problem, l);
     return run_greedy(l, X, support, stats);
+}
+
+int32_t csrec_admm(const csrec_problem* problem, const csrec_admm_params* params, float* X, float* Z,
+                   csrec_pixel_stats* stats) {
+    float thr = 0.f;
+    int e = check_admm(problem, params, &thr);
+    if (e) return e;
+    if (problem->P == 0) return CSREC_OK;
+    if (!X) return CSREC_E_INVAL;
+    if (!problem->workspace || problem->workspace_bytes < admm_workspace(problem->M)) return CSREC_E_WORKSPACE;
+    AdmmLaunch l{};
+    l.A = problem->A;
+    l.Y = problem->Y;
+    l.X0 = params->X0;
+    l.X = X;
+    l.Z = Z;
+    l.stats = stats;
+    l.M = problem->M;
+    l.N = problem->N;
+    l.P = problem->P;
+    l.max_iter = params->max_iter;
+    l.alpha = params->alpha;
+    l.thr = thr;
+    l.eps = (float)params->eps;
+    l.workspace = problem->workspace;
+    l.stream = reinterpret_cast<hipStream_t>(problem->stream);
+    return admm_launch(l);
 }
 
 int32_t csrec_lipschitz(const float* A, int32_t M, int32_t N, float* L_out, void* stream) {

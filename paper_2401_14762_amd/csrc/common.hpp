@@ -56,6 +56,27 @@ int fista_launch(const FistaLaunch& a);
 
 int lipschitz_launch(const float* A, int M, int N, float* L_out, hipStream_t stream);
 
+struct AdmmLaunch {
+    const float* A;
+    const float* Y;
+    const float* X0;
+    float* X;
+    float* Z;
+    csrec_pixel_stats* stats;
+    int M, N;
+    int64_t P;
+    int max_iter;
+    double alpha;
+    float thr;            // soft threshold of step 2
+    float eps;
+    void* workspace;      // >= admm_workspace(M) bytes: R = (alpha I + A A^T)^{-1}
+    hipStream_t stream;
+};
+
+int admm_supported(int M, int N);
+size_t admm_workspace(int M);
+int admm_launch(const AdmmLaunch& a);
+
 enum GreedyKind { GREEDY_GOMP = 0, GREEDY_COSAMP = 1, GREEDY_BIHT = 2, GREEDY_BIHT_ONE_BIT = 3 };
 
 struct GreedyLaunch {

@@ -85,3 +85,24 @@ def assert_fista_parity(X_gpu, A, Y, lam, L, iters, floor=1e-5, **kw):
     assert e.max() <= max(floor, 2.0 * e32.max()), (e.max(), e32.max())
     assert np.median(e) <= max(floor / 10, 2.0 * np.median(e32)), (np.median(e), np.median(e32))
     return ref, e
+
+
+def assert_admm_parity(X_gpu, Z_gpu, A, Y, lam, alpha, iters, floor=1e-5, **kw):
+    """ADMM parity, the bar of assert_fista_parity applied to x^I and z^I:
+    per pixel at most max(floor, 30 x) the error of the oracle's FP32
+    rounding model of Alg. 2 (which solves step 1 with an FP32 Cholesky
+    factor), and cube-wide max and median at most twice the model's."""
+    import oracle
+    ref = oracle.admm(A, Y, lam, alpha, iters, **kw)
+    r32 = oracle.admm(A, Y, lam, alpha, iters, dtype=np.float32, **kw)
+    for name, got in (("X", X_gpu), ("Z", Z_gpu)):
+        if got is None:
+            continue
+        e = rel_err_rows(got, ref[name])
+        e32 = rel_err_rows(r32[name], ref[name])
+        per_pixel = np.maximum(floor, 30.0 * e32)
+        bad = np.nonzero(e > per_pixel)[0]
+        assert len(bad) == 0, f"{name} pixels {bad[:8]}: err {e[bad[:8]]} vs fp32 model {e32[bad[:8]]}"
+        assert e.max() <= max(floor, 2.0 * e32.max()), (name, e.max(), e32.max())
+        assert np.median(e) <= max(floor / 10, 2.0 * np.median(e32)), (name, np.median(e), np.median(e32))
+    return ref

@@ -56,6 +56,8 @@ def test_struct_layout_matches_c(tmp_path):
         "sizeof(csrec_gomp_params), sizeof(csrec_cosamp_params), sizeof(csrec_biht_params),"
         "offsetof(csrec_problem, workspace_bytes), offsetof(csrec_biht_params, Ysign));"
         "printf(\"%zu %zu %zu\\n\", sizeof(csrec_server_cfg), sizeof(csrec_result), offsetof(csrec_result, t_done));"
+        "printf(\"%zu %zu %zu\\n\", sizeof(csrec_admm_params), offsetof(csrec_admm_params, X0),"
+        "offsetof(csrec_admm_params, threshold));"
         "return 0;}\n")
     exe = tmp_path / "sizes"
     subprocess.run([cc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
@@ -63,7 +65,8 @@ def test_struct_layout_matches_c(tmp_path):
     want = [ctypes.sizeof(L.Problem), ctypes.sizeof(L.PixelStats), ctypes.sizeof(L.FistaParams),
             ctypes.sizeof(L.GompParams), ctypes.sizeof(L.CosampParams), ctypes.sizeof(L.BihtParams),
             L.Problem.workspace_bytes.offset, L.BihtParams.Ysign.offset,
-            ctypes.sizeof(L.ServerCfg), ctypes.sizeof(L.Result), L.Result.t_done.offset]
+            ctypes.sizeof(L.ServerCfg), ctypes.sizeof(L.Result), L.Result.t_done.offset,
+            ctypes.sizeof(L.AdmmParams), L.AdmmParams.X0.offset, L.AdmmParams.threshold.offset]
     assert got == want
 
 
@@ -94,6 +97,15 @@ def _gomp(**kw):
     p = L.GompParams()
     p.struct_size = ctypes.sizeof(p)
     p.K, p.S, p.max_iter, p.prune, p.prec = 8, 2, 0, 0, 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _admm(**kw):
+    p = L.AdmmParams()
+    p.struct_size = ctypes.sizeof(p)
+    p.max_iter, p.lambda_, p.alpha, p.eps, p.threshold = 10, 0.01, 1.8, 0.0, 0
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -150,6 +162,35 @@ def test_validation_entry_points_enqueue_nothing(lib):
     p.struct_size = ctypes.sizeof(p)
     p.K, p.max_iter, p.mu, p.mode = 5, 10, 0.1, 1
     assert lib.csrec_biht(ctypes.byref(pb), ctypes.byref(p), ctypes.c_void_p(0x3000), None, None) == L.E_INVAL
+
+
+def test_admm_validation(lib):
+    """ADMM: alpha must be a positive finite number (FP32 too), the threshold
+    one of the two readings, the threshold value finite in FP32; M <= 96."""
+    pb = _problem()
+    assert _ws(lib, L.SOLVER_ADMM, pb, _admm()) == (L.OK, 40 * 40 * 4 // 256 * 256 + 256 * (40 * 40 * 4 % 256 > 0))
+    for bad in (dict(alpha=0.0), dict(alpha=-1.0), dict(alpha=float("nan")), dict(alpha=float("inf")),
+                dict(alpha=1e-50), dict(alpha=1e39), dict(lambda_=-1.0), dict(eps=float("nan")),
+                dict(max_iter=-1), dict(threshold=2), dict(threshold=-1),
+                dict(threshold=1, alpha=1e-30, lambda_=1e10)):
+        assert _ws(lib, L.SOLVER_ADMM, pb, _admm(**bad))[0] == L.E_INVAL, bad
+    wrong = _admm()
+    wrong.struct_size = 8
+    assert _ws(lib, L.SOLVER_ADMM, pb, wrong)[0] == L.E_INVAL
+    assert _ws(lib, L.SOLVER_ADMM, _problem(M=96, N=240), _admm())[0] == L.OK
+    assert _ws(lib, L.SOLVER_ADMM, _problem(M=97, N=240), _admm())[0] == L.E_UNSUPPORTED
+    assert _ws(lib, L.SOLVER_ADMM, _problem(M=40, N=20), _admm())[0] == L.E_SHAPE
+    assert _ws(lib, L.SOLVER_ADMM, _problem(P=0), _admm()) == (L.OK, 0)
+    # entry point: invalid parameters, missing output or workspace return before any launch
+    assert lib.csrec_admm(ctypes.byref(pb), ctypes.byref(_admm(alpha=0.0)), ctypes.c_void_p(0x3000), None,
+                          None) == L.E_INVAL
+    assert lib.csrec_admm(ctypes.byref(pb), ctypes.byref(_admm()), None, None, None) == L.E_INVAL
+    assert lib.csrec_admm(ctypes.byref(pb), ctypes.byref(_admm()), ctypes.c_void_p(0x3000), None,
+                          None) == L.E_WORKSPACE
+    pb.workspace, pb.workspace_bytes = 0x4000, 40 * 40 * 4 - 4
+    assert lib.csrec_admm(ctypes.byref(pb), ctypes.byref(_admm()), ctypes.c_void_p(0x3000), None,
+                          None) == L.E_WORKSPACE
+    assert lib.csrec_admm(ctypes.byref(_problem(P=0)), ctypes.byref(_admm()), None, None, None) == L.OK
 
 
 def test_workspace_sizes(lib):
