@@ -498,6 +498,59 @@ def check_admm_stop_rule(orc):
     assert np.all(o["iters"] == 1) and np.all(o["flags"] == orc.STOP_CONVERGED)
 
 
+# ---------------------------------------------------------------- sparsification (Section II)
+
+def check_sparsify_worked(orc):
+    """Hand-computed cases of the rule |x_n| - mu_x < T sigma_x -> x_n = 0
+    (Psi = I, so x = f)."""
+    # |x| = (3, 1, 0.5, 2): mu = 6.5 / 4 = 1.625; squared deviations sum to
+    # 1.890625 + 0.390625 + 1.265625 + 0.140625 = 3.6875, so sigma = sqrt(3.6875 / 3)
+    # = 1.10867789 (N - 1) and sqrt(3.6875 / 4) = 0.96014322 (N)
+    f = np.array([[3.0, -1.0, 0.5, 2.0]])
+    r = orc.sparsify(f, np.eye(4), 0.1)
+    assert abs(r["mu"][0] - 1.625) < 1e-15 and abs(r["sigma"][0] - math.sqrt(3.6875 / 3)) < 1e-15
+    # T = 0.1: threshold 1.625 + 0.1109 = 1.7359 keeps 3 and 2
+    assert np.array_equal(r["X"], [[3.0, 0.0, 0.0, 2.0]]) and r["kept"][0] == 2
+    # the rule reads |x|: negated entries keep their places and signs
+    assert np.array_equal(orc.sparsify(-f, np.eye(4), 0.1)["X"], [[-3.0, 0.0, 0.0, -2.0]])
+    # T = 0.36: 1.625 + 0.36 sigma is 2.0241 with N - 1 (drops 2) and 1.9706 with N (keeps it)
+    assert np.array_equal(orc.sparsify(f, np.eye(4), 0.36)["X"], [[3.0, 0.0, 0.0, 0.0]])
+    assert np.array_equal(orc.sparsify(f, np.eye(4), 0.36, ddof=0)["X"], [[3.0, 0.0, 0.0, 2.0]])
+    # the inequality is strict: with T = 0 an entry equal to the mean is kept
+    r = orc.sparsify(np.array([[1.0, 2.0, 3.0]]), np.eye(3), 0.0)
+    assert np.array_equal(r["X"], [[0.0, 2.0, 3.0]]) and r["kept"][0] == 2 and r["margin"][0] == 0.0
+    # a non-finite spectrum sparsifies to zero, with nothing kept
+    g = np.array([[1.0, np.nan, 2.0, 0.0], [4.0, 0.0, 0.0, 0.0]])
+    r = orc.sparsify(g, np.eye(4), 0.1)
+    assert np.all(r["X"][0] == 0.0) and r["kept"][0] == 0 and r["kept"][1] == 1
+
+
+def check_sparsify_transform(orc):
+    """x = Psi^T f for an orthonormal, non-symmetric Psi: a spectrum built
+    from 5 large and 59 tiny coefficients keeps exactly the large ones, with
+    their values; keep-all returns f (Parseval); positive scaling commutes;
+    raising T never keeps more."""
+    N = 64
+    Psi = _orthonormal(N, 31)
+    rng = _rng(32)
+    Xt = 0.01 * rng.standard_normal((20, N))
+    sup = np.stack([rng.choice(N, 5, replace=False) for _ in range(20)])
+    for p in range(20):
+        Xt[p, sup[p]] = rng.choice([-1.0, 1.0], 5) * (5.0 + rng.random(5))
+    F = Xt @ Psi.T
+    r = orc.sparsify(F, Psi, 0.1)
+    for p in range(20):
+        assert set(np.nonzero(r["X"][p])[0]) == set(sup[p])
+        assert np.allclose(r["X"][p, sup[p]], Xt[p, sup[p]], atol=1e-12)
+    assert np.allclose(r["F"], r["X"] @ Psi.T, atol=1e-12)
+    assert np.allclose(np.linalg.norm(r["F"], axis=1), np.linalg.norm(r["X"], axis=1), rtol=1e-12)
+    keep_all = orc.sparsify(F, Psi, -1e9)
+    assert np.allclose(keep_all["F"], F, atol=1e-12) and np.all(keep_all["kept"] == N)
+    assert np.allclose(orc.sparsify(7.5 * F, Psi, 0.1)["X"], 7.5 * r["X"], atol=1e-11)
+    k = [orc.sparsify(F, Psi, T)["kept"] for T in (-0.5, 0.0, 0.1, 0.5, 2.0)]
+    assert all(np.all(a >= b) for a, b in zip(k, k[1:]))
+
+
 def check_metrics():
     from oracle import metrics
     ref = _rng(27).standard_normal((10, 20))
@@ -505,6 +558,10 @@ def check_metrics():
     est = ref + 0.01
     assert abs(metrics.psnr(est, ref) - 20.0 * math.log10(5.0 / 0.01)) < 1e-9
     assert metrics.psnr(ref, ref) == float("inf")
+    flags = np.array([1, 2, 1, 3, 8])
+    assert metrics.psnr(ref, ref) == float("inf")
+    from oracle import protocol
+    assert protocol.convergence_ratio(flags, 1) == 3 / 5 and protocol.convergence_ratio(flags, 2) == 2 / 5
     e = np.zeros_like(ref)
     e[:, 0] = 1.0
     assert np.allclose(metrics.rel_err(ref + e, ref), 1.0 / np.linalg.norm(ref, axis=1))
@@ -524,5 +581,5 @@ ORACLE_CHECKS = [
     check_gomp_stop, check_cosamp_orthonormal, check_cosamp_recovery, check_cosamp_no_resolve,
     check_biht_orthonormal, check_biht_first_step, check_biht_second_step_mu,
     check_biht_recovery, check_one_bit, check_admm_matches_sklearn_lasso, check_admm_identity,
-    check_admm_kkt_and_dual, check_admm_stop_rule,
+    check_admm_kkt_and_dual, check_admm_stop_rule, check_sparsify_worked, check_sparsify_transform,
 ]

@@ -9,7 +9,9 @@ import pytest
 
 import oracle_pins as pins
 
-SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "cs.py")
+ORACLE_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
+SRC = os.path.join(ORACLE_DIR, "cs.py")
+PROTOCOL_SRC = os.path.join(ORACLE_DIR, "protocol.py")
 
 # (id, text to replace (first occurrence), replacement)
 MUTATIONS = [
@@ -47,15 +49,26 @@ MUTATIONS = [
     ("admm-dual-not-accumulated", "w_new = zt - z_new", "w_new = x_new - z_new"),
 ]
 
+# mistakes planted in the sparsification (Section II)
+PROTOCOL_MUTATIONS = [
+    ("sparsify-population-std", "def sparsify(F, Psi, T: float, ddof: int = 1)",
+     "def sparsify(F, Psi, T: float, ddof: int = 0)"),
+    ("sparsify-signed-not-magnitude", "mag = np.abs(X)", "mag = X"),
+    ("sparsify-non-strict", "zero = gap < 0.0", "zero = gap <= 0.0"),
+    ("sparsify-transposed-basis", "X = Fc @ Psi ", "X = Fc @ Psi.T "),
+    ("sparsify-no-mean", "gap = (mag - mu[:, None]) - T * sigma[:, None]", "gap = mag - T * sigma[:, None]"),
+    ("sparsify-keeps-nonfinite", "Fc = np.where(fin[:, None], F, 0.0)", "Fc = F"),
+]
 
-def _mutant(old, new):
-    with open(SRC) as f:
+
+def _mutant(old, new, src=SRC):
+    with open(src) as f:
         text = f.read()
     assert text.count(old) >= 1, old
     text = text.replace(old, new, 1)
     mod = types.ModuleType("oracle_mutant")
-    mod.__file__ = SRC
-    exec(compile(text, SRC + ":mutant", "exec"), mod.__dict__)
+    mod.__file__ = src
+    exec(compile(text, src + ":mutant", "exec"), mod.__dict__)
     return mod
 
 
@@ -64,6 +77,18 @@ def test_pins_catch_mutation(mid, old, new):
     mod = _mutant(old, new)
     failed = []
     for check in pins.ORACLE_CHECKS:
+        try:
+            check(mod)
+        except (AssertionError, ValueError, IndexError, FloatingPointError, AttributeError):
+            failed.append(check.__name__)
+    assert failed, f"no pin catches mutation {mid}"
+
+
+@pytest.mark.parametrize("mid,old,new", PROTOCOL_MUTATIONS, ids=[m[0] for m in PROTOCOL_MUTATIONS])
+def test_pins_catch_protocol_mutation(mid, old, new):
+    mod = _mutant(old, new, PROTOCOL_SRC)
+    failed = []
+    for check in (pins.check_sparsify_worked, pins.check_sparsify_transform):
         try:
             check(mod)
         except (AssertionError, ValueError, IndexError, FloatingPointError, AttributeError):
