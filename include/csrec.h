@@ -14,6 +14,10 @@
  *   csrec_cosamp  CoSaMP                                   (Alg. 5)
  *   csrec_admm    ADMM for the LASSO of Eq. 2             (Alg. 2)
  *
+ * and the pre-stage of the paper's evaluation protocol:
+ *
+ *   csrec_sparsify  sparsification of Section II and the compression y = A x_s
+ *
  * Layout.  A is M x N row-major FP32.  Y is P x M row-major FP32 (pixel
  * major: the measurements of one pixel are contiguous).  X is P x N
  * row-major FP32.  All of A, Y, X, support, stats and workspace are DEVICE
@@ -208,6 +212,19 @@ int32_t csrec_biht(const csrec_problem* problem, const csrec_biht_params* params
  * otherwise CSREC_E_UNSUPPORTED.  X may alias X0. */
 int32_t csrec_admm(const csrec_problem* problem, const csrec_admm_params* params, float* X, float* Z,
                    csrec_pixel_stats* stats);
+
+/* Sparsification (Section II) fused with the compression of the sparsified
+ * pixels.  For each of the P spectra f (rows of F, P x N): x = Psi^T f, where
+ * Psi (N x N row-major, f = Psi x) must be orthonormal; mu and sigma are the
+ * mean and the standard deviation of the N values |x_n| (denominator
+ * N - std_ddof: 1 is the sample form, 0 the population form); every x_n with
+ * |x_n| - mu < T sigma is set to 0.  Writes Xs (P x N) = the sparsified x,
+ * Y (P x M) = A Xs, and kept (P int32, nullable) = the entries kept.  A
+ * spectrum with a non-finite value gives x_s = 0, y = 0, kept = 0.  Every
+ * pointer is a device pointer; the decisions are taken in FP32.  Shapes as
+ * csrec_problem, M <= 96.  No workspace. */
+int32_t csrec_sparsify(const float* Psi, const float* A, const float* F, int32_t M, int32_t N, int64_t P,
+                       double T, int32_t std_ddof, float* Xs, float* Y, int32_t* kept, void* stream);
 
 /* Lipschitz constant L = lambda_max(A^T A) of Eq. 2 by power iteration on the device:
  * writes one float to *L_out (device pointer) on `stream`. */

@@ -22,7 +22,7 @@ from . import _lib
 from ._lib import (CsrecError, FLAG_CONVERGED, FLAG_FP64_FALLBACK, FLAG_ITER_CAP,
                    FLAG_NONFINITE, MAX_N)
 
-__all__ = ["fista", "admm", "gomp", "cosamp", "biht", "lipschitz", "Server", "CsrecError", "FLAG_CONVERGED",
+__all__ = ["sparsify", "fista", "admm", "gomp", "cosamp", "biht", "lipschitz", "Server", "CsrecError", "FLAG_CONVERGED",
            "FLAG_ITER_CAP", "FLAG_FP64_FALLBACK", "FLAG_NONFINITE", "MAX_N", "workspace_bytes",
            "library"]
 
@@ -213,6 +213,30 @@ def admm(A, Y, lam: float, alpha: float = 1.8, max_iter: int = 100, eps: float =
                               _ptr(st)), "csrec_admm")
     _keep_alive(ws, A.device, stream)
     return X, Z, _stats_view(st[:P])
+
+
+def sparsify(Psi, A, F, T: float = 0.1, ddof: int = 1, stream=None):
+    """Section II sparsification of the spectra F (P x N) in the basis Psi
+    (f = Psi x), fused with the compression of the sparsified pixels:
+    returns (Xs (P x N), Y = Xs A^T (P x M), kept (P int32))."""
+    torch = _torch()
+    lib = library()
+    _check_dev("A", A, torch.float32)
+    M, N = A.shape
+    _check_dev("Psi", Psi, torch.float32, (N, N))
+    _check_dev("F", F, torch.float32)
+    if F.shape[1] != N:
+        raise ValueError("F must be P x N")
+    P = F.shape[0]
+    Xs = torch.empty((P, N), dtype=torch.float32, device=A.device)
+    Y = torch.empty((P, M), dtype=torch.float32, device=A.device)
+    kept = torch.empty((max(P, 1),), dtype=torch.int32, device=A.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(A.device)
+    sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    _lib.check(lib.csrec_sparsify(_ptr(Psi), _ptr(A), _ptr(F), M, N, P, float(T), int(ddof), _ptr(Xs), _ptr(Y),
+                                  _ptr(kept), ctypes.c_void_p(sp)), "csrec_sparsify")
+    return Xs, Y, kept[:P]
 
 
 def _keep_alive(ws, device, stream):

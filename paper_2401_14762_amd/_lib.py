@@ -152,6 +152,9 @@ SIGNATURES = {
                                     ctypes.c_void_p]),
     "csrec_admm": (ctypes.c_int32, [_P(Problem), _P(AdmmParams), ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p]),
+    "csrec_sparsify": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "csrec_lipschitz": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_void_p]),
     "csrec_server_create": (ctypes.c_int32, [_P(ServerCfg), _P(ctypes.c_void_p)]),

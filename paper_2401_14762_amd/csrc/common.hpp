@@ -77,6 +77,10 @@ int admm_supported(int M, int N);
 size_t admm_workspace(int M);
 int admm_launch(const AdmmLaunch& a);
 
+int sparsify_supported(int M, int N);
+int sparsify_launch(const float* Psi, const float* A, const float* F, int M, int N, int64_t P, float T, int ddof,
+                    float* Xs, float* Y, int32_t* kept, hipStream_t stream);
+
 enum GreedyKind { GREEDY_GOMP = 0, GREEDY_COSAMP = 1, GREEDY_BIHT = 2, GREEDY_BIHT_ONE_BIT = 3 };
 
 struct GreedyLaunch {

@@ -193,6 +193,24 @@ def test_admm_validation(lib):
     assert lib.csrec_admm(ctypes.byref(_problem(P=0)), ctypes.byref(_admm()), None, None, None) == L.OK
 
 
+def test_sparsify_validation(lib):
+    """Shapes, ddof, T and pointers are checked before any launch."""
+    v = ctypes.c_void_p(0x3000)
+    ok = dict(Psi=v, A=v, F=v, M=40, N=100, P=10, T=0.1, ddof=1, Xs=v, Y=v)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.csrec_sparsify(a["Psi"], a["A"], a["F"], a["M"], a["N"], a["P"], a["T"], a["ddof"], a["Xs"],
+                                  a["Y"], None, None)
+    for bad in (dict(M=0), dict(M=100), dict(N=257), dict(P=-1)):
+        assert call(**bad) == L.E_SHAPE, bad
+    for bad in (dict(ddof=2), dict(ddof=-1), dict(T=float("nan")), dict(T=1e39), dict(Psi=None), dict(A=None),
+                dict(F=None), dict(Xs=None), dict(Y=None)):
+        assert call(**bad) == L.E_INVAL, bad
+    assert call(M=97, N=240) == L.E_UNSUPPORTED
+    assert call(P=0, Psi=None, F=None, Xs=None, Y=None) == L.OK
+
+
 def test_workspace_sizes(lib):
     pb = _problem(M=80, N=200, P=65536)
     rc, n = _ws(lib, L.SOLVER_FISTA, pb, _fista())
