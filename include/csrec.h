@@ -132,13 +132,15 @@ typedef struct {
     int32_t struct_size;      /* sizeof(csrec_gomp_params) */
     int32_t K;                /* kappa: sparsity of the returned x, 1 <= K */
     int32_t S;                /* G: atoms added per iteration, 1 <= S <= 8 */
-    int32_t max_iter;         /* 0 = min(K, floor(M / S)); S * max_iter <= min(M, 64) */
+    int32_t max_iter;         /* 0 = min(K, floor(M / S)); S * max_iter <= min(M, 96) */
     double res_tol;           /* stop when ||r|| <= res_tol * ||y|| (0 disables) */
     double eps;               /* stop when Delta < eps (0 disables) */
     int32_t prune;            /* CSREC_PRUNE_EACH or CSREC_PRUNE_FINAL */
     int32_t prec;             /* precision of the correlation A^T r */
     double pivot_fallback;    /* FP64 redo of a pixel when a Cholesky pivot ratio d_j / G_jj falls
-                                 below this (e.g. 1e-6); 0 disables */
+                                 below this (e.g. 1e-6), or when the FP32 error bound of its least
+                                 squares on c, 2^-24 trace(G[c,c]) trace(G[c,c]^-1), exceeds 1
+                                 (|c| near M); 0 disables both */
 } csrec_gomp_params;
 
 /* Alg. 5.  Inputs y, A, kappa (= K), eps. */

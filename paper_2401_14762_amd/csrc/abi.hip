@@ -66,7 +66,7 @@ int fill_gomp(const csrec_problem* p, const csrec_gomp_params* q, GreedyLaunch& 
     if (q->prec != CSREC_PREC_F32) return CSREC_E_UNSUPPORTED;
     const int imax = q->max_iter > 0 ? q->max_iter : (q->K < p->M / q->S ? q->K : p->M / q->S);
     if (imax < 1) return CSREC_E_INVAL;
-    if (q->S * imax > p->M || q->S * imax > GREEDY_CMAX || q->K > GREEDY_CMAX) return CSREC_E_SHAPE;
+    if (q->S * imax > p->M || q->S * imax > GOMP_CMAX || q->K > GOMP_CMAX) return CSREC_E_SHAPE;
     if (p->M > 96) return CSREC_E_UNSUPPORTED;
     if ((e = gomp_coop_supported(p->M, p->N, q->K, q->S, imax))) return e;
     l = GreedyLaunch{};

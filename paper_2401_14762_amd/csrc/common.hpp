@@ -104,7 +104,8 @@ struct GreedyLaunch {
 };
 
 // Largest support the least-squares state can hold.
-constexpr int GREEDY_CMAX = 64;
+constexpr int GREEDY_CMAX = 64;   // CoSaMP and BIHT: largest merged support
+constexpr int GOMP_CMAX = 96;     // gOMP: largest |c| = S * max_iter
 
 size_t greedy_workspace(const GreedyLaunch& a);
 int greedy_launch(const GreedyLaunch& a);

@@ -50,6 +50,7 @@ constexpr int kMaxNG = 4;         // atoms per lane and row: N <= 64 NG
 constexpr int kRowPad = 8;        // rows of the padded copy of A: multiple of 8
 constexpr int kMaxS = 8;
 constexpr int kGJ = 32;           // K up to this: the pruned system is solved in registers
+constexpr int kCU = 6;            // |c| <= 16 kCU entries: per-lane units of the rank and the Gram gather
 
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 
@@ -210,8 +211,11 @@ __device__ __forceinline__ float coldot4(const float* Wf, const float* v, int k,
 // the factor (Wf, zf, bf, idx) of size n.  The slot of row n must hold
 // G[idx[i], atom] for i < n (written before the barrier preceding the call).
 // All 64 lanes call it; `on` masks the pixels that take part.  Returns d / G_jj.
+// With want_sq it also sets row_sq to the squared norm of the new row of W
+// (summed over the pixel's lanes): the rows' squared norms add up to
+// ||W||_F^2 = trace(G[c,c]^{-1}).
 __device__ __forceinline__ float inv_append(bool on, int t, int n, float* Wf, float* zf, float* bf, int* idx, float* ltmp,
-                            int atom, float bj, float gjj) {
+                            int atom, float bj, float gjj, bool want_sq, float& row_sq) {
     float* wn = Wf + tri(n);   // G[idx, atom] now, the new row after the second barrier
     // l = W g (rows i = t + 16u)
     float ll = 0.f;
@@ -233,19 +237,22 @@ __device__ __forceinline__ float inv_append(bool on, int t, int n, float* Wf, fl
     const float dd = d > floor_d ? d : floor_d;
     const float inv = 1.f / sqrtf(dd);
     // new row: w[k] = -(sum_{i>=k} l_i W[i][k]) * inv, w[n] = inv; z_n = w . [b_c, bj]
-    float zp = 0.f;
+    float zp = 0.f, wsq = 0.f;
     if (on) {
         for (int k = t; k < n; k += 16) {
             const float w = -coldot4(Wf, ltmp, k, n) * inv;
             wn[k] = w;
             zp += w * bf[k];
+            wsq += w * w;
         }
         if (t == 0) {
             wn[n] = inv;
             zp += inv * bj;
+            wsq += inv * inv;
         }
     }
     zp = pix_sum(zp);
+    if (want_sq) row_sq = pix_sum(wsq);
     if (on && t == 0) {
         zf[n] = zp;
         bf[n] = bj;
@@ -273,14 +280,15 @@ __device__ __forceinline__ float rank_key(float v) {
 // order over distinct atoms and the ranks are a permutation: q[0..min(K, n))
 // is always fully written.  No barrier inside; s, c, vals must be readable
 // (their writes followed by a barrier).  s and c are read as 16-byte vectors
-// up to n rounded to 4.
+// up to n rounded to 4.  n <= 16 U.
+template <int U>
 __device__ __forceinline__ void rank_top(bool on, int t, int n, int K, const float* s, const int* c,
                                          const float* vals, int* q, float* qv) {
     if (!on) return;
-    float vk[4];
-    int ck[4], rk[4];
+    float vk[U];
+    int ck[U], rk[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
         const int k = t + 16 * u;
         vk[u] = k < n ? rank_key(s[k]) : 0.f;
         ck[u] = k < n ? c[k] : 0;
@@ -295,13 +303,13 @@ __device__ __forceinline__ void rank_top(bool on, int t, int n, int K, const flo
         for (int e = 0; e < 4; ++e) {
             if (i0 + e < n) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < U; ++u)
                     rk[u] += (v4[e] > vk[u] || (v4[e] == vk[u] && c4[e] < ck[u])) ? 1 : 0;
             }
         }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
         const int k = t + 16 * u;
         if (k < n && rk[u] < K) {
             q[rk[u]] = ck[u];
@@ -479,9 +487,12 @@ __device__ __forceinline__ void solve_list(bool on, int t, int n, int nmax, int 
 // Step 3 of Alg. 3 for the pixels with `on`: q = the K entries of c with
 // largest |s| (ties to the lower index), then s_q = G[q,q]^{-1} b_q.
 // Called by every lane (it holds barriers).
-__device__ __forceinline__ void prune_to_q(bool on, int t, int nc, int K, int N, const float* __restrict__ G32,
-                                           const PixLds L) {
-    rank_top(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+__device__ __forceinline__ void prune_to_q(bool on, int t, int nc, int nmax_c, int K, int N,
+                                           const float* __restrict__ G32, const PixLds L) {
+    if (nmax_c > 64)
+        rank_top<kCU>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+    else
+        rank_top<4>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
     __syncthreads();
     solve_list<false>(on, t, K, K, N, G32, L.q, L.bq, L.sq, L.Wq);
 }
@@ -559,6 +570,7 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
 
     bool active = valid && !bad;
     bool converged = false, fallback = false;
+    float trG = 0.f, trW = 0.f;   // trace(G[c,c]) and trace(G[c,c]^{-1}) (FP64 fallback test)
     int iters = 0, nc = 0, nx = 0;
     bool x_on_q = false;
     float last_d2 = __builtin_nanf(""), rn2 = y2;
@@ -634,9 +646,9 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
             float bpart = 0.f;
             if (j >= 0) {
                 const int n = nc + q;
-                float v[4];
+                float v[kCU];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < kCU; ++u) {
                     const int i = t + 16 * u;
                     v[u] = 0.f;
                     if (i <= n) {
@@ -652,7 +664,7 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
                                       : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < kCU; ++u) {
                     const int i = t + 16 * u;
                     if (i <= n) L.W[tri(n) + i] = v[u];
                 }
@@ -670,15 +682,24 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
             const int j = on ? L.sel[q] : 0;
             const float bj = on ? L.bsel[q] : 0.f;
             const float gjj = on ? L.W[tri(nc) + nc] : 1.f;
-            const float ratio = inv_append(on, t, nc, L.W, L.z, L.b, L.c, L.l, j, bj, gjj);
-            if (on && a.pivot_thr > 0.0 && (double)ratio < a.pivot_thr) fallback = true;
+            float row_sq = 0.f;
+            const float ratio = inv_append(on, t, nc, L.W, L.z, L.b, L.c, L.l, j, bj, gjj, a.pivot_thr > 0.0,
+                                           row_sq);
+            if (on && a.pivot_thr > 0.0) {
+                trG += gjj;
+                trW += row_sq;
+                // a small pivot, or the FP32 error bound of the solve on c,
+                // 2^-24 kappa(G[c,c]) <= 2^-24 trace(G[c,c]) trace(G[c,c]^{-1}),
+                // reaching the size of the solution itself
+                if ((double)ratio < a.pivot_thr || trG * trW * 5.9604645e-8f > 1.f) fallback = true;
+            }
             if (on) ++nc;
         }
         inv_solve(active, t, nc, L.W, L.z, L.s);
 
         // ---------------- step 3: prune to K and re-solve on q
         const bool prune_g = active && a.prune == CSREC_PRUNE_EACH && nc > K;
-        if (__any(prune_g)) prune_to_q(prune_g, t, nc, K, N, a.G32, L);
+        if (__any(prune_g)) prune_to_q(prune_g, t, nc, a.CM, K, N, a.G32, L);
         // a pixel that stopped earlier keeps the x of its last iteration
         if (prune_g) {
             nx = K;
@@ -717,7 +738,7 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
     // ---------------- prune placed after the loop (textbook gOMP)
     const bool final_prune = a.prune == CSREC_PRUNE_FINAL && nc > K && valid && !bad;
     if (__any(final_prune)) {
-        prune_to_q(final_prune, t, nc, K, N, a.G32, L);
+        prune_to_q(final_prune, t, nc, a.CM, K, N, a.G32, L);
         float n2 = 0.f;
         if (final_prune) {
             nx = K;
@@ -1032,7 +1053,7 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
         nmax = max(nmax, __shfl_xor(nmax, 1));
         nmax = max(nmax, __shfl_xor(nmax, 2));
         solve_list<true>(active, t, nc, nmax, N, a.G32, c, b, sv, scr);
-        rank_top(active, t, nc, K, sv, c, sv, q, sq);
+        rank_top<4>(active, t, nc, K, sv, c, sv, q, sq);
         if (active) nq = nc < K ? nc : K;
         __syncthreads();
 
@@ -1194,6 +1215,7 @@ size_t gomp_coop_dict_floats(int M, int N) { return (size_t)N * gomp_coop_mp(M) 
 int gomp_coop_supported(int M, int N, int K, int S, int Imax) {
     if (N > 64 * kMaxNG || M > 128 || S > kMaxS) return CSREC_E_UNSUPPORTED;   // M8 <= MP holds for M <= 128
     const int CM = S * Imax;
+    if (CM > 16 * kCU || K > 16 * kCU) return CSREC_E_UNSUPPORTED;
     const size_t lds = kGroups * gomp_coop_lds_floats(gomp_coop_mp(M), CM, K) * sizeof(float);
     return lds <= 160 * 1024 ? CSREC_OK : CSREC_E_UNSUPPORTED;
 }

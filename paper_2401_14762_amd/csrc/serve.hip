@@ -452,7 +452,7 @@ int32_t csrec_server_create(const csrec_server_cfg* cfg, csrec_server** out) {
     p.K = g.K;
     p.S = g.S;
     p.max_iter = g.max_iter > 0 ? g.max_iter : std::min(g.K, 96 / g.S);
-    if (g.S * p.max_iter > GREEDY_CMAX || g.K > GREEDY_CMAX) return CSREC_E_SHAPE;
+    if (g.S * p.max_iter > GOMP_CMAX || g.K > GOMP_CMAX) return CSREC_E_SHAPE;
     p.prune = g.prune;
     p.prec = g.prec;
     p.res_tol = (float)g.res_tol;
