@@ -17,6 +17,13 @@ events and reported under "breakdown" (--legs):
              correction pass and in FP32; gOMP FP32 with the FP64 fallback.
   other      512x512 N=200 M=80 K=15-sparse cube: CoSaMP (Alg. 5), BIHT
              (Alg. 4) and the one-bit BIHT on int8 signs.
+  protocol   the evaluation protocol of Section IV on synthetic cubes of the
+             shapes of its three data sets: sparsification (T = 0.1) and
+             compression on the GPU, then FISTA / ADMM (lambda 0.1, 100),
+             gOMP (G = floor(kappa/5)), BIHT (mu = 0.1) and CoSaMP at its
+             kappa pairs, eps = 1e-8, iteration caps for t_conv: the columns
+             of its Table I (PSNR vs the sparsified data, iterations,
+             convergence ratio, time).
   admm       the headline cube with ADMM (Alg. 2, 200 iterations, lambda=1e-2,
              alpha=1.8, threshold lambda*alpha as printed, FP32).
   serving    Poisson stream of tiles (200 tiles/s, sides log-uniform in
@@ -50,6 +57,8 @@ CORRECTION_ITERS = 20
 OTHER_K, COSAMP_ITERS, BIHT_REAL_ITERS, BIHT_1BIT_ITERS, BIHT_MU = 15, 30, 40, 100, 0.1
 PSNR_SAMPLE = 128
 ADMM_ITERS, ADMM_ALPHA = 200, 1.8
+PROTOCOL_T, PROTOCOL_EPS, PROTOCOL_LAMBDAS = 0.1, 1e-8, (0.1, 100.0)
+PROTOCOL_CONVEX_CAP, PROTOCOL_GREEDY_CAP = 2000, 1000
 
 
 def measured_traffic(kernel_src: str, summary: str):
@@ -77,7 +86,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--pixels", type=int, default=0, help="override the cube size (testing only)")
-    ap.add_argument("--legs", default="precision,other,admm,serving",
+    ap.add_argument("--legs", default="precision,other,admm,protocol,serving",
                     help="comma list of the legs measured after the timed region ('' for none)")
     ap.add_argument("--serve-tiles", type=int, default=400, help="measured serving tiles")
     ap.add_argument("--serve-warmup", type=int, default=40, help="serving tiles before the measured ones")
@@ -206,6 +215,80 @@ def leg_admm(torch, cs, pr, A, Y, stream, idx, samples):
             "achieved_tflops": tf, "mfma_fp32_frac": tf / FP32_MFMA_PEAK_TFLOPS}
 
 
+def leg_protocol(torch, cs, W, dev, stream, samples):
+    """Table I's columns on the synthetic stand-ins of the three data sets."""
+    out = {"workload": f"Section IV protocol on synthetic cubes of the data sets' shapes (peak {W.PAPER_PEAK:g}): "
+                       f"sparsify T={PROTOCOL_T}, 2.5x compression, eps={PROTOCOL_EPS:g}, caps "
+                       f"{PROTOCOL_CONVEX_CAP} (FISTA, ADMM alpha={ADMM_ALPHA}) / {PROTOCOL_GREEDY_CAP} (BIHT, "
+                       f"CoSaMP) iterations; gOMP G=floor(kappa/5) with the FP64 redo at 1e-6", "cubes": {}}
+    samples["protocol"] = {}
+    for ci, name in enumerate(W.PAPER_SHAPES):
+        c = W.paper_shape_cube(name)
+        P, M, N = c["P"], c["M"], c["N"]
+        sidx = W.pixel_subset(P, 256, 60 + ci)
+        smp = samples["protocol"][name] = dict(F=c["F"][sidx], A=c["A"], Psi=c["Psi"], kappas=c["kappas"], gpu={},
+                                               worst={})
+        tsidx = torch.from_numpy(sidx).to(dev)
+        log(f"leg protocol: {name} {P} pixels N={N} M={M}")
+        A = torch.from_numpy(c["A"]).to(dev)
+        Psi = torch.from_numpy(c["Psi"].astype(np.float32)).to(dev)
+        F = torch.from_numpy(c["F"].astype(np.float32)).to(dev)
+        (Xs, Y, kept), ms = event_timed(torch, stream, lambda: cs.sparsify(Psi, A, F, T=PROTOCOL_T))
+        Fs = Xs @ Psi.T
+        peak = torch.max(torch.abs(Fs)).item()
+
+        def quality(X):
+            mse = torch.mean(((X @ Psi.T).double() - Fs.double()) ** 2).item()
+            return 10.0 * math.log10(peak * peak / mse) if mse > 0 else float("inf")
+        flops = P * (2.0 * N * N + 2.0 * M * N)
+        row = {"pixels": P, "N": N, "M": M, "sparsify_ms": ms,
+               "sparsify_tflops": flops / (ms * 1e-3) / 1e12,
+               "zero_fraction": 1.0 - kept.sum().item() / (P * N),
+               "psnr_sparsified_vs_original_db": 10.0 * math.log10(
+                   torch.max(torch.abs(F)).item() ** 2 / torch.mean((Fs.double() - F.double()) ** 2).item()),
+               "solvers": {}}
+        L = float(np.linalg.norm(c["A"].astype(np.float64), 2) ** 2)
+        runs = {}
+        for lam in PROTOCOL_LAMBDAS:
+            runs[f"fista lambda={lam:g}"] = lambda lam=lam: cs.fista(A, Y, lam=lam, L=L, max_iter=PROTOCOL_CONVEX_CAP,
+                                                                     eps=PROTOCOL_EPS)
+            runs[f"admm lambda={lam:g}"] = lambda lam=lam: cs.admm(A, Y, lam=lam, alpha=ADMM_ALPHA,
+                                                                   max_iter=PROTOCOL_CONVEX_CAP, eps=PROTOCOL_EPS)
+        for kap in c["kappas"]:
+            runs[f"gomp kappa={kap}"] = lambda kap=kap: cs.gomp(A, Y, K=kap, S=kap // 5, eps=PROTOCOL_EPS,
+                                                                pivot_fallback=1e-6)
+            if 2 * kap <= min(M, 64):
+                runs[f"biht kappa={kap}"] = lambda kap=kap: cs.biht(A, Y, K=kap, max_iter=PROTOCOL_GREEDY_CAP, mu=BIHT_MU,
+                                                                    eps=PROTOCOL_EPS)
+            else:
+                row["solvers"][f"biht kappa={kap}"] = "unsupported: 2 kappa > min(M, 64)"
+            if 3 * kap <= min(M, 64):
+                runs[f"cosamp kappa={kap}"] = lambda kap=kap: cs.cosamp(A, Y, K=kap, max_iter=PROTOCOL_GREEDY_CAP,
+                                                                        eps=PROTOCOL_EPS)
+            else:
+                row["solvers"][f"cosamp kappa={kap}"] = "unsupported: 3 kappa > min(M, 64)"
+        for label, fn in runs.items():
+            res, ms = event_timed(torch, stream, fn, reps=1)
+            if label.startswith("gomp"):
+                smp["gpu"][label] = res[0][tsidx].cpu().numpy()
+                # the 8 pixels that dominate the cube's error, for the oracle to redo
+                worst = torch.argsort(((res[0] - Xs) ** 2).sum(1), descending=True)[:8].cpu().numpy()
+                smp["worst"][label] = (c["F"][worst], res[0][torch.from_numpy(worst).to(dev)].cpu().numpy())
+            st = res[-1]
+            fl = st["flags"]
+            row["solvers"][label] = {
+                "psnr_vs_sparsified_db": quality(res[0]),
+                "iterations_k": st["iters"].double().sum().item() / 1e3,
+                "convergence_pct": 100.0 * ((fl & 1) != 0).double().mean().item(),
+                "fp64_redo_pixels": int(((fl & 4) != 0).sum().item()),
+                "ms": ms}
+            del res
+        out["cubes"][name] = row
+        del A, Psi, F, Xs, Y, kept, Fs
+        torch.cuda.empty_cache()
+    return out
+
+
 def leg_serving(torch, cs, W, n_tiles, n_warm):
     stream = W.serving_stream(n_warm + n_tiles)
     rate = W.SERVING["rate"]
@@ -292,6 +375,31 @@ def cpu_baseline_leg(W, pr, L, idx_psnr, Xf_s, Xg_s, n_sample, samples):
     if "admm" in samples:
         ref = oracle.admm(pr.A, pr.Y[idx_psnr], LAMBDA, ADMM_ALPHA, ADMM_ITERS)
         q["plain_admm"] = psnr(samples["admm"]["gpu"] @ Psi.T, ref["X"] @ Psi.T)
+    for name, s in samples.get("protocol", {}).items():
+        # the oracle's own sparsification and gOMP on the same 256 pixels:
+        # the GPU's result against the oracle's, and each against the
+        # sparsified spectra (Table I's PSNR) on the sample
+        sp = oracle.sparsify(s["F"].astype(np.float32).astype(np.float64),
+                             s["Psi"].astype(np.float32).astype(np.float64), PROTOCOL_T)
+        Yo = (sp["X"] @ s["A"].astype(np.float64).T).astype(np.float32)
+        for kap in s["kappas"]:
+            ref = oracle.gomp(s["A"], Yo, K=kap, S=kap // 5, eps=PROTOCOL_EPS)
+            g = s["gpu"][f"gomp kappa={kap}"]
+            tag = f"protocol_{name}_gomp_kappa{kap}"
+            q[tag + "_gpu_vs_oracle"] = psnr(g @ s["Psi"].T, ref["X"] @ s["Psi"].T)
+            q[tag + "_gpu_vs_sparsified"] = psnr(g @ s["Psi"].T, sp["F"])
+            q[tag + "_oracle_vs_sparsified"] = psnr(ref["X"] @ s["Psi"].T, sp["F"])
+            # the GPU's 8 worst pixels of the whole cube, solved by the oracle:
+            # squared error of the GPU over that of the oracle (about 1 when the
+            # pixels fail in the algorithm itself, not in the arithmetic)
+            Fw, Xw = s["worst"][f"gomp kappa={kap}"]
+            spw = oracle.sparsify(Fw.astype(np.float32).astype(np.float64),
+                                  s["Psi"].astype(np.float32).astype(np.float64), PROTOCOL_T)
+            Yw = (spw["X"] @ s["A"].astype(np.float64).T).astype(np.float32)
+            rw = oracle.gomp(s["A"], Yw, K=kap, S=kap // 5, eps=PROTOCOL_EPS)
+            e_gpu = float(np.sum((Xw - spw["X"]) ** 2))
+            e_orc = float(np.sum((rw["X"] - spw["X"]) ** 2))
+            q[tag + "_worst8_err_gpu_over_oracle"] = e_gpu / e_orc if e_orc > 0 else None
     if "precision" in samples:
         s = samples["precision"]
         ref = oracle.fista(s["A"], s["Y"], LAMBDA, s["L"], FISTA_ITERS)
@@ -402,6 +510,8 @@ def main():
         breakdown["other_solvers"] = leg_other(torch, cs, W, dev, stream, samples)
     if "admm" in legs:
         breakdown["admm"] = leg_admm(torch, cs, pr, A, Y, stream, idx, samples)
+    if "protocol" in legs:
+        breakdown["protocol"] = leg_protocol(torch, cs, W, dev, stream, samples)
     if "serving" in legs:
         breakdown["serving"] = leg_serving(torch, cs, W, args.serve_tiles, args.serve_warmup)
 

@@ -192,6 +192,32 @@ def other_solvers_cube(P: Optional[int] = None) -> Problem:
                    X_true=X, Ysign=sign, meta=dict(c, P=P))
 
 
+# Synthetic stand-ins for the three data sets of Section IV (same spatial
+# and spectral shapes; the mixing model of mixing_spectra, 40 dB), scaled to
+# a peak of 1e4, the range of the 16-bit sensor counts of those data sets, so
+# that the lambda values of Section IV (0.1 and 100) keep their weight, and
+# the kappa pairs of Section IV for each.
+PAPER_SHAPES = {
+    "salinas-like": dict(config_id=5, rows=512, cols=217, N=224, kappas=(27, 33)),
+    "jasper-like": dict(config_id=6, rows=100, cols=100, N=198, kappas=(18, 24)),
+    "china-like": dict(config_id=7, rows=420, cols=140, N=154, kappas=(16, 22)),
+}
+PAPER_PEAK = 1.0e4
+
+
+def paper_shape_cube(name: str, P: Optional[int] = None) -> dict:
+    """Spectra F (P x N, FP64) of a PAPER_SHAPES cube, the basis Psi and the
+    dictionary A = Phi Psi (FP32) at M = round(N / 2.5)."""
+    c = PAPER_SHAPES[name]
+    N = c["N"]
+    M = m_for(N)
+    P = c["rows"] * c["cols"] if P is None else P
+    _, a32, psi, phi = dictionary(N, M, rng_for(c["config_id"], _S_PHI))
+    F = mixing_spectra(P, N, 40.0, c["config_id"])
+    F *= PAPER_PEAK / float(np.max(np.abs(F)))
+    return dict(name=name, F=F, A=a32, Psi=psi, Phi=phi, M=M, N=N, P=P, kappas=c["kappas"])
+
+
 def pixel_subset(P: int, n: int, config_id: int) -> np.ndarray:
     """Seeded sorted subset of n pixel indices out of P."""
     n = min(n, P)
