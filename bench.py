@@ -19,7 +19,7 @@ events and reported under "breakdown" (--legs):
              (Alg. 4) and the one-bit BIHT on int8 signs.
   protocol   the evaluation protocol of Section IV on synthetic cubes of the
              shapes of its three data sets: sparsification (T = 0.1) and
-             compression on the GPU, then FISTA / ADMM (lambda 0.1, 100),
+             compression (a random 40 % of the bands, as Section IV) on the GPU, then FISTA / ADMM (lambda 0.1, 100),
              gOMP (G = floor(kappa/5)), BIHT (mu = 0.1) and CoSaMP at its
              kappa pairs, eps = 1e-8, iteration caps for t_conv: the columns
              of its Table I (PSNR vs the sparsified data, iterations,
@@ -58,7 +58,7 @@ OTHER_K, COSAMP_ITERS, BIHT_REAL_ITERS, BIHT_1BIT_ITERS, BIHT_MU = 15, 30, 40, 1
 PSNR_SAMPLE = 128
 ADMM_ITERS, ADMM_ALPHA = 200, 1.8
 PROTOCOL_T, PROTOCOL_EPS, PROTOCOL_LAMBDAS = 0.1, 1e-8, (0.1, 100.0)
-PROTOCOL_CONVEX_CAP, PROTOCOL_GREEDY_CAP = 2000, 1000
+PROTOCOL_CONVEX_CAP, PROTOCOL_GREEDY_CAP = 10000, 1000
 
 
 def measured_traffic(kernel_src: str, summary: str):
@@ -218,7 +218,7 @@ def leg_admm(torch, cs, pr, A, Y, stream, idx, samples):
 def leg_protocol(torch, cs, W, dev, stream, samples):
     """Table I's columns on the synthetic stand-ins of the three data sets."""
     out = {"workload": f"Section IV protocol on synthetic cubes of the data sets' shapes (peak {W.PAPER_PEAK:g}): "
-                       f"sparsify T={PROTOCOL_T}, 2.5x compression, eps={PROTOCOL_EPS:g}, caps "
+                       f"sparsify T={PROTOCOL_T}, 2.5x compression by band subsampling, eps={PROTOCOL_EPS:g}, caps "
                        f"{PROTOCOL_CONVEX_CAP} (FISTA, ADMM alpha={ADMM_ALPHA}) / {PROTOCOL_GREEDY_CAP} (BIHT, "
                        f"CoSaMP) iterations; gOMP G=floor(kappa/5) with the FP64 redo at 1e-6", "cubes": {}}
     samples["protocol"] = {}
@@ -390,16 +390,15 @@ def cpu_baseline_leg(W, pr, L, idx_psnr, Xf_s, Xg_s, n_sample, samples):
             q[tag + "_gpu_vs_sparsified"] = psnr(g @ s["Psi"].T, sp["F"])
             q[tag + "_oracle_vs_sparsified"] = psnr(ref["X"] @ s["Psi"].T, sp["F"])
             # the GPU's 8 worst pixels of the whole cube, solved by the oracle:
-            # squared error of the GPU over that of the oracle (about 1 when the
-            # pixels fail in the algorithm itself, not in the arithmetic)
+            # both against the sparsified spectra of those pixels (equal when
+            # the pixels fail in the algorithm itself, not in the arithmetic)
             Fw, Xw = s["worst"][f"gomp kappa={kap}"]
             spw = oracle.sparsify(Fw.astype(np.float32).astype(np.float64),
                                   s["Psi"].astype(np.float32).astype(np.float64), PROTOCOL_T)
             Yw = (spw["X"] @ s["A"].astype(np.float64).T).astype(np.float32)
             rw = oracle.gomp(s["A"], Yw, K=kap, S=kap // 5, eps=PROTOCOL_EPS)
-            e_gpu = float(np.sum((Xw - spw["X"]) ** 2))
-            e_orc = float(np.sum((rw["X"] - spw["X"]) ** 2))
-            q[tag + "_worst8_err_gpu_over_oracle"] = e_gpu / e_orc if e_orc > 0 else None
+            q[tag + "_worst8_gpu_vs_sparsified"] = psnr(Xw @ s["Psi"].T, spw["F"])
+            q[tag + "_worst8_oracle_vs_sparsified"] = psnr(rw["X"] @ s["Psi"].T, spw["F"])
     if "precision" in samples:
         s = samples["precision"]
         ref = oracle.fista(s["A"], s["Y"], LAMBDA, s["L"], FISTA_ITERS)

@@ -13,7 +13,9 @@ Conventions (shared by every consumer):
   a real orthonormal basis keeps A real (A^* = A^T).
 * ``Phi`` is M x N with i.i.d. N(0, 1/M) entries (the paper's randomised
   measurement matrix, Section II), M = round(N / 2.5) for the 2.5x
-  compression of Section IV.
+  compression of Section IV -- or, with ``subsampled_dictionary``, the
+  random selection of M of the N spectral samples that Section IV applies
+  to its data sets (A = the selected rows of Psi).
 * Pixel-major layouts: Y is P x M, X is P x N, both row-major.
 * Every random draw comes from ``numpy.random.default_rng`` seeded with a
   ``SeedSequence([config_id, stream_id])`` so a config is reproducible
@@ -92,6 +94,17 @@ def dictionary(N: int, M: int, phi_seed) -> tuple:
     phi = gaussian_phi(M, N, phi_seed)
     a64 = phi @ psi
     return a64, a64.astype(np.float32), psi, phi
+
+
+def subsampled_dictionary(N: int, M: int, seed) -> tuple:
+    """A = Phi Psi with Phi the random selection of M of the N bands (sorted):
+    y = f[rows], A = Psi[rows, :].  Returns (A64, A32, Psi, Phi, rows)."""
+    psi = dct_synthesis(N)
+    rows = np.sort(np.random.default_rng(seed).choice(N, M, replace=False))
+    phi = np.zeros((M, N))
+    phi[np.arange(M), rows] = 1.0
+    a64 = psi[rows, :].copy()
+    return a64, a64.astype(np.float32), psi, phi, rows
 
 
 def sparse_coefficients(P: int, N: int, K: int, rng_support, rng_values) -> np.ndarray:
@@ -205,17 +218,23 @@ PAPER_SHAPES = {
 PAPER_PEAK = 1.0e4
 
 
-def paper_shape_cube(name: str, P: Optional[int] = None) -> dict:
+def paper_shape_cube(name: str, P: Optional[int] = None, sampling: str = "subsample") -> dict:
     """Spectra F (P x N, FP64) of a PAPER_SHAPES cube, the basis Psi and the
-    dictionary A = Phi Psi (FP32) at M = round(N / 2.5)."""
+    dictionary A = Phi Psi (FP32) at M = round(N / 2.5); sampling
+    "subsample" (Section IV: a random 40 % of the bands) or "gaussian"."""
     c = PAPER_SHAPES[name]
     N = c["N"]
     M = m_for(N)
     P = c["rows"] * c["cols"] if P is None else P
-    _, a32, psi, phi = dictionary(N, M, rng_for(c["config_id"], _S_PHI))
+    if sampling == "subsample":
+        _, a32, psi, phi, _ = subsampled_dictionary(N, M, rng_for(c["config_id"], _S_PHI))
+    elif sampling == "gaussian":
+        _, a32, psi, phi = dictionary(N, M, rng_for(c["config_id"], _S_PHI))
+    else:
+        raise ValueError(sampling)
     F = mixing_spectra(P, N, 40.0, c["config_id"])
     F *= PAPER_PEAK / float(np.max(np.abs(F)))
-    return dict(name=name, F=F, A=a32, Psi=psi, Phi=phi, M=M, N=N, P=P, kappas=c["kappas"])
+    return dict(name=name, F=F, A=a32, Psi=psi, Phi=phi, M=M, N=N, P=P, kappas=c["kappas"], sampling=sampling)
 
 
 def pixel_subset(P: int, n: int, config_id: int) -> np.ndarray:
