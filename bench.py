@@ -257,16 +257,17 @@ def leg_protocol(torch, cs, W, dev, stream, samples):
         for kap in c["kappas"]:
             runs[f"gomp kappa={kap}"] = lambda kap=kap: cs.gomp(A, Y, K=kap, S=kap // 5, eps=PROTOCOL_EPS,
                                                                 pivot_fallback=1e-6)
-            if 2 * kap <= min(M, 64):
+            if 2 * kap <= min(M, 96):
                 runs[f"biht kappa={kap}"] = lambda kap=kap: cs.biht(A, Y, K=kap, max_iter=PROTOCOL_GREEDY_CAP, mu=BIHT_MU,
                                                                     eps=PROTOCOL_EPS)
             else:
-                row["solvers"][f"biht kappa={kap}"] = "unsupported: 2 kappa > min(M, 64)"
-            if 3 * kap <= min(M, 64):
+                row["solvers"][f"biht kappa={kap}"] = "unsupported: 2 kappa > min(M, 96)"
+            if 3 * kap <= min(M, 96):
                 runs[f"cosamp kappa={kap}"] = lambda kap=kap: cs.cosamp(A, Y, K=kap, max_iter=PROTOCOL_GREEDY_CAP,
                                                                         eps=PROTOCOL_EPS)
             else:
-                row["solvers"][f"cosamp kappa={kap}"] = "unsupported: 3 kappa > min(M, 64)"
+                row["solvers"][f"cosamp kappa={kap}"] = ("unsupported: 3 kappa > M (the least squares on the merged "
+                                                         "support would be underdetermined)")
         for label, fn in runs.items():
             res, ms = event_timed(torch, stream, fn, reps=1)
             if label.startswith("gomp"):

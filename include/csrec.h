@@ -146,7 +146,7 @@ typedef struct {
 /* Alg. 5.  Inputs y, A, kappa (= K), eps. */
 typedef struct {
     int32_t struct_size;      /* sizeof(csrec_cosamp_params) */
-    int32_t K;                /* 1 <= K, 3K <= min(M, 64) */
+    int32_t K;                /* 1 <= K, 3K <= min(M, 96) */
     int32_t max_iter;         /* >= 0 */
     double eps;               /* stop when Delta < eps (0 disables) */
     double res_tol;           /* stop when ||r|| <= res_tol * ||y|| (0 disables) */
@@ -156,7 +156,7 @@ typedef struct {
 /* Alg. 4 (REAL) or binary IHT (ONE_BIT).  Inputs y, A, kappa (= K), mu, eps. */
 typedef struct {
     int32_t struct_size;      /* sizeof(csrec_biht_params) */
-    int32_t K;                /* REAL: 1 <= K, 2K <= min(M, 64);  ONE_BIT: 1 <= K <= N */
+    int32_t K;                /* REAL: 1 <= K, 2K <= min(M, 96);  ONE_BIT: 1 <= K <= min(N, 64) */
     int32_t max_iter;         /* >= 0 */
     double mu;                /* gradient step (0.1 in Section IV) */
     double eps;               /* REAL: stop when Delta < eps (0 disables) */

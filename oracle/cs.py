@@ -429,6 +429,7 @@ def cosamp(A, Y, K: int, max_iter: int, eps: float = 0.0, res_tol: float = 0.0,
     flags[~fin] |= STOP_NONFINITE
     sel_gap = np.full(P, np.inf)
     prune_gap = np.full(P, np.inf)
+    ls_cond = np.full(P, np.nan)
     active = fin.copy()
     for i in range(1, max_iter + 1):
         if not active.any():
@@ -441,6 +442,8 @@ def cosamp(A, Y, K: int, max_iter: int, eps: float = 0.0, res_tol: float = 0.0,
             sel_gap[a] = np.minimum(sel_gap[a], _ordered_gap(p, 2 * K))
         cs = [np.union1d(theta[j], cprev[a[j]]) for j in range(len(a))]
         ss = _lstsq_ragged(A, ya, cs)                               # step 2
+        if diagnostics:
+            ls_cond[a] = [np.linalg.cond(A[:, cj]) for cj in cs]
         xa = np.zeros((len(a), N))
         for j in range(len(a)):
             full = np.zeros(N)
@@ -469,7 +472,8 @@ def cosamp(A, Y, K: int, max_iter: int, eps: float = 0.0, res_tol: float = 0.0,
     resid = np.linalg.norm(Yc - x @ A.T, axis=1)
     out = dict(X=x, support=support, iters=iters, delta=delta, resid=resid, flags=flags)
     if diagnostics:
-        out.update(sel_gap=sel_gap, prune_gap=prune_gap)
+        # ls_cond: condition number of A(:, c) of the last solve (step 2)
+        out.update(sel_gap=sel_gap, prune_gap=prune_gap, ls_cond=ls_cond)
     return out
 
 

@@ -115,7 +115,7 @@ int fill_biht(const csrec_problem* p, const csrec_biht_params* q, GreedyLaunch& 
         return CSREC_E_INVAL;
     if ((e = check_prec(q->prec))) return e;
     if (q->prec != CSREC_PREC_F32) return CSREC_E_UNSUPPORTED;
-    if (one ? (q->K > p->N || q->K > GREEDY_CMAX) : (2 * q->K > p->M || 2 * q->K > GREEDY_CMAX))
+    if (one ? (q->K > p->N || q->K > 64) : (2 * q->K > p->M || 2 * q->K > GREEDY_CMAX))
         return CSREC_E_SHAPE;
     if (p->M > 96) return CSREC_E_UNSUPPORTED;
     l = GreedyLaunch{};

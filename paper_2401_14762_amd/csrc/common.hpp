@@ -104,7 +104,7 @@ struct GreedyLaunch {
 };
 
 // Largest support the least-squares state can hold.
-constexpr int GREEDY_CMAX = 64;   // CoSaMP and BIHT: largest merged support
+constexpr int GREEDY_CMAX = 96;   // CoSaMP and BIHT: largest merged support (3K, 2K)
 constexpr int GOMP_CMAX = 96;     // gOMP: largest |c| = S * max_iter
 
 size_t greedy_workspace(const GreedyLaunch& a);

@@ -1053,7 +1053,10 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
         nmax = max(nmax, __shfl_xor(nmax, 1));
         nmax = max(nmax, __shfl_xor(nmax, 2));
         solve_list<true>(active, t, nc, nmax, N, a.G32, c, b, sv, scr);
-        rank_top<4>(active, t, nc, K, sv, c, sv, q, sq);
+        if (other_nc(KIND, K) > 64)
+            rank_top<kCU>(active, t, nc, K, sv, c, sv, q, sq);
+        else
+            rank_top<4>(active, t, nc, K, sv, c, sv, q, sq);
         if (active) nq = nc < K ? nc : K;
         __syncthreads();
 
@@ -1266,7 +1269,9 @@ size_t coop_other_lds_floats(int kind, int M, int N, int K) {
 
 int coop_other_supported(int kind, int M, int N, int K) {
     if (N > 64 * kMaxNG || M > 128) return CSREC_E_UNSUPPORTED;
-    if (kind == GREEDY_COSAMP ? 2 * K > 64 : K > 64) return CSREC_E_UNSUPPORTED;   // selection bits per lane
+    // the previous support is read by 4 units of 16 lanes (K <= 64); the
+    // merged support is ranked by up to kCU units
+    if (K > 64 || other_nc(kind, K) > 16 * kCU) return CSREC_E_UNSUPPORTED;
     const size_t lds = kGroups * coop_other_lds_floats(kind, M, N, K) * sizeof(float);
     return lds <= 160 * 1024 ? CSREC_OK : CSREC_E_UNSUPPORTED;
 }
