@@ -263,6 +263,261 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void fista_f32_kernel(FistaArgs a
     }
 }
 
+template <int MT, int NT, int WAVES, int MINW, bool FREEZE>
+__device__ __forceinline__ void fista_f32s_body(const FistaArgs& a, const v4f* __restrict__ sA1,
+                                                const v4f* __restrict__ sA2) {
+    const int M = a.M, N = a.N;
+    float invL = a.invL, thr = a.thr;
+    if (a.L_dev) {
+        const float L = *a.L_dev;
+        invL = 1.f / L;
+        thr = (float)(a.lambda / (double)L);
+    }
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 4;
+    const int j = lane & 15;
+    const int64_t pix = ((int64_t)blockIdx.x * WAVES + wave) * 16 + j;
+    const bool valid = pix < a.P;
+
+    const int mu_j = 8 * ((j >> 2) & 1) + 4 * (j >> 3) + (j & 3);  // m of output row j (GEMM 1)
+    const int nu_j = 4 * (j & 3) + (j >> 2);                       // n of output row j (GEMM 2)
+    const int cm_h = 8 * (h & 1) + 4 * (h >> 1);
+    const v4f* a1 = sA1 + lane;   // + (mt NT + nt) 64: A[16 mt + mu_j][16 nt + 4 kk + h], kk = 0..3
+    const v4f* a2 = sA2 + lane;   // + (nt MT + mt) 64: A[16 mt + cm_h + kk][16 nt + nu_j], kk = 0..3
+
+    // ---- measurements, non-finite check
+    v4f Yr[MT];
+    int bad = 0;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * mt + cm_h + r;
+            float v = 0.f;
+            if (valid && m < M) {
+                v = a.Y[pix * M + m];
+                if (!isfinite(v)) bad = 1;
+            }
+            Yr[mt][r] = v;
+        }
+    bad |= __shfl_xor(bad, 16);
+    bad |= __shfl_xor(bad, 32);
+    if (bad) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) Yr[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+
+    // ---- starting point x^0 (z^0 = x^0)
+    v4f Xr[NT], Zr[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * nt + 4 * r + h;
+            float v = 0.f;
+            if (a.X0 && valid && !bad && n < N) v = a.X0[pix * N + n];
+            Xr[nt][r] = v;
+            Zr[nt][r] = v;
+        }
+
+    // U_0 = A x^0 - y; U_{-1} = U_0 (so z^0 = x^0 whatever b_0 is)
+    v4f U1[MT], V[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) U1[mt] = -Yr[mt];
+    if (a.X0) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const v4f av = a1[(mt * NT + nt) * 64];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    U1[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], Xr[nt][kk], U1[mt], 0, 0, 0);
+            }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) V[mt] = U1[mt];
+
+    bool active = valid && !bad;
+    bool converged = false;
+    int iters = 0;
+    float last_d2 = __builtin_nanf("");
+    double t = 1.0;
+    float bprev = 0.f;
+    const bool check_eps = a.eps > 0.f;
+
+    for (int it = 0; it < a.max_iter; ++it) {
+        // keeps the LDS operand reads inside the loop (they are loop-invariant,
+        // and hoisting them would need every element of A in registers)
+        asm volatile("" ::: "memory");
+        const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));   // step 3
+        const float bcur = (float)((t - 1.0) / tn);                  // step 4 coefficient
+        t = tn;
+
+        // V = A z^{i-1} - y
+        const float cp = 1.f + bprev;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) V[mt] = cp * U1[mt] - bprev * V[mt];
+
+        v4f Un[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) Un[mt] = -Yr[mt];
+
+        v4f Wn = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const v4f av = a2[mt * 64];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                Wn = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], V[mt][kk], Wn, 0, 0, 0);
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            // W = (A^T V) for 16 n-values of this tile          (step 1)
+            const v4f W = Wn;
+            if (nt + 1 < NT) {
+                Wn = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const v4f av = a2[((nt + 1) * MT + mt) * 64];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+                        Wn = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], V[mt][kk], Wn, 0, 0, 0);
+                }
+            }
+            // steps 1, 2, 4 elementwise
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float aux = Zr[nt][r] - W[r] * invL;
+                // sign(v) max(|v| - t, 0) = v - median(v, -t, t), bit for bit
+                const float xn = aux - __builtin_amdgcn_fmed3f(aux, -thr, thr);
+                const float zn = xn + bcur * (xn - Xr[nt][r]);
+                // without the Delta stop every pixel runs the whole loop (a pixel
+                // with zero y and zero x^0 stays at zero): nothing to freeze
+                Xr[nt][r] = (!FREEZE || active) ? xn : Xr[nt][r];
+                Zr[nt][r] = (!FREEZE || active) ? zn : Zr[nt][r];
+            }
+            // U_i += A(:, tile) x^i(tile)                        (step 5)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const v4f av = a1[(mt * NT + nt) * 64];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    Un[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], Xr[nt][kk], Un[mt], 0, 0, 0);
+            }
+        }
+
+        // Delta^2 = ||r^i - r^{i-1}||^2 with r^0 = y: the reference is U_{i-1},
+        // except in the first iteration from a given x^0, where it is -y.
+        const float c0 = (it == 0 && a.X0) ? 1.f : 0.f;
+        float d2 = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float ref = U1[mt][r] - c0 * (U1[mt][r] + Yr[mt][r]);
+                const float d = Un[mt][r] - ref;
+                d2 += d * d;
+            }
+        d2 = quad_sum(d2);
+        if (active) {
+            iters = it + 1;
+            last_d2 = d2;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            V[mt] = U1[mt];
+            U1[mt] = (!FREEZE || active) ? Un[mt] : U1[mt];
+        }
+        bprev = bcur;
+        if (check_eps) {
+            if (active && sqrtf(d2) < a.eps) {
+                active = false;
+                converged = true;
+            }
+            if (!__any(active)) break;
+        }
+    }
+
+    float r2 = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) r2 += U1[mt][r] * U1[mt][r];
+    r2 = quad_sum(r2);
+
+    if (valid) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * nt + 4 * r + h;
+                if (n < N) a.X[pix * N + n] = bad ? 0.f : Xr[nt][r];
+            }
+        if (a.stats && h == 0) {
+            csrec_pixel_stats s;
+            s.iters = bad ? 0 : iters + a.iter_offset;
+            s.flags = bad ? CSREC_FLAG_NONFINITE : (converged ? CSREC_FLAG_CONVERGED : CSREC_FLAG_ITER_CAP);
+            s.resid = bad ? 0.f : sqrtf(r2);
+            s.delta = bad ? __builtin_nanf("") : sqrtf(last_d2);
+            a.stats[pix] = s;
+        }
+    }
+}
+
+
+// The same iteration with A stored twice in LDS, pre-arranged so that the
+// four operand values a lane feeds to four consecutive MFMAs (k-steps kk =
+// 0..3 of one 16x16 tile of A or A^T) are 16 contiguous bytes: one
+// ds_read_b128 per four MFMAs, conflict-free (lane l reads bytes 16 l ..
+// 16 l + 15 of its tile's 1 KiB).  Two copies take 2 MT NT KiB, so this form
+// serves shapes with MT NT <= 80 (M = 80, N = 200 among them).  The A^T V
+// product of tile nt + 1 is issued before the epilogue of tile nt, so the
+// matrix cores work while the epilogue's vector instructions run; soft
+// thresholding is v - median(v, -t, t); and without the Delta stop no pixel
+// is frozen, which drops the per-element selects.
+template <int MT, int NT, int WAVES, int MINW>
+__global__ __launch_bounds__(WAVES * 64, MINW) void fista_f32s_kernel(FistaArgs a) {
+    constexpr int BLK = MT * NT * 64;
+    __shared__ v4f sA1[BLK];   // [mt][nt][lane]
+    __shared__ v4f sA2[BLK];   // [nt][mt][lane]
+    const int M = a.M, N = a.N;
+    for (int idx = threadIdx.x; idx < BLK; idx += WAVES * 64) {
+        const int l = idx & 63, blk = idx >> 6;
+        const int hh = l >> 4, jj = l & 15;
+        const int mu = 8 * ((jj >> 2) & 1) + 4 * (jj >> 3) + (jj & 3);
+        const int nu = 4 * (jj & 3) + (jj >> 2);
+        const int cm = 8 * (hh & 1) + 4 * (hh >> 1);
+        v4f v1, v2;
+        {
+            const int mt = blk / NT, nt = blk - (blk / NT) * NT;
+            const int row = 16 * mt + mu;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int col = 16 * nt + 4 * kk + hh;
+                v1[kk] = (row < M && col < N) ? a.A[(size_t)row * N + col] : 0.f;
+            }
+        }
+        {
+            const int nt = blk / MT, mt = blk - (blk / MT) * MT;
+            const int col = 16 * nt + nu;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int row = 16 * mt + cm + kk;
+                v2[kk] = (row < M && col < N) ? a.A[(size_t)row * N + col] : 0.f;
+            }
+        }
+        sA1[idx] = v1;
+        sA2[idx] = v2;
+    }
+    __syncthreads();
+    if (a.eps > 0.f)
+        fista_f32s_body<MT, NT, WAVES, MINW, true>(a, sA1, sA2);
+    else
+        fista_f32s_body<MT, NT, WAVES, MINW, false>(a, sA1, sA2);
+}
+
 // ---------------------------------------------------------------- 16-bit operands
 //
 // Same iteration with the two products on v_mfma_f32_16x16x32_{bf16,f16}:
@@ -525,6 +780,16 @@ const FistaVariant kVariants[] = {
     {8, 16, 4, fista_f32_kernel<8, 16, 4, 1>},
 };
 
+// The pre-arranged form (two LDS copies of A), for the shapes it fits.
+const FistaVariant kVariantsS[] = {
+    {1, 2, 4, fista_f32s_kernel<1, 2, 4, 2>},
+    {2, 4, 4, fista_f32s_kernel<2, 4, 4, 2>},
+    {3, 7, 4, fista_f32s_kernel<3, 7, 4, 2>},
+    {4, 8, 4, fista_f32s_kernel<4, 8, 4, 2>},
+    {4, 10, 4, fista_f32s_kernel<4, 10, 4, 1>},
+    {5, 13, 4, fista_f32s_kernel<5, 13, 4, 1>},
+};
+
 const FistaVariant kVariantsBF16[] = {
     {2, 8, 4, fista_lp_kernel<__bf16, 2, 8, 4, 2>},
     {4, 8, 4, fista_lp_kernel<__bf16, 4, 8, 4, 2>},
@@ -552,7 +817,9 @@ const FistaVariant* pick_from(const FistaVariant (&vs)[K], int M, int N) {
 const FistaVariant* pick(int M, int N, int prec) {
     if (prec == CSREC_PREC_BF16) return pick_from(kVariantsBF16, M, N);
     if (prec == CSREC_PREC_F16) return pick_from(kVariantsF16, M, N);
-    return pick_from(kVariants, M, N);
+    const FistaVariant* v = pick_from(kVariants, M, N);
+    const FistaVariant* w = pick_from(kVariantsS, M, N);
+    return (w && v && w->MT == v->MT && w->NT == v->NT) ? w : v;
 }
 
 const FistaVariant* pick_f32(int M, int N) {
