@@ -48,11 +48,6 @@ struct AdmmArgs {
     float alpha, thr, eps;
 };
 
-__device__ __forceinline__ float soft_thr(float v, float t) {
-    const float a = fabsf(v) - t;
-    return a > 0.f ? copysignf(a, v) : 0.f;
-}
-
 __device__ __forceinline__ float quad_sum(float v) {
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);
@@ -281,7 +276,7 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void admm_f32_kernel(AdmmArgs a) 
             for (int r = 0; r < 4; ++r) {
                 const float x = (Zr[nt][r] - Wr[nt][r]) + G[r];   // step 1
                 const float zt = x + Wr[nt][r];
-                const float zn = soft_thr(zt, thr);                // step 2
+                const float zn = zt - __builtin_amdgcn_fmed3f(zt, -thr, thr);   // step 2: soft threshold
                 const float wn = zt - zn;                          // step 3
                 // a pixel's last iteration keeps x^i in place of w^i, which
                 // no output needs: the frozen registers then hold x^I, z^I
@@ -351,6 +346,258 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void admm_f32_kernel(AdmmArgs a) 
     }
 }
 
+// The same iteration with A (twice) and R in LDS pre-arranged in the MFMA
+// operand order, as in the pre-arranged FISTA kernel: the four operand values
+// a lane feeds to four consecutive MFMAs are 16 contiguous bytes (one
+// ds_read_b128).  2 MT NT + MT^2 KiB of LDS: shapes with 2 MT NT + MT^2 <= 155.
+template <int MT, int NT, int WAVES, int MINW>
+__global__ __launch_bounds__(WAVES * 64, MINW) void admm_f32s_kernel(AdmmArgs a) {
+    constexpr int BA = MT * NT * 64;
+    constexpr int BR = MT * MT * 64;
+    __shared__ v4f sA1[BA];   // [mt][nt][lane]: A[16 mt + mu_j][16 nt + 4 kk + h]
+    __shared__ v4f sA2[BA];   // [nt][mt][lane]: A[16 mt + cm_h + kk][16 nt + nu_j]
+    __shared__ v4f sR3[BR];   // [mt][ms][lane]: R[16 ms + cm_h + kk][16 mt + mu_j]
+
+    const int M = a.M, N = a.N;
+    for (int idx = threadIdx.x; idx < BA + BR; idx += WAVES * 64) {
+        const int l = idx & 63;
+        const int hh = l >> 4, jj = l & 15;
+        const int mu = 8 * ((jj >> 2) & 1) + 4 * (jj >> 3) + (jj & 3);
+        const int nu = 4 * (jj & 3) + (jj >> 2);
+        const int cm = 8 * (hh & 1) + 4 * (hh >> 1);
+        if (idx < BA) {
+            const int blk = idx >> 6;
+            v4f v1, v2;
+            {
+                const int mt = blk / NT, nt = blk - (blk / NT) * NT;
+                const int row = 16 * mt + mu;
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int col = 16 * nt + 4 * kk + hh;
+                    v1[kk] = (row < M && col < N) ? a.A[(size_t)row * N + col] : 0.f;
+                }
+            }
+            {
+                const int nt = blk / MT, mt = blk - (blk / MT) * MT;
+                const int col = 16 * nt + nu;
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int row = 16 * mt + cm + kk;
+                    v2[kk] = (row < M && col < N) ? a.A[(size_t)row * N + col] : 0.f;
+                }
+            }
+            sA1[idx] = v1;
+            sA2[idx] = v2;
+        } else {
+            const int blk = (idx - BA) >> 6;
+            const int mt = blk / MT, ms = blk - (blk / MT) * MT;
+            const int col = 16 * mt + mu;
+            v4f v;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int row = 16 * ms + cm + kk;
+                v[kk] = (row < M && col < M) ? a.R[row * M + col] : 0.f;
+            }
+            sR3[idx - BA] = v;
+        }
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 4;
+    const int j = lane & 15;
+    const int64_t pix = ((int64_t)blockIdx.x * WAVES + wave) * 16 + j;
+    const bool valid = pix < a.P;
+
+    const int mu_j = 8 * ((j >> 2) & 1) + 4 * (j >> 3) + (j & 3);  // m of output row j (A v, R t)
+    const int nu_j = 4 * (j & 3) + (j >> 2);                       // n of output row j (A^T e)
+    const int cm_h = 8 * (h & 1) + 4 * (h >> 1);
+    const v4f* a1 = sA1 + lane;   // + (mt NT + nt) 64
+    const v4f* a2 = sA2 + lane;   // + (nt MT + mt) 64
+    const v4f* a3 = sR3 + lane;   // + (mt MT + ms) 64
+
+    // ---- measurements, non-finite check
+    v4f Rp[MT];   // r^{i-1}; r^0 = y
+    int bad = 0;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * mt + cm_h + r;
+            float v = 0.f;
+            if (valid && m < M) {
+                v = a.Y[pix * M + m];
+                if (!isfinite(v)) bad = 1;
+            }
+            Rp[mt][r] = v;
+        }
+    bad |= __shfl_xor(bad, 16);
+    bad |= __shfl_xor(bad, 32);
+    if (bad) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) Rp[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+
+    // q = R y
+    v4f Q[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        Q[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ms = 0; ms < MT; ++ms) {
+            const v4f rv = a3[(mt * MT + ms) * 64];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                Q[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[kk], Rp[ms][kk], Q[mt], 0, 0, 0);
+        }
+    }
+
+    // z^0 = w^0 = x^0
+    v4f Zr[NT], Wr[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * nt + 4 * r + h;
+            float v = 0.f;
+            if (a.X0 && valid && !bad && n < N) v = a.X0[pix * N + n];
+            Zr[nt][r] = v;
+            Wr[nt][r] = v;
+        }
+
+    // T = -A v^1 = A (w^0 - z^0) = 0
+    v4f T[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) T[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    bool active = valid && !bad;
+    bool converged = false;
+    int iters = 0;
+    float last_d2 = __builtin_nanf("");
+    const float alpha = a.alpha, thr = a.thr;
+    const bool check_eps = a.eps > 0.f;
+
+    for (int it = 0; it < a.max_iter; ++it) {
+        // keeps the LDS operand reads inside the loop (they are loop-invariant,
+        // and hoisting them would need every element of A and R in registers)
+        asm volatile("" ::: "memory");
+        // e = q - R A v = q + R T
+        v4f E[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            E[mt] = Q[mt];
+#pragma unroll
+            for (int ms = 0; ms < MT; ++ms) {
+                const v4f rv = a3[(mt * MT + ms) * 64];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    E[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[kk], T[ms][kk], E[mt], 0, 0, 0);
+            }
+        }
+        // step 4 ahead of the x update: r^i = alpha e, Delta = ||r^i - r^{i-1}||
+        float d2 = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float d = alpha * E[mt][r] - Rp[mt][r];
+                d2 += d * d;
+            }
+        d2 = quad_sum(d2);
+        const bool stop = check_eps && sqrtf(d2) < a.eps;
+        const bool last = active && (stop || it + 1 == a.max_iter);
+
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) T[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            // A^T e for 16 n-values of this tile
+            v4f G = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const v4f av = a2[(nt * MT + mt) * 64];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    G = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], E[mt][kk], G, 0, 0, 0);
+            }
+            v4f Vn;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float x = (Zr[nt][r] - Wr[nt][r]) + G[r];   // step 1
+                const float zt = x + Wr[nt][r];
+                const float zn = zt - __builtin_amdgcn_fmed3f(zt, -thr, thr);   // step 2: soft threshold
+                const float wn = zt - zn;                          // step 3
+                // a pixel's last iteration keeps x^i in place of w^i, which
+                // no output needs: the frozen registers then hold x^I, z^I
+                Vn[r] = wn - zn;
+                Zr[nt][r] = active ? zn : Zr[nt][r];
+                Wr[nt][r] = active ? (last ? x : wn) : Wr[nt][r];
+            }
+            // T = -A v of the next iteration, accumulated tile by tile
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const v4f av = a1[(mt * NT + nt) * 64];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    T[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], Vn[kk], T[mt], 0, 0, 0);
+            }
+        }
+        if (active) {
+            iters = it + 1;
+            last_d2 = d2;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) Rp[mt] = alpha * E[mt];
+        }
+        if (last) {
+            active = false;
+            converged = stop;
+        }
+        if (!__any(active)) break;
+    }
+
+    // ||y - A x^I||: r^I for pixels that iterated, y - A x^0 otherwise
+    if (a.max_iter == 0) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const v4f av = a1[(mt * NT + nt) * 64];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    Rp[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], -Zr[nt][kk], Rp[mt], 0, 0, 0);
+            }
+    }
+    float r2 = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) r2 += Rp[mt][r] * Rp[mt][r];
+    r2 = quad_sum(r2);
+
+    if (valid) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * nt + 4 * r + h;
+                if (n < N) {
+                    // a pixel that never iterated returns x^0 (0 when its y is not finite)
+                    a.X[pix * N + n] = iters == 0 ? Zr[nt][r] : Wr[nt][r];
+                    if (a.Z) a.Z[pix * N + n] = Zr[nt][r];
+                }
+            }
+        if (a.stats && h == 0) {
+            csrec_pixel_stats s;
+            s.iters = iters;
+            s.flags = bad ? CSREC_FLAG_NONFINITE : (converged ? CSREC_FLAG_CONVERGED : CSREC_FLAG_ITER_CAP);
+            s.resid = bad ? 0.f : sqrtf(r2);
+            s.delta = bad ? __builtin_nanf("") : sqrtf(last_d2);
+            a.stats[pix] = s;
+        }
+    }
+}
+
 typedef void (*admm_kernel_t)(AdmmArgs);
 
 struct AdmmVariant {
@@ -371,11 +618,22 @@ const AdmmVariant kAdmmVariants[] = {
     {6, 16, 4, admm_f32_kernel<6, 16, 4, 1>},
 };
 
+const AdmmVariant kAdmmVariantsS[] = {
+    {1, 2, 4, admm_f32s_kernel<1, 2, 4, 2>},
+    {2, 4, 4, admm_f32s_kernel<2, 4, 4, 2>},
+    {3, 7, 4, admm_f32s_kernel<3, 7, 4, 2>},
+    {4, 8, 4, admm_f32s_kernel<4, 8, 4, 2>},
+    {4, 10, 4, admm_f32s_kernel<4, 10, 4, 1>},
+    {5, 13, 4, admm_f32s_kernel<5, 13, 4, 1>},
+};
+
 const AdmmVariant* admm_pick(int M, int N) {
     const int mt = (int)ceil_div(M, 16), nt = (int)ceil_div(N, 16);
     const AdmmVariant* best = nullptr;
     for (const auto& v : kAdmmVariants)
         if (v.MT >= mt && v.NT >= nt && (!best || v.MT * v.NT < best->MT * best->NT)) best = &v;
+    for (const auto& v : kAdmmVariantsS)   // the pre-arranged form of the same tile shape, where it fits
+        if (best && v.MT == best->MT && v.NT == best->NT) return &v;
     return best;
 }
 
