@@ -58,7 +58,7 @@ OTHER_K, COSAMP_ITERS, BIHT_REAL_ITERS, BIHT_1BIT_ITERS, BIHT_MU = 15, 30, 40, 1
 PSNR_SAMPLE = 128
 ADMM_ITERS, ADMM_ALPHA = 200, 1.8
 PROTOCOL_T, PROTOCOL_EPS, PROTOCOL_LAMBDAS = 0.1, 1e-8, (0.1, 100.0)
-PROTOCOL_CONVEX_CAP, PROTOCOL_GREEDY_CAP = 10000, 1000
+PROTOCOL_CONVEX_CAP, PROTOCOL_BIHT_CAP, PROTOCOL_COSAMP_CAP = 10000, 1000, 200
 
 
 def measured_traffic(kernel_src: str, summary: str):
@@ -72,7 +72,7 @@ def measured_traffic(kernel_src: str, summary: str):
     except OSError:
         return None
     m = re.search(r"fista\.hip sha256 at measurement: `([0-9a-f]+)`", text)
-    row = re.search(r"fista_f32_kernel<[^|]*\| *\d+ *\| *\d+ *\| *([0-9.]+) MB", text)
+    row = re.search(r"fista_f32s?_kernel<5, 13[^|]*\| *\d+ *\| *\d+ *\| *([0-9.]+) MB", text)
     if not m or not row or m.group(1) != sha:
         return None
     return float(row.group(1)) * 1e6
@@ -219,8 +219,8 @@ def leg_protocol(torch, cs, W, dev, stream, samples):
     """Table I's columns on the synthetic stand-ins of the three data sets."""
     out = {"workload": f"Section IV protocol on synthetic cubes of the data sets' shapes (peak {W.PAPER_PEAK:g}): "
                        f"sparsify T={PROTOCOL_T}, 2.5x compression by band subsampling, eps={PROTOCOL_EPS:g}, caps "
-                       f"{PROTOCOL_CONVEX_CAP} (FISTA, ADMM alpha={ADMM_ALPHA}) / {PROTOCOL_GREEDY_CAP} (BIHT, "
-                       f"CoSaMP) iterations; gOMP G=floor(kappa/5) with the FP64 redo at 1e-6", "cubes": {}}
+                       f"{PROTOCOL_CONVEX_CAP} (FISTA, ADMM alpha={ADMM_ALPHA}) / {PROTOCOL_BIHT_CAP} (BIHT) / "
+                       f"{PROTOCOL_COSAMP_CAP} (CoSaMP) iterations; gOMP G=floor(kappa/5) with the FP64 redo at 1e-6", "cubes": {}}
     samples["protocol"] = {}
     for ci, name in enumerate(W.PAPER_SHAPES):
         c = W.paper_shape_cube(name)
@@ -258,12 +258,12 @@ def leg_protocol(torch, cs, W, dev, stream, samples):
             runs[f"gomp kappa={kap}"] = lambda kap=kap: cs.gomp(A, Y, K=kap, S=kap // 5, eps=PROTOCOL_EPS,
                                                                 pivot_fallback=1e-6)
             if 2 * kap <= min(M, 96):
-                runs[f"biht kappa={kap}"] = lambda kap=kap: cs.biht(A, Y, K=kap, max_iter=PROTOCOL_GREEDY_CAP, mu=BIHT_MU,
+                runs[f"biht kappa={kap}"] = lambda kap=kap: cs.biht(A, Y, K=kap, max_iter=PROTOCOL_BIHT_CAP, mu=BIHT_MU,
                                                                     eps=PROTOCOL_EPS)
             else:
                 row["solvers"][f"biht kappa={kap}"] = "unsupported: 2 kappa > min(M, 96)"
             if 3 * kap <= min(M, 96):
-                runs[f"cosamp kappa={kap}"] = lambda kap=kap: cs.cosamp(A, Y, K=kap, max_iter=PROTOCOL_GREEDY_CAP,
+                runs[f"cosamp kappa={kap}"] = lambda kap=kap: cs.cosamp(A, Y, K=kap, max_iter=PROTOCOL_COSAMP_CAP,
                                                                         eps=PROTOCOL_EPS)
             else:
                 row["solvers"][f"cosamp kappa={kap}"] = ("unsupported: 3 kappa > M (the least squares on the merged "
@@ -537,7 +537,7 @@ def main():
                                f"N={N} M={M}, FISTA {FISTA_ITERS} it lambda={LAMBDA} + gOMP S={GOMP_S} "
                                f"K={GOMP_K} res_tol={GOMP_TOL}",
                    "pixels": P, "N": N, "M": M},
-        "roofline": {"bound": "mfma", "kernel": "fista_f32_kernel", "achieved": achieved,
+        "roofline": {"bound": "mfma", "kernel": "fista_f32s_kernel", "achieved": achieved,
                      "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
                      "traffic": measured_traffic(os.path.join(ROOT, "paper_2401_14762_amd", "csrc", "fista.hip"),
