@@ -323,15 +323,15 @@ __device__ __forceinline__ void rank_top(bool on, int t, int n, int K, const flo
 // and zero right-hand sides, so every pixel runs the same nmax barriered
 // steps).  rhs (nmax entries) is destroyed.  Called by every lane.
 //
-// nmax <= kGJ: Gauss-Jordan elimination on registers.  Lane t owns rows t
-// and t + 16 of [G[L,L] | rhs], gathered in one batch.  Step k (fully
+// nmax <= GJ (GJ <= kGJ): Gauss-Jordan elimination on registers.  Lane t
+// owns rows t and t + 16 of [G[L,L] | rhs], gathered in one batch.  Step k (fully
 // unrolled, so every register index is static) publishes pivot row k
 // through a double-buffered LDS slot in scr (2 x (kGJ + 4) floats; one
 // barrier) and every other row subtracts its multiple of it over the columns
 // j >= k still in play; all-zero padding columns are skipped.  After nmax
 // steps row i reads d_i sol_i = rhs_i, with d_i the row's pivot.
 //
-// nmax > kGJ: right-looking LDL^T elimination of the lower triangle C of
+// nmax > GJ: right-looking LDL^T elimination of the lower triangle C of
 // G[L,L] in scr (tri(nmax) floats, gathered in one batch), the forward
 // substitution of rhs riding along, then a column-oriented back
 // substitution: 2 nmax steps, each one barrier and a set of independent
@@ -340,8 +340,8 @@ __device__ __forceinline__ void rank_top(bool on, int t, int n, int K, const flo
 //
 // Every pivot is floored at 2^-24 of the original diagonal like the appends,
 // so a numerically dependent atom keeps the solution finite.
-template <bool PAD>
-__device__ __forceinline__ void solve_list(bool on, int t, int n, int nmax, int N, const float* __restrict__ G32,
+template <bool PAD, int GJ>
+__device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, int N, const float* __restrict__ G32,
                                            const int* L, float* rhs, float* sol, float* scr) {
     if (!PAD) n = nmax;   // every pixel solves a full list
     if (PAD) {
@@ -349,26 +349,26 @@ __device__ __forceinline__ void solve_list(bool on, int t, int n, int nmax, int 
             for (int i = n + t; i < nmax; i += 16) rhs[i] = 0.f;
         __syncthreads();
     }
-    if (nmax <= kGJ) {
-        constexpr int W1 = kGJ + 1;          // nmax columns (padded to kGJ) + the right-hand side
-        constexpr int SLOT = kGJ + 4;
+    if (nmax <= GJ) {
+        constexpr int W1 = GJ + 1;          // nmax columns (padded to GJ) + the right-hand side
+        constexpr int SLOT = GJ + 4;
         float R0[W1], R1[W1];
         const bool h0 = on && t < n, h1 = on && t + 16 < n;
         const int q0 = clamp_atom(h0 ? L[t] : 0, N), q1 = clamp_atom(h1 ? L[t + 16] : 0, N);
 #pragma unroll
-        for (int j = 0; j < kGJ; ++j) {
+        for (int j = 0; j < GJ; ++j) {
             const bool hj = on && j < n;
             const int qj = clamp_atom(hj ? L[j] : 0, N);
             R0[j] = (h0 && hj) ? G32[(size_t)q0 * N + qj] : ((PAD && j == t) ? 1.f : 0.f);
             R1[j] = (h1 && hj) ? G32[(size_t)q1 * N + qj] : ((PAD && j == t + 16) ? 1.f : 0.f);
         }
-        R0[kGJ] = (PAD ? on && t < nmax : h0) ? rhs[t] : 0.f;
-        R1[kGJ] = (PAD ? on && t + 16 < nmax : h1) ? rhs[t + 16] : 0.f;
+        R0[GJ] = (PAD ? on && t < nmax : h0) ? rhs[t] : 0.f;
+        R1[GJ] = (PAD ? on && t + 16 < nmax : h1) ? rhs[t + 16] : 0.f;
         const float fl0 = (h0 ? G32[(size_t)q0 * N + q0] : 1.f) * 5.9604645e-8f;
         const float fl1 = (h1 ? G32[(size_t)q1 * N + q1] : 1.f) * 5.9604645e-8f;
         float dg0 = 1.f, dg1 = 1.f;
 #pragma unroll
-        for (int k = 0; k < kGJ; ++k) {
+        for (int k = 0; k < GJ; ++k) {
             if (k < nmax) {   // uniform
                 float* slot = scr + (k & 1) * SLOT;
                 if (t == (k & 15)) {
@@ -379,7 +379,7 @@ __device__ __forceinline__ void solve_list(bool on, int t, int n, int nmax, int 
                     if (on) {
 #pragma unroll
                         for (int j = k & ~3; j < W1 + 3; j += 4) {
-                            if (j >= nmax && j < kGJ) continue;   // all-zero padding columns (uniform)
+                            if (j >= nmax && j < GJ) continue;   // all-zero padding columns (uniform)
                             const float4 v = make_float4(R[j], j + 1 < W1 ? R[j + 1] : 0.f,
                                                          j + 2 < W1 ? R[j + 2] : 0.f, j + 3 < W1 ? R[j + 3] : 0.f);
                             *reinterpret_cast<float4*>(slot + j) = v;
@@ -393,7 +393,7 @@ __device__ __forceinline__ void solve_list(bool on, int t, int n, int nmax, int 
                     const float f1 = (t + 16 == k) ? 0.f : R1[k] * rp;
 #pragma unroll
                     for (int j = k & ~3; j < W1; j += 4) {
-                        if (j >= nmax && j < kGJ) continue;   // all-zero padding columns (uniform)
+                        if (j >= nmax && j < GJ) continue;   // all-zero padding columns (uniform)
                         const float4 v = *reinterpret_cast<const float4*>(slot + j);
                         const float pv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -407,8 +407,8 @@ __device__ __forceinline__ void solve_list(bool on, int t, int n, int nmax, int 
                 }
             }
         }
-        if (on && t < n) sol[t] = R0[kGJ] / dg0;
-        if (on && t + 16 < n) sol[t + 16] = R1[kGJ] / dg1;
+        if (on && t < n) sol[t] = R0[GJ] / dg0;
+        if (on && t + 16 < n) sol[t + 16] = R1[GJ] / dg1;
         __syncthreads();
         return;
     }
@@ -482,6 +482,20 @@ __device__ __forceinline__ void solve_list(bool on, int t, int n, int nmax, int 
         }
         __syncthreads();
     }
+}
+
+
+// The register elimination is unrolled over its width, and its code is most
+// of the kernel's: a list of at most kGJSmall atoms runs an instance of that
+// width, so the loop's instructions stay within the instruction cache.
+constexpr int kGJSmall = 20;
+template <bool PAD>
+__device__ __forceinline__ void solve_list(bool on, int t, int n, int nmax, int N, const float* __restrict__ G32,
+                                           const int* L, float* rhs, float* sol, float* scr) {
+    if (nmax <= kGJSmall)   // uniform over the wave
+        solve_list_w<PAD, kGJSmall>(on, t, n, nmax, N, G32, L, rhs, sol, scr);
+    else
+        solve_list_w<PAD, kGJ>(on, t, n, nmax, N, G32, L, rhs, sol, scr);
 }
 
 // Step 3 of Alg. 3 for the pixels with `on`: q = the K entries of c with
