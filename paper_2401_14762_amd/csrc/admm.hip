@@ -510,17 +510,19 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void admm_f32s_kernel(AdmmArgs a)
 
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) T[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+        // A^T e of tile 0; tile nt + 1's is interleaved with tile nt's A v
+        v4f Gn = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const v4f av = a2[mt * 64];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                Gn = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], E[mt][kk], Gn, 0, 0, 0);
+        }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             // A^T e for 16 n-values of this tile
-            v4f G = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const v4f av = a2[(nt * MT + mt) * 64];
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk)
-                    G = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], E[mt][kk], G, 0, 0, 0);
-            }
+            const v4f G = Gn;
             v4f Vn;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -534,13 +536,19 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void admm_f32s_kernel(AdmmArgs a)
                 Zr[nt][r] = active ? zn : Zr[nt][r];
                 Wr[nt][r] = active ? (last ? x : wn) : Wr[nt][r];
             }
-            // T = -A v of the next iteration, accumulated tile by tile
+            // T = -A v of the next iteration, accumulated tile by tile, with
+            // the next tile's A^T e interleaved (its single accumulator chain
+            // overlaps the MT independent ones of T)
+            if (nt + 1 < NT) Gn = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
                 const v4f av = a1[(mt * NT + nt) * 64];
+                const v4f bv = a2[((nt + 1 < NT ? nt + 1 : nt) * MT + mt) * 64];
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk)
+                for (int kk = 0; kk < 4; ++kk) {
                     T[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], Vn[kk], T[mt], 0, 0, 0);
+                    if (nt + 1 < NT) Gn = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[kk], E[mt][kk], Gn, 0, 0, 0);
+                }
             }
         }
         if (active) {

@@ -376,16 +376,6 @@ __device__ __forceinline__ void fista_f32s_body(const FistaArgs& a, const v4f* _
         for (int nt = 0; nt < NT; ++nt) {
             // W = (A^T V) for 16 n-values of this tile          (step 1)
             const v4f W = Wn;
-            if (nt + 1 < NT) {
-                Wn = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    const v4f av = a2[((nt + 1) * MT + mt) * 64];
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk)
-                        Wn = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], V[mt][kk], Wn, 0, 0, 0);
-                }
-            }
             // steps 1, 2, 4 elementwise
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -398,16 +388,21 @@ __device__ __forceinline__ void fista_f32s_body(const FistaArgs& a, const v4f* _
                 Xr[nt][r] = (!FREEZE || active) ? xn : Xr[nt][r];
                 Zr[nt][r] = (!FREEZE || active) ? zn : Zr[nt][r];
             }
-            // U_i += A(:, tile) x^i(tile)                        (step 5)
+            // U_i += A(:, tile) x^i(tile) (step 5), interleaved with the next
+            // tile's A^T V, whose single accumulator chain then overlaps the
+            // five independent ones of U_i
+            if (nt + 1 < NT) Wn = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
                 const v4f av = a1[(mt * NT + nt) * 64];
+                const v4f bv = a2[((nt + 1 < NT ? nt + 1 : nt) * MT + mt) * 64];
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk)
+                for (int kk = 0; kk < 4; ++kk) {
                     Un[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], Xr[nt][kk], Un[mt], 0, 0, 0);
+                    if (nt + 1 < NT) Wn = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[kk], V[mt][kk], Wn, 0, 0, 0);
+                }
             }
         }
-
         // Delta^2 = ||r^i - r^{i-1}||^2 with r^0 = y: the reference is U_{i-1},
         // except in the first iteration from a given x^0, where it is -y.
         const float c0 = (it == 0 && a.X0) ? 1.f : 0.f;
@@ -473,8 +468,9 @@ __device__ __forceinline__ void fista_f32s_body(const FistaArgs& a, const v4f* _
 // ds_read_b128 per four MFMAs, conflict-free (lane l reads bytes 16 l ..
 // 16 l + 15 of its tile's 1 KiB).  Two copies take 2 MT NT KiB, so this form
 // serves shapes with MT NT <= 80 (M = 80, N = 200 among them).  The A^T V
-// product of tile nt + 1 is issued before the epilogue of tile nt, so the
-// matrix cores work while the epilogue's vector instructions run; soft
+// product of tile nt + 1 is issued interleaved with tile nt's A x product,
+// so its single accumulator chain overlaps their five independent ones and
+// the matrix cores stay busy across the epilogue; soft
 // thresholding is v - median(v, -t, t); and without the Delta stop no pixel
 // is frozen, which drops the per-element selects.
 template <int MT, int NT, int WAVES, int MINW>
