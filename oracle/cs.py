@@ -198,6 +198,69 @@ def fista(A, Y, lam: float, L: float, max_iter: int, eps: float = 0.0, X0=None,
     return dict(X=x.astype(np.float64), iters=iters, delta=delta, resid=resid, flags=flags)
 
 
+def soft_threshold_complex(v: np.ndarray, thr: float) -> np.ndarray:
+    """sign(v) max(|v| - thr, 0) for complex v, sign(v) = v / |v| (0 at 0):
+    the magnitude shrinks, the phase is kept (Alg. 1 step 2 on x in C^N)."""
+    mag = np.abs(v)
+    scale = np.where(mag > thr, (mag - thr) / np.where(mag > 0, mag, 1.0), 0.0)
+    return v * scale.astype(v.real.dtype)
+
+
+def fista_complex(A, Y, lam: float, L: float, max_iter: int, eps: float = 0.0, X0=None,
+                  dtype=np.complex128) -> dict:
+    """FISTA (Alg. 1) for the complex measurement model of Section II (a
+    complex DFT basis makes A = Phi Psi and x complex): the steps of
+    ``fista`` with A^* the conjugate transpose and the soft threshold acting
+    on |x| (soft_threshold_complex).  L = lambda_max(A^* A).
+    dtype=np.complex64 is the FP32 rounding model.
+
+    Returns dict(X (complex128), iters, delta, resid, flags)."""
+    A = np.asarray(A, dtype=dtype)
+    Y = np.asarray(Y, dtype=dtype)
+    rdt = A.real.dtype.type
+    P, M = Y.shape
+    N = A.shape[1]
+    fin = _finite_rows(Y)
+    Yc = np.where(fin[:, None], Y, dtype(0.0))
+    Ah = np.conj(A)                  # rows v^T A^*^T = v^T conj(A): the row form of A^* v
+    x = np.zeros((P, N), dtype=dtype) if X0 is None else np.asarray(X0, dtype=dtype).copy()
+    x[~fin] = 0.0
+    z = x.copy()
+    r = Yc.copy()                    # r^0 = y
+    t = 1.0
+    iters = np.zeros(P, dtype=np.int64)
+    delta = np.full(P, np.nan)
+    flags = np.zeros(P, dtype=np.int64)
+    flags[~fin] |= STOP_NONFINITE
+    active = fin.copy()
+    for i in range(1, max_iter + 1):
+        if not active.any():
+            break
+        a = np.nonzero(active)[0]
+        za, xa, ya = z[a], x[a], Yc[a]
+        aux = za - rdt(1.0 / L) * ((za @ A.T - ya) @ Ah)           # step 1
+        x_new = soft_threshold_complex(aux, rdt(lam / L))          # step 2
+        t_new = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0         # step 3
+        z_new = x_new + rdt((t - 1.0) / t_new) * (x_new - xa)      # step 4
+        r_new = ya - x_new @ A.T                                   # step 5
+        d = np.linalg.norm(r_new - r[a], axis=1)
+        x[a], z[a], r[a] = x_new, z_new, r_new
+        iters[a] = i
+        delta[a] = d
+        t = t_new
+        stop = d < eps
+        flags[a[stop]] |= STOP_CONVERGED
+        active[a[stop]] = False
+    flags[active] |= STOP_ITER_CAP
+    resid = np.linalg.norm(Yc - x @ A.T, axis=1)
+    return dict(X=x.astype(np.complex128), iters=iters, delta=delta, resid=resid, flags=flags)
+
+
+def lipschitz_complex(A: np.ndarray) -> float:
+    """L = lambda_max(A^* A) = ||A||_2^2 for a complex A (Eq. 2)."""
+    return float(np.linalg.norm(np.asarray(A, dtype=np.complex128), 2) ** 2)
+
+
 # --------------------------------------------------------------------------
 # Alg. 2 -- ADMM
 # --------------------------------------------------------------------------

@@ -10,8 +10,8 @@ sparse, so before compression every pixel f is made kappa-sparse in the
 transform domain: with x = Psi^{-1} f and mu_x, sigma_x the mean and the
 standard deviation of the N magnitudes |x_n|, every x_n with
 |x_n| - mu_x < T sigma_x is set to zero, the rest are kept.  T (0.1 in
-Section IV) sets the sparsity.  Psi is orthonormal here (the DCT-II of the
-real basis reading), so Psi^{-1} = Psi^T.
+Section IV) sets the sparsity.  Psi is orthonormal or unitary (the real
+DCT-II, or the complex DFT basis of Section II), so Psi^{-1} = Psi^*.
 
 Readings:
 * sigma_x is the sample standard deviation (normalised by N - 1, the default
@@ -38,12 +38,14 @@ def sparsify(F, Psi, T: float, ddof: int = 1) -> dict:
     (P x N), kept (P), mu, sigma (P), margin (P)): margin is the smallest
     | |x_n| - mu - T sigma | of the pixel over (mu + sigma), the distance of
     its closest keep/zero decision from the threshold."""
-    F = np.asarray(F, dtype=np.float64)
-    Psi = np.asarray(Psi, dtype=np.float64)
+    F = np.asarray(F)
+    F = F.astype(np.complex128 if np.iscomplexobj(F) else np.float64)
+    Psi = np.asarray(Psi)
+    Psi = Psi.astype(np.complex128 if np.iscomplexobj(Psi) else np.float64)
     P, N = F.shape
     fin = np.all(np.isfinite(F), axis=1)
     Fc = np.where(fin[:, None], F, 0.0)
-    X = Fc @ Psi                                   # x = Psi^T f, one row per pixel
+    X = Fc @ np.conj(Psi)                          # x = Psi^* f, one row per pixel
     mag = np.abs(X)
     mu = mag.mean(axis=1)
     sigma = mag.std(axis=1, ddof=ddof) if N - ddof > 0 else np.zeros(P)

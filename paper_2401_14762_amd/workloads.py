@@ -50,6 +50,30 @@ def dct_synthesis(N: int) -> np.ndarray:
     return psi
 
 
+def dft_synthesis(N: int) -> np.ndarray:
+    """N x N unitary DFT synthesis matrix of Section II's complex basis:
+    Psi[n, k] = exp(2 pi i n k / N) / sqrt(N), f = Psi x, x = Psi^* f."""
+    n = np.arange(N)
+    return np.exp(2j * np.pi * np.outer(n, n) / N) / math.sqrt(N)
+
+
+def complex_dictionary(N: int, M: int, seed, sampling: str = "subsample") -> tuple:
+    """A = Phi Psi with the complex DFT basis (complex128, complex64), the
+    basis and Phi: "subsample" picks M of the N bands (Section IV),
+    "gaussian" draws N(0, 1/M) entries."""
+    psi = dft_synthesis(N)
+    if sampling == "subsample":
+        rows = np.sort(np.random.default_rng(seed).choice(N, M, replace=False))
+        phi = np.zeros((M, N))
+        phi[np.arange(M), rows] = 1.0
+    elif sampling == "gaussian":
+        phi = gaussian_phi(M, N, seed)
+    else:
+        raise ValueError(sampling)
+    a = phi @ psi
+    return a, a.astype(np.complex64), psi, phi
+
+
 def gaussian_phi(M: int, N: int, seed) -> np.ndarray:
     """Phi with i.i.d. N(0, 1/M) entries (FP64)."""
     rng = seed if isinstance(seed, np.random.Generator) else np.random.default_rng(seed)

@@ -47,6 +47,15 @@ def _sparse_problem(M, N, K, P, seed, noise=0.0):
 
 # ---------------------------------------------------------------- dictionary
 
+def check_dft_basis():
+    for N in (8, 100, 154):
+        psi = W.dft_synthesis(N)
+        assert np.max(np.abs(np.conj(psi.T) @ psi - np.eye(N))) < 1e-12
+        f = _rng(N).standard_normal(N)
+        # x = Psi^* f is the unitary DFT of f (numpy's forward FFT, scaled)
+        assert np.allclose(np.conj(psi.T) @ f, np.fft.fft(f) / math.sqrt(N), atol=1e-12)
+
+
 def check_dct_basis():
     for N in (8, 100, 200, 224):
         psi = W.dct_synthesis(N)
@@ -498,6 +507,88 @@ def check_admm_stop_rule(orc):
     assert np.all(o["iters"] == 1) and np.all(o["flags"] == orc.STOP_CONVERGED)
 
 
+# ---------------------------------------------------------------- complex FISTA (Section II DFT basis)
+
+def _complex_problem(M, N, K, P, seed):
+    rng = _rng(seed)
+    A = (rng.standard_normal((M, N)) + 1j * rng.standard_normal((M, N))) / math.sqrt(2 * M)
+    X = np.zeros((P, N), dtype=complex)
+    for p in range(P):
+        idx = rng.choice(N, K, replace=False)
+        X[p, idx] = (1.0 + rng.random(K)) * np.exp(2j * np.pi * rng.random(K))
+    return A, X, X @ A.T
+
+
+def check_fista_complex_real_case(orc):
+    """Real A and y: the complex iteration is the real one (imaginary parts stay 0)."""
+    A, _, Y = _sparse_problem(12, 30, 3, 5, 41)
+    L = orc.lipschitz(A)
+    r = orc.fista_complex(A, Y, 0.05, L, 60)
+    assert np.max(np.abs(r["X"].imag)) == 0.0
+    assert np.allclose(r["X"].real, orc.fista(A, Y, 0.05, L, 60)["X"], atol=1e-12)
+
+
+def check_fista_complex_identity(orc):
+    """A = c I, c complex: L = |c|^2 and from x^0 = 0 the first iterate is the
+    minimiser x* = sign(u) max(|u| - lam / |c|^2, 0), u = conj(c) y / |c|^2;
+    every later iterate stays there."""
+    c = 0.8 * np.exp(0.7j)
+    y = (_rng(42).standard_normal((4, 9)) + 1j * _rng(43).standard_normal((4, 9)))
+    lam = 0.3
+    u = np.conj(c) * y / abs(c) ** 2
+    mag = np.abs(u)
+    xs = np.where(mag > lam / abs(c) ** 2, u * (mag - lam / abs(c) ** 2) / np.where(mag > 0, mag, 1), 0)
+    for it in (1, 25):
+        r = orc.fista_complex(c * np.eye(9), y, lam, abs(c) ** 2, it)
+        assert np.allclose(r["X"], xs, atol=1e-12), it
+
+
+def check_fista_complex_phase_equivariance(orc):
+    """A -> e^{i a} A maps every iterate x -> e^{-i a} x, and y -> e^{i b} y
+    maps x -> e^{i b} x: the threshold acts on |x| only."""
+    A, _, Y = _complex_problem(15, 40, 4, 6, 44)
+    L = orc.lipschitz_complex(A)
+    r0 = orc.fista_complex(A, Y, 0.05, L, 40)
+    r1 = orc.fista_complex(np.exp(0.9j) * A, Y, 0.05, L, 40)
+    r2 = orc.fista_complex(A, np.exp(-1.3j) * Y, 0.05, L, 40)
+    assert np.allclose(r1["X"], np.exp(-0.9j) * r0["X"], atol=1e-10)
+    assert np.allclose(r2["X"], np.exp(-1.3j) * r0["X"], atol=1e-10)
+
+
+def check_fista_complex_kkt(orc):
+    """Run long, x meets the complex LASSO optimality conditions:
+    A^*(A x - y) + lam x / |x| = 0 on the support, |A^*(A x - y)| <= lam off it;
+    and exact sparse data is recovered for small lam."""
+    A, X, Y = _complex_problem(20, 50, 3, 5, 45)
+    L = orc.lipschitz_complex(A)
+    lam = 0.02
+    x = orc.fista_complex(A, Y, lam, L, 4000)["X"]
+    g = (x @ A.T - Y) @ np.conj(A)
+    on = np.abs(x) > 0
+    assert np.max(np.abs(g + lam * x / np.where(on, np.abs(x), 1))[on]) < 1e-8
+    assert np.max(np.abs(g)[~on]) <= lam + 1e-8
+    # the 3 largest |x| are the true support (lasso shrinks their values a little)
+    top = np.sort(np.argsort(-np.abs(x), axis=1)[:, :3], axis=1)
+    assert np.array_equal(top, np.sort(np.argsort(-np.abs(X), axis=1)[:, :3], axis=1))
+
+
+def check_sparsify_complex_basis(orc):
+    """With a unitary complex basis x = Psi^* f: a spectrum of 5 large and 59
+    tiny complex coefficients keeps exactly the large ones, with their values."""
+    N = 64
+    rng = _rng(46)
+    q, r = np.linalg.qr(rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))
+    Psi = q * (np.diag(r) / np.abs(np.diag(r)))[None, :]
+    Xt = 0.01 * (rng.standard_normal((10, N)) + 1j * rng.standard_normal((10, N)))
+    sup = np.stack([rng.choice(N, 5, replace=False) for _ in range(10)])
+    for p in range(10):
+        Xt[p, sup[p]] = (5.0 + rng.random(5)) * np.exp(2j * np.pi * rng.random(5))
+    res = orc.sparsify(Xt @ Psi.T, Psi, 0.1)
+    for p in range(10):
+        assert set(np.nonzero(res["X"][p])[0]) == set(sup[p])
+        assert np.allclose(res["X"][p, sup[p]], Xt[p, sup[p]], atol=1e-12)
+
+
 # ---------------------------------------------------------------- sparsification (Section II)
 
 def check_sparsify_worked(orc):
@@ -582,4 +673,6 @@ ORACLE_CHECKS = [
     check_biht_orthonormal, check_biht_first_step, check_biht_second_step_mu,
     check_biht_recovery, check_one_bit, check_admm_matches_sklearn_lasso, check_admm_identity,
     check_admm_kkt_and_dual, check_admm_stop_rule, check_sparsify_worked, check_sparsify_transform,
+    check_fista_complex_real_case, check_fista_complex_identity, check_fista_complex_phase_equivariance,
+    check_fista_complex_kkt, check_sparsify_complex_basis,
 ]

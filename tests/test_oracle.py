@@ -10,6 +10,10 @@ def test_dct_basis():
     pins.check_dct_basis()
 
 
+def test_dft_basis():
+    pins.check_dft_basis()
+
+
 def test_metrics():
     pins.check_metrics()
 

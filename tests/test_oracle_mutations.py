@@ -47,6 +47,11 @@ MUTATIONS = [
     ("admm-dual-sign", "rhs = Aty[a] + dtype(alpha) * (z[a] - w[a])", "rhs = Aty[a] + dtype(alpha) * (z[a] + w[a])"),
     ("admm-no-dual-in-threshold", "zt = x_new + w[a]", "zt = x_new"),
     ("admm-dual-not-accumulated", "w_new = zt - z_new", "w_new = x_new - z_new"),
+    ("cfista-transpose-not-adjoint", "Ah = np.conj(A) ", "Ah = A "),
+    ("cfista-separable-shrink", "x_new = soft_threshold_complex(aux, rdt(lam / L))",
+     "x_new = soft_threshold(aux.real, rdt(lam / L)) + 1j * soft_threshold(aux.imag, rdt(lam / L))"),
+    ("cfista-phase-dropped", "    return v * scale.astype(v.real.dtype)", "    return np.abs(v) * scale.astype(v.real.dtype)"),
+    ("cfista-no-momentum", "z_new = x_new + rdt((t - 1.0) / t_new) * (x_new - xa)", "z_new = x_new"),
 ]
 
 # mistakes planted in the sparsification (Section II)
@@ -55,7 +60,8 @@ PROTOCOL_MUTATIONS = [
      "def sparsify(F, Psi, T: float, ddof: int = 0)"),
     ("sparsify-signed-not-magnitude", "mag = np.abs(X)", "mag = X"),
     ("sparsify-non-strict", "zero = gap < 0.0", "zero = gap <= 0.0"),
-    ("sparsify-transposed-basis", "X = Fc @ Psi ", "X = Fc @ Psi.T "),
+    ("sparsify-transposed-basis", "X = Fc @ np.conj(Psi) ", "X = Fc @ np.conj(Psi).T "),
+    ("sparsify-no-conjugate", "X = Fc @ np.conj(Psi) ", "X = Fc @ Psi "),
     ("sparsify-no-mean", "gap = (mag - mu[:, None]) - T * sigma[:, None]", "gap = mag - T * sigma[:, None]"),
     ("sparsify-keeps-nonfinite", "Fc = np.where(fin[:, None], F, 0.0)", "Fc = F"),
 ]
@@ -88,7 +94,7 @@ def test_pins_catch_mutation(mid, old, new):
 def test_pins_catch_protocol_mutation(mid, old, new):
     mod = _mutant(old, new, PROTOCOL_SRC)
     failed = []
-    for check in (pins.check_sparsify_worked, pins.check_sparsify_transform):
+    for check in (pins.check_sparsify_worked, pins.check_sparsify_transform, pins.check_sparsify_complex_basis):
         try:
             check(mod)
         except (AssertionError, ValueError, IndexError, FloatingPointError, AttributeError):
