@@ -13,6 +13,8 @@
  *                 measurements (mode CSREC_BIHT_ONE_BIT; not from the paper)
  *   csrec_cosamp  CoSaMP                                   (Alg. 5)
  *   csrec_admm    ADMM for the LASSO of Eq. 2             (Alg. 2)
+ *   csrec_fista_complex  FISTA for complex A and y (Alg. 1 with the
+ *                 complex DFT basis of Section II)
  *
  * and the pre-stage of the paper's evaluation protocol:
  *
@@ -77,6 +79,7 @@ extern "C" {
 #define CSREC_SOLVER_COSAMP 2
 #define CSREC_SOLVER_BIHT   3
 #define CSREC_SOLVER_ADMM   4
+#define CSREC_SOLVER_FISTA_COMPLEX 5
 
 #define CSREC_MAX_N 256
 
@@ -214,6 +217,24 @@ int32_t csrec_biht(const csrec_problem* problem, const csrec_biht_params* params
  * otherwise CSREC_E_UNSUPPORTED.  X may alias X0. */
 int32_t csrec_admm(const csrec_problem* problem, const csrec_admm_params* params, float* X, float* Z,
                    csrec_pixel_stats* stats);
+
+/* FISTA (Alg. 1) for the complex measurement model of Section II: with the
+ * complex DFT basis, A = Phi Psi and x are complex; step 1 uses the conjugate
+ * transpose A^*, and the soft threshold of step 2 shrinks the magnitude |x_n|
+ * by lambda / L and keeps the phase (x_n = 0 when |x_n| <= lambda / L).
+ * Delta and resid are the complex 2-norms.
+ *
+ * problem->A is M x N complex and problem->Y P x M complex; params->X0 (P x N
+ * complex, nullable) and X (P x N complex) likewise.  Complex values are
+ * interleaved (re, im) FP32 pairs, so A holds 2 M N floats.  params->L > 0
+ * is lambda_max(A^* A); 0 estimates it on the device.  prec must be
+ * CSREC_PREC_F32 and correction_iters 0.  Needs a workspace of
+ * csrec_workspace_bytes(CSREC_SOLVER_FISTA_COMPLEX, ...) bytes (the real
+ * 2M x 2N' embedding [Re A, -Im A; Im A, Re A] of A, N' >= N a multiple of
+ * 16 chosen by the library, written on every call).  M <= 40 and N <= 112,
+ * otherwise CSREC_E_UNSUPPORTED.  X may alias X0. */
+int32_t csrec_fista_complex(const csrec_problem* problem, const csrec_fista_params* params, float* X,
+                            csrec_pixel_stats* stats);
 
 /* Sparsification (Section II) fused with the compression of the sparsified
  * pixels.  For each of the P spectra f (rows of F, P x N): x = Psi^T f, where

@@ -36,6 +36,18 @@ int check_fista(const csrec_problem* p, const csrec_fista_params* f) {
     return fista_supported(p->M, p->N, f->prec);
 }
 
+int check_fista_complex(const csrec_problem* p, const csrec_fista_params* f) {
+    int e = check_problem(p, true);
+    if (e) return e;
+    if (!f || f->struct_size != (int32_t)sizeof(csrec_fista_params)) return CSREC_E_INVAL;
+    if (f->max_iter < 0 || !finite_nonneg(f->lambda) || !finite_nonneg(f->L) || !finite_nonneg(f->eps))
+        return CSREC_E_INVAL;
+    if (f->correction_iters < 0) return CSREC_E_INVAL;
+    if ((e = check_prec(f->prec))) return e;
+    if (f->prec != CSREC_PREC_F32 || f->correction_iters != 0) return CSREC_E_UNSUPPORTED;
+    return fista_complex_supported(p->M, p->N);
+}
+
 int check_admm(const csrec_problem* p, const csrec_admm_params* q, float* thr) {
     int e = check_problem(p, true);
     if (e) return e;
@@ -198,6 +210,10 @@ int32_t csrec_workspace_bytes(int32_t solver, const csrec_problem* problem, cons
             *bytes = problem->P > 0 ? admm_workspace(problem->M) : 0;
             return CSREC_OK;
         }
+        case CSREC_SOLVER_FISTA_COMPLEX:
+            if ((e = check_fista_complex(problem, static_cast<const csrec_fista_params*>(params)))) return e;
+            *bytes = problem->P > 0 ? fista_complex_workspace(problem->M, problem->N) : 0;
+            return CSREC_OK;
         case CSREC_SOLVER_GOMP:
             e = fill_gomp(problem, static_cast<const csrec_gomp_params*>(params), l);
             break;
@@ -302,6 +318,37 @@ int32_t csrec_admm(const csrec_problem* problem, const csrec_admm_params* params
     l.workspace = problem->workspace;
     l.stream = reinterpret_cast<hipStream_t>(problem->stream);
     return admm_launch(l);
+}
+
+int32_t csrec_fista_complex(const csrec_problem* problem, const csrec_fista_params* params, float* X,
+                            csrec_pixel_stats* stats) {
+    int e = check_fista_complex(problem, params);
+    if (e) return e;
+    if (problem->P == 0) return CSREC_OK;
+    if (!X) return CSREC_E_INVAL;
+    if (!problem->workspace || problem->workspace_bytes < fista_complex_workspace(problem->M, problem->N))
+        return CSREC_E_WORKSPACE;
+    FistaLaunch l{};
+    l.A = problem->A;
+    l.Y = problem->Y;
+    l.X0 = params->X0;
+    l.X = X;
+    l.stats = stats;
+    l.M = problem->M;
+    l.N = problem->N;
+    l.P = problem->P;
+    l.max_iter = params->max_iter;
+    l.eps = (float)params->eps;
+    l.lambda = params->lambda;
+    l.prec = CSREC_PREC_F32;
+    l.workspace = problem->workspace;
+    l.stream = reinterpret_cast<hipStream_t>(problem->stream);
+    const bool power = !(params->L > 0.0);
+    if (!power) {
+        l.invL = (float)(1.0 / params->L);
+        l.thr = (float)(params->lambda / params->L);
+    }
+    return fista_complex_launch(l, power);
 }
 
 int32_t csrec_sparsify(const float* Psi, const float* A, const float* F, int32_t M, int32_t N, int64_t P,

@@ -56,6 +56,12 @@ int fista_launch(const FistaLaunch& a);
 
 int lipschitz_launch(const float* A, int M, int N, float* L_out, hipStream_t stream);
 
+// Complex FISTA: A, Y, X0, X interleaved complex; invL / thr are used when
+// `power` is false, otherwise L comes from a power iteration on the device.
+int fista_complex_supported(int M, int N);
+size_t fista_complex_workspace(int M, int N);
+int fista_complex_launch(const FistaLaunch& a, bool power);
+
 struct AdmmLaunch {
     const float* A;
     const float* Y;

@@ -261,6 +261,33 @@ def paper_shape_cube(name: str, P: Optional[int] = None, sampling: str = "subsam
     return dict(name=name, F=F, A=a32, Psi=psi, Phi=phi, M=M, N=N, P=P, kappas=c["kappas"], sampling=sampling)
 
 
+# Complex measurements with the DFT basis of Section II: K-sparse complex
+# coefficients (circular complex Gaussian values), y = A x (+ circular
+# complex white noise at snr_db).  Shapes within the complex FISTA kernel's
+# limits (N <= 112, M <= 40).
+COMPLEX = dict(config_id=8, side=64, N=100, M=40, K=8, snr_db=40.0)
+
+
+def complex_cube(P: Optional[int] = None, N: int = COMPLEX["N"], M: int = COMPLEX["M"], K: int = COMPLEX["K"],
+                 sampling: str = "gaussian", snr_db: Optional[float] = COMPLEX["snr_db"],
+                 config_id: int = COMPLEX["config_id"]) -> dict:
+    """A = Phi Psi with the unitary DFT synthesis Psi (complex64 A32 and
+    complex128 A64), X_true (P x N complex128, K-sparse) and Y (P x M
+    complex64).  sampling as complex_dictionary; snr_db None = noiseless."""
+    P = COMPLEX["side"] ** 2 if P is None else P
+    a64, a32, psi, phi = complex_dictionary(N, M, rng_for(config_id, _S_PHI), sampling)
+    supp = sparse_coefficients(P, N, K, rng_for(config_id, _S_SUPPORT), rng_for(config_id, _S_VALUES)) != 0.0
+    vals = rng_for(config_id, _S_ABUND).standard_normal((P, N, 2)) / math.sqrt(2.0)
+    X = np.where(supp, vals[..., 0] + 1j * vals[..., 1], 0.0)
+    Y0 = X @ a64.T
+    if snr_db is not None:
+        pw = np.sum(np.abs(Y0) ** 2, axis=1, keepdims=True) / (M * 10.0 ** (snr_db / 10.0))
+        w = rng_for(config_id, _S_NOISE).standard_normal((P, M, 2))
+        Y0 = Y0 + np.sqrt(pw / 2.0) * (w[..., 0] + 1j * w[..., 1])
+    return dict(A=a32, A64=a64, Psi=psi, Phi=phi, X_true=X, Y=Y0.astype(np.complex64), M=M, N=N, P=P,
+                sampling=sampling)
+
+
 def pixel_subset(P: int, n: int, config_id: int) -> np.ndarray:
     """Seeded sorted subset of n pixel indices out of P."""
     n = min(n, P)

@@ -35,8 +35,9 @@ def np_of(t):
 
 
 def rel_err_rows(est, ref):
-    est = np.asarray(est, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
+    dt = np.complex128 if (np.iscomplexobj(est) or np.iscomplexobj(ref)) else np.float64
+    est = np.asarray(est, dtype=dt)
+    ref = np.asarray(ref, dtype=dt)
     return np.linalg.norm(est - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-30)
 
 
@@ -106,3 +107,20 @@ def assert_admm_parity(X_gpu, Z_gpu, A, Y, lam, alpha, iters, floor=1e-5, **kw):
         assert e.max() <= max(floor, 2.0 * e32.max()), (name, e.max(), e32.max())
         assert np.median(e) <= max(floor / 10, 2.0 * np.median(e32)), (name, np.median(e), np.median(e32))
     return ref
+
+
+def assert_cfista_parity(X_gpu, A, Y, lam, L, iters, floor=1e-5, **kw):
+    """Complex FISTA parity: the bar of assert_fista_parity with the complex
+    oracle (complex128) and its complex64 rounding model, errors measured in
+    the complex 2-norm of each pixel's x."""
+    import oracle
+    ref = oracle.fista_complex(A, Y, lam, L, iters, **kw)
+    r32 = oracle.fista_complex(A, Y, lam, L, iters, dtype=np.complex64, **kw)
+    e = rel_err_rows(X_gpu, ref["X"])
+    e32 = rel_err_rows(r32["X"], ref["X"])
+    per_pixel = np.maximum(floor, 30.0 * e32)
+    bad = np.nonzero(e > per_pixel)[0]
+    assert len(bad) == 0, f"pixels {bad[:8]}: err {e[bad[:8]]} vs complex64 model {e32[bad[:8]]}"
+    assert e.max() <= max(floor, 2.0 * e32.max()), (e.max(), e32.max())
+    assert np.median(e) <= max(floor / 10, 2.0 * np.median(e32)), (np.median(e), np.median(e32))
+    return ref, e

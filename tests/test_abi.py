@@ -241,3 +241,31 @@ def test_one_hip_runtime_in_process():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "1"
+
+
+def test_fista_complex_validation(lib):
+    """Complex FISTA: FP32 only, no correction pass, M <= 40 and N <= 112,
+    a workspace for the real embedding of A (2M x 2N' floats, N' the
+    multiple of 16 the kernel tile uses) plus the device L slot."""
+    S = L.SOLVER_FISTA_COMPLEX
+    pb = _problem(M=40, N=100)
+    rc, n = _ws(lib, S, pb, _fista())
+    assert rc == L.OK and 2 * 40 * 2 * 112 * 4 <= n <= 2 * 40 * 2 * 112 * 4 + 512
+    assert _ws(lib, S, pb, _fista(L=0.0))[0] == L.OK
+    assert _ws(lib, S, pb, _fista(prec=1))[0] == L.E_UNSUPPORTED
+    assert _ws(lib, S, pb, _fista(correction_iters=5))[0] == L.E_UNSUPPORTED
+    assert _ws(lib, S, pb, _fista(prec=7))[0] == L.E_INVAL
+    assert _ws(lib, S, pb, _fista(lambda_=-1.0))[0] == L.E_INVAL
+    assert _ws(lib, S, _problem(M=41, N=112), _fista())[0] == L.E_UNSUPPORTED
+    assert _ws(lib, S, _problem(M=40, N=113), _fista())[0] == L.E_UNSUPPORTED
+    assert _ws(lib, S, _problem(M=5, N=17), _fista())[0] == L.OK
+    assert _ws(lib, S, _problem(M=20, N=10), _fista())[0] == L.E_SHAPE
+    assert _ws(lib, S, _problem(P=0), _fista()) == (L.OK, 0)
+    # entry point: bad parameters, a missing output or workspace return before any launch
+    v = ctypes.c_void_p(0x3000)
+    assert lib.csrec_fista_complex(ctypes.byref(pb), ctypes.byref(_fista(max_iter=-1)), v, None) == L.E_INVAL
+    assert lib.csrec_fista_complex(ctypes.byref(pb), ctypes.byref(_fista()), None, None) == L.E_INVAL
+    assert lib.csrec_fista_complex(ctypes.byref(pb), ctypes.byref(_fista()), v, None) == L.E_WORKSPACE
+    pb.workspace, pb.workspace_bytes = 0x4000, n - 4
+    assert lib.csrec_fista_complex(ctypes.byref(pb), ctypes.byref(_fista()), v, None) == L.E_WORKSPACE
+    assert lib.csrec_fista_complex(ctypes.byref(_problem(P=0)), ctypes.byref(_fista()), None, None) == L.OK
