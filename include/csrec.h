@@ -15,6 +15,8 @@
  *   csrec_admm    ADMM for the LASSO of Eq. 2             (Alg. 2)
  *   csrec_fista_complex  FISTA for complex A and y (Alg. 1 with the
  *                 complex DFT basis of Section II)
+ *   csrec_fista_hermitian  the same for real y and conjugate-symmetric A
+ *                 (a real Phi with the DFT basis): half-spectrum iteration
  *
  * and the pre-stage of the paper's evaluation protocol:
  *
@@ -80,6 +82,7 @@ extern "C" {
 #define CSREC_SOLVER_BIHT   3
 #define CSREC_SOLVER_ADMM   4
 #define CSREC_SOLVER_FISTA_COMPLEX 5
+#define CSREC_SOLVER_FISTA_HERMITIAN 6
 
 #define CSREC_MAX_N 256
 
@@ -235,6 +238,27 @@ int32_t csrec_admm(const csrec_problem* problem, const csrec_admm_params* params
  * otherwise CSREC_E_UNSUPPORTED.  X may alias X0. */
 int32_t csrec_fista_complex(const csrec_problem* problem, const csrec_fista_params* params, float* X,
                             csrec_pixel_stats* stats);
+
+/* FISTA (Alg. 1) with the complex DFT basis of Section II for REAL
+ * measurements: Phi real and the spectra real make y = Phi f real, and the
+ * columns of A = Phi Psi conjugate-symmetric, A[:, N-k] = conj(A[:, k]).
+ * Then every iterate of csrec_fista_complex started from a
+ * conjugate-symmetric x^0 (0 is one) is conjugate-symmetric,
+ * x_{N-k} = conj(x_k), and the library iterates on its half: the same x^I as
+ * csrec_fista_complex up to rounding, with the work of a real FISTA on N
+ * unknowns (the complex call iterates on 4 M N reals).
+ *
+ * problem->A is M x N complex (interleaved (re, im) FP32 pairs); only its
+ * columns 0 .. floor(N/2) are read, and A[:, 0] (and A[:, N/2], N even) are
+ * taken as real.  problem->Y is P x M REAL FP32.  params->X0 (P x N complex,
+ * nullable) is read at entries 0 .. floor(N/2) only.  X (P x N complex)
+ * receives the full conjugate-symmetric x^I.  params->L > 0 is
+ * lambda_max(A^* A); 0 estimates it on the device (needs the workspace of
+ * csrec_workspace_bytes(CSREC_SOLVER_FISTA_HERMITIAN, ...); none with L > 0).
+ * prec must be CSREC_PREC_F32 and correction_iters 0.  M <= 96,
+ * N <= CSREC_MAX_N.  X may alias X0. */
+int32_t csrec_fista_hermitian(const csrec_problem* problem, const csrec_fista_params* params, float* X,
+                              csrec_pixel_stats* stats);
 
 /* Sparsification (Section II) fused with the compression of the sparsified
  * pixels.  For each of the P spectra f (rows of F, P x N): x = Psi^T f, where

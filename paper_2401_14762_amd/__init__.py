@@ -11,6 +11,7 @@ device memory and the stream, the library's HIP kernels do all the work.
     X, S, st = biht(A, None, K=15, max_iter=100, Ysign=Ys, mode="one_bit")
     X, S, st = cosamp(A, Y, K=15, max_iter=30)                  # Alg. 5
     X, st = fista_complex(Ac, Yc, lam=1e-2, max_iter=200)       # Alg. 1, complex A
+    X, st = fista_hermitian(Ac, Y, lam=1e-2, max_iter=200)      # Alg. 1, DFT basis, real y
 
 A: M x N float32, Y: P x M float32, both CUDA (HIP) tensors, contiguous.
 ``st`` is a dict of per-pixel tensors: iters, flags, resid, delta.
@@ -23,7 +24,7 @@ from . import _lib
 from ._lib import (CsrecError, FLAG_CONVERGED, FLAG_FP64_FALLBACK, FLAG_ITER_CAP,
                    FLAG_NONFINITE, MAX_N)
 
-__all__ = ["sparsify", "fista", "fista_complex", "admm", "gomp", "cosamp", "biht", "lipschitz", "Server", "CsrecError", "FLAG_CONVERGED",
+__all__ = ["sparsify", "fista", "fista_complex", "fista_hermitian", "admm", "gomp", "cosamp", "biht", "lipschitz", "Server", "CsrecError", "FLAG_CONVERGED",
            "FLAG_ITER_CAP", "FLAG_FP64_FALLBACK", "FLAG_NONFINITE", "MAX_N", "workspace_bytes",
            "library"]
 
@@ -102,7 +103,7 @@ def workspace_bytes(solver: str, A, Y, **params) -> int:
 
 
 def _params(solver, A, P, kw):
-    if solver in ("fista", "fista_complex"):
+    if solver in ("fista", "fista_complex", "fista_hermitian"):
         p = _lib.FistaParams()
         p.struct_size = ctypes.sizeof(p)
         p.max_iter = int(kw.get("max_iter", 100))
@@ -113,7 +114,8 @@ def _params(solver, A, P, kw):
         p.X0 = x0.data_ptr() if x0 is not None else 0
         p.prec = _lib.PREC[kw.get("prec", "f32")]
         p.correction_iters = int(kw.get("correction_iters", 0))
-        return p, (_lib.SOLVER_FISTA if solver == "fista" else _lib.SOLVER_FISTA_COMPLEX)
+        return p, {"fista": _lib.SOLVER_FISTA, "fista_complex": _lib.SOLVER_FISTA_COMPLEX,
+                   "fista_hermitian": _lib.SOLVER_FISTA_HERMITIAN}[solver]
     if solver == "admm":
         p = _lib.AdmmParams()
         p.struct_size = ctypes.sizeof(p)
@@ -206,12 +208,42 @@ def fista_complex(A, Y, lam: float, L: float = 0.0, max_iter: int = 100, eps: fl
     pb = _problem(A, Y, P, stream)
     prm, sid = _params("fista_complex", A, P, dict(lam=lam, L=L, max_iter=max_iter, eps=eps, X0=X0))
     ws = _workspace(lib, sid, pb, prm, A.device)
-    X = out if out is not None else torch.empty((P, N), dtype=torch.complex64, device=A.device)
     if out is not None:
         _check_dev("out", out, torch.complex64, (P, N))
+    X = out if out is not None else torch.empty((P, N), dtype=torch.complex64, device=A.device)
     st = torch.empty((max(P, 1), 4), dtype=torch.int32, device=A.device)
     _lib.check(lib.csrec_fista_complex(ctypes.byref(pb), ctypes.byref(prm), _ptr(X), _ptr(st)),
                "csrec_fista_complex")
+    _keep_alive(ws, A.device, stream)
+    return X, _stats_view(st[:P])
+
+
+def fista_hermitian(A, Y, lam: float, L: float = 0.0, max_iter: int = 100, eps: float = 0.0, X0=None,
+                    stream=None, out=None):
+    """FISTA (Alg. 1) with the DFT basis for real measurements: A (M x N
+    complex64) with conjugate-symmetric columns (A = Phi Psi, Phi real), Y
+    (P x M float32).  The iterate is conjugate-symmetric and the library
+    iterates on its half (columns 0 .. N // 2 of A are read).  Returns
+    (X (P x N complex64, the full spectrum), stats)."""
+    torch = _torch()
+    lib = library()
+    _check_dev("A", A, torch.complex64)
+    M, N = A.shape
+    _check_dev("Y", Y, torch.float32)
+    P = Y.shape[0]
+    if Y.shape[1] != M:
+        raise ValueError("Y must be P x M")
+    if X0 is not None:
+        _check_dev("X0", X0, torch.complex64, (P, N))
+    pb = _problem(A, Y, P, stream)
+    prm, sid = _params("fista_hermitian", A, P, dict(lam=lam, L=L, max_iter=max_iter, eps=eps, X0=X0))
+    ws = _workspace(lib, sid, pb, prm, A.device)
+    if out is not None:
+        _check_dev("out", out, torch.complex64, (P, N))
+    X = out if out is not None else torch.empty((P, N), dtype=torch.complex64, device=A.device)
+    st = torch.empty((max(P, 1), 4), dtype=torch.int32, device=A.device)
+    _lib.check(lib.csrec_fista_hermitian(ctypes.byref(pb), ctypes.byref(prm), _ptr(X), _ptr(st)),
+               "csrec_fista_hermitian")
     _keep_alive(ws, A.device, stream)
     return X, _stats_view(st[:P])
 

@@ -17,7 +17,8 @@ CSREC_ABI_VERSION = 1
 OK, E_INVAL, E_SHAPE, E_WORKSPACE, E_DEVICE, E_UNSUPPORTED, E_BUDGET = 0, -1, -2, -3, -4, -5, -6
 PREC = {"f32": 0, "bf16": 1, "f16": 2}
 FLAG_CONVERGED, FLAG_ITER_CAP, FLAG_FP64_FALLBACK, FLAG_NONFINITE = 1, 2, 4, 8
-SOLVER_FISTA, SOLVER_GOMP, SOLVER_COSAMP, SOLVER_BIHT, SOLVER_ADMM, SOLVER_FISTA_COMPLEX = 0, 1, 2, 3, 4, 5
+SOLVER_FISTA, SOLVER_GOMP, SOLVER_COSAMP, SOLVER_BIHT, SOLVER_ADMM = 0, 1, 2, 3, 4
+SOLVER_FISTA_COMPLEX, SOLVER_FISTA_HERMITIAN = 5, 6
 ADMM_THR = {"paper": 0, "standard": 1}
 PRUNE = {"each": 0, "final": 1}
 BIHT_MODE = {"real": 0, "one_bit": 1}
@@ -145,6 +146,7 @@ SIGNATURES = {
                                                _P(ctypes.c_size_t)]),
     "csrec_fista": (ctypes.c_int32, [_P(Problem), _P(FistaParams), ctypes.c_void_p, ctypes.c_void_p]),
     "csrec_fista_complex": (ctypes.c_int32, [_P(Problem), _P(FistaParams), ctypes.c_void_p, ctypes.c_void_p]),
+    "csrec_fista_hermitian": (ctypes.c_int32, [_P(Problem), _P(FistaParams), ctypes.c_void_p, ctypes.c_void_p]),
     "csrec_gomp": (ctypes.c_int32, [_P(Problem), _P(GompParams), ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p]),
     "csrec_cosamp": (ctypes.c_int32, [_P(Problem), _P(CosampParams), ctypes.c_void_p,

@@ -48,6 +48,13 @@ int check_fista_complex(const csrec_problem* p, const csrec_fista_params* f) {
     return fista_complex_supported(p->M, p->N);
 }
 
+int check_fista_hermitian(const csrec_problem* p, const csrec_fista_params* f) {
+    int e = check_fista_complex(p, f);
+    if (e != CSREC_OK && e != CSREC_E_UNSUPPORTED) return e;
+    if (f->prec != CSREC_PREC_F32 || f->correction_iters != 0) return CSREC_E_UNSUPPORTED;
+    return fista_hermitian_supported(p->M, p->N);
+}
+
 int check_admm(const csrec_problem* p, const csrec_admm_params* q, float* thr) {
     int e = check_problem(p, true);
     if (e) return e;
@@ -214,6 +221,12 @@ int32_t csrec_workspace_bytes(int32_t solver, const csrec_problem* problem, cons
             if ((e = check_fista_complex(problem, static_cast<const csrec_fista_params*>(params)))) return e;
             *bytes = problem->P > 0 ? fista_complex_workspace(problem->M, problem->N) : 0;
             return CSREC_OK;
+        case CSREC_SOLVER_FISTA_HERMITIAN: {
+            const csrec_fista_params* f = static_cast<const csrec_fista_params*>(params);
+            if ((e = check_fista_hermitian(problem, f))) return e;
+            *bytes = problem->P > 0 ? fista_hermitian_workspace(problem->M, problem->N, !(f->L > 0.0)) : 0;
+            return CSREC_OK;
+        }
         case CSREC_SOLVER_GOMP:
             e = fill_gomp(problem, static_cast<const csrec_gomp_params*>(params), l);
             break;
@@ -349,6 +362,38 @@ int32_t csrec_fista_complex(const csrec_problem* problem, const csrec_fista_para
         l.thr = (float)(params->lambda / params->L);
     }
     return fista_complex_launch(l, power);
+}
+
+int32_t csrec_fista_hermitian(const csrec_problem* problem, const csrec_fista_params* params, float* X,
+                              csrec_pixel_stats* stats) {
+    int e = check_fista_hermitian(problem, params);
+    if (e) return e;
+    if (problem->P == 0) return CSREC_OK;
+    if (!X) return CSREC_E_INVAL;
+    const bool power = !(params->L > 0.0);
+    if (power && (!problem->workspace ||
+                  problem->workspace_bytes < fista_hermitian_workspace(problem->M, problem->N, true)))
+        return CSREC_E_WORKSPACE;
+    FistaLaunch l{};
+    l.A = problem->A;
+    l.Y = problem->Y;
+    l.X0 = params->X0;
+    l.X = X;
+    l.stats = stats;
+    l.M = problem->M;
+    l.N = problem->N;
+    l.P = problem->P;
+    l.max_iter = params->max_iter;
+    l.eps = (float)params->eps;
+    l.lambda = params->lambda;
+    l.prec = CSREC_PREC_F32;
+    l.workspace = problem->workspace;
+    l.stream = reinterpret_cast<hipStream_t>(problem->stream);
+    if (!power) {
+        l.invL = (float)(1.0 / params->L);
+        l.thr = (float)(params->lambda / params->L);
+    }
+    return fista_hermitian_launch(l, power);
 }
 
 int32_t csrec_sparsify(const float* Psi, const float* A, const float* F, int32_t M, int32_t N, int64_t P,

@@ -61,6 +61,10 @@ int lipschitz_launch(const float* A, int M, int N, float* L_out, hipStream_t str
 int fista_complex_supported(int M, int N);
 size_t fista_complex_workspace(int M, int N);
 int fista_complex_launch(const FistaLaunch& a, bool power);
+// Real y, conjugate-symmetric columns of A: the half-spectrum iteration.
+int fista_hermitian_supported(int M, int N);
+size_t fista_hermitian_workspace(int M, int N, bool power);
+int fista_hermitian_launch(const FistaLaunch& a, bool power);
 
 struct AdmmLaunch {
     const float* A;

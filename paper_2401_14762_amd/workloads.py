@@ -288,6 +288,28 @@ def complex_cube(P: Optional[int] = None, N: int = COMPLEX["N"], M: int = COMPLE
                 sampling=sampling)
 
 
+def paper_shape_dft(name: str, P: Optional[int] = None, sampling: str = "subsample") -> dict:
+    """A PAPER_SHAPES cube measured for the complex DFT basis: the real
+    spectra F and the real Phi of paper_shape_cube, Y = F Phi^T (real, FP32:
+    y = Phi f), and A = Phi Psi with the unitary DFT synthesis Psi (complex64
+    A, complex128 A64; its columns are conjugate-symmetric)."""
+    c = paper_shape_cube(name, P, sampling)
+    psi = dft_synthesis(c["N"])
+    a64 = c["Phi"] @ psi
+    Y = (c["F"] @ c["Phi"].T).astype(np.float32)
+    return dict(c, A=a64.astype(np.complex64), A64=a64, Psi=psi, Y=Y)
+
+
+def dft_mixing_cube(P: int, N: int, M: int, sampling: str = "gaussian", config_id: int = 9) -> dict:
+    """Mixing-model spectra (40 dB) of N bands measured by a real Phi, with
+    A = Phi Psi for the unitary DFT basis: Y (P x M float32) real,
+    A (M x N complex64) conjugate-symmetric."""
+    a64, a32, psi, phi = complex_dictionary(N, M, rng_for(config_id, _S_PHI), sampling)
+    F = mixing_spectra(P, N, 40.0, config_id)
+    return dict(A=a32, A64=a64, Psi=psi, Phi=phi, F=F, Y=(F @ phi.T).astype(np.float32), M=M, N=N, P=P,
+                sampling=sampling)
+
+
 def pixel_subset(P: int, n: int, config_id: int) -> np.ndarray:
     """Seeded sorted subset of n pixel indices out of P."""
     n = min(n, P)

@@ -269,3 +269,26 @@ def test_fista_complex_validation(lib):
     pb.workspace, pb.workspace_bytes = 0x4000, n - 4
     assert lib.csrec_fista_complex(ctypes.byref(pb), ctypes.byref(_fista()), v, None) == L.E_WORKSPACE
     assert lib.csrec_fista_complex(ctypes.byref(_problem(P=0)), ctypes.byref(_fista()), None, None) == L.OK
+
+
+def test_fista_hermitian_validation(lib):
+    """Half-spectrum FISTA: FP32 only, M <= 96, N <= 256; no workspace with
+    a given L, C diag(sqrt(w)) (M x 2S floats, S = 16 ceil(ceil(N/2) / 16))
+    plus the L slot for the device estimate."""
+    S = L.SOLVER_FISTA_HERMITIAN
+    pb = _problem(M=90, N=224)
+    assert _ws(lib, S, pb, _fista()) == (L.OK, 0)
+    rc, n = _ws(lib, S, pb, _fista(L=0.0))
+    assert rc == L.OK and n == 90 * 2 * 112 * 4 // 256 * 256 + 256 * ((90 * 2 * 112 * 4) % 256 > 0) + 256
+    assert _ws(lib, S, pb, _fista(prec=2))[0] == L.E_UNSUPPORTED
+    assert _ws(lib, S, pb, _fista(correction_iters=1))[0] == L.E_UNSUPPORTED
+    assert _ws(lib, S, pb, _fista(eps=-1.0))[0] == L.E_INVAL
+    assert _ws(lib, S, _problem(M=96, N=256), _fista())[0] == L.OK
+    assert _ws(lib, S, _problem(M=97, N=256), _fista())[0] == L.E_UNSUPPORTED
+    assert _ws(lib, S, _problem(M=40, N=257), _fista())[0] == L.E_SHAPE
+    assert _ws(lib, S, _problem(P=0), _fista(L=0.0)) == (L.OK, 0)
+    v = ctypes.c_void_p(0x3000)
+    assert lib.csrec_fista_hermitian(ctypes.byref(pb), ctypes.byref(_fista(lambda_=-1.0)), v, None) == L.E_INVAL
+    assert lib.csrec_fista_hermitian(ctypes.byref(pb), ctypes.byref(_fista()), None, None) == L.E_INVAL
+    assert lib.csrec_fista_hermitian(ctypes.byref(pb), ctypes.byref(_fista(L=0.0)), v, None) == L.E_WORKSPACE
+    assert lib.csrec_fista_hermitian(ctypes.byref(_problem(P=0)), ctypes.byref(_fista()), None, None) == L.OK
