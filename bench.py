@@ -26,6 +26,10 @@ events and reported under "breakdown" (--legs):
              convergence ratio, time).
   admm       the headline cube with ADMM (Alg. 2, 200 iterations, lambda=1e-2,
              alpha=1.8, threshold lambda*alpha as printed, FP32).
+  dft        FISTA with the complex DFT basis (Section II): complex y on a
+             256x256 N=100 M=40 cube, and real y = Phi f (the half-spectrum
+             iteration) on the cubes of the data sets' shapes and a 256x256
+             N=200 M=80 cube; 200 iterations, FP32.
   serving    Poisson stream of tiles (200 tiles/s, sides log-uniform in
              [64, 512], N in {100, 200, 224}) through csrec_server_*:
              p50 / p99 latency (done - submit) and pixels/s.
@@ -59,6 +63,7 @@ PSNR_SAMPLE = 128
 ADMM_ITERS, ADMM_ALPHA = 200, 1.8
 PROTOCOL_T, PROTOCOL_EPS, PROTOCOL_LAMBDAS = 0.1, 1e-8, (0.1, 100.0)
 PROTOCOL_CONVEX_CAP, PROTOCOL_BIHT_CAP, PROTOCOL_COSAMP_CAP = 10000, 1000, 200
+DFT_ITERS = 200
 
 
 def measured_traffic(kernel_src: str, summary: str):
@@ -86,7 +91,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--pixels", type=int, default=0, help="override the cube size (testing only)")
-    ap.add_argument("--legs", default="precision,other,admm,protocol,serving",
+    ap.add_argument("--legs", default="precision,other,admm,dft,protocol,serving",
                     help="comma list of the legs measured after the timed region ('' for none)")
     ap.add_argument("--serve-tiles", type=int, default=400, help="measured serving tiles")
     ap.add_argument("--serve-warmup", type=int, default=40, help="serving tiles before the measured ones")
@@ -213,6 +218,53 @@ def leg_admm(torch, cs, pr, A, Y, stream, idx, samples):
     return {"workload": f"plain mixing-model cube, ADMM {ADMM_ITERS} it lambda={LAMBDA} alpha={ADMM_ALPHA} "
                         f"(threshold lambda*alpha), FP32", "pixels": P, "ms": ms, "pixels_per_s": P / (ms * 1e-3),
             "achieved_tflops": tf, "mfma_fp32_frac": tf / FP32_MFMA_PEAK_TFLOPS}
+
+
+def leg_dft(torch, cs, W, dev, stream, samples):
+    """FISTA with the complex DFT basis of Section II.  complex: complex y on
+    a 256x256 N=100 M=40 cube (the real embedding of A, 16 M N flops per
+    pixel-iteration: A x and A^* v in complex arithmetic).  hermitian: real
+    y = Phi f on the cubes of the data sets' shapes and on a 256x256 N=200
+    M=80 cube (the half-spectrum iteration, 4 M N flops per pixel-iteration:
+    two real M x N products; the complex iteration it reproduces counts
+    16 M N)."""
+    out = {"workload": f"FISTA {DFT_ITERS} it, complex DFT basis, FP32", "complex": {}, "hermitian": {}}
+    samples["dft"] = {}
+    c = W.complex_cube(65536)
+    P, M, N = c["P"], c["M"], c["N"]
+    log(f"leg dft: complex {P} pixels N={N} M={M}")
+    L = float(np.linalg.norm(c["A"].astype(np.complex128), 2) ** 2)
+    A = torch.from_numpy(c["A"]).to(dev)
+    Y = torch.from_numpy(c["Y"]).to(dev)
+    X = torch.empty((P, N), dtype=torch.complex64, device=dev)
+    _, ms = event_timed(torch, stream, lambda: cs.fista_complex(A, Y, lam=LAMBDA, L=L, max_iter=DFT_ITERS, out=X))
+    tf = P * DFT_ITERS * 16.0 * M * N / (ms * 1e-3) / 1e12
+    out["complex"] = {"cube": f"256x256 N={N} M={M} K={W.COMPLEX['K']}-sparse complex, 40 dB", "pixels": P,
+                      "ms": ms, "pixels_per_s": P / (ms * 1e-3), "achieved_tflops": tf,
+                      "mfma_fp32_frac": tf / FP32_MFMA_PEAK_TFLOPS}
+    del A, Y, X
+    cubes = [(name, W.paper_shape_dft(name), 100.0) for name in W.PAPER_SHAPES]
+    cubes.append(("mixing-256x256", W.dft_mixing_cube(65536, 200, 80, "gaussian"), LAMBDA))
+    for name, c, lam in cubes:
+        P, M, N = c["P"], c["M"], c["N"]
+        log(f"leg dft: hermitian {name} {P} pixels N={N} M={M}")
+        L = float(np.linalg.norm(c["A"].astype(np.complex128), 2) ** 2)
+        A = torch.from_numpy(c["A"]).to(dev)
+        Y = torch.from_numpy(c["Y"]).to(dev)
+        X = torch.empty((P, N), dtype=torch.complex64, device=dev)
+        _, ms = event_timed(torch, stream, lambda: cs.fista_hermitian(A, Y, lam=lam, L=L, max_iter=DFT_ITERS, out=X))
+        tf = P * DFT_ITERS * 4.0 * M * N / (ms * 1e-3) / 1e12
+        out["hermitian"][name] = {"pixels": P, "N": N, "M": M, "lambda": lam, "ms": ms,
+                                  "pixels_per_s": P / (ms * 1e-3), "achieved_tflops": tf,
+                                  "mfma_fp32_frac": tf / FP32_MFMA_PEAK_TFLOPS,
+                                  "complex_equivalent_tflops": 4.0 * tf}
+        if name == "salinas-like":
+            sidx = W.pixel_subset(P, 128, 77)
+            samples["dft"][name] = dict(A=c["A"], Y=c["Y"][sidx], Psi=c["Psi"], L=L, lam=lam,
+                                        gpu=X[torch.from_numpy(sidx).to(dev)].cpu().numpy())
+        del A, Y, X
+        torch.cuda.empty_cache()
+    return out
 
 
 def leg_protocol(torch, cs, W, dev, stream, samples):
@@ -376,6 +428,10 @@ def cpu_baseline_leg(W, pr, L, idx_psnr, Xf_s, Xg_s, n_sample, samples):
     if "admm" in samples:
         ref = oracle.admm(pr.A, pr.Y[idx_psnr], LAMBDA, ADMM_ALPHA, ADMM_ITERS)
         q["plain_admm"] = psnr(samples["admm"]["gpu"] @ Psi.T, ref["X"] @ Psi.T)
+    for name, s in samples.get("dft", {}).items():
+        ref = oracle.fista_complex(s["A"], s["Y"].astype(np.complex64), s["lam"], s["L"], DFT_ITERS)
+        # the spectra Psi x are real: compare their real parts
+        q[f"dft_hermitian_{name}"] = psnr((s["gpu"] @ s["Psi"].T).real, (ref["X"] @ s["Psi"].T).real)
     for name, s in samples.get("protocol", {}).items():
         # the oracle's own sparsification and gOMP on the same 256 pixels:
         # the GPU's result against the oracle's, and each against the
@@ -510,6 +566,8 @@ def main():
         breakdown["other_solvers"] = leg_other(torch, cs, W, dev, stream, samples)
     if "admm" in legs:
         breakdown["admm"] = leg_admm(torch, cs, pr, A, Y, stream, idx, samples)
+    if "dft" in legs:
+        breakdown["dft"] = leg_dft(torch, cs, W, dev, stream, samples)
     if "protocol" in legs:
         breakdown["protocol"] = leg_protocol(torch, cs, W, dev, stream, samples)
     if "serving" in legs:
