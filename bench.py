@@ -89,7 +89,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--pixels", type=int, default=0, help="override the cube size (testing only)")
     ap.add_argument("--legs", default="precision,other,admm,dft,protocol,serving",
                     help="comma list of the legs measured after the timed region ('' for none)")
