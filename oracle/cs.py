@@ -341,6 +341,61 @@ def admm(A, Y, lam: float, alpha: float, max_iter: int, eps: float = 0.0, X0=Non
                 flags=flags)
 
 
+def admm_complex(A, Y, lam: float, alpha: float, max_iter: int, eps: float = 0.0, X0=None,
+                 threshold: str = "paper", dtype=np.complex128) -> dict:
+    """ADMM (Alg. 2) for the complex measurement model of Section II (a
+    complex DFT basis makes A = Phi Psi and x complex): the steps of ``admm``
+    with A^* the conjugate transpose -- step 1 solves with the Hermitian
+    positive definite A^* A + alpha I by its Cholesky factor C C^* -- and the
+    soft threshold of step 2 acting on |x + w| (soft_threshold_complex).
+    Threshold as admm_threshold.  dtype=np.complex64 is the FP32 rounding
+    model.
+
+    Returns dict(X = x^I, Z = z^I (complex128), iters, delta, resid, flags)."""
+    A = np.asarray(A, dtype=dtype)
+    Y = np.asarray(Y, dtype=dtype)
+    rdt = A.real.dtype.type
+    P, M = Y.shape
+    N = A.shape[1]
+    tau = rdt(admm_threshold(lam, alpha, threshold))
+    fin = _finite_rows(Y)
+    Yc = np.where(fin[:, None], Y, dtype(0.0))
+    xc = np.zeros((P, N), dtype=dtype) if X0 is None else np.asarray(X0, dtype=dtype).copy()
+    xc[~fin] = 0.0
+    zc = xc.copy()
+    wc = xc.copy()
+    rc = Yc.copy()                   # r^0 = y
+    A64 = A.astype(np.complex128)
+    Cf = np.linalg.cholesky(np.conj(A64).T @ A64 + alpha * np.eye(N)).astype(dtype)   # A^* A + alpha I = C C^*
+    Ahy = Yc @ np.conj(A)            # rows (A^* y)^T
+    iters = np.zeros(P, dtype=np.int64)
+    delta = np.full(P, np.nan)
+    flags = np.zeros(P, dtype=np.int64)
+    flags[~fin] |= STOP_NONFINITE
+    live = fin.copy()
+    for i in range(1, max_iter + 1):
+        if not live.any():
+            break
+        a = np.nonzero(live)[0]
+        b = Ahy[a] + rdt(alpha) * (zc[a] - wc[a])                        # step 1
+        xn = np.linalg.solve(np.conj(Cf).T, np.linalg.solve(Cf, b.T)).T.astype(dtype)
+        v = xn + wc[a]
+        zn = soft_threshold_complex(v, tau)                              # step 2
+        wn = v - zn                                                      # step 3
+        rn = Yc[a] - xn @ A.T                                            # step 4
+        d = np.linalg.norm(rn - rc[a], axis=1)
+        xc[a], zc[a], wc[a], rc[a] = xn, zn, wn, rn
+        iters[a] = i
+        delta[a] = d
+        stop = d < eps
+        flags[a[stop]] |= STOP_CONVERGED
+        live[a[stop]] = False
+    flags[live] |= STOP_ITER_CAP
+    resid = np.linalg.norm(Yc - xc @ A.T, axis=1)
+    return dict(X=xc.astype(np.complex128), Z=zc.astype(np.complex128), iters=iters, delta=delta, resid=resid,
+                flags=flags)
+
+
 # --------------------------------------------------------------------------
 # Alg. 3 -- gOMP
 # --------------------------------------------------------------------------

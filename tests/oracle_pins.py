@@ -572,6 +572,59 @@ def check_fista_complex_kkt(orc):
     assert np.array_equal(top, np.sort(np.argsort(-np.abs(X), axis=1)[:, :3], axis=1))
 
 
+def check_admm_complex_real_case(orc):
+    """Real A and y: complex ADMM is the real one, both threshold readings."""
+    A, _, Y = _sparse_problem(12, 30, 3, 5, 51)
+    for mode in ("paper", "standard"):
+        r = orc.admm_complex(A, Y, 0.05, 1.8, 60, threshold=mode)
+        o = orc.admm(A, Y, 0.05, 1.8, 60, threshold=mode)
+        assert np.max(np.abs(r["X"].imag)) == 0.0 and np.max(np.abs(r["Z"].imag)) == 0.0
+        assert np.allclose(r["X"].real, o["X"], atol=1e-12) and np.allclose(r["Z"].real, o["Z"], atol=1e-12)
+        assert np.allclose(r["delta"], o["delta"], rtol=1e-10)
+
+
+def check_admm_complex_identity(orc):
+    """A = c I, c complex: with threshold tau the iteration solves Eq. 2 with
+    weight tau alpha, whose minimiser is x* = sign(u) max(|u| - tau alpha /
+    |c|^2, 0), u = conj(c) y / |c|^2; z^I and x^I converge to it."""
+    c = 0.8 * np.exp(0.7j)
+    y = (_rng(52).standard_normal((4, 9)) + 1j * _rng(53).standard_normal((4, 9)))
+    lam, alpha = 0.2, 1.8
+    u = np.conj(c) * y / abs(c) ** 2
+    mag = np.abs(u)
+    for mode, tau in (("paper", lam * alpha), ("standard", lam / alpha)):
+        w = tau * alpha / abs(c) ** 2
+        xs = np.where(mag > w, u * (mag - w) / np.where(mag > 0, mag, 1), 0)
+        r = orc.admm_complex(c * np.eye(9), y, lam, alpha, 3000, threshold=mode)
+        assert np.allclose(r["Z"], xs, atol=1e-9) and np.allclose(r["X"], xs, atol=1e-9), mode
+
+
+def check_admm_complex_matches_fista_complex(orc):
+    """Both solve the complex LASSO: ADMM with the lam / alpha threshold and
+    FISTA with weight lam reach the same minimiser; the paper's lam alpha
+    threshold solves it with weight lam alpha^2."""
+    A, _, Y = _complex_problem(15, 40, 3, 4, 54)
+    L = orc.lipschitz_complex(A)
+    lam, alpha = 0.03, 1.8
+    xf = orc.fista_complex(A, Y, lam, L, 6000)["X"]
+    xa = orc.admm_complex(A, Y, lam, alpha, 6000, threshold="standard")["Z"]
+    assert np.allclose(xa, xf, atol=1e-7), np.abs(xa - xf).max()
+    xf2 = orc.fista_complex(A, Y, lam * alpha * alpha, L, 6000)["X"]
+    xa2 = orc.admm_complex(A, Y, lam, alpha, 6000, threshold="paper")["Z"]
+    assert np.allclose(xa2, xf2, atol=1e-7), np.abs(xa2 - xf2).max()
+
+
+def check_admm_complex_phase_equivariance(orc):
+    """A -> e^{i a} A maps x -> e^{-i a} x, y -> e^{i b} y maps x -> e^{i b} x."""
+    A, _, Y = _complex_problem(15, 40, 4, 6, 55)
+    r0 = orc.admm_complex(A, Y, 0.05, 1.8, 40)
+    r1 = orc.admm_complex(np.exp(0.9j) * A, Y, 0.05, 1.8, 40)
+    r2 = orc.admm_complex(A, np.exp(-1.3j) * Y, 0.05, 1.8, 40)
+    assert np.allclose(r1["X"], np.exp(-0.9j) * r0["X"], atol=1e-10)
+    assert np.allclose(r2["X"], np.exp(-1.3j) * r0["X"], atol=1e-10)
+    assert np.allclose(r2["delta"], r0["delta"], rtol=1e-9)
+
+
 def check_sparsify_complex_basis(orc):
     """With a unitary complex basis x = Psi^* f: a spectrum of 5 large and 59
     tiny complex coefficients keeps exactly the large ones, with their values."""
@@ -674,5 +727,6 @@ ORACLE_CHECKS = [
     check_biht_recovery, check_one_bit, check_admm_matches_sklearn_lasso, check_admm_identity,
     check_admm_kkt_and_dual, check_admm_stop_rule, check_sparsify_worked, check_sparsify_transform,
     check_fista_complex_real_case, check_fista_complex_identity, check_fista_complex_phase_equivariance,
-    check_fista_complex_kkt, check_sparsify_complex_basis,
+    check_fista_complex_kkt, check_sparsify_complex_basis, check_admm_complex_real_case, check_admm_complex_identity,
+    check_admm_complex_matches_fista_complex, check_admm_complex_phase_equivariance,
 ]

@@ -52,6 +52,13 @@ MUTATIONS = [
      "x_new = soft_threshold(aux.real, rdt(lam / L)) + 1j * soft_threshold(aux.imag, rdt(lam / L))"),
     ("cfista-phase-dropped", "    return v * scale.astype(v.real.dtype)", "    return np.abs(v) * scale.astype(v.real.dtype)"),
     ("cfista-no-momentum", "z_new = x_new + rdt((t - 1.0) / t_new) * (x_new - xa)", "z_new = x_new"),
+    ("cadmm-transpose-not-adjoint", "Ahy = Yc @ np.conj(A) ", "Ahy = Yc @ A "),
+    ("cadmm-gram-not-hermitian", "np.linalg.cholesky(np.conj(A64).T @ A64 + alpha * np.eye(N))",
+     "np.linalg.cholesky(A64.T @ A64 + alpha * np.eye(N))"),
+    ("cadmm-factor-not-conjugated", "np.linalg.solve(np.conj(Cf).T, ", "np.linalg.solve(Cf.T, "),
+    ("cadmm-separable-shrink", "zn = soft_threshold_complex(v, tau)",
+     "zn = soft_threshold(v.real, tau) + 1j * soft_threshold(v.imag, tau)"),
+    ("cadmm-no-dual-in-threshold", "v = xn + wc[a]", "v = xn"),
 ]
 
 # mistakes planted in the sparsification (Section II)
