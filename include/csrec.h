@@ -17,6 +17,7 @@
  *                 complex DFT basis of Section II)
  *   csrec_fista_hermitian  the same for real y and conjugate-symmetric A
  *                 (a real Phi with the DFT basis): half-spectrum iteration
+ *   csrec_admm_hermitian   ADMM (Alg. 2) in the same setting
  *
  * and the pre-stage of the paper's evaluation protocol:
  *
@@ -83,6 +84,7 @@ extern "C" {
 #define CSREC_SOLVER_ADMM   4
 #define CSREC_SOLVER_FISTA_COMPLEX 5
 #define CSREC_SOLVER_FISTA_HERMITIAN 6
+#define CSREC_SOLVER_ADMM_HERMITIAN 7
 
 #define CSREC_MAX_N 256
 
@@ -259,6 +261,27 @@ int32_t csrec_fista_complex(const csrec_problem* problem, const csrec_fista_para
  * N <= CSREC_MAX_N.  X may alias X0. */
 int32_t csrec_fista_hermitian(const csrec_problem* problem, const csrec_fista_params* params, float* X,
                               csrec_pixel_stats* stats);
+
+/* ADMM (Alg. 2) with the complex DFT basis of Section II for REAL
+ * measurements, the setting of csrec_fista_hermitian: step 1 with A^* (the
+ * conjugate transpose), step 2's soft threshold on |x_k + w_k| (magnitude
+ * shrunk, phase kept), threshold as params->threshold.  Every iterate from a
+ * conjugate-symmetric x^0 is conjugate-symmetric, and the library iterates
+ * on the half spectrum: the same x^I and z^I as the full complex iteration up
+ * to rounding, with the work of a real ADMM on N unknowns.
+ *
+ * problem->A is M x N complex (interleaved (re, im) FP32 pairs); only its
+ * columns 0 .. floor(N/2) are read, and A[:, 0] (and A[:, N/2], N even) are
+ * taken as real.  problem->Y is P x M REAL FP32.  params->X0 (P x N complex,
+ * nullable) is read at entries 0 .. floor(N/2).  X and Z (P x N complex, Z
+ * nullable) receive the full conjugate-symmetric x^I and z^I; stats as
+ * csrec_admm.  Needs the workspace of
+ * csrec_workspace_bytes(CSREC_SOLVER_ADMM_HERMITIAN, ...): a real M x 2N'
+ * matrix of the half-spectrum layout (N' >= ceil(N/2) a multiple of 16) and
+ * the M x M matrix (alpha I + A A^*)^{-1}, formed on the device (the latter
+ * in FP64) on every call.  M <= 96, N <= CSREC_MAX_N. */
+int32_t csrec_admm_hermitian(const csrec_problem* problem, const csrec_admm_params* params, float* X, float* Z,
+                             csrec_pixel_stats* stats);
 
 /* Sparsification (Section II) fused with the compression of the sparsified
  * pixels.  For each of the P spectra f (rows of F, P x N): x = Psi^T f, where

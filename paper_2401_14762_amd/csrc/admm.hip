@@ -654,13 +654,20 @@ int admm_supported(int M, int N) {
 
 size_t admm_workspace(int M) { return align_up((size_t)M * M * sizeof(float), 256); }
 
+int admm_prepare_launch(const float* A, int M, int N, double alpha, float* R, hipStream_t stream) {
+    if (M > ADMM_MAX_M) return CSREC_E_UNSUPPORTED;
+    hipLaunchKernelGGL(admm_prepare_kernel, dim3(1), dim3(PREP_THREADS), 0, stream, A, M, N, alpha, R);
+    CSREC_HIP_TRY(hipGetLastError());
+    return CSREC_OK;
+}
+
 int admm_launch(const AdmmLaunch& l) {
     if (l.P == 0) return CSREC_OK;
     const AdmmVariant* v = admm_pick(l.M, l.N);
     if (!v || l.M > ADMM_MAX_M) return CSREC_E_UNSUPPORTED;
     float* R = static_cast<float*>(l.workspace);
-    hipLaunchKernelGGL(admm_prepare_kernel, dim3(1), dim3(PREP_THREADS), 0, l.stream, l.A, l.M, l.N, l.alpha, R);
-    CSREC_HIP_TRY(hipGetLastError());
+    int e = admm_prepare_launch(l.A, l.M, l.N, l.alpha, R, l.stream);
+    if (e) return e;
     AdmmArgs a;
     a.A = l.A;
     a.R = R;

@@ -65,6 +65,8 @@ int fista_complex_launch(const FistaLaunch& a, bool power);
 int fista_hermitian_supported(int M, int N);
 size_t fista_hermitian_workspace(int M, int N, bool power);
 int fista_hermitian_launch(const FistaLaunch& a, bool power);
+// Ch = C diag(sqrt(w)) (M x 2S) of the half-spectrum layout, S = 16 NTH
+int herm_scaled_launch(const float* A, int M, int N, int S, float* Ch, hipStream_t stream);
 
 struct AdmmLaunch {
     const float* A;
@@ -86,6 +88,12 @@ struct AdmmLaunch {
 int admm_supported(int M, int N);
 size_t admm_workspace(int M);
 int admm_launch(const AdmmLaunch& a);
+// R = (alpha I + A A^T)^{-1} (M x M) of an M x N matrix A
+int admm_prepare_launch(const float* A, int M, int N, double alpha, float* R, hipStream_t stream);
+// ADMM with the DFT basis on real y (half spectrum): A complex, X / Z complex
+int admm_hermitian_supported(int M, int N);
+size_t admm_hermitian_workspace(int M, int N);
+int admm_hermitian_launch(const AdmmLaunch& a);
 
 int sparsify_supported(int M, int N);
 int sparsify_launch(const float* Psi, const float* A, const float* F, int M, int N, int64_t P, float T, int ddof,

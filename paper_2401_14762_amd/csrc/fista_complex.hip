@@ -799,6 +799,14 @@ int fista_complex_launch(const FistaLaunch& l, bool power) {
 
 int fista_hermitian_supported(int M, int N) { return hpick(M, N) ? CSREC_OK : CSREC_E_UNSUPPORTED; }
 
+int herm_scaled_launch(const float* A, int M, int N, int S, float* Ch, hipStream_t stream) {
+    const int total = M * 2 * S;
+    hipLaunchKernelGGL(herm_scaled_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, stream, A, M, N,
+                       (N + 1) / 2, S, Ch);
+    CSREC_HIP_TRY(hipGetLastError());
+    return CSREC_OK;
+}
+
 // the device L: C diag(sqrt(w)) then the L slot
 size_t fista_hermitian_workspace(int M, int N, bool power) {
     const HVariant* v = hpick(M, N);
@@ -832,11 +840,9 @@ int fista_hermitian_launch(const FistaLaunch& l, bool power) {
         char* ws = static_cast<char*>(l.workspace);
         float* Ch = reinterpret_cast<float*>(ws);
         float* Ld = reinterpret_cast<float*>(ws + align_up((size_t)l.M * 2 * S * sizeof(float), 256));
-        const int total = l.M * 2 * S;
-        hipLaunchKernelGGL(herm_scaled_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, l.stream, l.A, l.M,
-                           l.N, Ha, S, Ch);
-        CSREC_HIP_TRY(hipGetLastError());
-        int e = lipschitz_launch(Ch, l.M, 2 * S, Ld, l.stream);
+        int e = herm_scaled_launch(l.A, l.M, l.N, S, Ch, l.stream);
+        if (e) return e;
+        e = lipschitz_launch(Ch, l.M, 2 * S, Ld, l.stream);
         if (e) return e;
         a.L_dev = Ld;
     }

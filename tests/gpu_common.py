@@ -124,3 +124,22 @@ def assert_cfista_parity(X_gpu, A, Y, lam, L, iters, floor=1e-5, **kw):
     assert e.max() <= max(floor, 2.0 * e32.max()), (e.max(), e32.max())
     assert np.median(e) <= max(floor / 10, 2.0 * np.median(e32)), (np.median(e), np.median(e32))
     return ref, e
+
+
+def assert_cadmm_parity(X_gpu, Z_gpu, A, Y, lam, alpha, iters, floor=1e-5, **kw):
+    """Complex ADMM parity: the bar of assert_admm_parity with the complex
+    oracle (complex128) and its complex64 rounding model, on x^I and z^I."""
+    import oracle
+    ref = oracle.admm_complex(A, Y, lam, alpha, iters, **kw)
+    r32 = oracle.admm_complex(A, Y, lam, alpha, iters, dtype=np.complex64, **kw)
+    for name, got in (("X", X_gpu), ("Z", Z_gpu)):
+        if got is None:
+            continue
+        e = rel_err_rows(got, ref[name])
+        e32 = rel_err_rows(r32[name], ref[name])
+        per_pixel = np.maximum(floor, 30.0 * e32)
+        bad = np.nonzero(e > per_pixel)[0]
+        assert len(bad) == 0, f"{name} pixels {bad[:8]}: err {e[bad[:8]]} vs complex64 model {e32[bad[:8]]}"
+        assert e.max() <= max(floor, 2.0 * e32.max()), (name, e.max(), e32.max())
+        assert np.median(e) <= max(floor / 10, 2.0 * np.median(e32)), (name, np.median(e), np.median(e32))
+    return ref

@@ -292,3 +292,22 @@ def test_fista_hermitian_validation(lib):
     assert lib.csrec_fista_hermitian(ctypes.byref(pb), ctypes.byref(_fista()), None, None) == L.E_INVAL
     assert lib.csrec_fista_hermitian(ctypes.byref(pb), ctypes.byref(_fista(L=0.0)), v, None) == L.E_WORKSPACE
     assert lib.csrec_fista_hermitian(ctypes.byref(_problem(P=0)), ctypes.byref(_fista()), None, None) == L.OK
+
+
+def test_admm_hermitian_validation(lib):
+    """Half-spectrum ADMM: the parameter checks of csrec_admm, M <= 96,
+    N <= 256; workspace = the half-spectrum matrix (M x 2S) + R (M x M)."""
+    S = L.SOLVER_ADMM_HERMITIAN
+    pb = _problem(M=90, N=224)
+    rc, n = _ws(lib, S, pb, _admm())
+    assert rc == L.OK and n == 90 * 224 * 4 + (90 * 90 * 4 + 255) // 256 * 256
+    for bad in (dict(alpha=0.0), dict(lambda_=-1.0), dict(threshold=3), dict(max_iter=-1)):
+        assert _ws(lib, S, pb, _admm(**bad))[0] == L.E_INVAL, bad
+    assert _ws(lib, S, _problem(M=96, N=256), _admm())[0] == L.OK
+    assert _ws(lib, S, _problem(M=97, N=256), _admm())[0] == L.E_UNSUPPORTED
+    assert _ws(lib, S, _problem(M=40, N=257), _admm())[0] == L.E_SHAPE
+    assert _ws(lib, S, _problem(P=0), _admm()) == (L.OK, 0)
+    v = ctypes.c_void_p(0x3000)
+    assert lib.csrec_admm_hermitian(ctypes.byref(pb), ctypes.byref(_admm()), None, None, None) == L.E_INVAL
+    assert lib.csrec_admm_hermitian(ctypes.byref(pb), ctypes.byref(_admm()), v, None, None) == L.E_WORKSPACE
+    assert lib.csrec_admm_hermitian(ctypes.byref(_problem(P=0)), ctypes.byref(_admm()), None, None, None) == L.OK

@@ -1,0 +1,153 @@
+"""GPU parity of csrec_admm_hermitian (Alg. 2 with the complex DFT basis of
+Section II, real measurements y = Phi f) against the FP64 complex oracle,
+which iterates on the full complex x with the Hermitian Cholesky factor of
+A^* A + alpha I.
+
+The kernel iterates on the half spectrum in scaled coordinates, with
+(alpha I + A A^*)^{-1} formed on the device; the oracle knows nothing of
+that reduction.  Tolerance (assert_cadmm_parity): per pixel, x^I and z^I
+within max(1e-5, 30x) the error of the oracle's complex64 rounding model,
+cube-wide max and median within twice the model's.  Outputs are checked to
+be exactly conjugate-symmetric."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import assert_cadmm_parity, note, np_of, require_gpu, to_dev
+from paper_2401_14762_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ALPHA = 1.8      # the penalty of Section IV
+LAM = 1e-2
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _run(torch, A, Y, lam, iters, **kw):
+    import paper_2401_14762_amd as cs
+    X0 = kw.pop("X0", None)
+    if X0 is not None:
+        kw["X0"] = to_dev(torch, X0.astype(np.complex64))
+    X, Z, st = cs.admm_hermitian(to_dev(torch, A), to_dev(torch, Y), lam=lam, max_iter=iters, want_z=True, **kw)
+    torch.cuda.synchronize()
+    return np_of(X), np_of(Z), {k: np_of(v) for k, v in st.items()}
+
+
+def _symmetric(X):
+    N = X.shape[1]
+    assert np.all(X[:, 0].imag == 0.0)
+    if N % 2 == 0:
+        assert np.all(X[:, N // 2].imag == 0.0)
+    k = np.arange(1, N)
+    assert np.array_equal(X[:, N - k], np.conj(X[:, k]))
+
+
+def _hermitian(x):
+    x = x.copy()
+    N = x.shape[1]
+    x[:, 0] = x[:, 0].real
+    if N % 2 == 0:
+        x[:, N // 2] = x[:, N // 2].real
+    k = np.arange(1, (N + 1) // 2)
+    x[:, N - k] = np.conj(x[:, k])
+    return x
+
+
+def _parity(X, Z, A, Y, lam, iters, **kw):
+    _symmetric(X)
+    _symmetric(Z)
+    return assert_cadmm_parity(X, Z, A, Y.astype(np.complex64), lam, ALPHA, iters, **kw)
+
+
+@pytest.mark.parametrize("N,M,sampling", [(17, 6, "gaussian"), (64, 24, "subsample"), (100, 40, "gaussian"),
+                                          (101, 40, "subsample"), (154, 62, "gaussian"), (198, 79, "subsample"),
+                                          (224, 90, "gaussian"), (255, 96, "subsample"), (256, 96, "gaussian")])
+def test_shapes(torch, N, M, sampling):
+    """Every kernel tile (M up to 32, 48, 64, 80, 96; half spectra up to 32,
+    64, 80, 112, 128 slots), odd and even N, both samplings."""
+    c = W.dft_mixing_cube(130, N, M, sampling, config_id=400 + N)
+    note(f"admm_hermitian N={N} M={M} {sampling} 100 it")
+    X, Z, st = _run(torch, c["A"], c["Y"], LAM, 100, alpha=ALPHA)
+    _parity(X, Z, c["A"], c["Y"], LAM, 100)
+    resid = np.linalg.norm(c["Y"].astype(np.float64) - (X.astype(np.complex128) @ c["A"].astype(np.complex128).T).real,
+                           axis=1)
+    assert np.all(np.abs(st["resid"] - resid) <= 1e-5 * np.linalg.norm(c["Y"], axis=1) + 1e-7)
+
+
+@pytest.mark.parametrize("threshold", ["paper", "standard"])
+def test_threshold_readings(torch, threshold):
+    c = W.dft_mixing_cube(256, 200, 80, "gaussian", config_id=410)
+    note(f"admm_hermitian N=200 M=80 threshold={threshold} 200 it")
+    X, Z, st = _run(torch, c["A"], c["Y"], LAM, 200, alpha=ALPHA, threshold=threshold)
+    _parity(X, Z, c["A"], c["Y"], LAM, 200, threshold=threshold)
+    assert np.all(st["iters"] == 200) and np.all(st["flags"] == oracle.STOP_ITER_CAP)
+
+
+@pytest.mark.parametrize("name", sorted(W.PAPER_SHAPES))
+def test_paper_cube_full_launch_sampled(torch, name):
+    """The data-set-shaped cubes at full size (40 % of the bands sampled,
+    peak 1e4, lambda = 0.1 of Section IV): the whole cube in one launch,
+    256 seeded pixels against the oracle."""
+    c = W.paper_shape_dft(name)
+    note(f"admm_hermitian {name} P={c['P']} N={c['N']} M={c['M']} 150 it (full launch)")
+    X, Z, _ = _run(torch, c["A"], c["Y"], 0.1, 150, alpha=ALPHA)
+    idx = W.pixel_subset(c["P"], 256, 500 + c["N"])
+    _parity(X[idx], Z[idx], c["A"], c["Y"][idx], 0.1, 150)
+
+
+@pytest.mark.parametrize("P", [1, 15, 17, 64, 65, 1000])
+def test_ragged_pixel_counts(torch, P):
+    c = W.dft_mixing_cube(P, 100, 40)
+    note(f"admm_hermitian ragged P={P}")
+    X, Z, _ = _run(torch, c["A"], c["Y"], LAM, 60, alpha=ALPHA)
+    _parity(X, Z, c["A"], c["Y"], LAM, 60)
+
+
+def test_eps_stop_and_x0(torch):
+    c = W.dft_mixing_cube(257, 200, 80)
+    eps = 1e-4
+    note("admm_hermitian eps stop")
+    X, Z, st = _run(torch, c["A"], c["Y"], LAM, 400, alpha=ALPHA, eps=eps)
+    Yc = c["Y"].astype(np.complex64)
+    ref = oracle.admm_complex(c["A"], Yc, LAM, ALPHA, 400, eps=eps)
+    same = st["iters"] == ref["iters"]
+    assert np.mean(same) > 0.97
+    _symmetric(X)
+    assert_cadmm_parity(X[same], Z[same], c["A"], Yc[same], LAM, ALPHA, 400, eps=eps)
+    assert np.all(st["flags"][st["iters"] < 400] & oracle.STOP_CONVERGED)
+    x0 = _hermitian(ref["X"].astype(np.complex64))
+    note("admm_hermitian warm start X0")
+    Xw, Zw, stw = _run(torch, c["A"], c["Y"], LAM, 20, alpha=ALPHA, X0=x0)
+    refw = assert_cadmm_parity(Xw, Zw, c["A"], Yc, LAM, ALPHA, 20, X0=x0.astype(np.complex128))
+    assert np.allclose(stw["delta"], refw["delta"], rtol=1e-3, atol=1e-6)
+
+
+def test_nonfinite_pixel_and_zero(torch):
+    c = W.dft_mixing_cube(40, 100, 40)
+    Y = c["Y"].copy()
+    Y[3, 5] = np.nan
+    Y[7, 0] = np.inf
+    Y[9] = 0.0
+    note("admm_hermitian nonfinite pixels")
+    X, Z, st = _run(torch, c["A"], Y, LAM, 30, alpha=ALPHA)
+    assert np.all(X[[3, 7, 9]] == 0.0) and np.all(Z[[3, 7, 9]] == 0.0)
+    assert st["flags"][3] == oracle.STOP_NONFINITE and st["flags"][7] == oracle.STOP_NONFINITE
+    assert st["iters"][3] == 0 and st["iters"][7] == 0
+    good = np.setdiff1d(np.arange(40), [3, 7, 9])
+    _parity(X[good], Z[good], c["A"], Y[good], LAM, 30)
+
+
+def test_zero_iterations_and_empty(torch):
+    import paper_2401_14762_amd as cs
+    c = W.dft_mixing_cube(20, 100, 40)
+    note("admm_hermitian max_iter=0")
+    X, Z, st = _run(torch, c["A"], c["Y"], LAM, 0, alpha=ALPHA)
+    assert np.all(X == 0) and np.all(Z == 0) and np.all(st["iters"] == 0)
+    assert np.allclose(st["resid"], np.linalg.norm(c["Y"], axis=1), rtol=1e-6)
+    Y = torch.empty((0, 40), dtype=torch.float32, device="cuda")
+    X0, _, _ = cs.admm_hermitian(to_dev(torch, c["A"]), Y, lam=LAM, max_iter=5)
+    assert X0.shape == (0, 100)
