@@ -29,7 +29,8 @@ events and reported under "breakdown" (--legs):
   dft        FISTA with the complex DFT basis (Section II): complex y on a
              256x256 N=100 M=40 cube, and real y = Phi f (the half-spectrum
              iteration) on the cubes of the data sets' shapes and a 256x256
-             N=200 M=80 cube; 200 iterations, FP32.
+             N=200 M=80 cube; ADMM (half spectrum) on two of them; 200
+             iterations, FP32.
   serving    Poisson stream of tiles (200 tiles/s, sides log-uniform in
              [64, 512], N in {100, 200, 224}) through csrec_server_*:
              p50 / p99 latency (done - submit) and pixels/s.
@@ -221,14 +222,16 @@ def leg_admm(torch, cs, pr, A, Y, stream, idx, samples):
 
 
 def leg_dft(torch, cs, W, dev, stream, samples):
-    """FISTA with the complex DFT basis of Section II.  complex: complex y on
-    a 256x256 N=100 M=40 cube (the real embedding of A, 16 M N flops per
-    pixel-iteration: A x and A^* v in complex arithmetic).  hermitian: real
-    y = Phi f on the cubes of the data sets' shapes and on a 256x256 N=200
-    M=80 cube (the half-spectrum iteration, 4 M N flops per pixel-iteration:
-    two real M x N products; the complex iteration it reproduces counts
-    16 M N)."""
-    out = {"workload": f"FISTA {DFT_ITERS} it, complex DFT basis, FP32", "complex": {}, "hermitian": {}}
+    """FISTA and ADMM with the complex DFT basis of Section II.  complex:
+    FISTA on complex y, a 256x256 N=100 M=40 cube (the real embedding of A,
+    16 M N flops per pixel-iteration: A x and A^* v in complex arithmetic).
+    hermitian: real y = Phi f on the cubes of the data sets' shapes and on a
+    256x256 N=200 M=80 cube (the half-spectrum iteration, 4 M N flops per
+    pixel-iteration: two real M x N products; the complex iteration it
+    reproduces counts 16 M N); ADMM on the salinas-like and the 256x256
+    cubes."""
+    out = {"workload": f"FISTA / ADMM (alpha={ADMM_ALPHA}) {DFT_ITERS} it, complex DFT basis, FP32", "complex": {},
+           "hermitian": {}}
     samples["dft"] = {}
     c = W.complex_cube(65536)
     P, M, N = c["P"], c["M"], c["N"]
@@ -258,6 +261,14 @@ def leg_dft(torch, cs, W, dev, stream, samples):
                                   "pixels_per_s": P / (ms * 1e-3), "achieved_tflops": tf,
                                   "mfma_fp32_frac": tf / FP32_MFMA_PEAK_TFLOPS,
                                   "complex_equivalent_tflops": 4.0 * tf}
+        if name in ("salinas-like", "mixing-256x256"):
+            # ADMM (Alg. 2) on the same cube: 4 M N + 2 M^2 flops per
+            # pixel-iteration (Ch v, R t, Ch^T e), (alpha I + A A^*)^{-1} included
+            _, ms_a = event_timed(torch, stream, lambda: cs.admm_hermitian(A, Y, lam=lam, alpha=ADMM_ALPHA,
+                                                                           max_iter=DFT_ITERS, out=X))
+            tfa = P * DFT_ITERS * (4.0 * M * N + 2.0 * M * M) / (ms_a * 1e-3) / 1e12
+            out["hermitian"][name]["admm"] = {"ms": ms_a, "pixels_per_s": P / (ms_a * 1e-3),
+                                              "achieved_tflops": tfa, "mfma_fp32_frac": tfa / FP32_MFMA_PEAK_TFLOPS}
         if name == "salinas-like":
             sidx = W.pixel_subset(P, 128, 77)
             samples["dft"][name] = dict(A=c["A"], Y=c["Y"][sidx], Psi=c["Psi"], L=L, lam=lam,
