@@ -18,6 +18,7 @@
  *   csrec_fista_hermitian  the same for real y and conjugate-symmetric A
  *                 (a real Phi with the DFT basis): half-spectrum iteration
  *   csrec_admm_hermitian   ADMM (Alg. 2) in the same setting
+ *   csrec_admm_complex     ADMM (Alg. 2) for complex A and y
  *
  * and the pre-stage of the paper's evaluation protocol:
  *
@@ -85,6 +86,7 @@ extern "C" {
 #define CSREC_SOLVER_FISTA_COMPLEX 5
 #define CSREC_SOLVER_FISTA_HERMITIAN 6
 #define CSREC_SOLVER_ADMM_HERMITIAN 7
+#define CSREC_SOLVER_ADMM_COMPLEX 8
 
 #define CSREC_MAX_N 256
 
@@ -282,6 +284,19 @@ int32_t csrec_fista_hermitian(const csrec_problem* problem, const csrec_fista_pa
  * in FP64) on every call.  M <= 96, N <= CSREC_MAX_N. */
 int32_t csrec_admm_hermitian(const csrec_problem* problem, const csrec_admm_params* params, float* X, float* Z,
                              csrec_pixel_stats* stats);
+
+/* ADMM (Alg. 2) for the complex measurement model of Section II (complex A
+ * and y): step 1 with A^* (the conjugate transpose), step 2's soft threshold
+ * on |x_n + w_n| (magnitude shrunk, phase kept).  A (M x N), Y (P x M),
+ * params->X0, X and Z (P x N; X0, Z nullable) are complex, interleaved
+ * (re, im) FP32 pairs; stats as csrec_admm.  Needs the workspace of
+ * csrec_workspace_bytes(CSREC_SOLVER_ADMM_COMPLEX, ...): the real embedding
+ * [Re A, -Im A; Im A, Re A] (2M x 2N' floats, N' >= N a multiple of 16) and
+ * the 2M x 2M embedding of (alpha I + A A^*)^{-1}, formed on the device on
+ * every call.  M <= 48, N <= 128, otherwise CSREC_E_UNSUPPORTED.  X may
+ * alias X0. */
+int32_t csrec_admm_complex(const csrec_problem* problem, const csrec_admm_params* params, float* X, float* Z,
+                           csrec_pixel_stats* stats);
 
 /* Sparsification (Section II) fused with the compression of the sparsified
  * pixels.  For each of the P spectra f (rows of F, P x N): x = Psi^T f, where

@@ -13,6 +13,7 @@ device memory and the stream, the library's HIP kernels do all the work.
     X, st = fista_complex(Ac, Yc, lam=1e-2, max_iter=200)       # Alg. 1, complex A
     X, st = fista_hermitian(Ac, Y, lam=1e-2, max_iter=200)      # Alg. 1, DFT basis, real y
     X, Z, st = admm_hermitian(Ac, Y, lam=1e-2, alpha=1.8)       # Alg. 2, DFT basis, real y
+    X, Z, st = admm_complex(Ac, Yc, lam=1e-2, alpha=1.8)        # Alg. 2, complex A and y
 
 A: M x N float32, Y: P x M float32, both CUDA (HIP) tensors, contiguous.
 ``st`` is a dict of per-pixel tensors: iters, flags, resid, delta.
@@ -25,7 +26,7 @@ from . import _lib
 from ._lib import (CsrecError, FLAG_CONVERGED, FLAG_FP64_FALLBACK, FLAG_ITER_CAP,
                    FLAG_NONFINITE, MAX_N)
 
-__all__ = ["sparsify", "fista", "fista_complex", "fista_hermitian", "admm", "admm_hermitian", "gomp", "cosamp", "biht", "lipschitz", "Server", "CsrecError", "FLAG_CONVERGED",
+__all__ = ["sparsify", "fista", "fista_complex", "fista_hermitian", "admm", "admm_hermitian", "admm_complex", "gomp", "cosamp", "biht", "lipschitz", "Server", "CsrecError", "FLAG_CONVERGED",
            "FLAG_ITER_CAP", "FLAG_FP64_FALLBACK", "FLAG_NONFINITE", "MAX_N", "workspace_bytes",
            "library"]
 
@@ -117,7 +118,7 @@ def _params(solver, A, P, kw):
         p.correction_iters = int(kw.get("correction_iters", 0))
         return p, {"fista": _lib.SOLVER_FISTA, "fista_complex": _lib.SOLVER_FISTA_COMPLEX,
                    "fista_hermitian": _lib.SOLVER_FISTA_HERMITIAN}[solver]
-    if solver in ("admm", "admm_hermitian"):
+    if solver in ("admm", "admm_hermitian", "admm_complex"):
         p = _lib.AdmmParams()
         p.struct_size = ctypes.sizeof(p)
         p.max_iter = int(kw.get("max_iter", 100))
@@ -129,7 +130,8 @@ def _params(solver, A, P, kw):
         if kw.get("threshold", "paper") not in _lib.ADMM_THR:
             raise ValueError(f"threshold must be one of {sorted(_lib.ADMM_THR)}")
         p.threshold = _lib.ADMM_THR[kw.get("threshold", "paper")]
-        return p, (_lib.SOLVER_ADMM if solver == "admm" else _lib.SOLVER_ADMM_HERMITIAN)
+        return p, {"admm": _lib.SOLVER_ADMM, "admm_hermitian": _lib.SOLVER_ADMM_HERMITIAN,
+                   "admm_complex": _lib.SOLVER_ADMM_COMPLEX}[solver]
     if solver == "gomp":
         p = _lib.GompParams()
         p.struct_size = ctypes.sizeof(p)
@@ -303,6 +305,36 @@ def admm_hermitian(A, Y, lam: float, alpha: float = 1.8, max_iter: int = 100, ep
     st = torch.empty((max(P, 1), 4), dtype=torch.int32, device=A.device)
     _lib.check(lib.csrec_admm_hermitian(ctypes.byref(pb), ctypes.byref(prm), _ptr(X), _ptr(Z), _ptr(st)),
                "csrec_admm_hermitian")
+    _keep_alive(ws, A.device, stream)
+    return X, Z, _stats_view(st[:P])
+
+
+def admm_complex(A, Y, lam: float, alpha: float = 1.8, max_iter: int = 100, eps: float = 0.0, X0=None,
+                 threshold: str = "paper", want_z: bool = False, stream=None, out=None):
+    """ADMM (Alg. 2) for complex A (M x N) and Y (P x M), both complex64:
+    A^* in step 1, the soft threshold on |x + w|.  Returns (X = x^I,
+    Z = z^I or None (P x N complex64), stats)."""
+    torch = _torch()
+    lib = library()
+    _check_dev("A", A, torch.complex64)
+    M, N = A.shape
+    _check_dev("Y", Y, torch.complex64)
+    P = Y.shape[0]
+    if Y.shape[1] != M:
+        raise ValueError("Y must be P x M")
+    if X0 is not None:
+        _check_dev("X0", X0, torch.complex64, (P, N))
+    pb = _problem(A, Y, P, stream)
+    prm, sid = _params("admm_complex", A, P, dict(lam=lam, alpha=alpha, max_iter=max_iter, eps=eps, X0=X0,
+                                                  threshold=threshold))
+    ws = _workspace(lib, sid, pb, prm, A.device)
+    if out is not None:
+        _check_dev("out", out, torch.complex64, (P, N))
+    X = out if out is not None else torch.empty((P, N), dtype=torch.complex64, device=A.device)
+    Z = torch.empty((P, N), dtype=torch.complex64, device=A.device) if want_z else None
+    st = torch.empty((max(P, 1), 4), dtype=torch.int32, device=A.device)
+    _lib.check(lib.csrec_admm_complex(ctypes.byref(pb), ctypes.byref(prm), _ptr(X), _ptr(Z), _ptr(st)),
+               "csrec_admm_complex")
     _keep_alive(ws, A.device, stream)
     return X, Z, _stats_view(st[:P])
 

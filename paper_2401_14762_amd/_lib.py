@@ -18,7 +18,7 @@ OK, E_INVAL, E_SHAPE, E_WORKSPACE, E_DEVICE, E_UNSUPPORTED, E_BUDGET = 0, -1, -2
 PREC = {"f32": 0, "bf16": 1, "f16": 2}
 FLAG_CONVERGED, FLAG_ITER_CAP, FLAG_FP64_FALLBACK, FLAG_NONFINITE = 1, 2, 4, 8
 SOLVER_FISTA, SOLVER_GOMP, SOLVER_COSAMP, SOLVER_BIHT, SOLVER_ADMM = 0, 1, 2, 3, 4
-SOLVER_FISTA_COMPLEX, SOLVER_FISTA_HERMITIAN, SOLVER_ADMM_HERMITIAN = 5, 6, 7
+SOLVER_FISTA_COMPLEX, SOLVER_FISTA_HERMITIAN, SOLVER_ADMM_HERMITIAN, SOLVER_ADMM_COMPLEX = 5, 6, 7, 8
 ADMM_THR = {"paper": 0, "standard": 1}
 PRUNE = {"each": 0, "final": 1}
 BIHT_MODE = {"real": 0, "one_bit": 1}
@@ -157,6 +157,8 @@ SIGNATURES = {
                                     ctypes.c_void_p]),
     "csrec_admm_hermitian": (ctypes.c_int32, [_P(Problem), _P(AdmmParams), ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p]),
+    "csrec_admm_complex": (ctypes.c_int32, [_P(Problem), _P(AdmmParams), ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
     "csrec_sparsify": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),

@@ -80,6 +80,12 @@ int check_admm_hermitian(const csrec_problem* p, const csrec_admm_params* q, flo
     return admm_hermitian_supported(p->M, p->N);
 }
 
+int check_admm_complex(const csrec_problem* p, const csrec_admm_params* q, float* thr) {
+    int e = check_admm(p, q, thr);
+    if (e != CSREC_OK && e != CSREC_E_UNSUPPORTED) return e;
+    return admm_complex_supported(p->M, p->N);
+}
+
 int fill_gomp(const csrec_problem* p, const csrec_gomp_params* q, GreedyLaunch& l) {
     int e = check_problem(p, true);
     if (e) return e;
@@ -228,6 +234,12 @@ int32_t csrec_workspace_bytes(int32_t solver, const csrec_problem* problem, cons
             if ((e = check_fista_complex(problem, static_cast<const csrec_fista_params*>(params)))) return e;
             *bytes = problem->P > 0 ? fista_complex_workspace(problem->M, problem->N) : 0;
             return CSREC_OK;
+        case CSREC_SOLVER_ADMM_COMPLEX: {
+            float thr;
+            if ((e = check_admm_complex(problem, static_cast<const csrec_admm_params*>(params), &thr))) return e;
+            *bytes = problem->P > 0 ? admm_complex_workspace(problem->M, problem->N) : 0;
+            return CSREC_OK;
+        }
         case CSREC_SOLVER_ADMM_HERMITIAN: {
             float thr;
             if ((e = check_admm_hermitian(problem, static_cast<const csrec_admm_params*>(params), &thr))) return e;
@@ -435,6 +447,34 @@ int32_t csrec_admm_hermitian(const csrec_problem* problem, const csrec_admm_para
     l.workspace = problem->workspace;
     l.stream = reinterpret_cast<hipStream_t>(problem->stream);
     return admm_hermitian_launch(l);
+}
+
+int32_t csrec_admm_complex(const csrec_problem* problem, const csrec_admm_params* params, float* X, float* Z,
+                           csrec_pixel_stats* stats) {
+    float thr = 0.f;
+    int e = check_admm_complex(problem, params, &thr);
+    if (e) return e;
+    if (problem->P == 0) return CSREC_OK;
+    if (!X) return CSREC_E_INVAL;
+    if (!problem->workspace || problem->workspace_bytes < admm_complex_workspace(problem->M, problem->N))
+        return CSREC_E_WORKSPACE;
+    AdmmLaunch l{};
+    l.A = problem->A;
+    l.Y = problem->Y;
+    l.X0 = params->X0;
+    l.X = X;
+    l.Z = Z;
+    l.stats = stats;
+    l.M = problem->M;
+    l.N = problem->N;
+    l.P = problem->P;
+    l.max_iter = params->max_iter;
+    l.alpha = params->alpha;
+    l.thr = thr;
+    l.eps = (float)params->eps;
+    l.workspace = problem->workspace;
+    l.stream = reinterpret_cast<hipStream_t>(problem->stream);
+    return admm_complex_launch(l);
 }
 
 int32_t csrec_sparsify(const float* Psi, const float* A, const float* F, int32_t M, int32_t N, int64_t P,

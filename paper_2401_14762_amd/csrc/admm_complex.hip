@@ -23,6 +23,14 @@
 // iteration are those of the real kernel; the tile loop runs over the pairs
 // (p, p + NTH), and the next pair's Ch^T e is interleaved with this pair's
 // Ch v.
+//
+// Complex y (CY).  The same kernel runs ADMM on the real embedding
+// A' = [Re A, -Im A; Im A, Re A] (2M x 2N', N' = 16 NTH): A' [Re x; Im x] =
+// [Re Ax; Im Ax], A'^T [Re u; Im u] = [Re A^*u; Im A^*u], ||x|| is the
+// 2-norm of [Re x; Im x], and (alpha I + A' A'^T)^{-1} is the embedding of
+// (alpha I + A A^*)^{-1}.  Re x_n and Im x_n again sit in tiles p and
+// p + NTH; the threshold is tau on every pair, and there is no mirrored
+// half.
 #include "common.hpp"
 
 #include <cmath>
@@ -34,14 +42,14 @@ constexpr float kSqrt2 = 1.41421356237309515f;
 constexpr float kRsqrt2 = 0.707106781186547573f;
 
 struct AdmmHArgs {
-    const float* Ch;      // M x 2S row-major (S = 16 NTH)
+    const float* Ch;      // M x 2S row-major (S = 16 NTH); CY: the embedding A'
     const float* R;       // M x M row-major, symmetric
-    const float* Y;       // P x M real
-    const float* X0;      // P x N complex, nullable; entries 0 .. floor(N/2) are read
+    const float* Y;       // P x M real; CY: P x Mc complex (M = 2 Mc)
+    const float* X0;      // P x N complex, nullable; real y: entries 0 .. floor(N/2) are read
     float* X;             // P x N complex
     float* Z;             // P x N complex, nullable
     csrec_pixel_stats* stats;
-    int M, N, Ha;
+    int M, N, Ha, Mc;
     int64_t P;
     int max_iter;
     float alpha, thr, eps;
@@ -92,7 +100,7 @@ struct OpsSingle {
     }
 };
 
-template <int MT, int NTH, class Ops>
+template <int MT, int NTH, bool CY, class Ops>
 __device__ __forceinline__ void admm_h_body(const AdmmHArgs& a, const Ops& ops, int h, int j, int64_t pix) {
     constexpr int NT = 2 * NTH;
     const int M = a.M, N = a.N, Ha = a.Ha;
@@ -109,7 +117,12 @@ __device__ __forceinline__ void admm_h_body(const AdmmHArgs& a, const Ops& ops, 
             const int m = 16 * mt + cm_h + r;
             float v = 0.f;
             if (valid && m < M) {
-                v = a.Y[pix * M + m];
+                if constexpr (CY) {
+                    const int mc = m < a.Mc ? m : m - a.Mc;
+                    v = a.Y[((size_t)pix * a.Mc + mc) * 2 + (m < a.Mc ? 0 : 1)];
+                } else {
+                    v = a.Y[pix * M + m];
+                }
                 if (!isfinite(v)) bad = 1;
             }
             Rp[mt][r] = v;
@@ -143,7 +156,12 @@ __device__ __forceinline__ void admm_h_body(const AdmmHArgs& a, const Ops& ops, 
         for (int r = 0; r < 4; ++r) {
             const int s = 16 * p + 4 * r + h;
             float va = 0.f, vb = 0.f;
-            if (a.X0 && valid && !bad) {
+            if (CY) {
+                if (a.X0 && valid && !bad && s < N) {
+                    va = a.X0[((size_t)pix * N + s) * 2];
+                    vb = a.X0[((size_t)pix * N + s) * 2 + 1];
+                }
+            } else if (a.X0 && valid && !bad) {
                 if (s == 0) {
                     va = a.X0[(size_t)pix * N * 2];
                     if (!(N & 1)) vb = a.X0[((size_t)pix * N + N / 2) * 2];
@@ -167,7 +185,7 @@ __device__ __forceinline__ void admm_h_body(const AdmmHArgs& a, const Ops& ops, 
     bool converged = false;
     int iters = 0;
     float last_d2 = __builtin_nanf("");
-    const float alpha = a.alpha, thr = a.thr, thr_pair = a.thr * kSqrt2;
+    const float alpha = a.alpha, thr = a.thr, thr_pair = CY ? a.thr : a.thr * kSqrt2;
     const bool check_eps = a.eps > 0.f;
 
     for (int it = 0; it < a.max_iter; ++it) {
@@ -229,7 +247,7 @@ __device__ __forceinline__ void admm_h_body(const AdmmHArgs& a, const Ops& ops, 
                 const float mag = sqrtf(ta * ta + tb * tb);
                 const float sc = mag > thr_pair ? (mag - thr_pair) / mag : 0.f;
                 float za = ta * sc, zb = tb * sc;
-                if (p == 0 && r == 0) {
+                if (!CY && p == 0 && r == 0) {
                     // slot 0: x_0 and x_{N/2}, two real scalars, threshold tau
                     za = h0 ? ta - __builtin_amdgcn_fmed3f(ta, -thr, thr) : za;
                     zb = h0 ? tb - __builtin_amdgcn_fmed3f(tb, -thr, thr) : zb;
@@ -310,7 +328,16 @@ __device__ __forceinline__ void admm_h_body(const AdmmHArgs& a, const Ops& ops, 
                 const float xa = iters == 0 ? Zr[p][r] : Wr[p][r];
                 const float xb = iters == 0 ? Zr[p + NTH][r] : Wr[p + NTH][r];
                 const float za = Zr[p][r], zb = Zr[p + NTH][r];
-                if (s == 0) {
+                if (CY) {
+                    if (s < N) {
+                        X[2 * s] = xa;
+                        X[2 * s + 1] = xb;
+                        if (Zo) {
+                            Zo[2 * s] = za;
+                            Zo[2 * s + 1] = zb;
+                        }
+                    }
+                } else if (s == 0) {
                     X[0] = xa;
                     X[1] = 0.f;
                     if (!(N & 1)) {
@@ -351,7 +378,7 @@ __device__ __forceinline__ void admm_h_body(const AdmmHArgs& a, const Ops& ops, 
 
 // PRE: Ch twice and R once in LDS in the operand order ((4 MT NTH + MT^2)
 // KiB); otherwise each once with padded pitches.
-template <int MT, int NTH, int WAVES, int MINW, bool PRE>
+template <int MT, int NTH, int WAVES, int MINW, bool PRE, bool CY>
 __global__ __launch_bounds__(WAVES * 64, MINW) void admm_h32_kernel(AdmmHArgs a) {
     constexpr int NT = 2 * NTH;
     constexpr int NC = 16 * NT;   // columns of Ch
@@ -411,7 +438,7 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void admm_h32_kernel(AdmmHArgs a)
         }
         __syncthreads();
         const OpsPre<MT, NT> ops{sA1 + lane, sA2 + lane, sR3 + lane};
-        admm_h_body<MT, NTH>(a, ops, h, j, pix);
+        admm_h_body<MT, NTH, CY>(a, ops, h, j, pix);
     } else {
         using O = OpsSingle<MT, NT>;
         constexpr int PA = O::PA, PR = O::PR, ROWS = 16 * MT;
@@ -427,7 +454,7 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void admm_h32_kernel(AdmmHArgs a)
         }
         __syncthreads();
         const O ops{sA + mu_j * PA + h, sA + cm_h * PA + nu_j, sR + cm_h * PR + mu_j};
-        admm_h_body<MT, NTH>(a, ops, h, j, pix);
+        admm_h_body<MT, NTH, CY>(a, ops, h, j, pix);
     }
 }
 
@@ -435,25 +462,28 @@ typedef void (*admm_h_kernel_t)(AdmmHArgs);
 
 struct AHVariant {
     int MT, NTH;
-    admm_h_kernel_t fn;
+    admm_h_kernel_t fn;    // real y, half spectrum
+    admm_h_kernel_t fnc;   // complex y, embedding
 };
 
+#define ADMM_H_VARIANT(MT, NTH, MINW, PRE) \
+    { MT, NTH, admm_h32_kernel<MT, NTH, 4, MINW, PRE, false>, admm_h32_kernel<MT, NTH, 4, MINW, PRE, true> }
 const AHVariant kAHVariants[] = {
-    {2, 2, admm_h32_kernel<2, 2, 4, 2, true>},
-    {3, 4, admm_h32_kernel<3, 4, 4, 2, true>},
-    {4, 5, admm_h32_kernel<4, 5, 4, 1, true>},
-    {5, 7, admm_h32_kernel<5, 7, 4, 1, false>},
-    {6, 7, admm_h32_kernel<6, 7, 4, 1, false>},
-    {6, 8, admm_h32_kernel<6, 8, 4, 1, false>},
+    ADMM_H_VARIANT(2, 2, 2, true),  ADMM_H_VARIANT(3, 4, 2, true),  ADMM_H_VARIANT(4, 5, 1, true),
+    ADMM_H_VARIANT(5, 7, 1, false), ADMM_H_VARIANT(6, 7, 1, false), ADMM_H_VARIANT(6, 8, 1, false),
 };
+#undef ADMM_H_VARIANT
 
-const AHVariant* ahpick(int M, int N) {
-    const int mt = (int)ceil_div(M, 16), nth = (int)ceil_div((N + 1) / 2, 16);
+// rows: M (real y) or 2M (complex y); pairs: ceil(N/2) slots (real y) or N (complex y)
+const AHVariant* ahpick_rows(int rows, int pairs) {
+    const int mt = (int)ceil_div(rows, 16), nth = (int)ceil_div(pairs, 16);
     const AHVariant* best = nullptr;
     for (const auto& v : kAHVariants)
         if (v.MT >= mt && v.NTH >= nth && (!best || v.MT * v.NTH < best->MT * best->NTH)) best = &v;
     return best;
 }
+
+const AHVariant* ahpick(int M, int N) { return ahpick_rows(M, (N + 1) / 2); }
 
 }  // namespace
 
@@ -486,6 +516,7 @@ int admm_hermitian_launch(const AdmmLaunch& l) {
     a.Z = l.Z;
     a.stats = l.stats;
     a.M = l.M;
+    a.Mc = l.M;
     a.N = l.N;
     a.Ha = (l.N + 1) / 2;
     a.P = l.P;
@@ -496,6 +527,53 @@ int admm_hermitian_launch(const AdmmLaunch& l) {
     const int64_t blocks = ceil_div(l.P, 16 * 4);
     if (blocks > 0x7fffffff) return CSREC_E_SHAPE;
     hipLaunchKernelGGL(v->fn, dim3((unsigned)blocks), dim3(64 * 4), 0, l.stream, a);
+    CSREC_HIP_TRY(hipGetLastError());
+    return CSREC_OK;
+}
+
+int admm_complex_supported(int M, int N) {
+    return (2 * M <= 96 && ahpick_rows(2 * M, N)) ? CSREC_OK : CSREC_E_UNSUPPORTED;
+}
+
+// A' (2M x 2S floats), then R (2M x 2M floats)
+size_t admm_complex_workspace(int M, int N) {
+    const AHVariant* v = ahpick_rows(2 * M, N);
+    if (!v) return 0;
+    return align_up((size_t)2 * M * 2 * 16 * v->NTH * sizeof(float), 256) +
+           align_up((size_t)4 * M * M * sizeof(float), 256);
+}
+
+int admm_complex_launch(const AdmmLaunch& l) {
+    if (l.P == 0) return CSREC_OK;
+    const AHVariant* v = ahpick_rows(2 * l.M, l.N);
+    if (!v || 2 * l.M > 96) return CSREC_E_UNSUPPORTED;
+    const int S = 16 * v->NTH;
+    char* ws = static_cast<char*>(l.workspace);
+    float* Ap = reinterpret_cast<float*>(ws);
+    float* R = reinterpret_cast<float*>(ws + align_up((size_t)2 * l.M * 2 * S * sizeof(float), 256));
+    int e = complex_embed_launch(l.A, l.M, l.N, S, Ap, l.stream);
+    if (e) return e;
+    if ((e = admm_prepare_launch(Ap, 2 * l.M, 2 * S, l.alpha, R, l.stream))) return e;
+    AdmmHArgs a;
+    a.Ch = Ap;
+    a.R = R;
+    a.Y = l.Y;
+    a.X0 = l.X0;
+    a.X = l.X;
+    a.Z = l.Z;
+    a.stats = l.stats;
+    a.M = 2 * l.M;
+    a.Mc = l.M;
+    a.N = l.N;
+    a.Ha = l.N;
+    a.P = l.P;
+    a.max_iter = l.max_iter;
+    a.alpha = (float)l.alpha;
+    a.thr = l.thr;
+    a.eps = l.eps;
+    const int64_t blocks = ceil_div(l.P, 16 * 4);
+    if (blocks > 0x7fffffff) return CSREC_E_SHAPE;
+    hipLaunchKernelGGL(v->fnc, dim3((unsigned)blocks), dim3(64 * 4), 0, l.stream, a);
     CSREC_HIP_TRY(hipGetLastError());
     return CSREC_OK;
 }

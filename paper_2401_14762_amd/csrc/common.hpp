@@ -65,6 +65,8 @@ int fista_complex_launch(const FistaLaunch& a, bool power);
 int fista_hermitian_supported(int M, int N);
 size_t fista_hermitian_workspace(int M, int N, bool power);
 int fista_hermitian_launch(const FistaLaunch& a, bool power);
+// A' = [Re A, -Im A; Im A, Re A] (2M x 2NP) of complex A (M x N)
+int complex_embed_launch(const float* A, int M, int N, int NP, float* Ap, hipStream_t stream);
 // Ch = C diag(sqrt(w)) (M x 2S) of the half-spectrum layout, S = 16 NTH
 int herm_scaled_launch(const float* A, int M, int N, int S, float* Ch, hipStream_t stream);
 
@@ -94,6 +96,10 @@ int admm_prepare_launch(const float* A, int M, int N, double alpha, float* R, hi
 int admm_hermitian_supported(int M, int N);
 size_t admm_hermitian_workspace(int M, int N);
 int admm_hermitian_launch(const AdmmLaunch& a);
+// ADMM with complex A and y (real embedding): A, Y, X0, X, Z complex
+int admm_complex_supported(int M, int N);
+size_t admm_complex_workspace(int M, int N);
+int admm_complex_launch(const AdmmLaunch& a);
 
 int sparsify_supported(int M, int N);
 int sparsify_launch(const float* Psi, const float* A, const float* F, int M, int N, int64_t P, float T, int ddof,

@@ -747,6 +747,13 @@ const HVariant* hpick(int M, int N) {
 
 int fista_complex_supported(int M, int N) { return cpick(M, N) ? CSREC_OK : CSREC_E_UNSUPPORTED; }
 
+int complex_embed_launch(const float* A, int M, int N, int NP, float* Ap, hipStream_t stream) {
+    const int64_t total = (int64_t)2 * M * 2 * NP;
+    hipLaunchKernelGGL(embed_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, stream, A, M, N, NP, Ap);
+    CSREC_HIP_TRY(hipGetLastError());
+    return CSREC_OK;
+}
+
 // A' has 2 NP columns with NP = 16 NTH of the chosen variant, so that the
 // imaginary block starts at tile NTH.
 size_t fista_complex_workspace(int M, int N) {
@@ -764,10 +771,8 @@ int fista_complex_launch(const FistaLaunch& l, bool power) {
     char* ws = static_cast<char*>(l.workspace);
     float* Ap = reinterpret_cast<float*>(ws);
     float* Ld = reinterpret_cast<float*>(ws + align_up((size_t)2 * l.M * 2 * NP * sizeof(float), 256));
-    const int64_t total = (int64_t)2 * l.M * 2 * NP;
-    hipLaunchKernelGGL(embed_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, l.stream, l.A, l.M, l.N, NP,
-                       Ap);
-    CSREC_HIP_TRY(hipGetLastError());
+    int e0 = complex_embed_launch(l.A, l.M, l.N, NP, Ap, l.stream);
+    if (e0) return e0;
     CFistaArgs a;
     a.Ap = Ap;
     a.Y = l.Y;

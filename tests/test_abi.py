@@ -311,3 +311,22 @@ def test_admm_hermitian_validation(lib):
     assert lib.csrec_admm_hermitian(ctypes.byref(pb), ctypes.byref(_admm()), None, None, None) == L.E_INVAL
     assert lib.csrec_admm_hermitian(ctypes.byref(pb), ctypes.byref(_admm()), v, None, None) == L.E_WORKSPACE
     assert lib.csrec_admm_hermitian(ctypes.byref(_problem(P=0)), ctypes.byref(_admm()), None, None, None) == L.OK
+
+
+def test_admm_complex_validation(lib):
+    """Complex ADMM: the parameter checks of csrec_admm, M <= 48, N <= 128;
+    workspace = the embedding (2M x 2N') + the embedded R (2M x 2M)."""
+    S = L.SOLVER_ADMM_COMPLEX
+    pb = _problem(M=40, N=100)
+    rc, n = _ws(lib, S, pb, _admm())
+    assert rc == L.OK and n == 80 * 224 * 4 + (80 * 80 * 4 + 255) // 256 * 256
+    for bad in (dict(alpha=-1.0), dict(lambda_=float("nan")), dict(threshold=2)):
+        assert _ws(lib, S, pb, _admm(**bad))[0] == L.E_INVAL, bad
+    assert _ws(lib, S, _problem(M=48, N=128), _admm())[0] == L.OK
+    assert _ws(lib, S, _problem(M=49, N=128), _admm())[0] == L.E_UNSUPPORTED
+    assert _ws(lib, S, _problem(M=40, N=129), _admm())[0] == L.E_UNSUPPORTED
+    assert _ws(lib, S, _problem(P=0), _admm()) == (L.OK, 0)
+    v = ctypes.c_void_p(0x3000)
+    assert lib.csrec_admm_complex(ctypes.byref(pb), ctypes.byref(_admm()), None, None, None) == L.E_INVAL
+    assert lib.csrec_admm_complex(ctypes.byref(pb), ctypes.byref(_admm()), v, None, None) == L.E_WORKSPACE
+    assert lib.csrec_admm_complex(ctypes.byref(_problem(P=0)), ctypes.byref(_admm()), None, None, None) == L.OK

@@ -1,0 +1,111 @@
+"""GPU parity of csrec_admm_complex (Alg. 2 for complex A and y, Section II's
+complex measurement model) against the FP64 complex ADMM oracle.
+
+The kernel runs the real iteration on the embedding [Re A, -Im A; Im A, Re A]
+with (alpha I + A A^*)^{-1} embedded likewise, and the soft threshold on each
+(Re, Im) pair.  Tolerance (assert_cadmm_parity): x^I and z^I per pixel within
+max(1e-5, 30x) the error of the oracle's complex64 rounding model, cube-wide
+max and median within twice the model's."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import assert_cadmm_parity, note, np_of, require_gpu, to_dev
+from paper_2401_14762_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ALPHA = 1.8
+LAM = 1e-2
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _run(torch, A, Y, lam, iters, **kw):
+    import paper_2401_14762_amd as cs
+    X0 = kw.pop("X0", None)
+    if X0 is not None:
+        kw["X0"] = to_dev(torch, X0.astype(np.complex64))
+    X, Z, st = cs.admm_complex(to_dev(torch, A), to_dev(torch, Y), lam=lam, max_iter=iters, want_z=True, **kw)
+    torch.cuda.synchronize()
+    return np_of(X), np_of(Z), {k: np_of(v) for k, v in st.items()}
+
+
+@pytest.mark.parametrize("N,M,sampling", [(17, 5, "gaussian"), (30, 12, "subsample"), (60, 24, "gaussian"),
+                                          (80, 32, "subsample"), (100, 40, "gaussian"), (112, 45, "gaussian"),
+                                          (128, 48, "subsample")])
+def test_shapes(torch, N, M, sampling):
+    """Every kernel tile (2M up to 32, 48, 64, 80, 96 rows; N up to 32, 64,
+    80, 112, 128) with ragged M and N and both samplings."""
+    c = W.complex_cube(130, N=N, M=M, K=max(2, M // 5), sampling=sampling, config_id=600 + N)
+    note(f"admm_complex N={N} M={M} {sampling} 100 it")
+    X, Z, st = _run(torch, c["A"], c["Y"], LAM, 100, alpha=ALPHA)
+    assert_cadmm_parity(X, Z, c["A"], c["Y"], LAM, ALPHA, 100)
+    resid = np.linalg.norm(c["Y"].astype(np.complex128) - X.astype(np.complex128) @ c["A"].astype(np.complex128).T,
+                           axis=1)
+    assert np.all(np.abs(st["resid"] - resid) <= 1e-5 * np.linalg.norm(c["Y"], axis=1) + 1e-7)
+
+
+@pytest.mark.parametrize("threshold", ["paper", "standard"])
+def test_threshold_readings_full_cube(torch, threshold):
+    """256x256 N=100 M=40 in one launch; 512 seeded pixels against the oracle."""
+    c = W.complex_cube(65536)
+    note(f"admm_complex 256x256 N=100 M=40 threshold={threshold} 200 it (full launch)")
+    X, Z, st = _run(torch, c["A"], c["Y"], LAM, 200, alpha=ALPHA, threshold=threshold)
+    idx = W.pixel_subset(c["P"], 512, 8)
+    assert_cadmm_parity(X[idx], Z[idx], c["A"], c["Y"][idx], LAM, ALPHA, 200, threshold=threshold)
+    assert np.all(st["iters"] == 200)
+
+
+@pytest.mark.parametrize("P", [1, 15, 17, 64, 65, 1000])
+def test_ragged_pixel_counts(torch, P):
+    c = W.complex_cube(P)
+    note(f"admm_complex ragged P={P}")
+    X, Z, _ = _run(torch, c["A"], c["Y"], LAM, 60, alpha=ALPHA)
+    assert_cadmm_parity(X, Z, c["A"], c["Y"], LAM, ALPHA, 60)
+
+
+def test_eps_stop_and_x0(torch):
+    c = W.complex_cube(257)
+    eps = 1e-4
+    note("admm_complex eps stop")
+    X, Z, st = _run(torch, c["A"], c["Y"], LAM, 400, alpha=ALPHA, eps=eps)
+    ref = oracle.admm_complex(c["A"], c["Y"], LAM, ALPHA, 400, eps=eps)
+    same = st["iters"] == ref["iters"]
+    assert np.mean(same) > 0.97
+    assert_cadmm_parity(X[same], Z[same], c["A"], c["Y"][same], LAM, ALPHA, 400, eps=eps)
+    assert np.all(st["flags"][st["iters"] < 400] & oracle.STOP_CONVERGED)
+    x0 = ref["X"].astype(np.complex64)
+    note("admm_complex warm start X0")
+    Xw, Zw, stw = _run(torch, c["A"], c["Y"], LAM, 20, alpha=ALPHA, X0=x0)
+    refw = assert_cadmm_parity(Xw, Zw, c["A"], c["Y"], LAM, ALPHA, 20, X0=x0.astype(np.complex128))
+    assert np.allclose(stw["delta"], refw["delta"], rtol=1e-3, atol=1e-6)
+
+
+def test_nonfinite_pixel_and_zero(torch):
+    c = W.complex_cube(40)
+    Y = c["Y"].copy()
+    Y[3, 5] = np.nan
+    Y[7, 0] = complex(0.0, np.inf)
+    Y[9] = 0.0
+    note("admm_complex nonfinite pixels")
+    X, Z, st = _run(torch, c["A"], Y, LAM, 30, alpha=ALPHA)
+    assert np.all(X[[3, 7, 9]] == 0.0) and np.all(Z[[3, 7, 9]] == 0.0)
+    assert st["flags"][3] == oracle.STOP_NONFINITE and st["flags"][7] == oracle.STOP_NONFINITE
+    good = np.setdiff1d(np.arange(40), [3, 7, 9])
+    assert_cadmm_parity(X[good], Z[good], c["A"], Y[good], LAM, ALPHA, 30)
+
+
+def test_zero_iterations_and_empty(torch):
+    import paper_2401_14762_amd as cs
+    c = W.complex_cube(20)
+    note("admm_complex max_iter=0")
+    X, Z, st = _run(torch, c["A"], c["Y"], LAM, 0, alpha=ALPHA)
+    assert np.all(X == 0) and np.all(Z == 0) and np.all(st["iters"] == 0)
+    assert np.allclose(st["resid"], np.linalg.norm(c["Y"], axis=1), rtol=1e-6)
+    Y = torch.empty((0, c["M"]), dtype=torch.complex64, device="cuda")
+    X0, _, _ = cs.admm_complex(to_dev(torch, c["A"]), Y, lam=LAM, max_iter=5)
+    assert X0.shape == (0, c["N"])
