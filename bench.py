@@ -223,8 +223,9 @@ def leg_admm(torch, cs, pr, A, Y, stream, idx, samples):
 
 def leg_dft(torch, cs, W, dev, stream, samples):
     """FISTA and ADMM with the complex DFT basis of Section II.  complex:
-    FISTA on complex y, a 256x256 N=100 M=40 cube (the real embedding of A,
-    16 M N flops per pixel-iteration: A x and A^* v in complex arithmetic).
+    FISTA and ADMM on complex y, a 256x256 N=100 M=40 cube (the real
+    embedding of A; FISTA 16 M N flops per pixel-iteration: A x and A^* v in
+    complex arithmetic).
     hermitian: real y = Phi f on the cubes of the data sets' shapes and on a
     256x256 N=200 M=80 cube (the half-spectrum iteration, 4 M N flops per
     pixel-iteration: two real M x N products; the complex iteration it
@@ -245,6 +246,13 @@ def leg_dft(torch, cs, W, dev, stream, samples):
     out["complex"] = {"cube": f"256x256 N={N} M={M} K={W.COMPLEX['K']}-sparse complex, 40 dB", "pixels": P,
                       "ms": ms, "pixels_per_s": P / (ms * 1e-3), "achieved_tflops": tf,
                       "mfma_fp32_frac": tf / FP32_MFMA_PEAK_TFLOPS}
+    # ADMM on the same cube: 16 M N + 8 M^2 flops per pixel-iteration (A v,
+    # R t, A^* e in complex arithmetic), (alpha I + A A^*)^{-1} included
+    _, ms_a = event_timed(torch, stream, lambda: cs.admm_complex(A, Y, lam=LAMBDA, alpha=ADMM_ALPHA,
+                                                                 max_iter=DFT_ITERS, out=X))
+    tfa = P * DFT_ITERS * (16.0 * M * N + 8.0 * M * M) / (ms_a * 1e-3) / 1e12
+    out["complex"]["admm"] = {"ms": ms_a, "pixels_per_s": P / (ms_a * 1e-3), "achieved_tflops": tfa,
+                              "mfma_fp32_frac": tfa / FP32_MFMA_PEAK_TFLOPS}
     del A, Y, X
     cubes = [(name, W.paper_shape_dft(name), 100.0) for name in W.PAPER_SHAPES]
     cubes.append(("mixing-256x256", W.dft_mixing_cube(65536, 200, 80, "gaussian"), LAMBDA))
