@@ -238,7 +238,7 @@ int32_t csrec_admm(const csrec_problem* problem, const csrec_admm_params* params
  * CSREC_PREC_F32 and correction_iters 0.  Needs a workspace of
  * csrec_workspace_bytes(CSREC_SOLVER_FISTA_COMPLEX, ...) bytes (the real
  * 2M x 2N' embedding [Re A, -Im A; Im A, Re A] of A, N' >= N a multiple of
- * 16 chosen by the library, written on every call).  M <= 40 and N <= 112,
+ * 16 chosen by the library, written on every call).  M <= 48 and N <= 128,
  * otherwise CSREC_E_UNSUPPORTED.  X may alias X0. */
 int32_t csrec_fista_complex(const csrec_problem* problem, const csrec_fista_params* params, float* X,
                             csrec_pixel_stats* stats);

@@ -263,8 +263,8 @@ def paper_shape_cube(name: str, P: Optional[int] = None, sampling: str = "subsam
 
 # Complex measurements with the DFT basis of Section II: K-sparse complex
 # coefficients (circular complex Gaussian values), y = A x (+ circular
-# complex white noise at snr_db).  Shapes within the complex FISTA kernel's
-# limits (N <= 112, M <= 40).
+# complex white noise at snr_db).  Shapes within the complex-y kernels'
+# limits (N <= 128, M <= 48).
 COMPLEX = dict(config_id=8, side=64, N=100, M=40, K=8, snr_db=40.0)
 
 

@@ -244,7 +244,7 @@ def test_one_hip_runtime_in_process():
 
 
 def test_fista_complex_validation(lib):
-    """Complex FISTA: FP32 only, no correction pass, M <= 40 and N <= 112,
+    """Complex FISTA: FP32 only, no correction pass, M <= 48 and N <= 128,
     a workspace for the real embedding of A (2M x 2N' floats, N' the
     multiple of 16 the kernel tile uses) plus the device L slot."""
     S = L.SOLVER_FISTA_COMPLEX
@@ -256,8 +256,9 @@ def test_fista_complex_validation(lib):
     assert _ws(lib, S, pb, _fista(correction_iters=5))[0] == L.E_UNSUPPORTED
     assert _ws(lib, S, pb, _fista(prec=7))[0] == L.E_INVAL
     assert _ws(lib, S, pb, _fista(lambda_=-1.0))[0] == L.E_INVAL
-    assert _ws(lib, S, _problem(M=41, N=112), _fista())[0] == L.E_UNSUPPORTED
-    assert _ws(lib, S, _problem(M=40, N=113), _fista())[0] == L.E_UNSUPPORTED
+    assert _ws(lib, S, _problem(M=48, N=128), _fista())[0] == L.OK
+    assert _ws(lib, S, _problem(M=49, N=128), _fista())[0] == L.E_UNSUPPORTED
+    assert _ws(lib, S, _problem(M=40, N=129), _fista())[0] == L.E_UNSUPPORTED
     assert _ws(lib, S, _problem(M=5, N=17), _fista())[0] == L.OK
     assert _ws(lib, S, _problem(M=20, N=10), _fista())[0] == L.E_SHAPE
     assert _ws(lib, S, _problem(P=0), _fista()) == (L.OK, 0)

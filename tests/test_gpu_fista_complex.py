@@ -2,7 +2,8 @@
 Section II) against the FP64 complex oracle.
 
 The kernel runs the real iteration on the embedding [Re A, -Im A; Im A, Re A]
-with the soft threshold applied to each pair (Re x_n, Im x_n).  Tolerance
+with the soft threshold applied to each pair (Re x_n, Im x_n) (the pair
+kernel of the half-spectrum entry point in its complex-y mode).  Tolerance
 (assert_cfista_parity): per-pixel relative error of x^I (complex 2-norm) at
 most max(1e-5, 30x) that of the oracle's complex64 rounding model, cube-wide
 max and median at most twice the model's.  Stats: the iteration count
@@ -53,10 +54,11 @@ def test_tiny_all_pixels(torch):
 
 @pytest.mark.parametrize("N,M,sampling", [(17, 5, "gaussian"), (30, 12, "subsample"), (32, 16, "gaussian"),
                                           (60, 24, "gaussian"), (64, 24, "subsample"), (80, 32, "gaussian"),
-                                          (100, 40, "subsample"), (112, 40, "gaussian")])
+                                          (100, 40, "subsample"), (112, 40, "gaussian"), (112, 45, "subsample"),
+                                          (128, 48, "gaussian")])
 def test_shapes(torch, N, M, sampling):
-    """Every kernel tile (2M up to 32, 48, 64, 80 rows; N up to 32, 64, 80,
-    112) with ragged M and N and both samplings of Section IV."""
+    """Every kernel tile (2M up to 32, 48, 64, 80, 96 rows; N up to 32, 64,
+    80, 112, 128) with ragged M and N and both samplings of Section IV."""
     c = W.complex_cube(130, N=N, M=M, K=max(2, M // 5), sampling=sampling, config_id=100 + N)
     L = oracle.lipschitz_complex(c["A"])
     note(f"fista_complex N={N} M={M} {sampling} 80 it")
