@@ -23,6 +23,7 @@
  * and the pre-stage of the paper's evaluation protocol:
  *
  *   csrec_sparsify  sparsification of Section II and the compression y = A x_s
+ *   csrec_sparsify_dft  the same with the complex DFT basis (real spectra)
  *
  * Layout.  A is M x N row-major FP32.  Y is P x M row-major FP32 (pixel
  * major: the measurements of one pixel are contiguous).  X is P x N
@@ -310,6 +311,24 @@ int32_t csrec_admm_complex(const csrec_problem* problem, const csrec_admm_params
  * csrec_problem, M <= 96.  No workspace. */
 int32_t csrec_sparsify(const float* Psi, const float* A, const float* F, int32_t M, int32_t N, int64_t P,
                        double T, int32_t std_ddof, float* Xs, float* Y, int32_t* kept, void* stream);
+
+/* Sparsification (Section II) with the complex DFT basis, fused with the
+ * compression: for each real spectrum f (rows of F, P x N), x = Psi^* f,
+ * where Psi (N x N complex) must be unitary with conjugate-symmetric
+ * columns, Psi[:, N-k] = conj(Psi[:, k]) (the DFT), so that x is
+ * conjugate-symmetric; mu and sigma are the mean and the standard deviation
+ * of the N magnitudes |x_k| (denominator N - std_ddof); every x_k with
+ * |x_k| - mu < T sigma is set to 0 (x_k and x_{N-k} share the decision).
+ * Writes Xs (P x N complex) = the sparsified x, Y (P x M REAL) = A Xs for A
+ * (M x N complex) with conjugate-symmetric columns (A = Phi Psi, Phi real;
+ * Y is real), and kept (P int32, nullable) = the entries kept (of N).
+ * Only columns 0 .. floor(N/2) of Psi and A are read.  Complex values are
+ * interleaved (re, im) FP32 pairs; every pointer is a device pointer; the
+ * decisions are taken in FP32.  A spectrum with a non-finite value gives
+ * x_s = 0, y = 0, kept = 0.  Shapes as csrec_problem, M <= 96.  No
+ * workspace. */
+int32_t csrec_sparsify_dft(const float* Psi, const float* A, const float* F, int32_t M, int32_t N, int64_t P,
+                           double T, int32_t std_ddof, float* Xs, float* Y, int32_t* kept, void* stream);
 
 /* Lipschitz constant L = lambda_max(A^T A) of Eq. 2 by power iteration on the device:
  * writes one float to *L_out (device pointer) on `stream`. */

@@ -26,7 +26,7 @@ from . import _lib
 from ._lib import (CsrecError, FLAG_CONVERGED, FLAG_FP64_FALLBACK, FLAG_ITER_CAP,
                    FLAG_NONFINITE, MAX_N)
 
-__all__ = ["sparsify", "fista", "fista_complex", "fista_hermitian", "admm", "admm_hermitian", "admm_complex", "gomp", "cosamp", "biht", "lipschitz", "Server", "CsrecError", "FLAG_CONVERGED",
+__all__ = ["sparsify", "sparsify_dft", "fista", "fista_complex", "fista_hermitian", "admm", "admm_hermitian", "admm_complex", "gomp", "cosamp", "biht", "lipschitz", "Server", "CsrecError", "FLAG_CONVERGED",
            "FLAG_ITER_CAP", "FLAG_FP64_FALLBACK", "FLAG_NONFINITE", "MAX_N", "workspace_bytes",
            "library"]
 
@@ -360,6 +360,32 @@ def sparsify(Psi, A, F, T: float = 0.1, ddof: int = 1, stream=None):
     sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
     _lib.check(lib.csrec_sparsify(_ptr(Psi), _ptr(A), _ptr(F), M, N, P, float(T), int(ddof), _ptr(Xs), _ptr(Y),
                                   _ptr(kept), ctypes.c_void_p(sp)), "csrec_sparsify")
+    return Xs, Y, kept[:P]
+
+
+def sparsify_dft(Psi, A, F, T: float = 0.1, ddof: int = 1, stream=None):
+    """Section II sparsification with the complex DFT basis Psi (N x N
+    complex64, conjugate-symmetric columns) of the real spectra F (P x N
+    float32), fused with the compression by A (M x N complex64, A = Phi Psi
+    with Phi real): returns (Xs (P x N complex64), Y = Re(Xs A^T) (P x M
+    float32), kept (P int32))."""
+    torch = _torch()
+    lib = library()
+    _check_dev("A", A, torch.complex64)
+    M, N = A.shape
+    _check_dev("Psi", Psi, torch.complex64, (N, N))
+    _check_dev("F", F, torch.float32)
+    if F.shape[1] != N:
+        raise ValueError("F must be P x N")
+    P = F.shape[0]
+    Xs = torch.empty((P, N), dtype=torch.complex64, device=A.device)
+    Y = torch.empty((P, M), dtype=torch.float32, device=A.device)
+    kept = torch.empty((max(P, 1),), dtype=torch.int32, device=A.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(A.device)
+    sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    _lib.check(lib.csrec_sparsify_dft(_ptr(Psi), _ptr(A), _ptr(F), M, N, P, float(T), int(ddof), _ptr(Xs), _ptr(Y),
+                                      _ptr(kept), ctypes.c_void_p(sp)), "csrec_sparsify_dft")
     return Xs, Y, kept[:P]
 
 

@@ -488,6 +488,18 @@ int32_t csrec_sparsify(const float* Psi, const float* A, const float* F, int32_t
     return sparsify_launch(Psi, A, F, M, N, P, (float)T, std_ddof, Xs, Y, kept, reinterpret_cast<hipStream_t>(stream));
 }
 
+int32_t csrec_sparsify_dft(const float* Psi, const float* A, const float* F, int32_t M, int32_t N, int64_t P,
+                           double T, int32_t std_ddof, float* Xs, float* Y, int32_t* kept, void* stream) {
+    if (M < 1 || M >= N || N > CSREC_MAX_N || P < 0) return CSREC_E_SHAPE;
+    if (std_ddof != 0 && std_ddof != 1) return CSREC_E_INVAL;
+    if (!std::isfinite((float)T)) return CSREC_E_INVAL;
+    if (P > 0 && (!Psi || !A || !F || !Xs || !Y)) return CSREC_E_INVAL;
+    int e = sparsify_dft_supported(M, N);
+    if (e) return e;
+    return sparsify_dft_launch(Psi, A, F, M, N, P, (float)T, std_ddof, Xs, Y, kept,
+                               reinterpret_cast<hipStream_t>(stream));
+}
+
 int32_t csrec_lipschitz(const float* A, int32_t M, int32_t N, float* L_out, void* stream) {
     if (!A || !L_out) return CSREC_E_INVAL;
     if (M < 1 || M >= N || N > CSREC_MAX_N) return CSREC_E_SHAPE;

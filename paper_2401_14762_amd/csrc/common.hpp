@@ -27,6 +27,22 @@ void set_hip_error(hipError_t e);
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
 
+// Entry (row, col) of the real M x 2S half-spectrum matrix of a complex
+// M x N matrix A with conjugate-symmetric columns (S = 16 NTH, Ha = ceil(N/2)):
+// columns [0, S) hold Re A[:, k] (k < Ha), column S holds Re A[:, N/2] (N
+// even), columns S + s hold -Im A[:, s] (1 <= s < Ha); zero elsewhere.  With
+// u the half-spectrum slots of a conjugate-symmetric x (a_s = Re x_s,
+// b_s = Im x_s, x_{N/2} in b-slot 0), A x = C (w u) for w = 1 on x_0 and
+// x_{N/2}, 2 on the pairs (k, N-k), and (Re, Im) of A^* v are C^T v for real v.
+__device__ __forceinline__ float half_spectrum_entry(const float* __restrict__ A, int M, int N, int Ha, int S,
+                                                    int row, int col) {
+    if (row >= M) return 0.f;
+    if (col < S) return col < Ha ? A[((size_t)row * N + col) * 2] : 0.f;
+    const int s = col - S;
+    if (s == 0) return (N & 1) ? 0.f : A[((size_t)row * N + N / 2) * 2];
+    return s < Ha ? -A[((size_t)row * N + s) * 2 + 1] : 0.f;
+}
+
 // ---------------------------------------------------------------- launchers
 // Each returns CSREC_OK or an error code; arguments are already validated.
 
@@ -102,6 +118,11 @@ size_t admm_complex_workspace(int M, int N);
 int admm_complex_launch(const AdmmLaunch& a);
 
 int sparsify_supported(int M, int N);
+// Sparsification with a conjugate-symmetric complex basis (the DFT) of real
+// spectra: Psi (N x N), A (M x N) complex; Xs (P x N) complex, Y real.
+int sparsify_dft_supported(int M, int N);
+int sparsify_dft_launch(const float* Psi, const float* A, const float* F, int M, int N, int64_t P, float T, int ddof,
+                        float* Xs, float* Y, int32_t* kept, hipStream_t stream);
 int sparsify_launch(const float* Psi, const float* A, const float* F, int M, int N, int64_t P, float T, int ddof,
                     float* Xs, float* Y, int32_t* kept, hipStream_t stream);
 

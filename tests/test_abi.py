@@ -331,3 +331,21 @@ def test_admm_complex_validation(lib):
     assert lib.csrec_admm_complex(ctypes.byref(pb), ctypes.byref(_admm()), None, None, None) == L.E_INVAL
     assert lib.csrec_admm_complex(ctypes.byref(pb), ctypes.byref(_admm()), v, None, None) == L.E_WORKSPACE
     assert lib.csrec_admm_complex(ctypes.byref(_problem(P=0)), ctypes.byref(_admm()), None, None, None) == L.OK
+
+
+def test_sparsify_dft_validation(lib):
+    """DFT sparsification: shapes, ddof, T and pointers checked before any launch."""
+    v = ctypes.c_void_p(0x3000)
+    ok = dict(Psi=v, A=v, F=v, M=90, N=224, P=10, T=0.1, ddof=1, Xs=v, Y=v)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.csrec_sparsify_dft(a["Psi"], a["A"], a["F"], a["M"], a["N"], a["P"], a["T"], a["ddof"], a["Xs"],
+                                      a["Y"], None, None)
+    for bad in (dict(M=0), dict(M=224), dict(N=257), dict(P=-1)):
+        assert call(**bad) == L.E_SHAPE, bad
+    for bad in (dict(ddof=2), dict(T=float("inf")), dict(Psi=None), dict(A=None), dict(F=None), dict(Xs=None),
+                dict(Y=None)):
+        assert call(**bad) == L.E_INVAL, bad
+    assert call(M=97, N=240) == L.E_UNSUPPORTED
+    assert call(P=0, Psi=None, F=None, Xs=None, Y=None) == L.OK
