@@ -271,6 +271,11 @@ def leg_dft(torch, cs, W, dev, stream, samples):
                                   "pixels_per_s": P / (ms * 1e-3), "achieved_tflops": tf,
                                   "mfma_fp32_frac": tf / FP32_MFMA_PEAK_TFLOPS,
                                   "complex_equivalent_tflops": 4.0 * tf}
+        if name == "salinas-like":
+            # the FISTA result, sampled before the ADMM run below reuses X
+            sidx = W.pixel_subset(P, 128, 77)
+            samples["dft"][name] = dict(A=c["A"], Y=c["Y"][sidx], Psi=c["Psi"], L=L, lam=lam,
+                                        gpu=X[torch.from_numpy(sidx).to(dev)].cpu().numpy())
         if name in ("salinas-like", "mixing-256x256"):
             # ADMM (Alg. 2) on the same cube: 4 M N + 2 M^2 flops per
             # pixel-iteration (Ch v, R t, Ch^T e), (alpha I + A A^*)^{-1} included
@@ -279,10 +284,6 @@ def leg_dft(torch, cs, W, dev, stream, samples):
             tfa = P * DFT_ITERS * (4.0 * M * N + 2.0 * M * M) / (ms_a * 1e-3) / 1e12
             out["hermitian"][name]["admm"] = {"ms": ms_a, "pixels_per_s": P / (ms_a * 1e-3),
                                               "achieved_tflops": tfa, "mfma_fp32_frac": tfa / FP32_MFMA_PEAK_TFLOPS}
-        if name == "salinas-like":
-            sidx = W.pixel_subset(P, 128, 77)
-            samples["dft"][name] = dict(A=c["A"], Y=c["Y"][sidx], Psi=c["Psi"], L=L, lam=lam,
-                                        gpu=X[torch.from_numpy(sidx).to(dev)].cpu().numpy())
         del A, Y, X
         torch.cuda.empty_cache()
     return out
