@@ -245,6 +245,9 @@ def leg_dft(torch, cs, W, dev, stream, samples):
     X = torch.empty((P, N), dtype=torch.complex64, device=dev)
     _, ms = event_timed(torch, stream, lambda: cs.fista_complex(A, Y, lam=LAMBDA, L=L, max_iter=DFT_ITERS, out=X))
     tf = P * DFT_ITERS * 16.0 * M * N / (ms * 1e-3) / 1e12
+    csidx = W.pixel_subset(P, 128, 78)
+    tcs = torch.from_numpy(csidx).to(dev)
+    samples["dft"]["complex"] = dict(A=c["A"], Y=c["Y"][csidx], L=L, lam=LAMBDA, gpu=X[tcs].cpu().numpy())
     out["complex"] = {"cube": f"256x256 N={N} M={M} K={W.COMPLEX['K']}-sparse complex, 40 dB", "pixels": P,
                       "ms": ms, "pixels_per_s": P / (ms * 1e-3), "achieved_tflops": tf,
                       "mfma_fp32_frac": tf / FP32_MFMA_PEAK_TFLOPS}
@@ -253,6 +256,7 @@ def leg_dft(torch, cs, W, dev, stream, samples):
     _, ms_a = event_timed(torch, stream, lambda: cs.admm_complex(A, Y, lam=LAMBDA, alpha=ADMM_ALPHA,
                                                                  max_iter=DFT_ITERS, out=X))
     tfa = P * DFT_ITERS * (16.0 * M * N + 8.0 * M * M) / (ms_a * 1e-3) / 1e12
+    samples["dft"]["complex"]["gpu_admm"] = X[tcs].cpu().numpy()
     out["complex"]["admm"] = {"ms": ms_a, "pixels_per_s": P / (ms_a * 1e-3), "achieved_tflops": tfa,
                               "mfma_fp32_frac": tfa / FP32_MFMA_PEAK_TFLOPS}
     del A, Y, X
@@ -282,6 +286,8 @@ def leg_dft(torch, cs, W, dev, stream, samples):
             _, ms_a = event_timed(torch, stream, lambda: cs.admm_hermitian(A, Y, lam=lam, alpha=ADMM_ALPHA,
                                                                            max_iter=DFT_ITERS, out=X))
             tfa = P * DFT_ITERS * (4.0 * M * N + 2.0 * M * M) / (ms_a * 1e-3) / 1e12
+            if name == "salinas-like":
+                samples["dft"][name]["gpu_admm"] = X[torch.from_numpy(sidx).to(dev)].cpu().numpy()
             out["hermitian"][name]["admm"] = {"ms": ms_a, "pixels_per_s": P / (ms_a * 1e-3),
                                               "achieved_tflops": tfa, "mfma_fp32_frac": tfa / FP32_MFMA_PEAK_TFLOPS}
         del A, Y, X
@@ -498,9 +504,19 @@ def cpu_baseline_leg(W, pr, L, idx_psnr, Xf_s, Xg_s, n_sample, samples):
         ref = oracle.admm(pr.A, pr.Y[idx_psnr], LAMBDA, ADMM_ALPHA, ADMM_ITERS)
         q["plain_admm"] = psnr(samples["admm"]["gpu"] @ Psi.T, ref["X"] @ Psi.T)
     for name, s in samples.get("dft", {}).items():
-        ref = oracle.fista_complex(s["A"], s["Y"].astype(np.complex64), s["lam"], s["L"], DFT_ITERS)
-        # the spectra Psi x are real: compare their real parts
-        q[f"dft_hermitian_{name}"] = psnr((s["gpu"] @ s["Psi"].T).real, (ref["X"] @ s["Psi"].T).real)
+        Yc = s["Y"].astype(np.complex64)
+        ref = oracle.fista_complex(s["A"], Yc, s["lam"], s["L"], DFT_ITERS)
+        refa = oracle.admm_complex(s["A"], Yc, s["lam"], ADMM_ALPHA, DFT_ITERS)
+        if name == "complex":
+            # complex coefficients against the oracle's (PSNR over re and im)
+            for tag, g, r in (("fista", s["gpu"], ref["X"]), ("admm", s["gpu_admm"], refa["X"])):
+                q[f"dft_complex_{tag}"] = psnr(np.concatenate([g.real, g.imag], 1),
+                                               np.concatenate([r.real, r.imag], 1))
+        else:
+            # the spectra Psi x are real: compare their real parts
+            q[f"dft_hermitian_{name}"] = psnr((s["gpu"] @ s["Psi"].T).real, (ref["X"] @ s["Psi"].T).real)
+            q[f"dft_hermitian_admm_{name}"] = psnr((s["gpu_admm"] @ s["Psi"].T).real,
+                                                   (refa["X"] @ s["Psi"].T).real)
     for name, s in samples.get("protocol", {}).items():
         # the oracle's own sparsification and gOMP on the same 256 pixels:
         # the GPU's result against the oracle's, and each against the
