@@ -67,6 +67,202 @@ __device__ __forceinline__ float quad_sum(float v) {
     return v;
 }
 
+template <int MT, int NT, int WAVES, int MINW>
+__global__ __launch_bounds__(WAVES * 64, MINW) void fista_f32_kernel(FistaArgs a) {
+    constexpr int PA = 16 * NT + 2;   // LDS row pitch of A (floats)
+    constexpr int ROWS = 16 * MT;
+    __shared__ float sA[ROWS * PA];
+
+    const int M = a.M, N = a.N;
+    for (int idx = threadIdx.x; idx < ROWS * PA; idx += WAVES * 64) {
+        const int row = idx / PA;
+        const int col = idx - row * PA;
+        float v = 0.f;
+        if (row < M && col < N) v = a.A[(size_t)row * N + col];
+        sA[idx] = v;
+    }
+
+    float invL = a.invL, thr = a.thr;
+    if (a.L_dev) {
+        const float L = *a.L_dev;
+        invL = 1.f / L;
+        thr = (float)(a.lambda / (double)L);
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 4;
+    const int j = lane & 15;
+    const int64_t pix = ((int64_t)blockIdx.x * WAVES + wave) * 16 + j;
+    const bool valid = pix < a.P;
+
+    const int mu_j = 8 * ((j >> 2) & 1) + 4 * (j >> 3) + (j & 3);  // m of output row j (GEMM 1)
+    const int nu_j = 4 * (j & 3) + (j >> 2);                       // n of output row j (GEMM 2)
+    const int cm_h = 8 * (h & 1) + 4 * (h >> 1);
+    const float* a1 = sA + mu_j * PA + h;      // + 16 mt PA + 16 nt + 4 kk
+    const float* a2 = sA + cm_h * PA + nu_j;   // + (16 mt + kk) PA + 16 nt
+
+    // ---- measurements, non-finite check
+    v4f Yr[MT];
+    int bad = 0;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * mt + cm_h + r;
+            float v = 0.f;
+            if (valid && m < M) {
+                v = a.Y[pix * M + m];
+                if (!isfinite(v)) bad = 1;
+            }
+            Yr[mt][r] = v;
+        }
+    bad |= __shfl_xor(bad, 16);
+    bad |= __shfl_xor(bad, 32);
+    if (bad) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) Yr[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+
+    // ---- starting point x^0 (z^0 = x^0)
+    v4f Xr[NT], Zr[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * nt + 4 * r + h;
+            float v = 0.f;
+            if (a.X0 && valid && !bad && n < N) v = a.X0[pix * N + n];
+            Xr[nt][r] = v;
+            Zr[nt][r] = v;
+        }
+
+    // U_0 = A x^0 - y; U_{-1} = U_0 (so z^0 = x^0 whatever b_0 is)
+    v4f U1[MT], V[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) U1[mt] = -Yr[mt];
+    if (a.X0) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    U1[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                        a1[16 * mt * PA + 16 * nt + 4 * kk], Xr[nt][kk], U1[mt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) V[mt] = U1[mt];
+
+    bool active = valid && !bad;
+    bool converged = false;
+    int iters = 0;
+    float last_d2 = __builtin_nanf("");
+    double t = 1.0;
+    float bprev = 0.f;
+    const bool check_eps = a.eps > 0.f;
+
+    for (int it = 0; it < a.max_iter; ++it) {
+        const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));   // step 3
+        const float bcur = (float)((t - 1.0) / tn);                  // step 4 coefficient
+        t = tn;
+
+        // V = A z^{i-1} - y
+        const float cp = 1.f + bprev;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) V[mt] = cp * U1[mt] - bprev * V[mt];
+
+        v4f Un[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) Un[mt] = -Yr[mt];
+
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            // W = (A^T V) for 16 n-values of this tile          (step 1)
+            v4f W = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    W = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[(16 * mt + kk) * PA + 16 * nt],
+                                                             V[mt][kk], W, 0, 0, 0);
+            // steps 1, 2, 4 elementwise
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float aux = Zr[nt][r] - W[r] * invL;
+                const float xn = soft_thr(aux, thr);
+                const float zn = xn + bcur * (xn - Xr[nt][r]);
+                Xr[nt][r] = active ? xn : Xr[nt][r];
+                Zr[nt][r] = active ? zn : Zr[nt][r];
+            }
+            // U_i += A(:, tile) x^i(tile)                        (step 5)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    Un[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                        a1[16 * mt * PA + 16 * nt + 4 * kk], Xr[nt][kk], Un[mt], 0, 0, 0);
+        }
+
+        // Delta^2 = ||r^i - r^{i-1}||^2 with r^0 = y: the reference is U_{i-1},
+        // except in the first iteration from a given x^0, where it is -y.
+        const float c0 = (it == 0 && a.X0) ? 1.f : 0.f;
+        float d2 = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float ref = U1[mt][r] - c0 * (U1[mt][r] + Yr[mt][r]);
+                const float d = Un[mt][r] - ref;
+                d2 += d * d;
+            }
+        d2 = quad_sum(d2);
+        if (active) {
+            iters = it + 1;
+            last_d2 = d2;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            V[mt] = U1[mt];
+            U1[mt] = active ? Un[mt] : U1[mt];
+        }
+        bprev = bcur;
+        if (check_eps) {
+            if (active && sqrtf(d2) < a.eps) {
+                active = false;
+                converged = true;
+            }
+            if (!__any(active)) break;
+        }
+    }
+
+    float r2 = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) r2 += U1[mt][r] * U1[mt][r];
+    r2 = quad_sum(r2);
+
+    if (valid) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * nt + 4 * r + h;
+                if (n < N) a.X[pix * N + n] = bad ? 0.f : Xr[nt][r];
+            }
+        if (a.stats && h == 0) {
+            csrec_pixel_stats s;
+            s.iters = bad ? 0 : iters + a.iter_offset;
+            s.flags = bad ? CSREC_FLAG_NONFINITE : (converged ? CSREC_FLAG_CONVERGED : CSREC_FLAG_ITER_CAP);
+            s.resid = bad ? 0.f : sqrtf(r2);
+            s.delta = bad ? __builtin_nanf("") : sqrtf(last_d2);
+            a.stats[pix] = s;
+        }
+    }
+}
+
 // Operand reads of the two products, in the MFMA operand order:
 //   fwd(mt, nt)[kk] = A[16 mt + mu_j][16 nt + 4 kk + h]     (A x, B operand x)
 //   bwd(nt, mt)[kk] = A[16 mt + cm_h + kk][16 nt + nu_j]   (A^T v, B operand v)
@@ -358,11 +554,14 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void fista_f32s_kernel(FistaArgs 
         fista_f32s_body<MT, NT, WAVES, false, OpsPre<MT, NT>>(a, sA1, sA2);
 }
 
-// The same iteration with A once in LDS (row pitch 16 NT + 2), for the
-// shapes whose two pre-arranged copies exceed the LDS (MT NT > 80:
-// N = 224, M = 90 among them): 4 (16 MT (16 NT + 2)) bytes, 127 KiB at (7, 16).
+// The interleaved iteration with A once in LDS (row pitch 16 NT + 2), for
+// the shapes whose two pre-arranged copies exceed the LDS (MT NT > 80:
+// N = 224, M = 90 among them): 4 (16 MT (16 NT + 2)) bytes, 127 KiB at
+// (7, 16).  It runs the solves without the Delta stop; with it, the
+// per-element freeze selects of the interleaved loop make it slower than
+// fista_f32_kernel, which serves those.
 template <int MT, int NT, int WAVES, int MINW>
-__global__ __launch_bounds__(WAVES * 64, MINW) void fista_f32_kernel(FistaArgs a) {
+__global__ __launch_bounds__(WAVES * 64, MINW) void fista_f32i_kernel(FistaArgs a) {
     constexpr int PA = OpsSingle<NT>::PA;
     constexpr int ROWS = 16 * MT;
     __shared__ float sA[ROWS * PA];
@@ -622,6 +821,7 @@ typedef void (*fista_kernel_t)(FistaArgs);
 struct FistaVariant {
     int MT, NT, waves;
     fista_kernel_t fn;
+    fista_kernel_t fn_nostop = nullptr;   // for eps = 0, where faster
 };
 
 // Tile shapes instantiated: the 2.5x-compressed band counts of the paper's
@@ -629,15 +829,15 @@ struct FistaVariant {
 // general shapes.  A shape runs on the smallest variant covering it; the
 // extra rows/columns of A are zero in LDS.
 const FistaVariant kVariants[] = {
-    {1, 2, 4, fista_f32_kernel<1, 2, 4, 2>},
-    {2, 4, 4, fista_f32_kernel<2, 4, 4, 2>},
-    {3, 7, 4, fista_f32_kernel<3, 7, 4, 2>},
-    {4, 8, 4, fista_f32_kernel<4, 8, 4, 2>},
-    {4, 10, 4, fista_f32_kernel<4, 10, 4, 1>},
-    {5, 13, 4, fista_f32_kernel<5, 13, 4, 1>},
-    {6, 14, 4, fista_f32_kernel<6, 14, 4, 1>},
-    {7, 16, 4, fista_f32_kernel<7, 16, 4, 1>},
-    {8, 16, 4, fista_f32_kernel<8, 16, 4, 1>},
+    {1, 2, 4, fista_f32_kernel<1, 2, 4, 2>, fista_f32i_kernel<1, 2, 4, 2>},
+    {2, 4, 4, fista_f32_kernel<2, 4, 4, 2>, fista_f32i_kernel<2, 4, 4, 2>},
+    {3, 7, 4, fista_f32_kernel<3, 7, 4, 2>, fista_f32i_kernel<3, 7, 4, 2>},
+    {4, 8, 4, fista_f32_kernel<4, 8, 4, 2>, fista_f32i_kernel<4, 8, 4, 2>},
+    {4, 10, 4, fista_f32_kernel<4, 10, 4, 1>, fista_f32i_kernel<4, 10, 4, 1>},
+    {5, 13, 4, fista_f32_kernel<5, 13, 4, 1>, fista_f32i_kernel<5, 13, 4, 1>},
+    {6, 14, 4, fista_f32_kernel<6, 14, 4, 1>, fista_f32i_kernel<6, 14, 4, 1>},
+    {7, 16, 4, fista_f32_kernel<7, 16, 4, 1>, fista_f32i_kernel<7, 16, 4, 1>},
+    {8, 16, 4, fista_f32_kernel<8, 16, 4, 1>, fista_f32i_kernel<8, 16, 4, 1>},
 };
 
 // The pre-arranged form (two LDS copies of A), for the shapes it fits.
@@ -705,7 +905,8 @@ int launch_variant(const FistaVariant* v, const FistaArgs& a, hipStream_t stream
     const int64_t pix_per_block = 16 * v->waves;
     const int64_t blocks = ceil_div(a.P, pix_per_block);
     if (blocks > 0x7fffffff) return CSREC_E_SHAPE;
-    hipLaunchKernelGGL(v->fn, dim3((unsigned)blocks), dim3(64 * v->waves), 0, stream, a);
+    const fista_kernel_t fn = (a.eps > 0.f || !v->fn_nostop) ? v->fn : v->fn_nostop;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * v->waves), 0, stream, a);
     CSREC_HIP_TRY(hipGetLastError());
     return CSREC_OK;
 }
