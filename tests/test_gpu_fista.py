@@ -86,6 +86,31 @@ def test_band_counts(torch, N):
     assert_fista_parity(X, a32, Y, 1e-2, L, 60)
 
 
+@pytest.mark.parametrize("N", [224, 256])
+def test_single_copy_shapes_with_and_without_stop(torch, N):
+    """The shapes whose two pre-arranged copies of A exceed the LDS run the
+    interleaved single-copy kernel without the Delta stop and the
+    non-interleaved one with it: both to the parity bar, and with a stop
+    whose threshold no pixel reaches both give the same x."""
+    M = W.m_for(N) if N < 256 else 96
+    a64, a32, _, phi = W.dictionary(N, M, 9)
+    F = W.mixing_spectra(200, N, 40.0, 6)
+    Y = (F @ phi.T).astype(np.float32)
+    L = oracle.lipschitz(a32)
+    note(f"fista single-copy N={N} M={M} eps=0 and eps>0")
+    X0, _ = _run(torch, a32, Y, 1e-2, L, 80)
+    assert_fista_parity(X0, a32, Y, 1e-2, L, 80)
+    eps = 1e-4
+    Xe, ste = _run(torch, a32, Y, 1e-2, L, 300, eps=eps)
+    ref = oracle.fista(a32, Y, 1e-2, L, 300, eps=eps)
+    same = ste["iters"] == ref["iters"]
+    assert np.mean(same) > 0.97
+    assert_fista_parity(Xe[same], a32, Y[same], 1e-2, L, 300, eps=eps)
+    Xt, stt = _run(torch, a32, Y, 1e-2, L, 80, eps=1e-30)
+    assert np.all(stt["iters"] == 80)
+    assert np.allclose(Xt, X0, rtol=0, atol=1e-6 * np.abs(X0).max())
+
+
 def test_eps_stop_and_x0(torch):
     """Per-pixel Delta < eps stop and a caller-supplied starting point."""
     pr = W.plain_cube(257)
