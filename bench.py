@@ -572,7 +572,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solve is pixel-parallel with no cross-GPU exchange, "
-              "and runs on more than one GPU are not part of this build (run with --gpus 1)",
+              "and multi-GPU runs are not implemented (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
     import torch
