@@ -38,3 +38,50 @@ def test_paper_shape_cubes():
     assert W.PAPER_SHAPES["salinas-like"]["rows"] * W.PAPER_SHAPES["salinas-like"]["cols"] == 111104
     with pytest.raises(ValueError):
         W.paper_shape_cube("jasper-like", P=4, sampling="other")
+
+
+@pytest.mark.parametrize("N", [17, 64, 101, 224])
+def test_dft_basis_inputs(N):
+    """The DFT synthesis matrix is unitary; A = Phi Psi with a real Phi has
+    conjugate-symmetric columns (column 0, and N/2 for even N, real), so the
+    measurements Phi f of a real spectrum are real and equal A x for the
+    conjugate-symmetric x = Psi^* f -- the structure the half-spectrum
+    solvers rely on."""
+    psi = W.dft_synthesis(N)
+    assert np.allclose(psi @ np.conj(psi).T, np.eye(N), atol=1e-12)
+    M = max(2, W.m_for(N))
+    for sampling in ("gaussian", "subsample"):
+        c = W.dft_mixing_cube(8, N, M, sampling, config_id=N)
+        A = c["A64"]
+        k = np.arange(1, N)
+        assert np.allclose(A[:, N - k], np.conj(A[:, k]), atol=1e-12)
+        assert np.max(np.abs(A[:, 0].imag)) <= 1e-12
+        if N % 2 == 0:
+            assert np.max(np.abs(A[:, N // 2].imag)) <= 1e-12
+        x = c["F"] @ np.conj(psi)                          # x = Psi^* f per pixel
+        assert np.allclose(x[:, N - k], np.conj(x[:, k]), atol=1e-10)
+        assert c["Y"].dtype == np.float32
+        assert np.allclose(x @ A.T, c["F"] @ c["Phi"].T, atol=1e-9)
+        assert np.allclose(c["Y"], c["F"] @ c["Phi"].T, rtol=1e-5, atol=1e-6)
+
+
+def test_complex_cube():
+    """K-sparse complex coefficients, y = A x (+ noise at the stated SNR),
+    complex64 inputs, reproducible from the seed."""
+    c = W.complex_cube(50, snr_db=None)
+    assert c["A"].dtype == np.complex64 and c["Y"].dtype == np.complex64
+    assert np.all(np.count_nonzero(c["X_true"], axis=1) == W.COMPLEX["K"])
+    assert np.allclose(c["Y"], c["X_true"] @ c["A64"].T, atol=1e-5)
+    n = W.complex_cube(2000)
+    noise = n["Y"].astype(np.complex128) - n["X_true"] @ n["A64"].T
+    snr = 10 * np.log10(np.sum(np.abs(n["X_true"] @ n["A64"].T) ** 2) / np.sum(np.abs(noise) ** 2))
+    assert abs(snr - W.COMPLEX["snr_db"]) < 0.5
+    assert np.array_equal(W.complex_cube(20)["Y"], W.complex_cube(20)["Y"])
+
+
+def test_paper_shape_dft():
+    d = W.paper_shape_dft("china-like", P=100)
+    c = W.paper_shape_cube("china-like", P=100)
+    assert np.array_equal(d["F"], c["F"]) and np.array_equal(d["Phi"], c["Phi"])
+    assert d["A"].shape == (c["M"], c["N"]) and d["A"].dtype == np.complex64
+    assert d["Y"].dtype == np.float32 and np.allclose(d["Y"], c["F"] @ c["Phi"].T, rtol=1e-5, atol=1e-2)
