@@ -312,6 +312,103 @@ def check_gomp_stop(orc):
                            atol=1e-12 * c * np.abs(base["X"]).max())
 
 
+def check_gomp_final_prune(orc):
+    """prune='final' (Alg. 3 step 3 applied once, after the loop).
+
+    With G = 1 the loop without a prune is textbook OMP, so the grown set
+    after I iterations and its values are scikit-learn's OMP with I atoms; the
+    final step keeps the K largest of those values (ties to the lower index)
+    and solves the least squares again on them (NumPy's SVD lstsq).  The
+    orthonormal closed form of the per-iteration prune holds as well, and a
+    run that never grows past K is not pruned."""
+    from sklearn.linear_model import OrthogonalMatchingPursuit
+    A, _, Y = _sparse_problem(40, 90, 6, 6, 41, noise=0.05)
+    K, I = 4, 9
+    out = orc.gomp(A, Y, K=K, S=1, max_iter=I, prune="final")
+    each = orc.gomp(A, Y, K=K, S=1, max_iter=I, prune="each")
+    differs = 0
+    for p in range(Y.shape[0]):
+        coef = OrthogonalMatchingPursuit(n_nonzero_coefs=I, fit_intercept=False).fit(A, Y[p]).coef_
+        grown = np.nonzero(coef)[0]
+        assert len(grown) == I
+        q = grown[np.argsort(-np.abs(coef[grown]), kind="stable")[:K]]
+        want = np.zeros(A.shape[1])
+        want[q] = np.linalg.lstsq(A[:, q], Y[p], rcond=None)[0]
+        assert np.max(np.abs(out["X"][p] - want)) < 1e-9, p
+        assert out["support"][p].tolist() == np.sort(q).tolist()
+        assert np.linalg.norm(want - coef) > 1e-6       # the re-solve changes the values
+        differs += np.max(np.abs(each["X"][p] - want)) > 1e-9
+    assert differs > 0                                    # the two placements are different methods
+    # orthonormal A: the K largest |A^T y| with the values A^T y
+    N = 24
+    Q = _orthonormal(N, 42)
+    Yq = _rng(43).standard_normal((4, N))
+    cq = Yq @ Q
+    for K2, S2, it in ((5, 2, 4), (3, 3, 2)):
+        o = orc.gomp(Q, Yq, K=K2, S=S2, max_iter=it, prune="final")
+        for p in range(4):
+            top = np.argsort(-np.abs(cq[p]), kind="stable")[:K2]
+            want = np.zeros(N)
+            want[top] = cq[p, top]
+            assert np.max(np.abs(o["X"][p] - want)) < 1e-12
+            assert o["support"][p].tolist() == np.sort(top).tolist()
+    # |c| never exceeds K: no prune, the OMP solution with I atoms
+    o = orc.gomp(A, Y, K=6, S=1, max_iter=5, prune="final")
+    for p in range(Y.shape[0]):
+        coef = OrthogonalMatchingPursuit(n_nonzero_coefs=5, fit_intercept=False).fit(A, Y[p]).coef_
+        assert np.max(np.abs(o["X"][p] - coef)) < 1e-9
+
+
+def check_gomp_diagnostics_by_hand(orc):
+    """The near-tie diagnostics of gOMP on cases worked by hand.
+
+    A = I (M = N = 8), y = (4, 1, 2.5, 0.5, -2, 0, 0.25, 1.5), G = 1, K = 2,
+    4 iterations.  The correlations are the residual, which is y with the
+    selected entries removed:
+      i=1: |p| sorted 4, 2.5, ...            gap 1.5 / 4
+      i=2: over the unselected 2.5, 2, ...    gap 0.5 / 2.5
+      i=3: 2, 1.5, ...                        gap 0.5 / 2
+      i=4: 1.5, 1, ...                        gap 0.5 / 1.5
+    so the selection gap is 0.2 (relative to the largest compared value) and
+    0.5 / ||y|| on the ||y|| scale.  Prunes (|c| > 2) at i = 3, 4 rank
+    |s| = (4, 2.5, 2) and (4, 2.5, 2, 1.5): gap 0.5 / 4, and on the ||s||
+    scale 0.5 / sqrt(28.5) (the larger s).  The residual keeps y's entries
+    1, 3, 5, 6, 7 and 4 (pruned back) from i = 2 on, ||r||^2 = 7.5625 of
+    ||y||^2 = 29.8125; with res_tol = 0.1 the stop margin is
+    |sqrt(7.5625 / 29.8125) - 0.1| / 0.1.  Every pivot ratio of an
+    orthonormal support is 1.
+
+    Pivot ratio: a0 = 2 e0 and a1 = 3 (cos t, sin t, 0) at angle t: the
+    second Cholesky pivot squared of their Gram matrix is the second atom's
+    squared norm times sin^2 t, so the ratio to its diagonal entry is
+    sin^2 t whichever atom comes first."""
+    y = np.array([[4.0, 1.0, 2.5, 0.5, -2.0, 0.0, 0.25, 1.5]])
+    ny2 = float(np.sum(y * y))
+    assert ny2 == 29.8125
+    o = orc.gomp(np.eye(8), y, K=2, S=1, max_iter=4, res_tol=0.1, diagnostics=True)
+    assert abs(o["sel_gap"][0] - 0.2) < 1e-15
+    assert abs(o["sel_gap_abs"][0] - 0.5 / math.sqrt(ny2)) < 1e-15
+    assert abs(o["prune_gap"][0] - 0.125) < 1e-15
+    assert abs(o["prune_gap_abs"][0] - 0.5 / math.sqrt(28.5)) < 1e-15
+    assert abs(o["stop_margin"][0] - abs(math.sqrt(7.5625 / ny2) - 0.1) / 0.1) < 1e-12
+    assert abs(o["min_pivot"][0] - 1.0) < 1e-15
+    assert o["support"][0].tolist() == [0, 2]
+    for t in (0.3, 1e-3):
+        A = np.array([[2.0, 3.0 * math.cos(t), 0.0],
+                      [0.0, 3.0 * math.sin(t), 0.0],
+                      [0.0, 0.0, 1.0]])
+        yy = (A[:, 0] + 0.5 * A[:, 1])[None, :]
+        d = orc.gomp(A, yy, K=2, S=2, max_iter=1, diagnostics=True)
+        assert sorted(d["support"][0].tolist()) == [0, 1]
+        assert abs(d["min_pivot"][0] / math.sin(t) ** 2 - 1.0) < 1e-9
+    # CoSaMP and BIHT report the same selection gap of their first step
+    # (A = I: p = y, 2K resp. K largest)
+    c = orc.cosamp(np.eye(8), y, K=1, max_iter=1, diagnostics=True)
+    assert abs(c["sel_gap"][0] - 0.5 / 4.0) < 1e-15          # 2nd (2.5) vs 3rd (2)
+    b = orc.biht(np.eye(8), y, K=2, max_iter=1, mu=1.0, diagnostics=True)
+    assert abs(b["sel_gap"][0] - 0.5 / 4.0) < 1e-15          # u = mu y: 2nd (2.5) vs 3rd (2)
+
+
 # ---------------------------------------------------------------- CoSaMP
 
 def check_cosamp_orthonormal(orc):
@@ -413,6 +510,32 @@ def check_biht_recovery(orc):
     out = orc.biht(A, Y, K=5, max_iter=30, mu=1.0)
     assert np.mean(np.max(np.abs(out["X"] - X), axis=1) < 1e-10) >= 0.9
     assert np.all(np.count_nonzero(out["X"], axis=1) <= 5)
+
+
+def check_cosamp_biht_res_tol(orc):
+    """The residual stop of CoSaMP and BIHT is relative, ||r|| <= res_tol ||y||
+    (the reading shared with gOMP): on exact sparse data every pixel stops
+    with CONVERGED before the cap, the stop is the first iteration meeting
+    the rule, and scaling y by 1e-9 or 1e9 scales x and keeps the iteration
+    counts."""
+    A, X, Y = _sparse_problem(50, 100, 4, 8, 44)
+    tol = 1e-8
+    runs = (lambda y, it: orc.cosamp(A, y, K=4, max_iter=it, res_tol=tol),
+            lambda y, it: orc.biht(A, y, K=4, max_iter=it, mu=1.0, res_tol=tol))
+    for run in runs:
+        base = run(Y, 40)
+        assert np.all(base["iters"] < 40) and np.all(base["flags"] & orc.STOP_CONVERGED)
+        ny = np.linalg.norm(Y, axis=1)
+        assert np.all(base["resid"] <= tol * ny)
+        for p in range(Y.shape[0]):
+            k = int(base["iters"][p])
+            if k > 1:
+                prev = run(Y[p:p + 1], k - 1)
+                assert prev["resid"][0] > tol * ny[p] and prev["flags"][0] & orc.STOP_ITER_CAP
+        for c in (1e-9, 1e9):
+            sc = run(c * Y, 40)
+            assert np.array_equal(sc["iters"], base["iters"])
+            assert np.allclose(sc["X"], c * base["X"], rtol=1e-9, atol=1e-12 * c * np.abs(base["X"]).max())
 
 
 def check_one_bit(orc):
@@ -722,7 +845,8 @@ ORACLE_CHECKS = [
     check_fista_stop_rule, check_fista_nonfinite, check_lstsq, check_top_indices,
     check_gomp_is_omp_when_S1, check_gomp_orthonormal, check_gomp_exact_recovery,
     check_gomp_brute_force, check_gomp_prune_invariants, check_gomp_no_reselect,
-    check_gomp_stop, check_cosamp_orthonormal, check_cosamp_recovery, check_cosamp_no_resolve,
+    check_gomp_stop, check_gomp_final_prune, check_gomp_diagnostics_by_hand, check_cosamp_biht_res_tol,
+    check_cosamp_orthonormal, check_cosamp_recovery, check_cosamp_no_resolve,
     check_biht_orthonormal, check_biht_first_step, check_biht_second_step_mu,
     check_biht_recovery, check_one_bit, check_admm_matches_sklearn_lasso, check_admm_identity,
     check_admm_kkt_and_dual, check_admm_stop_rule, check_sparsify_worked, check_sparsify_transform,

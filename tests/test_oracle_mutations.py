@@ -1,19 +1,25 @@
 """Plant plausible mistakes in a copy of the oracle source (on the CPU) and
-check that the pins catch every one of them.  The real oracle is untouched."""
-import importlib.util
+check that the pins catch every one of them.  The real oracle is untouched.
+
+A mutant is the whole oracle: the mutated module's functions laid over the
+real package's, so every check finds every function it calls and fails only
+on wrong arithmetic.  An unmutated copy must pass every check, and a check
+that raises anything but a wrong-value error is a bug of the harness, not a
+catch."""
 import os
-import sys
 import types
 
+import numpy as np
 import pytest
 
+import oracle
 import oracle_pins as pins
 
 ORACLE_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
 SRC = os.path.join(ORACLE_DIR, "cs.py")
 PROTOCOL_SRC = os.path.join(ORACLE_DIR, "protocol.py")
 
-# (id, text to replace (first occurrence), replacement)
+# (id, text to replace, replacement[, which occurrence (1 = first)])
 MUTATIONS = [
     ("fista-threshold-lam", "soft_threshold(aux, dtype(lam / L))", "soft_threshold(aux, dtype(lam))"),
     ("fista-no-step-1/L", "(1.0 / L) * ((za @ A.T - ya) @ A)", "((za @ A.T - ya) @ A)"),
@@ -59,6 +65,26 @@ MUTATIONS = [
     ("cadmm-separable-shrink", "zn = soft_threshold_complex(v, tau)",
      "zn = soft_threshold(v.real, tau) + 1j * soft_threshold(v.imag, tau)"),
     ("cadmm-no-dual-in-threshold", "v = xn + wc[a]", "v = xn"),
+    # gOMP's prune after the loop (Alg. 3 step 3 applied once)
+    ("gomp-final-skipped", 'if prune == "final":', "if False:"),
+    ("gomp-final-no-resolve", "sq = lstsq_on_support(A, Yc[big], q)", "sq = x[big[:, None], q]"),
+    # the near-tie diagnostics that decide which pixels get exact parity
+    ("ordered-gap-zero", "return (srt[:, k - 1] - nxt) / top", "return 0.0 * (srt[:, k - 1] - nxt) / top"),
+    ("ordered-gap-scale-ignored",
+     "top = np.maximum(srt[:, 0] if scale is None else np.asarray(scale, dtype=np.float64), 1e-300)",
+     "top = np.maximum(srt[:, 0], 1e-300)"),
+    ("ordered-gap-kth-vs-first", "return (srt[:, k - 1] - nxt) / top", "return (srt[:, 0] - nxt) / top"),
+    ("pivot-ratio-infinite", "return np.min(d / np.maximum(g, 1e-300), axis=1)",
+     "return np.full(cols.shape[0], np.inf)"),
+    ("pivot-ratio-unnormalised", "return np.min(d / np.maximum(g, 1e-300), axis=1)",
+     "return np.min(d, axis=1)"),
+    ("stop-margin-absolute", "np.abs(rn / np.maximum(ynorm[a], 1e-300) - res_tol) / res_tol)",
+     "np.abs(rn - res_tol) / res_tol)"),
+    # the relative residual stop of CoSaMP (first occurrence) and BIHT (second)
+    ("cosamp-absolute-res-tol", "stop = (d < eps) | (rn <= res_tol * ynorm[a])",
+     "stop = (d < eps) | (rn <= res_tol)", 1),
+    ("biht-absolute-res-tol", "stop = (d < eps) | (rn <= res_tol * ynorm[a])",
+     "stop = (d < eps) | (rn <= res_tol)", 2),
 ]
 
 # mistakes planted in the sparsification (Section II)
@@ -74,36 +100,68 @@ PROTOCOL_MUTATIONS = [
 ]
 
 
-def _mutant(old, new, src=SRC):
+# Errors a wrong oracle raises on its own (a failed comparison, a shape or
+# value error of NumPy from a wrong index or operand, a floating-point trap);
+# anything else (a missing name, a type error) means the check could not run.
+CATCHES = (AssertionError, ValueError, IndexError, FloatingPointError, np.linalg.LinAlgError)
+
+
+def _replace_nth(text, old, new, nth):
+    at = -1
+    for _ in range(nth):
+        at = text.index(old, at + 1)
+    return text[:at] + new + text[at + len(old):]
+
+
+def _mutant(old, new, src=SRC, nth=1):
+    """The oracle package with ``src`` replaced by a copy whose ``nth``
+    occurrence of ``old`` reads ``new`` (old is None: an unmutated copy)."""
     with open(src) as f:
         text = f.read()
-    assert text.count(old) >= 1, old
-    text = text.replace(old, new, 1)
+    if old is not None:
+        assert text.count(old) >= nth, old
+        text = _replace_nth(text, old, new, nth)
     mod = types.ModuleType("oracle_mutant")
     mod.__file__ = src
     exec(compile(text, src + ":mutant", "exec"), mod.__dict__)
-    return mod
+    whole = types.ModuleType("oracle_whole")
+    for name in dir(oracle):
+        if not name.startswith("__"):
+            setattr(whole, name, getattr(oracle, name))
+    for name, val in mod.__dict__.items():
+        if not name.startswith("__"):
+            setattr(whole, name, val)
+    return whole
 
 
-@pytest.mark.parametrize("mid,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_pins_catch_mutation(mid, old, new):
-    mod = _mutant(old, new)
-    failed = []
+def _failing_checks(mod):
+    """The first check that fails on ``mod`` (one catch is enough), as a list."""
     for check in pins.ORACLE_CHECKS:
         try:
             check(mod)
-        except (AssertionError, ValueError, IndexError, FloatingPointError, AttributeError):
-            failed.append(check.__name__)
+        except CATCHES:
+            return [check.__name__]
+    return []
+
+
+@pytest.mark.parametrize("src", [SRC, PROTOCOL_SRC], ids=["cs", "protocol"])
+def test_unmutated_copy_passes_every_check(src):
+    """The harness itself: a copy of the oracle with nothing planted passes
+    every pin, so a failure under a mutation is the mutation's doing."""
+    mod = _mutant(None, None, src)
+    for check in pins.ORACLE_CHECKS:
+        check(mod)          # any exception fails this test
+
+
+@pytest.mark.parametrize("mut", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_mutation(mut):
+    mid, old, new = mut[:3]
+    nth = mut[3] if len(mut) > 3 else 1
+    failed = _failing_checks(_mutant(old, new, SRC, nth))
     assert failed, f"no pin catches mutation {mid}"
 
 
 @pytest.mark.parametrize("mid,old,new", PROTOCOL_MUTATIONS, ids=[m[0] for m in PROTOCOL_MUTATIONS])
 def test_pins_catch_protocol_mutation(mid, old, new):
-    mod = _mutant(old, new, PROTOCOL_SRC)
-    failed = []
-    for check in (pins.check_sparsify_worked, pins.check_sparsify_transform, pins.check_sparsify_complex_basis):
-        try:
-            check(mod)
-        except (AssertionError, ValueError, IndexError, FloatingPointError, AttributeError):
-            failed.append(check.__name__)
+    failed = _failing_checks(_mutant(old, new, PROTOCOL_SRC))
     assert failed, f"no pin catches mutation {mid}"
