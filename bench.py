@@ -96,8 +96,8 @@ def parse():
     ap.add_argument("--pixels", type=int, default=0, help="override the cube size (testing only)")
     ap.add_argument("--legs", default="precision,other,admm,dft,protocol,serving",
                     help="comma list of the legs measured after the timed region ('' for none)")
-    ap.add_argument("--serve-tiles", type=int, default=400, help="measured serving tiles")
-    ap.add_argument("--serve-warmup", type=int, default=40, help="serving tiles before the measured ones")
+    ap.add_argument("--serve-tiles", type=int, default=2000, help="measured serving tiles")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="serving tiles before the measured ones")
     return ap.parse_args()
 
 
@@ -429,11 +429,14 @@ def leg_serving(torch, cs, W, n_tiles, n_warm):
         pools[N] = (F @ phi.T).astype(np.float32)
         dicts[N] = a32
     budget = 24 << 30
+    batch_pixels = 262144
     done, lag = {}, {}
-    with cs.Server(K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL, hbm_budget_bytes=budget) as srv:
+    st0 = None
+    with cs.Server(K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL, hbm_budget_bytes=budget,
+                   batch_pixels=batch_pixels) as srv:
         ids = {N: srv.add_dict(a) for N, a in dicts.items()}
         t0 = time.perf_counter()
-        for tile in stream:
+        for i, tile in enumerate(stream):
             while True:
                 for r in srv.poll(1024, fetch=False):
                     done[r["tag"]] = r
@@ -443,11 +446,23 @@ def leg_serving(torch, cs, W, n_tiles, n_warm):
                 time.sleep(min(wait, 0.002))
             P = tile.side * tile.side
             off = (tile.seed % (side_max * side_max - P + 1))
+            if i == n_warm:
+                st0 = srv.stats()
             lag[tile.tag] = time.perf_counter() - (t0 + tile.t_arrival)
             srv.submit(ids[tile.N], pools[tile.N][off:off + P], tile.tag)
+            if (i + 1) % 500 == 0:
+                log(f"  serving: {i + 1} tiles submitted")
         srv.drain()
+        st1 = srv.stats()
         for r in srv.poll(4096, fetch=False):
             done[r["tag"]] = r
+    # occupancy over the measured window: time averages between the two snapshots
+    win = st1["elapsed_s"] - st0["elapsed_s"]
+    px_in_flight = (st1["mean_pixels_in_flight"] * st1["elapsed_s"]
+                    - st0["mean_pixels_in_flight"] * st0["elapsed_s"]) / win
+    pool_bytes = (st1["mean_pool_bytes"] * st1["elapsed_s"] - st0["mean_pool_bytes"] * st0["elapsed_s"]) / win
+    batches = st1["batches"] - st0["batches"]
+    launched = st1["pixels_launched"] - st0["pixels_launched"]
     meas = [t for t in stream[n_warm:]]
     bad = [t.tag for t in meas if t.tag not in done or done[t.tag]["status"] != 0]
     # open-loop latency: from the scheduled arrival (a client that submits
@@ -464,8 +479,17 @@ def leg_serving(torch, cs, W, n_tiles, n_warm):
                         f"K={GOMP_K} res_tol={GOMP_TOL} FP32, HBM budget {budget >> 30} GiB",
             "tiles": len(meas), "warmup_tiles": n_warm, "failed_tiles": len(bad),
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            # stability over the run: the same percentiles on each half of the measured tiles
+            "p50_p99_ms_halves": [[float(np.percentile(h, 50) * 1e3), float(np.percentile(h, 99) * 1e3)]
+                                  for h in np.array_split(lat, 2)],
             "submit_lag_p99_ms": float(np.percentile(lag_v, 99) * 1e3),
-            "pixels_per_s": px / (t_last - t_first), "offered_pixels_per_s": px / span if span > 0 else None}
+            "pixels_per_s": px / (t_last - t_first), "offered_pixels_per_s": px / span if span > 0 else None,
+            "batch_pixels": batch_pixels, "batches": batches,
+            "mean_batch_fill": launched / (batches * batch_pixels) if batches else None,
+            "busy_fraction": (st1["busy_s"] - st0["busy_s"]) / win,
+            "slot_occupancy": px_in_flight / (2 * batch_pixels),
+            "pool_occupancy": pool_bytes / budget,
+            "pageable_fallbacks": {"inputs": st1["host_in_pageable"], "results": st1["host_out_pageable"]}}
 
 
 # ------------------------------------------------------------------ CPU (oracle) leg

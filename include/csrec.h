@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define CSREC_ABI_VERSION 1
+#define CSREC_ABI_VERSION 2
 
 /* return codes */
 #define CSREC_OK             0
@@ -340,17 +340,32 @@ int32_t csrec_lipschitz(const float* A, int32_t M, int32_t N, float* L_out, void
  * A server owns, on one device: a pool of `hbm_budget_bytes` for the tiles'
  * measurements and results, a batch workspace for `batch_pixels` pixels of
  * solver state, the registered dictionaries (A with its Gram matrix, resident
- * until destroy) and a scheduler thread.  Submitted tiles wait in arrival
- * order until their measurements and results fit in the pool (admission);
- * admitted tiles are cut into pixel chunks, and chunks of any admitted tiles
- * -- also of different band counts -- are solved together in batched
- * launches, up to two batches in flight, so that tiles arriving while others
- * run join the next launch.  Each pixel's result depends only on its own
- * measurements and its dictionary: a tile's result is bit-identical whether
- * it runs alone or mixed with others.
+ * until destroy), a pinned host staging pool and a scheduler thread.
  *
- * Threading: submit/poll/release/drain may be called from any host thread.
- * Host buffers passed to submit are copied before the call returns.
+ *   submit     the tile's measurements are copied into the pinned staging
+ *              pool, or into pageable memory when the pool is full now;
+ *   admission  tiles leave the arrival queue strictly in order when their
+ *              device buffers (Y in; X, support, stats out) fit in the
+ *              device pool; the input copy is enqueued at once and its
+ *              staging freed when it has completed;
+ *   batching   admitted tiles are cut into chunks of at most chunk_pixels;
+ *              a batch takes chunks of any admitted tiles -- of any band
+ *              count -- up to batch_pixels, and runs them as persistent
+ *              grouped launches (one per parameter class and kernel
+ *              variant): resident workgroups claim 4-pixel units of all the
+ *              batch's tiles in admission order until none is left; two
+ *              batches are in flight at most, so tiles admitted while one
+ *              runs join the next;
+ *   retirement a solved tile's results are copied into the pinned pool, or
+ *              into pageable memory when it is full now; then its device
+ *              buffers are freed.
+ * No step waits for host memory, so every submitted tile finishes whatever
+ * the caller does with polled results.  Each pixel's result depends only on
+ * its own measurements, its dictionary and its tile's parameters: a tile's
+ * result is bit-identical whether it runs alone or mixed with others.
+ *
+ * Threading: submit/poll/release/drain/stats may be called from any host
+ * thread.  Host buffers passed to submit are copied before the call returns.
  * ---------------------------------------------------------------------- */
 typedef struct csrec_server csrec_server;
 
@@ -358,9 +373,10 @@ typedef struct {
     int32_t struct_size;          /* sizeof(csrec_server_cfg) */
     int32_t device;               /* HIP device ordinal */
     size_t hbm_budget_bytes;      /* pool for admitted tiles (Y in, X/support/stats out) */
-    int64_t batch_pixels;         /* pixels per batched launch (solver workspace capacity) */
+    int64_t batch_pixels;         /* pixels per batch (solver workspace capacity) */
     int64_t chunk_pixels;         /* largest piece of one tile in a batch */
-    csrec_gomp_params gomp;       /* solver parameters of every tile (K, S, res_tol, ...) */
+    csrec_gomp_params gomp;       /* default parameters of a tile; their K, S and max_iter fix
+                                     the batch workspace layout */
 } csrec_server_cfg;
 
 typedef struct {
@@ -369,32 +385,55 @@ typedef struct {
     int32_t dict_id;
     int64_t P;
     int32_t N, K;
-    const float* X;               /* host, P x N; valid until csrec_server_release(tag) */
+    const float* X;               /* host, P x N; valid until csrec_server_release(tag); NULL on error */
     const int32_t* support;       /* host, P x K */
     const csrec_pixel_stats* stats; /* host, P */
     double t_submit, t_admit, t_done; /* seconds since server creation */
 } csrec_result;
 
+/* Counters since creation.  Slot occupancy is mean_pixels_in_flight over
+ * (2 x batch_pixels) (two batches in flight at most); pool occupancy is
+ * mean_pool_bytes over hbm_budget_bytes. */
+typedef struct {
+    int32_t struct_size;          /* sizeof(csrec_server_stats), set by the caller */
+    int64_t tiles_submitted, tiles_finished;
+    int64_t batches, pixels_launched;
+    int64_t host_in_pageable;     /* tiles whose measurements were staged in pageable memory */
+    int64_t host_out_pageable;    /* tiles whose results went to pageable memory */
+    double elapsed_s;             /* since creation */
+    double busy_s;                /* time with at least one batch in flight */
+    double mean_pixels_in_flight; /* time average of the pixels of the batches in flight */
+    double mean_pool_bytes;       /* time average of the device pool bytes in use */
+} csrec_server_stats;
+
 /* Creates the server: allocates once its device pool (hbm_budget_bytes), its
  * batch workspace and a pinned host staging pool of min(max(budget, 64 MiB),
- * 4 GiB) for inputs and results, and starts its scheduler thread. */
+ * 4 GiB) for inputs and results, and starts its scheduler thread.  On an
+ * error everything allocated so far is freed. */
 int32_t csrec_server_create(const csrec_server_cfg* cfg, csrec_server** out);
-/* Registers a dictionary (host A, M x N row-major); returns its id. */
+/* Registers a dictionary (host A, M x N row-major, M <= 96); returns its id
+ * (at most 64 dictionaries per server). */
 int32_t csrec_server_add_dict(csrec_server* srv, const float* A_host, int32_t M, int32_t N, int32_t* dict_id);
 /* Queues a tile of P pixels (host Y, P x M row-major) for dictionary dict_id.
- * CSREC_E_BUDGET if the tile alone exceeds the pool or the batch workspace. */
-int32_t csrec_server_submit(csrec_server* srv, int32_t dict_id, const float* Y_host, int64_t P, uint64_t tag);
-/* Moves up to max finished tiles into out; *n receives the count.  The
- * results live in the server's pinned host staging pool (pageable memory
- * only for a tile too large for it) until csrec_server_release: a caller
- * that keeps many results unreleased stalls the copy-back of later tiles,
- * and with it admission. */
+ * params (nullable: the server's cfg.gomp) may change res_tol, eps, prune,
+ * pivot_fallback (> 0 only on a server created with one) and max_iter (up to
+ * the server's); K and S must be the server's (CSREC_E_UNSUPPORTED
+ * otherwise).  CSREC_E_BUDGET if the tile alone exceeds the device pool;
+ * CSREC_E_INVAL for a tag that is still queued, in flight, or polled and not
+ * released. */
+int32_t csrec_server_submit(csrec_server* srv, int32_t dict_id, const float* Y_host, int64_t P,
+                            const csrec_gomp_params* params, uint64_t tag);
+/* Moves up to max finished tiles into out; *n receives the count.  Their
+ * results stay valid until csrec_server_release(tag). */
 int32_t csrec_server_poll(csrec_server* srv, csrec_result* out, int32_t max, int32_t* n);
-/* Frees the host results of a polled tile. */
+/* Frees the host results of a polled tile; its tag may then be reused. */
 int32_t csrec_server_release(csrec_server* srv, uint64_t tag);
 /* Blocks until every submitted tile has finished (results stay pollable). */
 int32_t csrec_server_drain(csrec_server* srv);
-/* Stops the scheduler and frees every resource of the server. */
+/* Fills *stats (stats->struct_size set by the caller). */
+int32_t csrec_server_get_stats(csrec_server* srv, csrec_server_stats* stats);
+/* Waits for the submitted tiles, stops the scheduler and frees every
+ * resource of the server. */
 int32_t csrec_server_destroy(csrec_server* srv);
 
 #ifdef __cplusplus

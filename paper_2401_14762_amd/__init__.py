@@ -470,8 +470,8 @@ class Server:
     submit / admit / done times (seconds since creation)."""
 
     def __init__(self, K: int, S: int, res_tol: float = 0.0, max_iter: int = 0, prune: str = "each",
-                 pivot_fallback: float = 0.0, hbm_budget_bytes: int = 4 << 30, batch_pixels: int = 262144,
-                 chunk_pixels: int = 65536, device: int = 0):
+                 pivot_fallback: float = 0.0, prec: str = "f32", hbm_budget_bytes: int = 4 << 30,
+                 batch_pixels: int = 262144, chunk_pixels: int = 65536, device: int = 0):
         import numpy as np  # noqa: F401
         lib = library()
         cfg = _lib.ServerCfg()
@@ -480,8 +480,9 @@ class Server:
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
         cfg.batch_pixels = int(batch_pixels)
         cfg.chunk_pixels = int(chunk_pixels)
-        g, _ = _params("gomp", None, 0, dict(K=K, S=S, max_iter=max_iter, res_tol=res_tol, prune=prune,
-                                            pivot_fallback=pivot_fallback))
+        self._defaults = dict(K=K, S=S, max_iter=max_iter, res_tol=res_tol, prune=prune,
+                              pivot_fallback=pivot_fallback, prec=prec)
+        g, _ = _params("gomp", None, 0, self._defaults)
         cfg.gomp = g
         h = ctypes.c_void_p(0)
         _lib.check(lib.csrec_server_create(ctypes.byref(cfg), ctypes.byref(h)), "csrec_server_create")
@@ -498,16 +499,35 @@ class Server:
         self._dicts[did.value] = (M, N)
         return did.value
 
-    def submit(self, dict_id: int, Y, tag: int) -> None:
+    def submit(self, dict_id: int, Y, tag: int, **params) -> None:
+        """Queues tile Y (P x M) under `tag`.  Keyword parameters (res_tol, eps,
+        prune, pivot_fallback, max_iter, prec) override the server's for this
+        tile; none given = the server's."""
         import numpy as np
         Y = np.ascontiguousarray(Y, dtype=np.float32)
-        _lib.check(self._lib.csrec_server_submit(self._h, dict_id, Y.ctypes.data, Y.shape[0], tag),
+        pp = None
+        if params:
+            kw = dict(self._defaults)
+            kw.update(params)
+            g, _ = _params("gomp", None, 0, kw)
+            pp = ctypes.byref(g)
+        _lib.check(self._lib.csrec_server_submit(self._h, dict_id, Y.ctypes.data, Y.shape[0], pp, tag),
                    "csrec_server_submit")
 
-    def poll(self, max_results: int = 256, fetch: bool = True) -> list:
+    def stats(self) -> dict:
+        """Counters since creation: tiles, batches, pixels launched, pageable
+        fallbacks, elapsed and busy seconds, time-averaged pixels in flight and
+        device pool bytes in use."""
+        st = _lib.ServerStats()
+        st.struct_size = ctypes.sizeof(st)
+        _lib.check(self._lib.csrec_server_get_stats(self._h, ctypes.byref(st)), "csrec_server_get_stats")
+        return {name: getattr(st, name) for name, _ in _lib.ServerStats._fields_ if name != "struct_size"}
+
+    def poll(self, max_results: int = 256, fetch: bool = True, release: bool = True) -> list:
         """Finished tiles as dicts (tag, status, X, support, iters, flags, t_submit, t_admit, t_done);
-        arrays are copies, the server's buffers are released.  With fetch=False
-        only the tag, status, pixel count and times are returned."""
+        arrays are copies, and the server's buffers are released unless
+        release=False.  With fetch=False only the tag, status, pixel count and
+        times are returned."""
         import numpy as np
         buf = (_lib.Result * max_results)()
         n = ctypes.c_int32(0)
@@ -518,7 +538,8 @@ class Server:
             if not fetch:
                 out.append(dict(tag=r.tag, status=r.status, dict_id=r.dict_id, P=P, t_submit=r.t_submit,
                                 t_admit=r.t_admit, t_done=r.t_done))
-                self._lib.csrec_server_release(self._h, r.tag)
+                if release:
+                    self._lib.csrec_server_release(self._h, r.tag)
                 continue
             if P > 0 and r.status == 0:
                 X = np.ctypeslib.as_array((ctypes.c_float * (P * N)).from_address(r.X)).reshape(P, N).copy()
@@ -531,8 +552,17 @@ class Server:
             out.append(dict(tag=r.tag, status=r.status, dict_id=r.dict_id, X=X, support=S, iters=st[:, 0],
                             flags=st[:, 1].view(np.uint32), resid=st[:, 2].view(np.float32),
                             t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done))
-            self._lib.csrec_server_release(self._h, r.tag)
+            if release:
+                self._lib.csrec_server_release(self._h, r.tag)
         return out
+
+    def poll_held(self, max_results: int = 256) -> list:
+        """Like poll(), but the server keeps each tile's host results until
+        release(tag) is called (the arrays returned are still copies)."""
+        return self.poll(max_results, release=False)
+
+    def release(self, tag: int) -> None:
+        _lib.check(self._lib.csrec_server_release(self._h, tag), "csrec_server_release")
 
     def drain(self) -> None:
         _lib.check(self._lib.csrec_server_drain(self._h), "csrec_server_drain")

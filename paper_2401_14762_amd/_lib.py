@@ -12,7 +12,7 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcsrec.so")
 
-CSREC_ABI_VERSION = 1
+CSREC_ABI_VERSION = 2
 
 OK, E_INVAL, E_SHAPE, E_WORKSPACE, E_DEVICE, E_UNSUPPORTED, E_BUDGET = 0, -1, -2, -3, -4, -5, -6
 PREC = {"f32": 0, "bf16": 1, "f16": 2}
@@ -136,6 +136,22 @@ class Result(ctypes.Structure):
     ]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_int32),
+        ("tiles_submitted", ctypes.c_int64),
+        ("tiles_finished", ctypes.c_int64),
+        ("batches", ctypes.c_int64),
+        ("pixels_launched", ctypes.c_int64),
+        ("host_in_pageable", ctypes.c_int64),
+        ("host_out_pageable", ctypes.c_int64),
+        ("elapsed_s", ctypes.c_double),
+        ("busy_s", ctypes.c_double),
+        ("mean_pixels_in_flight", ctypes.c_double),
+        ("mean_pool_bytes", ctypes.c_double),
+    ]
+
+
 # every symbol the header declares, with (restype, argtypes)
 _P = ctypes.POINTER
 SIGNATURES = {
@@ -171,11 +187,12 @@ SIGNATURES = {
     "csrec_server_add_dict": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                                ctypes.c_int32, _P(ctypes.c_int32)]),
     "csrec_server_submit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
-                                             ctypes.c_int64, ctypes.c_uint64]),
+                                             ctypes.c_int64, _P(GompParams), ctypes.c_uint64]),
     "csrec_server_poll": (ctypes.c_int32, [ctypes.c_void_p, _P(Result), ctypes.c_int32,
                                            _P(ctypes.c_int32)]),
     "csrec_server_release": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64]),
     "csrec_server_drain": (ctypes.c_int32, [ctypes.c_void_p]),
+    "csrec_server_get_stats": (ctypes.c_int32, [ctypes.c_void_p, _P(ServerStats)]),
     "csrec_server_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
 }
 

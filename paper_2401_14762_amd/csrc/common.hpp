@@ -170,6 +170,8 @@ struct GreedyTileItem {
 };
 int greedy_mmax_class(int M);
 size_t greedy_group_item_bytes();
+// bytes of the host and device item tables of one grouped launch of nitems
+size_t greedy_group_table_bytes(int nitems);
 size_t greedy_group_workspace(const GreedyLaunch& proto_max, int64_t batch_pixels);
 int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* items, int nitems,
                         int64_t batch_pixels, void* ws, void* table_host, void* table_dev, hipStream_t stream);
@@ -198,6 +200,7 @@ struct GompCoopItem {
     int64_t p0, np;
 };
 size_t gomp_coop_item_bytes();
+size_t gomp_coop_table_extra();      // bytes after a grouped launch's items (its work cursor)
 int gomp_coop_class(int M, int N);   // items of one grouped launch share it (0..3)
 // CoSaMP (Alg. 5), BIHT (Alg. 4) and one-bit BIHT on the same on-chip design.
 size_t coop_other_lds_floats(int kind, int M, int N, int K);

@@ -1157,18 +1157,36 @@ struct CoopItem {
     int64_t block0;
 };
 
-// Grouped launch: blocks [items[i].block0, items[i+1].block0) solve item i.
+// Grouped launch with persistent workgroups: the grid holds at most as many
+// single-wave workgroups as the CUs keep resident, and each of them claims
+// 4-pixel units in order from the cursor behind the item table (zeroed by
+// the table's copy) until every unit of every item is taken; unit u belongs
+// to the last item i with items[i].block0 <= u.  Units of the items of all
+// tiles in the batch are claimed in admission order, so a wave that finishes
+// a unit of early-stopping pixels takes the next unit at once.
 template <int MSLOT, int NG>
-__global__ __launch_bounds__(64, 2) void gomp_coop_grouped_kernel(const CoopItem* __restrict__ items, int nitems) {
+__global__ __launch_bounds__(64, 2) void gomp_coop_persistent_kernel(const CoopItem* __restrict__ items, int nitems,
+                                                                     int64_t units,
+                                                                     unsigned long long* __restrict__ cursor) {
     extern __shared__ float lds[];
-    int it = 0;
-    while (it + 1 < nitems && items[it + 1].block0 <= (int64_t)blockIdx.x) ++it;
-    const CoopArgs a = items[it].a;
-    gomp_coop_body<MSLOT, NG>(a, (int64_t)blockIdx.x - items[it].block0, lds);
+    while (true) {
+        unsigned long long u = 0;
+        if (threadIdx.x == 0) u = atomicAdd(cursor, 1ull);
+        u = __shfl(u, 0);
+        if ((int64_t)u >= units) break;
+        int lo = 0, hi = nitems - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].block0 <= (int64_t)u) lo = mid; else hi = mid - 1;
+        }
+        const CoopArgs a = items[lo].a;
+        gomp_coop_body<MSLOT, NG>(a, (int64_t)u - items[lo].block0, lds);
+        __syncthreads();
+    }
 }
 
 typedef void (*coop_kernel_t)(CoopArgs);
-typedef void (*coop_grouped_t)(const CoopItem*, int);
+typedef void (*coop_grouped_t)(const CoopItem*, int, int64_t, unsigned long long*);
 
 coop_kernel_t pick_coop(int MP, int NG) {
     if (MP == 64) return NG == 2 ? gomp_coop_kernel<4, 2> : gomp_coop_kernel<4, 4>;
@@ -1176,8 +1194,8 @@ coop_kernel_t pick_coop(int MP, int NG) {
 }
 
 coop_grouped_t pick_coop_grouped(int MP, int NG) {
-    if (MP == 64) return NG == 2 ? gomp_coop_grouped_kernel<4, 2> : gomp_coop_grouped_kernel<4, 4>;
-    return NG == 2 ? gomp_coop_grouped_kernel<8, 2> : gomp_coop_grouped_kernel<8, 4>;
+    if (MP == 64) return NG == 2 ? gomp_coop_persistent_kernel<4, 2> : gomp_coop_persistent_kernel<4, 4>;
+    return NG == 2 ? gomp_coop_persistent_kernel<8, 2> : gomp_coop_persistent_kernel<8, 4>;
 }
 
 // The two dictionary copies: AT (N x MP, rows zero padded) and Ap (M8 x NP,
@@ -1321,11 +1339,25 @@ int coop_other_launch(int kind, const float* Y, const int8_t* Ysign, float* X, i
 }
 
 size_t gomp_coop_item_bytes() { return sizeof(CoopItem); }
+size_t gomp_coop_table_extra() { return 64; }
 
 // Items of one launch must share MP (64 or 128) and the atom grouping NG
 // (gomp_coop_class tells them apart).
 int gomp_coop_class(int M, int N) { return (gomp_coop_mp(M) == 64 ? 0 : 2) + (coop_ng(N) == 2 ? 0 : 1); }
 
+namespace {
+// Workgroups of `fn` that the device keeps resident at `lds` bytes each.
+int64_t resident_groups(const void* fn, size_t lds) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds) != hipSuccess) return 0;
+    return (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+}
+}  // namespace
+
+// table_host / table_dev: nitems items and gomp_coop_table_extra() bytes
+// behind them (the work cursor).
 int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_host, void* table_dev, int K, int S,
                            int prune, float res_tol, float eps, double pivot_thr, hipStream_t stream) {
     if (nitems <= 0) return CSREC_OK;
@@ -1351,12 +1383,19 @@ int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_ho
         const size_t need = (size_t)kGroups * a.lds_floats * sizeof(float);
         lds = need > lds ? need : lds;
     }
-    CSREC_HIP_TRY(hipMemcpyAsync(table_dev, th, (size_t)nitems * sizeof(CoopItem), hipMemcpyHostToDevice, stream));
+    const size_t tbytes = (size_t)nitems * sizeof(CoopItem);
+    unsigned long long* cur_h = reinterpret_cast<unsigned long long*>(static_cast<char*>(table_host) + tbytes);
+    *cur_h = 0ull;
+    CSREC_HIP_TRY(hipMemcpyAsync(table_dev, th, tbytes + sizeof(unsigned long long), hipMemcpyHostToDevice,
+                                 stream));
     const CoopItem* td = static_cast<const CoopItem*>(table_dev);
+    unsigned long long* cur_d = reinterpret_cast<unsigned long long*>(static_cast<char*>(table_dev) + tbytes);
     const coop_grouped_t fn = pick_coop_grouped(th[0].a.MP, th[0].a.NP / 64);
     CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds));
-    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64), lds, stream, td, nitems);
+    int64_t grid = resident_groups(reinterpret_cast<const void*>(fn), lds);
+    if (grid <= 0 || grid > blocks) grid = blocks;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64), lds, stream, td, nitems, blocks, cur_d);
     CSREC_HIP_TRY(hipGetLastError());
     return CSREC_OK;
 }

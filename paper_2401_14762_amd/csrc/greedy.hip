@@ -611,6 +611,13 @@ int greedy_mmax_class(int M) { return mmax_for(M); }
 
 size_t greedy_group_item_bytes() { return sizeof(GroupItem); }
 
+size_t greedy_group_table_bytes(int nitems) {
+    // the FP64 redo table, then up to four on-chip kernel tables (one per
+    // kernel variant), each with its work cursor and padded to 256 bytes
+    return align_up((size_t)nitems * sizeof(GroupItem), 256) + (size_t)nitems * gomp_coop_item_bytes() +
+           4 * (gomp_coop_table_extra() + 256);
+}
+
 size_t greedy_group_workspace(const GreedyLaunch& proto_max, int64_t batch_pixels) {
     return layout_for(proto_max, batch_pixels).total;
 }
@@ -681,7 +688,7 @@ int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* ite
     // pass 0: the on-chip gOMP kernel, items grouped by kernel variant
     char* chost = static_cast<char*>(table_host) + align_up((size_t)nitems * sizeof(GroupItem), 256);
     char* cdev = static_cast<char*>(table_dev) + align_up((size_t)nitems * sizeof(GroupItem), 256);
-    int cfirst = 0;
+    size_t coff = 0;
     for (int cls = 0; cls < 4; ++cls) {
         std::vector<GompCoopItem> ci;
         for (int k = 0; k < nt; ++k) {
@@ -703,11 +710,10 @@ int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* ite
             ci.push_back(c);
         }
         if (ci.empty()) continue;
-        const int e = gomp_coop_group_launch(ci.data(), (int)ci.size(), chost + cfirst * gomp_coop_item_bytes(),
-                                             cdev + cfirst * gomp_coop_item_bytes(), pm.K, pm.S, pm.prune,
-                                             pm.res_tol, pm.eps, pm.pivot_fallback, stream);
+        const int e = gomp_coop_group_launch(ci.data(), (int)ci.size(), chost + coff, cdev + coff, pm.K, pm.S,
+                                             pm.prune, pm.res_tol, pm.eps, pm.pivot_fallback, stream);
         if (e) return e;
-        cfirst += (int)ci.size();
+        coff += align_up(ci.size() * gomp_coop_item_bytes() + gomp_coop_table_extra(), 256);
     }
     if (!dbl) return CSREC_OK;
     // pass 1: FP64 redo of the marked pixels (scratch-based kernel)

@@ -1,154 +1,205 @@
 // Serving runtime: continuous batching of cube tiles through gOMP (Alg. 3).
 //
-// Host side of the request loop.  One scheduler thread per server:
-//   submission -- the caller's measurements are copied into a pinned host
-//                 staging pool (first fit; pageable memory only for a tile
-//                 that could never fit it), outside the server lock;
-//   admission  -- tiles leave the arrival queue in order when their device
-//                 buffers (Y in, X / support / stats out) fit in the device
-//                 pool; their input copy runs on the host-to-device stream;
-//   batching   -- admitted tiles are cut into pixel chunks; one batch takes
-//                 chunks of several tiles (any band counts) up to the batch
-//                 capacity and runs them in grouped launches, at most two
-//                 batches in flight on the compute stream, so tiles admitted
-//                 while a batch runs join the next one; a batch waits (on the
-//                 device) for the input copies of its tiles;
-//   retirement -- a finished batch credits its chunks; a tile whose pixels
-//                 are all done is copied into pinned host result memory on
-//                 the device-to-host stream, and once that copy's event has
-//                 completed its device memory is freed and its latency
-//                 stamped.
-// Every HIP call the scheduler makes under the lock is asynchronous (event
-// queries, copies between pinned and device memory, launches), so submit and
-// poll never wait behind a transfer.  Dictionaries (A, its copies for the
-// on-chip kernel and its Gram matrix in FP32 and FP64) stay on the device from
-// csrec_server_add_dict until destroy; the per-pixel solver state of a batch
-// lives in the batch workspace.  Nothing is allocated on the device after
-// creation except dictionaries.
+// The scheduling core (admission by device budget, batching, retirement,
+// host staging) is serving::Scheduler in serve_policy.hpp; this file is its
+// HIP executor and the C ABI around it.
+//
+// Executor.  Three non-blocking streams at the default priority: input
+// copies (host to device), the batched solves, and result copies (device to
+// host).  A batch's solve waits on the device for the input copies of its
+// tiles; one batch is one persistent grouped launch of the on-chip gOMP
+// kernel per parameter class and kernel variant (every item of every tile in
+// it is claimed unit by unit by resident workgroups), followed, when the
+// class has an FP64 fallback threshold, by the grouped FP64 redo of the
+// pixels the FP32 pass flagged.  Each operation ends with an event that the
+// scheduler polls; events are recycled.  Dictionaries (A, its copies for
+// the on-chip kernel and its Gram matrix in FP32 and FP64) stay on the device
+// from csrec_server_add_dict until destroy; the per-pixel state of a batch
+// lives in the batch workspace.  After creation nothing is allocated on the
+// device except dictionaries.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
+#include <array>
 #include <atomic>
-#include <chrono>
-#include <condition_variable>
-#include <cstring>
-#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
-#include <thread>
 #include <vector>
 
 #include "common.hpp"
+#include "serve_policy.hpp"
 
 namespace csrec {
 namespace {
 
-double now_since(std::chrono::steady_clock::time_point t0) {
-    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-}
-
-// First-fit allocator over one device buffer (256-byte granules).
-class Pool {
-   public:
-    void init(char* base, size_t bytes) {
-        base_ = base;
-        free_.clear();
-        free_[0] = bytes;
-        cap_ = bytes;
-    }
-    char* alloc(size_t bytes) {
-        bytes = align_up(bytes, 256);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                const size_t off = it->first, len = it->second;
-                free_.erase(it);
-                if (len > bytes) free_[off + bytes] = len - bytes;
-                used_[off] = bytes;
-                return base_ + off;
-            }
-        }
-        return nullptr;
-    }
-    void release(char* p) {
-        const size_t off = (size_t)(p - base_);
-        auto u = used_.find(off);
-        if (u == used_.end()) return;
-        size_t len = u->second;
-        used_.erase(u);
-        size_t start = off;
-        auto nx = free_.lower_bound(off);
-        if (nx != free_.end() && nx->first == off + len) {
-            len += nx->second;
-            free_.erase(nx);
-        }
-        auto pv = free_.lower_bound(off);
-        if (pv != free_.begin()) {
-            --pv;
-            if (pv->first + pv->second == off) {
-                start = pv->first;
-                len += pv->second;
-                free_.erase(pv);
-            }
-        }
-        free_[start] = len;
-    }
-    size_t capacity() const { return cap_; }
-
-   private:
-    char* base_ = nullptr;
-    size_t cap_ = 0;
-    std::map<size_t, size_t> free_, used_;
-};
+constexpr int kMaxDicts = 64;
 
 struct Dict {
-    int M = 0, N = 0, imax = 0;
+    int M = 0, N = 0;
     float* A = nullptr;
     float* AT = nullptr;
     float* G32 = nullptr;
     double* G64 = nullptr;
 };
 
-struct Tile {
-    uint64_t tag = 0;
-    int dict = 0;
-    int64_t P = 0;
-    char* hin = nullptr;                   // pinned staging of the measurements (host pool) ...
-    std::vector<float> Yv;                 // ... or a pageable copy when the pool cannot hold them
-    char* mem = nullptr;                   // device pool allocation
-    float* dY = nullptr;
-    float* dX = nullptr;
-    int32_t* dS = nullptr;
-    csrec_pixel_stats* dSt = nullptr;
-    hipEvent_t ev_in = nullptr;            // input copy done (host-to-device stream)
-    hipEvent_t ev_out = nullptr;           // result copy done (device-to-host stream)
-    bool in_waited = false;                // the compute stream already waits on ev_in
-    int64_t issued = 0, done = 0;
-    double t_submit = 0, t_admit = 0, t_done = 0;
-    int status = CSREC_OK;
-    char* hout = nullptr;                  // pinned results (host pool), or the vectors below
-    std::vector<float> Xv;
-    std::vector<int32_t> Sv;
-    std::vector<csrec_pixel_stats> Stv;
-    float* X = nullptr;
-    int32_t* S = nullptr;
-    csrec_pixel_stats* St = nullptr;
-};
-
-struct Batch {
-    hipEvent_t ev = nullptr;
-    std::vector<std::pair<Tile*, int64_t>> parts;
-};
-
-size_t tile_bytes(const Dict& d, int64_t P, int K) {
-    return align_up((size_t)P * d.M * 4, 256) + align_up((size_t)P * d.N * 4, 256) +
-           align_up((size_t)P * K * 4, 256) + align_up((size_t)P * sizeof(csrec_pixel_stats), 256);
+void free_dict(Dict& d) {
+    if (d.A) hipFree(d.A);
+    if (d.AT) hipFree(d.AT);
+    if (d.G32) hipFree(d.G32);
+    if (d.G64) hipFree(d.G64);
+    d = Dict{};
 }
 
-size_t result_bytes(const Dict& d, int64_t P, int K) {
-    return align_up((size_t)P * d.N * 4, 256) + align_up((size_t)P * K * 4, 256) +
-           align_up((size_t)P * sizeof(csrec_pixel_stats), 256);
-}
+class HipExecutor : public serving::Executor {
+   public:
+    hipStream_t compute = nullptr, h2d = nullptr, d2h = nullptr;
+    char* dev_base = nullptr;        // device pool
+    char* host_base = nullptr;       // pinned host staging pool
+    char* ws = nullptr;              // batch workspace
+    char* table_dev = nullptr;       // launch item tables, two halves
+    char* table_host[2] = {nullptr, nullptr};
+    size_t table_bytes = 0;
+    int flip = 0;
+    int64_t batch_pixels = 0;
+    GreedyLaunch proto{};            // layout of the batch workspace (maximal shape)
+    const std::array<Dict, kMaxDicts>* dicts = nullptr;
+
+    ~HipExecutor() override {
+        for (auto& kv : live_) hipEventDestroy(kv.second);
+        for (hipEvent_t e : spare_) hipEventDestroy(e);
+    }
+
+    int input_start(serving::Tile& t, uint64_t* h) override {
+        const void* src = t.hin_pool ? static_cast<const void*>(host_base + t.hin_off)
+                                     : static_cast<const void*>(t.hin_vec.data());
+        hipError_t e = hipMemcpyAsync(dev_base + t.dev_off, src, (size_t)t.P * t.M * 4, hipMemcpyHostToDevice, h2d);
+        if (e != hipSuccess) return fail(e);
+        return record(h2d, h);
+    }
+
+    int launch(const std::vector<serving::Chunk>& chunks, uint64_t* h) override {
+        // the solve waits for the input copies still in flight
+        std::vector<uint64_t> waited;
+        for (const auto& c : chunks) {
+            const serving::Tile* t = c.tile;
+            if (t->in_done || !t->ev_in) continue;
+            if (std::find(waited.begin(), waited.end(), t->ev_in) != waited.end()) continue;
+            waited.push_back(t->ev_in);
+            hipError_t e = hipStreamWaitEvent(compute, live_.at(t->ev_in), 0);
+            if (e != hipSuccess) return fail(e);
+        }
+        char* thost = table_host[flip];
+        char* tdev = table_dev + (size_t)flip * table_bytes;
+        flip ^= 1;
+        size_t off = 0;
+        size_t i = 0;
+        while (i < chunks.size()) {
+            // one parameter class: chunks[i, j)
+            size_t j = i + 1;
+            while (j < chunks.size() && chunks[j].tile->prm.same_launch(chunks[i].tile->prm)) ++j;
+            const serving::TileParams& prm = chunks[i].tile->prm;
+            std::vector<GreedyTileItem> items;
+            items.reserve(j - i);
+            for (size_t k = i; k < j; ++k) {
+                const serving::Tile* t = chunks[k].tile;
+                const Dict& d = (*dicts)[t->dict];
+                char* blk = dev_base + t->dev_off;
+                GreedyTileItem it{};
+                it.A = d.A;
+                it.dict = d.AT;
+                it.Y = reinterpret_cast<const float*>(blk);
+                it.X = reinterpret_cast<float*>(blk + t->dev_x());
+                it.support = reinterpret_cast<int32_t*>(blk + t->dev_s());
+                it.stats = reinterpret_cast<csrec_pixel_stats*>(blk + t->dev_st());
+                it.G32 = d.G32;
+                it.G64 = d.G64;
+                it.M = d.M;
+                it.N = d.N;
+                it.max_iter = t->prm.max_iter;
+                it.p0 = chunks[k].p0;
+                it.np = chunks[k].np;
+                items.push_back(it);
+            }
+            GreedyLaunch pm = proto;
+            pm.prune = prm.prune;
+            pm.prec = prm.prec;
+            pm.res_tol = prm.res_tol;
+            pm.eps = prm.eps;
+            pm.pivot_fallback = prm.pivot_fallback;
+            const int e = greedy_group_launch(pm, items.data(), (int)items.size(), batch_pixels, ws, thost + off,
+                                              tdev + off, compute);
+            if (e) return e;
+            off += align_up(greedy_group_table_bytes((int)items.size()), 256);
+            i = j;
+        }
+        return record(compute, h);
+    }
+
+    int output_start(serving::Tile& t, uint64_t* h) override {
+        char* dst = t.hout_pool ? host_base + t.hout_off : t.hout_vec.data();
+        const char* blk = dev_base + t.dev_off;
+        hipError_t e = hipMemcpyAsync(dst, blk + t.dev_x(), (size_t)t.P * t.N * 4, hipMemcpyDeviceToHost, d2h);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dst + t.out_s(), blk + t.dev_s(), (size_t)t.P * t.prm.K * 4, hipMemcpyDeviceToHost,
+                               d2h);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dst + t.out_st(), blk + t.dev_st(), (size_t)t.P * sizeof(csrec_pixel_stats),
+                               hipMemcpyDeviceToHost, d2h);
+        if (e != hipSuccess) return fail(e);
+        return record(d2h, h);
+    }
+
+    int query(uint64_t h) override {
+        auto it = live_.find(h);
+        if (it == live_.end()) return CSREC_E_INVAL;
+        const hipError_t q = hipEventQuery(it->second);
+        if (q == hipSuccess) return 0;
+        if (q == hipErrorNotReady) return 1;
+        return fail(q);
+    }
+
+    void forget(uint64_t h) override {
+        auto it = live_.find(h);
+        if (it == live_.end()) return;
+        spare_.push_back(it->second);
+        live_.erase(it);
+    }
+
+    char* host_ptr(size_t off) override { return host_base + off; }
+
+    void wait_idle() override {
+        hipStreamSynchronize(h2d);
+        hipStreamSynchronize(compute);
+        hipStreamSynchronize(d2h);
+    }
+
+   private:
+    static int fail(hipError_t e) {
+        set_hip_error(e);
+        return CSREC_E_DEVICE;
+    }
+    int record(hipStream_t s, uint64_t* h) {
+        hipEvent_t ev = nullptr;
+        if (!spare_.empty()) {
+            ev = spare_.back();
+            spare_.pop_back();
+        } else {
+            hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) return fail(e);
+        }
+        hipError_t e = hipEventRecord(ev, s);
+        if (e != hipSuccess) {
+            spare_.push_back(ev);
+            return fail(e);
+        }
+        *h = next_++;
+        live_[*h] = ev;
+        return CSREC_OK;
+    }
+    std::map<uint64_t, hipEvent_t> live_;
+    std::vector<hipEvent_t> spare_;
+    uint64_t next_ = 1;
+};
 
 // Pinned host staging: the device budget, at least 64 MiB and at most 4 GiB.
 size_t host_pool_bytes(size_t hbm_budget) {
@@ -156,327 +207,140 @@ size_t host_pool_bytes(size_t hbm_budget) {
     return hbm_budget < lo ? lo : (hbm_budget > hi ? hi : hbm_budget);
 }
 
+int check_gomp_params(const csrec_gomp_params& g) {
+    if (g.struct_size != (int32_t)sizeof(csrec_gomp_params)) return CSREC_E_INVAL;
+    if (g.K < 1 || g.S < 1 || g.S > 8 || g.max_iter < 0) return CSREC_E_INVAL;
+    if (g.prune != CSREC_PRUNE_EACH && g.prune != CSREC_PRUNE_FINAL) return CSREC_E_INVAL;
+    if (!(g.res_tol >= 0) || !(g.eps >= 0) || !(g.pivot_fallback >= 0)) return CSREC_E_INVAL;
+    if (g.prec != CSREC_PREC_F32 && g.prec != CSREC_PREC_BF16 && g.prec != CSREC_PREC_F16) return CSREC_E_INVAL;
+    if (g.prec != CSREC_PREC_F32) return CSREC_E_UNSUPPORTED;
+    return CSREC_OK;
+}
+
 }  // namespace
 }  // namespace csrec
 
 struct csrec_server {
     csrec_server_cfg cfg{};
-    std::chrono::steady_clock::time_point t0;
-    hipStream_t compute = nullptr, h2d = nullptr, d2h = nullptr;
-    char* pool_mem = nullptr;
-    char* host_mem = nullptr;             // pinned staging for inputs and results
-    csrec::Pool hpool;
-    char* ws = nullptr;
-    size_t ws_bytes = 0;
-    void* table_dev = nullptr;
-    void* table_host[2] = {nullptr, nullptr};
-    int table_flip = 0;
-    int max_items = 0;
-    csrec::Pool pool;
-    std::vector<csrec::Dict> dicts;
-    csrec::GreedyLaunch proto{};          // maximal shape of the batch workspace layout
-    std::mutex mu;
-    std::condition_variable cv;
-    std::deque<std::unique_ptr<csrec::Tile>> pending;
-    std::vector<std::unique_ptr<csrec::Tile>> admitted;  // on the device, chunks being solved
-    std::deque<std::unique_ptr<csrec::Tile>> computed;   // solved, waiting for host result memory
-    std::vector<std::unique_ptr<csrec::Tile>> copying;   // result copy in flight
-    std::deque<std::unique_ptr<csrec::Tile>> finished;   // not yet polled
-    std::map<uint64_t, std::unique_ptr<csrec::Tile>> polled;
-    std::deque<csrec::Batch> inflight;
-    std::thread th;
-    bool stop = false;
-    int error = CSREC_OK;
-    int64_t outstanding = 0;
+    csrec::HipExecutor ex;
+    std::unique_ptr<csrec::serving::Scheduler> sch;
+    std::array<csrec::Dict, csrec::kMaxDicts> dicts{};
+    std::atomic<int> ndicts{0};
+    std::mutex dict_mu;
+    int imax_cap = 0;                     // largest max_iter the batch workspace is laid out for
 };
 
-namespace csrec {
+using namespace csrec;
+
 namespace {
 
-// Starts the result copy of a solved tile into pinned host memory; false
-// when the host pool is momentarily full (retried on a later step).  A tile
-// whose results could never fit the pool is copied into pageable vectors.
-bool start_output(csrec_server* s, Tile* t) {
-    const Dict& d = s->dicts[t->dict];
-    const int K = s->cfg.gomp.K;
-    const size_t bytes = result_bytes(d, t->P, K);
-    char* h = s->hpool.alloc(bytes);
-    if (!h && bytes <= s->hpool.capacity()) return false;
-    if (h) {
-        t->hout = h;
-        t->X = reinterpret_cast<float*>(h);
-        t->S = reinterpret_cast<int32_t*>(h + align_up((size_t)t->P * d.N * 4, 256));
-        t->St = reinterpret_cast<csrec_pixel_stats*>(reinterpret_cast<char*>(t->S) + align_up((size_t)t->P * K * 4, 256));
-    } else {
-        t->Xv.resize((size_t)t->P * d.N);
-        t->Sv.resize((size_t)t->P * K);
-        t->Stv.resize((size_t)t->P);
-        t->X = t->Xv.data();
-        t->S = t->Sv.data();
-        t->St = t->Stv.data();
-    }
-    hipError_t e = hipEventCreateWithFlags(&t->ev_out, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipMemcpyAsync(t->X, t->dX, (size_t)t->P * d.N * 4, hipMemcpyDeviceToHost, s->d2h);
-    if (e == hipSuccess) e = hipMemcpyAsync(t->S, t->dS, (size_t)t->P * K * 4, hipMemcpyDeviceToHost, s->d2h);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(t->St, t->dSt, (size_t)t->P * sizeof(csrec_pixel_stats), hipMemcpyDeviceToHost, s->d2h);
-    if (e == hipSuccess) e = hipEventRecord(t->ev_out, s->d2h);
-    if (e != hipSuccess) {
-        set_hip_error(e);
-        s->error = CSREC_E_DEVICE;
-        t->status = CSREC_E_DEVICE;
-    }
-    return true;
-}
-
-// One scheduler step under the lock; returns true when it did something.
-bool schedule_once(csrec_server* s) {
-    bool worked = false;
-    // ---- retire finished batches (oldest first)
-    while (!s->inflight.empty()) {
-        Batch& b = s->inflight.front();
-        const hipError_t q = hipEventQuery(b.ev);
-        if (q == hipErrorNotReady) break;
-        if (q != hipSuccess) {
-            set_hip_error(q);
-            s->error = CSREC_E_DEVICE;
-        }
-        for (auto& pr : b.parts) pr.first->done += pr.second;
-        hipEventDestroy(b.ev);
-        s->inflight.pop_front();
-        worked = true;
-    }
-    // ---- solved tiles leave the admitted set in order of admission
-    for (auto it = s->admitted.begin(); it != s->admitted.end();) {
-        if ((*it)->done == (*it)->P) {
-            s->computed.push_back(std::move(*it));
-            it = s->admitted.erase(it);
-            worked = true;
-        } else {
-            ++it;
-        }
-    }
-    while (!s->computed.empty() && start_output(s, s->computed.front().get())) {
-        s->copying.push_back(std::move(s->computed.front()));
-        s->computed.pop_front();
-        worked = true;
-    }
-    // ---- result copies that completed
-    for (auto it = s->copying.begin(); it != s->copying.end();) {
-        Tile* t = it->get();
-        const hipError_t q = hipEventQuery(t->ev_out);
-        if (q == hipErrorNotReady) {
-            ++it;
-            continue;
-        }
-        if (q != hipSuccess) {
-            set_hip_error(q);
-            s->error = CSREC_E_DEVICE;
-            t->status = CSREC_E_DEVICE;
-        }
-        t->t_done = now_since(s->t0);
-        s->pool.release(t->mem);
-        t->mem = nullptr;
-        if (t->hin) s->hpool.release(t->hin);
-        t->hin = nullptr;
-        std::vector<float>().swap(t->Yv);
-        --s->outstanding;
-        s->finished.push_back(std::move(*it));
-        it = s->copying.erase(it);
-        worked = true;
-    }
-    // ---- admission in arrival order
-    while (!s->pending.empty()) {
-        Tile* t = s->pending.front().get();
-        const Dict& d = s->dicts[t->dict];
-        const size_t need = tile_bytes(d, t->P, s->cfg.gomp.K);
-        char* m = s->pool.alloc(need);
-        if (!m) break;
-        t->mem = m;
-        t->dY = reinterpret_cast<float*>(m);
-        t->dX = reinterpret_cast<float*>(m + align_up((size_t)t->P * d.M * 4, 256));
-        t->dS = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(t->dX) + align_up((size_t)t->P * d.N * 4, 256));
-        t->dSt = reinterpret_cast<csrec_pixel_stats*>(reinterpret_cast<char*>(t->dS) +
-                                                      align_up((size_t)t->P * s->cfg.gomp.K * 4, 256));
-        const void* src = t->hin ? static_cast<const void*>(t->hin) : static_cast<const void*>(t->Yv.data());
-        hipError_t e = hipEventCreateWithFlags(&t->ev_in, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMemcpyAsync(t->dY, src, (size_t)t->P * d.M * 4, hipMemcpyHostToDevice, s->h2d);
-        if (e == hipSuccess) e = hipEventRecord(t->ev_in, s->h2d);
-        if (e != hipSuccess) {
-            set_hip_error(e);
-            s->error = CSREC_E_DEVICE;
-        }
-        t->t_admit = now_since(s->t0);
-        s->admitted.push_back(std::move(s->pending.front()));
-        s->pending.pop_front();
-        worked = true;
-    }
-    // ---- issue a batch
-    if (s->inflight.size() < 2) {
-        std::vector<GreedyTileItem> items;
-        Batch b;
-        int64_t room = s->cfg.batch_pixels;
-        for (auto& up : s->admitted) {
-            Tile* t = up.get();
-            while (t->issued < t->P && room > 0 && (int)items.size() < s->max_items) {
-                const int64_t np = std::min({t->P - t->issued, s->cfg.chunk_pixels, room});
-                const Dict& d = s->dicts[t->dict];
-                GreedyTileItem it{};
-                it.A = d.A;
-                it.dict = d.AT;
-                it.Y = t->dY;
-                it.X = t->dX;
-                it.support = t->dS;
-                it.stats = t->dSt;
-                it.G32 = d.G32;
-                it.G64 = d.G64;
-                it.M = d.M;
-                it.N = d.N;
-                it.max_iter = d.imax;
-                it.p0 = t->issued;
-                it.np = np;
-                items.push_back(it);
-                b.parts.push_back({t, np});
-                t->issued += np;
-                room -= np;
-            }
-            if (room <= 0 || (int)items.size() >= s->max_items) break;
-        }
-        if (!items.empty()) {
-            hipError_t he = hipSuccess;
-            for (auto& pr : b.parts) {
-                Tile* t = pr.first;
-                if (!t->in_waited && he == hipSuccess) {
-                    he = hipStreamWaitEvent(s->compute, t->ev_in, 0);
-                    t->in_waited = true;
-                }
-            }
-            int e = greedy_group_launch(s->proto, items.data(), (int)items.size(), s->cfg.batch_pixels, s->ws,
-                                        s->table_host[s->table_flip], s->table_dev, s->compute);
-            s->table_flip ^= 1;
-            if (he == hipSuccess) he = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
-            if (he == hipSuccess) he = hipEventRecord(b.ev, s->compute);
-            if (e != CSREC_OK || he != hipSuccess) {
-                if (he != hipSuccess) set_hip_error(he);
-                s->error = e != CSREC_OK ? e : CSREC_E_DEVICE;
-            }
-            s->inflight.push_back(std::move(b));
-            worked = true;
-        }
-    }
-    return worked;
-}
-
-// Releases a tile's host and device resources (lock held).
-void drop_tile(csrec_server* s, Tile* t) {
-    if (t->mem) s->pool.release(t->mem);
-    if (t->hin) s->hpool.release(t->hin);
-    if (t->hout) s->hpool.release(t->hout);
-    if (t->ev_in) hipEventDestroy(t->ev_in);
-    if (t->ev_out) hipEventDestroy(t->ev_out);
-    t->mem = t->hin = t->hout = nullptr;
-    t->ev_in = t->ev_out = nullptr;
-}
-
-void scheduler(csrec_server* s) {
+// Frees everything the server holds (any subset may be allocated).
+void server_free(csrec_server* s) {
+    if (!s) return;
+    if (s->sch) s->sch->shutdown();
+    s->sch.reset();
     hipSetDevice(s->cfg.device);
-    std::unique_lock<std::mutex> lk(s->mu);
-    while (true) {
-        if (s->stop && s->pending.empty() && s->admitted.empty() && s->computed.empty() && s->copying.empty() &&
-            s->inflight.empty())
-            break;
-        if (s->error != CSREC_OK && s->inflight.empty()) {
-            // fail every queued tile and stop issuing work
-            for (auto& t : s->pending) {
-                t->status = s->error;
-                --s->outstanding;
-                s->finished.push_back(std::move(t));
-            }
-            s->pending.clear();
-            hipStreamSynchronize(s->h2d);
-            hipStreamSynchronize(s->d2h);
-            for (auto* lst : {&s->admitted, &s->copying}) {
-                for (auto& t : *lst) {
-                    t->status = s->error;
-                    if (t->mem) s->pool.release(t->mem);
-                    t->mem = nullptr;
-                    --s->outstanding;
-                    s->finished.push_back(std::move(t));
-                }
-                lst->clear();
-            }
-            for (auto& t : s->computed) {
-                t->status = s->error;
-                if (t->mem) s->pool.release(t->mem);
-                t->mem = nullptr;
-                --s->outstanding;
-                s->finished.push_back(std::move(t));
-            }
-            s->computed.clear();
-            s->cv.notify_all();
-            if (s->stop) break;
-            s->cv.wait_for(lk, std::chrono::milliseconds(1));
-            continue;
-        }
-        const bool worked = schedule_once(s);
-        if (worked) s->cv.notify_all();
-        if (!worked) s->cv.wait_for(lk, std::chrono::microseconds(50));
-    }
-    s->cv.notify_all();
+    for (auto& d : s->dicts) free_dict(d);
+    HipExecutor& x = s->ex;
+    if (x.dev_base) hipFree(x.dev_base);
+    if (x.ws) hipFree(x.ws);
+    if (x.table_dev) hipFree(x.table_dev);
+    if (x.table_host[0]) hipHostFree(x.table_host[0]);
+    if (x.table_host[1]) hipHostFree(x.table_host[1]);
+    if (x.host_base) hipHostFree(x.host_base);
+    if (x.compute) hipStreamDestroy(x.compute);
+    if (x.h2d) hipStreamDestroy(x.h2d);
+    if (x.d2h) hipStreamDestroy(x.d2h);
+    delete s;
+}
+
+// The server's parameters with a tile's overrides, checked against the
+// batch workspace: K and S must be the server's; max_iter may be smaller;
+// an FP64 fallback needs a server created with one.
+int resolve_params(const csrec_server* s, const csrec::Dict& d, const csrec_gomp_params* q,
+                   serving::TileParams* out) {
+    const csrec_gomp_params& g = q ? *q : s->cfg.gomp;
+    int e = check_gomp_params(g);
+    if (e) return e;
+    if (g.K != s->cfg.gomp.K || g.S != s->cfg.gomp.S) return CSREC_E_UNSUPPORTED;
+    if (g.pivot_fallback > 0 && !(s->cfg.gomp.pivot_fallback > 0)) return CSREC_E_UNSUPPORTED;
+    const int imax = g.max_iter > 0 ? g.max_iter : std::min(g.K, d.M / g.S);
+    if (imax < 1 || g.S * imax > d.M || imax > s->imax_cap) return CSREC_E_SHAPE;
+    if (gomp_coop_supported(d.M, d.N, g.K, g.S, imax) != CSREC_OK) return CSREC_E_UNSUPPORTED;
+    out->K = g.K;
+    out->S = g.S;
+    out->max_iter = imax;
+    out->prune = g.prune;
+    out->prec = g.prec;
+    out->res_tol = (float)g.res_tol;
+    out->eps = (float)g.eps;
+    out->pivot_fallback = g.pivot_fallback;
+    return CSREC_OK;
 }
 
 }  // namespace
-}  // namespace csrec
-
-using namespace csrec;
 
 extern "C" {
 
 int32_t csrec_server_create(const csrec_server_cfg* cfg, csrec_server** out) {
     if (!cfg || !out || cfg->struct_size != (int32_t)sizeof(csrec_server_cfg)) return CSREC_E_INVAL;
     const csrec_gomp_params& g = cfg->gomp;
-    if (g.struct_size != (int32_t)sizeof(csrec_gomp_params) || g.K < 1 || g.S < 1 || g.S > 8 || g.max_iter < 0 ||
-        g.prec != CSREC_PREC_F32 || (g.prune != CSREC_PRUNE_EACH && g.prune != CSREC_PRUNE_FINAL) ||
-        !(g.res_tol >= 0) || !(g.eps >= 0) || !(g.pivot_fallback >= 0))
-        return g.prec != CSREC_PREC_F32 ? CSREC_E_UNSUPPORTED : CSREC_E_INVAL;
+    int e = check_gomp_params(g);
+    if (e) return e;
     if (cfg->hbm_budget_bytes < 4096 || cfg->batch_pixels < 256 || cfg->chunk_pixels < 1) return CSREC_E_INVAL;
-    std::unique_ptr<csrec_server> s(new csrec_server());
+    const int imax = g.max_iter > 0 ? g.max_iter : std::min(g.K, 96 / g.S);
+    if (g.S * imax > GOMP_CMAX || g.K > GOMP_CMAX) return CSREC_E_SHAPE;
+    csrec_server* s = new csrec_server();
     s->cfg = *cfg;
-    s->t0 = std::chrono::steady_clock::now();
-    CSREC_HIP_TRY(hipSetDevice(cfg->device));
+    s->imax_cap = imax;
+    HipExecutor& x = s->ex;
+    x.dicts = &s->dicts;
+    x.batch_pixels = cfg->batch_pixels;
     // the batch workspace is laid out for the largest shape a dictionary may have
-    GreedyLaunch& p = s->proto;
+    GreedyLaunch& p = x.proto;
     p.kind = GREEDY_GOMP;
     p.M = 96;
     p.N = CSREC_MAX_N;
     p.K = g.K;
     p.S = g.S;
-    p.max_iter = g.max_iter > 0 ? g.max_iter : std::min(g.K, 96 / g.S);
-    if (g.S * p.max_iter > GOMP_CMAX || g.K > GOMP_CMAX) return CSREC_E_SHAPE;
+    p.max_iter = imax;
     p.prune = g.prune;
     p.prec = g.prec;
     p.res_tol = (float)g.res_tol;
     p.eps = (float)g.eps;
     p.pivot_fallback = g.pivot_fallback;
-    s->ws_bytes = greedy_group_workspace(p, cfg->batch_pixels);
-    s->max_items = (int)std::min<int64_t>(4096, cfg->batch_pixels);
-    CSREC_HIP_TRY(hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking));
-    CSREC_HIP_TRY(hipStreamCreateWithFlags(&s->h2d, hipStreamNonBlocking));
-    CSREC_HIP_TRY(hipStreamCreateWithFlags(&s->d2h, hipStreamNonBlocking));
-    CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&s->pool_mem), cfg->hbm_budget_bytes));
+    const size_t ws_bytes = greedy_group_workspace(p, cfg->batch_pixels);
+    const int max_items = (int)std::min<int64_t>(4096, cfg->batch_pixels);
+    // every parameter class of a batch takes its own slice of the table
+    x.table_bytes = align_up(greedy_group_table_bytes(max_items), 256) + (size_t)max_items * 2048;
     const size_t hb = host_pool_bytes(cfg->hbm_budget_bytes);
-    CSREC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&s->host_mem), hb, hipHostMallocDefault));
-    s->hpool.init(s->host_mem, hb);
-    CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&s->ws), s->ws_bytes));
-    const size_t tb = align_up((size_t)s->max_items * greedy_group_item_bytes(), 256) +
-                      (size_t)s->max_items * gomp_coop_item_bytes();
-    CSREC_HIP_TRY(hipMalloc(&s->table_dev, tb));
-    CSREC_HIP_TRY(hipHostMalloc(&s->table_host[0], tb, hipHostMallocDefault));
-    CSREC_HIP_TRY(hipHostMalloc(&s->table_host[1], tb, hipHostMallocDefault));
-    s->pool.init(s->pool_mem, cfg->hbm_budget_bytes);
-    csrec_server* raw = s.release();
-    raw->th = std::thread(scheduler, raw);
-    *out = raw;
+    hipError_t he = hipSetDevice(cfg->device);
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&x.compute, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&x.h2d, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&x.d2h, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipMalloc(reinterpret_cast<void**>(&x.dev_base), cfg->hbm_budget_bytes);
+    if (he == hipSuccess) he = hipHostMalloc(reinterpret_cast<void**>(&x.host_base), hb, hipHostMallocDefault);
+    if (he == hipSuccess) he = hipMalloc(reinterpret_cast<void**>(&x.ws), ws_bytes);
+    if (he == hipSuccess) he = hipMalloc(reinterpret_cast<void**>(&x.table_dev), 2 * x.table_bytes);
+    if (he == hipSuccess)
+        he = hipHostMalloc(reinterpret_cast<void**>(&x.table_host[0]), x.table_bytes, hipHostMallocDefault);
+    if (he == hipSuccess)
+        he = hipHostMalloc(reinterpret_cast<void**>(&x.table_host[1]), x.table_bytes, hipHostMallocDefault);
+    if (he != hipSuccess) {
+        set_hip_error(he);
+        server_free(s);
+        return CSREC_E_DEVICE;
+    }
+    serving::Config sc;
+    sc.dev_bytes = cfg->hbm_budget_bytes;
+    sc.host_bytes = hb;
+    sc.batch_pixels = cfg->batch_pixels;
+    sc.chunk_pixels = cfg->chunk_pixels;
+    sc.max_items = max_items;
+    sc.max_inflight = 2;
+    s->sch.reset(new serving::Scheduler(sc, &s->ex));
+    s->sch->start();
+    *out = s;
     return CSREC_OK;
 }
 
@@ -485,145 +349,110 @@ int32_t csrec_server_add_dict(csrec_server* s, const float* A_host, int32_t M, i
     if (M < 1 || M >= N || N > CSREC_MAX_N) return CSREC_E_SHAPE;
     if (M > 96) return CSREC_E_UNSUPPORTED;
     const csrec_gomp_params& g = s->cfg.gomp;
+    const int imax = g.max_iter > 0 ? g.max_iter : std::min(g.K, M / g.S);
+    if (imax < 1 || g.S * imax > M || imax > s->imax_cap) return CSREC_E_SHAPE;
+    if (gomp_coop_supported(M, N, g.K, g.S, imax) != CSREC_OK) return CSREC_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(s->dict_mu);
+    const int id = s->ndicts.load(std::memory_order_relaxed);
+    if (id >= kMaxDicts) return CSREC_E_INVAL;
     Dict d;
     d.M = M;
     d.N = N;
-    d.imax = g.max_iter > 0 ? g.max_iter : std::min(g.K, M / g.S);
-    if (d.imax < 1 || g.S * d.imax > M || d.imax > s->proto.max_iter) return CSREC_E_SHAPE;
-    if (gomp_coop_supported(M, N, g.K, g.S, d.imax) != CSREC_OK) return CSREC_E_UNSUPPORTED;
-    CSREC_HIP_TRY(hipSetDevice(s->cfg.device));
-    CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d.A), (size_t)M * N * 4));
-    CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d.G32), (size_t)N * N * 4));
-    CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d.AT), gomp_coop_dict_floats(M, N) * 4));
-    if (g.pivot_fallback > 0) CSREC_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d.G64), (size_t)N * N * 8));
     hipStream_t st = nullptr;
-    CSREC_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    hipError_t e = hipMemcpyAsync(d.A, A_host, (size_t)M * N * 4, hipMemcpyHostToDevice, st);
-    int rc = (e == hipSuccess) ? greedy_gram(d.A, M, N, d.G32, d.G64, st) : CSREC_E_DEVICE;
-    if (rc == CSREC_OK) gomp_coop_prepare(d.A, M, N, d.AT, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    hipStreamDestroy(st);
-    if (e != hipSuccess) {
-        set_hip_error(e);
-        return CSREC_E_DEVICE;
+    hipError_t e = hipSetDevice(s->cfg.device);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d.A), (size_t)M * N * 4);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d.G32), (size_t)N * N * 4);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d.AT), gomp_coop_dict_floats(M, N) * 4);
+    if (e == hipSuccess && g.pivot_fallback > 0) e = hipMalloc(reinterpret_cast<void**>(&d.G64), (size_t)N * N * 8);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.A, A_host, (size_t)M * N * 4, hipMemcpyHostToDevice, st);
+    int rc = CSREC_OK;
+    if (e == hipSuccess) rc = greedy_gram(d.A, M, N, d.G32, d.G64, st);
+    if (e == hipSuccess && rc == CSREC_OK) {
+        gomp_coop_prepare(d.A, M, N, d.AT, st);
+        e = hipGetLastError();
     }
-    if (rc) return rc;
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->dicts.push_back(d);
-    *dict_id = (int32_t)s->dicts.size() - 1;
+    if (st) {
+        const hipError_t e2 = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = e2;
+        hipStreamDestroy(st);
+    }
+    if (e != hipSuccess || rc != CSREC_OK) {
+        if (e != hipSuccess) set_hip_error(e);
+        free_dict(d);
+        return e != hipSuccess ? CSREC_E_DEVICE : rc;
+    }
+    s->dicts[id] = d;
+    s->ndicts.store(id + 1, std::memory_order_release);
+    *dict_id = id;
     return CSREC_OK;
 }
 
-int32_t csrec_server_submit(csrec_server* s, int32_t dict_id, const float* Y_host, int64_t P, uint64_t tag) {
+int32_t csrec_server_submit(csrec_server* s, int32_t dict_id, const float* Y_host, int64_t P,
+                            const csrec_gomp_params* params, uint64_t tag) {
     if (!s || (P > 0 && !Y_host) || P < 0) return CSREC_E_INVAL;
-    std::unique_ptr<Tile> t(new Tile());
-    t->t_submit = now_since(s->t0);
-    int M = 0;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (dict_id < 0 || dict_id >= (int32_t)s->dicts.size()) return CSREC_E_INVAL;
-        if (s->error) return s->error;
-        const Dict& d = s->dicts[dict_id];
-        if (tile_bytes(d, P, s->cfg.gomp.K) > s->pool.capacity()) return CSREC_E_BUDGET;
-        if (P > s->cfg.batch_pixels * 4096) return CSREC_E_BUDGET;
-        M = d.M;
-        if (P > 0) t->hin = s->hpool.alloc((size_t)P * M * 4);
-    }
-    // copied outside the lock
-    if (t->hin)
-        std::memcpy(t->hin, Y_host, (size_t)P * M * 4);
-    else
-        t->Yv.assign(Y_host, Y_host + (size_t)P * M);
-    t->tag = tag;
-    t->dict = dict_id;
-    t->P = P;
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (P == 0) {
-        t->t_admit = t->t_done = t->t_submit;
-        s->finished.push_back(std::move(t));
-    } else {
-        ++s->outstanding;
-        s->pending.push_back(std::move(t));
-    }
-    s->cv.notify_all();
-    return CSREC_OK;
+    if (dict_id < 0 || dict_id >= s->ndicts.load(std::memory_order_acquire)) return CSREC_E_INVAL;
+    const Dict& d = s->dicts[dict_id];
+    serving::TileParams prm;
+    const int e = resolve_params(s, d, params, &prm);
+    if (e) return e;
+    return s->sch->submit(dict_id, d.M, d.N, prm, Y_host, P, tag);
 }
 
 int32_t csrec_server_poll(csrec_server* s, csrec_result* out, int32_t max, int32_t* n) {
     if (!s || !n || (max > 0 && !out)) return CSREC_E_INVAL;
-    std::lock_guard<std::mutex> lk(s->mu);
-    int32_t k = 0;
-    while (k < max && !s->finished.empty()) {
-        std::unique_ptr<Tile> t = std::move(s->finished.front());
-        s->finished.pop_front();
-        const Dict& d = s->dicts[t->dict];
-        csrec_result& r = out[k++];
+    std::vector<const serving::Tile*> got;
+    s->sch->poll(got, max);
+    for (size_t k = 0; k < got.size(); ++k) {
+        const serving::Tile* t = got[k];
+        csrec_result& r = out[k];
         r.tag = t->tag;
         r.status = t->status;
         r.dict_id = t->dict;
         r.P = t->P;
-        r.N = d.N;
-        r.K = s->cfg.gomp.K;
-        r.X = t->X;
-        r.support = t->S;
-        r.stats = t->St;
+        r.N = t->N;
+        r.K = t->prm.K;
+        char* base = t->status == CSREC_OK ? s->sch->results(t) : nullptr;
+        r.X = base ? reinterpret_cast<const float*>(base) : nullptr;
+        r.support = base ? reinterpret_cast<const int32_t*>(base + t->out_s()) : nullptr;
+        r.stats = base ? reinterpret_cast<const csrec_pixel_stats*>(base + t->out_st()) : nullptr;
         r.t_submit = t->t_submit;
         r.t_admit = t->t_admit;
         r.t_done = t->t_done;
-        s->polled[t->tag] = std::move(t);
     }
-    *n = k;
+    *n = (int32_t)got.size();
     return CSREC_OK;
 }
 
 int32_t csrec_server_release(csrec_server* s, uint64_t tag) {
     if (!s) return CSREC_E_INVAL;
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->polled.find(tag);
-    if (it != s->polled.end()) {
-        drop_tile(s, it->second.get());
-        s->polled.erase(it);
-    }
-    return CSREC_OK;
+    return s->sch->release(tag);
 }
 
 int32_t csrec_server_drain(csrec_server* s) {
     if (!s) return CSREC_E_INVAL;
-    std::unique_lock<std::mutex> lk(s->mu);
-    s->cv.wait(lk, [s] { return s->outstanding == 0; });
-    return s->error;
+    return s->sch->drain();
+}
+
+int32_t csrec_server_get_stats(csrec_server* s, csrec_server_stats* out) {
+    if (!s || !out || out->struct_size != (int32_t)sizeof(csrec_server_stats)) return CSREC_E_INVAL;
+    const serving::Counters c = s->sch->counters();
+    out->tiles_submitted = c.tiles_submitted;
+    out->tiles_finished = c.tiles_finished;
+    out->batches = c.batches;
+    out->pixels_launched = c.pixels_launched;
+    out->host_in_pageable = c.host_in_pageable;
+    out->host_out_pageable = c.host_out_pageable;
+    out->elapsed_s = c.elapsed_s;
+    out->busy_s = c.busy_s;
+    out->mean_pixels_in_flight = c.elapsed_s > 0 ? c.slot_px_s / c.elapsed_s : 0.0;
+    out->mean_pool_bytes = c.elapsed_s > 0 ? c.pool_bytes_s / c.elapsed_s : 0.0;
+    return CSREC_OK;
 }
 
 int32_t csrec_server_destroy(csrec_server* s) {
     if (!s) return CSREC_E_INVAL;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->stop = true;
-        s->cv.notify_all();
-    }
-    if (s->th.joinable()) s->th.join();
-    hipSetDevice(s->cfg.device);
-    hipStreamSynchronize(s->compute);
-    hipStreamSynchronize(s->h2d);
-    hipStreamSynchronize(s->d2h);
-    for (auto& kv : s->polled) drop_tile(s, kv.second.get());
-    for (auto& t : s->finished) drop_tile(s, t.get());
-    for (auto& d : s->dicts) {
-        hipFree(d.A);
-        hipFree(d.AT);
-        hipFree(d.G32);
-        if (d.G64) hipFree(d.G64);
-    }
-    hipFree(s->pool_mem);
-    hipFree(s->ws);
-    hipFree(s->table_dev);
-    hipHostFree(s->table_host[0]);
-    hipHostFree(s->table_host[1]);
-    hipHostFree(s->host_mem);
-    hipStreamDestroy(s->compute);
-    hipStreamDestroy(s->h2d);
-    hipStreamDestroy(s->d2h);
-    delete s;
+    server_free(s);
     return CSREC_OK;
 }
 

@@ -130,3 +130,78 @@ def test_fp64_fallback_through_the_server(torch):
     ok = fb & (ref["sel_gap"] >= GAP) & (ref["prune_gap"] >= GAP)
     assert ok.any()
     assert rel_err_rows(Xs[ok], ref["X"][ok]).max() < 1e-5
+
+
+def test_per_tile_parameters_and_tags(torch):
+    """Tiles with their own res_tol / max_iter / prune share the server with
+    tiles on its defaults; each equals the direct csrec_gomp call with its own
+    parameters.  A tag still in use is refused; a released one is reusable."""
+    import paper_2401_14762_amd as cs
+    tiles, dicts = _tiles(), _dicts()
+    own = {1: dict(res_tol=1e-2), 3: dict(max_iter=12, prune="final"), 4: dict(res_tol=0.0, max_iter=5)}
+    note("serving: per-tile parameters")
+    with cs.Server(K=K, S=S, res_tol=TOL, hbm_budget_bytes=1 << 30, batch_pixels=32768, chunk_pixels=4096) as srv:
+        ids = {N: srv.add_dict(A) for N, A in dicts.items()}
+        for tag, (N, Y) in enumerate(tiles):
+            srv.submit(ids[N], Y, tag, **own.get(tag, {}))
+        with pytest.raises(cs.CsrecError) as ei:
+            srv.submit(ids[tiles[0][0]], tiles[0][1], 0)
+        assert ei.value.code == -1
+        with pytest.raises(cs.CsrecError) as ei:
+            srv.submit(ids[100], tiles[0][1], 99, K=K + 1)
+        assert ei.value.code == -5
+        srv.drain()
+        res = {r["tag"]: r for r in srv.poll(1000)}
+        # polled and released by poll(): tag 0 may be used again
+        srv.submit(ids[tiles[0][0]], tiles[0][1], 0)
+        srv.drain()
+        again = srv.poll(10)
+        st = srv.stats()
+    assert len(again) == 1 and np.array_equal(again[0]["X"], res[0]["X"])
+    for tag, (N, Y) in enumerate(tiles):
+        kw = dict(K=K, S=S, res_tol=TOL)
+        kw.update(own.get(tag, {}))
+        X, Sup, sd = cs.gomp(to_dev(torch, dicts[N]), to_dev(torch, Y), **kw)
+        torch.cuda.synchronize()
+        assert res[tag]["status"] == 0
+        assert np.array_equal(res[tag]["X"], np_of(X)), tag
+        assert np.array_equal(res[tag]["support"], np_of(Sup)), tag
+        assert np.array_equal(res[tag]["iters"], np_of(sd["iters"])), tag
+    assert st["tiles_submitted"] == len(tiles) + 1 and st["tiles_finished"] == len(tiles) + 1
+    assert st["pixels_launched"] == sum(Y.shape[0] for _, Y in tiles) + tiles[0][1].shape[0]
+    assert 0 < st["busy_s"] <= st["elapsed_s"] and st["mean_pixels_in_flight"] > 0
+
+
+def test_results_held_with_a_small_host_pool(torch):
+    """A caller that polls but releases nothing while the pinned staging pool
+    (64 MiB, its minimum, with a 64 MiB device budget) is far smaller than the
+    results: every tile still finishes (results beyond the pool go to
+    pageable memory), and each equals the run with a large pool."""
+    import paper_2401_14762_amd as cs
+    dicts = _dicts()
+    _, a32, _, phi = W.serving_dictionary(224)
+    tiles = []
+    for i in range(10):
+        F = W.mixing_spectra(128 * 128, 224, 40.0, 900 + i)
+        tiles.append((224, (F @ phi.T).astype(np.float32)))
+    note("serving: results held, 64 MiB pinned pool, 10 tiles of 16384 pixels at N=224")
+    got = {}
+    with cs.Server(K=K, S=S, res_tol=TOL, hbm_budget_bytes=64 << 20, batch_pixels=32768,
+                   chunk_pixels=8192) as srv:
+        d = srv.add_dict(dicts[224])
+        for tag, (_, Y) in enumerate(tiles):
+            srv.submit(d, Y, tag)
+        held = []
+        while len(got) < len(tiles):
+            for r in srv.poll_held(16):
+                got[r["tag"]] = r
+                held.append(r["tag"])
+        srv.drain()
+        st = srv.stats()
+        for tag in held:
+            srv.release(tag)
+    assert st["host_out_pageable"] > 0
+    ref = _serve(cs, tiles, dicts, budget=1 << 30)
+    for tag in range(len(tiles)):
+        assert got[tag]["status"] == 0
+        assert np.array_equal(got[tag]["X"], ref[tag]["X"]), tag
