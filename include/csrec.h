@@ -219,6 +219,25 @@ int32_t csrec_cosamp(const csrec_problem* problem, const csrec_cosamp_params* pa
 int32_t csrec_biht(const csrec_problem* problem, const csrec_biht_params* params, float* X,
                    int32_t* support, csrec_pixel_stats* stats);
 
+/* gOMP (Alg. 3) without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The same arguments and results as csrec_gomp
+ * (bit-identical X, support and stats), but problem->workspace is not used:
+ * the Gram matrices, the dictionary copies, the FP64 hand-off flags and the
+ * FP64 redo state live in one fixed scratch array of
+ * CSREC_NOALLOC_SCRATCH_MB MiB in device memory, one per device, held from
+ * the first call on that device until the process ends.  Nothing in it must
+ * start at zero: every call writes what it reads.  Pixels are solved in
+ * chunks of up to 65,536, and the FP64 redo (pivot_fallback > 0) reuses as
+ * many per-pixel state columns as fit.  CSREC_E_WORKSPACE when a shape needs
+ * more than the scratch holds (the Gram matrices and flags, or 64 redo
+ * columns).  All calls on one device share its scratch and keep the last
+ * call's contents: calls that overlap on one device (two streams, two host
+ * threads) race and give undefined results; serialise them. */
+#define CSREC_NOALLOC_SCRATCH_MB 32
+int32_t csrec_gomp_noalloc(const csrec_problem* problem, const csrec_gomp_params* params, float* X,
+                           int32_t* support, csrec_pixel_stats* stats);
+
 /* ADMM (Alg. 2): X (P x N) receives x^I, Z (P x N, nullable) z^I; stats nullable (resid is
  * ||y - A x^I||).  Needs a workspace of csrec_workspace_bytes() (the M x M matrix
  * (alpha I + A A^T)^{-1}, formed on the device in FP64 on every call).  FP32; M <= 96,

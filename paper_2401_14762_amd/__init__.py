@@ -428,6 +428,41 @@ def gomp(A, Y, K: int, S: int = 1, max_iter: int = 0, res_tol: float = 0.0, eps:
                         pivot_fallback=pivot_fallback))
 
 
+def gomp_noalloc(A, Y, K: int, S: int = 1, max_iter: int = 0, res_tol: float = 0.0, eps: float = 0.0,
+                 prune: str = "each", prec: str = "f32", pivot_fallback: float = 0.0, stream=None, out=None):
+    """gOMP through csrec_gomp_noalloc: no workspace, the library's fixed
+    per-device scratch instead (calls on one device must not overlap).
+    out = (X (P x N float32), support (P x K int32), stats (P x 4 int32))
+    receives the results when given, so that the call allocates nothing;
+    otherwise they are allocated here.  Returns (X, support, stats)."""
+    torch = _torch()
+    lib = library()
+    _check_dev("A", A, torch.float32)
+    _check_dev("Y", Y, torch.float32)
+    M, N = A.shape
+    P = Y.shape[0]
+    if Y.shape[1] != M:
+        raise ValueError("Y must be P x M")
+    pb = _problem(A, Y, P, stream)
+    prm, _ = _params("gomp", A, P, dict(K=K, S=S, max_iter=max_iter, res_tol=res_tol, eps=eps, prune=prune,
+                                         prec=prec, pivot_fallback=pivot_fallback))
+    if out is None:
+        X = torch.empty((P, N), dtype=torch.float32, device=A.device)
+        Sp = torch.empty((max(P, 1), K), dtype=torch.int32, device=A.device)
+        st = torch.empty((max(P, 1), 4), dtype=torch.int32, device=A.device)
+    else:
+        X, Sp, st = out
+        if (X.shape[0] < P or X.shape[1] != N or Sp.shape[0] < P or Sp.shape[1] != K or st.shape[0] < P
+                or st.shape[1] != 4 or not (X.is_contiguous() and Sp.is_contiguous() and st.is_contiguous())):
+            raise ValueError("out must be contiguous (P x N float32, P x K int32, P x 4 int32) tensors")
+        _check_dev("X", X, torch.float32)
+        _check_dev("support", Sp, torch.int32)
+        _check_dev("stats", st, torch.int32)
+    _lib.check(lib.csrec_gomp_noalloc(ctypes.byref(pb), ctypes.byref(prm), _ptr(X), _ptr(Sp), _ptr(st)),
+               "csrec_gomp_noalloc")
+    return X[:P], Sp[:P], _stats_view(st[:P])
+
+
 def cosamp(A, Y, K: int, max_iter: int = 30, eps: float = 0.0, res_tol: float = 0.0,
            prec: str = "f32", stream=None):
     """CoSaMP (Alg. 5) on every pixel: returns (X, support, stats)."""

@@ -165,6 +165,8 @@ SIGNATURES = {
     "csrec_fista_hermitian": (ctypes.c_int32, [_P(Problem), _P(FistaParams), ctypes.c_void_p, ctypes.c_void_p]),
     "csrec_gomp": (ctypes.c_int32, [_P(Problem), _P(GompParams), ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p]),
+    "csrec_gomp_noalloc": (ctypes.c_int32, [_P(Problem), _P(GompParams), ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
     "csrec_cosamp": (ctypes.c_int32, [_P(Problem), _P(CosampParams), ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),
     "csrec_biht": (ctypes.c_int32, [_P(Problem), _P(BihtParams), ctypes.c_void_p, ctypes.c_void_p,

@@ -2,6 +2,7 @@
 // dispatch to the kernels.  No device memory is allocated here.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -311,6 +312,69 @@ int32_t csrec_gomp(const csrec_problem* problem, const csrec_gomp_params* params
     if (e) return e;
     fill_problem(problem, l);
     return run_greedy(l, X, support, stats);
+}
+
+}  // extern "C"
+
+// The scratch of csrec_gomp_noalloc: one array per device, kept until the
+// process ends.  In host code its name stands for the symbol, not a device
+// address: every use goes through the address hipGetSymbolAddress returns
+// for the current device, looked up once per device.
+namespace {
+constexpr size_t kNoallocScratchBytes = (size_t)CSREC_NOALLOC_SCRATCH_MB << 20;
+static __device__ __align__(256) char csrec_noalloc_scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (null and *err set on failure).
+char* noalloc_scratch(int* err) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_hip_error(e);
+        *err = CSREC_E_DEVICE;
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = CSREC_E_DEVICE;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(csrec_noalloc_scratch));
+        if (e != hipSuccess || !p) {
+            set_hip_error(e);
+            *err = CSREC_E_DEVICE;
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int32_t csrec_gomp_noalloc(const csrec_problem* problem, const csrec_gomp_params* params, float* X,
+                           int32_t* support, csrec_pixel_stats* stats) {
+    GreedyLaunch l{};
+    int e = fill_gomp(problem, params, l);
+    if (e) return e;
+    fill_problem(problem, l);
+    l.workspace = nullptr;
+    l.workspace_bytes = 0;
+    if (l.P > 0 && !X) return CSREC_E_INVAL;
+    l.X = X;
+    l.support = support;
+    l.stats = stats;
+    if (l.P == 0) return CSREC_OK;
+    if (greedy_gomp_scratch_cols(l, kNoallocScratchBytes) < 0) return CSREC_E_WORKSPACE;
+    char* scr = noalloc_scratch(&e);
+    if (!scr) return e;
+    return greedy_gomp_scratch_launch(l, scr, kNoallocScratchBytes);
 }
 
 int32_t csrec_cosamp(const csrec_problem* problem, const csrec_cosamp_params* params, float* X,

@@ -154,6 +154,10 @@ constexpr int GOMP_CMAX = 96;     // gOMP: largest |c| = S * max_iter
 
 size_t greedy_workspace(const GreedyLaunch& a);
 int greedy_launch(const GreedyLaunch& a);
+// gOMP on a fixed device scratch of cap bytes (a.workspace is not used):
+// FP64 redo columns that fit (-1: the shape does not fit), and the launch
+int64_t greedy_gomp_scratch_cols(const GreedyLaunch& a, size_t cap);
+int greedy_gomp_scratch_launch(const GreedyLaunch& a, char* scratch, size_t cap);
 
 // Grouped gOMP launches over pixel chunks of several tiles (serving).
 struct GreedyTileItem {

@@ -243,27 +243,28 @@ __device__ __forceinline__ int extract_bits(const Col<uint32_t>& bits, int NW, c
     return cnt;
 }
 
-// One workgroup of a solve: pixels p0 + block*blockDim + [0, blockDim) of the
-// problem in g (at most np of them), using scratch columns slot0 + the same
-// offsets.  Shared by the plain launch and the grouped (serving) launch.
-template <int MMAX, int SMAX, typename T>
-__device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t np, int pass, int64_t block,
-                                             int64_t slot0, float* sAT) {
+// A^T into LDS: row n holds column n of A, padded to MMAX + 4 values.
+template <int MMAX>
+__device__ __forceinline__ void load_at(const GArgs& g, float* sAT) {
     constexpr int PAT = MMAX + 4;
-    const int M = g.M, N = g.N, K = g.K;
+    const int M = g.M, N = g.N;
     for (int idx = threadIdx.x; idx < N * PAT; idx += blockDim.x) {
         const int n = idx / PAT;
         const int m = idx - n * PAT;
         sAT[idx] = (m < M) ? g.A[(size_t)m * N + n] : 0.f;
     }
     __syncthreads();
+}
 
-    const int64_t within = block * blockDim.x + threadIdx.x;
-    if (within >= np) return;
-    const int64_t pix = p0 + within;
-    const int64_t local = slot0 + within;   // scratch column
-    if (pass == 1 && g.fbflag[local] == 0u) return;   // FP64 redo only for marked pixels
-    const Scratch<T> s = make_scratch<T>(g, local, MMAX);
+// One pixel: measurements Y[pix], FP64 hand-off flag fbflag[fidx], scratch
+// column col (A^T already in sAT).
+template <int MMAX, int SMAX, typename T>
+__device__ __forceinline__ void greedy_pixel(const GArgs& g, int64_t pix, int64_t fidx, int64_t col, int pass,
+                                             const float* sAT) {
+    constexpr int PAT = MMAX + 4;
+    const int M = g.M, N = g.N, K = g.K;
+    if (pass == 1 && g.fbflag[fidx] == 0u) return;   // FP64 redo only for marked pixels
+    const Scratch<T> s = make_scratch<T>(g, col, MMAX);
     const int NW = (N + 31) / 32;
 
     // ---- measurements
@@ -470,7 +471,7 @@ __device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t
     }
 
     if (pass == 0 && g.fbflag) {
-        g.fbflag[local] = fallback ? 1u : 0u;
+        g.fbflag[fidx] = fallback ? 1u : 0u;
         if (fallback) return;   // the FP64 pass writes this pixel's results
     }
 
@@ -498,10 +499,35 @@ __device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t
     }
 }
 
+// One workgroup of a solve: pixels p0 + block*blockDim + [0, blockDim) of the
+// problem in g (at most np of them), using scratch columns slot0 + the same
+// offsets.  Shared by the plain launch and the grouped (serving) launch.
+template <int MMAX, int SMAX, typename T>
+__device__ __forceinline__ void greedy_block(const GArgs& g, int64_t p0, int64_t np, int pass, int64_t block,
+                                             int64_t slot0, float* sAT) {
+    load_at<MMAX>(g, sAT);
+    const int64_t within = block * blockDim.x + threadIdx.x;
+    if (within >= np) return;
+    greedy_pixel<MMAX, SMAX, T>(g, p0 + within, slot0 + within, slot0 + within, pass, sAT);
+}
+
 template <int MMAX, int SMAX, typename T>
 __global__ __launch_bounds__(256, 2) void greedy_kernel(GArgs g, int64_t p0, int64_t np, int pass) {
     extern __shared__ float sAT[];
     greedy_block<MMAX, SMAX, T>(g, p0, np, pass, blockIdx.x, 0, sAT);
+}
+
+// The FP64 redo over pixels [p0, p0 + np) with g.CH scratch columns: thread
+// c takes the flagged pixels c, c + CH, c + 2 CH, ... one after the other in
+// column c, so a scratch smaller than the chunk serves it.  gridDim.x *
+// blockDim.x == g.CH.
+template <int MMAX, int SMAX, typename T>
+__global__ __launch_bounds__(256, 2) void greedy_redo_strided_kernel(GArgs g, int64_t p0, int64_t np) {
+    extern __shared__ float sAT[];
+    load_at<MMAX>(g, sAT);
+    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t within = col; within < np; within += g.CH)
+        greedy_pixel<MMAX, SMAX, T>(g, p0 + within, within, col, 1, sAT);
 }
 
 // Grouped launch: blocks [items[i].block0, items[i+1].block0) solve item i
@@ -810,6 +836,109 @@ int greedy_launch(const GreedyLaunch& a) {
         if (dbl) {
             hipLaunchKernelGGL(redo, dim3((unsigned)ceil_div(np, threads)), dim3(threads), lds, a.stream, g, p0,
                                np, 1);
+            CSREC_HIP_TRY(hipGetLastError());
+        }
+    }
+    return CSREC_OK;
+}
+
+}  // namespace csrec
+
+namespace csrec {
+
+namespace {
+typedef void (*rk_t)(GArgs, int64_t, int64_t);
+rk_t pick_redo_strided(int M, int S) {
+    if (M <= 48) return S <= 2 ? greedy_redo_strided_kernel<48, 2, double> : greedy_redo_strided_kernel<48, 8, double>;
+    if (M <= 80) return S <= 2 ? greedy_redo_strided_kernel<80, 2, double> : greedy_redo_strided_kernel<80, 8, double>;
+    if (M <= 96) return S <= 2 ? greedy_redo_strided_kernel<96, 2, double> : greedy_redo_strided_kernel<96, 8, double>;
+    return nullptr;
+}
+constexpr int kRedoThreads = 64;   // the strided redo's block; its column count is a multiple of it
+}  // namespace
+
+// Layout of gOMP on a fixed scratch of `cap` bytes: the Gram matrices, the
+// dictionary copies and the FP64 hand-off flags of one chunk as in the
+// workspace layout, then the FP64 redo's per-pixel state for as many
+// columns (multiples of kRedoThreads, at most the chunk) as fit.  Returns
+// the column count, 0 without an FP64 fallback, or -1 when it does not fit.
+int64_t greedy_gomp_scratch_cols(const GreedyLaunch& a, size_t cap) {
+    const Layout L = layout_for(a);
+    const bool dbl = a.pivot_fallback > 0.0;
+    if (L.off_T > cap) return -1;
+    if (!dbl) return 0;
+    const int NW = (a.N + 31) / 32;
+    const int64_t tent = (int64_t)L.CM * (L.CM + 1) / 2 + 3 * (int64_t)L.CM;
+    const int64_t ient = a.N + L.LM + 3 * L.CM + 2 * NW;
+    const int64_t per_col = tent * 8 + ient * 4 + (int64_t)mmax_for(a.M) * 4;
+    const int64_t room = (int64_t)cap - (int64_t)L.off_T - 3 * 256;
+    int64_t cols = room > 0 ? room / per_col : 0;
+    cols = cols / kRedoThreads * kRedoThreads;
+    const int64_t chunk_cols = (L.CH + kRedoThreads - 1) / kRedoThreads * kRedoThreads;
+    if (cols > chunk_cols) cols = chunk_cols;
+    return cols >= kRedoThreads ? cols : -1;
+}
+
+int greedy_gomp_scratch_launch(const GreedyLaunch& a, char* scr, size_t cap) {
+    if (a.P == 0) return CSREC_OK;
+    if (a.M > 96 || a.kind != GREEDY_GOMP) return CSREC_E_UNSUPPORTED;
+    const int64_t cols = greedy_gomp_scratch_cols(a, cap);
+    if (cols < 0) return CSREC_E_WORKSPACE;
+    const Layout L = layout_for(a);
+    const bool dbl = a.pivot_fallback > 0.0;
+    const int NW = (a.N + 31) / 32;
+    const int64_t tent = (int64_t)L.CM * (L.CM + 1) / 2 + 3 * (int64_t)L.CM;
+    const int64_t ient = a.N + L.LM + 3 * L.CM + 2 * NW;
+    GArgs g;
+    g.A = a.A;
+    g.Y = a.Y;
+    g.X = a.X;
+    g.support = a.support;
+    g.stats = a.stats;
+    g.G32 = reinterpret_cast<const float*>(scr + L.gram32);
+    g.G64 = dbl ? reinterpret_cast<const double*>(scr + L.gram64) : nullptr;
+    g.M = a.M;
+    g.N = a.N;
+    g.K = a.K;
+    g.S = a.S;
+    g.Imax = a.max_iter;
+    g.prune = a.prune;
+    g.res_tol = a.res_tol;
+    g.eps = a.eps;
+    g.pivot_thr = a.pivot_fallback;
+    g.scr = scr;
+    g.CH = cols;
+    g.CM = L.CM;
+    g.LM = L.LM;
+    g.off_T = (int64_t)L.off_T;
+    g.off_i = g.off_T + (int64_t)align_up((size_t)(tent * cols * 8), 256);
+    g.off_r = g.off_i + (int64_t)align_up((size_t)(ient * cols * 4), 256);
+    g.fbflag = dbl ? reinterpret_cast<uint32_t*>(scr + L.off_f) : nullptr;
+    if (dbl && (size_t)g.off_r + align_up((size_t)mmax_for(a.M) * cols * 4, 256) > cap) return CSREC_E_WORKSPACE;
+
+    hipLaunchKernelGGL(gram_kernel, dim3(a.N), dim3(256), 0, a.stream, a.A, a.M, a.N,
+                       reinterpret_cast<float*>(scr + L.gram32),
+                       dbl ? reinterpret_cast<double*>(scr + L.gram64) : nullptr);
+    CSREC_HIP_TRY(hipGetLastError());
+    float* dictbuf = reinterpret_cast<float*>(scr + L.off_AT);
+    gomp_coop_prepare(a.A, a.M, a.N, dictbuf, a.stream);
+    CSREC_HIP_TRY(hipGetLastError());
+    const size_t lds = (size_t)a.N * (mmax_for(a.M) + 4) * sizeof(float);
+    const rk_t redo = dbl ? pick_redo_strided(a.M, a.S) : nullptr;
+    if (dbl) {
+        if (!redo) return CSREC_E_UNSUPPORTED;
+        CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(redo),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    for (int64_t p0 = 0; p0 < a.P; p0 += L.CH) {
+        const int64_t np = (a.P - p0) < L.CH ? (a.P - p0) : L.CH;
+        const int e = gomp_coop_launch(a.Y, a.X, a.support, a.stats, g.G32, dictbuf, g.fbflag, a.M, a.N, p0, np,
+                                       a.K, a.S, a.max_iter, a.prune, a.res_tol, a.eps, a.pivot_fallback,
+                                       a.stream);
+        if (e) return e;
+        if (dbl) {
+            hipLaunchKernelGGL(redo, dim3((unsigned)(cols / kRedoThreads)), dim3(kRedoThreads), lds, a.stream, g,
+                               p0, np);
             CSREC_HIP_TRY(hipGetLastError());
         }
     }
