@@ -169,6 +169,19 @@ def leg_precision(torch, cs, W, dev, stream, samples):
     fb = int(((res[2]["flags"] & 4) != 0).sum().item())
     out.update(gomp_ms=ms, gomp_pixels_per_s=P / (ms * 1e-3), gomp_fp64_fallback_pixels=fb)
     gpu["gomp"] = res[0][torch.from_numpy(idx).to(dev)].cpu().numpy()
+    out["gomp_f32_psnr_vs_truth_db"] = psnr_dev(torch, res[0], Psi, F_true)
+    S32 = res[1]
+    # the correlation A^T r on 16-bit MFMA (FP32 accumulation), least squares,
+    # prune and residual in FP32
+    for prec in ("bf16", "f16"):
+        rl, ms = event_timed(torch, stream, lambda: cs.gomp(A, Y, K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL,
+                                                            pivot_fallback=1e-6, prec=prec))
+        out[f"gomp_{prec}_ms"] = ms
+        out[f"gomp_{prec}_pixels_per_s"] = P / (ms * 1e-3)
+        out[f"gomp_{prec}_psnr_vs_truth_db"] = psnr_dev(torch, rl[0], Psi, F_true)
+        out[f"gomp_{prec}_same_support_as_f32"] = float((rl[1] == S32).all(dim=1).float().mean().item())
+        gpu[f"gomp_{prec}"] = rl[0][torch.from_numpy(idx).to(dev)].cpu().numpy()
+        del rl
     samples["precision"] = dict(A=pr.A, Y=pr.Y[idx], L=L, Psi=pr.Psi, gpu=gpu)
     del A, Y, X, F_true, res
     torch.cuda.empty_cache()
@@ -398,9 +411,10 @@ def leg_protocol(torch, cs, W, dev, stream, samples):
             res, ms = event_timed(torch, stream, fn, reps=1)
             if label.startswith("gomp"):
                 smp["gpu"][label] = res[0][tsidx].cpu().numpy()
-                # the 8 pixels that dominate the cube's error, for the oracle to redo
-                worst = torch.argsort(((res[0] - Xs) ** 2).sum(1), descending=True)[:8].cpu().numpy()
-                smp["worst"][label] = (c["F"][worst], res[0][torch.from_numpy(worst).to(dev)].cpu().numpy())
+                # the 8 pixels that dominate the cube's error, for the oracle to
+                # redo on the same measurements
+                worst = torch.argsort(((res[0] - Xs) ** 2).sum(1), descending=True)[:8]
+                smp["worst"][label] = (Y[worst].cpu().numpy(), Xs[worst].cpu().numpy(), res[0][worst].cpu().numpy())
             st = res[-1]
             fl = st["flags"]
             row["solvers"][label] = {
@@ -417,10 +431,10 @@ def leg_protocol(torch, cs, W, dev, stream, samples):
     return out
 
 
-def leg_serving(torch, cs, W, n_tiles, n_warm):
+def leg_serving(torch, cs, W, n_tiles, n_warm, prec="f32"):
     stream = W.serving_stream(n_warm + n_tiles)
     rate = W.SERVING["rate"]
-    log(f"leg serving: {n_warm} + {n_tiles} tiles at {rate:g} tiles/s")
+    log(f"leg serving ({prec}): {n_warm} + {n_tiles} tiles at {rate:g} tiles/s")
     pools, dicts = {}, {}
     side_max = W.SERVING["side_max"]
     for N in W.SERVING["bands"]:
@@ -433,7 +447,7 @@ def leg_serving(torch, cs, W, n_tiles, n_warm):
     done, lag = {}, {}
     st0 = None
     with cs.Server(K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL, hbm_budget_bytes=budget,
-                   batch_pixels=batch_pixels) as srv:
+                   batch_pixels=batch_pixels, prec=prec) as srv:
         ids = {N: srv.add_dict(a) for N, a in dicts.items()}
         t0 = time.perf_counter()
         for i, tile in enumerate(stream):
@@ -476,7 +490,7 @@ def leg_serving(torch, cs, W, n_tiles, n_warm):
     span = meas[-1].t_arrival - meas[0].t_arrival
     return {"workload": f"Poisson tile stream {rate:g} tiles/s, square tiles side log-uniform in "
                         f"[{W.SERVING['side_min']}, {side_max}], N in {list(W.SERVING['bands'])}, gOMP S={GOMP_S} "
-                        f"K={GOMP_K} res_tol={GOMP_TOL} FP32, HBM budget {budget >> 30} GiB",
+                        f"K={GOMP_K} res_tol={GOMP_TOL} {prec.upper()} correlation, HBM budget {budget >> 30} GiB",
             "tiles": len(meas), "warmup_tiles": n_warm, "failed_tiles": len(bad),
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             # stability over the run: the same percentiles on each half of the measured tiles
@@ -517,6 +531,23 @@ def cpu_baseline_leg(W, pr, L, idx_psnr, Xf_s, Xg_s, n_sample, samples):
     cpu = {"value": n / cdt, "unit": "pixels/s", "cores": int(threads), "kind": "oracle",
            "sample": f"{n} seeded pixels of the same cube, FISTA {FISTA_ITERS} it + gOMP, FP64 NumPy "
                      f"({cdt:.1f} s)"}
+    # the BLAS behind NumPy, and the same oracle on one core (an eighth of the sample)
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        blas = [f"{i.get('internal_api')} {i.get('version')} ({os.path.basename(i.get('filepath', ''))})"
+                for i in threadpool_info() if i.get("user_api") == "blas"]
+        cpu["blas"] = "; ".join(blas) if blas else None
+        n1 = max(256, n // 8)
+        log(f"cpu oracle on {n1} pixels, one core")
+        with threadpool_limits(limits=1):
+            c1 = time.perf_counter()
+            oracle.fista(pr.A, pr.Y[sidx[:n1]], LAMBDA, L, FISTA_ITERS)
+            oracle.gomp(pr.A, pr.Y[sidx[:n1]], K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL)
+            dt1 = time.perf_counter() - c1
+        cpu["value_1core"] = n1 / dt1
+        cpu["sample_1core"] = f"the first {n1} pixels of the sample on one BLAS thread ({dt1:.1f} s)"
+    except ImportError:
+        cpu["blas"] = None
     # PSNR of the spectra against the oracle's, on seeded samples
     q = {}
     Psi = pr.Psi
@@ -555,16 +586,14 @@ def cpu_baseline_leg(W, pr, L, idx_psnr, Xf_s, Xg_s, n_sample, samples):
             q[tag + "_gpu_vs_oracle"] = psnr(g @ s["Psi"].T, ref["X"] @ s["Psi"].T)
             q[tag + "_gpu_vs_sparsified"] = psnr(g @ s["Psi"].T, sp["F"])
             q[tag + "_oracle_vs_sparsified"] = psnr(ref["X"] @ s["Psi"].T, sp["F"])
-            # the GPU's 8 worst pixels of the whole cube, solved by the oracle:
-            # both against the sparsified spectra of those pixels (equal when
-            # the pixels fail in the algorithm itself, not in the arithmetic)
-            Fw, Xw = s["worst"][f"gomp kappa={kap}"]
-            spw = oracle.sparsify(Fw.astype(np.float32).astype(np.float64),
-                                  s["Psi"].astype(np.float32).astype(np.float64), PROTOCOL_T)
-            Yw = (spw["X"] @ s["A"].astype(np.float64).T).astype(np.float32)
+            # the GPU's 8 worst pixels of the whole cube, solved by the oracle on
+            # the same (GPU-sparsified) measurements: both against the GPU's
+            # sparsified coefficients of those pixels, and against each other
+            Yw, Xsw, Xw = s["worst"][f"gomp kappa={kap}"]
             rw = oracle.gomp(s["A"], Yw, K=kap, S=kap // 5, eps=PROTOCOL_EPS)
-            q[tag + "_worst8_gpu_vs_sparsified"] = psnr(Xw @ s["Psi"].T, spw["F"])
-            q[tag + "_worst8_oracle_vs_sparsified"] = psnr(rw["X"] @ s["Psi"].T, spw["F"])
+            q[tag + "_worst8_gpu_vs_sparsified"] = psnr(Xw @ s["Psi"].T, Xsw @ s["Psi"].T)
+            q[tag + "_worst8_oracle_vs_sparsified"] = psnr(rw["X"] @ s["Psi"].T, Xsw @ s["Psi"].T)
+            q[tag + "_worst8_gpu_vs_oracle"] = psnr(Xw @ s["Psi"].T, rw["X"] @ s["Psi"].T)
     if "precision" in samples:
         s = samples["precision"]
         ref = oracle.fista(s["A"], s["Y"], LAMBDA, s["L"], FISTA_ITERS)
@@ -577,6 +606,9 @@ def cpu_baseline_leg(W, pr, L, idx_psnr, Xf_s, Xg_s, n_sample, samples):
                 q["precision_fista_f32"] = psnr(g @ s["Psi"].T, ref["X"] @ s["Psi"].T)
         ref = oracle.gomp(s["A"], s["Y"], K=GOMP_K, S=GOMP_S, res_tol=GOMP_TOL)
         q["precision_gomp"] = psnr(s["gpu"]["gomp"] @ s["Psi"].T, ref["X"] @ s["Psi"].T)
+        for prec in ("bf16", "f16"):
+            if f"gomp_{prec}" in s["gpu"]:
+                q[f"precision_gomp_{prec}"] = psnr(s["gpu"][f"gomp_{prec}"] @ s["Psi"].T, ref["X"] @ s["Psi"].T)
     if "other" in samples:
         s = samples["other"]
         refs = {"cosamp": oracle.cosamp(s["A"], s["Y"], K=OTHER_K, max_iter=COSAMP_ITERS),
@@ -681,6 +713,7 @@ def main():
         breakdown["protocol"] = leg_protocol(torch, cs, W, dev, stream, samples)
     if "serving" in legs:
         breakdown["serving"] = leg_serving(torch, cs, W, args.serve_tiles, args.serve_warmup)
+        breakdown["serving_bf16"] = leg_serving(torch, cs, W, args.serve_tiles, args.serve_warmup, prec="bf16")
 
     cpu = None
     if not args.no_cpu:

@@ -147,11 +147,15 @@ typedef struct {
     double res_tol;           /* stop when ||r|| <= res_tol * ||y|| (0 disables) */
     double eps;               /* stop when Delta < eps (0 disables) */
     int32_t prune;            /* CSREC_PRUNE_EACH or CSREC_PRUNE_FINAL */
-    int32_t prec;             /* precision of the correlation A^T r */
+    int32_t prec;             /* precision of the correlation A^T r of step 1: CSREC_PREC_F32, or
+                                 BF16 / F16 operands on MFMA with FP32 accumulation (r rounded to
+                                 the format); the least squares, the prune and the residual stay in
+                                 FP32, so x is the FP32 least-squares solution on the support the
+                                 16-bit correlation selected */
     double pivot_fallback;    /* FP64 redo of a pixel when a Cholesky pivot ratio d_j / G_jj falls
-                                 below this (e.g. 1e-6), or when the FP32 error bound of its least
-                                 squares on c, 2^-24 trace(G[c,c]) trace(G[c,c]^-1), exceeds 1
-                                 (|c| near M); 0 disables both */
+                                 below this (e.g. 1e-6), or when the FP32 error estimate of its least
+                                 squares on c, 2^-24 trace(G[c,c]) trace(G[c,c]^-1) / |c|, exceeds
+                                 1e-5 (ill-conditioned supports, |c| near M); 0 disables both */
 } csrec_gomp_params;
 
 /* Alg. 5.  Inputs y, A, kappa (= K), eps. */
@@ -161,7 +165,8 @@ typedef struct {
     int32_t max_iter;         /* >= 0 */
     double eps;               /* stop when Delta < eps (0 disables) */
     double res_tol;           /* stop when ||r|| <= res_tol * ||y|| (0 disables) */
-    int32_t prec;             /* precision of the correlation A^T r */
+    int32_t prec;             /* precision of the correlation A^T r (as csrec_gomp_params.prec; the
+                                 first correlation, A^T y, the least-squares right-hand sides, is FP32) */
 } csrec_cosamp_params;
 
 /* Alg. 4 (REAL) or binary IHT (ONE_BIT).  Inputs y, A, kappa (= K), mu, eps. */
@@ -174,7 +179,8 @@ typedef struct {
     double res_tol;           /* REAL: stop when ||r|| <= res_tol * ||y|| (0 disables) */
     int32_t mode;             /* CSREC_BIHT_REAL or CSREC_BIHT_ONE_BIT */
     const int8_t* Ysign;      /* ONE_BIT: device P x M signs in {-1, +1}; REAL: ignored */
-    int32_t prec;             /* precision of the correlation */
+    int32_t prec;             /* precision of the correlation (as csrec_cosamp_params.prec; ONE_BIT
+                                 has no least squares: its x carries the 16-bit rounding) */
 } csrec_biht_params;
 
 /* Alg. 2.  Inputs y, A, x^0, lambda, alpha, eps (kappa is unused by ADMM).

@@ -47,6 +47,31 @@ STOP_FALLBACK = 4    # (GPU only) least squares redone in FP64
 STOP_NONFINITE = 8   # non-finite measurements: x = 0, no iterations
 
 
+def round_to_format(v, fmt: str) -> np.ndarray:
+    """v rounded to a shorter floating-point format, returned as float64: a
+    rounding model of products whose operands a 16-bit MFMA receives.  The
+    value is first rounded to IEEE binary32 (as FP32 data is), then
+    'bf16': bfloat16 keeps the upper 16 bits of the binary32 encoding (sign,
+    8 exponent bits, 7 significand bits), rounded to nearest, ties to even
+    significand; 'f16': IEEE binary16, rounded to nearest even.  'f64' and
+    'f32' return v rounded to that format."""
+    v32 = np.asarray(v, dtype=np.float64).astype(np.float32)
+    if fmt == "f64":
+        return np.asarray(v, dtype=np.float64)
+    if fmt == "f32":
+        return v32.astype(np.float64)
+    if fmt == "f16":
+        return v32.astype(np.float16).astype(np.float64)
+    if fmt != "bf16":
+        raise ValueError(f"unknown format {fmt}")
+    bits = v32.view(np.uint32).astype(np.uint64)
+    keep = (bits >> 16) & 1                      # lowest kept bit: ties go to the even one
+    rounded = ((bits + 0x7FFF + keep) >> 16) << 16
+    finite = np.isfinite(v32)
+    out = np.where(finite, (rounded & 0xFFFFFFFF).astype(np.uint32).view(np.float32), v32)
+    return out.astype(np.float64)
+
+
 def _f64(a) -> np.ndarray:
     return np.asarray(a, dtype=np.float64)
 
@@ -401,7 +426,7 @@ def admm_complex(A, Y, lam: float, alpha: float, max_iter: int, eps: float = 0.0
 # --------------------------------------------------------------------------
 
 def gomp(A, Y, K: int, S: int, max_iter: int = 0, res_tol: float = 0.0, eps: float = 0.0,
-         prune: str = "each", diagnostics: bool = False) -> dict:
+         prune: str = "each", diagnostics: bool = False, corr_format: str = "f64") -> dict:
     """Generalised OMP (Alg. 3): kappa = K, G = S atoms per iteration.
 
     Per iteration i, for each pixel still running:
@@ -421,7 +446,16 @@ def gomp(A, Y, K: int, S: int, max_iter: int = 0, res_tol: float = 0.0, eps: flo
     the largest compared value (sel_gap, prune_gap) and relative to the scale
     on which rounding perturbs the compared values -- ||y|| for the
     correlations, which are formed from a residual y - A x, and ||s|| for the
-    least-squares coefficients (sel_gap_abs, prune_gap_abs)."""
+    least-squares coefficients (sel_gap_abs, prune_gap_abs).  sel_gap_l1 is
+    the selection gap relative to max_n sum_m |A_mn| |r_m|, the scale of the
+    error of a correlation whose operands are rounded to a shorter format:
+    rounding A and r to a significand of p bits (unit roundoff u = 2^-p)
+    moves each |p_n| by at most about 2u sum_m |A_mn| |r_m|.
+
+    corr_format ('f64' by default, 'bf16', 'f16') is a rounding model of a
+    correlation computed on 16-bit operands: step 1 uses A and r rounded to
+    that format (round_to_format), their products summed in FP64; every
+    other step is unchanged."""
     A = _f64(A)
     Y = _f64(Y)
     P, M = Y.shape
@@ -432,6 +466,7 @@ def gomp(A, Y, K: int, S: int, max_iter: int = 0, res_tol: float = 0.0, eps: flo
     fin = _finite_rows(Y)
     Yc = np.where(fin[:, None], Y, 0.0)
     ynorm = np.linalg.norm(Yc, axis=1)
+    Acorr = round_to_format(A, corr_format) if corr_format != "f64" else A
     x = np.zeros((P, N))
     r = Yc.copy()
     c = np.full((P, S * I_max), -1, dtype=np.int64)
@@ -444,6 +479,7 @@ def gomp(A, Y, K: int, S: int, max_iter: int = 0, res_tol: float = 0.0, eps: flo
     sel_gap = np.full(P, np.inf)
     prune_gap = np.full(P, np.inf)
     sel_gap_abs = np.full(P, np.inf)
+    sel_gap_l1 = np.full(P, np.inf)
     prune_gap_abs = np.full(P, np.inf)
     stop_margin = np.full(P, np.inf)
     min_pivot = np.full(P, np.inf)
@@ -453,12 +489,17 @@ def gomp(A, Y, K: int, S: int, max_iter: int = 0, res_tol: float = 0.0, eps: flo
             break
         a = np.nonzero(active)[0]
         ra, ya = r[a], Yc[a]
-        p = ra @ A                                              # step 1: A^T r
+        if corr_format == "f64":
+            p = ra @ A                                          # step 1: A^T r
+        else:
+            p = round_to_format(ra, corr_format) @ Acorr        # step 1 on rounded operands
         allowed = ~in_c[a]
         theta = top_indices(p, S, allowed)
         if diagnostics:
             sel_gap[a] = np.minimum(sel_gap[a], _ordered_gap(p, S, allowed))
             sel_gap_abs[a] = np.minimum(sel_gap_abs[a], _ordered_gap(p, S, allowed, ynorm[a]))
+            l1 = np.max(np.abs(ra) @ np.abs(A), axis=1)
+            sel_gap_l1[a] = np.minimum(sel_gap_l1[a], _ordered_gap(p, S, allowed, l1))
         c[a, (i - 1) * S:i * S] = theta
         in_c[a[:, None], theta] = True
         cur = c[a, :i * S]
@@ -510,7 +551,8 @@ def gomp(A, Y, K: int, S: int, max_iter: int = 0, res_tol: float = 0.0, eps: flo
     out = dict(X=x, support=support, iters=iters, delta=delta, resid=resid, flags=flags)
     if diagnostics:
         out.update(sel_gap=sel_gap, prune_gap=prune_gap, stop_margin=stop_margin,
-                   min_pivot=min_pivot, sel_gap_abs=sel_gap_abs, prune_gap_abs=prune_gap_abs)
+                   min_pivot=min_pivot, sel_gap_abs=sel_gap_abs, prune_gap_abs=prune_gap_abs,
+                   sel_gap_l1=sel_gap_l1)
     return out
 
 

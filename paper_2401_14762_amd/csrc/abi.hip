@@ -96,7 +96,6 @@ int fill_gomp(const csrec_problem* p, const csrec_gomp_params* q, GreedyLaunch& 
         return CSREC_E_INVAL;
     if (q->prune != CSREC_PRUNE_EACH && q->prune != CSREC_PRUNE_FINAL) return CSREC_E_INVAL;
     if ((e = check_prec(q->prec))) return e;
-    if (q->prec != CSREC_PREC_F32) return CSREC_E_UNSUPPORTED;
     const int imax = q->max_iter > 0 ? q->max_iter : (q->K < p->M / q->S ? q->K : p->M / q->S);
     if (imax < 1) return CSREC_E_INVAL;
     if (q->S * imax > p->M || q->S * imax > GOMP_CMAX || q->K > GOMP_CMAX) return CSREC_E_SHAPE;
@@ -122,7 +121,6 @@ int fill_cosamp(const csrec_problem* p, const csrec_cosamp_params* q, GreedyLaun
     if (q->K < 1 || q->max_iter < 0 || !finite_nonneg(q->eps) || !finite_nonneg(q->res_tol))
         return CSREC_E_INVAL;
     if ((e = check_prec(q->prec))) return e;
-    if (q->prec != CSREC_PREC_F32) return CSREC_E_UNSUPPORTED;
     if (3 * q->K > p->M || 3 * q->K > GREEDY_CMAX) return CSREC_E_SHAPE;
     if (p->M > 96) return CSREC_E_UNSUPPORTED;
     l = GreedyLaunch{};
@@ -147,7 +145,6 @@ int fill_biht(const csrec_problem* p, const csrec_biht_params* q, GreedyLaunch& 
         !finite_nonneg(q->res_tol))
         return CSREC_E_INVAL;
     if ((e = check_prec(q->prec))) return e;
-    if (q->prec != CSREC_PREC_F32) return CSREC_E_UNSUPPORTED;
     if (one ? (q->K > p->N || q->K > 64) : (2 * q->K > p->M || 2 * q->K > GREEDY_CMAX))
         return CSREC_E_SHAPE;
     if (p->M > 96) return CSREC_E_UNSUPPORTED;

@@ -191,7 +191,7 @@ int gomp_coop_supported(int M, int N, int K, int S, int Imax);
 void gomp_coop_prepare(const float* A, int M, int N, float* dictbuf, hipStream_t stream);
 int gomp_coop_launch(const float* Y, float* X, int32_t* support, csrec_pixel_stats* stats, const float* G32,
                      const float* dictbuf, uint32_t* fbflag, int M, int N, int64_t p0, int64_t P, int K, int S,
-                     int Imax, int prune, float res_tol, float eps, double pivot_thr, hipStream_t stream);
+                     int Imax, int prune, float res_tol, float eps, double pivot_thr, int prec, hipStream_t stream);
 struct GompCoopItem {
     const float* dict;    // gomp_coop_prepare output for this item's A
     const float* Y;
@@ -211,8 +211,8 @@ size_t coop_other_lds_floats(int kind, int M, int N, int K);
 int coop_other_supported(int kind, int M, int N, int K);
 int coop_other_launch(int kind, const float* Y, const int8_t* Ysign, float* X, int32_t* support,
                       csrec_pixel_stats* stats, const float* G32, const float* dictbuf, int M, int N, int64_t p0,
-                      int64_t P, int K, int Imax, float mu, float res_tol, float eps, hipStream_t stream);
+                      int64_t P, int K, int Imax, float mu, float res_tol, float eps, int prec, hipStream_t stream);
 int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_host, void* table_dev, int K, int S,
-                           int prune, float res_tol, float eps, double pivot_thr, hipStream_t stream);
+                           int prune, float res_tol, float eps, double pivot_thr, int prec, hipStream_t stream);
 
 }  // namespace csrec

@@ -51,6 +51,7 @@ constexpr int kRowPad = 8;        // rows of the padded copy of A: multiple of 8
 constexpr int kMaxS = 8;
 constexpr int kGJ = 32;           // K up to this: the pruned system is solved in registers
 constexpr int kCU = 6;            // |c| <= 16 kCU entries: per-lane units of the rank and the Gram gather
+constexpr float kFp32Tol = 1e-5f; // relative accuracy an FP32 least squares must keep, or the pixel is redone in FP64
 
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 
@@ -72,14 +73,39 @@ struct CoopArgs {
     int lds_floats;       // per pixel
     float mu;             // BIHT step
     const int8_t* Ysign;  // one-bit BIHT: P x M signs
+    const __bf16* Abf;    // (M8 / 4) x NP x 4: A in BF16, four consecutive rows of an atom together
+    const _Float16* Ahf;  // the same in FP16
+    int prec;             // precision of the correlation A^T v (CSREC_PREC_*)
 };
 
 __host__ __device__ __forceinline__ int tri(int k) { return k * (k + 1) / 2; }
+
+// Every kernel here is one wavefront per workgroup, and lanes exchange data
+// only through LDS and cross-lane operations: the LDS executes a wave's
+// instructions in issue order, so what lanes wrote is visible to a later
+// read by any lane of the wave once the compiler keeps the order.  This
+// orders LDS accesses across the point for the compiler without the
+// workgroup barrier's waits on outstanding global loads.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 __host__ __device__ __forceinline__ int up4(int k) { return (k + 3) & ~3; }
 
 // Atom indices read back from LDS are kept inside [0, N) before they address
 // global memory.
 __device__ __forceinline__ int clamp_atom(int j, int N) { return (unsigned)j < (unsigned)N ? j : 0; }
+
+// Largest value over the wave.
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
 
 // Sum over the 16 lanes of a pixel (lanes x, x + 4, ..., x + 60).
 __device__ __forceinline__ float pix_sum(float v) {
@@ -227,7 +253,7 @@ __device__ __forceinline__ float inv_append(bool on, int t, int n, float* Wf, fl
         }
     }
     ll = pix_sum(ll);
-    __syncthreads();
+    wave_sync();
     const float d = gjj - ll;
     const float ratio = d / gjj;
     // A pivot below FP32 resolution (the atom is numerically in the span) is
@@ -258,7 +284,7 @@ __device__ __forceinline__ float inv_append(bool on, int t, int n, float* Wf, fl
         bf[n] = bj;
         idx[n] = atom;
     }
-    __syncthreads();
+    wave_sync();
     return ratio;
 }
 
@@ -266,7 +292,7 @@ __device__ __forceinline__ float inv_append(bool on, int t, int n, float* Wf, fl
 __device__ __forceinline__ void inv_solve(bool on, int t, int n, const float* Wf, const float* zf, float* sf) {
     if (on)
         for (int k = t; k < n; k += 16) sf[k] = coldot4(Wf, zf, k, n);
-    __syncthreads();
+    wave_sync();
 }
 
 __device__ __forceinline__ float rank_key(float v) {
@@ -347,7 +373,7 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
     if (PAD) {
         if (on)
             for (int i = n + t; i < nmax; i += 16) rhs[i] = 0.f;
-        __syncthreads();
+        wave_sync();
     }
     if (nmax <= GJ) {
         constexpr int W1 = GJ + 1;          // nmax columns (padded to GJ) + the right-hand side
@@ -386,7 +412,7 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
                         }
                     }
                 }
-                __syncthreads();
+                wave_sync();
                 if (on) {
                     const float rp = 1.f / slot[k];
                     const float f0 = (t == k) ? 0.f : R0[k] * rp;
@@ -409,7 +435,7 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
         }
         if (on && t < n) sol[t] = R0[GJ] / dg0;
         if (on && t + 16 < n) sol[t + 16] = R1[GJ] / dg1;
-        __syncthreads();
+        wave_sync();
         return;
     }
     // all Gram entries of G[L,L] (lower triangle) in one batch of loads:
@@ -445,7 +471,7 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
             }
         }
     }
-    __syncthreads();
+    wave_sync();
     // LDL^T elimination with the forward substitution of rhs
     for (int k = 0; k < nmax; ++k) {
         if (on) {
@@ -471,7 +497,7 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
             }
             if (t == 0) C[tri(k) + k] = piv;
         }
-        __syncthreads();
+        wave_sync();
     }
     // back substitution: sol_i = (bt_i - sum_{k>i} C_ki sol_k) / D_i, column-oriented
     for (int i = nmax - 1; i >= 0; --i) {
@@ -480,7 +506,7 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
             for (int k = t; k < i; k += 16) rhs[k] -= C[tri(i) + k] * si;
             if (t == 0) sol[i] = si;
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -503,12 +529,118 @@ __device__ __forceinline__ void solve_list(bool on, int t, int n, int nmax, int 
 // Called by every lane (it holds barriers).
 __device__ __forceinline__ void prune_to_q(bool on, int t, int nc, int nmax_c, int K, int N,
                                            const float* __restrict__ G32, const PixLds L) {
-    if (nmax_c > 64)
-        rank_top<kCU>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
-    else
+    // as many 16-atom rank units as the longest list in the wave needs
+    const int nw = wave_max(on ? nc : 0);
+    if (nw <= 32)
+        rank_top<2>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+    else if (nw <= 48)
+        rank_top<3>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+    else if (nw <= 64)
         rank_top<4>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
-    __syncthreads();
+    else
+        rank_top<kCU>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+    (void)nmax_c;
+    wave_sync();
     solve_list<false>(on, t, K, K, N, G32, L.q, L.bq, L.sq, L.Wq);
+}
+
+// p = A^T v for the wave's 4 pixels, v in the pixel's LDS vector rb (MP
+// entries, zero beyond M), on MFMA; lane 4b + x receives p of pixel x for
+// atoms 4 NG b + NG i + g in acc[g][i].
+//
+// FP32: v_mfma_f32_4x4x1_16b_f32, one row m per instruction; lane l loads
+// atoms NG l .. NG l + NG - 1 of row m of the padded copy Ap (coalesced over
+// the wave), eight rows ahead of their use.
+//
+// BF16 / FP16: v_mfma_f32_4x4x4_16b_{bf16,f16}, four rows per instruction,
+// FP32 accumulation: lane l loads the four rows of each of its NG atoms
+// from the 16-bit copy (laid out (M8 / 4) x NP x 4, so that this is one
+// contiguous 8 NG-byte load), and v is rounded to the same format.  Half the
+// bytes and a quarter of the instructions of the FP32 form.
+template <typename H>
+__device__ __forceinline__ v4f_t mfma_4x4x4(const H __attribute__((ext_vector_type(4))) & a,
+                                            const H __attribute__((ext_vector_type(4))) & b, v4f_t c);
+template <>
+__device__ __forceinline__ v4f_t mfma_4x4x4<__bf16>(const __bf16 __attribute__((ext_vector_type(4))) & a,
+                                                    const __bf16 __attribute__((ext_vector_type(4))) & b, v4f_t c) {
+    return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ v4f_t mfma_4x4x4<_Float16>(const _Float16 __attribute__((ext_vector_type(4))) & a,
+                                                      const _Float16 __attribute__((ext_vector_type(4))) & b,
+                                                      v4f_t c) {
+    return __builtin_amdgcn_mfma_f32_4x4x4f16(a, b, c, 0, 0, 0);
+}
+
+template <int NG, typename H>
+__device__ __forceinline__ void correlate16(const H* __restrict__ Ah, int NP, const float* rb, int lane, int M8,
+                                            v4f_t (&acc)[NG]) {
+    typedef H v4h __attribute__((ext_vector_type(4)));
+    constexpr int AHEAD = 2;   // 4-row blocks loaded ahead of their use
+    const v4h* ap = reinterpret_cast<const v4h*>(Ah) + NG * lane;   // block m4 starts at m4 * NP vectors
+    const int nb = M8 / 4;
+    v4h cur[AHEAD][NG];
+#pragma unroll
+    for (int d = 0; d < AHEAD; ++d)
+#pragma unroll
+        for (int g = 0; g < NG; ++g) cur[d][g] = d < nb ? ap[(size_t)d * NP + g] : v4h{};
+    for (int m4 = 0; m4 < nb; m4 += AHEAD) {
+        v4h nxt[AHEAD][NG];
+#pragma unroll
+        for (int d = 0; d < AHEAD; ++d)
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+                nxt[d][g] = m4 + AHEAD + d < nb ? ap[(size_t)(m4 + AHEAD + d) * NP + g] : v4h{};
+#pragma unroll
+        for (int d = 0; d < AHEAD; ++d) {
+            if (m4 + d < nb) {
+                const float4 rr = *reinterpret_cast<const float4*>(rb + 4 * (m4 + d));
+                const v4h bv = {(H)rr.x, (H)rr.y, (H)rr.z, (H)rr.w};
+#pragma unroll
+                for (int g = 0; g < NG; ++g) acc[g] = mfma_4x4x4<H>(cur[d][g], bv, acc[g]);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < AHEAD; ++d)
+#pragma unroll
+            for (int g = 0; g < NG; ++g) cur[d][g] = nxt[d][g];
+    }
+}
+
+template <int NG>
+__device__ __forceinline__ void correlate(const CoopArgs& a, const float* rb, int lane, int M8, int prec,
+                                          v4f_t (&acc)[NG]) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g) acc[g] = v4f_t{0.f, 0.f, 0.f, 0.f};
+    if (prec == CSREC_PREC_BF16) {
+        correlate16<NG, __bf16>(a.Abf, a.NP, rb, lane, M8, acc);
+        return;
+    }
+    if (prec == CSREC_PREC_F16) {
+        correlate16<NG, _Float16>(a.Ahf, a.NP, rb, lane, M8, acc);
+        return;
+    }
+    typedef float vNG __attribute__((ext_vector_type(NG)));
+    const vNG* ap = reinterpret_cast<const vNG*>(a.Ap) + lane;   // row m starts at m * 64 vectors
+    vNG cur[kRowPad], nxt[kRowPad];
+#pragma unroll
+    for (int r8 = 0; r8 < kRowPad; ++r8) cur[r8] = ap[(size_t)r8 * 64];
+    for (int m0 = 0; m0 < M8; m0 += kRowPad) {
+        if (m0 + kRowPad < M8) {
+#pragma unroll
+            for (int r8 = 0; r8 < kRowPad; ++r8) nxt[r8] = ap[(size_t)(m0 + kRowPad + r8) * 64];
+        }
+        const float4 r0 = *reinterpret_cast<const float4*>(rb + m0);
+        const float4 r1 = *reinterpret_cast<const float4*>(rb + m0 + 4);
+        const float rv[kRowPad] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+        for (int r8 = 0; r8 < kRowPad; ++r8)
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+                acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(cur[r8][g], rv[r8], acc[g], 0, 0, 0);
+#pragma unroll
+        for (int r8 = 0; r8 < kRowPad; ++r8) cur[r8] = nxt[r8];
+    }
 }
 
 // r = y - sum_k xv[k] A[:, xi[k]] for the lane's m = 4t + j + 64i.
@@ -598,33 +730,9 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
             const int m = 4 * t + (u & 3) + 64 * (u >> 2);
             if (m < MP) L.rb[m] = r[u];
         }
-        __syncthreads();
+        wave_sync();
         v4f_t acc[NG];
-#pragma unroll
-        for (int g = 0; g < NG; ++g) acc[g] = v4f_t{0.f, 0.f, 0.f, 0.f};
-        {
-            typedef float vNG __attribute__((ext_vector_type(NG)));
-            const vNG* ap = reinterpret_cast<const vNG*>(a.Ap) + lane;   // row m starts at m * 64 vectors
-            vNG cur[kRowPad], nxt[kRowPad];
-#pragma unroll
-            for (int r8 = 0; r8 < kRowPad; ++r8) cur[r8] = ap[(size_t)r8 * 64];
-            for (int m0 = 0; m0 < M8; m0 += kRowPad) {
-                if (m0 + kRowPad < M8) {
-#pragma unroll
-                    for (int r8 = 0; r8 < kRowPad; ++r8) nxt[r8] = ap[(size_t)(m0 + kRowPad + r8) * 64];
-                }
-                const float4 r0 = *reinterpret_cast<const float4*>(L.rb + m0);
-                const float4 r1 = *reinterpret_cast<const float4*>(L.rb + m0 + 4);
-                const float rv[kRowPad] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
-#pragma unroll
-                for (int r8 = 0; r8 < kRowPad; ++r8)
-#pragma unroll
-                    for (int g = 0; g < NG; ++g)
-                        acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(cur[r8][g], rv[r8], acc[g], 0, 0, 0);
-#pragma unroll
-                for (int r8 = 0; r8 < kRowPad; ++r8) cur[r8] = nxt[r8];
-            }
-        }
+        correlate<NG>(a, L.rb, lane, M8, a.prec, acc);
         // S rounds of argmax; the winners are appended in selection order.
         // Lane t holds atoms 4 NG t + NG i + g (entry i of accumulator g).
         int nsel = 0;
@@ -649,7 +757,7 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
             if (t == 0) L.sel[q] = bi;
             nsel += (bi >= 0) ? 1 : 0;   // the valid selections form a prefix
         }
-        __syncthreads();
+        wave_sync();
 
         // ---------------- step 2: append the atoms, s = W^T (W b_c)
         // gather G[c + earlier selections, j] into the slot of row nc + q and
@@ -690,7 +798,7 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
             const float bj = pix_sum(bpart);
             if (t == 0) L.bsel[q] = bj;
         }
-        __syncthreads();
+        wave_sync();
         for (int q = 0; q < a.S; ++q) {
             const bool on = q < nq;
             const int j = on ? L.sel[q] : 0;
@@ -702,10 +810,15 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
             if (on && a.pivot_thr > 0.0) {
                 trG += gjj;
                 trW += row_sq;
-                // a small pivot, or the FP32 error bound of the solve on c,
-                // 2^-24 kappa(G[c,c]) <= 2^-24 trace(G[c,c]) trace(G[c,c]^{-1}),
-                // reaching the size of the solution itself
-                if ((double)ratio < a.pivot_thr || trG * trW * 5.9604645e-8f > 1.f) fallback = true;
+                // a small pivot, or an FP32 error estimate of the normal
+                // equations on c above the FP32 result tolerance kFp32Tol:
+                // 2^-24 kappa(G[c,c]), kappa estimated as
+                // trace(G[c,c]) trace(G[c,c]^{-1}) / |c| (between the lower
+                // bound, that over |c|^2, and the upper bound, the product
+                // itself).  Pruned supports q are subsets of c, and the
+                // estimate of c bounds theirs.
+                if ((double)ratio < a.pivot_thr || trG * trW * 5.9604645e-8f > kFp32Tol * (float)(nc + 1))
+                    fallback = true;
             }
             if (on) ++nc;
         }
@@ -745,7 +858,7 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
                 converged = true;
             }
         }
-        __syncthreads();
+        wave_sync();
         if (!__any(active)) break;
     }
 
@@ -915,33 +1028,11 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
             const int m = 4 * t + (u & 3) + 64 * (u >> 2);
             if (m < MP) rb[m] = v[u];
         }
-        __syncthreads();
+        wave_sync();
         v4f_t acc[NG];
-#pragma unroll
-        for (int g = 0; g < NG; ++g) acc[g] = v4f_t{0.f, 0.f, 0.f, 0.f};
-        {
-            typedef float vNG __attribute__((ext_vector_type(NG)));
-            const vNG* ap = reinterpret_cast<const vNG*>(a.Ap) + lane;
-            vNG cur[kRowPad], nxt[kRowPad];
-#pragma unroll
-            for (int r8 = 0; r8 < kRowPad; ++r8) cur[r8] = ap[(size_t)r8 * 64];
-            for (int m0 = 0; m0 < M8; m0 += kRowPad) {
-                if (m0 + kRowPad < M8) {
-#pragma unroll
-                    for (int r8 = 0; r8 < kRowPad; ++r8) nxt[r8] = ap[(size_t)(m0 + kRowPad + r8) * 64];
-                }
-                const float4 r0 = *reinterpret_cast<const float4*>(rb + m0);
-                const float4 r1 = *reinterpret_cast<const float4*>(rb + m0 + 4);
-                const float rv[kRowPad] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
-#pragma unroll
-                for (int r8 = 0; r8 < kRowPad; ++r8)
-#pragma unroll
-                    for (int g = 0; g < NG; ++g)
-                        acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(cur[r8][g], rv[r8], acc[g], 0, 0, 0);
-#pragma unroll
-                for (int r8 = 0; r8 < kRowPad; ++r8) cur[r8] = nxt[r8];
-            }
-        }
+        // the first correlation of CoSaMP and BIHT is A^T y, the right-hand
+        // sides of every least-squares solve: always in FP32
+        correlate<NG>(a, rb, lane, M8, (it == 1 && KIND != GREEDY_BIHT_ONE_BIT) ? CSREC_PREC_F32 : a.prec, acc);
         float u[NV];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -996,7 +1087,7 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
             if (t == 0) sel[qq] = bi;
             nsl += (bi >= 0) ? 1 : 0;
         }
-        __syncthreads();
+        wave_sync();
         if (KIND == GREEDY_BIHT_ONE_BIT) {
             // x = H_K(u), then v = y - sgn(A x)
             if (active) {
@@ -1006,7 +1097,7 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
                 }
                 nq = nsl;
             }
-            __syncthreads();
+            wave_sync();
             if (active) {
                 const float zero[MSLOT] = {};
                 float ax[MSLOT];
@@ -1028,7 +1119,7 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
                 last_d2 = d2;
                 rn2 = n2;
             }
-            __syncthreads();
+            wave_sync();
             continue;
         }
         // ---------------- step 3: c = Theta U previous support; least squares; keep K
@@ -1060,19 +1151,24 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
             }
             nc = nsl + total;
         }
-        __syncthreads();
+        wave_sync();
         if (active)
             for (int k = t; k < nc; k += 16) b[k] = ball[clamp_atom(c[k], N)];
         int nmax = nc;
         nmax = max(nmax, __shfl_xor(nmax, 1));
         nmax = max(nmax, __shfl_xor(nmax, 2));
         solve_list<true>(active, t, nc, nmax, N, a.G32, c, b, sv, scr);
-        if (other_nc(KIND, K) > 64)
-            rank_top<kCU>(active, t, nc, K, sv, c, sv, q, sq);
-        else
+        // as many 16-atom rank units as the longest list in the wave needs
+        if (nmax <= 32)
+            rank_top<2>(active, t, nc, K, sv, c, sv, q, sq);
+        else if (nmax <= 48)
+            rank_top<3>(active, t, nc, K, sv, c, sv, q, sq);
+        else if (nmax <= 64)
             rank_top<4>(active, t, nc, K, sv, c, sv, q, sq);
+        else
+            rank_top<kCU>(active, t, nc, K, sv, c, sv, q, sq);
         if (active) nq = nc < K ? nc : K;
-        __syncthreads();
+        wave_sync();
 
         // ---------------- step 4: residual r = y - A x, Delta, stop
         if (active) {
@@ -1096,7 +1192,7 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
                 converged = true;
             }
         }
-        __syncthreads();
+        wave_sync();
         if (!__any(active)) break;
     }
 
@@ -1170,18 +1266,21 @@ __global__ __launch_bounds__(64, 2) void gomp_coop_persistent_kernel(const CoopI
                                                                      unsigned long long* __restrict__ cursor) {
     extern __shared__ float lds[];
     while (true) {
-        unsigned long long u = 0;
-        if (threadIdx.x == 0) u = atomicAdd(cursor, 1ull);
-        u = __shfl(u, 0);
-        if ((int64_t)u >= units) break;
+        unsigned long long c = 0;
+        if (threadIdx.x == 0) c = atomicAdd(cursor, 1ull);
+        // lane 0's claim, made wave-uniform so that the item lookup and its
+        // arguments live in scalar registers
+        const int64_t u = (int64_t)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(c >> 32)) << 32) |
+                                    (unsigned)__builtin_amdgcn_readfirstlane((int)(c & 0xffffffffull)));
+        if (u >= units) break;
         int lo = 0, hi = nitems - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (items[mid].block0 <= (int64_t)u) lo = mid; else hi = mid - 1;
+            if (items[mid].block0 <= u) lo = mid; else hi = mid - 1;
         }
         const CoopArgs a = items[lo].a;
-        gomp_coop_body<MSLOT, NG>(a, (int64_t)u - items[lo].block0, lds);
-        __syncthreads();
+        gomp_coop_body<MSLOT, NG>(a, u - items[lo].block0, lds);
+        wave_sync();
     }
 }
 
@@ -1201,16 +1300,26 @@ coop_grouped_t pick_coop_grouped(int MP, int NG) {
 // The two dictionary copies: AT (N x MP, rows zero padded) and Ap (M8 x NP,
 // zero rows and columns).  Block n < N writes row n of AT; block N + m
 // (m < M8) writes row m of Ap.
+// The dictionary copies: AT (N x MP, rows zero padded), Ap (M8 x NP, zero
+// rows and columns) and Ap in BF16 and FP16 laid out (M8 / 4) x NP x 4
+// (entry (m, n) at ((m / 4) NP + n) 4 + m % 4).  Block n < N writes row n of
+// AT; block N + m (m < M8) writes row m of Ap and of the 16-bit copies.
 __global__ void prepare_kernel(const float* __restrict__ A, int M, int N, int MP, int M8, int NP,
-                               float* __restrict__ AT, float* __restrict__ Ap) {
+                               float* __restrict__ AT, float* __restrict__ Ap, __bf16* __restrict__ Abf,
+                               _Float16* __restrict__ Ahf) {
     const int bidx = blockIdx.x;
     if (bidx < N) {
         for (int m = threadIdx.x; m < MP; m += blockDim.x)
             AT[(size_t)bidx * MP + m] = m < M ? A[(size_t)m * N + bidx] : 0.f;
     } else {
         const int m = bidx - N;
-        for (int n = threadIdx.x; n < NP; n += blockDim.x)
-            Ap[(size_t)m * NP + n] = (m < M && n < N) ? A[(size_t)m * N + n] : 0.f;
+        for (int n = threadIdx.x; n < NP; n += blockDim.x) {
+            const float v = (m < M && n < N) ? A[(size_t)m * N + n] : 0.f;
+            Ap[(size_t)m * NP + n] = v;
+            const size_t o = ((size_t)(m / 4) * NP + n) * 4 + (m % 4);
+            Abf[o] = (__bf16)v;
+            Ahf[o] = (_Float16)v;
+        }
     }
 }
 
@@ -1219,13 +1328,17 @@ int coop_np(int N) { return 64 * coop_ng(N); }
 int coop_m8(int M) { return (M + kRowPad - 1) / kRowPad * kRowPad; }
 
 void fill_args(CoopArgs& a, const float* dictbuf, int M, int N, int K, int S, int Imax, int prune, float res_tol,
-               float eps, double pivot_thr) {
+               float eps, double pivot_thr, int prec) {
     a.M = M;
     a.N = N;
     a.MP = gomp_coop_mp(M);
     a.NP = coop_np(N);
     a.AT = dictbuf;
     a.Ap = dictbuf + (size_t)N * a.MP;
+    const size_t n16 = (size_t)coop_m8(M) * a.NP;   // entries of each 16-bit copy
+    a.Abf = reinterpret_cast<const __bf16*>(a.Ap + n16);
+    a.Ahf = reinterpret_cast<const _Float16*>(a.Ap + n16 + n16 / 2);
+    a.prec = prec;
     a.K = K;
     a.S = S;
     a.Imax = Imax;
@@ -1245,7 +1358,10 @@ int gomp_coop_mp(int M) { return M <= 64 ? 64 : 128; }
 
 size_t gomp_coop_lds_floats(int MP, int CM, int K) { return (size_t)lds_plan(MP, CM, K).total; }
 
-size_t gomp_coop_dict_floats(int M, int N) { return (size_t)N * gomp_coop_mp(M) + (size_t)coop_m8(M) * coop_np(N); }
+size_t gomp_coop_dict_floats(int M, int N) {
+    // AT, Ap, and the BF16 and FP16 copies of Ap (half a float per entry each)
+    return (size_t)N * gomp_coop_mp(M) + 2 * (size_t)coop_m8(M) * coop_np(N);
+}
 
 int gomp_coop_supported(int M, int N, int K, int S, int Imax) {
     if (N > 64 * kMaxNG || M > 128 || S > kMaxS) return CSREC_E_UNSUPPORTED;   // M8 <= MP holds for M <= 128
@@ -1257,18 +1373,20 @@ int gomp_coop_supported(int M, int N, int K, int S, int Imax) {
 
 void gomp_coop_prepare(const float* A, int M, int N, float* dictbuf, hipStream_t stream) {
     const int MP = gomp_coop_mp(M), M8 = coop_m8(M), NP = coop_np(N);
-    hipLaunchKernelGGL(prepare_kernel, dim3(N + M8), dim3(128), 0, stream, A, M, N, MP, M8, NP, dictbuf,
-                       dictbuf + (size_t)N * MP);
+    float* Ap = dictbuf + (size_t)N * MP;
+    const size_t n16 = (size_t)M8 * NP;
+    hipLaunchKernelGGL(prepare_kernel, dim3(N + M8), dim3(128), 0, stream, A, M, N, MP, M8, NP, dictbuf, Ap,
+                       reinterpret_cast<__bf16*>(Ap + n16), reinterpret_cast<_Float16*>(Ap + n16 + n16 / 2));
 }
 
 // dictbuf (gomp_coop_dict_floats(M, N) floats, built by gomp_coop_prepare);
 // fbflag (P entries) may be null.
 int gomp_coop_launch(const float* Y, float* X, int32_t* support, csrec_pixel_stats* stats, const float* G32,
                      const float* dictbuf, uint32_t* fbflag, int M, int N, int64_t p0, int64_t P, int K, int S,
-                     int Imax, int prune, float res_tol, float eps, double pivot_thr, hipStream_t stream) {
+                     int Imax, int prune, float res_tol, float eps, double pivot_thr, int prec, hipStream_t stream) {
     if (P == 0) return CSREC_OK;
     CoopArgs a;
-    fill_args(a, dictbuf, M, N, K, S, Imax, prune, res_tol, eps, pivot_thr);
+    fill_args(a, dictbuf, M, N, K, S, Imax, prune, res_tol, eps, pivot_thr, prec);
     a.Y = Y;
     a.G32 = G32;
     a.X = X;
@@ -1310,10 +1428,10 @@ int coop_other_supported(int kind, int M, int N, int K) {
 
 int coop_other_launch(int kind, const float* Y, const int8_t* Ysign, float* X, int32_t* support,
                       csrec_pixel_stats* stats, const float* G32, const float* dictbuf, int M, int N, int64_t p0,
-                      int64_t P, int K, int Imax, float mu, float res_tol, float eps, hipStream_t stream) {
+                      int64_t P, int K, int Imax, float mu, float res_tol, float eps, int prec, hipStream_t stream) {
     if (P == 0) return CSREC_OK;
     CoopArgs a;
-    fill_args(a, dictbuf, M, N, K, 1, Imax, 0, res_tol, eps, 0.0);
+    fill_args(a, dictbuf, M, N, K, 1, Imax, 0, res_tol, eps, 0.0, prec);
     a.lds_floats = (int)coop_other_lds_floats(kind, M, N, K);
     a.Y = Y;
     a.Ysign = Ysign;
@@ -1359,7 +1477,7 @@ int64_t resident_groups(const void* fn, size_t lds) {
 // table_host / table_dev: nitems items and gomp_coop_table_extra() bytes
 // behind them (the work cursor).
 int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_host, void* table_dev, int K, int S,
-                           int prune, float res_tol, float eps, double pivot_thr, hipStream_t stream) {
+                           int prune, float res_tol, float eps, double pivot_thr, int prec, hipStream_t stream) {
     if (nitems <= 0) return CSREC_OK;
     CoopItem* th = static_cast<CoopItem*>(table_host);
     int64_t blocks = 0;
@@ -1369,7 +1487,7 @@ int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_ho
         const GompCoopItem& it = items[i];
         if (gomp_coop_class(it.M, it.N) != cls) return CSREC_E_INVAL;
         CoopArgs& a = th[i].a;
-        fill_args(a, it.dict, it.M, it.N, K, S, it.max_iter, prune, res_tol, eps, pivot_thr);
+        fill_args(a, it.dict, it.M, it.N, K, S, it.max_iter, prune, res_tol, eps, pivot_thr, prec);
         a.Y = it.Y;
         a.G32 = it.G32;
         a.X = it.X;

@@ -737,7 +737,7 @@ int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* ite
         }
         if (ci.empty()) continue;
         const int e = gomp_coop_group_launch(ci.data(), (int)ci.size(), chost + coff, cdev + coff, pm.K, pm.S,
-                                             pm.prune, pm.res_tol, pm.eps, pm.pivot_fallback, stream);
+                                             pm.prune, pm.res_tol, pm.eps, pm.pivot_fallback, pm.prec, stream);
         if (e) return e;
         coff += align_up(ci.size() * gomp_coop_item_bytes() + gomp_coop_table_extra(), 256);
     }
@@ -811,7 +811,7 @@ int greedy_launch(const GreedyLaunch& a) {
         for (int64_t p0 = 0; p0 < a.P; p0 += L.CH) {
             const int64_t np = (a.P - p0) < L.CH ? (a.P - p0) : L.CH;
             const int e = coop_other_launch(a.kind, a.Y, a.Ysign, a.X, a.support, a.stats, g.G32, dictbuf, a.M, a.N,
-                                            p0, np, a.K, a.max_iter, a.mu, a.res_tol, a.eps, a.stream);
+                                            p0, np, a.K, a.max_iter, a.mu, a.res_tol, a.eps, a.prec, a.stream);
             if (e) return e;
         }
         return CSREC_OK;
@@ -831,7 +831,7 @@ int greedy_launch(const GreedyLaunch& a) {
         const int64_t np = (a.P - p0) < L.CH ? (a.P - p0) : L.CH;
         const int e = gomp_coop_launch(a.Y, a.X, a.support, a.stats, g.G32, dictbuf, g.fbflag, a.M, a.N, p0, np,
                                        a.K, a.S, a.max_iter, a.prune, a.res_tol, a.eps, a.pivot_fallback,
-                                       a.stream);
+                                       a.prec, a.stream);
         if (e) return e;
         if (dbl) {
             hipLaunchKernelGGL(redo, dim3((unsigned)ceil_div(np, threads)), dim3(threads), lds, a.stream, g, p0,
@@ -934,7 +934,7 @@ int greedy_gomp_scratch_launch(const GreedyLaunch& a, char* scr, size_t cap) {
         const int64_t np = (a.P - p0) < L.CH ? (a.P - p0) : L.CH;
         const int e = gomp_coop_launch(a.Y, a.X, a.support, a.stats, g.G32, dictbuf, g.fbflag, a.M, a.N, p0, np,
                                        a.K, a.S, a.max_iter, a.prune, a.res_tol, a.eps, a.pivot_fallback,
-                                       a.stream);
+                                       a.prec, a.stream);
         if (e) return e;
         if (dbl) {
             hipLaunchKernelGGL(redo, dim3((unsigned)(cols / kRedoThreads)), dim3(kRedoThreads), lds, a.stream, g,

@@ -213,7 +213,6 @@ int check_gomp_params(const csrec_gomp_params& g) {
     if (g.prune != CSREC_PRUNE_EACH && g.prune != CSREC_PRUNE_FINAL) return CSREC_E_INVAL;
     if (!(g.res_tol >= 0) || !(g.eps >= 0) || !(g.pivot_fallback >= 0)) return CSREC_E_INVAL;
     if (g.prec != CSREC_PREC_F32 && g.prec != CSREC_PREC_BF16 && g.prec != CSREC_PREC_F16) return CSREC_E_INVAL;
-    if (g.prec != CSREC_PREC_F32) return CSREC_E_UNSUPPORTED;
     return CSREC_OK;
 }
 

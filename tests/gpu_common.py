@@ -143,3 +143,24 @@ def assert_cadmm_parity(X_gpu, Z_gpu, A, Y, lam, alpha, iters, floor=1e-5, **kw)
         assert e.max() <= max(floor, 2.0 * e32.max()), (name, e.max(), e32.max())
         assert np.median(e) <= max(floor / 10, 2.0 * np.median(e32)), (name, np.median(e), np.median(e32))
     return ref
+
+
+def ls_on_own_support(A, Y, S):
+    """Per pixel, the FP64 least-squares solution of Alg. 3 step 2 on the
+    pixel's own support (the non-negative entries of its row of S), as a
+    dense P x N matrix: what x must be once a greedy solver has chosen that
+    support, whatever the choice."""
+    import oracle
+    A = np.asarray(A, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    P, N = Y.shape[0], A.shape[1]
+    X = np.zeros((P, N))
+    sizes = (S >= 0).sum(axis=1)
+    for k in np.unique(sizes):
+        rows = np.nonzero(sizes == k)[0]
+        if k == 0:
+            continue
+        cols = np.stack([np.sort(S[r][S[r] >= 0]) for r in rows])
+        sol = oracle.lstsq_on_support(A, Y[rows], cols)
+        X[rows[:, None], cols] = sol
+    return X

@@ -393,6 +393,15 @@ def check_gomp_diagnostics_by_hand(orc):
     assert abs(o["stop_margin"][0] - abs(math.sqrt(7.5625 / ny2) - 0.1) / 0.1) < 1e-12
     assert abs(o["min_pivot"][0] - 1.0) < 1e-15
     assert o["support"][0].tolist() == [0, 2]
+    # A = I: sum_m |A_mn| |r_m| = |r_n| = |p_n|, so the l1-scaled gap is sel_gap
+    assert abs(o["sel_gap_l1"][0] - 0.2) < 1e-15
+    # columns (3, -3) and (1, 1), y = (1, 1): p = (0, 2) but sum_m |A_mn| |y_m| =
+    # (6, 2); the one selection's gap 2 - 0 is 1 of max |p| and 1/3 of the l1 scale
+    d = orc.gomp(np.array([[3.0, 1.0], [-3.0, 1.0]]), np.array([[1.0, 1.0]]), K=1, S=1, max_iter=1,
+                 diagnostics=True)
+    assert d["support"][0].tolist() == [1]
+    assert abs(d["sel_gap"][0] - 1.0) < 1e-15
+    assert abs(d["sel_gap_l1"][0] - 1.0 / 3.0) < 1e-15
     for t in (0.3, 1e-3):
         A = np.array([[2.0, 3.0 * math.cos(t), 0.0],
                       [0.0, 3.0 * math.sin(t), 0.0],
@@ -407,6 +416,32 @@ def check_gomp_diagnostics_by_hand(orc):
     assert abs(c["sel_gap"][0] - 0.5 / 4.0) < 1e-15          # 2nd (2.5) vs 3rd (2)
     b = orc.biht(np.eye(8), y, K=2, max_iter=1, mu=1.0, diagnostics=True)
     assert abs(b["sel_gap"][0] - 0.5 / 4.0) < 1e-15          # u = mu y: 2nd (2.5) vs 3rd (2)
+
+
+def check_round_to_format(orc):
+    """The 16-bit rounding model of the correlation (round_to_format) and
+    gOMP's corr_format.  BF16 keeps 8 significant bits: spacing 2^-7 on
+    [1, 2), so 1 + 2^-9 rounds down, 1 + 2^-8 is a tie and goes to the even
+    significand (1), 1 + 3 2^-8 is a tie between 1 + 2^-7 (odd) and 1 + 2^-6
+    (even); pi is 3.140625; FP16 (11 bits) ties 1 + 2^-11 to 1 and
+    1 + 3 2^-11 to 1 + 2^-9, and 65520 overflows to inf.  Random values agree
+    with torch's float32 -> bfloat16 / float16 conversions (round to nearest
+    even).  With A = I and y = (1, 1 + 2^-8) the FP64 correlation selects
+    atom 1, the BF16 model sees a tie and selects atom 0 (ties to the lower
+    index)."""
+    bf = orc.round_to_format(np.array([1 + 2.0 ** -9, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, math.pi, -2.5, 2.0 ** -130]),
+                             "bf16")
+    assert bf.tolist() == [1.0, 1.0, 1 + 2.0 ** -6, 3.140625, -2.5, 2.0 ** -130]
+    h = orc.round_to_format(np.array([1 + 2.0 ** -11, 1 + 3 * 2.0 ** -11, 65520.0]), "f16")
+    assert h[0] == 1.0 and h[1] == 1 + 2.0 ** -9 and np.isinf(h[2])
+    import torch
+    v = np.random.default_rng(0).standard_normal(4096) * np.exp(np.random.default_rng(1).uniform(-20, 20, 4096))
+    t = torch.from_numpy(v.astype(np.float32))
+    assert np.array_equal(orc.round_to_format(v, "bf16"), t.to(torch.bfloat16).to(torch.float64).numpy())
+    assert np.array_equal(orc.round_to_format(v, "f16"), t.to(torch.float16).to(torch.float64).numpy())
+    y = np.array([[1.0, 1.0 + 2.0 ** -8]])
+    assert orc.gomp(np.eye(2), y, K=1, S=1, max_iter=1)["support"][0].tolist() == [1]
+    assert orc.gomp(np.eye(2), y, K=1, S=1, max_iter=1, corr_format="bf16")["support"][0].tolist() == [0]
 
 
 # ---------------------------------------------------------------- CoSaMP
@@ -845,7 +880,8 @@ ORACLE_CHECKS = [
     check_fista_stop_rule, check_fista_nonfinite, check_lstsq, check_top_indices,
     check_gomp_is_omp_when_S1, check_gomp_orthonormal, check_gomp_exact_recovery,
     check_gomp_brute_force, check_gomp_prune_invariants, check_gomp_no_reselect,
-    check_gomp_stop, check_gomp_final_prune, check_gomp_diagnostics_by_hand, check_cosamp_biht_res_tol,
+    check_gomp_stop, check_gomp_final_prune, check_gomp_diagnostics_by_hand, check_round_to_format,
+    check_cosamp_biht_res_tol,
     check_cosamp_orthonormal, check_cosamp_recovery, check_cosamp_no_resolve,
     check_biht_orthonormal, check_biht_first_step, check_biht_second_step_mu,
     check_biht_recovery, check_one_bit, check_admm_matches_sklearn_lasso, check_admm_identity,

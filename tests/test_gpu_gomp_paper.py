@@ -136,3 +136,35 @@ def test_cosamp_biht_paper_points(torch, N, kind, K):
         ref = oracle.biht(A, Y, K=K, max_iter=300, mu=0.1, eps=1e-8)
     torch.cuda.synchronize()
     _check_unique_part(np_of(X), np_of(Sup), ref, K, N, tol)
+
+
+@pytest.mark.parametrize("name,K", [("china-like", 22), ("salinas-like", 33)])
+def test_full_cube_worst_pixels(torch, name, K):
+    """The whole data-set-shaped cube as the protocol runs it (GPU
+    sparsification at T = 0.1, band subsampling, G = floor(kappa / 5),
+    eps = 1e-8, FP64 redo at pivot ratio 1e-6 or an FP32 error estimate
+    above 1e-5): the 16 pixels with the largest relative residual and the 16
+    farthest from their own sparsified coefficients, redone by the oracle on
+    the same measurements, pass the unique-part check.  These are the pixels
+    where an FP32 least squares on a long, ill-conditioned support (|c| near
+    M) would lose accuracy."""
+    import paper_2401_14762_amd as cs
+    c = W.paper_shape_cube(name)
+    A = to_dev(torch, c["A"])
+    Psi = torch.from_numpy(c["Psi"].astype(np.float32)).cuda()
+    F = torch.from_numpy(c["F"].astype(np.float32)).cuda()
+    note(f"gomp full cube {name} {c['P']} pixels kappa={K} G={K // 5}")
+    Xs, Y, _ = cs.sparsify(Psi, A, F, T=0.1)
+    X, Sup, st = cs.gomp(A, Y, K=K, S=K // 5, eps=1e-8, pivot_fallback=1e-6)
+    torch.cuda.synchronize()
+    rel_res = st["resid"] / torch.linalg.norm(Y, dim=1).clamp_min(1e-30)
+    rel_err = torch.linalg.norm(X - Xs, dim=1) / torch.linalg.norm(Xs, dim=1).clamp_min(1e-30)
+    idx = torch.unique(torch.cat([torch.argsort(rel_res, descending=True)[:16],
+                                  torch.argsort(rel_err, descending=True)[:16]])).cpu().numpy()
+    redo = int(((st["flags"] & 4) != 0).sum().item())
+    note(f"  {redo} pixels redone in FP64; largest error against the sparsified coefficients "
+         f"{rel_err.max().item():.2e}")
+    Yw = np_of(Y)[idx]
+    ref = oracle.gomp(c["A"], Yw, K=K, S=K // 5, eps=1e-8)
+    _check_unique_part(np_of(X)[idx], np_of(Sup)[idx], ref, K, c["N"])
+    assert rel_err.max().item() <= 1e-5

@@ -138,7 +138,8 @@ def test_per_tile_parameters_and_tags(torch):
     parameters.  A tag still in use is refused; a released one is reusable."""
     import paper_2401_14762_amd as cs
     tiles, dicts = _tiles(), _dicts()
-    own = {1: dict(res_tol=1e-2), 3: dict(max_iter=12, prune="final"), 4: dict(res_tol=0.0, max_iter=5)}
+    own = {1: dict(res_tol=1e-2), 3: dict(max_iter=12, prune="final"), 4: dict(res_tol=0.0, max_iter=5),
+           5: dict(prec="bf16"), 2: dict(prec="f16")}
     note("serving: per-tile parameters")
     with cs.Server(K=K, S=S, res_tol=TOL, hbm_budget_bytes=1 << 30, batch_pixels=32768, chunk_pixels=4096) as srv:
         ids = {N: srv.add_dict(A) for N, A in dicts.items()}

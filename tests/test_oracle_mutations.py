@@ -74,6 +74,13 @@ MUTATIONS = [
      "top = np.maximum(srt[:, 0] if scale is None else np.asarray(scale, dtype=np.float64), 1e-300)",
      "top = np.maximum(srt[:, 0], 1e-300)"),
     ("ordered-gap-kth-vs-first", "return (srt[:, k - 1] - nxt) / top", "return (srt[:, 0] - nxt) / top"),
+    ("sel-gap-l1-cancelling-sum", "l1 = np.max(np.abs(ra) @ np.abs(A), axis=1)",
+     "l1 = np.max(np.abs(ra @ A), axis=1)"),
+    ("sel-gap-l1-max-r", "l1 = np.max(np.abs(ra) @ np.abs(A), axis=1)", "l1 = np.max(np.abs(ra), axis=1)"),
+    ("bf16-ties-away", "keep = (bits >> 16) & 1                      # lowest kept bit: ties go to the even one",
+     "keep = 1 + 0 * bits"),
+    ("bf16-truncate", "rounded = ((bits + 0x7FFF + keep) >> 16) << 16", "rounded = (bits >> 16) << 16"),
+    ("corr-format-unrounded-r", "p = round_to_format(ra, corr_format) @ Acorr", "p = ra @ Acorr"),
     ("pivot-ratio-infinite", "return np.min(d / np.maximum(g, 1e-300), axis=1)",
      "return np.full(cols.shape[0], np.inf)"),
     ("pivot-ratio-unnormalised", "return np.min(d / np.maximum(g, 1e-300), axis=1)",
