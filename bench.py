@@ -393,6 +393,11 @@ def leg_protocol(torch, cs, W, dev, stream, samples):
                                                                      eps=PROTOCOL_EPS)
             runs[f"admm lambda={lam:g}"] = lambda lam=lam: cs.admm(A, Y, lam=lam, alpha=ADMM_ALPHA,
                                                                    max_iter=PROTOCOL_CONVEX_CAP, eps=PROTOCOL_EPS)
+            # the other reading of Alg. 2 step 2's threshold (lambda / alpha:
+            # the same LASSO as FISTA's at weight lambda)
+            runs[f"admm lambda={lam:g} threshold lambda/alpha"] = lambda lam=lam: cs.admm(
+                A, Y, lam=lam, alpha=ADMM_ALPHA, max_iter=PROTOCOL_CONVEX_CAP, eps=PROTOCOL_EPS,
+                threshold="standard")
         for kap in c["kappas"]:
             runs[f"gomp kappa={kap}"] = lambda kap=kap: cs.gomp(A, Y, K=kap, S=kap // 5, eps=PROTOCOL_EPS,
                                                                 pivot_fallback=1e-6)

@@ -444,6 +444,118 @@ def check_round_to_format(orc):
     assert orc.gomp(np.eye(2), y, K=1, S=1, max_iter=1, corr_format="bf16")["support"][0].tolist() == [0]
 
 
+# ------------------------------------------------- complex greedy solvers
+
+def check_greedy_complex_real_case(orc):
+    """With real A and y and every atom its own group, the complex gOMP,
+    CoSaMP and BIHT are the real ones (same supports, same x to 1e-10)."""
+    rng = np.random.default_rng(3)
+    M, N, P = 24, 60, 12
+    A = rng.standard_normal((M, N)) / math.sqrt(M)
+    X = np.zeros((P, N))
+    for p in range(P):
+        X[p, rng.choice(N, 4, replace=False)] = rng.standard_normal(4)
+    Y = X @ A.T + 0.01 * rng.standard_normal((P, M))
+    pairs = ((orc.gomp_complex(A, Y, K=5, S=2, res_tol=1e-6), orc.gomp(A, Y, K=5, S=2, res_tol=1e-6)),
+             (orc.cosamp_complex(A, Y, K=4, max_iter=6), orc.cosamp(A, Y, K=4, max_iter=6)),
+             (orc.biht_complex(A, Y, K=4, max_iter=6, mu=0.3), orc.biht(A, Y, K=4, max_iter=6, mu=0.3)))
+    for got, ref in pairs:
+        assert np.array_equal(got["support"], ref["support"])
+        assert np.abs(got["X"] - ref["X"]).max() < 1e-10
+        assert np.abs(got["X"].imag).max() == 0.0
+        assert np.array_equal(got["iters"], ref["iters"])
+
+
+def check_greedy_complex_recovery_and_phase(orc):
+    """Complex Gaussian A (M = 20, N = 40), noiseless y of a 3-sparse complex
+    x: gOMP (S = 1, K = 3), CoSaMP (K = 3) and BIHT (K = 3, mu = 0.5) recover
+    x exactly; y -> e^{i phi} y gives x -> e^{i phi} x with the same support
+    (the correlation is A^* r, so |p| is phase-blind)."""
+    rng = np.random.default_rng(8)
+    M, N, P = 20, 40, 6
+    A = (rng.standard_normal((M, N)) + 1j * rng.standard_normal((M, N))) / math.sqrt(2 * M)
+    X = np.zeros((P, N), dtype=complex)
+    for p in range(P):
+        X[p, rng.choice(N, 3, replace=False)] = (1.0 + rng.random(3)) * np.exp(2j * np.pi * rng.random(3))
+    Y = X @ A.T
+    ph = np.exp(0.7j)
+    for fn in (lambda y: orc.gomp_complex(A, y, K=3, S=1),
+               lambda y: orc.cosamp_complex(A, y, K=3, max_iter=8),
+               lambda y: orc.biht_complex(A, y, K=3, max_iter=60, mu=0.5)):
+        o = fn(Y)
+        assert np.abs(o["X"] - X).max() < 1e-9
+        o2 = fn(Y * ph)
+        assert np.array_equal(o2["support"], o["support"])
+        assert np.abs(o2["X"] - o["X"] * ph).max() < 1e-9
+
+
+def check_greedy_complex_unitary_dft(orc):
+    """A = the unitary DFT synthesis (M = N = 16), a real y, conjugate pairs
+    as groups: gOMP with S = 1 and K = max_iter = 3 picks the three groups of
+    largest |Psi^* y| in order and returns x = Psi^* y on their bins (a
+    unitary A makes every least squares a projection); the x is
+    conjugate-symmetric and A x is real."""
+    N = 16
+    n = np.arange(N)
+    Psi = np.exp(2j * np.pi * np.outer(n, n) / N) / math.sqrt(N)
+    y = np.random.default_rng(4).standard_normal((1, N))
+    groups = orc.conj_pair_groups(N)
+    assert [g.tolist() for g in groups[:3]] == [[0], [1, 15], [2, 14]] and groups[-1].tolist() == [8]
+    o = orc.gomp_complex(Psi, y, K=3, S=1, max_iter=3, groups=groups)
+    p = (y @ np.conj(Psi))[0]
+    score = np.array([np.sqrt(np.mean(np.abs(p[g]) ** 2)) for g in groups])
+    top = np.argsort(-score, kind="stable")[:3]
+    bins = np.sort(np.concatenate([groups[g] for g in top]))
+    sup = o["support"][0]
+    assert sup[sup >= 0].tolist() == bins.tolist()
+    ref = np.zeros(N, dtype=complex)
+    ref[bins] = p[bins]
+    assert np.abs(o["X"][0] - ref).max() < 1e-12
+    assert np.abs(o["X"][0][1:][::-1] - np.conj(o["X"][0][1:])).max() < 1e-12
+    assert np.abs((o["X"] @ Psi.T).imag).max() < 1e-12
+    # a pair scores |p_k| (the RMS over its two equal members), not less: with
+    # x_0 = 1 and |x_2| = |x_14| = 1.2 the pair comes first
+    xs = np.zeros(N, dtype=complex)
+    xs[0], xs[2], xs[14] = 1.0, 1.2j, -1.2j
+    f = (Psi @ xs).real[None, :]
+    o = orc.gomp_complex(Psi, f, K=1, S=1, max_iter=1, groups=groups)
+    assert o["support"][0].tolist() == [2, 14]
+
+
+def check_greedy_complex_conjugate_pairs(orc):
+    """A = Phi Psi for a real Phi (M = 14 of N = 24 bands) and the DFT basis,
+    y = Phi f real: with conjugate pairs as groups, every solver returns a
+    conjugate-symmetric x (x_{N-k} = conj(x_k)), a support closed under
+    k <-> N-k, and a real A x; a spectrum of two pairs and the DC bin is
+    recovered exactly by gOMP (S = 1, K = 3)."""
+    N, M = 24, 14
+    n = np.arange(N)
+    Psi = np.exp(2j * np.pi * np.outer(n, n) / N) / math.sqrt(N)
+    rows = np.sort(np.random.default_rng(5).choice(N, M, replace=False))
+    A = Psi[rows]
+    groups = orc.conj_pair_groups(N)
+    xs = np.zeros((1, N), dtype=complex)
+    xs[0, 0] = 1.5
+    for k, v in ((3, 1.0 - 0.5j), (7, -0.8 + 0.3j)):
+        xs[0, k], xs[0, N - k] = v, np.conj(v)
+    f = (xs @ Psi.T).real
+    o = orc.gomp_complex(A, f[:, rows], K=3, S=1, groups=groups)
+    assert np.abs(o["X"] - xs).max() < 1e-10
+    rng = np.random.default_rng(6)
+    F = rng.standard_normal((5, N))
+    Y = F[:, rows]
+    for fn in (lambda y: orc.gomp_complex(A, y, K=3, S=1, groups=groups),
+               lambda y: orc.cosamp_complex(A, y, K=1, max_iter=5, groups=groups),
+               lambda y: orc.biht_complex(A, y, K=2, max_iter=5, mu=0.3, groups=groups)):
+        o = fn(Y)
+        X = o["X"]
+        assert np.abs(X[:, 1:][:, ::-1] - np.conj(X[:, 1:])).max() < 1e-10
+        assert np.abs((X @ A.T).imag).max() < 1e-10
+        for row in o["support"]:
+            s = set(int(v) for v in row if v >= 0)
+            assert s == {(N - v) % N for v in s}
+
+
 # ---------------------------------------------------------------- CoSaMP
 
 def check_cosamp_orthonormal(orc):
@@ -881,6 +993,8 @@ ORACLE_CHECKS = [
     check_gomp_is_omp_when_S1, check_gomp_orthonormal, check_gomp_exact_recovery,
     check_gomp_brute_force, check_gomp_prune_invariants, check_gomp_no_reselect,
     check_gomp_stop, check_gomp_final_prune, check_gomp_diagnostics_by_hand, check_round_to_format,
+    check_greedy_complex_real_case, check_greedy_complex_recovery_and_phase, check_greedy_complex_unitary_dft,
+    check_greedy_complex_conjugate_pairs,
     check_cosamp_biht_res_tol,
     check_cosamp_orthonormal, check_cosamp_recovery, check_cosamp_no_resolve,
     check_biht_orthonormal, check_biht_first_step, check_biht_second_step_mu,

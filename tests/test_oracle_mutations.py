@@ -18,6 +18,7 @@ import oracle_pins as pins
 ORACLE_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
 SRC = os.path.join(ORACLE_DIR, "cs.py")
 PROTOCOL_SRC = os.path.join(ORACLE_DIR, "protocol.py")
+COMPLEX_SRC = os.path.join(ORACLE_DIR, "greedy_complex.py")
 
 # (id, text to replace, replacement[, which occurrence (1 = first)])
 MUTATIONS = [
@@ -107,6 +108,22 @@ PROTOCOL_MUTATIONS = [
 ]
 
 
+# mistakes planted in the complex greedy solvers (the DFT basis)
+COMPLEX_MUTATIONS = [
+    ("gompc-transpose-not-adjoint", "    Ah = np.conj(A)\n    fin = _finite_rows(Y)\n    Yc = np.where(fin[:, None], Y, 0.0)\n    ynorm = np.linalg.norm(Yc, axis=1)\n    x = np.zeros((P, N), dtype=np.complex128)\n    r = Yc.copy()\n    c = [",
+     "    Ah = A\n    fin = _finite_rows(Y)\n    Yc = np.where(fin[:, None], Y, 0.0)\n    ynorm = np.linalg.norm(Yc, axis=1)\n    x = np.zeros((P, N), dtype=np.complex128)\n    r = Yc.copy()\n    c = ["),
+    ("lstsq-complex-no-conj", "return np.linalg.solve(R, np.conj(Q).T @ y)", "return np.linalg.solve(R, Q.T @ y)"),
+    ("group-score-one-member", "a2[:, np.where(valid, tab, 0)], 0.0).sum(axis=2)",
+     "a2[:, np.where(valid, tab, 0)], 0.0)[:, :, :1].sum(axis=2)"),
+    ("pair-groups-shifted", "out.append(np.array([k, N - k]))", "out.append(np.array([k, N - k - 1]))"),
+    ("gompc-no-mask", "            allowed[j, c[pix]] = False\n", "            pass\n"),
+    ("gompc-prune-no-resolve", "                xp[qc] = lstsq_complex(A, Yc[pix], qc)\n            r_new",
+     "                xp[qc] = np.zeros(N, dtype=np.complex128)[qc] + 0 * xp[qc]\n            r_new"),
+    ("cosampc-K-not-2K", "theta = _top_groups(sc, 2 * K)", "theta = _top_groups(sc, K)"),
+    ("bihtc-no-mu", "u = xa + mu * ((Yc[a] - xa @ A.T) @ Ah)", "u = xa + ((Yc[a] - xa @ A.T) @ Ah)"),
+]
+
+
 # Errors a wrong oracle raises on its own (a failed comparison, a shape or
 # value error of NumPy from a wrong index or operand, a floating-point trap);
 # anything else (a missing name, a type error) means the check could not run.
@@ -130,6 +147,7 @@ def _mutant(old, new, src=SRC, nth=1):
         text = _replace_nth(text, old, new, nth)
     mod = types.ModuleType("oracle_mutant")
     mod.__file__ = src
+    mod.__package__ = "oracle"   # relative imports of the copy resolve in the package
     exec(compile(text, src + ":mutant", "exec"), mod.__dict__)
     whole = types.ModuleType("oracle_whole")
     for name in dir(oracle):
@@ -151,7 +169,7 @@ def _failing_checks(mod):
     return []
 
 
-@pytest.mark.parametrize("src", [SRC, PROTOCOL_SRC], ids=["cs", "protocol"])
+@pytest.mark.parametrize("src", [SRC, PROTOCOL_SRC, COMPLEX_SRC], ids=["cs", "protocol", "greedy_complex"])
 def test_unmutated_copy_passes_every_check(src):
     """The harness itself: a copy of the oracle with nothing planted passes
     every pin, so a failure under a mutation is the mutation's doing."""
@@ -171,4 +189,10 @@ def test_pins_catch_mutation(mut):
 @pytest.mark.parametrize("mid,old,new", PROTOCOL_MUTATIONS, ids=[m[0] for m in PROTOCOL_MUTATIONS])
 def test_pins_catch_protocol_mutation(mid, old, new):
     failed = _failing_checks(_mutant(old, new, PROTOCOL_SRC))
+    assert failed, f"no pin catches mutation {mid}"
+
+
+@pytest.mark.parametrize("mid,old,new", COMPLEX_MUTATIONS, ids=[m[0] for m in COMPLEX_MUTATIONS])
+def test_pins_catch_complex_mutation(mid, old, new):
+    failed = _failing_checks(_mutant(old, new, COMPLEX_SRC))
     assert failed, f"no pin catches mutation {mid}"
