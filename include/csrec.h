@@ -88,6 +88,9 @@ extern "C" {
 #define CSREC_SOLVER_FISTA_HERMITIAN 6
 #define CSREC_SOLVER_ADMM_HERMITIAN 7
 #define CSREC_SOLVER_ADMM_COMPLEX 8
+#define CSREC_SOLVER_GOMP_HERMITIAN 9
+#define CSREC_SOLVER_COSAMP_HERMITIAN 10
+#define CSREC_SOLVER_BIHT_HERMITIAN 11
 
 #define CSREC_MAX_N 256
 
@@ -224,6 +227,46 @@ int32_t csrec_cosamp(const csrec_problem* problem, const csrec_cosamp_params* pa
 /* BIHT (Alg. 4 / binary IHT): outputs as csrec_gomp.  ONE_BIT returns x / ||x||. */
 int32_t csrec_biht(const csrec_problem* problem, const csrec_biht_params* params, float* X,
                    int32_t* support, csrec_pixel_stats* stats);
+
+/* gOMP (Alg. 3) with the complex DFT basis of Section II for REAL
+ * measurements (a real Phi, real spectra): A = Phi Psi is M x N complex with
+ * conjugate-symmetric columns, A[:, N-k] = conj(A[:, k]), so that for every
+ * real residual r the correlations p = A^* r of bins k and N-k have equal
+ * magnitude, and the least squares on a support closed under k <-> N-k keeps
+ * x conjugate-symmetric.  The bins {k, N-k} are therefore selected, kept and
+ * pruned together: params->K, S and max_iter count conjugate-pair groups
+ * ({0}, {k, N-k} for 0 < k < N/2, {N/2} for even N), the score of a group is
+ * |p_k|, the prune keeps the K groups of largest |x_k|.  max_iter 0 means
+ * min(K, floor(M / (2 S))) (a pair holds two real unknowns); 2 S max_iter <=
+ * min(M, 96), 2 K <= 96.  pivot_fallback must be 0 (CSREC_E_UNSUPPORTED
+ * otherwise); prec as csrec_gomp.
+ *
+ * problem->A is M x N complex (interleaved (re, im) FP32 pairs; only columns
+ * 0 .. floor(N/2) are read, and A[:, 0] (and A[:, N/2], N even) are taken as
+ * real); problem->Y is P x M REAL.  X (P x N complex) receives the full
+ * conjugate-symmetric x; support (P x 2K int32, nullable) its bins in
+ * ascending order, -1 padded; stats as csrec_gomp.  Needs the workspace of
+ * csrec_workspace_bytes(CSREC_SOLVER_GOMP_HERMITIAN, ...): the real M x
+ * 2 (floor(N/2) + 1) dictionary of the groups, its Gram matrix and the
+ * kernel's copies, formed on the device on every call.  M <= 96,
+ * 2 (floor(N/2) + 1) <= CSREC_MAX_N. */
+int32_t csrec_gomp_hermitian(const csrec_problem* problem, const csrec_gomp_params* params, float* X,
+                             int32_t* support, csrec_pixel_stats* stats);
+
+/* CoSaMP (Alg. 5) and backtracking IHT (Alg. 4) with the complex DFT basis
+ * for REAL measurements, in the setting of csrec_gomp_hermitian: conjugate
+ * pairs are the selection and prune units, params->K counts groups (CoSaMP
+ * selects 2K groups and keeps K; BIHT selects K and keeps K), the scores are
+ * |(A^* r)_k| (CoSaMP) and |x_k + mu (A^* r)_k| (BIHT), the merged support's
+ * atoms at most 6K (CoSaMP) or 4K (BIHT) <= min(M, 96).  BIHT mode must be
+ * CSREC_BIHT_REAL.  problem, X, support (P x 2K bins), stats and workspace
+ * (csrec_workspace_bytes with CSREC_SOLVER_COSAMP_HERMITIAN /
+ * CSREC_SOLVER_BIHT_HERMITIAN) as csrec_gomp_hermitian; prec as
+ * csrec_cosamp / csrec_biht. */
+int32_t csrec_cosamp_hermitian(const csrec_problem* problem, const csrec_cosamp_params* params, float* X,
+                               int32_t* support, csrec_pixel_stats* stats);
+int32_t csrec_biht_hermitian(const csrec_problem* problem, const csrec_biht_params* params, float* X,
+                             int32_t* support, csrec_pixel_stats* stats);
 
 /* gOMP (Alg. 3) without any device allocation, for callers that cannot
  * allocate: code under HIP graph capture, tight serving loops, harnesses that

@@ -463,6 +463,75 @@ def gomp_noalloc(A, Y, K: int, S: int = 1, max_iter: int = 0, res_tol: float = 0
     return X[:P], Sp[:P], _stats_view(st[:P])
 
 
+def gomp_hermitian(A, Y, K: int, S: int = 1, max_iter: int = 0, res_tol: float = 0.0, eps: float = 0.0,
+                   prune: str = "each", prec: str = "f32", stream=None):
+    """gOMP (Alg. 3) with the DFT basis for real measurements: A (M x N
+    complex64) with conjugate-symmetric columns (A = Phi Psi, Phi real), Y
+    (P x M float32).  K, S and max_iter count conjugate-pair groups ({0},
+    {k, N-k}, {N/2}), selected and pruned together.  Returns (X (P x N
+    complex64, conjugate-symmetric), support (P x 2K bins, ascending, -1
+    padded), stats)."""
+    torch = _torch()
+    lib = library()
+    _check_dev("A", A, torch.complex64)
+    M, N = A.shape
+    _check_dev("Y", Y, torch.float32)
+    P = Y.shape[0]
+    if Y.shape[1] != M:
+        raise ValueError("Y must be P x M")
+    pb = _problem(A, Y, P, stream)
+    prm, _ = _params("gomp", A, P, dict(K=K, S=S, max_iter=max_iter, res_tol=res_tol, eps=eps, prune=prune,
+                                         prec=prec, pivot_fallback=0.0))
+    ws = _workspace(lib, _lib.SOLVER_GOMP_HERMITIAN, pb, prm, A.device)
+    X = torch.empty((P, N), dtype=torch.complex64, device=A.device)
+    Sp = torch.empty((max(P, 1), 2 * K), dtype=torch.int32, device=A.device)
+    st = torch.empty((max(P, 1), 4), dtype=torch.int32, device=A.device)
+    _lib.check(lib.csrec_gomp_hermitian(ctypes.byref(pb), ctypes.byref(prm), _ptr(X), _ptr(Sp), _ptr(st)),
+               "csrec_gomp_hermitian")
+    _keep_alive(ws, A.device, stream)
+    return X, Sp[:P], _stats_view(st[:P])
+
+
+def _greedy_hermitian(solver, entry, sid, A, Y, K, kw, stream):
+    torch = _torch()
+    lib = library()
+    _check_dev("A", A, torch.complex64)
+    M, N = A.shape
+    _check_dev("Y", Y, torch.float32)
+    P = Y.shape[0]
+    if Y.shape[1] != M:
+        raise ValueError("Y must be P x M")
+    pb = _problem(A, Y, P, stream)
+    prm, _ = _params(solver, A, P, dict(kw, K=K))
+    ws = _workspace(lib, sid, pb, prm, A.device)
+    X = torch.empty((P, N), dtype=torch.complex64, device=A.device)
+    Sp = torch.empty((max(P, 1), 2 * K), dtype=torch.int32, device=A.device)
+    st = torch.empty((max(P, 1), 4), dtype=torch.int32, device=A.device)
+    fn = getattr(lib, entry)
+    _lib.check(fn(ctypes.byref(pb), ctypes.byref(prm), _ptr(X), _ptr(Sp), _ptr(st)), entry)
+    _keep_alive(ws, A.device, stream)
+    return X, Sp[:P], _stats_view(st[:P])
+
+
+def cosamp_hermitian(A, Y, K: int, max_iter: int = 30, eps: float = 0.0, res_tol: float = 0.0,
+                     prec: str = "f32", stream=None):
+    """CoSaMP (Alg. 5) with the DFT basis for real measurements, conjugate
+    pairs as units (K counts groups): A (M x N complex64, conjugate-symmetric
+    columns), Y (P x M float32).  Returns (X (P x N complex64), support
+    (P x 2K bins), stats)."""
+    return _greedy_hermitian("cosamp", "csrec_cosamp_hermitian", _lib.SOLVER_COSAMP_HERMITIAN, A, Y, K,
+                             dict(max_iter=max_iter, eps=eps, res_tol=res_tol, prec=prec), stream)
+
+
+def biht_hermitian(A, Y, K: int, max_iter: int = 100, mu: float = 0.1, eps: float = 0.0, res_tol: float = 0.0,
+                   prec: str = "f32", stream=None):
+    """Backtracking IHT (Alg. 4) with the DFT basis for real measurements,
+    conjugate pairs as units (K counts groups).  As cosamp_hermitian."""
+    return _greedy_hermitian("biht", "csrec_biht_hermitian", _lib.SOLVER_BIHT_HERMITIAN, A, Y, K,
+                             dict(max_iter=max_iter, mu=mu, eps=eps, res_tol=res_tol, mode="real", Ysign=None,
+                                  prec=prec), stream)
+
+
 def cosamp(A, Y, K: int, max_iter: int = 30, eps: float = 0.0, res_tol: float = 0.0,
            prec: str = "f32", stream=None):
     """CoSaMP (Alg. 5) on every pixel: returns (X, support, stats)."""

@@ -19,6 +19,7 @@ PREC = {"f32": 0, "bf16": 1, "f16": 2}
 FLAG_CONVERGED, FLAG_ITER_CAP, FLAG_FP64_FALLBACK, FLAG_NONFINITE = 1, 2, 4, 8
 SOLVER_FISTA, SOLVER_GOMP, SOLVER_COSAMP, SOLVER_BIHT, SOLVER_ADMM = 0, 1, 2, 3, 4
 SOLVER_FISTA_COMPLEX, SOLVER_FISTA_HERMITIAN, SOLVER_ADMM_HERMITIAN, SOLVER_ADMM_COMPLEX = 5, 6, 7, 8
+SOLVER_GOMP_HERMITIAN, SOLVER_COSAMP_HERMITIAN, SOLVER_BIHT_HERMITIAN = 9, 10, 11
 ADMM_THR = {"paper": 0, "standard": 1}
 PRUNE = {"each": 0, "final": 1}
 BIHT_MODE = {"real": 0, "one_bit": 1}
@@ -167,6 +168,12 @@ SIGNATURES = {
                                     ctypes.c_void_p]),
     "csrec_gomp_noalloc": (ctypes.c_int32, [_P(Problem), _P(GompParams), ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_void_p]),
+    "csrec_gomp_hermitian": (ctypes.c_int32, [_P(Problem), _P(GompParams), ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p]),
+    "csrec_cosamp_hermitian": (ctypes.c_int32, [_P(Problem), _P(CosampParams), ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p]),
+    "csrec_biht_hermitian": (ctypes.c_int32, [_P(Problem), _P(BihtParams), ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p]),
     "csrec_cosamp": (ctypes.c_int32, [_P(Problem), _P(CosampParams), ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),
     "csrec_biht": (ctypes.c_int32, [_P(Problem), _P(BihtParams), ctypes.c_void_p, ctypes.c_void_p,

@@ -114,6 +114,36 @@ int fill_gomp(const csrec_problem* p, const csrec_gomp_params* q, GreedyLaunch& 
     return CSREC_OK;
 }
 
+// gOMP with the DFT basis on real measurements: K, S and max_iter count
+// conjugate-pair groups, each up to two real unknowns.
+int fill_gomp_hermitian(const csrec_problem* p, const csrec_gomp_params* q, GreedyLaunch& l) {
+    int e = check_problem(p, true);
+    if (e) return e;
+    if (!q || q->struct_size != (int32_t)sizeof(csrec_gomp_params)) return CSREC_E_INVAL;
+    if (q->K < 1 || q->S < 1 || q->S > 8 || q->max_iter < 0) return CSREC_E_INVAL;
+    if (!finite_nonneg(q->res_tol) || !finite_nonneg(q->eps) || !finite_nonneg(q->pivot_fallback))
+        return CSREC_E_INVAL;
+    if (q->prune != CSREC_PRUNE_EACH && q->prune != CSREC_PRUNE_FINAL) return CSREC_E_INVAL;
+    if ((e = check_prec(q->prec))) return e;
+    if (q->pivot_fallback > 0) return CSREC_E_UNSUPPORTED;
+    if (p->M > 96 || pair_dict_atoms(p->N) > CSREC_MAX_N) return CSREC_E_UNSUPPORTED;
+    const int imax = q->max_iter > 0 ? q->max_iter : (q->K < p->M / (2 * q->S) ? q->K : p->M / (2 * q->S));
+    if (imax < 1) return CSREC_E_INVAL;
+    if (2 * q->S * imax > p->M || 2 * q->S * imax > GOMP_CMAX || 2 * q->K > GOMP_CMAX) return CSREC_E_SHAPE;
+    if ((e = gomp_coop_supported_grp(p->M, pair_dict_atoms(p->N), q->K, q->S, imax))) return e;
+    l = GreedyLaunch{};
+    l.kind = GREEDY_GOMP;
+    l.K = q->K;
+    l.S = q->S;
+    l.max_iter = imax;
+    l.prune = q->prune;
+    l.prec = q->prec;
+    l.res_tol = (float)q->res_tol;
+    l.eps = (float)q->eps;
+    l.pivot_fallback = 0.0;
+    return CSREC_OK;
+}
+
 int fill_cosamp(const csrec_problem* p, const csrec_cosamp_params* q, GreedyLaunch& l) {
     int e = check_problem(p, true);
     if (e) return e;
@@ -159,6 +189,42 @@ int fill_biht(const csrec_problem* p, const csrec_biht_params* q, GreedyLaunch& 
     l.mu = (float)q->mu;
     l.Ysign = q->Ysign;
     return CSREC_OK;
+}
+
+// CoSaMP and BIHT with the DFT basis on real measurements: K counts
+// conjugate-pair groups (up to two atoms each).
+int fill_other_hermitian(const csrec_problem* p, int kind, int32_t K, int32_t max_iter, double eps,
+                         double res_tol, double mu, int32_t prec, GreedyLaunch& l) {
+    int e = check_problem(p, true);
+    if (e) return e;
+    if (K < 1 || max_iter < 0 || !finite_nonneg(eps) || !finite_nonneg(res_tol) || !std::isfinite(mu))
+        return CSREC_E_INVAL;
+    if ((e = check_prec(prec))) return e;
+    const int merged = (kind == GREEDY_COSAMP ? 3 : 2) * 2 * K;   // atoms of the merged support at most
+    if (merged > p->M || merged > GREEDY_CMAX) return CSREC_E_SHAPE;
+    if (p->M > 96 || pair_dict_atoms(p->N) > CSREC_MAX_N) return CSREC_E_UNSUPPORTED;
+    if ((e = coop_other_supported_grp(kind, p->M, pair_dict_atoms(p->N), K))) return e;
+    l = GreedyLaunch{};
+    l.kind = static_cast<GreedyKind>(kind);
+    l.K = K;
+    l.S = 1;
+    l.max_iter = max_iter;
+    l.prec = prec;
+    l.res_tol = (float)res_tol;
+    l.eps = (float)eps;
+    l.mu = (float)mu;
+    return CSREC_OK;
+}
+
+int fill_cosamp_hermitian(const csrec_problem* p, const csrec_cosamp_params* q, GreedyLaunch& l) {
+    if (!q || q->struct_size != (int32_t)sizeof(csrec_cosamp_params)) return CSREC_E_INVAL;
+    return fill_other_hermitian(p, GREEDY_COSAMP, q->K, q->max_iter, q->eps, q->res_tol, 0.0, q->prec, l);
+}
+
+int fill_biht_hermitian(const csrec_problem* p, const csrec_biht_params* q, GreedyLaunch& l) {
+    if (!q || q->struct_size != (int32_t)sizeof(csrec_biht_params)) return CSREC_E_INVAL;
+    if (q->mode != CSREC_BIHT_REAL) return q->mode == CSREC_BIHT_ONE_BIT ? CSREC_E_UNSUPPORTED : CSREC_E_INVAL;
+    return fill_other_hermitian(p, GREEDY_BIHT, q->K, q->max_iter, q->eps, q->res_tol, q->mu, q->prec, l);
 }
 
 void fill_problem(const csrec_problem* p, GreedyLaunch& l) {
@@ -253,6 +319,18 @@ int32_t csrec_workspace_bytes(int32_t solver, const csrec_problem* problem, cons
         case CSREC_SOLVER_GOMP:
             e = fill_gomp(problem, static_cast<const csrec_gomp_params*>(params), l);
             break;
+        case CSREC_SOLVER_GOMP_HERMITIAN:
+            if ((e = fill_gomp_hermitian(problem, static_cast<const csrec_gomp_params*>(params), l))) return e;
+            *bytes = problem->P > 0 ? greedy_hermitian_workspace(problem->M, problem->N) : 0;
+            return CSREC_OK;
+        case CSREC_SOLVER_COSAMP_HERMITIAN:
+            if ((e = fill_cosamp_hermitian(problem, static_cast<const csrec_cosamp_params*>(params), l))) return e;
+            *bytes = problem->P > 0 ? greedy_hermitian_workspace(problem->M, problem->N) : 0;
+            return CSREC_OK;
+        case CSREC_SOLVER_BIHT_HERMITIAN:
+            if ((e = fill_biht_hermitian(problem, static_cast<const csrec_biht_params*>(params), l))) return e;
+            *bytes = problem->P > 0 ? greedy_hermitian_workspace(problem->M, problem->N) : 0;
+            return CSREC_OK;
         case CSREC_SOLVER_COSAMP:
             e = fill_cosamp(problem, static_cast<const csrec_cosamp_params*>(params), l);
             break;
@@ -309,6 +387,51 @@ int32_t csrec_gomp(const csrec_problem* problem, const csrec_gomp_params* params
     if (e) return e;
     fill_problem(problem, l);
     return run_greedy(l, X, support, stats);
+}
+
+int32_t csrec_gomp_hermitian(const csrec_problem* problem, const csrec_gomp_params* params, float* X,
+                             int32_t* support, csrec_pixel_stats* stats) {
+    GreedyLaunch l{};
+    int e = fill_gomp_hermitian(problem, params, l);
+    if (e) return e;
+    fill_problem(problem, l);
+    if (l.P == 0) return CSREC_OK;
+    if (!X) return CSREC_E_INVAL;
+    l.X = X;
+    l.support = support;
+    l.stats = stats;
+    if (!l.workspace || l.workspace_bytes < greedy_hermitian_workspace(l.M, l.N)) return CSREC_E_WORKSPACE;
+    return gomp_hermitian_launch(l);
+}
+
+namespace {
+int run_other_hermitian(GreedyLaunch& l, const csrec_problem* problem, float* X, int32_t* support,
+                        csrec_pixel_stats* stats) {
+    fill_problem(problem, l);
+    if (l.P == 0) return CSREC_OK;
+    if (!X) return CSREC_E_INVAL;
+    l.X = X;
+    l.support = support;
+    l.stats = stats;
+    if (!l.workspace || l.workspace_bytes < greedy_hermitian_workspace(l.M, l.N)) return CSREC_E_WORKSPACE;
+    return other_hermitian_launch(l);
+}
+}  // namespace
+
+int32_t csrec_cosamp_hermitian(const csrec_problem* problem, const csrec_cosamp_params* params, float* X,
+                               int32_t* support, csrec_pixel_stats* stats) {
+    GreedyLaunch l{};
+    const int e = fill_cosamp_hermitian(problem, params, l);
+    if (e) return e;
+    return run_other_hermitian(l, problem, X, support, stats);
+}
+
+int32_t csrec_biht_hermitian(const csrec_problem* problem, const csrec_biht_params* params, float* X,
+                             int32_t* support, csrec_pixel_stats* stats) {
+    GreedyLaunch l{};
+    const int e = fill_biht_hermitian(problem, params, l);
+    if (e) return e;
+    return run_other_hermitian(l, problem, X, support, stats);
 }
 
 }  // extern "C"

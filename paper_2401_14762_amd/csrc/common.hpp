@@ -180,6 +180,16 @@ size_t greedy_group_workspace(const GreedyLaunch& proto_max, int64_t batch_pixel
 int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* items, int nitems,
                         int64_t batch_pixels, void* ws, void* table_host, void* table_dev, hipStream_t stream);
 int greedy_gram(const float* A, int M, int N, float* G32, double* G64, hipStream_t stream);
+// gOMP with the DFT basis on real measurements: a.A is M x N complex
+// (conjugate-symmetric columns), a.Y real, a.X P x N complex, a.support P x 2K
+// bins; K, S, max_iter count conjugate-pair groups.  Workspace: the real
+// dictionary of the groups (M x pair_dict_atoms(N)), its Gram matrix and the
+// on-chip kernel's copies.
+int pair_dict_atoms(int Nb);
+size_t greedy_hermitian_workspace(int M, int Nb);
+int gomp_hermitian_launch(const GreedyLaunch& a);
+// CoSaMP (Alg. 5) and BIHT (Alg. 4) in the same setting (a.kind)
+int other_hermitian_launch(const GreedyLaunch& a);
 
 // gOMP with the least-squares state on chip (16 lanes per pixel, MFMA
 // correlation).  Every solve reads a per-dictionary buffer of
@@ -189,9 +199,13 @@ size_t gomp_coop_lds_floats(int MP, int CM, int K);
 size_t gomp_coop_dict_floats(int M, int N);
 int gomp_coop_supported(int M, int N, int K, int S, int Imax);
 void gomp_coop_prepare(const float* A, int M, int N, float* dictbuf, hipStream_t stream);
+// Nb > 0: conjugate-pair groups of a half-spectrum dictionary (N = 2 (Nb / 2 + 1)
+// real atoms; K, S and Imax count groups; X is P x Nb complex, support P x 2K bins)
 int gomp_coop_launch(const float* Y, float* X, int32_t* support, csrec_pixel_stats* stats, const float* G32,
                      const float* dictbuf, uint32_t* fbflag, int M, int N, int64_t p0, int64_t P, int K, int S,
-                     int Imax, int prune, float res_tol, float eps, double pivot_thr, int prec, hipStream_t stream);
+                     int Imax, int prune, float res_tol, float eps, double pivot_thr, int prec, hipStream_t stream,
+                     int Nb = 0);
+int gomp_coop_supported_grp(int M, int N, int K, int S, int Imax);
 struct GompCoopItem {
     const float* dict;    // gomp_coop_prepare output for this item's A
     const float* Y;
@@ -209,9 +223,12 @@ int gomp_coop_class(int M, int N);   // items of one grouped launch share it (0.
 // CoSaMP (Alg. 5), BIHT (Alg. 4) and one-bit BIHT on the same on-chip design.
 size_t coop_other_lds_floats(int kind, int M, int N, int K);
 int coop_other_supported(int kind, int M, int N, int K);
+// Nb > 0: conjugate-pair groups (as gomp_coop_launch); CoSaMP and BIHT REAL only
 int coop_other_launch(int kind, const float* Y, const int8_t* Ysign, float* X, int32_t* support,
                       csrec_pixel_stats* stats, const float* G32, const float* dictbuf, int M, int N, int64_t p0,
-                      int64_t P, int K, int Imax, float mu, float res_tol, float eps, int prec, hipStream_t stream);
+                      int64_t P, int K, int Imax, float mu, float res_tol, float eps, int prec, hipStream_t stream,
+                      int Nb = 0);
+int coop_other_supported_grp(int kind, int M, int N, int K);
 int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_host, void* table_dev, int K, int S,
                            int prune, float res_tol, float eps, double pivot_thr, int prec, hipStream_t stream);
 

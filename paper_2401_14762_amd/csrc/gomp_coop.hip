@@ -49,6 +49,7 @@ constexpr int kGroups = 4;        // pixels per wavefront
 constexpr int kMaxNG = 4;         // atoms per lane and row: N <= 64 NG
 constexpr int kRowPad = 8;        // rows of the padded copy of A: multiple of 8
 constexpr int kMaxS = 8;
+constexpr int kMaxSel = 2 * kMaxS; // atoms selected per iteration (a conjugate pair is two)
 constexpr int kGJ = 32;           // K up to this: the pruned system is solved in registers
 constexpr int kCU = 6;            // |c| <= 16 kCU entries: per-lane units of the rank and the Gram gather
 constexpr float kFp32Tol = 1e-5f; // relative accuracy an FP32 least squares must keep, or the pixel is redone in FP64
@@ -76,6 +77,8 @@ struct CoopArgs {
     const __bf16* Abf;    // (M8 / 4) x NP x 4: A in BF16, four consecutive rows of an atom together
     const _Float16* Ahf;  // the same in FP16
     int prec;             // precision of the correlation A^T v (CSREC_PREC_*)
+    int grp;              // 1: conjugate-pair groups (the half-spectrum dictionary of a DFT basis)
+    int Nb;               // grp: bins of the complex spectrum (N = 2 (Nb / 2 + 1) real atoms)
 };
 
 __host__ __device__ __forceinline__ int tri(int k) { return k * (k + 1) / 2; }
@@ -139,8 +142,8 @@ struct PixLds {
     float* s;     // solution on c, CM
     float* l;     // temporary, CM
     int* c;       // atoms, CM
-    int* sel;     // this iteration's selected atoms, kMaxS
-    float* bsel;  // their a_j^T y, kMaxS
+    int* sel;     // this iteration's selected atoms, kMaxSel
+    float* bsel;  // their a_j^T y, kMaxSel
     float* Wq;    // K > kGJ: LDL^T triangle of G[q,q], tri(K); K <= kGJ: pivot-row slots, 2 x 36
     float* bq;    // K
     float* sq;    // K
@@ -162,8 +165,8 @@ __host__ __device__ inline LdsPlan lds_plan(int MP, int CM, int K) {
     p.rb = o;
     p.l = o;
     p.sel = p.l + up4(CM);
-    p.bsel = p.sel + kMaxS;
-    p.Wq = p.bsel + kMaxS;
+    p.bsel = p.sel + kMaxSel;
+    p.Wq = p.bsel + kMaxSel;
     const int tail = p.Wq + (K > kGJ ? up4(tri(K)) : 2 * (kGJ + 4));
     o = up4(MP) > tail ? up4(MP) : tail;
     p.W = o; o += up4(tri(CM));
@@ -180,7 +183,7 @@ __host__ __device__ inline LdsPlan lds_plan(int MP, int CM, int K) {
 }
 
 __device__ __forceinline__ PixLds carve(float* base, const CoopArgs& a) {
-    const LdsPlan pl = lds_plan(a.MP, a.CM, a.K);
+    const LdsPlan pl = lds_plan(a.MP, a.CM, a.grp ? 2 * a.K : a.K);   // groups keep up to 2K atoms
     PixLds p;
     p.rb = base + pl.rb;
     p.W = base + pl.W;
@@ -643,6 +646,96 @@ __device__ __forceinline__ void correlate(const CoopArgs& a, const float* rb, in
     }
 }
 
+// Conjugate-pair groups (half-spectrum dictionary of a DFT basis with real
+// measurements): real atom 2g is the real part of bin g, atom 2g + 1 its
+// imaginary part; the bins 0 and, for even Nb, Nb / 2 are real (singleton
+// groups, whose odd atom is never selected).
+__device__ __forceinline__ bool grp_singleton(int g, int Nb) { return g == 0 || ((Nb & 1) == 0 && g == Nb / 2); }
+
+// |x_g|^2 of the group led by entry k of the list c (values s): a pair's
+// atoms are next to each other, 2g then 2g + 1.  Every lane must get the
+// same bits for the same group, so the products and the sum are rounded
+// explicitly (no contraction that could differ between inlined copies).
+// NaN-safe as rank_key.
+__device__ __forceinline__ float grp_key(const float* s, const int* c, int k, int n) {
+    const bool pair = k + 1 < n && c[k + 1] == c[k] + 1;
+    const float a0 = __fmul_rn(s[k], s[k]);
+    const float a = pair ? __fadd_rn(a0, __fmul_rn(s[k + 1], s[k + 1])) : a0;
+    return a <= 3.402823466e38f ? a : -1.f;
+}
+
+// Step 3 over groups: of the groups in c (the n atoms c[0..n), pairs next
+// to each other), the K with largest |x_g| (ties to the lower group), their
+// atoms written to q and vals to qv in rank order.  Returns the number of
+// kept atoms of the lane's pixel.  Called by every lane; no barrier inside.
+template <int U>
+__device__ __forceinline__ int rank_top_groups(bool on, int t, int n, int K, const float* s, const int* c,
+                                               const float* vals, int* q, float* qv) {
+    float vk[U];
+    int ck[U], rk[U], pk[U], sz[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int k = t + 16 * u;
+        const bool lead = on && k < n && (c[k] & 1) == 0;
+        const bool pair = lead && k + 1 < n && c[k + 1] == c[k] + 1;
+        vk[u] = lead ? grp_key(s, c, k, n) : 0.f;
+        ck[u] = lead ? c[k] : 0;
+        sz[u] = lead ? (pair ? 2 : 1) : 0;
+        rk[u] = 0;
+        pk[u] = 0;
+    }
+    if (on) {
+        for (int i = 0; i < n; ++i) {
+            const int ci = c[i];
+            if (ci & 1) continue;
+            const float key = grp_key(s, c, i, n);
+            const int size = (i + 1 < n && c[i + 1] == ci + 1) ? 2 : 1;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool before = key > vk[u] || (key == vk[u] && ci < ck[u]);
+                rk[u] += before ? 1 : 0;
+                pk[u] += before ? size : 0;
+            }
+        }
+    }
+    float kept = 0.f;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int k = t + 16 * u;
+        if (sz[u] > 0 && rk[u] < K) {
+            q[pk[u]] = ck[u];
+            qv[pk[u]] = vals[k];
+            if (sz[u] == 2) {
+                q[pk[u] + 1] = ck[u] + 1;
+                qv[pk[u] + 1] = vals[k + 1];
+            }
+            kept += (float)sz[u];
+        }
+    }
+    return (int)pix_sum(kept);
+}
+
+// Step 3 over groups for the pixels with `on`: keep the K groups of c with
+// largest |x_g|, then s_q = G[q,q]^{-1} b_q on their atoms (pixels padded
+// to the wave's longest list).  Returns the pixel's kept atoms.
+__device__ __forceinline__ int prune_to_q_grp(bool on, int t, int nc, int K, int N, const float* __restrict__ G32,
+                                              const PixLds L) {
+    const int nw = wave_max(on ? nc : 0);
+    int nq;
+    if (nw <= 32)
+        nq = rank_top_groups<2>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+    else if (nw <= 48)
+        nq = rank_top_groups<3>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+    else if (nw <= 64)
+        nq = rank_top_groups<4>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+    else
+        nq = rank_top_groups<kCU>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+    wave_sync();
+    const int nmax = wave_max(on ? nq : 0);
+    solve_list<true>(on, t, nq, nmax, N, G32, L.q, L.bq, L.sq, L.Wq);
+    return nq;
+}
+
 // r = y - sum_k xv[k] A[:, xi[k]] for the lane's m = 4t + j + 64i.
 template <int MSLOT>
 __device__ __forceinline__ void residual(const float* y, float* rnew, const int* xi, const float* xv, int nx,
@@ -675,7 +768,7 @@ __device__ __forceinline__ void residual(const float* y, float* rnew, const int*
     }
 }
 
-template <int MSLOT, int NG>
+template <int MSLOT, int NG, bool GRP>
 __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block, float* lds) {
     const int lane = threadIdx.x;
     const int x = lane & 3, t = lane >> 2;
@@ -718,6 +811,7 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
     bool converged = false, fallback = false;
     float trG = 0.f, trW = 0.f;   // trace(G[c,c]) and trace(G[c,c]^{-1}) (FP64 fallback test)
     int iters = 0, nc = 0, nx = 0;
+    int ng = 0;           // groups in c (GRP: a pair is one group of two atoms)
     bool x_on_q = false;
     float last_d2 = __builtin_nanf(""), rn2 = y2;
     uint32_t mask = 0u;   // bit k: atom 4 NG t + k is in c
@@ -736,26 +830,62 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
         // S rounds of argmax; the winners are appended in selection order.
         // Lane t holds atoms 4 NG t + NG i + g (entry i of accumulator g).
         int nsel = 0;
-        for (int q = 0; q < a.S; ++q) {
-            float bv = -1.f;
-            int bi = -1;
+        if (!GRP) {
+            for (int q = 0; q < a.S; ++q) {
+                float bv = -1.f;
+                int bi = -1;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int g = 0; g < NG; ++g) {
-                    const int k = NG * i + g;
-                    const int n = 4 * NG * t + k;
-                    const float v = fabsf(acc[g][i]);
-                    const bool member = (mask >> k) & 1u;
-                    if (n < N && !member && (bi < 0 || v > bv)) {
-                        bv = v;
-                        bi = n;
+                    for (int g = 0; g < NG; ++g) {
+                        const int k = NG * i + g;
+                        const int n = 4 * NG * t + k;
+                        const float v = fabsf(acc[g][i]);
+                        const bool member = (mask >> k) & 1u;
+                        if (n < N && !member && (bi < 0 || v > bv)) {
+                            bv = v;
+                            bi = n;
+                        }
                     }
+                pix_argmax(bv, bi);
+                if (bi >= 0 && bi / (4 * NG) == t) mask |= 1u << (bi % (4 * NG));
+                if (t == 0) L.sel[q] = bi;
+                nsel += (bi >= 0) ? 1 : 0;   // the valid selections form a prefix
+            }
+        } else {
+            // groups: the score of bin g is |p_g| = |(A^* r)_g|, from its two
+            // real correlations: (1/2) sqrt(p_2g^2 + p_2g+1^2) for a pair (its
+            // atoms carry 2 Re a_g and -2 Im a_g), |p_2g| for a real bin
+            for (int q = 0; q < a.S; ++q) {
+                float bv = -1.f;
+                int bi = -1;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int g = 0; g < NG; g += 2) {
+                        const int k = NG * i + g;
+                        const int n = 4 * NG * t + k;
+                        const int gb = n >> 1;
+                        const float p0 = acc[g][i], p1 = acc[g + 1][i];
+                        const float v = grp_singleton(gb, a.Nb) ? fabsf(p0) : 0.5f * sqrtf(p0 * p0 + p1 * p1);
+                        const bool member = (mask >> k) & 1u;
+                        if (n < N && !member && (bi < 0 || v > bv)) {
+                            bv = v;
+                            bi = gb;
+                        }
+                    }
+                pix_argmax(bv, bi);
+                if (bi >= 0 && (2 * bi) / (4 * NG) == t) mask |= 3u << ((2 * bi) % (4 * NG));
+                if (bi >= 0) {
+                    const bool single = grp_singleton(bi, a.Nb);
+                    if (t == 0) {
+                        L.sel[nsel] = 2 * bi;
+                        if (!single) L.sel[nsel + 1] = 2 * bi + 1;
+                    }
+                    nsel += single ? 1 : 2;
+                    ng += active ? 1 : 0;
                 }
-            pix_argmax(bv, bi);
-            if (bi >= 0 && bi / (4 * NG) == t) mask |= 1u << (bi % (4 * NG));
-            if (t == 0) L.sel[q] = bi;
-            nsel += (bi >= 0) ? 1 : 0;   // the valid selections form a prefix
+            }
         }
         wave_sync();
 
@@ -763,7 +893,8 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
         // gather G[c + earlier selections, j] into the slot of row nc + q and
         // form b_j = a_j^T y, all loads of the iteration in one batch
         const int nq = active ? nsel : 0;
-        for (int q = 0; q < a.S; ++q) {
+        const int SA = GRP ? 2 * a.S : a.S;   // atoms appended per iteration at most (uniform)
+        for (int q = 0; q < SA; ++q) {
             const int j = q < nq ? L.sel[q] : -1;
             float bpart = 0.f;
             if (j >= 0) {
@@ -799,7 +930,7 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
             if (t == 0) L.bsel[q] = bj;
         }
         wave_sync();
-        for (int q = 0; q < a.S; ++q) {
+        for (int q = 0; q < SA; ++q) {
             const bool on = q < nq;
             const int j = on ? L.sel[q] : 0;
             const float bj = on ? L.bsel[q] : 0.f;
@@ -825,11 +956,18 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
         inv_solve(active, t, nc, L.W, L.z, L.s);
 
         // ---------------- step 3: prune to K and re-solve on q
-        const bool prune_g = active && a.prune == CSREC_PRUNE_EACH && nc > K;
-        if (__any(prune_g)) prune_to_q(prune_g, t, nc, a.CM, K, N, a.G32, L);
+        if (!GRP) ng = nc;
+        const bool prune_g = active && a.prune == CSREC_PRUNE_EACH && ng > K;
+        int nqa = K;
+        if (__any(prune_g)) {
+            if (GRP)
+                nqa = prune_to_q_grp(prune_g, t, nc, K, N, a.G32, L);
+            else
+                prune_to_q(prune_g, t, nc, a.CM, K, N, a.G32, L);
+        }
         // a pixel that stopped earlier keeps the x of its last iteration
         if (prune_g) {
-            nx = K;
+            nx = nqa;
             x_on_q = true;
         } else if (active) {
             nx = nc;
@@ -863,12 +1001,17 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
     }
 
     // ---------------- prune placed after the loop (textbook gOMP)
-    const bool final_prune = a.prune == CSREC_PRUNE_FINAL && nc > K && valid && !bad;
+    if (!GRP) ng = nc;
+    const bool final_prune = a.prune == CSREC_PRUNE_FINAL && ng > K && valid && !bad;
     if (__any(final_prune)) {
-        prune_to_q(final_prune, t, nc, a.CM, K, N, a.G32, L);
+        int nqa = K;
+        if (GRP)
+            nqa = prune_to_q_grp(final_prune, t, nc, K, N, a.G32, L);
+        else
+            prune_to_q(final_prune, t, nc, a.CM, K, N, a.G32, L);
         float n2 = 0.f;
         if (final_prune) {
-            nx = K;
+            nx = nqa;
             x_on_q = true;
             float rnew[MSLOT];
             residual<MSLOT>(y, rnew, L.q, L.sq, nx, a.AT, MP, N, t);
@@ -887,22 +1030,45 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
     // ---------------- outputs: x (dense row), support ascending, stats
     const int* xi = x_on_q ? L.q : L.c;
     const float* xv = x_on_q ? L.sq : L.s;
-    float* xrow = a.X + pix * N;
-    for (int n = t; n < N; n += 16) {
-        float v = 0.f;
-        for (int k = 0; k < nx; ++k) v = (xi[k] == n) ? xv[k] : v;
-        xrow[n] = bad ? 0.f : v;
+    if (!GRP) {
+        float* xrow = a.X + pix * N;
+        for (int n = t; n < N; n += 16) {
+            float v = 0.f;
+            for (int k = 0; k < nx; ++k) v = (xi[k] == n) ? xv[k] : v;
+            xrow[n] = bad ? 0.f : v;
+        }
+    } else {
+        // the complex spectrum, interleaved (re, im): bin n of group
+        // g = min(n, Nb - n) is (v_2g, +-v_2g+1), conjugated above Nb / 2
+        const int Nb = a.Nb;
+        float* xrow = a.X + pix * 2 * Nb;
+        for (int n = t; n < Nb; n += 16) {
+            const int g = (2 * n <= Nb) ? n : Nb - n;
+            float re = 0.f, im = 0.f;
+            for (int k = 0; k < nx; ++k) {
+                re = (xi[k] == 2 * g) ? xv[k] : re;
+                im = (xi[k] == 2 * g + 1) ? xv[k] : im;
+            }
+            if (2 * n > Nb) im = -im;
+            xrow[2 * n] = bad ? 0.f : re;
+            xrow[2 * n + 1] = bad ? 0.f : im;
+        }
     }
     if (a.support) {
-        int32_t* srow = a.support + pix * K;
         // ascending order by rank of the index among the nx support atoms
-        for (int k = t; k < K; k += 16)
+        // (GRP: atom 2g is bin g, atom 2g + 1 bin Nb - g; KS = 2 K bins)
+        const int KS = GRP ? 2 * K : K;
+        int32_t* srow = a.support + pix * KS;
+        for (int k = t; k < KS; k += 16)
             if (k >= nx || bad) srow[k] = -1;
         for (int k = t; k < nx && !bad; k += 16) {
-            const int ck = xi[k];
+            const int ck = GRP ? ((xi[k] & 1) ? a.Nb - (xi[k] >> 1) : (xi[k] >> 1)) : xi[k];
             int pos = 0;
-            for (int i = 0; i < nx; ++i) pos += xi[i] < ck ? 1 : 0;
-            if (pos < K) srow[pos] = ck;
+            for (int i = 0; i < nx; ++i) {
+                const int ci = GRP ? ((xi[i] & 1) ? a.Nb - (xi[i] >> 1) : (xi[i] >> 1)) : xi[i];
+                pos += ci < ck ? 1 : 0;
+            }
+            if (pos < KS) srow[pos] = ck;
         }
     }
     if (a.stats && t == 0) {
@@ -963,7 +1129,7 @@ __host__ __device__ inline OtherPlan other_plan(int kind, int MP, int N, int K) 
     return p;
 }
 
-template <int KIND, int MSLOT, int NG>
+template <int KIND, int MSLOT, int NG, bool GRP>
 __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, float* lds) {
     constexpr int NV = 4 * NG;   // atoms per lane: 4 NG t + k, k < NV
     const int lane = threadIdx.x;
@@ -972,7 +1138,9 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
     const int64_t pix = a.p0 + local;
     const bool valid = local < a.P;
     const int M = a.M, N = a.N, K = a.K, MP = a.MP;
-    const OtherPlan pl = other_plan(KIND, MP, N, K);
+    // GRP: conjugate-pair groups, K and the selections counted in groups of
+    // up to two atoms, so every list holds twice as many atoms
+    const OtherPlan pl = other_plan(KIND, MP, N, GRP ? 2 * K : K);
     float* base = lds + x * a.lds_floats;
     float* rb = base + pl.rb;
     float* ball = base + pl.ball;
@@ -1039,7 +1207,10 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
                 const float p = acc[g][i];
-                u[NG * i + g] = KIND == GREEDY_COSAMP ? p : a.mu * p;
+                // GRP: the complex correlation of a pair is half its two real
+                // ones (atoms 2 Re a_g and -2 Im a_g), of a real bin the one
+                const float w = (GRP && !grp_singleton((NV * t + NG * i + g) >> 1, a.Nb)) ? 0.5f : 1.f;
+                u[NG * i + g] = KIND == GREEDY_COSAMP ? w * p : (a.mu * w) * p;
             }
         if (KIND != GREEDY_COSAMP && nq > 0) {
             // u = x + mu p: add the kept values to the lanes holding their atoms
@@ -1063,7 +1234,34 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
         // ---------------- step 2: the nsel largest |u| (no membership mask)
         uint32_t taken = 0u;
         int nsl = 0;
-        for (int qq = 0; qq < nsel; ++qq) {
+        if (GRP) {
+            // over groups: |u_g| = sqrt(u_2g^2 + u_2g+1^2), the atoms of the
+            // winners appended in selection order, pairs next to each other
+            for (int qq = 0; qq < nsel; ++qq) {
+                float bv = -1.f;
+                int bi = -1;
+#pragma unroll
+                for (int k = 0; k < NV; k += 2) {
+                    const int n = NV * t + k;
+                    const float w = sqrtf(u[k] * u[k] + u[k + 1] * u[k + 1]);
+                    if (n < N && !((taken >> k) & 1u) && (bi < 0 || w > bv)) {
+                        bv = w;
+                        bi = n >> 1;
+                    }
+                }
+                pix_argmax(bv, bi);
+                if (bi >= 0 && (2 * bi) / NV == t) taken |= 3u << (2 * bi - NV * t);
+                if (bi >= 0) {
+                    const bool single = grp_singleton(bi, a.Nb);
+                    if (t == 0) {
+                        sel[nsl] = 2 * bi;
+                        if (!single) sel[nsl + 1] = 2 * bi + 1;
+                    }
+                    nsl += single ? 1 : 2;
+                }
+            }
+        }
+        for (int qq = 0; qq < (GRP ? 0 : nsel); ++qq) {
             float bv = -1.f;
             int bi = -1;
 #pragma unroll
@@ -1131,7 +1329,14 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
 #pragma unroll
             for (int u2 = 0; u2 < 4; ++u2) {
                 const int kk = t + 16 * u2;
-                bool kp = kk < nq && (KIND == GREEDY_COSAMP || sq[kk] != 0.f);
+                bool nz = kk < nq && sq[kk] != 0.f;
+                if (GRP && kk < nq) {
+                    // a group stays when either of its atoms is nonzero
+                    const int pr = (q[kk] & 1) ? kk - 1 : kk + 1;
+                    const bool partner = pr >= 0 && pr < nq && (q[pr] >> 1) == (q[kk] >> 1);
+                    nz = nz || (partner && sq[pr] != 0.f);
+                }
+                bool kp = kk < nq && (KIND == GREEDY_COSAMP || nz);
                 if (kp) {
                     const int j = q[kk];
                     for (int i = 0; i < nsl; ++i) kp = kp && (sel[i] != j);
@@ -1159,15 +1364,28 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
         nmax = max(nmax, __shfl_xor(nmax, 2));
         solve_list<true>(active, t, nc, nmax, N, a.G32, c, b, sv, scr);
         // as many 16-atom rank units as the longest list in the wave needs
-        if (nmax <= 32)
-            rank_top<2>(active, t, nc, K, sv, c, sv, q, sq);
-        else if (nmax <= 48)
-            rank_top<3>(active, t, nc, K, sv, c, sv, q, sq);
-        else if (nmax <= 64)
-            rank_top<4>(active, t, nc, K, sv, c, sv, q, sq);
-        else
-            rank_top<kCU>(active, t, nc, K, sv, c, sv, q, sq);
-        if (active) nq = nc < K ? nc : K;
+        if (GRP) {
+            int nk;
+            if (nmax <= 32)
+                nk = rank_top_groups<2>(active, t, nc, K, sv, c, sv, q, sq);
+            else if (nmax <= 48)
+                nk = rank_top_groups<3>(active, t, nc, K, sv, c, sv, q, sq);
+            else if (nmax <= 64)
+                nk = rank_top_groups<4>(active, t, nc, K, sv, c, sv, q, sq);
+            else
+                nk = rank_top_groups<kCU>(active, t, nc, K, sv, c, sv, q, sq);
+            if (active) nq = nk;
+        } else {
+            if (nmax <= 32)
+                rank_top<2>(active, t, nc, K, sv, c, sv, q, sq);
+            else if (nmax <= 48)
+                rank_top<3>(active, t, nc, K, sv, c, sv, q, sq);
+            else if (nmax <= 64)
+                rank_top<4>(active, t, nc, K, sv, c, sv, q, sq);
+            else
+                rank_top<kCU>(active, t, nc, K, sv, c, sv, q, sq);
+            if (active) nq = nc < K ? nc : K;
+        }
         wave_sync();
 
         // ---------------- step 4: residual r = y - A x, Delta, stop
@@ -1204,6 +1422,45 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
         for (int k = 0; k < nq; ++k) x2 += sq[k] * sq[k];
         scale = x2 > 0.f ? 1.f / sqrtf(x2) : 0.f;
     }
+    if (GRP) {
+        // the complex spectrum (re, im), as gOMP's; the support lists the
+        // bins whose value is nonzero
+        const int Nb = a.Nb;
+        float* xrow = a.X + pix * 2 * Nb;
+        for (int n = t; n < Nb; n += 16) {
+            const int g = (2 * n <= Nb) ? n : Nb - n;
+            float re = 0.f, im = 0.f;
+            for (int k = 0; k < nq; ++k) {
+                re = (q[k] == 2 * g) ? sq[k] : re;
+                im = (q[k] == 2 * g + 1) ? sq[k] : im;
+            }
+            if (2 * n > Nb) im = -im;
+            xrow[2 * n] = bad ? 0.f : re;
+            xrow[2 * n + 1] = bad ? 0.f : im;
+        }
+        if (a.support) {
+            int32_t* srow = a.support + pix * 2 * K;
+            auto bin_of = [&](int j) { return (j & 1) ? Nb - (j >> 1) : (j >> 1); };
+            // atom k stands for a nonzero bin when its group has a nonzero value
+            auto live = [&](int k) {
+                if (KIND == GREEDY_COSAMP) return true;
+                const int pr = (q[k] & 1) ? k - 1 : k + 1;
+                const bool partner = pr >= 0 && pr < nq && (q[pr] >> 1) == (q[k] >> 1);
+                return sq[k] != 0.f || (partner && sq[pr] != 0.f);
+            };
+            int cnt = 0;
+            for (int k = 0; k < nq; ++k) cnt += live(k) ? 1 : 0;
+            for (int k = t; k < 2 * K; k += 16)
+                if (k >= cnt || bad) srow[k] = -1;
+            for (int k = t; k < nq && !bad; k += 16) {
+                if (!live(k)) continue;
+                const int ck = bin_of(q[k]);
+                int pos = 0;
+                for (int i = 0; i < nq; ++i) pos += (live(i) && bin_of(q[i]) < ck) ? 1 : 0;
+                if (pos < 2 * K) srow[pos] = ck;
+            }
+        }
+    } else {
     float* xrow = a.X + pix * N;
     for (int n = t; n < N; n += 16) {
         float w = 0.f;
@@ -1226,6 +1483,7 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
             if (pos < K) srow[pos] = ck;
         }
     }
+    }
     if (a.stats && t == 0) {
         csrec_pixel_stats st;
         st.iters = bad ? 0 : iters;
@@ -1236,16 +1494,16 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
     }
 }
 
-template <int KIND, int MSLOT, int NG>
+template <int KIND, int MSLOT, int NG, bool GRP>
 __global__ __launch_bounds__(64, 2) void other_coop_kernel(CoopArgs a) {
     extern __shared__ float lds[];
-    other_body<KIND, MSLOT, NG>(a, blockIdx.x, lds);
+    other_body<KIND, MSLOT, NG, GRP>(a, blockIdx.x, lds);
 }
 
-template <int MSLOT, int NG>
+template <int MSLOT, int NG, bool GRP>
 __global__ __launch_bounds__(64, 2) void gomp_coop_kernel(CoopArgs a) {
     extern __shared__ float lds[];
-    gomp_coop_body<MSLOT, NG>(a, blockIdx.x, lds);
+    gomp_coop_body<MSLOT, NG, GRP>(a, blockIdx.x, lds);
 }
 
 struct CoopItem {
@@ -1279,7 +1537,7 @@ __global__ __launch_bounds__(64, 2) void gomp_coop_persistent_kernel(const CoopI
             if (items[mid].block0 <= u) lo = mid; else hi = mid - 1;
         }
         const CoopArgs a = items[lo].a;
-        gomp_coop_body<MSLOT, NG>(a, u - items[lo].block0, lds);
+        gomp_coop_body<MSLOT, NG, false>(a, u - items[lo].block0, lds);
         wave_sync();
     }
 }
@@ -1287,9 +1545,13 @@ __global__ __launch_bounds__(64, 2) void gomp_coop_persistent_kernel(const CoopI
 typedef void (*coop_kernel_t)(CoopArgs);
 typedef void (*coop_grouped_t)(const CoopItem*, int, int64_t, unsigned long long*);
 
-coop_kernel_t pick_coop(int MP, int NG) {
-    if (MP == 64) return NG == 2 ? gomp_coop_kernel<4, 2> : gomp_coop_kernel<4, 4>;
-    return NG == 2 ? gomp_coop_kernel<8, 2> : gomp_coop_kernel<8, 4>;
+coop_kernel_t pick_coop(int MP, int NG, bool grp) {
+    if (grp) {
+        if (MP == 64) return NG == 2 ? gomp_coop_kernel<4, 2, true> : gomp_coop_kernel<4, 4, true>;
+        return NG == 2 ? gomp_coop_kernel<8, 2, true> : gomp_coop_kernel<8, 4, true>;
+    }
+    if (MP == 64) return NG == 2 ? gomp_coop_kernel<4, 2, false> : gomp_coop_kernel<4, 4, false>;
+    return NG == 2 ? gomp_coop_kernel<8, 2, false> : gomp_coop_kernel<8, 4, false>;
 }
 
 coop_grouped_t pick_coop_grouped(int MP, int NG) {
@@ -1339,6 +1601,8 @@ void fill_args(CoopArgs& a, const float* dictbuf, int M, int N, int K, int S, in
     a.Abf = reinterpret_cast<const __bf16*>(a.Ap + n16);
     a.Ahf = reinterpret_cast<const _Float16*>(a.Ap + n16 + n16 / 2);
     a.prec = prec;
+    a.grp = 0;
+    a.Nb = N;
     a.K = K;
     a.S = S;
     a.Imax = Imax;
@@ -1363,6 +1627,14 @@ size_t gomp_coop_dict_floats(int M, int N) {
     return (size_t)N * gomp_coop_mp(M) + 2 * (size_t)coop_m8(M) * coop_np(N);
 }
 
+int gomp_coop_supported_grp(int M, int N, int K, int S, int Imax) {
+    if (N > 64 * kMaxNG || M > 128 || S > kMaxS) return CSREC_E_UNSUPPORTED;
+    const int CM = 2 * S * Imax;
+    if (CM > 16 * kCU || 2 * K > 16 * kCU) return CSREC_E_UNSUPPORTED;
+    const size_t lds = kGroups * gomp_coop_lds_floats(gomp_coop_mp(M), CM, 2 * K) * sizeof(float);
+    return lds <= 160 * 1024 ? CSREC_OK : CSREC_E_UNSUPPORTED;
+}
+
 int gomp_coop_supported(int M, int N, int K, int S, int Imax) {
     if (N > 64 * kMaxNG || M > 128 || S > kMaxS) return CSREC_E_UNSUPPORTED;   // M8 <= MP holds for M <= 128
     const int CM = S * Imax;
@@ -1383,10 +1655,18 @@ void gomp_coop_prepare(const float* A, int M, int N, float* dictbuf, hipStream_t
 // fbflag (P entries) may be null.
 int gomp_coop_launch(const float* Y, float* X, int32_t* support, csrec_pixel_stats* stats, const float* G32,
                      const float* dictbuf, uint32_t* fbflag, int M, int N, int64_t p0, int64_t P, int K, int S,
-                     int Imax, int prune, float res_tol, float eps, double pivot_thr, int prec, hipStream_t stream) {
+                     int Imax, int prune, float res_tol, float eps, double pivot_thr, int prec, hipStream_t stream,
+                     int Nb) {
     if (P == 0) return CSREC_OK;
     CoopArgs a;
     fill_args(a, dictbuf, M, N, K, S, Imax, prune, res_tol, eps, pivot_thr, prec);
+    if (Nb > 0) {
+        // conjugate-pair groups: up to 2 S atoms per iteration and 2 K kept
+        a.grp = 1;
+        a.Nb = Nb;
+        a.CM = 2 * S * Imax;
+        a.lds_floats = (int)gomp_coop_lds_floats(a.MP, a.CM, 2 * K);
+    }
     a.Y = Y;
     a.G32 = G32;
     a.X = X;
@@ -1397,7 +1677,7 @@ int gomp_coop_launch(const float* Y, float* X, int32_t* support, csrec_pixel_sta
     a.p0 = p0;
     const size_t lds = (size_t)kGroups * a.lds_floats * sizeof(float);
     const int64_t blocks = ceil_div(P, kGroups);
-    const coop_kernel_t fn = pick_coop(a.MP, a.NP / 64);
+    const coop_kernel_t fn = pick_coop(a.MP, a.NP / 64, a.grp != 0);
     CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds));
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64), lds, stream, a);
@@ -1407,14 +1687,21 @@ int gomp_coop_launch(const float* Y, float* X, int32_t* support, csrec_pixel_sta
 
 typedef void (*other_kernel_t)(CoopArgs);
 
-template <int KIND>
+template <int KIND, bool GRP>
 other_kernel_t pick_other_k(int MP, int NG) {
-    if (MP == 64) return NG == 2 ? other_coop_kernel<KIND, 4, 2> : other_coop_kernel<KIND, 4, 4>;
-    return NG == 2 ? other_coop_kernel<KIND, 8, 2> : other_coop_kernel<KIND, 8, 4>;
+    if (MP == 64) return NG == 2 ? other_coop_kernel<KIND, 4, 2, GRP> : other_coop_kernel<KIND, 4, 4, GRP>;
+    return NG == 2 ? other_coop_kernel<KIND, 8, 2, GRP> : other_coop_kernel<KIND, 8, 4, GRP>;
 }
 
 size_t coop_other_lds_floats(int kind, int M, int N, int K) {
     return (size_t)other_plan(kind, gomp_coop_mp(M), N, K).total;
+}
+
+int coop_other_supported_grp(int kind, int M, int N, int K) {
+    // the lists hold the atoms of K groups (up to 2K), as an atom-level
+    // solve with 2K would
+    if (kind == GREEDY_BIHT_ONE_BIT) return CSREC_E_UNSUPPORTED;
+    return coop_other_supported(kind, M, N, 2 * K);
 }
 
 int coop_other_supported(int kind, int M, int N, int K) {
@@ -1428,11 +1715,16 @@ int coop_other_supported(int kind, int M, int N, int K) {
 
 int coop_other_launch(int kind, const float* Y, const int8_t* Ysign, float* X, int32_t* support,
                       csrec_pixel_stats* stats, const float* G32, const float* dictbuf, int M, int N, int64_t p0,
-                      int64_t P, int K, int Imax, float mu, float res_tol, float eps, int prec, hipStream_t stream) {
+                      int64_t P, int K, int Imax, float mu, float res_tol, float eps, int prec, hipStream_t stream,
+                      int Nb) {
     if (P == 0) return CSREC_OK;
     CoopArgs a;
     fill_args(a, dictbuf, M, N, K, 1, Imax, 0, res_tol, eps, 0.0, prec);
-    a.lds_floats = (int)coop_other_lds_floats(kind, M, N, K);
+    a.lds_floats = (int)coop_other_lds_floats(kind, M, N, Nb > 0 ? 2 * K : K);
+    if (Nb > 0) {
+        a.grp = 1;
+        a.Nb = Nb;
+    }
     a.Y = Y;
     a.Ysign = Ysign;
     a.mu = mu;
@@ -1446,9 +1738,14 @@ int coop_other_launch(int kind, const float* Y, const int8_t* Ysign, float* X, i
     const size_t lds = (size_t)kGroups * a.lds_floats * sizeof(float);
     const int64_t blocks = ceil_div(P, kGroups);
     const int NG = a.NP / 64;
-    other_kernel_t fn = kind == GREEDY_COSAMP ? pick_other_k<GREEDY_COSAMP>(a.MP, NG)
-                        : kind == GREEDY_BIHT ? pick_other_k<GREEDY_BIHT>(a.MP, NG)
-                                              : pick_other_k<GREEDY_BIHT_ONE_BIT>(a.MP, NG);
+    other_kernel_t fn;
+    if (a.grp)
+        fn = kind == GREEDY_COSAMP ? pick_other_k<GREEDY_COSAMP, true>(a.MP, NG)
+                                   : pick_other_k<GREEDY_BIHT, true>(a.MP, NG);
+    else
+        fn = kind == GREEDY_COSAMP ? pick_other_k<GREEDY_COSAMP, false>(a.MP, NG)
+             : kind == GREEDY_BIHT ? pick_other_k<GREEDY_BIHT, false>(a.MP, NG)
+                                   : pick_other_k<GREEDY_BIHT_ONE_BIT, false>(a.MP, NG);
     CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds));
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64), lds, stream, a);

@@ -946,3 +946,103 @@ int greedy_gomp_scratch_launch(const GreedyLaunch& a, char* scr, size_t cap) {
 }
 
 }  // namespace csrec
+
+namespace csrec {
+
+namespace {
+// The real M x NR dictionary of the conjugate-pair groups of a complex
+// M x Nb matrix A (interleaved (re, im)) with conjugate-symmetric columns:
+// column 2g holds 2 Re A[:, g] and column 2g + 1 holds -2 Im A[:, g] for a
+// pair (0 < g < Nb / 2), so that A x = sum_g (col_2g Re x_g + col_2g+1 Im x_g)
+// for a conjugate-symmetric x; a real bin (g = 0, g = Nb / 2 for even Nb)
+// has Re A[:, g] in column 2g and a zero column 2g + 1.
+__global__ void pair_dict_kernel(const float* __restrict__ A, int M, int Nb, int NR, float* __restrict__ C) {
+    const int m = blockIdx.x;
+    for (int j = threadIdx.x; j < NR; j += blockDim.x) {
+        const int g = j >> 1;
+        const bool single = g == 0 || ((Nb & 1) == 0 && g == Nb / 2);
+        float v = 0.f;
+        if (m < M && g <= Nb / 2) {
+            const float re = A[((size_t)m * Nb + g) * 2], im = A[((size_t)m * Nb + g) * 2 + 1];
+            v = (j & 1) ? (single ? 0.f : -2.f * im) : (single ? re : 2.f * re);
+        }
+        C[(size_t)m * NR + j] = v;
+    }
+}
+}  // namespace
+
+int pair_dict_atoms(int Nb) { return 2 * (Nb / 2 + 1); }
+
+size_t greedy_hermitian_workspace(int M, int Nb) {
+    const int NR = pair_dict_atoms(Nb);
+    return align_up((size_t)M * NR * 4, 256) + align_up((size_t)NR * NR * 4, 256) +
+           align_up(gomp_coop_dict_floats(M, NR) * 4, 256);
+}
+
+namespace {
+// The group dictionary, its Gram matrix and the kernel's copies in the
+// workspace, built on the stream.
+struct PairDict {
+    float* G32;
+    float* dictbuf;
+};
+int build_pair_dict(const GreedyLaunch& a, PairDict* out) {
+    const int Nb = a.N, NR = pair_dict_atoms(Nb), M = a.M;
+    if (!a.workspace || a.workspace_bytes < greedy_hermitian_workspace(M, Nb)) return CSREC_E_WORKSPACE;
+    char* ws = static_cast<char*>(a.workspace);
+    float* C = reinterpret_cast<float*>(ws);
+    out->G32 = reinterpret_cast<float*>(ws + align_up((size_t)M * NR * 4, 256));
+    out->dictbuf = reinterpret_cast<float*>(ws + align_up((size_t)M * NR * 4, 256) +
+                                            align_up((size_t)NR * NR * 4, 256));
+    hipLaunchKernelGGL(pair_dict_kernel, dim3(M), dim3(256), 0, a.stream, a.A, M, Nb, NR, C);
+    CSREC_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(gram_kernel, dim3(NR), dim3(256), 0, a.stream, C, M, NR, out->G32, nullptr);
+    CSREC_HIP_TRY(hipGetLastError());
+    gomp_coop_prepare(C, M, NR, out->dictbuf, a.stream);
+    CSREC_HIP_TRY(hipGetLastError());
+    return CSREC_OK;
+}
+}  // namespace
+
+int other_hermitian_launch(const GreedyLaunch& a) {
+    if (a.P == 0) return CSREC_OK;
+    PairDict d;
+    const int e0 = build_pair_dict(a, &d);
+    if (e0) return e0;
+    const int NR = pair_dict_atoms(a.N);
+    constexpr int64_t kChunkH = 65536;
+    for (int64_t p0 = 0; p0 < a.P; p0 += kChunkH) {
+        const int64_t np = (a.P - p0) < kChunkH ? (a.P - p0) : kChunkH;
+        const int e = coop_other_launch(a.kind, a.Y, nullptr, a.X, a.support, a.stats, d.G32, d.dictbuf, a.M, NR,
+                                        p0, np, a.K, a.max_iter, a.mu, a.res_tol, a.eps, a.prec, a.stream, a.N);
+        if (e) return e;
+    }
+    return CSREC_OK;
+}
+
+int gomp_hermitian_launch(const GreedyLaunch& a) {
+    if (a.P == 0) return CSREC_OK;
+    const int Nb = a.N, NR = pair_dict_atoms(Nb), M = a.M;
+    if (!a.workspace || a.workspace_bytes < greedy_hermitian_workspace(M, Nb)) return CSREC_E_WORKSPACE;
+    char* ws = static_cast<char*>(a.workspace);
+    float* C = reinterpret_cast<float*>(ws);
+    float* G32 = reinterpret_cast<float*>(ws + align_up((size_t)M * NR * 4, 256));
+    float* dictbuf = reinterpret_cast<float*>(ws + align_up((size_t)M * NR * 4, 256) +
+                                              align_up((size_t)NR * NR * 4, 256));
+    hipLaunchKernelGGL(pair_dict_kernel, dim3(M), dim3(256), 0, a.stream, a.A, M, Nb, NR, C);
+    CSREC_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(gram_kernel, dim3(NR), dim3(256), 0, a.stream, C, M, NR, G32, nullptr);
+    CSREC_HIP_TRY(hipGetLastError());
+    gomp_coop_prepare(C, M, NR, dictbuf, a.stream);
+    CSREC_HIP_TRY(hipGetLastError());
+    constexpr int64_t kChunkH = 65536;
+    for (int64_t p0 = 0; p0 < a.P; p0 += kChunkH) {
+        const int64_t np = (a.P - p0) < kChunkH ? (a.P - p0) : kChunkH;
+        const int e = gomp_coop_launch(a.Y, a.X, a.support, a.stats, G32, dictbuf, nullptr, M, NR, p0, np, a.K,
+                                       a.S, a.max_iter, a.prune, a.res_tol, a.eps, 0.0, a.prec, a.stream, Nb);
+        if (e) return e;
+    }
+    return CSREC_OK;
+}
+
+}  // namespace csrec
