@@ -114,16 +114,25 @@ def _ordered_gap(values: np.ndarray, k: int, allowed: Optional[np.ndarray] = Non
 
 
 def lstsq_on_support(A: np.ndarray, Y: np.ndarray, cols: np.ndarray) -> np.ndarray:
-    """s = B^+ y with B = A(:, cols) per pixel (Alg. 3 step 2), for a batch of
-    supports of one common size.  cols: P x k int; Y: P x M.  Returns P x k.
+    """s = B^+ y with B = A(:, cols) per pixel (Alg. 3 step 2, Alg. 5 step 2),
+    for a batch of supports of one common size.  cols: P x k int; Y: P x M.
+    Returns P x k.
 
-    Householder QR of each B (M x k, full column rank), then R s = Q^T y."""
+    k <= M: Householder QR of each B (M x k, full column rank), then
+    R s = Q^T y, the least-squares solution.
+    k > M (CoSaMP's merged support when 3K > M): B has full row rank M and
+    B^+ y is the minimum-norm solution of B s = y: with the QR of B^T
+    (k x M, full column rank), B = R^T Q^T, so s = Q w with R^T w = y."""
     A = _f64(A)
     Y = _f64(Y)
     cols = np.asarray(cols)
     if cols.shape[1] == 0:
         return np.zeros((Y.shape[0], 0))
     B = np.transpose(A[:, cols], (1, 0, 2))          # P x M x k
+    if cols.shape[1] > A.shape[0]:
+        Q, R = np.linalg.qr(np.transpose(B, (0, 2, 1)))                   # P x k x M, P x M x M
+        w = np.linalg.solve(np.transpose(R, (0, 2, 1)), Y[..., None])[..., 0]
+        return np.einsum("pkm,pm->pk", Q, w)
     Q, R = np.linalg.qr(B)                            # P x M x k, P x k x k
     qty = np.einsum("pmk,pm->pk", Q, Y)
     return np.linalg.solve(R, qty[..., None])[..., 0]
@@ -566,7 +575,9 @@ def cosamp(A, Y, K: int, max_iter: int, eps: float = 0.0, res_tol: float = 0.0,
 
     Per iteration i:
       1. p = A^T r^{i-1};  Theta = argmax_2K |p|;  c = Theta U c^{i-1}
-      2. s = A(:, c)^+ y
+      2. s = A(:, c)^+ y  (the least-squares solution while |c| <= M, the
+         minimum-norm solution of A(:, c) s = y once |c| > M, which the
+         pseudo-inverse gives; |c| <= 3K)
       3. q = argmax_K |s|;  s = s(q);  c = c(q);  x = 0, x(c) = s
       4. r^i = y - A x,  Delta = ||r^i - r^{i-1}||;  stop when Delta < eps
     (the kept values are the least-squares values on the larger set, no
@@ -575,8 +586,8 @@ def cosamp(A, Y, K: int, max_iter: int, eps: float = 0.0, res_tol: float = 0.0,
     Y = _f64(Y)
     P, M = Y.shape
     N = A.shape[1]
-    if 3 * K > M:
-        raise ValueError("3K exceeds M: the merged support could make the least squares underdetermined")
+    if 3 * K > N:
+        raise ValueError("3K exceeds N")
     fin = _finite_rows(Y)
     Yc = np.where(fin[:, None], Y, 0.0)
     ynorm = np.linalg.norm(Yc, axis=1)

@@ -203,6 +203,55 @@ def check_lstsq(orc):
         assert np.max(np.abs(B.T @ (Y[p] - B @ s[p]))) < 1e-11   # normal equations
 
 
+def check_lstsq_min_norm(orc):
+    """More columns than rows (CoSaMP's merged support when 3K > M): the
+    pseudo-inverse solution, i.e. the minimum-norm solution of B s = y --
+    against numpy's SVD pseudo-inverse, and by its two defining properties:
+    B s = y exactly, and s orthogonal to the null space of B (SciPy's SVD
+    null-space basis)."""
+    from scipy.linalg import null_space
+    rng = _rng(31)
+    A = rng.standard_normal((9, 40))
+    Y = rng.standard_normal((5, 9))
+    for k in (10, 13):
+        cols = np.stack([np.sort(rng.choice(40, k, replace=False)) for _ in range(5)])
+        s = orc.lstsq_on_support(A, Y, cols)
+        for p in range(5):
+            B = A[:, cols[p]]
+            assert np.max(np.abs(s[p] - np.linalg.pinv(B) @ Y[p])) < 1e-11
+            assert np.max(np.abs(B @ s[p] - Y[p])) < 1e-11
+            assert np.max(np.abs(null_space(B).T @ s[p])) < 1e-11
+
+
+def check_cosamp_wide(orc):
+    """CoSaMP with 3K > M: a replay of Alg. 5 with numpy's SVD pseudo-inverse
+    as step 2 (two iterations, at least one pixel reaching |c| > M) gives the
+    same x; the iterate with |c| > M fits y exactly on c before the prune."""
+    rng = _rng(32)
+    M, N, K = 10, 40, 4
+    A = rng.standard_normal((M, N))
+    Y = rng.standard_normal((6, M))
+    out = orc.cosamp(A, Y, K=K, max_iter=2)
+    wide = 0
+    for p in range(6):
+        x = np.zeros(N)
+        prev = np.zeros(0, dtype=int)
+        for _ in range(2):
+            r = Y[p] - A @ x
+            theta = np.argsort(-np.abs(A.T @ r), kind="stable")[:2 * K]
+            c = np.union1d(theta, prev)
+            s = np.linalg.pinv(A[:, c]) @ Y[p]
+            if len(c) > M:
+                wide += 1
+                assert np.max(np.abs(A[:, c] @ s - Y[p])) < 1e-10
+            keep = np.argsort(-np.abs(s), kind="stable")[:K]
+            x = np.zeros(N)
+            x[c[keep]] = s[keep]
+            prev = np.sort(c[keep])
+        assert np.max(np.abs(out["X"][p] - x)) < 1e-10
+    assert wide > 0
+
+
 def check_top_indices(orc):
     v = np.array([[0.5, -2.0, 2.0, 1.0, -2.0, 0.1]])
     assert orc.top_indices(v, 3).tolist() == [[1, 2, 4]]
@@ -989,14 +1038,14 @@ def check_metrics():
 ORACLE_CHECKS = [
     check_lipschitz, check_fista_identity, check_fista_zero_solution,
     check_fista_diagonal_momentum, check_fista_matches_sklearn_lasso, check_fista_kkt_and_rate,
-    check_fista_stop_rule, check_fista_nonfinite, check_lstsq, check_top_indices,
+    check_fista_stop_rule, check_fista_nonfinite, check_lstsq, check_lstsq_min_norm, check_top_indices,
     check_gomp_is_omp_when_S1, check_gomp_orthonormal, check_gomp_exact_recovery,
     check_gomp_brute_force, check_gomp_prune_invariants, check_gomp_no_reselect,
     check_gomp_stop, check_gomp_final_prune, check_gomp_diagnostics_by_hand, check_round_to_format,
     check_greedy_complex_real_case, check_greedy_complex_recovery_and_phase, check_greedy_complex_unitary_dft,
     check_greedy_complex_conjugate_pairs,
     check_cosamp_biht_res_tol,
-    check_cosamp_orthonormal, check_cosamp_recovery, check_cosamp_no_resolve,
+    check_cosamp_orthonormal, check_cosamp_recovery, check_cosamp_no_resolve, check_cosamp_wide,
     check_biht_orthonormal, check_biht_first_step, check_biht_second_step_mu,
     check_biht_recovery, check_one_bit, check_admm_matches_sklearn_lasso, check_admm_identity,
     check_admm_kkt_and_dual, check_admm_stop_rule, check_sparsify_worked, check_sparsify_transform,

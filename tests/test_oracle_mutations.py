@@ -33,6 +33,11 @@ MUTATIONS = [
      'order = key.shape[1] - 1 - np.argsort(-key[:, ::-1], axis=1, kind="stable")'),
     ("lstsq-transposed-R", "np.linalg.solve(R, qty[..., None])",
      "np.linalg.solve(np.transpose(R, (0, 2, 1)), qty[..., None])"),
+    ("min-norm-untransposed-R", "w = np.linalg.solve(np.transpose(R, (0, 2, 1)), Y[..., None])[..., 0]",
+     "w = np.linalg.solve(R, Y[..., None])[..., 0]"),
+    ("min-norm-ridge", "if cols.shape[1] > A.shape[0]:",
+     "if cols.shape[1] > A.shape[0]:\n        G = np.einsum('pmi,pmj->pij', B, B) + 1e-6 * np.eye(cols.shape[1])\n"
+     "        return np.linalg.solve(G, np.einsum('pmk,pm->pk', B, Y)[..., None])[..., 0]"),
     ("gomp-no-mask", "theta = top_indices(p, S, allowed)", "theta = top_indices(p, S)"),
     ("gomp-no-prune", 'if prune == "each" and i * S > K:', "if False:"),
     ("gomp-prune-no-resolve", "sq = lstsq_on_support(A, ya, q)",
