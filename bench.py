@@ -65,6 +65,14 @@ OTHER_K, COSAMP_ITERS, BIHT_REAL_ITERS, BIHT_1BIT_ITERS, BIHT_MU = 15, 30, 40, 1
 PSNR_SAMPLE = 128
 ADMM_ITERS, ADMM_ALPHA = 200, 1.8
 PROTOCOL_T, PROTOCOL_EPS, PROTOCOL_LAMBDAS = 0.1, 1e-8, (0.1, 100.0)
+# CoSaMP, BIHT and the DFT-basis greedy runs also stop at ||r|| <= 1e-6 ||y||:
+# FP32 does not resolve the absolute Delta < 1e-8 at a peak of 1e4, so those
+# runs would otherwise report no convergence and run to the cap
+PROTOCOL_RES_TOL = 1e-6
+# gOMP's FP64 redo at a pivot ratio below 1e-6 or an FP32 error estimate above
+# 1e-7: at these operating points (|c| near M) nearly every pixel's least
+# squares is too ill-conditioned for FP32 to keep the FP64 oracle's accuracy
+PROTOCOL_REDO_TOL = 1e-7
 PROTOCOL_CONVEX_CAP, PROTOCOL_BIHT_CAP, PROTOCOL_COSAMP_CAP = 10000, 1000, 200
 DFT_ITERS = 200
 
@@ -312,7 +320,8 @@ def protocol_dft_cube(torch, cs, W, dev, stream, name):
     """The protocol with the paper's complex DFT basis on one cube: GPU
     sparsification of the real spectra (x = Psi^* f, T = 0.1) and
     compression y = Phi f_s (real), then FISTA and ADMM on the half spectrum
-    at the two lambdas, eps and caps as the real-basis protocol; PSNR of the
+    at the two lambdas, and gOMP, BIHT and CoSaMP on conjugate pairs at the
+    cube's kappa pair, eps and caps as the real-basis protocol; PSNR of the
     recovered spectra Psi x against the sparsified ones."""
     c = W.paper_shape_dft(name)
     P, M, N = c["P"], c["M"], c["N"]
@@ -338,6 +347,20 @@ def protocol_dft_cube(torch, cs, W, dev, stream, name):
                                                                            eps=PROTOCOL_EPS)
         runs[f"admm lambda={lam:g}"] = lambda lam=lam: cs.admm_hermitian(A, Y, lam=lam, alpha=ADMM_ALPHA,
                                                                          max_iter=PROTOCOL_CONVEX_CAP, eps=PROTOCOL_EPS)
+    # greedy solvers on conjugate pairs: kappa nonzero bins are ceil(kappa / 2)
+    # groups, G = floor(kappa / 5) bins per iteration max(1, floor(kappa / 10))
+    # groups
+    for kap in c["kappas"]:
+        kg, sg = (kap + 1) // 2, max(1, kap // 10)
+        runs[f"gomp kappa={kap} ({kg} groups)"] = lambda kg=kg, sg=sg: cs.gomp_hermitian(
+            A, Y, K=kg, S=sg, res_tol=PROTOCOL_RES_TOL, eps=PROTOCOL_EPS)
+        runs[f"biht kappa={kap} ({kg} groups)"] = lambda kg=kg: cs.biht_hermitian(
+            A, Y, K=kg, max_iter=PROTOCOL_BIHT_CAP, mu=BIHT_MU, eps=PROTOCOL_EPS, res_tol=PROTOCOL_RES_TOL)
+        if 6 * kg <= min(M, 96):
+            runs[f"cosamp kappa={kap} ({kg} groups)"] = lambda kg=kg: cs.cosamp_hermitian(
+                A, Y, K=kg, max_iter=PROTOCOL_COSAMP_CAP, eps=PROTOCOL_EPS, res_tol=PROTOCOL_RES_TOL)
+        else:
+            row["solvers"][f"cosamp kappa={kap} ({kg} groups)"] = "unsupported: 6 groups' columns > M"
     for label, fn in runs.items():
         res, ms = event_timed(torch, stream, fn, reps=1)
         st = res[-1]
@@ -358,7 +381,11 @@ def leg_protocol(torch, cs, W, dev, stream, samples):
     out = {"workload": f"Section IV protocol on synthetic cubes of the data sets' shapes (peak {W.PAPER_PEAK:g}): "
                        f"sparsify T={PROTOCOL_T}, 2.5x compression by band subsampling, eps={PROTOCOL_EPS:g}, caps "
                        f"{PROTOCOL_CONVEX_CAP} (FISTA, ADMM alpha={ADMM_ALPHA}) / {PROTOCOL_BIHT_CAP} (BIHT) / "
-                       f"{PROTOCOL_COSAMP_CAP} (CoSaMP) iterations; gOMP G=floor(kappa/5) with the FP64 redo at 1e-6", "cubes": {}}
+                       f"{PROTOCOL_COSAMP_CAP} (CoSaMP) iterations, CoSaMP and BIHT also stopping at ||r|| <= "
+                       f"{PROTOCOL_RES_TOL:g} ||y||; gOMP G=floor(kappa/5) with the FP64 redo at pivot "
+                       f"ratio 1e-6 or FP32 error estimate {PROTOCOL_REDO_TOL:g}; CoSaMP at "
+                       f"3 kappa > M with the minimum-norm least squares (FP64); DFT basis: FISTA, ADMM and the "
+                       f"greedy solvers on conjugate pairs (ceil(kappa/2) groups)", "cubes": {}}
     out["cubes_dft"] = {}
     samples["protocol"] = {}
     for ci, name in enumerate(W.PAPER_SHAPES):
@@ -400,18 +427,17 @@ def leg_protocol(torch, cs, W, dev, stream, samples):
                 threshold="standard")
         for kap in c["kappas"]:
             runs[f"gomp kappa={kap}"] = lambda kap=kap: cs.gomp(A, Y, K=kap, S=kap // 5, eps=PROTOCOL_EPS,
-                                                                pivot_fallback=1e-6)
+                                                                pivot_fallback=1e-6, redo_tol=PROTOCOL_REDO_TOL)
             if 2 * kap <= min(M, 96):
                 runs[f"biht kappa={kap}"] = lambda kap=kap: cs.biht(A, Y, K=kap, max_iter=PROTOCOL_BIHT_CAP, mu=BIHT_MU,
-                                                                    eps=PROTOCOL_EPS)
+                                                                    eps=PROTOCOL_EPS, res_tol=PROTOCOL_RES_TOL)
             else:
                 row["solvers"][f"biht kappa={kap}"] = "unsupported: 2 kappa > min(M, 96)"
-            if 3 * kap <= min(M, 96):
-                runs[f"cosamp kappa={kap}"] = lambda kap=kap: cs.cosamp(A, Y, K=kap, max_iter=PROTOCOL_COSAMP_CAP,
-                                                                        eps=PROTOCOL_EPS)
-            else:
-                row["solvers"][f"cosamp kappa={kap}"] = ("unsupported: 3 kappa > M (the least squares on the merged "
-                                                         "support would be underdetermined)")
+            # 3 kappa > M: the FP64 path, minimum-norm least squares once the
+            # merged support outgrows M
+            tag = "" if 3 * kap <= M else " (3 kappa > M: minimum-norm, FP64)"
+            runs[f"cosamp kappa={kap}{tag}"] = lambda kap=kap: cs.cosamp(A, Y, K=kap, max_iter=PROTOCOL_COSAMP_CAP,
+                                                                         eps=PROTOCOL_EPS, res_tol=PROTOCOL_RES_TOL)
         for label, fn in runs.items():
             res, ms = event_timed(torch, stream, fn, reps=1)
             if label.startswith("gomp"):

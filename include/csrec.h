@@ -72,6 +72,9 @@ extern "C" {
 #define CSREC_PREC_BF16 1   /* BF16 operands on MFMA, FP32 accumulation and state */
 #define CSREC_PREC_F16  2   /* FP16 operands on MFMA, FP32 accumulation and state */
 
+/* gOMP's FP64 redo: default FP32 error-estimate threshold (csrec_gomp_params.redo_tol) */
+#define CSREC_REDO_TOL_DEFAULT 1e-5
+
 /* per-pixel flags (csrec_pixel_stats.flags) */
 #define CSREC_FLAG_CONVERGED     1u  /* stopped by Delta < eps or the residual tolerance */
 #define CSREC_FLAG_ITER_CAP      2u  /* ran max_iter iterations */
@@ -158,18 +161,26 @@ typedef struct {
     double pivot_fallback;    /* FP64 redo of a pixel when a Cholesky pivot ratio d_j / G_jj falls
                                  below this (e.g. 1e-6), or when the FP32 error estimate of its least
                                  squares on c, 2^-24 trace(G[c,c]) trace(G[c,c]^-1) / |c|, exceeds
-                                 1e-5 (ill-conditioned supports, |c| near M); 0 disables both */
+                                 redo_tol (ill-conditioned supports, |c| near M); 0 disables both */
+    double redo_tol;          /* >= 0; the FP32 error estimate that sends a pixel to the FP64 redo
+                                 (0 = CSREC_REDO_TOL_DEFAULT); used only with pivot_fallback > 0.
+                                 A smaller value redoes more pixels: at 1e-7 the supports near M of
+                                 Section IV's operating points go to FP64 whole */
 } csrec_gomp_params;
 
 /* Alg. 5.  Inputs y, A, kappa (= K), eps. */
 typedef struct {
     int32_t struct_size;      /* sizeof(csrec_cosamp_params) */
-    int32_t K;                /* 1 <= K, 3K <= min(M, 96) */
+    int32_t K;                /* 1 <= K; 3K <= M (on-chip FP32 path, 3K <= 96), or 3K > M with
+                                 3K <= min(N, 128) (the FP64 path: step 2's pseudo-inverse is the
+                                 least-squares solution while |c| <= M and the minimum-norm solution
+                                 of A(:, c) s = y once |c| > M; M <= 96) */
     int32_t max_iter;         /* >= 0 */
     double eps;               /* stop when Delta < eps (0 disables) */
     double res_tol;           /* stop when ||r|| <= res_tol * ||y|| (0 disables) */
     int32_t prec;             /* precision of the correlation A^T r (as csrec_gomp_params.prec; the
-                                 first correlation, A^T y, the least-squares right-hand sides, is FP32) */
+                                 first correlation, A^T y, the least-squares right-hand sides, is FP32);
+                                 3K > M: CSREC_PREC_F32 only (that path computes in FP64) */
 } csrec_cosamp_params;
 
 /* Alg. 4 (REAL) or binary IHT (ONE_BIT).  Inputs y, A, kappa (= K), mu, eps. */
@@ -220,7 +231,9 @@ int32_t csrec_fista(const csrec_problem* problem, const csrec_fista_params* para
 int32_t csrec_gomp(const csrec_problem* problem, const csrec_gomp_params* params, float* X,
                    int32_t* support, csrec_pixel_stats* stats);
 
-/* CoSaMP (Alg. 5): outputs as csrec_gomp. */
+/* CoSaMP (Alg. 5): outputs as csrec_gomp.  With 3K > M the merged support can
+ * hold more atoms than measurements; that case runs one pixel per workgroup in
+ * FP64 and needs no workspace (csrec_workspace_bytes reports 0). */
 int32_t csrec_cosamp(const csrec_problem* problem, const csrec_cosamp_params* params, float* X,
                      int32_t* support, csrec_pixel_stats* stats);
 

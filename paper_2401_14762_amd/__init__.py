@@ -143,6 +143,7 @@ def _params(solver, A, P, kw):
         p.prune = _lib.PRUNE[kw.get("prune", "each")]
         p.prec = _lib.PREC[kw.get("prec", "f32")]
         p.pivot_fallback = float(kw.get("pivot_fallback", 0.0))
+        p.redo_tol = float(kw.get("redo_tol", 0.0))
         return p, _lib.SOLVER_GOMP
     if solver == "cosamp":
         p = _lib.CosampParams()
@@ -421,15 +422,19 @@ def _greedy(solver, entry, A, Y, P, stream, kw):
 
 
 def gomp(A, Y, K: int, S: int = 1, max_iter: int = 0, res_tol: float = 0.0, eps: float = 0.0,
-         prune: str = "each", prec: str = "f32", pivot_fallback: float = 0.0, stream=None):
-    """gOMP (Alg. 3) on every pixel: returns (X, support (P x K, ascending, -1 padded), stats)."""
+         prune: str = "each", prec: str = "f32", pivot_fallback: float = 0.0, redo_tol: float = 0.0,
+         stream=None):
+    """gOMP (Alg. 3) on every pixel: returns (X, support (P x K, ascending, -1 padded), stats).
+    pivot_fallback > 0 redoes in FP64 the pixels whose pivot ratio falls below
+    it or whose FP32 error estimate exceeds redo_tol (0: the library's 1e-5)."""
     return _greedy("gomp", "csrec_gomp", A, Y, Y.shape[0], stream,
                    dict(K=K, S=S, max_iter=max_iter, res_tol=res_tol, eps=eps, prune=prune, prec=prec,
-                        pivot_fallback=pivot_fallback))
+                        pivot_fallback=pivot_fallback, redo_tol=redo_tol))
 
 
 def gomp_noalloc(A, Y, K: int, S: int = 1, max_iter: int = 0, res_tol: float = 0.0, eps: float = 0.0,
-                 prune: str = "each", prec: str = "f32", pivot_fallback: float = 0.0, stream=None, out=None):
+                 prune: str = "each", prec: str = "f32", pivot_fallback: float = 0.0, redo_tol: float = 0.0,
+                 stream=None, out=None):
     """gOMP through csrec_gomp_noalloc: no workspace, the library's fixed
     per-device scratch instead (calls on one device must not overlap).
     out = (X (P x N float32), support (P x K int32), stats (P x 4 int32))
@@ -445,7 +450,7 @@ def gomp_noalloc(A, Y, K: int, S: int = 1, max_iter: int = 0, res_tol: float = 0
         raise ValueError("Y must be P x M")
     pb = _problem(A, Y, P, stream)
     prm, _ = _params("gomp", A, P, dict(K=K, S=S, max_iter=max_iter, res_tol=res_tol, eps=eps, prune=prune,
-                                         prec=prec, pivot_fallback=pivot_fallback))
+                                         prec=prec, pivot_fallback=pivot_fallback, redo_tol=redo_tol))
     if out is None:
         X = torch.empty((P, N), dtype=torch.float32, device=A.device)
         Sp = torch.empty((max(P, 1), K), dtype=torch.int32, device=A.device)
@@ -574,7 +579,8 @@ class Server:
     submit / admit / done times (seconds since creation)."""
 
     def __init__(self, K: int, S: int, res_tol: float = 0.0, max_iter: int = 0, prune: str = "each",
-                 pivot_fallback: float = 0.0, prec: str = "f32", hbm_budget_bytes: int = 4 << 30,
+                 pivot_fallback: float = 0.0, prec: str = "f32", redo_tol: float = 0.0,
+                 hbm_budget_bytes: int = 4 << 30,
                  batch_pixels: int = 262144, chunk_pixels: int = 65536, device: int = 0):
         import numpy as np  # noqa: F401
         lib = library()
@@ -585,7 +591,7 @@ class Server:
         cfg.batch_pixels = int(batch_pixels)
         cfg.chunk_pixels = int(chunk_pixels)
         self._defaults = dict(K=K, S=S, max_iter=max_iter, res_tol=res_tol, prune=prune,
-                              pivot_fallback=pivot_fallback, prec=prec)
+                              pivot_fallback=pivot_fallback, prec=prec, redo_tol=redo_tol)
         g, _ = _params("gomp", None, 0, self._defaults)
         cfg.gomp = g
         h = ctypes.c_void_p(0)
@@ -605,7 +611,7 @@ class Server:
 
     def submit(self, dict_id: int, Y, tag: int, **params) -> None:
         """Queues tile Y (P x M) under `tag`.  Keyword parameters (res_tol, eps,
-        prune, pivot_fallback, max_iter, prec) override the server's for this
+        prune, pivot_fallback, redo_tol, max_iter, prec) override the server's for this
         tile; none given = the server's."""
         import numpy as np
         Y = np.ascontiguousarray(Y, dtype=np.float32)

@@ -81,6 +81,7 @@ class GompParams(ctypes.Structure):
         ("prune", ctypes.c_int32),
         ("prec", ctypes.c_int32),
         ("pivot_fallback", ctypes.c_double),
+        ("redo_tol", ctypes.c_double),
     ]
 
 

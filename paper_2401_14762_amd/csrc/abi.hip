@@ -92,7 +92,8 @@ int fill_gomp(const csrec_problem* p, const csrec_gomp_params* q, GreedyLaunch& 
     if (e) return e;
     if (!q || q->struct_size != (int32_t)sizeof(csrec_gomp_params)) return CSREC_E_INVAL;
     if (q->K < 1 || q->S < 1 || q->S > 8 || q->max_iter < 0) return CSREC_E_INVAL;
-    if (!finite_nonneg(q->res_tol) || !finite_nonneg(q->eps) || !finite_nonneg(q->pivot_fallback))
+    if (!finite_nonneg(q->res_tol) || !finite_nonneg(q->eps) || !finite_nonneg(q->pivot_fallback) ||
+        !finite_nonneg(q->redo_tol))
         return CSREC_E_INVAL;
     if (q->prune != CSREC_PRUNE_EACH && q->prune != CSREC_PRUNE_FINAL) return CSREC_E_INVAL;
     if ((e = check_prec(q->prec))) return e;
@@ -111,6 +112,7 @@ int fill_gomp(const csrec_problem* p, const csrec_gomp_params* q, GreedyLaunch& 
     l.res_tol = (float)q->res_tol;
     l.eps = (float)q->eps;
     l.pivot_fallback = q->pivot_fallback;
+    l.redo_tol = q->redo_tol > 0.0 ? q->redo_tol : CSREC_REDO_TOL_DEFAULT;
     return CSREC_OK;
 }
 
@@ -151,8 +153,14 @@ int fill_cosamp(const csrec_problem* p, const csrec_cosamp_params* q, GreedyLaun
     if (q->K < 1 || q->max_iter < 0 || !finite_nonneg(q->eps) || !finite_nonneg(q->res_tol))
         return CSREC_E_INVAL;
     if ((e = check_prec(q->prec))) return e;
-    if (3 * q->K > p->M || 3 * q->K > GREEDY_CMAX) return CSREC_E_SHAPE;
     if (p->M > 96) return CSREC_E_UNSUPPORTED;
+    if (3 * q->K > p->M) {
+        // the merged support can outgrow M: the FP64 minimum-norm path
+        if ((e = cosamp_wide_supported(p->M, p->N, q->K))) return e;
+        if (q->prec != CSREC_PREC_F32) return CSREC_E_UNSUPPORTED;
+    } else if (3 * q->K > GREEDY_CMAX) {
+        return CSREC_E_SHAPE;
+    }
     l = GreedyLaunch{};
     l.kind = GREEDY_COSAMP;
     l.K = q->K;
@@ -245,7 +253,7 @@ int run_greedy(GreedyLaunch& l, float* X, int32_t* support, csrec_pixel_stats* s
     l.stats = stats;
     if (l.P == 0) return CSREC_OK;
     const size_t need = greedy_workspace(l);
-    if (!l.workspace || l.workspace_bytes < need) return CSREC_E_WORKSPACE;
+    if (need > 0 && (!l.workspace || l.workspace_bytes < need)) return CSREC_E_WORKSPACE;
     return greedy_launch(l);
 }
 }  // namespace

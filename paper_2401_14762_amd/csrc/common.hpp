@@ -143,6 +143,7 @@ struct GreedyLaunch {
     int prec;
     float res_tol, eps, mu;
     double pivot_fallback;
+    double redo_tol;      // FP32 error estimate above which gOMP redoes a pixel in FP64
     void* workspace;
     size_t workspace_bytes;
     hipStream_t stream;
@@ -154,6 +155,10 @@ constexpr int GOMP_CMAX = 96;     // gOMP: largest |c| = S * max_iter
 
 size_t greedy_workspace(const GreedyLaunch& a);
 int greedy_launch(const GreedyLaunch& a);
+// CoSaMP with 3K > M (minimum-norm least squares once |c| > M; FP64, no workspace)
+int cosamp_wide_supported(int M, int N, int K);
+int cosamp_wide_launch(const GreedyLaunch& a);
+inline bool cosamp_is_wide(const GreedyLaunch& a) { return a.kind == GREEDY_COSAMP && 3 * a.K > a.M; }
 // gOMP on a fixed device scratch of cap bytes (a.workspace is not used):
 // FP64 redo columns that fit (-1: the shape does not fit), and the launch
 int64_t greedy_gomp_scratch_cols(const GreedyLaunch& a, size_t cap);
@@ -203,7 +208,7 @@ void gomp_coop_prepare(const float* A, int M, int N, float* dictbuf, hipStream_t
 // real atoms; K, S and Imax count groups; X is P x Nb complex, support P x 2K bins)
 int gomp_coop_launch(const float* Y, float* X, int32_t* support, csrec_pixel_stats* stats, const float* G32,
                      const float* dictbuf, uint32_t* fbflag, int M, int N, int64_t p0, int64_t P, int K, int S,
-                     int Imax, int prune, float res_tol, float eps, double pivot_thr, int prec, hipStream_t stream,
+                     int Imax, int prune, float res_tol, float eps, double pivot_thr, float redo_tol, int prec, hipStream_t stream,
                      int Nb = 0);
 int gomp_coop_supported_grp(int M, int N, int K, int S, int Imax);
 struct GompCoopItem {
@@ -230,6 +235,7 @@ int coop_other_launch(int kind, const float* Y, const int8_t* Ysign, float* X, i
                       int Nb = 0);
 int coop_other_supported_grp(int kind, int M, int N, int K);
 int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_host, void* table_dev, int K, int S,
-                           int prune, float res_tol, float eps, double pivot_thr, int prec, hipStream_t stream);
+                           int prune, float res_tol, float eps, double pivot_thr, float redo_tol, int prec,
+                           hipStream_t stream);
 
 }  // namespace csrec

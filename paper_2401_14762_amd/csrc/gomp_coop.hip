@@ -52,7 +52,6 @@ constexpr int kMaxS = 8;
 constexpr int kMaxSel = 2 * kMaxS; // atoms selected per iteration (a conjugate pair is two)
 constexpr int kGJ = 32;           // K up to this: the pruned system is solved in registers
 constexpr int kCU = 6;            // |c| <= 16 kCU entries: per-lane units of the rank and the Gram gather
-constexpr float kFp32Tol = 1e-5f; // relative accuracy an FP32 least squares must keep, or the pixel is redone in FP64
 
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 
@@ -68,6 +67,7 @@ struct CoopArgs {
     int M, N, MP, NP, K, S, Imax, prune;
     float res_tol, eps;
     double pivot_thr;
+    float redo_tol;       // relative accuracy an FP32 least squares must keep, or the pixel is redone in FP64
     int64_t P;            // pixels of this launch
     int64_t p0;           // first pixel (index into Y/X/support/stats)
     int CM;               // S * Imax
@@ -942,13 +942,13 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
                 trG += gjj;
                 trW += row_sq;
                 // a small pivot, or an FP32 error estimate of the normal
-                // equations on c above the FP32 result tolerance kFp32Tol:
+                // equations on c above the FP32 result tolerance redo_tol:
                 // 2^-24 kappa(G[c,c]), kappa estimated as
                 // trace(G[c,c]) trace(G[c,c]^{-1}) / |c| (between the lower
                 // bound, that over |c|^2, and the upper bound, the product
                 // itself).  Pruned supports q are subsets of c, and the
                 // estimate of c bounds theirs.
-                if ((double)ratio < a.pivot_thr || trG * trW * 5.9604645e-8f > kFp32Tol * (float)(nc + 1))
+                if ((double)ratio < a.pivot_thr || trG * trW * 5.9604645e-8f > a.redo_tol * (float)(nc + 1))
                     fallback = true;
             }
             if (on) ++nc;
@@ -1590,7 +1590,7 @@ int coop_np(int N) { return 64 * coop_ng(N); }
 int coop_m8(int M) { return (M + kRowPad - 1) / kRowPad * kRowPad; }
 
 void fill_args(CoopArgs& a, const float* dictbuf, int M, int N, int K, int S, int Imax, int prune, float res_tol,
-               float eps, double pivot_thr, int prec) {
+               float eps, double pivot_thr, float redo_tol, int prec) {
     a.M = M;
     a.N = N;
     a.MP = gomp_coop_mp(M);
@@ -1610,6 +1610,7 @@ void fill_args(CoopArgs& a, const float* dictbuf, int M, int N, int K, int S, in
     a.res_tol = res_tol;
     a.eps = eps;
     a.pivot_thr = pivot_thr;
+    a.redo_tol = redo_tol;
     a.CM = S * Imax;
     a.lds_floats = (int)gomp_coop_lds_floats(a.MP, a.CM, K);
     a.mu = 0.f;
@@ -1655,11 +1656,11 @@ void gomp_coop_prepare(const float* A, int M, int N, float* dictbuf, hipStream_t
 // fbflag (P entries) may be null.
 int gomp_coop_launch(const float* Y, float* X, int32_t* support, csrec_pixel_stats* stats, const float* G32,
                      const float* dictbuf, uint32_t* fbflag, int M, int N, int64_t p0, int64_t P, int K, int S,
-                     int Imax, int prune, float res_tol, float eps, double pivot_thr, int prec, hipStream_t stream,
+                     int Imax, int prune, float res_tol, float eps, double pivot_thr, float redo_tol, int prec, hipStream_t stream,
                      int Nb) {
     if (P == 0) return CSREC_OK;
     CoopArgs a;
-    fill_args(a, dictbuf, M, N, K, S, Imax, prune, res_tol, eps, pivot_thr, prec);
+    fill_args(a, dictbuf, M, N, K, S, Imax, prune, res_tol, eps, pivot_thr, redo_tol, prec);
     if (Nb > 0) {
         // conjugate-pair groups: up to 2 S atoms per iteration and 2 K kept
         a.grp = 1;
@@ -1719,7 +1720,7 @@ int coop_other_launch(int kind, const float* Y, const int8_t* Ysign, float* X, i
                       int Nb) {
     if (P == 0) return CSREC_OK;
     CoopArgs a;
-    fill_args(a, dictbuf, M, N, K, 1, Imax, 0, res_tol, eps, 0.0, prec);
+    fill_args(a, dictbuf, M, N, K, 1, Imax, 0, res_tol, eps, 0.0, 0.f, prec);
     a.lds_floats = (int)coop_other_lds_floats(kind, M, N, Nb > 0 ? 2 * K : K);
     if (Nb > 0) {
         a.grp = 1;
@@ -1774,7 +1775,8 @@ int64_t resident_groups(const void* fn, size_t lds) {
 // table_host / table_dev: nitems items and gomp_coop_table_extra() bytes
 // behind them (the work cursor).
 int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_host, void* table_dev, int K, int S,
-                           int prune, float res_tol, float eps, double pivot_thr, int prec, hipStream_t stream) {
+                           int prune, float res_tol, float eps, double pivot_thr, float redo_tol, int prec,
+                           hipStream_t stream) {
     if (nitems <= 0) return CSREC_OK;
     CoopItem* th = static_cast<CoopItem*>(table_host);
     int64_t blocks = 0;
@@ -1784,7 +1786,7 @@ int gomp_coop_group_launch(const GompCoopItem* items, int nitems, void* table_ho
         const GompCoopItem& it = items[i];
         if (gomp_coop_class(it.M, it.N) != cls) return CSREC_E_INVAL;
         CoopArgs& a = th[i].a;
-        fill_args(a, it.dict, it.M, it.N, K, S, it.max_iter, prune, res_tol, eps, pivot_thr, prec);
+        fill_args(a, it.dict, it.M, it.N, K, S, it.max_iter, prune, res_tol, eps, pivot_thr, redo_tol, prec);
         a.Y = it.Y;
         a.G32 = it.G32;
         a.X = it.X;

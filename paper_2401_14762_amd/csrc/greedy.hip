@@ -615,7 +615,7 @@ Layout layout_for(const GreedyLaunch& a, int64_t ch_override = 0) {
 
 }  // namespace
 
-size_t greedy_workspace(const GreedyLaunch& a) { return layout_for(a).total; }
+size_t greedy_workspace(const GreedyLaunch& a) { return cosamp_is_wide(a) ? 0 : layout_for(a).total; }
 
 // ---------------------------------------------------------------- grouped (serving) launches
 
@@ -737,7 +737,8 @@ int greedy_group_launch(const GreedyLaunch& proto_max, const GreedyTileItem* ite
         }
         if (ci.empty()) continue;
         const int e = gomp_coop_group_launch(ci.data(), (int)ci.size(), chost + coff, cdev + coff, pm.K, pm.S,
-                                             pm.prune, pm.res_tol, pm.eps, pm.pivot_fallback, pm.prec, stream);
+                                             pm.prune, pm.res_tol, pm.eps, pm.pivot_fallback, (float)pm.redo_tol,
+                                             pm.prec, stream);
         if (e) return e;
         coff += align_up(ci.size() * gomp_coop_item_bytes() + gomp_coop_table_extra(), 256);
     }
@@ -766,6 +767,7 @@ int greedy_gram(const float* A, int M, int N, float* G32, double* G64, hipStream
 int greedy_launch(const GreedyLaunch& a) {
     if (a.P == 0) return CSREC_OK;
     if (a.M > 96) return CSREC_E_UNSUPPORTED;
+    if (cosamp_is_wide(a)) return cosamp_wide_launch(a);
     const Layout L = layout_for(a);
     if (!a.workspace || a.workspace_bytes < L.total) return CSREC_E_WORKSPACE;
     const bool dbl = a.kind == GREEDY_GOMP && a.pivot_fallback > 0.0;
@@ -831,7 +833,7 @@ int greedy_launch(const GreedyLaunch& a) {
         const int64_t np = (a.P - p0) < L.CH ? (a.P - p0) : L.CH;
         const int e = gomp_coop_launch(a.Y, a.X, a.support, a.stats, g.G32, dictbuf, g.fbflag, a.M, a.N, p0, np,
                                        a.K, a.S, a.max_iter, a.prune, a.res_tol, a.eps, a.pivot_fallback,
-                                       a.prec, a.stream);
+                                       (float)a.redo_tol, a.prec, a.stream);
         if (e) return e;
         if (dbl) {
             hipLaunchKernelGGL(redo, dim3((unsigned)ceil_div(np, threads)), dim3(threads), lds, a.stream, g, p0,
@@ -934,7 +936,7 @@ int greedy_gomp_scratch_launch(const GreedyLaunch& a, char* scr, size_t cap) {
         const int64_t np = (a.P - p0) < L.CH ? (a.P - p0) : L.CH;
         const int e = gomp_coop_launch(a.Y, a.X, a.support, a.stats, g.G32, dictbuf, g.fbflag, a.M, a.N, p0, np,
                                        a.K, a.S, a.max_iter, a.prune, a.res_tol, a.eps, a.pivot_fallback,
-                                       a.prec, a.stream);
+                                       (float)a.redo_tol, a.prec, a.stream);
         if (e) return e;
         if (dbl) {
             hipLaunchKernelGGL(redo, dim3((unsigned)(cols / kRedoThreads)), dim3(kRedoThreads), lds, a.stream, g,
@@ -1039,7 +1041,7 @@ int gomp_hermitian_launch(const GreedyLaunch& a) {
     for (int64_t p0 = 0; p0 < a.P; p0 += kChunkH) {
         const int64_t np = (a.P - p0) < kChunkH ? (a.P - p0) : kChunkH;
         const int e = gomp_coop_launch(a.Y, a.X, a.support, a.stats, G32, dictbuf, nullptr, M, NR, p0, np, a.K,
-                                       a.S, a.max_iter, a.prune, a.res_tol, a.eps, 0.0, a.prec, a.stream, Nb);
+                                       a.S, a.max_iter, a.prune, a.res_tol, a.eps, 0.0, 0.f, a.prec, a.stream, Nb);
         if (e) return e;
     }
     return CSREC_OK;

@@ -126,6 +126,7 @@ class HipExecutor : public serving::Executor {
             pm.res_tol = prm.res_tol;
             pm.eps = prm.eps;
             pm.pivot_fallback = prm.pivot_fallback;
+            pm.redo_tol = prm.redo_tol;
             const int e = greedy_group_launch(pm, items.data(), (int)items.size(), batch_pixels, ws, thost + off,
                                               tdev + off, compute);
             if (e) return e;
@@ -211,7 +212,9 @@ int check_gomp_params(const csrec_gomp_params& g) {
     if (g.struct_size != (int32_t)sizeof(csrec_gomp_params)) return CSREC_E_INVAL;
     if (g.K < 1 || g.S < 1 || g.S > 8 || g.max_iter < 0) return CSREC_E_INVAL;
     if (g.prune != CSREC_PRUNE_EACH && g.prune != CSREC_PRUNE_FINAL) return CSREC_E_INVAL;
-    if (!(g.res_tol >= 0) || !(g.eps >= 0) || !(g.pivot_fallback >= 0)) return CSREC_E_INVAL;
+    if (!(g.res_tol >= 0) || !(g.eps >= 0) || !(g.pivot_fallback >= 0) || !(g.redo_tol >= 0) ||
+        !std::isfinite(g.redo_tol))
+        return CSREC_E_INVAL;
     if (g.prec != CSREC_PREC_F32 && g.prec != CSREC_PREC_BF16 && g.prec != CSREC_PREC_F16) return CSREC_E_INVAL;
     return CSREC_OK;
 }
@@ -274,6 +277,7 @@ int resolve_params(const csrec_server* s, const csrec::Dict& d, const csrec_gomp
     out->res_tol = (float)g.res_tol;
     out->eps = (float)g.eps;
     out->pivot_fallback = g.pivot_fallback;
+    out->redo_tol = g.redo_tol > 0.0 ? g.redo_tol : CSREC_REDO_TOL_DEFAULT;
     return CSREC_OK;
 }
 
@@ -308,6 +312,7 @@ int32_t csrec_server_create(const csrec_server_cfg* cfg, csrec_server** out) {
     p.res_tol = (float)g.res_tol;
     p.eps = (float)g.eps;
     p.pivot_fallback = g.pivot_fallback;
+    p.redo_tol = g.redo_tol > 0.0 ? g.redo_tol : CSREC_REDO_TOL_DEFAULT;
     const size_t ws_bytes = greedy_group_workspace(p, cfg->batch_pixels);
     const int max_items = (int)std::min<int64_t>(4096, cfg->batch_pixels);
     // every parameter class of a batch takes its own slice of the table

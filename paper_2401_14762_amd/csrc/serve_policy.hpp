@@ -117,10 +117,10 @@ class RangePool {
 struct TileParams {
     int K = 0, S = 0, max_iter = 0, prune = 0, prec = 0;
     float res_tol = 0.f, eps = 0.f;
-    double pivot_fallback = 0.0;
+    double pivot_fallback = 0.0, redo_tol = 0.0;
     bool same_launch(const TileParams& o) const {
         return K == o.K && S == o.S && prune == o.prune && prec == o.prec && res_tol == o.res_tol && eps == o.eps &&
-               pivot_fallback == o.pivot_fallback;
+               pivot_fallback == o.pivot_fallback && redo_tol == o.redo_tol;
     }
 };
 

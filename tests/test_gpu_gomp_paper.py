@@ -168,3 +168,38 @@ def test_full_cube_worst_pixels(torch, name, K):
     ref = oracle.gomp(c["A"], Yw, K=K, S=K // 5, eps=1e-8)
     _check_unique_part(np_of(X)[idx], np_of(Sup)[idx], ref, K, c["N"])
     assert rel_err.max().item() <= 1e-5
+
+
+@pytest.mark.parametrize("name,K", [("china-like", 22), ("salinas-like", 33)])
+def test_full_cube_redo_tol(torch, name, K):
+    """The same full cubes with the FP64 redo's error-estimate threshold at
+    1e-7 instead of the default 1e-5: no fewer pixels go to FP64, and the 8
+    pixels farthest from their sparsified coefficients reach the FP64
+    oracle's PSNR on those pixels (Table I's gOMP rows) within 3 dB."""
+    import math
+    import paper_2401_14762_amd as cs
+    c = W.paper_shape_cube(name)
+    A = to_dev(torch, c["A"])
+    Psi = torch.from_numpy(c["Psi"].astype(np.float32)).cuda()
+    F = torch.from_numpy(c["F"].astype(np.float32)).cuda()
+    note(f"gomp full cube {name} kappa={K} redo_tol 1e-7")
+    Xs, Y, _ = cs.sparsify(Psi, A, F, T=0.1)
+    _, _, st5 = cs.gomp(A, Y, K=K, S=K // 5, eps=1e-8, pivot_fallback=1e-6)
+    X, Sup, st = cs.gomp(A, Y, K=K, S=K // 5, eps=1e-8, pivot_fallback=1e-6, redo_tol=1e-7)
+    torch.cuda.synchronize()
+    n5 = int(((st5["flags"] & 4) != 0).sum().item())
+    n7 = int(((st["flags"] & 4) != 0).sum().item())
+    note(f"  FP64 redo: {n5} pixels at 1e-5, {n7} at 1e-7 of {c['P']}")
+    assert n7 >= n5
+    worst = torch.argsort(((X - Xs) ** 2).sum(1), descending=True)[:8].cpu().numpy()
+    Psi64 = c["Psi"].astype(np.float64)
+    Yw, Xsw, Xw = np_of(Y)[worst], np_of(Xs)[worst].astype(np.float64), np_of(X)[worst].astype(np.float64)
+    ref = oracle.gomp(c["A"], Yw, K=K, S=K // 5, eps=1e-8)
+
+    def psnr(est, want):
+        e, w = est @ Psi64.T, want @ Psi64.T
+        mse = np.mean((e - w) ** 2)
+        return math.inf if mse == 0 else 10 * math.log10(np.max(np.abs(w)) ** 2 / mse)
+    pg, po = psnr(Xw, Xsw), psnr(ref["X"], Xsw)
+    note(f"  worst 8: GPU {pg:.1f} dB, oracle {po:.1f} dB against the sparsified spectra")
+    assert pg >= po - 3.0
