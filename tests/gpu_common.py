@@ -67,20 +67,64 @@ STOP_MARGIN = 1e-3
 PIVOT = 1e-6
 
 
+def fp32_model_err(fn, ref, names, A, Y, *args, **kw):
+    """Per-pixel error against ref of two FP32 (complex64) evaluations of the
+    same iteration, fn(..., dtype=...) as given and on the problem with atoms
+    and rows reversed (the iteration is equivariant under that permutation,
+    the rounding order of every sum is not), and the larger of the two: a
+    pixel's sensitivity to FP32 rounding, which one evaluation alone can
+    understate by chance."""
+    r1 = fn(A, Y, *args, **kw)
+    kw2 = dict(kw)
+    if kw2.get("X0") is not None:
+        kw2["X0"] = np.ascontiguousarray(np.asarray(kw2["X0"])[:, ::-1])
+    r2 = fn(np.ascontiguousarray(np.asarray(A)[::-1, ::-1]), np.ascontiguousarray(np.asarray(Y)[:, ::-1]),
+            *args, **kw2)
+    out = {}
+    for n in names:
+        e1 = rel_err_rows(r1[n], ref[n])
+        e2 = rel_err_rows(np.asarray(r2[n])[:, ::-1], ref[n])
+        out[n] = np.maximum(e1, e2)
+    return out
+
+
+def report_parity(what, e, e32, floor=1e-5):
+    """Prints the fraction of pixels within the floor (1e-5) and the
+    distribution of the per-pixel ratio of the GPU's error to the FP32
+    rounding model's."""
+    ratio = e / np.maximum(e32, 1e-30)
+    q = np.quantile(ratio, [0.5, 0.9, 0.99, 1.0])
+    note(f"parity {what}: {np.mean(e <= floor):.4%} of {len(e)} pixels within {floor:g}; "
+         f"err / fp32-model err p50 {q[0]:.3g} p90 {q[1]:.3g} p99 {q[2]:.3g} max {q[3]:.3g}; "
+         f"max err {e.max():.3g} (model {e32.max():.3g})")
+
+
+# Per-pixel factor on the FP32 models' error (fp32_model_err).  Measured over
+# every FISTA / ADMM parity check (196 checks, 41,000 pixel results, real,
+# complex and half-spectrum kernels): the ratio of the GPU's error to the
+# larger of the two models' has median about 0.9 and p99 at most 5.75; its
+# largest value is 7.44, on the tiny cube at lambda = 1e-3 after 500
+# iterations, where FP32 itself moves x by 0.7 %; every other check stays
+# at or below 4.26.  (Against one model alone the largest ratio was 16.4: a
+# single rounding order can understate a pixel's sensitivity by chance.)
+MODEL_FACTOR = 10.0
+
+
 def assert_fista_parity(X_gpu, A, Y, lam, L, iters, floor=1e-5, **kw):
     """FISTA parity: per pixel, the GPU's relative error against the FP64
-    oracle is at most max(floor, 30 x) that of a plain FP32 evaluation of the
-    same iteration (the oracle's FP32 rounding model), and over the cube the
-    largest and the median error are at most twice the rounding model's.
+    oracle is at most max(floor, MODEL_FACTOR x) that of FP32 evaluations of
+    the same iteration (the larger of the oracle's two FP32 rounding models,
+    fp32_model_err), and over the cube the largest and the median error are
+    at most twice the rounding models'.
     Where the problem is well conditioned this is the 1e-5 bar; where a 2^-24
     perturbation already moves x by more (small lambda, many iterations), the
     bar is what FP32 arithmetic permits."""
     import oracle
     ref = oracle.fista(A, Y, lam, L, iters, **kw)
-    r32 = oracle.fista(A, Y, lam, L, iters, dtype=np.float32, **kw)
     e = rel_err_rows(X_gpu, ref["X"])
-    e32 = rel_err_rows(r32["X"], ref["X"])
-    per_pixel = np.maximum(floor, 30.0 * e32)
+    e32 = fp32_model_err(oracle.fista, ref, ["X"], A, Y, lam, L, iters, dtype=np.float32, **kw)["X"]
+    report_parity(f"lam={lam:g} it={iters} P={len(e)}", e, e32, floor)
+    per_pixel = np.maximum(floor, MODEL_FACTOR * e32)
     bad = np.nonzero(e > per_pixel)[0]
     assert len(bad) == 0, f"pixels {bad[:8]}: err {e[bad[:8]]} vs fp32 model {e32[bad[:8]]}"
     assert e.max() <= max(floor, 2.0 * e32.max()), (e.max(), e32.max())
@@ -90,18 +134,19 @@ def assert_fista_parity(X_gpu, A, Y, lam, L, iters, floor=1e-5, **kw):
 
 def assert_admm_parity(X_gpu, Z_gpu, A, Y, lam, alpha, iters, floor=1e-5, **kw):
     """ADMM parity, the bar of assert_fista_parity applied to x^I and z^I:
-    per pixel at most max(floor, 30 x) the error of the oracle's FP32
-    rounding model of Alg. 2 (which solves step 1 with an FP32 Cholesky
+    per pixel at most max(floor, MODEL_FACTOR x) the error of the oracle's FP32
+    rounding models of Alg. 2 (which solves step 1 with an FP32 Cholesky
     factor), and cube-wide max and median at most twice the model's."""
     import oracle
     ref = oracle.admm(A, Y, lam, alpha, iters, **kw)
-    r32 = oracle.admm(A, Y, lam, alpha, iters, dtype=np.float32, **kw)
+    m32 = fp32_model_err(oracle.admm, ref, ["X", "Z"], A, Y, lam, alpha, iters, dtype=np.float32, **kw)
     for name, got in (("X", X_gpu), ("Z", Z_gpu)):
         if got is None:
             continue
         e = rel_err_rows(got, ref[name])
-        e32 = rel_err_rows(r32[name], ref[name])
-        per_pixel = np.maximum(floor, 30.0 * e32)
+        e32 = m32[name]
+        report_parity(f"{name} lam={lam:g} alpha={alpha:g} it={iters} P={len(e)}", e, e32, floor)
+        per_pixel = np.maximum(floor, MODEL_FACTOR * e32)
         bad = np.nonzero(e > per_pixel)[0]
         assert len(bad) == 0, f"{name} pixels {bad[:8]}: err {e[bad[:8]]} vs fp32 model {e32[bad[:8]]}"
         assert e.max() <= max(floor, 2.0 * e32.max()), (name, e.max(), e32.max())
@@ -115,10 +160,10 @@ def assert_cfista_parity(X_gpu, A, Y, lam, L, iters, floor=1e-5, **kw):
     the complex 2-norm of each pixel's x."""
     import oracle
     ref = oracle.fista_complex(A, Y, lam, L, iters, **kw)
-    r32 = oracle.fista_complex(A, Y, lam, L, iters, dtype=np.complex64, **kw)
     e = rel_err_rows(X_gpu, ref["X"])
-    e32 = rel_err_rows(r32["X"], ref["X"])
-    per_pixel = np.maximum(floor, 30.0 * e32)
+    e32 = fp32_model_err(oracle.fista_complex, ref, ["X"], A, Y, lam, L, iters, dtype=np.complex64, **kw)["X"]
+    report_parity(f"lam={lam:g} it={iters} P={len(e)}", e, e32, floor)
+    per_pixel = np.maximum(floor, MODEL_FACTOR * e32)
     bad = np.nonzero(e > per_pixel)[0]
     assert len(bad) == 0, f"pixels {bad[:8]}: err {e[bad[:8]]} vs complex64 model {e32[bad[:8]]}"
     assert e.max() <= max(floor, 2.0 * e32.max()), (e.max(), e32.max())
@@ -131,13 +176,14 @@ def assert_cadmm_parity(X_gpu, Z_gpu, A, Y, lam, alpha, iters, floor=1e-5, **kw)
     oracle (complex128) and its complex64 rounding model, on x^I and z^I."""
     import oracle
     ref = oracle.admm_complex(A, Y, lam, alpha, iters, **kw)
-    r32 = oracle.admm_complex(A, Y, lam, alpha, iters, dtype=np.complex64, **kw)
+    m32 = fp32_model_err(oracle.admm_complex, ref, ["X", "Z"], A, Y, lam, alpha, iters, dtype=np.complex64, **kw)
     for name, got in (("X", X_gpu), ("Z", Z_gpu)):
         if got is None:
             continue
         e = rel_err_rows(got, ref[name])
-        e32 = rel_err_rows(r32[name], ref[name])
-        per_pixel = np.maximum(floor, 30.0 * e32)
+        e32 = m32[name]
+        report_parity(f"{name} lam={lam:g} alpha={alpha:g} it={iters} P={len(e)}", e, e32, floor)
+        per_pixel = np.maximum(floor, MODEL_FACTOR * e32)
         bad = np.nonzero(e > per_pixel)[0]
         assert len(bad) == 0, f"{name} pixels {bad[:8]}: err {e[bad[:8]]} vs complex64 model {e32[bad[:8]]}"
         assert e.max() <= max(floor, 2.0 * e32.max()), (name, e.max(), e32.max())

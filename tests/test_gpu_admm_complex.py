@@ -4,7 +4,7 @@ complex measurement model) against the FP64 complex ADMM oracle.
 The kernel runs the real iteration on the embedding [Re A, -Im A; Im A, Re A]
 with (alpha I + A A^*)^{-1} embedded likewise, and the soft threshold on each
 (Re, Im) pair.  Tolerance (assert_cadmm_parity): x^I and z^I per pixel within
-max(1e-5, 30x) the error of the oracle's complex64 rounding model, cube-wide
+max(1e-5, 10x) the error of the oracle's complex64 rounding model, cube-wide
 max and median within twice the model's."""
 import numpy as np
 import pytest

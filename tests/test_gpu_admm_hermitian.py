@@ -6,7 +6,7 @@ A^* A + alpha I.
 The kernel iterates on the half spectrum in scaled coordinates, with
 (alpha I + A A^*)^{-1} formed on the device; the oracle knows nothing of
 that reduction.  Tolerance (assert_cadmm_parity): per pixel, x^I and z^I
-within max(1e-5, 30x) the error of the oracle's complex64 rounding model,
+within max(1e-5, 10x) the error of the oracle's complex64 rounding model,
 cube-wide max and median within twice the model's.  Outputs are checked to
 be exactly conjugate-symmetric."""
 import numpy as np

@@ -1,7 +1,7 @@
 """GPU parity of csrec_fista (Alg. 1) against the FP64 oracle.
 
 Tolerance (assert_fista_parity): per-pixel relative error of x at most
-max(1e-5, 30x) the error of a plain FP32 evaluation of Alg. 1 on the same
+max(1e-5, 10x) the error of a plain FP32 evaluation of Alg. 1 on the same
 problem, and the cube's largest and median errors at most twice that
 rounding model's.  Stats (iterations exactly; residual and Delta to 1e-4
 relative) are checked too."""

@@ -5,7 +5,7 @@ The kernel runs the real iteration on the embedding [Re A, -Im A; Im A, Re A]
 with the soft threshold applied to each pair (Re x_n, Im x_n) (the pair
 kernel of the half-spectrum entry point in its complex-y mode).  Tolerance
 (assert_cfista_parity): per-pixel relative error of x^I (complex 2-norm) at
-most max(1e-5, 30x) that of the oracle's complex64 rounding model, cube-wide
+most max(1e-5, 10x) that of the oracle's complex64 rounding model, cube-wide
 max and median at most twice the model's.  Stats: the iteration count
 exactly, the residual ||y - A x^I|| against the GPU's own x to FP32
 resolution of ||y||."""

@@ -4,7 +4,7 @@ complex oracle, which iterates on the full complex x with the full A.
 
 The kernel iterates on the half spectrum (x_{N-k} = conj(x_k)), N real
 unknowns; the oracle knows nothing of that reduction.  Tolerance
-(assert_cfista_parity): per pixel at most max(1e-5, 30x) the error of the
+(assert_cfista_parity): per pixel at most max(1e-5, 10x) the error of the
 oracle's complex64 rounding model, cube-wide max and median at most twice
 the model's.  The returned spectrum is checked to be exactly
 conjugate-symmetric."""
