@@ -621,13 +621,24 @@ __device__ __forceinline__ typename Vec8<H>::type pack8(const v4f& lo, const v4f
     return v;
 }
 
-// MT, NT even (tile pairs); WAVES wavefronts of 16 pixels each.
-template <typename H, int MT, int NT, int WAVES, int MINW>
+// MT, NT even (tile pairs); WAVES wavefronts of 16 pixels each.  FREEZE:
+// the Delta stop (a pixel stops updating once Delta < eps).  Without it
+// (eps = 0) no pixel is frozen: the per-element selects go, Delta is formed
+// in the last iteration only (for the stats), the new residual accumulates
+// in place of the old one once V has been packed, and the soft threshold is
+// v - median(v, -t, t); that drops one residual array (MT v4f) and about a
+// third of the epilogue's instructions, so the large shapes run two waves
+// per SIMD (WAVES = 8 sharing one LDS copy of A).
+template <typename H, int MT, int NT, int WAVES, int MINW, bool FREEZE = true>
 __global__ __launch_bounds__(WAVES * 64, MINW) void fista_lp_kernel(FistaArgs a) {
     typedef typename Vec8<H>::type h8;
     constexpr int MS = MT / 2, NS = NT / 2;
+    // eight waves without the stop keep y in LDS (each lane its own MT
+    // v4f), which frees MT v4f registers for the second wave per SIMD
+    constexpr bool YL = !FREEZE && WAVES >= 8;
     __shared__ h8 sA1[MT * NS * 64];
     __shared__ h8 sA2[NT * MS * 64];
+    __shared__ v4f sY[YL ? WAVES * MT * 64 : 1];
     const int M = a.M, N = a.N;
 
     // swizzled LDS images of A: one thread builds one lane's 8-vector
@@ -726,6 +737,75 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void fista_lp_kernel(FistaArgs a)
     float bprev = 0.f;
     const bool check_eps = a.eps > 0.f;
 
+    if constexpr (!FREEZE) {
+        v4f* const ylds = sY + (YL ? wave * MT * 64 + lane : 0);
+        if constexpr (YL) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) ylds[mt * 64] = Yr[mt];
+        }
+        // y of tile mt: from LDS (YL) or the registers
+        auto yt = [&](int mt) -> v4f { if constexpr (YL) return ylds[mt * 64]; else return Yr[mt]; };
+        for (int it = 0; it < a.max_iter; ++it) {
+            const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+            const float bcur = (float)((t - 1.0) / tn);
+            t = tn;
+            const float cp = 1.f + bprev;
+            // V = A z^{i-1} - y, packed; then V keeps U_{i-1} and U1
+            // accumulates U_i = A x^i - y
+            h8 Vb[MS];
+#pragma unroll
+            for (int sp = 0; sp < MS; ++sp) {
+                const v4f v0 = cp * U1[2 * sp] - bprev * V[2 * sp];
+                const v4f v1 = cp * U1[2 * sp + 1] - bprev * V[2 * sp + 1];
+                Vb[sp] = pack8<H>(v0, v1);
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                V[mt] = U1[mt];
+                U1[mt] = -yt(mt);
+            }
+#pragma unroll
+            for (int np = 0; np < NS; ++np) {
+                // keeps the scheduler from hoisting the operand reads of every
+                // tile pair at once (their registers would not fit)
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int nt = 2 * np + q;
+                    v4f W = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int sp = 0; sp < MS; ++sp) W = mfma16<H>(sA2[(nt * MS + sp) * 64 + lane], Vb[sp], W);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float aux = Zr[nt][r] - W[r] * invL;
+                        const float xn = aux - __builtin_amdgcn_fmed3f(aux, -thr, thr);
+                        Zr[nt][r] = xn + bcur * (xn - Xr[nt][r]);
+                        Xr[nt][r] = xn;
+                    }
+                }
+                const h8 xb = pack8<H>(Xr[2 * np], Xr[2 * np + 1]);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) U1[mt] = mfma16<H>(sA1[(mt * NS + np) * 64 + lane], xb, U1[mt]);
+            }
+            if (it == a.max_iter - 1) {
+                const float c0 = (it == 0 && a.X0) ? 1.f : 0.f;
+                float d2 = 0.f;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const v4f y = yt(mt);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float ref = V[mt][r] - c0 * (V[mt][r] + y[r]);
+                        const float d = U1[mt][r] - ref;
+                        d2 += d * d;
+                    }
+                }
+                last_d2 = quad_sum(d2);
+            }
+            bprev = bcur;
+        }
+        iters = a.max_iter;
+    } else {
     for (int it = 0; it < a.max_iter; ++it) {
         const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
         const float bcur = (float)((t - 1.0) / tn);
@@ -789,6 +869,7 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void fista_lp_kernel(FistaArgs a)
             if (!__any(active)) break;
         }
     }
+    }
     float r2 = 0.f;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -822,6 +903,7 @@ struct FistaVariant {
     int MT, NT, waves;
     fista_kernel_t fn;
     fista_kernel_t fn_nostop = nullptr;   // for eps = 0, where faster
+    int waves_nostop = 0;                 // its workgroup's waves (0: waves)
 };
 
 // Tile shapes instantiated: the 2.5x-compressed band counts of the paper's
@@ -850,19 +932,23 @@ const FistaVariant kVariantsS[] = {
     {5, 13, 4, fista_f32s_kernel<5, 13, 4, 1>},
 };
 
+// Without the Delta stop the (6, 14) shape runs eight waves on one LDS copy
+// of A (two per SIMD: the copy, 84 KiB, leaves no room for a second
+// workgroup) with y in LDS; at (8, 16) the copy (128 KiB) leaves no room for
+// y, and it stays at four.
 const FistaVariant kVariantsBF16[] = {
-    {2, 8, 4, fista_lp_kernel<__bf16, 2, 8, 4, 2>},
-    {4, 8, 4, fista_lp_kernel<__bf16, 4, 8, 4, 2>},
-    {4, 10, 4, fista_lp_kernel<__bf16, 4, 10, 4, 2>},
-    {6, 14, 4, fista_lp_kernel<__bf16, 6, 14, 4, 1>},
-    {8, 16, 4, fista_lp_kernel<__bf16, 8, 16, 4, 1>},
+    {2, 8, 4, fista_lp_kernel<__bf16, 2, 8, 4, 2>, fista_lp_kernel<__bf16, 2, 8, 4, 2, false>},
+    {4, 8, 4, fista_lp_kernel<__bf16, 4, 8, 4, 2>, fista_lp_kernel<__bf16, 4, 8, 4, 2, false>},
+    {4, 10, 4, fista_lp_kernel<__bf16, 4, 10, 4, 2>, fista_lp_kernel<__bf16, 4, 10, 4, 2, false>},
+    {6, 14, 4, fista_lp_kernel<__bf16, 6, 14, 4, 1>, fista_lp_kernel<__bf16, 6, 14, 8, 1, false>, 8},
+    {8, 16, 4, fista_lp_kernel<__bf16, 8, 16, 4, 1>, fista_lp_kernel<__bf16, 8, 16, 4, 1, false>},
 };
 const FistaVariant kVariantsF16[] = {
-    {2, 8, 4, fista_lp_kernel<_Float16, 2, 8, 4, 2>},
-    {4, 8, 4, fista_lp_kernel<_Float16, 4, 8, 4, 2>},
-    {4, 10, 4, fista_lp_kernel<_Float16, 4, 10, 4, 2>},
-    {6, 14, 4, fista_lp_kernel<_Float16, 6, 14, 4, 1>},
-    {8, 16, 4, fista_lp_kernel<_Float16, 8, 16, 4, 1>},
+    {2, 8, 4, fista_lp_kernel<_Float16, 2, 8, 4, 2>, fista_lp_kernel<_Float16, 2, 8, 4, 2, false>},
+    {4, 8, 4, fista_lp_kernel<_Float16, 4, 8, 4, 2>, fista_lp_kernel<_Float16, 4, 8, 4, 2, false>},
+    {4, 10, 4, fista_lp_kernel<_Float16, 4, 10, 4, 2>, fista_lp_kernel<_Float16, 4, 10, 4, 2, false>},
+    {6, 14, 4, fista_lp_kernel<_Float16, 6, 14, 4, 1>, fista_lp_kernel<_Float16, 6, 14, 8, 1, false>, 8},
+    {8, 16, 4, fista_lp_kernel<_Float16, 8, 16, 4, 1>, fista_lp_kernel<_Float16, 8, 16, 4, 1, false>},
 };
 
 template <size_t K>
@@ -902,11 +988,13 @@ size_t fista_workspace(int, int, int64_t, int) { return 0; }
 
 namespace {
 int launch_variant(const FistaVariant* v, const FistaArgs& a, hipStream_t stream) {
-    const int64_t pix_per_block = 16 * v->waves;
+    const bool nostop = a.eps <= 0.f && v->fn_nostop;
+    const fista_kernel_t fn = nostop ? v->fn_nostop : v->fn;
+    const int waves = (nostop && v->waves_nostop) ? v->waves_nostop : v->waves;
+    const int64_t pix_per_block = 16 * waves;
     const int64_t blocks = ceil_div(a.P, pix_per_block);
     if (blocks > 0x7fffffff) return CSREC_E_SHAPE;
-    const fista_kernel_t fn = (a.eps > 0.f || !v->fn_nostop) ? v->fn : v->fn_nostop;
-    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * v->waves), 0, stream, a);
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * waves), 0, stream, a);
     CSREC_HIP_TRY(hipGetLastError());
     return CSREC_OK;
 }
