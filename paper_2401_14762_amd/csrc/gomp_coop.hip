@@ -148,10 +148,11 @@ struct PixLds {
     float* bq;    // K
     float* sq;    // K
     int* q;       // K
+    int* kp;      // CM: 1 where position k of c was kept by the last prune
 };
 
 struct LdsPlan {
-    int rb, W, z, b, s, l, c, sel, bsel, Wq, bq, sq, q, total;
+    int rb, W, z, b, s, l, c, sel, bsel, Wq, bq, sq, q, kp, total;
 };
 
 // Offsets (floats) of one pixel's region; the stride is padded to 8 mod 64
@@ -177,6 +178,7 @@ __host__ __device__ inline LdsPlan lds_plan(int MP, int CM, int K) {
     p.bq = o; o += up4(K);
     p.sq = o; o += up4(K);
     p.q = o; o += up4(K);
+    p.kp = o; o += up4(CM);
     o += ((8 - o) % 64 + 64) % 64;
     p.total = o;
     return p;
@@ -198,6 +200,7 @@ __device__ __forceinline__ PixLds carve(float* base, const CoopArgs& a) {
     p.bq = base + pl.bq;
     p.sq = base + pl.sq;
     p.q = reinterpret_cast<int*>(base + pl.q);
+    p.kp = reinterpret_cast<int*>(base + pl.kp);
     return p;
 }
 
@@ -530,21 +533,92 @@ __device__ __forceinline__ void solve_list(bool on, int t, int n, int nmax, int 
 // Step 3 of Alg. 3 for the pixels with `on`: q = the K entries of c with
 // largest |s| (ties to the lower index), then s_q = G[q,q]^{-1} b_q.
 // Called by every lane (it holds barriers).
-__device__ __forceinline__ void prune_to_q(bool on, int t, int nc, int nmax_c, int K, int N,
+// gOMP's prune: the K entries of largest |s| on c, ranked as rank_top, but
+// written to q (atoms) and qv (their vals) in the order of their positions
+// in c, so that the same kept set always gives the same list.  kp holds the
+// kept flag of every position of c from the last prune (0 for positions
+// appended since); it is updated here.  Returns, for a pixel with on, whether
+// the kept set differs from the last prune's (the same on the pixel's 16
+// lanes).  Called by every lane of the wave.
+template <int U>
+__device__ __forceinline__ bool rank_keep(bool on, int t, int n, int K, const float* s, const int* c,
+                                          const float* vals, int* q, float* qv, int* kp) {
+    int diff = 0;
+    if (on) {
+        float vk[U];
+        int ck[U], rk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = t + 16 * u;
+            vk[u] = k < n ? rank_key(s[k]) : 0.f;
+            ck[u] = k < n ? c[k] : 0;
+            rk[u] = 0;
+        }
+        for (int i0 = 0; i0 < n; i0 += 4) {
+            const float4 sv = *reinterpret_cast<const float4*>(s + i0);
+            const int4 cv = *reinterpret_cast<const int4*>(c + i0);
+            const float v4[4] = {rank_key(sv.x), rank_key(sv.y), rank_key(sv.z), rank_key(sv.w)};
+            const int c4[4] = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (i0 + e < n) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        rk[u] += (v4[e] > vk[u] || (v4[e] == vk[u] && c4[e] < ck[u])) ? 1 : 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = t + 16 * u;
+            if (k < n) {
+                const bool kept = rk[u] < K;
+                diff |= ((kp[k] != 0) != kept) ? 1 : 0;
+                kp[k] = kept ? 1 : 0;
+            }
+        }
+    }
+    wave_sync();
+    // the kept positions in order (everything read back from LDS, so nothing
+    // is held in registers across the barrier)
+    if (on) {
+        for (int k = t; k < n; k += 16) {
+            if (kp[k]) {
+                int idx = 0;
+                for (int i = 0; i < k; ++i) idx += kp[i];
+                q[idx] = c[k];
+                qv[idx] = vals[k];
+            }
+        }
+    }
+    diff |= __shfl_xor(diff, 4);
+    diff |= __shfl_xor(diff, 8);
+    diff |= __shfl_xor(diff, 16);
+    diff |= __shfl_xor(diff, 32);
+    return on && diff != 0;
+}
+
+// Returns, for a pixel with on, whether its kept set q changed since the
+// last prune.  The solve on q is skipped when no pixel of the wave needs it:
+// a pixel whose q did not change keeps the solution of its last prune, which
+// the same list and right-hand side would reproduce exactly.
+__device__ __forceinline__ bool prune_to_q(bool on, int t, int nc, int nmax_c, int K, int N,
                                            const float* __restrict__ G32, const PixLds L) {
     // as many 16-atom rank units as the longest list in the wave needs
     const int nw = wave_max(on ? nc : 0);
+    bool changed;
     if (nw <= 32)
-        rank_top<2>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+        changed = rank_keep<2>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq, L.kp);
     else if (nw <= 48)
-        rank_top<3>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+        changed = rank_keep<3>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq, L.kp);
     else if (nw <= 64)
-        rank_top<4>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+        changed = rank_keep<4>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq, L.kp);
     else
-        rank_top<kCU>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq);
+        changed = rank_keep<kCU>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq, L.kp);
     (void)nmax_c;
     wave_sync();
-    solve_list<false>(on, t, K, K, N, G32, L.q, L.bq, L.sq, L.Wq);
+    if (__any(changed)) solve_list<false>(on, t, K, K, N, G32, L.q, L.bq, L.sq, L.Wq);
+    return changed;
 }
 
 // p = A^T v for the wave's 4 pixels, v in the pixel's LDS vector rb (MP
@@ -816,17 +890,21 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
     float last_d2 = __builtin_nanf(""), rn2 = y2;
     uint32_t mask = 0u;   // bit k: atom 4 NG t + k is in c
     const int M8 = (M + kRowPad - 1) / kRowPad * kRowPad;
+    for (int k = t; k < a.CM; k += 16) L.kp[k] = 0;
+    v4f_t acc[NG];
+    bool same_r = false;   // every active pixel of the wave kept r last iteration: p = A^T r is unchanged
 
     for (int it = 1; it <= a.Imax; ++it) {
         // ---------------- step 1: p = A^T r on MFMA, top-S over the non-members
+        if (!same_r) {
 #pragma unroll
-        for (int u = 0; u < MSLOT; ++u) {
-            const int m = 4 * t + (u & 3) + 64 * (u >> 2);
-            if (m < MP) L.rb[m] = r[u];
+            for (int u = 0; u < MSLOT; ++u) {
+                const int m = 4 * t + (u & 3) + 64 * (u >> 2);
+                if (m < MP) L.rb[m] = r[u];
+            }
+            wave_sync();
+            correlate<NG>(a, L.rb, lane, M8, a.prec, acc);
         }
-        wave_sync();
-        v4f_t acc[NG];
-        correlate<NG>(a, L.rb, lane, M8, a.prec, acc);
         // S rounds of argmax; the winners are appended in selection order.
         // Lane t holds atoms 4 NG t + NG i + g (entry i of accumulator g).
         int nsel = 0;
@@ -959,11 +1037,15 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
         if (!GRP) ng = nc;
         const bool prune_g = active && a.prune == CSREC_PRUNE_EACH && ng > K;
         int nqa = K;
+        bool q_same = false;   // q (and so x and r) as after the last prune
         if (__any(prune_g)) {
             if (GRP)
                 nqa = prune_to_q_grp(prune_g, t, nc, K, N, a.G32, L);
-            else
-                prune_to_q(prune_g, t, nc, a.CM, K, N, a.G32, L);
+            else {
+                // called by every lane (it synchronises the wave); not short-circuited
+                const bool changed = prune_to_q(prune_g, t, nc, a.CM, K, N, a.G32, L);
+                q_same = prune_g && !changed;
+            }
         }
         // a pixel that stopped earlier keeps the x of its last iteration
         if (prune_g) {
@@ -975,19 +1057,26 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
         }
 
         // ---------------- step 4: residual r = y - A x, Delta, stop
+        // (when every active pixel of the wave kept its q, r is unchanged:
+        // Delta = 0, the norm as before)
+        const bool keep_r = __all(!active || q_same);
+        same_r = keep_r;
         if (active) {
-            float rnew[MSLOT];
-            residual<MSLOT>(y, rnew, x_on_q ? L.q : L.c, x_on_q ? L.sq : L.s, nx, a.AT, MP, N, t);
-            float d2 = 0.f, n2 = 0.f;
+            float d2 = 0.f, n2 = rn2;
+            if (!keep_r) {
+                float rnew[MSLOT];
+                residual<MSLOT>(y, rnew, x_on_q ? L.q : L.c, x_on_q ? L.sq : L.s, nx, a.AT, MP, N, t);
+                n2 = 0.f;
 #pragma unroll
-            for (int u = 0; u < MSLOT; ++u) {
-                const float dlt = rnew[u] - r[u];
-                d2 += dlt * dlt;
-                n2 += rnew[u] * rnew[u];
-                r[u] = rnew[u];
+                for (int u = 0; u < MSLOT; ++u) {
+                    const float dlt = rnew[u] - r[u];
+                    d2 += dlt * dlt;
+                    n2 += rnew[u] * rnew[u];
+                    r[u] = rnew[u];
+                }
+                d2 = pix_sum(d2);
+                n2 = pix_sum(n2);
             }
-            d2 = pix_sum(d2);
-            n2 = pix_sum(n2);
             iters = it;
             last_d2 = d2;
             rn2 = n2;
