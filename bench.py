@@ -88,7 +88,7 @@ def measured_traffic(kernel_src: str, summary: str):
     except OSError:
         return None
     m = re.search(r"fista\.hip sha256 at measurement: `([0-9a-f]+)`", text)
-    row = re.search(r"fista_f32s?_kernel<5, 13[^|]*\| *\d+ *\| *\d+ *\| *([0-9.]+) MB", text)
+    row = re.search(r"fista_f32(?:s|i8)?_kernel<5, 13[^|]*\| *\d+ *\| *\d+ *\| *([0-9.]+) MB", text)
     if not m or not row or m.group(1) != sha:
         return None
     return float(row.group(1)) * 1e6
@@ -768,7 +768,7 @@ def main():
                                f"N={N} M={M}, FISTA {FISTA_ITERS} it lambda={LAMBDA} + gOMP S={GOMP_S} "
                                f"K={GOMP_K} res_tol={GOMP_TOL}",
                    "pixels": P, "N": N, "M": M},
-        "roofline": {"bound": "mfma", "kernel": "fista_f32s_kernel", "achieved": achieved,
+        "roofline": {"bound": "mfma", "kernel": "fista_f32i8_kernel<5, 13>", "achieved": achieved,
                      "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
                      "traffic": measured_traffic(os.path.join(ROOT, "paper_2401_14762_amd", "csrc", "fista.hip"),

@@ -305,8 +305,12 @@ struct OpsSingle {
     }
 };
 
-template <int MT, int NT, int WAVES, bool FREEZE, class Ops>
-__device__ __forceinline__ void fista_f32s_body(const FistaArgs& a, const void* lds1, const void* lds2) {
+// YL: y kept in LDS (ysh: WAVES MT 64 v4f, each lane its own MT entries)
+// instead of registers, and the scheduler held to one tile at a time, for
+// the eight-wave form (two waves per SIMD on one LDS copy of A).
+template <int MT, int NT, int WAVES, bool FREEZE, class Ops, bool YL = false>
+__device__ __forceinline__ void fista_f32s_body(const FistaArgs& a, const void* lds1, const void* lds2,
+                                                v4f* ysh = nullptr) {
     const int M = a.M, N = a.N;
     float invL = a.invL, thr = a.thr;
     if (a.L_dev) {
@@ -363,6 +367,13 @@ __device__ __forceinline__ void fista_f32s_body(const FistaArgs& a, const void* 
 
     // U_0 = A x^0 - y; U_{-1} = U_0 (so z^0 = x^0 whatever b_0 is)
     v4f U1[MT], V[MT];
+    v4f* const ylds = YL ? ysh + wave * MT * 64 + lane : nullptr;
+    if constexpr (YL) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) ylds[mt * 64] = Yr[mt];
+    }
+    // y of tile mt inside the loop: from LDS (YL) or the registers
+    auto yt = [&](int mt) -> v4f { if constexpr (YL) return ylds[mt * 64]; else return Yr[mt]; };
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) U1[mt] = -Yr[mt];
     if (a.X0) {
@@ -402,7 +413,7 @@ __device__ __forceinline__ void fista_f32s_body(const FistaArgs& a, const void* 
 
         v4f Un[MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) Un[mt] = -Yr[mt];
+        for (int mt = 0; mt < MT; ++mt) Un[mt] = -yt(mt);
 
         v4f Wn = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -414,6 +425,7 @@ __device__ __forceinline__ void fista_f32s_body(const FistaArgs& a, const void* 
         }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
+            if constexpr (YL) __builtin_amdgcn_sched_barrier(0);
             // W = (A^T V) for 16 n-values of this tile          (step 1)
             const v4f W = Wn;
             // steps 1, 2, 4 elementwise
@@ -445,21 +457,24 @@ __device__ __forceinline__ void fista_f32s_body(const FistaArgs& a, const void* 
         }
         // Delta^2 = ||r^i - r^{i-1}||^2 with r^0 = y: the reference is U_{i-1},
         // except in the first iteration from a given x^0, where it is -y.
-        const float c0 = (it == 0 && a.X0) ? 1.f : 0.f;
+        // (without the stop only the last iteration's Delta is reported)
         float d2 = 0.f;
+        if (FREEZE || it == a.max_iter - 1) {
+            const float c0 = (it == 0 && a.X0) ? 1.f : 0.f;
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+            for (int mt = 0; mt < MT; ++mt) {
+                const v4f y = yt(mt);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float ref = U1[mt][r] - c0 * (U1[mt][r] + Yr[mt][r]);
-                const float d = Un[mt][r] - ref;
-                d2 += d * d;
+                for (int r = 0; r < 4; ++r) {
+                    const float ref = U1[mt][r] - c0 * (U1[mt][r] + y[r]);
+                    const float d = Un[mt][r] - ref;
+                    d2 += d * d;
+                }
             }
-        d2 = quad_sum(d2);
-        if (active) {
-            iters = it + 1;
-            last_d2 = d2;
+            d2 = quad_sum(d2);
+            if (active) last_d2 = d2;
         }
+        if (active) iters = it + 1;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             V[mt] = U1[mt];
@@ -575,6 +590,25 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void fista_f32i_kernel(FistaArgs 
         fista_f32s_body<MT, NT, WAVES, true, OpsSingle<NT>>(a, sA, nullptr);
     else
         fista_f32s_body<MT, NT, WAVES, false, OpsSingle<NT>>(a, sA, nullptr);
+}
+
+// The interleaved single-copy iteration without the Delta stop (only eps = 0
+// is dispatched here), eight waves per workgroup on the one LDS copy of A
+// (two per SIMD; a second workgroup would not fit beside the copy) and y in
+// LDS, which is what lets the state fit in 256 registers.
+template <int MT, int NT>
+__global__ __launch_bounds__(512, 1) void fista_f32i8_kernel(FistaArgs a) {
+    constexpr int PA = OpsSingle<NT>::PA;
+    constexpr int ROWS = 16 * MT;
+    __shared__ float sA[ROWS * PA];
+    __shared__ v4f sY[8 * MT * 64];
+    const int M = a.M, N = a.N;
+    for (int idx = threadIdx.x; idx < ROWS * PA; idx += 512) {
+        const int row = idx / PA, col = idx - (idx / PA) * PA;
+        sA[idx] = (row < M && col < N) ? a.A[(size_t)row * N + col] : 0.f;
+    }
+    __syncthreads();
+    fista_f32s_body<MT, NT, 8, false, OpsSingle<NT>, true>(a, sA, nullptr, sY);
 }
 
 // ---------------------------------------------------------------- 16-bit operands
@@ -917,19 +951,23 @@ const FistaVariant kVariants[] = {
     {4, 8, 4, fista_f32_kernel<4, 8, 4, 2>, fista_f32i_kernel<4, 8, 4, 2>},
     {4, 10, 4, fista_f32_kernel<4, 10, 4, 1>, fista_f32i_kernel<4, 10, 4, 1>},
     {5, 13, 4, fista_f32_kernel<5, 13, 4, 1>, fista_f32i_kernel<5, 13, 4, 1>},
-    {6, 14, 4, fista_f32_kernel<6, 14, 4, 1>, fista_f32i_kernel<6, 14, 4, 1>},
+    {6, 14, 4, fista_f32_kernel<6, 14, 4, 1>, fista_f32i8_kernel<6, 14>, 8},
     {7, 16, 4, fista_f32_kernel<7, 16, 4, 1>, fista_f32i_kernel<7, 16, 4, 1>},
     {8, 16, 4, fista_f32_kernel<8, 16, 4, 1>, fista_f32i_kernel<8, 16, 4, 1>},
 };
 
-// The pre-arranged form (two LDS copies of A), for the shapes it fits.
+// The pre-arranged form (two LDS copies of A), for the shapes it fits; at
+// (4, 10) and (5, 13) the solves without the Delta stop run the eight-wave
+// single-copy form instead, whose second wave per SIMD outweighs the four
+// 4-byte operand reads per 16-byte one (6.59 against 7.63 ms on the
+// 256x256 N=200 M=80 cube, 200 iterations).
 const FistaVariant kVariantsS[] = {
     {1, 2, 4, fista_f32s_kernel<1, 2, 4, 2>},
     {2, 4, 4, fista_f32s_kernel<2, 4, 4, 2>},
     {3, 7, 4, fista_f32s_kernel<3, 7, 4, 2>},
     {4, 8, 4, fista_f32s_kernel<4, 8, 4, 2>},
-    {4, 10, 4, fista_f32s_kernel<4, 10, 4, 1>},
-    {5, 13, 4, fista_f32s_kernel<5, 13, 4, 1>},
+    {4, 10, 4, fista_f32s_kernel<4, 10, 4, 1>, fista_f32i8_kernel<4, 10>, 8},
+    {5, 13, 4, fista_f32s_kernel<5, 13, 4, 1>, fista_f32i8_kernel<5, 13>, 8},
 };
 
 // Without the Delta stop the (6, 14) shape runs eight waves on one LDS copy

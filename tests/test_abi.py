@@ -58,6 +58,7 @@ def test_struct_layout_matches_c(tmp_path):
         "printf(\"%zu %zu %zu\\n\", sizeof(csrec_server_cfg), sizeof(csrec_result), offsetof(csrec_result, t_done));"
         "printf(\"%zu %zu %zu\\n\", sizeof(csrec_admm_params), offsetof(csrec_admm_params, X0),"
         "offsetof(csrec_admm_params, threshold));"
+        "printf(\"%zu %zu\\n\", offsetof(csrec_gomp_params, pivot_fallback), offsetof(csrec_gomp_params, redo_tol));"
         "return 0;}\n")
     exe = tmp_path / "sizes"
     subprocess.run([cc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
@@ -66,7 +67,8 @@ def test_struct_layout_matches_c(tmp_path):
             ctypes.sizeof(L.GompParams), ctypes.sizeof(L.CosampParams), ctypes.sizeof(L.BihtParams),
             L.Problem.workspace_bytes.offset, L.BihtParams.Ysign.offset,
             ctypes.sizeof(L.ServerCfg), ctypes.sizeof(L.Result), L.Result.t_done.offset,
-            ctypes.sizeof(L.AdmmParams), L.AdmmParams.X0.offset, L.AdmmParams.threshold.offset]
+            ctypes.sizeof(L.AdmmParams), L.AdmmParams.X0.offset, L.AdmmParams.threshold.offset,
+            L.GompParams.pivot_fallback.offset, L.GompParams.redo_tol.offset]
     assert got == want
 
 
@@ -142,6 +144,33 @@ def test_validation_params(lib):
     n = ctypes.c_size_t(0)
     assert lib.csrec_workspace_bytes(L.SOLVER_FISTA, None, ctypes.byref(_fista()), ctypes.byref(n)) == L.E_INVAL
     assert lib.csrec_workspace_bytes(L.SOLVER_FISTA, ctypes.byref(pb), ctypes.byref(_fista()), None) == L.E_INVAL
+
+
+def _cosamp(**kw):
+    p = L.CosampParams()
+    p.struct_size = ctypes.sizeof(p)
+    p.K, p.max_iter, p.eps, p.res_tol, p.prec = 8, 10, 0.0, 0.0, 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_cosamp_3k_above_m_and_redo_tol(lib):
+    """CoSaMP with 3K > M takes the FP64 path, which needs no workspace and
+    computes in FP64 only (16-bit correlations refused); 3K must not exceed N
+    nor 128.  gOMP's redo_tol must be finite and non-negative."""
+    pb = _problem(40, 100, 16)
+    rc, n = _ws(lib, L.SOLVER_COSAMP, pb, _cosamp(K=10))         # 3K = 30 <= M: on-chip path
+    assert rc == L.OK and n > 0
+    rc, n = _ws(lib, L.SOLVER_COSAMP, pb, _cosamp(K=15))         # 3K = 45 > M
+    assert rc == L.OK and n == 0
+    assert _ws(lib, L.SOLVER_COSAMP, pb, _cosamp(K=15, prec=1))[0] == L.E_UNSUPPORTED
+    assert _ws(lib, L.SOLVER_COSAMP, pb, _cosamp(K=34))[0] == L.E_SHAPE          # 3K > N
+    assert _ws(lib, L.SOLVER_COSAMP, _problem(40, 200, 16), _cosamp(K=43))[0] == L.E_SHAPE   # 3K > 128
+    for bad in (-1.0, float("nan"), float("inf")):
+        assert _ws(lib, L.SOLVER_GOMP, pb, _gomp(pivot_fallback=1e-6, redo_tol=bad))[0] == L.E_INVAL, bad
+    rc, n = _ws(lib, L.SOLVER_GOMP, pb, _gomp(pivot_fallback=1e-6, redo_tol=1e-7))
+    assert rc == L.OK and n > 0
 
 
 def test_validation_entry_points_enqueue_nothing(lib):

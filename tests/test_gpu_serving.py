@@ -115,6 +115,8 @@ def test_fp64_fallback_through_the_server(torch):
         did = srv.add_dict(A32)
         srv.submit(did, Y[:77], 0)
         srv.submit(did, Y[77:], 1)
+        # a tile with its own FP32 error-estimate threshold (its own launch class)
+        srv.submit(did, Y, 2, redo_tol=1e-9)
         srv.drain()
         res = {r["tag"]: r for r in srv.poll(10)}
     Xs = np.concatenate([res[0]["X"], res[1]["X"]])
@@ -130,6 +132,15 @@ def test_fp64_fallback_through_the_server(torch):
     ok = fb & (ref["sel_gap"] >= GAP) & (ref["prune_gap"] >= GAP)
     assert ok.any()
     assert rel_err_rows(Xs[ok], ref["X"][ok]).max() < 1e-5
+    # redo_tol per tile: equal to the direct call with it, no fewer FP64 redos
+    X9, S9, st9 = cs.gomp(to_dev(torch, A32), to_dev(torch, Y), K=6, S=2, res_tol=1e-6, pivot_fallback=1e-6,
+                          redo_tol=1e-9)
+    torch.cuda.synchronize()
+    assert res[2]["status"] == 0
+    assert np.array_equal(res[2]["X"], np_of(X9)) and np.array_equal(res[2]["support"], np_of(S9))
+    fl9 = res[2]["flags"]
+    assert np.array_equal(fl9, np_of(st9["flags"]).view(np.uint32))
+    assert ((fl9 & oracle.STOP_FALLBACK) != 0).sum() >= fb.sum()
 
 
 def test_per_tile_parameters_and_tags(torch):
