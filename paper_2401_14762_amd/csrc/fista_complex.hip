@@ -138,8 +138,12 @@ struct OpsSingle {
     }
 };
 
-template <int MT, int NTH, bool FREEZE, bool CY, class Ops>
-__device__ __forceinline__ void herm_body(const HermArgs& a, const Ops& ops, int h, int j, int64_t pix) {
+// YL: y kept in LDS (ysh: this wave's MT 64 v4f, each lane its own MT
+// entries) instead of registers, and the scheduler held to one tile pair at a
+// time: the eight-wave form.
+template <int MT, int NTH, bool FREEZE, bool CY, class Ops, bool YL = false>
+__device__ __forceinline__ void herm_body(const HermArgs& a, const Ops& ops, int h, int j, int64_t pix,
+                                          v4f* ysh = nullptr) {
     constexpr int NT = 2 * NTH;
     const int M = a.M, N = a.N, Ha = a.Ha;
     float invL = a.invL, thr = a.thr;
@@ -214,6 +218,13 @@ __device__ __forceinline__ void herm_body(const HermArgs& a, const Ops& ops, int
     };
 
     v4f U1[MT], V[MT];
+    v4f* const ylds = YL ? ysh + (threadIdx.x & 63) : nullptr;
+    if constexpr (YL) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) ylds[mt * 64] = Yr[mt];
+    }
+    // y of tile mt inside the loop: from LDS (YL) or the registers
+    auto yt = [&](int mt) -> v4f { if constexpr (YL) return ylds[mt * 64]; else return Yr[mt]; };
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) U1[mt] = -Yr[mt];
     if (a.X0) {
@@ -252,7 +263,7 @@ __device__ __forceinline__ void herm_body(const HermArgs& a, const Ops& ops, int
         for (int mt = 0; mt < MT; ++mt) V[mt] = cp * U1[mt] - bprev * V[mt];
         v4f Un[MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) Un[mt] = -Yr[mt];
+        for (int mt = 0; mt < MT; ++mt) Un[mt] = -yt(mt);
 
         v4f Wa = {0.f, 0.f, 0.f, 0.f}, Wb = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -267,6 +278,7 @@ __device__ __forceinline__ void herm_body(const HermArgs& a, const Ops& ops, int
         }
 #pragma unroll
         for (int p = 0; p < NTH; ++p) {
+            if constexpr (YL) __builtin_amdgcn_sched_barrier(0);
             const v4f Ga = Wa, Gb = Wb;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -312,21 +324,24 @@ __device__ __forceinline__ void herm_body(const HermArgs& a, const Ops& ops, int
             }
         }
 
-        const float c0 = (it == 0 && a.X0) ? 1.f : 0.f;
+        // (without the stop only the last iteration's Delta is reported)
         float d2 = 0.f;
+        if (FREEZE || it == a.max_iter - 1) {
+            const float c0 = (it == 0 && a.X0) ? 1.f : 0.f;
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+            for (int mt = 0; mt < MT; ++mt) {
+                const v4f y = yt(mt);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float ref = U1[mt][r] - c0 * (U1[mt][r] + Yr[mt][r]);
-                const float d = Un[mt][r] - ref;
-                d2 += d * d;
+                for (int r = 0; r < 4; ++r) {
+                    const float ref = U1[mt][r] - c0 * (U1[mt][r] + y[r]);
+                    const float d = Un[mt][r] - ref;
+                    d2 += d * d;
+                }
             }
-        d2 = quad_sum(d2);
-        if (active) {
-            iters = it + 1;
-            last_d2 = d2;
+            d2 = quad_sum(d2);
+            if (active) last_d2 = d2;
         }
+        if (active) iters = it + 1;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             V[mt] = U1[mt];
@@ -454,21 +469,63 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void fista_h32_kernel(HermArgs a)
     }
 }
 
+// The single-copy iteration without the Delta stop (only eps = 0 is
+// dispatched here), eight waves per workgroup on the one LDS copy of C (two
+// per SIMD) and y in LDS, which is what lets the state fit in 256 registers.
+template <int MT, int NTH, bool CY>
+__global__ __launch_bounds__(512, 1) void fista_h32i8_kernel(HermArgs a) {
+    constexpr int NT = 2 * NTH;
+    constexpr int S = 16 * NTH;
+    constexpr int PA = OpsSingle<NT>::PA;
+    __shared__ float sA[16 * MT * PA];
+    __shared__ v4f sY[8 * MT * 64];
+    const int M = a.M, N = a.N, Ha = a.Ha;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 4;
+    const int j = lane & 15;
+    const int64_t pix = ((int64_t)blockIdx.x * 8 + wave) * 16 + j;
+    const int mu_j = 8 * ((j >> 2) & 1) + 4 * (j >> 3) + (j & 3);
+    const int nu_j = 4 * (j & 3) + (j >> 2);
+    const int cm_h = 8 * (h & 1) + 4 * (h >> 1);
+    for (int idx = threadIdx.x; idx < 16 * MT * PA; idx += 512) {
+        const int row = idx / PA, col = idx - (idx / PA) * PA;
+        float v = 0.f;
+        if (col < 2 * S) {
+            if constexpr (CY) v = row < M ? a.Ap[(size_t)row * 2 * S + col] : 0.f;
+            else v = herm_c(a.A, M, N, Ha, S, row, col);
+        }
+        sA[idx] = v;
+    }
+    __syncthreads();
+    const OpsSingle<NT> ops{sA + mu_j * PA + h, sA + cm_h * PA + nu_j};
+    herm_body<MT, NTH, false, CY, OpsSingle<NT>, true>(a, ops, h, j, pix, sY + wave * MT * 64);
+}
+
 typedef void (*herm_kernel_t)(HermArgs);
 
 struct HVariant {
     int MT, NTH;
     herm_kernel_t fn;    // real y, half spectrum
     herm_kernel_t fnc;   // complex y, embedding
+    herm_kernel_t fn8 = nullptr;    // eps = 0, eight waves per workgroup (real y)
+    herm_kernel_t fnc8 = nullptr;   // the same for complex y
 };
 
 #define FISTA_H_VARIANT(MT, NTH, MINW, PRE) \
     { MT, NTH, fista_h32_kernel<MT, NTH, 4, MINW, PRE, false>, fista_h32_kernel<MT, NTH, 4, MINW, PRE, true> }
+#define FISTA_H_VARIANT8(MT, NTH, MINW, PRE)                                                               \
+    { MT, NTH, fista_h32_kernel<MT, NTH, 4, MINW, PRE, false>, fista_h32_kernel<MT, NTH, 4, MINW, PRE, true>, \
+      fista_h32i8_kernel<MT, NTH, false>, fista_h32i8_kernel<MT, NTH, true> }
+// (4, 5) runs its solves without the Delta stop on eight waves (one copy of C
+// plus y fit in LDS, and the state in 256 registers); the larger shapes would
+// spill 40-70 registers there and keep four waves
 const HVariant kHVariants[] = {
-    FISTA_H_VARIANT(2, 2, 2, true),  FISTA_H_VARIANT(3, 4, 2, true),  FISTA_H_VARIANT(4, 5, 1, true),
+    FISTA_H_VARIANT(2, 2, 2, true),  FISTA_H_VARIANT(3, 4, 2, true),  FISTA_H_VARIANT8(4, 5, 1, true),
     FISTA_H_VARIANT(5, 7, 1, true),  FISTA_H_VARIANT(6, 7, 1, false), FISTA_H_VARIANT(6, 8, 1, false),
 };
 #undef FISTA_H_VARIANT
+#undef FISTA_H_VARIANT8
 
 // rows: M (real y) or 2M (complex y); pairs: ceil(N/2) slots (real y) or N (complex y)
 const HVariant* hpick_rows(int rows, int pairs) {
@@ -536,9 +593,11 @@ int fista_complex_launch(const FistaLaunch& l, bool power) {
         if ((e = lipschitz_launch(Ap, 2 * l.M, 2 * S, Ld, l.stream))) return e;
         a.L_dev = Ld;
     }
-    const int64_t blocks = ceil_div(l.P, 16 * 4);
+    const bool w8 = a.eps <= 0.f && v->fnc8;
+    const int waves = w8 ? 8 : 4;
+    const int64_t blocks = ceil_div(l.P, 16 * waves);
     if (blocks > 0x7fffffff) return CSREC_E_SHAPE;
-    hipLaunchKernelGGL(v->fnc, dim3((unsigned)blocks), dim3(64 * 4), 0, l.stream, a);
+    hipLaunchKernelGGL(w8 ? v->fnc8 : v->fnc, dim3((unsigned)blocks), dim3(64 * waves), 0, l.stream, a);
     CSREC_HIP_TRY(hipGetLastError());
     return CSREC_OK;
 }
@@ -594,9 +653,11 @@ int fista_hermitian_launch(const FistaLaunch& l, bool power) {
         if (e) return e;
         a.L_dev = Ld;
     }
-    const int64_t blocks = ceil_div(l.P, 16 * 4);
+    const bool w8 = a.eps <= 0.f && v->fn8;
+    const int waves = w8 ? 8 : 4;
+    const int64_t blocks = ceil_div(l.P, 16 * waves);
     if (blocks > 0x7fffffff) return CSREC_E_SHAPE;
-    hipLaunchKernelGGL(v->fn, dim3((unsigned)blocks), dim3(64 * 4), 0, l.stream, a);
+    hipLaunchKernelGGL(w8 ? v->fn8 : v->fn, dim3((unsigned)blocks), dim3(64 * waves), 0, l.stream, a);
     CSREC_HIP_TRY(hipGetLastError());
     return CSREC_OK;
 }
