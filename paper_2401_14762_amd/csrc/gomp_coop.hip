@@ -544,6 +544,9 @@ template <int U>
 __device__ __forceinline__ bool rank_keep(bool on, int t, int n, int K, const float* s, const int* c,
                                           const float* vals, int* q, float* qv, int* kp) {
     int diff = 0;
+    bool kept[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) kept[u] = false;
     if (on) {
         float vk[U];
         int ck[U], rk[U];
@@ -572,24 +575,29 @@ __device__ __forceinline__ bool rank_keep(bool on, int t, int n, int K, const fl
         for (int u = 0; u < U; ++u) {
             const int k = t + 16 * u;
             if (k < n) {
-                const bool kept = rk[u] < K;
-                diff |= ((kp[k] != 0) != kept) ? 1 : 0;
-                kp[k] = kept ? 1 : 0;
+                kept[u] = rk[u] < K;
+                diff |= ((kp[k] != 0) != kept[u]) ? 1 : 0;
+                kp[k] = kept[u] ? 1 : 0;
             }
         }
     }
-    wave_sync();
-    // the kept positions in order (everything read back from LDS, so nothing
-    // is held in registers across the barrier)
-    if (on) {
-        for (int k = t; k < n; k += 16) {
-            if (kp[k]) {
-                int idx = 0;
-                for (int i = 0; i < k; ++i) idx += kp[i];
-                q[idx] = c[k];
-                qv[idx] = vals[k];
-            }
+    // the kept positions in order: position k = t + 16 u goes to the number
+    // of kept positions before it, counted from one ballot per unit (the
+    // pixel's 16 lanes are lanes x, x + 4, ..., x + 60 of the wave)
+    const int lane = threadIdx.x & 63;
+    const unsigned long long pix_bits = 0x1111111111111111ull << (lane & 3);
+    const unsigned long long below = pix_bits & ((1ull << lane) - 1ull);
+    int base = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const unsigned long long m = __ballot(kept[u]);
+        if (kept[u]) {
+            const int idx = base + __popcll(m & below);
+            const int k = t + 16 * u;
+            q[idx] = c[k];
+            qv[idx] = vals[k];
         }
+        base += __popcll(m & pix_bits);
     }
     diff |= __shfl_xor(diff, 4);
     diff |= __shfl_xor(diff, 8);
