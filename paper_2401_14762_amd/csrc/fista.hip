@@ -772,31 +772,34 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void fista_lp_kernel(FistaArgs a)
     const bool check_eps = a.eps > 0.f;
 
     if constexpr (!FREEZE) {
+        // -y is kept (LDS for YL, else the registers), so that U_i starts
+        // from it without a negation per iteration
         v4f* const ylds = sY + (YL ? wave * MT * 64 + lane : 0);
-        if constexpr (YL) {
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) ylds[mt * 64] = Yr[mt];
+        for (int mt = 0; mt < MT; ++mt) {
+            if constexpr (YL) ylds[mt * 64] = -Yr[mt];
+            else Yr[mt] = -Yr[mt];
         }
-        // y of tile mt: from LDS (YL) or the registers
-        auto yt = [&](int mt) -> v4f { if constexpr (YL) return ylds[mt * 64]; else return Yr[mt]; };
+        auto ynt = [&](int mt) -> v4f { if constexpr (YL) return ylds[mt * 64]; else return Yr[mt]; };
         for (int it = 0; it < a.max_iter; ++it) {
             const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
             const float bcur = (float)((t - 1.0) / tn);
             t = tn;
-            const float cp = 1.f + bprev;
-            // V = A z^{i-1} - y, packed; then V keeps U_{i-1} and U1
-            // accumulates U_i = A x^i - y
+            // -V / L with V = A z^{i-1} - y, packed, so that the MFMA
+            // accumulates z - A^T V / L onto z (step 1); then V keeps U_{i-1}
+            // and U1 accumulates U_i = A x^i - y
+            const float cu = -(1.f + bprev) * invL, cv = bprev * invL;
             h8 Vb[MS];
 #pragma unroll
             for (int sp = 0; sp < MS; ++sp) {
-                const v4f v0 = cp * U1[2 * sp] - bprev * V[2 * sp];
-                const v4f v1 = cp * U1[2 * sp + 1] - bprev * V[2 * sp + 1];
+                const v4f v0 = cu * U1[2 * sp] + cv * V[2 * sp];
+                const v4f v1 = cu * U1[2 * sp + 1] + cv * V[2 * sp + 1];
                 Vb[sp] = pack8<H>(v0, v1);
             }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
                 V[mt] = U1[mt];
-                U1[mt] = -yt(mt);
+                U1[mt] = ynt(mt);
             }
 #pragma unroll
             for (int np = 0; np < NS; ++np) {
@@ -806,12 +809,12 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void fista_lp_kernel(FistaArgs a)
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
                     const int nt = 2 * np + q;
-                    v4f W = {0.f, 0.f, 0.f, 0.f};
+                    v4f aux4 = Zr[nt];
 #pragma unroll
-                    for (int sp = 0; sp < MS; ++sp) W = mfma16<H>(sA2[(nt * MS + sp) * 64 + lane], Vb[sp], W);
+                    for (int sp = 0; sp < MS; ++sp) aux4 = mfma16<H>(sA2[(nt * MS + sp) * 64 + lane], Vb[sp], aux4);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const float aux = Zr[nt][r] - W[r] * invL;
+                        const float aux = aux4[r];
                         const float xn = aux - __builtin_amdgcn_fmed3f(aux, -thr, thr);
                         Zr[nt][r] = xn + bcur * (xn - Xr[nt][r]);
                         Xr[nt][r] = xn;
@@ -826,10 +829,10 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void fista_lp_kernel(FistaArgs a)
                 float d2 = 0.f;
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
-                    const v4f y = yt(mt);
+                    const v4f yn = ynt(mt);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const float ref = V[mt][r] - c0 * (V[mt][r] + y[r]);
+                        const float ref = V[mt][r] - c0 * (V[mt][r] - yn[r]);
                         const float d = U1[mt][r] - ref;
                         d2 += d * d;
                     }
