@@ -237,6 +237,7 @@ def cosamp_complex(A, Y, K: int, max_iter: int, eps: float = 0.0, res_tol: float
     flags[~fin] |= STOP_NONFINITE
     sel_gap = np.full(P, np.inf)
     prune_gap = np.full(P, np.inf)
+    ls_cond = np.full(P, np.nan)
     active = fin.copy()
     for i in range(1, max_iter + 1):
         if not active.any():
@@ -251,6 +252,8 @@ def cosamp_complex(A, Y, K: int, max_iter: int, eps: float = 0.0, res_tol: float
             cols = _atoms_of(cg, tab)
             full = np.zeros(N, dtype=np.complex128)
             full[cols] = lstsq_complex(A, Yc[pix], cols)        # step 2
+            if diagnostics:
+                ls_cond[pix] = np.linalg.cond(A[:, cols])
             inc = np.zeros(G, dtype=bool)
             inc[cg] = True
             gs = group_scores(full[None, :], tab)
@@ -273,7 +276,8 @@ def cosamp_complex(A, Y, K: int, max_iter: int, eps: float = 0.0, res_tol: float
     resid = np.linalg.norm(Yc - x @ A.T, axis=1)
     out = dict(X=x, support=_support_table(x, K * gmax), iters=iters, delta=delta, resid=resid, flags=flags)
     if diagnostics:
-        out.update(sel_gap=sel_gap, prune_gap=prune_gap)
+        # ls_cond: condition number of A(:, c) of the last solve (step 2)
+        out.update(sel_gap=sel_gap, prune_gap=prune_gap, ls_cond=ls_cond)
     return out
 
 
@@ -305,6 +309,7 @@ def biht_complex(A, Y, K: int, max_iter: int, mu: float = 0.1, eps: float = 0.0,
     flags[~fin] |= STOP_NONFINITE
     sel_gap = np.full(P, np.inf)
     prune_gap = np.full(P, np.inf)
+    ls_cond = np.full(P, np.nan)
     active = fin.copy()
     for i in range(1, max_iter + 1):
         if not active.any():
@@ -322,6 +327,8 @@ def biht_complex(A, Y, K: int, max_iter: int, mu: float = 0.1, eps: float = 0.0,
             cols = _atoms_of(cg, tab)
             full = np.zeros(N, dtype=np.complex128)
             full[cols] = lstsq_complex(A, Yc[pix], cols)        # step 2
+            if diagnostics:
+                ls_cond[pix] = np.linalg.cond(A[:, cols])
             inc = np.zeros(G, dtype=bool)
             inc[cg] = True
             gs = group_scores(full[None, :], tab)
@@ -343,5 +350,6 @@ def biht_complex(A, Y, K: int, max_iter: int, mu: float = 0.1, eps: float = 0.0,
     resid = np.linalg.norm(Yc - x @ A.T, axis=1)
     out = dict(X=x, support=_support_table(x, K * gmax), iters=iters, delta=delta, resid=resid, flags=flags)
     if diagnostics:
-        out.update(sel_gap=sel_gap, prune_gap=prune_gap)
+        # ls_cond: condition number of A(:, c) of the last solve (step 2)
+        out.update(sel_gap=sel_gap, prune_gap=prune_gap, ls_cond=ls_cond)
     return out
