@@ -24,6 +24,8 @@
 // and the least-squares solution of G[c,c] s = b_c is s = W^T (W b_c), with
 // z = W b_c extended by one dot product per append.  Every one of these is a
 // matrix-vector product whose rows (or columns) the 16 lanes split.  The
+// atoms of an iteration are appended two at a time, with one pass over W's
+// rows (both l) and one over its columns (both new rows) per pair.  The
 // Gram entries an append needs are gathered from global memory beforehand,
 // all at once, into the packed slot of the row the append then writes.
 // d / G_jj is the pivot ratio (squared distance of a_j from span(A[:, c])
@@ -239,59 +241,157 @@ __device__ __forceinline__ float coldot4(const float* Wf, const float* v, int k,
     return (s0 + s1) + (s2 + s3);
 }
 
-// One bordered step of the inverse factor: appends atom `atom` (rhs bj) to
-// the factor (Wf, zf, bf, idx) of size n.  The slot of row n must hold
-// G[idx[i], atom] for i < n (written before the barrier preceding the call).
-// All 64 lanes call it; `on` masks the pixels that take part.  Returns d / G_jj.
-// With want_sq it also sets row_sq to the squared norm of the new row of W
-// (summed over the pixel's lanes): the rows' squared norms add up to
-// ||W||_F^2 = trace(G[c,c]^{-1}).
-__device__ __forceinline__ float inv_append(bool on, int t, int n, float* Wf, float* zf, float* bf, int* idx, float* ltmp,
-                            int atom, float bj, float gjj, bool want_sq, float& row_sq) {
-    float* wn = Wf + tri(n);   // G[idx, atom] now, the new row after the second barrier
-    // l = W g (rows i = t + 16u)
-    float ll = 0.f;
-    if (on) {
+// dot4 of u against two vectors at once (u read once).
+__device__ __forceinline__ void dot4x2(const float* u, const float* v0, const float* v1, int len, float& r0,
+                                       float& r1) {
+    float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
+    int k = 0;
+    for (; k + 2 <= len; k += 2) {
+        const float u0 = u[k], u1 = u[k + 1];
+        a0 += u0 * v0[k];
+        a1 += u1 * v0[k + 1];
+        b0 += u0 * v1[k];
+        b1 += u1 * v1[k + 1];
+    }
+    if (k < len) {
+        a0 += u[k] * v0[k];
+        b0 += u[k] * v1[k];
+    }
+    r0 = a0 + a1;
+    r1 = b0 + b1;
+}
+
+// coldot4 against two vectors at once (the column of W read once).
+__device__ __forceinline__ void coldot4x2(const float* Wf, const float* v0, const float* v1, int k, int n, float& r0,
+                                          float& r1) {
+    float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
+    int i = k;
+    int off = tri(k) + k;
+    for (; i + 2 <= n; i += 2) {
+        const int o1 = off + i + 1;
+        const float w0 = Wf[off], w1 = Wf[o1];
+        a0 += v0[i] * w0;
+        a1 += v0[i + 1] * w1;
+        b0 += v1[i] * w0;
+        b1 += v1[i + 1] * w1;
+        off = o1 + i + 2;
+    }
+    if (i < n) {
+        a0 += v0[i] * Wf[off];
+        b0 += v1[i] * Wf[off];
+    }
+    r0 = a0 + a1;
+    r1 = b0 + b1;
+}
+
+// Two bordered steps in one pass over W: appends atom j0 (the slot of row n
+// holds G[idx, j0] and G_00) and, where on1, atom j1 (the slot of row n + 1
+// holds G[idx, j1], G[j0, j1] and G_11) to the factor of size n.  With
+// l0 = W g0 and l1 = W g1 (one pass over W's rows), the Schur complement of
+// G[c,c] in the 2 x 2 block is [[G_00 - l0.l0, .], [G_01 - l0.l1,
+// G_11 - l1.l1]]; its Cholesky factor gives the pivots d0 = G_00 - |l0|^2
+// and d1 = G_11 - |l1|^2 - e^2 with e = (G_01 - l0.l1) / sqrt(d0), the
+// last entry of atom j1's l once j0 is in the factor.  The new rows are
+// then, with Q_u = W^T l_u (one pass over W's columns):
+//   row n     = [-Q_0, 1] / sqrt(d0)
+//   row n + 1 = [-(Q_1 + e row_n[:n]), -e / sqrt(d0), 1] / sqrt(d1)
+// which is what two single steps compute.  l0 and l1 are LDS scratch of n
+// floats each.  All 64 lanes call it; on0 masks the pixels that append,
+// on1 (implies on0) those that append a second atom.  Returns the pivot
+// ratios d / G_jj, the diagonal entries G_jj and, with want_sq, the squared
+// norms of the new rows of W.
+__device__ __forceinline__ void inv_append2(bool on0, bool on1, int t, int n, float* Wf, float* zf, float* bf,
+                                            int* idx, float* l0, float* l1, int j0, int j1, float b0, float b1,
+                                            bool want_sq, float& ratio0, float& ratio1, float& g00, float& g11,
+                                            float& sq0, float& sq1) {
+    float* w0 = Wf + tri(n);
+    float* w1 = Wf + tri(n + 1);
+    float a00 = 0.f, a01 = 0.f, a11 = 0.f;
+    if (on1) {
         for (int i = t; i < n; i += 16) {
-            const float acc = dot4(Wf + tri(i), wn, i + 1);
-            ltmp[i] = acc;
-            ll += acc * acc;
+            float p0, p1;
+            dot4x2(Wf + tri(i), w0, w1, i + 1, p0, p1);
+            l0[i] = p0;
+            l1[i] = p1;
+            a00 += p0 * p0;
+            a01 += p0 * p1;
+            a11 += p1 * p1;
+        }
+    } else if (on0) {
+        for (int i = t; i < n; i += 16) {
+            const float p0 = dot4(Wf + tri(i), w0, i + 1);
+            l0[i] = p0;
+            a00 += p0 * p0;
         }
     }
-    ll = pix_sum(ll);
+    g00 = on0 ? w0[n] : 1.f;
+    const float g01 = on1 ? w1[n] : 0.f;
+    g11 = on1 ? w1[n + 1] : 1.f;
+    a00 = pix_sum(a00);
+    a01 = pix_sum(a01);
+    a11 = pix_sum(a11);
     wave_sync();
-    const float d = gjj - ll;
-    const float ratio = d / gjj;
     // A pivot below FP32 resolution (the atom is numerically in the span) is
     // floored so the factor stays finite; such a pixel carries a ratio far
     // below any fallback threshold.
-    const float floor_d = gjj * 5.9604645e-8f;
-    const float dd = d > floor_d ? d : floor_d;
-    const float inv = 1.f / sqrtf(dd);
-    // new row: w[k] = -(sum_{i>=k} l_i W[i][k]) * inv, w[n] = inv; z_n = w . [b_c, bj]
-    float zp = 0.f, wsq = 0.f;
-    if (on) {
+    const float d0 = g00 - a00;
+    ratio0 = d0 / g00;
+    const float inv0 = 1.f / sqrtf(d0 > g00 * 5.9604645e-8f ? d0 : g00 * 5.9604645e-8f);
+    const float e = (g01 - a01) * inv0;
+    const float d1 = g11 - a11 - e * e;
+    ratio1 = d1 / g11;
+    const float inv1 = 1.f / sqrtf(d1 > g11 * 5.9604645e-8f ? d1 : g11 * 5.9604645e-8f);
+    float z0 = 0.f, z1 = 0.f, s0 = 0.f, s1 = 0.f;
+    if (on1) {
         for (int k = t; k < n; k += 16) {
-            const float w = -coldot4(Wf, ltmp, k, n) * inv;
-            wn[k] = w;
-            zp += w * bf[k];
-            wsq += w * w;
+            float q0, q1;
+            coldot4x2(Wf, l0, l1, k, n, q0, q1);
+            const float u0 = -q0 * inv0;
+            const float u1 = -(q1 + e * u0) * inv1;
+            w0[k] = u0;
+            w1[k] = u1;
+            z0 += u0 * bf[k];
+            z1 += u1 * bf[k];
+            s0 += u0 * u0;
+            s1 += u1 * u1;
         }
-        if (t == 0) {
-            wn[n] = inv;
-            zp += inv * bj;
-            wsq += inv * inv;
+    } else if (on0) {
+        for (int k = t; k < n; k += 16) {
+            const float u0 = -coldot4(Wf, l0, k, n) * inv0;
+            w0[k] = u0;
+            z0 += u0 * bf[k];
+            s0 += u0 * u0;
         }
     }
-    zp = pix_sum(zp);
-    if (want_sq) row_sq = pix_sum(wsq);
-    if (on && t == 0) {
-        zf[n] = zp;
-        bf[n] = bj;
-        idx[n] = atom;
+    if (on0 && t == 0) {
+        w0[n] = inv0;
+        z0 += inv0 * b0;
+        s0 += inv0 * inv0;
+        if (on1) {
+            const float u1n = -e * inv0 * inv1;
+            w1[n] = u1n;
+            w1[n + 1] = inv1;
+            z1 += u1n * b0 + inv1 * b1;
+            s1 += u1n * u1n + inv1 * inv1;
+        }
+    }
+    z0 = pix_sum(z0);
+    z1 = pix_sum(z1);
+    if (want_sq) {
+        sq0 = pix_sum(s0);
+        sq1 = pix_sum(s1);
+    }
+    if (on0 && t == 0) {
+        zf[n] = z0;
+        bf[n] = b0;
+        idx[n] = j0;
+        if (on1) {
+            zf[n + 1] = z1;
+            bf[n + 1] = b1;
+            idx[n + 1] = j1;
+        }
     }
     wave_sync();
-    return ratio;
 }
 
 // s = W^T z on the first n entries (columns k = t + 16u).
@@ -1016,28 +1116,37 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
             if (t == 0) L.bsel[q] = bj;
         }
         wave_sync();
-        for (int q = 0; q < SA; ++q) {
-            const bool on = q < nq;
-            const int j = on ? L.sel[q] : 0;
-            const float bj = on ? L.bsel[q] : 0.f;
-            const float gjj = on ? L.W[tri(nc) + nc] : 1.f;
-            float row_sq = 0.f;
-            const float ratio = inv_append(on, t, nc, L.W, L.z, L.b, L.c, L.l, j, bj, gjj, a.pivot_thr > 0.0,
-                                           row_sq);
-            if (on && a.pivot_thr > 0.0) {
-                trG += gjj;
-                trW += row_sq;
-                // a small pivot, or an FP32 error estimate of the normal
-                // equations on c above the FP32 result tolerance redo_tol:
-                // 2^-24 kappa(G[c,c]), kappa estimated as
-                // trace(G[c,c]) trace(G[c,c]^{-1}) / |c| (between the lower
-                // bound, that over |c|^2, and the upper bound, the product
-                // itself).  Pruned supports q are subsets of c, and the
-                // estimate of c bounds theirs.
-                if ((double)ratio < a.pivot_thr || trG * trW * 5.9604645e-8f > a.redo_tol * (float)(nc + 1))
+        // appended two at a time (one pass over W per pair); L.s is free
+        // until the solve below and holds the second atom's l
+        for (int q = 0; q < SA; q += 2) {
+            const bool on0 = q < nq, on1 = q + 1 < nq;
+            const int j0 = on0 ? L.sel[q] : 0, j1 = on1 ? L.sel[q + 1] : 0;
+            const float b0 = on0 ? L.bsel[q] : 0.f, b1 = on1 ? L.bsel[q + 1] : 0.f;
+            float ratio0, ratio1, g00, g11, sq0 = 0.f, sq1 = 0.f;
+            const bool want = a.pivot_thr > 0.0;
+            inv_append2(on0, on1, t, nc, L.W, L.z, L.b, L.c, L.l, L.s, j0, j1, b0, b1, want, ratio0, ratio1, g00,
+                        g11, sq0, sq1);
+            // a small pivot, or an FP32 error estimate of the normal
+            // equations on c above the FP32 result tolerance redo_tol:
+            // 2^-24 kappa(G[c,c]), kappa estimated as trace(G[c,c])
+            // trace(G[c,c]^{-1}) / |c| (between the lower bound, that over
+            // |c|^2, and the upper bound, the product itself).  Pruned
+            // supports q are subsets of c, and the estimate of c bounds
+            // theirs.
+            if (on0 && want) {
+                trG += g00;
+                trW += sq0;
+                if ((double)ratio0 < a.pivot_thr || trG * trW * 5.9604645e-8f > a.redo_tol * (float)(nc + 1))
                     fallback = true;
             }
-            if (on) ++nc;
+            if (on0) ++nc;
+            if (on1 && want) {
+                trG += g11;
+                trW += sq1;
+                if ((double)ratio1 < a.pivot_thr || trG * trW * 5.9604645e-8f > a.redo_tol * (float)(nc + 1))
+                    fallback = true;
+            }
+            if (on1) ++nc;
         }
         inv_solve(active, t, nc, L.W, L.z, L.s);
 
