@@ -54,6 +54,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_MFMA_PEAK_TFLOPS = 157.3
+FP32_VALU_TFLOPS = 78.6        # 256 CUs x 64 lanes x 2 flops x 2.4 GHz, no packed FP32 forms
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20      # calibration copy: 256 MiB read + 256 MiB written
 
@@ -92,6 +93,35 @@ def measured_traffic(kernel_src: str, summary: str):
     if not m or not row or m.group(1) != sha:
         return None
     return float(row.group(1)) * 1e6
+
+
+def gomp_sum_of_parts(iters, M: int, N: int, K: int, S: int, ms: float) -> dict:
+    """gOMP's launch time against the sum of its parts: the correlations'
+    flops at the FP32 MFMA peak plus the least-squares, prune and residual
+    flops at the FP32 VALU rate without packed forms (256 CUs x 4 SIMDs x
+    16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s), over the iterations each
+    pixel ran (Alg. 3 as written: every iteration's correlation counts).
+    Per iteration with |c| = n before the S appends:
+      correlation 2MN; append at size m: 2m(m+1) + 2m (l = W g, the new row
+      of W, z); solve s = W^T z at size n + S: (n + S)(n + S + 1); prune when
+      n + S > K: an SPD solve of size K, K^3/3 + 2K^2; residual 2M min(n + S, K)."""
+    gemm = other = 0.0
+    hist = np.bincount(np.asarray(iters, dtype=np.int64))
+    for it in range(1, len(hist)):
+        npix = float(hist[it:].sum())       # pixels that ran iteration it
+        if npix == 0:
+            continue
+        n = S * (it - 1)
+        c = n + S
+        work = sum(2.0 * m * (m + 1) + 2.0 * m for m in range(n, c)) + c * (c + 1.0)
+        if c > K:
+            work += K ** 3 / 3.0 + 2.0 * K * K
+        work += 2.0 * M * min(c, K)
+        gemm += npix * 2.0 * M * N
+        other += npix * work
+    bound_ms = (gemm / (FP32_MFMA_PEAK_TFLOPS * 1e12) + other / (FP32_VALU_TFLOPS * 1e12)) * 1e3
+    return {"gemm_gflop": gemm / 1e9, "other_gflop": other / 1e9, "bound_ms": bound_ms, "frac": bound_ms / ms,
+            "peaks": f"FP32 MFMA {FP32_MFMA_PEAK_TFLOPS} TFLOP/s, FP32 VALU {FP32_VALU_TFLOPS} TFLOP/s (non-packed)"}
 
 
 def parse():
@@ -723,6 +753,7 @@ def main():
     idx = W.pixel_subset(P, 256, 99)
     Xf_s = Xf.cpu().numpy()[idx]
     Xg_s = res[0].cpu().numpy()[idx]
+    gomp_iters = res[2]["iters"].cpu().numpy()
     del res
 
     legs = [s for s in args.legs.split(",") if s]
@@ -730,6 +761,7 @@ def main():
         "fista_ms": fista_avg_ms, "gomp_ms": float(np.mean(gomp_ms)),
         "fista_pixels_per_s": P / (fista_avg_ms * 1e-3),
         "gomp_pixels_per_s": P / (float(np.mean(gomp_ms)) * 1e-3),
+        "gomp_sum_of_parts": gomp_sum_of_parts(gomp_iters, M, N, GOMP_K, GOMP_S, float(np.mean(gomp_ms))),
     }
     samples = {}
     if "precision" in legs:
