@@ -617,6 +617,99 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
 }
 
 
+// The register Gauss-Jordan elimination of solve_list_w for lists of 33 to
+// 48 atoms (CoSaMP's merged supports up to 3K = 48): lane t owns rows t,
+// t + 16 and t + 32 of [G[L,L] | rhs].  Step k publishes pivot row k through
+// the double-buffered slot (one wave barrier) and every other row subtracts
+// its multiple of it, so a solve is nmax steps with every row update in
+// registers, against 2 nmax barriered steps of the LDS LDL^T form.  Same
+// pivot floors, padding and arguments as solve_list_w; scr holds at least
+// 2 (48 + 4) floats.  Called by every lane.
+template <bool PAD>
+__device__ __forceinline__ void solve_gj48(bool on, int t, int n, int nmax, int N, const float* __restrict__ G32,
+                                           const int* L, float* rhs, float* sol, float* scr) {
+    constexpr int GJ = 48, RPL = 3;
+    constexpr int W1 = GJ + 1;   // nmax columns (padded to GJ) + the right-hand side
+    constexpr int SLOT = GJ + 4;
+    if (!PAD) n = nmax;
+    if (PAD) {
+        if (on)
+            for (int i = n + t; i < nmax; i += 16) rhs[i] = 0.f;
+        wave_sync();
+    }
+    float R[RPL][W1];
+    bool h[RPL];
+    int qr[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        h[r] = on && t + 16 * r < n;
+        qr[r] = clamp_atom(h[r] ? L[t + 16 * r] : 0, N);
+    }
+#pragma unroll
+    for (int j = 0; j < GJ; ++j) {
+        if ((j & 7) == 0) __builtin_amdgcn_sched_barrier(0);   // 24 gathers in flight at a time
+        const bool hj = on && j < n;
+        const int qj = clamp_atom(hj ? L[j] : 0, N);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r)
+            R[r][j] = (h[r] && hj) ? G32[(size_t)qr[r] * N + qj] : ((PAD && j == t + 16 * r) ? 1.f : 0.f);
+    }
+    float fl[RPL], dg[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        R[r][GJ] = (PAD ? on && t + 16 * r < nmax : h[r]) ? rhs[t + 16 * r] : 0.f;
+        fl[r] = (h[r] ? G32[(size_t)qr[r] * N + qr[r]] : 1.f) * 5.9604645e-8f;
+        dg[r] = 1.f;
+    }
+#pragma unroll
+    for (int k = 0; k < GJ; ++k) {
+        if (k < nmax) {   // uniform
+            float* slot = scr + (k & 1) * SLOT;
+            const int kr = k >> 4;
+            if (t == (k & 15)) {
+                R[kr][k] = R[kr][k] > fl[kr] ? R[kr][k] : fl[kr];
+                dg[kr] = R[kr][k];
+                if (on) {
+#pragma unroll
+                    for (int j = k & ~3; j < W1 + 3; j += 4) {
+                        if (j >= nmax && j < GJ) continue;   // all-zero padding columns (uniform)
+                        const float4 v = make_float4(R[kr][j], j + 1 < W1 ? R[kr][j + 1] : 0.f,
+                                                     j + 2 < W1 ? R[kr][j + 2] : 0.f, j + 3 < W1 ? R[kr][j + 3] : 0.f);
+                        *reinterpret_cast<float4*>(slot + j) = v;
+                    }
+                }
+            }
+            wave_sync();
+            if (on) {
+                const float rp = 1.f / slot[k];
+                float f[RPL];
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) f[r] = (t + 16 * r == k) ? 0.f : R[r][k] * rp;
+#pragma unroll
+                for (int j = k & ~3; j < W1; j += 4) {
+                    if (j >= nmax && j < GJ) continue;   // all-zero padding columns (uniform)
+                    // a few pivot-row reads in flight at a time: the rows
+                    // already take 3 (GJ + 1) registers
+                    if (((j - (k & ~3)) & 15) == 0) __builtin_amdgcn_sched_barrier(0);
+                    const float4 v = *reinterpret_cast<const float4*>(slot + j);
+                    const float pv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (j + e > k && j + e < W1) {
+#pragma unroll
+                            for (int r = 0; r < RPL; ++r) R[r][j + e] -= f[r] * pv[e];
+                        }
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+        if (on && t + 16 * r < n) sol[t + 16 * r] = R[r][GJ] / dg[r];
+    wave_sync();
+}
+
 // The register elimination is unrolled over its width, and its code is most
 // of the kernel's: a list of at most kGJSmall atoms runs an instance of that
 // width, so the loop's instructions stay within the instruction cache.
@@ -1568,7 +1661,10 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
         int nmax = nc;
         nmax = max(nmax, __shfl_xor(nmax, 1));
         nmax = max(nmax, __shfl_xor(nmax, 2));
-        solve_list<true>(active, t, nc, nmax, N, a.G32, c, b, sv, scr);
+        if (KIND == GREEDY_COSAMP && nmax > kGJ && nmax <= 48)   // uniform over the wave
+            solve_gj48<true>(active, t, nc, nmax, N, a.G32, c, b, sv, scr);
+        else
+            solve_list<true>(active, t, nc, nmax, N, a.G32, c, b, sv, scr);
         // as many 16-atom rank units as the longest list in the wave needs
         if (GRP) {
             int nk;
