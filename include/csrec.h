@@ -80,6 +80,10 @@ extern "C" {
 #define CSREC_FLAG_ITER_CAP      2u  /* ran max_iter iterations */
 #define CSREC_FLAG_FP64_FALLBACK 4u  /* gOMP least squares redone in FP64 (pivot ratio) */
 #define CSREC_FLAG_NONFINITE     8u  /* non-finite measurement: x = 0, no iterations */
+#define CSREC_FLAG_FP32_LIMIT   16u  /* CoSaMP (FP32 path): a least-squares pivot ratio d / G_jj
+                                        fell below 2^-20, so the FP32 solve on the merged support
+                                        had no correct digit; the pixel stopped with the previous
+                                        iterate (iters counts the iterations it completed) */
 
 /* solver ids for csrec_workspace_bytes */
 #define CSREC_SOLVER_FISTA  0

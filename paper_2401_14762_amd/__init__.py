@@ -23,11 +23,11 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (CsrecError, FLAG_CONVERGED, FLAG_FP64_FALLBACK, FLAG_ITER_CAP,
+from ._lib import (CsrecError, FLAG_CONVERGED, FLAG_FP32_LIMIT, FLAG_FP64_FALLBACK, FLAG_ITER_CAP,
                    FLAG_NONFINITE, MAX_N)
 
 __all__ = ["sparsify", "sparsify_dft", "fista", "fista_complex", "fista_hermitian", "admm", "admm_hermitian", "admm_complex", "gomp", "cosamp", "biht", "lipschitz", "Server", "CsrecError", "FLAG_CONVERGED",
-           "FLAG_ITER_CAP", "FLAG_FP64_FALLBACK", "FLAG_NONFINITE", "MAX_N", "workspace_bytes",
+           "FLAG_ITER_CAP", "FLAG_FP64_FALLBACK", "FLAG_NONFINITE", "FLAG_FP32_LIMIT", "MAX_N", "workspace_bytes",
            "library"]
 
 

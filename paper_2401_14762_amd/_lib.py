@@ -16,7 +16,7 @@ CSREC_ABI_VERSION = 2
 
 OK, E_INVAL, E_SHAPE, E_WORKSPACE, E_DEVICE, E_UNSUPPORTED, E_BUDGET = 0, -1, -2, -3, -4, -5, -6
 PREC = {"f32": 0, "bf16": 1, "f16": 2}
-FLAG_CONVERGED, FLAG_ITER_CAP, FLAG_FP64_FALLBACK, FLAG_NONFINITE = 1, 2, 4, 8
+FLAG_CONVERGED, FLAG_ITER_CAP, FLAG_FP64_FALLBACK, FLAG_NONFINITE, FLAG_FP32_LIMIT = 1, 2, 4, 8, 16
 SOLVER_FISTA, SOLVER_GOMP, SOLVER_COSAMP, SOLVER_BIHT, SOLVER_ADMM = 0, 1, 2, 3, 4
 SOLVER_FISTA_COMPLEX, SOLVER_FISTA_HERMITIAN, SOLVER_ADMM_HERMITIAN, SOLVER_ADMM_COMPLEX = 5, 6, 7, 8
 SOLVER_GOMP_HERMITIAN, SOLVER_COSAMP_HERMITIAN, SOLVER_BIHT_HERMITIAN = 9, 10, 11

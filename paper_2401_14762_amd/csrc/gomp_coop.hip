@@ -53,6 +53,7 @@ constexpr int kRowPad = 8;        // rows of the padded copy of A: multiple of 8
 constexpr int kMaxS = 8;
 constexpr int kMaxSel = 2 * kMaxS; // atoms selected per iteration (a conjugate pair is two)
 constexpr int kGJ = 32;           // K up to this: the pruned system is solved in registers
+constexpr float kFp32Limit = 9.5367432e-7f;   // 2^-20: CoSaMP's pivot-ratio limit of an FP32 solve
 constexpr int kCU = 6;            // |c| <= 16 kCU entries: per-lane units of the rank and the Gram gather
 
 typedef float v4f_t __attribute__((ext_vector_type(4)));
@@ -472,9 +473,15 @@ __device__ __forceinline__ void rank_top(bool on, int t, int n, int K, const flo
 //
 // Every pivot is floored at 2^-24 of the original diagonal like the appends,
 // so a numerically dependent atom keeps the solution finite.
-template <bool PAD, int GJ>
+// With RATIO, *rmin receives this lane's smallest pivot ratio d_k / G_kk
+// (the Schur-complement pivot over the original diagonal, before the floor)
+// over the pivots it saw: the Gauss-Jordan forms see their own rows', the
+// LDL^T form every pivot of the pixel.
+template <bool PAD, int GJ, bool RATIO = false>
 __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, int N, const float* __restrict__ G32,
-                                           const int* L, float* rhs, float* sol, float* scr) {
+                                           const int* L, float* rhs, float* sol, float* scr,
+                                           float* rmin = nullptr) {
+    float rl = 1.f;
     if (!PAD) n = nmax;   // every pixel solves a full list
     if (PAD) {
         if (on)
@@ -506,6 +513,7 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
                 if (t == (k & 15)) {
                     float* R = k < 16 ? R0 : R1;
                     const float fl = k < 16 ? fl0 : fl1;
+                    if constexpr (RATIO) rl = fminf(rl, R[k] / (fl * 16777216.f));
                     R[k] = R[k] > fl ? R[k] : fl;
                     if (k < 16) dg0 = R[k]; else dg1 = R[k];
                     if (on) {
@@ -541,6 +549,7 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
         }
         if (on && t < n) sol[t] = R0[GJ] / dg0;
         if (on && t + 16 < n) sol[t + 16] = R1[GJ] / dg1;
+        if constexpr (RATIO) *rmin = rl;
         wave_sync();
         return;
     }
@@ -583,6 +592,7 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
         if (on) {
             float piv = C[tri(k) + k];
             const float fl = sol[k] * 5.9604645e-8f;
+            if constexpr (RATIO) rl = fminf(rl, piv / sol[k]);
             piv = piv > fl ? piv : fl;
             const float rp = 1.f / piv;
             const float bk = rhs[k];
@@ -614,6 +624,7 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
         }
         wave_sync();
     }
+    if constexpr (RATIO) *rmin = rl;
 }
 
 
@@ -625,9 +636,11 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
 // registers, against 2 nmax barriered steps of the LDS LDL^T form.  Same
 // pivot floors, padding and arguments as solve_list_w; scr holds at least
 // 2 (48 + 4) floats.  Called by every lane.
-template <bool PAD>
+template <bool PAD, bool RATIO = false>
 __device__ __forceinline__ void solve_gj48(bool on, int t, int n, int nmax, int N, const float* __restrict__ G32,
-                                           const int* L, float* rhs, float* sol, float* scr) {
+                                           const int* L, float* rhs, float* sol, float* scr,
+                                           float* rmin = nullptr) {
+    float rl = 1.f;
     constexpr int GJ = 48, RPL = 3;
     constexpr int W1 = GJ + 1;   // nmax columns (padded to GJ) + the right-hand side
     constexpr int SLOT = GJ + 4;
@@ -667,6 +680,7 @@ __device__ __forceinline__ void solve_gj48(bool on, int t, int n, int nmax, int 
             float* slot = scr + (k & 1) * SLOT;
             const int kr = k >> 4;
             if (t == (k & 15)) {
+                if constexpr (RATIO) rl = fminf(rl, R[kr][k] / (fl[kr] * 16777216.f));
                 R[kr][k] = R[kr][k] > fl[kr] ? R[kr][k] : fl[kr];
                 dg[kr] = R[kr][k];
                 if (on) {
@@ -707,6 +721,7 @@ __device__ __forceinline__ void solve_gj48(bool on, int t, int n, int nmax, int 
 #pragma unroll
     for (int r = 0; r < RPL; ++r)
         if (on && t + 16 * r < n) sol[t + 16 * r] = R[r][GJ] / dg[r];
+    if constexpr (RATIO) *rmin = rl;
     wave_sync();
 }
 
@@ -714,13 +729,14 @@ __device__ __forceinline__ void solve_gj48(bool on, int t, int n, int nmax, int 
 // of the kernel's: a list of at most kGJSmall atoms runs an instance of that
 // width, so the loop's instructions stay within the instruction cache.
 constexpr int kGJSmall = 20;
-template <bool PAD>
+template <bool PAD, bool RATIO = false>
 __device__ __forceinline__ void solve_list(bool on, int t, int n, int nmax, int N, const float* __restrict__ G32,
-                                           const int* L, float* rhs, float* sol, float* scr) {
+                                           const int* L, float* rhs, float* sol, float* scr,
+                                           float* rmin = nullptr) {
     if (nmax <= kGJSmall)   // uniform over the wave
-        solve_list_w<PAD, kGJSmall>(on, t, n, nmax, N, G32, L, rhs, sol, scr);
+        solve_list_w<PAD, kGJSmall, RATIO>(on, t, n, nmax, N, G32, L, rhs, sol, scr, rmin);
     else
-        solve_list_w<PAD, kGJ>(on, t, n, nmax, N, G32, L, rhs, sol, scr);
+        solve_list_w<PAD, kGJ, RATIO>(on, t, n, nmax, N, G32, L, rhs, sol, scr, rmin);
 }
 
 // Step 3 of Alg. 3 for the pixels with `on`: q = the K entries of c with
@@ -1483,7 +1499,7 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
     const float ynorm = sqrtf(y2);
 
     bool active = valid && !bad;
-    bool converged = false;
+    bool converged = false, limited = false;
     int iters = 0, nq = 0;
     float last_d2 = __builtin_nanf(""), rn2 = y2;
     const int M8 = (M + kRowPad - 1) / kRowPad * kRowPad;
@@ -1661,10 +1677,29 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
         int nmax = nc;
         nmax = max(nmax, __shfl_xor(nmax, 1));
         nmax = max(nmax, __shfl_xor(nmax, 2));
-        if (KIND == GREEDY_COSAMP && nmax > kGJ && nmax <= 48)   // uniform over the wave
-            solve_gj48<true>(active, t, nc, nmax, N, a.G32, c, b, sv, scr);
-        else
+        if (KIND == GREEDY_COSAMP) {
+            // A pivot ratio below kFp32Limit leaves the FP32 solution of the
+            // normal equations on c without a correct digit (its error bound
+            // is about 2^-24 over the ratio): the pixel stops with its
+            // previous iterate instead of pruning it (CSREC_FLAG_FP32_LIMIT).
+            // It happens where FP32 cannot reach the residual stop and the
+            // further iterations select rounding-level atoms into c.
+            float rl = 1.f;
+            if (nmax > kGJ && nmax <= 48)   // uniform over the wave
+                solve_gj48<true, true>(active, t, nc, nmax, N, a.G32, c, b, sv, scr, &rl);
+            else
+                solve_list<true, true>(active, t, nc, nmax, N, a.G32, c, b, sv, scr, &rl);
+            rl = fminf(rl, __shfl_xor(rl, 4));
+            rl = fminf(rl, __shfl_xor(rl, 8));
+            rl = fminf(rl, __shfl_xor(rl, 16));
+            rl = fminf(rl, __shfl_xor(rl, 32));
+            if (active && !(rl >= kFp32Limit)) {
+                active = false;
+                limited = true;
+            }
+        } else {
             solve_list<true>(active, t, nc, nmax, N, a.G32, c, b, sv, scr);
+        }
         // as many 16-atom rank units as the longest list in the wave needs
         if (GRP) {
             int nk;
@@ -1789,7 +1824,7 @@ __device__ __forceinline__ void other_body(const CoopArgs& a, int64_t block, flo
     if (a.stats && t == 0) {
         csrec_pixel_stats st;
         st.iters = bad ? 0 : iters;
-        st.flags = bad ? CSREC_FLAG_NONFINITE : (converged ? CSREC_FLAG_CONVERGED : CSREC_FLAG_ITER_CAP);
+        st.flags = bad ? CSREC_FLAG_NONFINITE : (limited ? CSREC_FLAG_FP32_LIMIT : (converged ? CSREC_FLAG_CONVERGED : CSREC_FLAG_ITER_CAP));
         st.resid = bad ? 0.f : sqrtf(rn2);
         st.delta = sqrtf(last_d2);
         a.stats[pix] = st;
