@@ -35,6 +35,16 @@ def test_header_declares_entry_points():
         assert must in names
 
 
+def test_flag_values_match_the_header():
+    """The binding's stats flags are the header's CSREC_FLAG_* values."""
+    text = open(HEADER).read()
+    flags = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+CSREC_FLAG_(\w+)\s+(\d+)u", text)}
+    assert set(flags) == {"CONVERGED", "ITER_CAP", "FP64_FALLBACK", "NONFINITE", "FP32_LIMIT"}
+    for name, value in flags.items():
+        assert getattr(L, "FLAG_" + name) == value, name
+    assert len(set(flags.values())) == len(flags) and all(v & (v - 1) == 0 for v in flags.values())
+
+
 def test_exports_every_declared_symbol(lib):
     for name in _declared_functions():
         assert hasattr(lib, name), name
