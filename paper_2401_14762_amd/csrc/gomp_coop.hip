@@ -553,41 +553,37 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
         wave_sync();
         return;
     }
-    // all Gram entries of G[L,L] (lower triangle) in one batch of loads:
-    // entry (r, i), i <= r, goes to C[tri(r) + i] (identity beyond n); the
-    // diagonal is also kept in sol (the pivot floors), which the back
+    // all Gram entries of G[L,L] (lower triangle): lane t gathers rows
+    // r = t + 16 m, entry (r, i), i <= r, to C[tri(r) + i] (identity beyond
+    // n); the diagonal is also kept in sol (the pivot floors), which the back
     // substitution overwrites last
     float* C = scr;
     if (on) {
-        const int TK = tri(nmax);
-        for (int e0 = 0; e0 < TK; e0 += 64) {
-            float v[4];
-            int dst[4], row[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = e0 + 16 * u + t;
-                dst[u] = -1;
-                row[u] = 0;
-                v[u] = 0.f;
-                if (e < TK) {
-                    int r = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
-                    while (tri(r + 1) <= e) ++r;
-                    while (tri(r) > e) --r;
-                    const int i = e - tri(r);
-                    v[u] = r < n ? G32[(size_t)clamp_atom(L[i], N) * N + clamp_atom(L[r], N)] : (i == r ? 1.f : 0.f);
-                    dst[u] = e;
-                    row[u] = (i == r) ? r : -1;
+        for (int r = t; r < nmax; r += 16) {
+            float* cr = C + tri(r);
+            if (r < n) {
+                const int qr = clamp_atom(L[r], N);
+                int i = 0;
+                for (; i + 4 <= r + 1; i += 4) {
+                    const float g0 = G32[(size_t)clamp_atom(L[i], N) * N + qr];
+                    const float g1 = G32[(size_t)clamp_atom(L[i + 1], N) * N + qr];
+                    const float g2 = G32[(size_t)clamp_atom(L[i + 2], N) * N + qr];
+                    const float g3 = G32[(size_t)clamp_atom(L[i + 3], N) * N + qr];
+                    cr[i] = g0;
+                    cr[i + 1] = g1;
+                    cr[i + 2] = g2;
+                    cr[i + 3] = g3;
                 }
+                for (; i <= r; ++i) cr[i] = G32[(size_t)clamp_atom(L[i], N) * N + qr];
+            } else {
+                for (int i = 0; i <= r; ++i) cr[i] = i == r ? 1.f : 0.f;
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (dst[u] >= 0) C[dst[u]] = v[u];
-                if (dst[u] >= 0 && row[u] >= 0) sol[row[u]] = v[u];
-            }
+            sol[r] = cr[r];
         }
     }
     wave_sync();
-    // LDL^T elimination with the forward substitution of rhs
+    // LDL^T elimination with the forward substitution of rhs (column k of
+    // rows j read at tri(j) + k, advanced by j + 1 per row)
     for (int k = 0; k < nmax; ++k) {
         if (on) {
             float piv = C[tri(k) + k];
@@ -600,15 +596,20 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
                 float* ci = C + tri(i);
                 const float f = ci[k] * rp;
                 int j = k + 1;
+                int off = tri(j) + k;
                 for (; j + 4 <= i + 1; j += 4) {
-                    const float c0 = C[tri(j) + k], c1 = C[tri(j + 1) + k], c2 = C[tri(j + 2) + k],
-                                c3 = C[tri(j + 3) + k];
+                    const int o1 = off + j + 1, o2 = o1 + j + 2, o3 = o2 + j + 3;
+                    const float c0 = C[off], c1 = C[o1], c2 = C[o2], c3 = C[o3];
                     ci[j] -= f * c0;
                     ci[j + 1] -= f * c1;
                     ci[j + 2] -= f * c2;
                     ci[j + 3] -= f * c3;
+                    off = o3 + j + 4;
                 }
-                for (; j <= i; ++j) ci[j] -= f * C[tri(j) + k];
+                for (; j <= i; ++j) {
+                    ci[j] -= f * C[off];
+                    off += j + 1;
+                }
                 rhs[i] -= f * bk;
             }
             if (t == 0) C[tri(k) + k] = piv;
