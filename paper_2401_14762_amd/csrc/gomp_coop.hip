@@ -582,38 +582,64 @@ __device__ __forceinline__ void solve_list_w(bool on, int t, int n, int nmax, in
         }
     }
     wave_sync();
-    // LDL^T elimination with the forward substitution of rhs (column k of
-    // rows j read at tri(j) + k, advanced by j + 1 per row)
-    for (int k = 0; k < nmax; ++k) {
+    // LDL^T elimination with the forward substitution of rhs, two pivots per
+    // pass over the trailing rows: pivot k first updates column k + 1 and
+    // rhs[k + 1] (barrier), then every row i >= k + 2 takes both pivots' terms
+    // in one read and write per entry, in the order of two single steps (so
+    // the factor is bit-identical to them).  Column k of rows j is read at
+    // tri(j) + k, advanced by j + 1 per row; column k + 1 sits next to it.
+    auto pivot = [&](int k) {
+        float piv = C[tri(k) + k];
+        const float fl = sol[k] * 5.9604645e-8f;
+        if constexpr (RATIO) rl = fminf(rl, piv / sol[k]);
+        return piv > fl ? piv : fl;
+    };
+    int k = 0;
+    for (; k + 1 < nmax; k += 2) {
+        float rp0 = 0.f;
         if (on) {
-            float piv = C[tri(k) + k];
-            const float fl = sol[k] * 5.9604645e-8f;
-            if constexpr (RATIO) rl = fminf(rl, piv / sol[k]);
-            piv = piv > fl ? piv : fl;
-            const float rp = 1.f / piv;
-            const float bk = rhs[k];
+            const float piv = pivot(k);
+            rp0 = 1.f / piv;
+            const float c10 = C[tri(k + 1) + k];
             for (int i = k + 1 + t; i < nmax; i += 16) {
                 float* ci = C + tri(i);
-                const float f = ci[k] * rp;
-                int j = k + 1;
-                int off = tri(j) + k;
-                for (; j + 4 <= i + 1; j += 4) {
-                    const int o1 = off + j + 1, o2 = o1 + j + 2, o3 = o2 + j + 3;
-                    const float c0 = C[off], c1 = C[o1], c2 = C[o2], c3 = C[o3];
-                    ci[j] -= f * c0;
-                    ci[j + 1] -= f * c1;
-                    ci[j + 2] -= f * c2;
-                    ci[j + 3] -= f * c3;
-                    off = o3 + j + 4;
-                }
-                for (; j <= i; ++j) {
-                    ci[j] -= f * C[off];
+                const float f = ci[k] * rp0;
+                ci[k + 1] -= f * c10;
+            }
+            if (t == 0) {
+                const float f = c10 * rp0;
+                rhs[k + 1] -= f * rhs[k];
+                C[tri(k) + k] = piv;
+            }
+        }
+        wave_sync();
+        if (on) {
+            const float piv1 = pivot(k + 1);
+            const float rp1 = 1.f / piv1;
+            const float bk = rhs[k], bk1 = rhs[k + 1];
+            for (int i = k + 2 + t; i < nmax; i += 16) {
+                float* ci = C + tri(i);
+                const float f0 = ci[k] * rp0;
+                const float f1 = ci[k + 1] * rp1;
+                int off = tri(k + 2) + k;
+                for (int j = k + 2; j <= i; ++j) {
+                    float x = ci[j];
+                    x -= f0 * C[off];
+                    x -= f1 * C[off + 1];
+                    ci[j] = x;
                     off += j + 1;
                 }
-                rhs[i] -= f * bk;
+                float r = rhs[i];
+                r -= f0 * bk;
+                r -= f1 * bk1;
+                rhs[i] = r;
             }
-            if (t == 0) C[tri(k) + k] = piv;
+            if (t == 0) C[tri(k + 1) + k + 1] = piv1;
         }
+        wave_sync();
+    }
+    if (k < nmax) {   // the last pivot of an odd count (no rows below it)
+        if (on && t == 0) C[tri(k) + k] = pivot(k);
         wave_sync();
     }
     // back substitution: sol_i = (bt_i - sum_{k>i} C_ki sol_k) / D_i, column-oriented
