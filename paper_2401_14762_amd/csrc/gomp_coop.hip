@@ -846,6 +846,9 @@ __device__ __forceinline__ bool rank_keep(bool on, int t, int n, int K, const fl
 // last prune.  The solve on q is skipped when no pixel of the wave needs it:
 // a pixel whose q did not change keeps the solution of its last prune, which
 // the same list and right-hand side would reproduce exactly.
+// BIG: K up to 48 solves q by the three-row register elimination (a kernel
+// instance of its own, so the smaller K keep their register budget).
+template <bool BIG = false>
 __device__ __forceinline__ bool prune_to_q(bool on, int t, int nc, int nmax_c, int K, int N,
                                            const float* __restrict__ G32, const PixLds L) {
     // as many 16-atom rank units as the longest list in the wave needs
@@ -861,7 +864,12 @@ __device__ __forceinline__ bool prune_to_q(bool on, int t, int nc, int nmax_c, i
         changed = rank_keep<kCU>(on, t, nc, K, L.s, L.c, L.b, L.q, L.bq, L.kp);
     (void)nmax_c;
     wave_sync();
-    if (__any(changed)) solve_list<false>(on, t, K, K, N, G32, L.q, L.bq, L.sq, L.Wq);
+    if (__any(changed)) {
+        if (BIG && K > kGJ && K <= 48)   // uniform
+            solve_gj48<false>(on, t, K, K, N, G32, L.q, L.bq, L.sq, L.Wq);
+        else
+            solve_list<false>(on, t, K, K, N, G32, L.q, L.bq, L.sq, L.Wq);
+    }
     return changed;
 }
 
@@ -1086,7 +1094,7 @@ __device__ __forceinline__ void residual(const float* y, float* rnew, const int*
     }
 }
 
-template <int MSLOT, int NG, bool GRP>
+template <int MSLOT, int NG, bool GRP, bool BIG = false>
 __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block, float* lds) {
     const int lane = threadIdx.x;
     const int x = lane & 3, t = lane >> 2;
@@ -1296,7 +1304,7 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
                 nqa = prune_to_q_grp(prune_g, t, nc, K, N, a.G32, L);
             else {
                 // called by every lane (it synchronises the wave); not short-circuited
-                const bool changed = prune_to_q(prune_g, t, nc, a.CM, K, N, a.G32, L);
+                const bool changed = prune_to_q<BIG>(prune_g, t, nc, a.CM, K, N, a.G32, L);
                 q_same = prune_g && !changed;
             }
         }
@@ -1350,7 +1358,7 @@ __device__ __forceinline__ void gomp_coop_body(const CoopArgs& a, int64_t block,
         if (GRP)
             nqa = prune_to_q_grp(final_prune, t, nc, K, N, a.G32, L);
         else
-            prune_to_q(final_prune, t, nc, a.CM, K, N, a.G32, L);
+            prune_to_q<BIG>(final_prune, t, nc, a.CM, K, N, a.G32, L);
         float n2 = 0.f;
         if (final_prune) {
             nx = nqa;
@@ -1864,10 +1872,10 @@ __global__ __launch_bounds__(64, 2) void other_coop_kernel(CoopArgs a) {
     other_body<KIND, MSLOT, NG, GRP>(a, blockIdx.x, lds);
 }
 
-template <int MSLOT, int NG, bool GRP>
+template <int MSLOT, int NG, bool GRP, bool BIG = false>
 __global__ __launch_bounds__(64, 2) void gomp_coop_kernel(CoopArgs a) {
     extern __shared__ float lds[];
-    gomp_coop_body<MSLOT, NG, GRP>(a, blockIdx.x, lds);
+    gomp_coop_body<MSLOT, NG, GRP, BIG>(a, blockIdx.x, lds);
 }
 
 struct CoopItem {
@@ -1909,10 +1917,14 @@ __global__ __launch_bounds__(64, 2) void gomp_coop_persistent_kernel(const CoopI
 typedef void (*coop_kernel_t)(CoopArgs);
 typedef void (*coop_grouped_t)(const CoopItem*, int, int64_t, unsigned long long*);
 
-coop_kernel_t pick_coop(int MP, int NG, bool grp) {
+coop_kernel_t pick_coop(int MP, int NG, bool grp, bool big = false) {
     if (grp) {
         if (MP == 64) return NG == 2 ? gomp_coop_kernel<4, 2, true> : gomp_coop_kernel<4, 4, true>;
         return NG == 2 ? gomp_coop_kernel<8, 2, true> : gomp_coop_kernel<8, 4, true>;
+    }
+    if (big) {   // K from 33 to 48
+        if (MP == 64) return NG == 2 ? gomp_coop_kernel<4, 2, false, true> : gomp_coop_kernel<4, 4, false, true>;
+        return NG == 2 ? gomp_coop_kernel<8, 2, false, true> : gomp_coop_kernel<8, 4, false, true>;
     }
     if (MP == 64) return NG == 2 ? gomp_coop_kernel<4, 2, false> : gomp_coop_kernel<4, 4, false>;
     return NG == 2 ? gomp_coop_kernel<8, 2, false> : gomp_coop_kernel<8, 4, false>;
@@ -2042,7 +2054,7 @@ int gomp_coop_launch(const float* Y, float* X, int32_t* support, csrec_pixel_sta
     a.p0 = p0;
     const size_t lds = (size_t)kGroups * a.lds_floats * sizeof(float);
     const int64_t blocks = ceil_div(P, kGroups);
-    const coop_kernel_t fn = pick_coop(a.MP, a.NP / 64, a.grp != 0);
+    const coop_kernel_t fn = pick_coop(a.MP, a.NP / 64, a.grp != 0, K > kGJ && K <= 48);
     CSREC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds));
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64), lds, stream, a);
