@@ -523,7 +523,7 @@ def cosamp_hermitian(A, Y, K: int, max_iter: int = 30, eps: float = 0.0, res_tol
     """CoSaMP (Alg. 5) with the DFT basis for real measurements, conjugate
     pairs as units (K counts groups): A (M x N complex64, conjugate-symmetric
     columns), Y (P x M float32).  Returns (X (P x N complex64), support
-    (P x 2K bins), stats)."""
+    (P x 2K bins), stats); FLAG_FP32_LIMIT as for cosamp."""
     return _greedy_hermitian("cosamp", "csrec_cosamp_hermitian", _lib.SOLVER_COSAMP_HERMITIAN, A, Y, K,
                              dict(max_iter=max_iter, eps=eps, res_tol=res_tol, prec=prec), stream)
 
@@ -539,7 +539,9 @@ def biht_hermitian(A, Y, K: int, max_iter: int = 100, mu: float = 0.1, eps: floa
 
 def cosamp(A, Y, K: int, max_iter: int = 30, eps: float = 0.0, res_tol: float = 0.0,
            prec: str = "f32", stream=None):
-    """CoSaMP (Alg. 5) on every pixel: returns (X, support, stats)."""
+    """CoSaMP (Alg. 5) on every pixel: returns (X, support, stats).  On the
+    FP32 path (3K <= M) a pixel whose least-squares solve meets a pivot ratio
+    below 2^-20 stops with its previous iterate, flagged FLAG_FP32_LIMIT."""
     return _greedy("cosamp", "csrec_cosamp", A, Y, Y.shape[0], stream,
                    dict(K=K, max_iter=max_iter, eps=eps, res_tol=res_tol, prec=prec))
 
